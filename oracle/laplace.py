@@ -1,0 +1,547 @@
+"""Iterative Vecchia-Laplace inference (oracle side).  TEST INFRASTRUCTURE ONLY.
+
+Plain FP64 NumPy/SciPy, following the paper step by step:
+
+  likelihoods      Sec. 2 (log-concave p(y|mu)); Bernoulli-logit of Sec. 4.1,
+                   Poisson log-link, Gaussian (exact-Laplace special case)
+  pcg              appendix algorithm "Preconditioned conjugate gradient
+                   algorithm with Lanczos tridiagonal matrix", run column by
+                   column (each probe has its own recurrence)
+  slq_quadrature   e_1^T log(T~) e_1 from the CG coefficients, eq. (def_SLQ)
+  find_mode        Newton iteration eq. (newton) with CG solves, eq. (pcls1)
+                   for VADU and eq. (pcls2) for LRAC
+  neg_log_marglik  eq. (VLA_loss) with the log-determinant split
+                   eq. (logdetsplit) (VADU, Sec. 3.1.1) or eq. (logdetsplit2)
+                   (LRAC, Sec. 3.1.2) and SLQ for the last term
+  grad_theta       App. "Gradients of Vecchia-Laplace approximations" with the
+                   VADU STE / control-variate formulas of the appendix
+                   "Derivatives of log-determinants ... Preconditioner VADU"
+  predict          eq. (latentpostpredictive) with B_p = I and the simulation
+                   algorithm (Sec. 3.3.1, Alg. simAlgo)
+
+Readings of silent or ambiguous points (all listed in the design doc):
+  * CG stops when the unpreconditioned residual 2-norm is below `cg_tol`
+    (absolute), u_0 = 0, at most `max_cg` iterations.
+  * Newton starts at b = 0, takes full steps and stops when
+    |Psi_new - Psi_old| <= newton_tol * |Psi_old|, Psi(b) = log p(y|F+b)
+    - b^T Sigma~^{-1} b / 2; W for the marginal likelihood is taken at the
+    final mode.
+  * SLQ uses Rademacher probes eps; for VADU z = B^T (W+D^{-1})^{1/2} eps so
+    that Cov(z) = P; the weight ||P^{-1/2} z||^2 is r_0^T z_0 of the CG run
+    (first form of eq. def_SLQ).  For LRAC z = L_k eps_k + W^{-1/2} eps_n.
+  * Control-variate weight c = sample Cov(h, r) / sample Var(r) over the t
+    probes; c = 0 when Var(r) <= 1e-10 mean(r)^2 (then r is constant and the
+    c-terms cancel exactly).  For the mu-derivative one c per component.
+  * The full negative log-likelihood is used (log y! for Poisson and the
+    Gaussian constants included).
+  * Prediction: m nearest training points, Gaussian z^(1), z^(2).
+
+Parity: see the pins in tests/test_oracle_laplace.py.  Large-n absolute
+values have no pin beyond these (parity unpinned at n >= 1e5 except through
+the small-n pins of the same code).
+"""
+import numpy as np
+import scipy.sparse as sp
+from scipy.sparse.linalg import spsolve_triangular
+from scipy.special import gammaln
+
+from . import rng as _rng
+from . import vecchia as _vec
+
+LIK_BERNOULLI_LOGIT = 0
+LIK_POISSON = 1
+LIK_GAUSSIAN = 2
+
+PRECOND_VADU = 0
+PRECOND_LRAC = 1
+
+
+# ----------------------------------------------------------------------------
+# likelihoods: log p, d/dmu, W = -d2/dmu2, dW/dmu = -d3/dmu3
+# ----------------------------------------------------------------------------
+def _sigmoid(x):
+    return 0.5 * (1.0 + np.tanh(0.5 * x))
+
+
+def lik_logp(lik, y, mu, aux=None):
+    if lik == LIK_BERNOULLI_LOGIT:
+        # y mu - log(1 + e^mu)
+        return y * mu - np.logaddexp(0.0, mu)
+    if lik == LIK_POISSON:
+        return y * mu - np.exp(mu) - gammaln(y + 1.0)
+    if lik == LIK_GAUSSIAN:
+        tau2 = float(aux)
+        return -0.5 * (y - mu) ** 2 / tau2 - 0.5 * np.log(2.0 * np.pi * tau2)
+    raise ValueError("unknown likelihood")
+
+
+def lik_grad(lik, y, mu, aux=None):
+    if lik == LIK_BERNOULLI_LOGIT:
+        return y - _sigmoid(mu)
+    if lik == LIK_POISSON:
+        return y - np.exp(mu)
+    if lik == LIK_GAUSSIAN:
+        return (y - mu) / float(aux)
+    raise ValueError("unknown likelihood")
+
+
+def lik_W(lik, y, mu, aux=None):
+    if lik == LIK_BERNOULLI_LOGIT:
+        p = _sigmoid(mu)
+        return p * (1.0 - p)
+    if lik == LIK_POISSON:
+        return np.exp(mu)
+    if lik == LIK_GAUSSIAN:
+        return np.full_like(mu, 1.0 / float(aux))
+    raise ValueError("unknown likelihood")
+
+
+def lik_dW(lik, y, mu, aux=None):
+    """d W_ii / d mu_i = -d^3 log p / d mu^3."""
+    if lik == LIK_BERNOULLI_LOGIT:
+        p = _sigmoid(mu)
+        return p * (1.0 - p) * (1.0 - 2.0 * p)
+    if lik == LIK_POISSON:
+        return np.exp(mu)
+    if lik == LIK_GAUSSIAN:
+        return np.zeros_like(mu)
+    raise ValueError("unknown likelihood")
+
+
+# ----------------------------------------------------------------------------
+# the model: Vecchia factor plus sparse operators
+# ----------------------------------------------------------------------------
+class Model:
+    """Vecchia factor of one data set at one theta (Sec. 2.1)."""
+
+    def __init__(self, coords, m, kind, theta, nbr=None, deriv=False):
+        self.coords = np.asarray(coords, dtype=np.float64)
+        self.n = self.coords.shape[0]
+        self.m = m
+        self.kind = kind
+        self.theta = (float(theta[0]), float(theta[1]))
+        self.nbr = _vec.neighbours(self.coords, m) if nbr is None else nbr
+        out = _vec.factor(self.coords, self.nbr, kind, self.theta, deriv=deriv)
+        if deriv:
+            self.A, self.D, self.dA, self.dD = out
+            self.dB = [_vec.sparse_dB(self.dA[k], self.nbr) for k in range(2)]
+        else:
+            self.A, self.D = out
+        self.Dinv = 1.0 / self.D
+        self.B = _vec.sparse_B(self.A, self.nbr)
+        self.Bt = self.B.T.tocsr()
+
+    # B^{-1} x and B^{-T} x by sparse triangular solves
+    def solve_B(self, x):
+        return spsolve_triangular(self.B, x, lower=True, unit_diagonal=True)
+
+    def solve_Bt(self, x):
+        return spsolve_triangular(self.Bt, x, lower=False, unit_diagonal=True)
+
+    def prec_apply(self, x):
+        """Sigma~^{-1} x = B^T D^{-1} B x."""
+        return self.Bt @ (_col(self.Dinv, x) * (self.B @ x))
+
+    def cov_apply(self, x):
+        """Sigma~ x = B^{-1} D B^{-T} x (two triangular solves, Sec. 3)."""
+        return self.solve_B(_col(self.D, x) * self.solve_Bt(x))
+
+
+def _col(v, x):
+    """Broadcast a length-n vector against x (n or n x t)."""
+    return v if x.ndim == 1 else v[:, None]
+
+
+# ----------------------------------------------------------------------------
+# preconditioned CG with Lanczos coefficients (appendix algorithm)
+# ----------------------------------------------------------------------------
+class CGResult:
+    def __init__(self, U, alphas, betas, iters, r0z0, Z0):
+        self.U = U              # approximate solutions, n x t
+        self.alphas = alphas    # list per column of alpha_1..alpha_l
+        self.betas = betas      # list per column of beta_1..beta_l
+        self.iters = iters      # iterations per column
+        self.r0z0 = r0z0        # r_0^T z_0 per column
+        self.Z0 = Z0            # z_0 = P^{-1} r_0, n x t
+
+
+def pcg(apply_A, apply_Pinv, rhs, tol, max_iter, forced_iters=None):
+    """Preconditioned CG on every column of `rhs` independently.
+
+    Literal reading of the appendix algorithm: u_0 = 0, r_0 = b, z_0 = P^{-1}
+    r_0, h_0 = z_0; per iteration l: v = A h, alpha = r^T z / h^T v,
+    u += alpha h, r -= alpha v, stop flag if ||r||_2 < tol, z = P^{-1} r,
+    beta = r_new^T z_new / r^T z, h = z + beta h.  A column that stopped keeps
+    its state.  `forced_iters` (per column) replaces the stopping test by a
+    fixed iteration count (replay of another run's counts)."""
+    X = rhs if rhs.ndim == 2 else rhs[:, None]
+    n, t = X.shape
+    U = np.zeros((n, t))
+    R = X.copy()
+    Z = apply_Pinv(R)
+    H = Z.copy()
+    rz = np.einsum("ij,ij->j", R, Z)
+    r0z0 = rz.copy()
+    Z0 = Z.copy()
+    active = np.ones(t, dtype=bool)
+    iters = np.zeros(t, dtype=np.int64)
+    alphas = [[] for _ in range(t)]
+    betas = [[] for _ in range(t)]
+    for it in range(max_iter):
+        if forced_iters is not None:
+            active &= iters < np.asarray(forced_iters)
+        if not active.any():
+            break
+        cols = np.nonzero(active)[0]
+        Hc = H[:, cols]
+        V = apply_A(Hc)
+        alpha = rz[cols] / np.einsum("ij,ij->j", Hc, V)
+        U[:, cols] += alpha * Hc
+        R[:, cols] -= alpha * V
+        rnorm = np.sqrt(np.einsum("ij,ij->j", R[:, cols], R[:, cols]))
+        Znew = apply_Pinv(R[:, cols])
+        rz_new = np.einsum("ij,ij->j", R[:, cols], Znew)
+        beta = rz_new / rz[cols]
+        H[:, cols] = Znew + beta * Hc
+        rz[cols] = rz_new
+        for q, c in enumerate(cols):
+            alphas[c].append(alpha[q])
+            betas[c].append(beta[q])
+            iters[c] += 1
+        if forced_iters is None:
+            stop = rnorm < tol
+            active[cols[stop]] = False
+    if rhs.ndim == 1:
+        U = U[:, 0]
+    return CGResult(U, alphas, betas, iters, r0z0, Z0)
+
+
+def lanczos_tridiag(alphas, betas):
+    """T~ from CG coefficients (appendix algorithm): T_{1,1} = 1/alpha_1,
+    T_{j,j} = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+    T_{j-1,j} = T_{j,j-1} = sqrt(beta_{j-1})/alpha_{j-1}."""
+    L = len(alphas)
+    T = np.zeros((L, L))
+    for j in range(L):
+        T[j, j] = 1.0 / alphas[j] + (betas[j - 1] / alphas[j - 1] if j > 0 else 0.0)
+        if j > 0:
+            T[j - 1, j] = T[j, j - 1] = np.sqrt(betas[j - 1]) / alphas[j - 1]
+    return T
+
+
+def slq_quadrature(alphas, betas):
+    """e_1^T log(T~) e_1 = sum_j V_{1j}^2 log(lambda_j) (eq. def_SLQ)."""
+    T = lanczos_tridiag(alphas, betas)
+    lam, V = np.linalg.eigh(T)
+    return float(np.sum(V[0, :] ** 2 * np.log(lam)))
+
+
+# ----------------------------------------------------------------------------
+# operators of the two CG forms
+# ----------------------------------------------------------------------------
+def vadu_ops(model, W):
+    """A = W + B^T D^{-1} B and P_VADU^{-1} = B^{-1} (W + D^{-1})^{-1} B^{-T}
+    (eq. pcls1, eq. P_VADU)."""
+    wd = W + model.Dinv
+
+    def apply_A(X):
+        return _col(W, X) * X + model.prec_apply(X)
+
+    def apply_Pinv(X):
+        return model.solve_B(model.solve_Bt(X) / _col(wd, X))
+
+    return apply_A, apply_Pinv
+
+
+def pivoted_cholesky(coords, kind, theta, k):
+    """Rank-k pivoted Cholesky of the original covariance matrix Sigma
+    (Sec. 3.1.2): pivot = largest remaining diagonal (first index on ties)."""
+    sigma2, rho = theta
+    n = coords.shape[0]
+    k = min(k, n)
+    L = np.zeros((n, k))
+    d = np.full(n, float(sigma2))
+    for j in range(k):
+        p = int(np.argmax(d))
+        col = _vec.covariance(_vec.sqdist(coords, coords[p]), kind, sigma2, rho)
+        L[:, j] = (col - L[:, :j] @ L[p, :j]) / np.sqrt(d[p])
+        d = d - L[:, j] ** 2
+    return L
+
+
+class LracPrecond:
+    """P_LRAC = L_k L_k^T + W^{-1} (eq. P_LRAC) with Woodbury solves and the
+    determinant lemma."""
+
+    def __init__(self, L, W):
+        self.L = L
+        self.W = W
+        k = L.shape[1]
+        self.M = np.eye(k) + L.T @ (W[:, None] * L)
+        self.Mc = np.linalg.cholesky(self.M)
+        self.logdet = 2.0 * np.sum(np.log(np.diag(self.Mc))) - np.sum(np.log(W))
+
+    def solve(self, X):
+        """P^{-1} X = W X - W L M^{-1} L^T W X."""
+        WX = _col(self.W, X) * X
+        Y = np.linalg.solve(self.M, self.L.T @ WX)
+        return WX - _col(self.W, X) * (self.L @ Y)
+
+
+def lrac_ops(model, W, L):
+    """Operator Sigma~ + W^{-1} of eq. (pcls2) and P_LRAC^{-1}."""
+    P = LracPrecond(L, W)
+
+    def apply_A(X):
+        return model.cov_apply(X) + X / _col(W, X)
+
+    return apply_A, P.solve, P
+
+
+# ----------------------------------------------------------------------------
+# Newton mode finding, eq. (newton)
+# ----------------------------------------------------------------------------
+class Opts:
+    def __init__(self, **kw):
+        self.max_newton = 100
+        self.newton_tol = 1e-6
+        self.max_cg = 1000
+        self.cg_tol = 1e-3
+        self.num_probes = 50
+        self.num_pred_samples = 2000
+        self.pred_cg_tol = 1e-3
+        self.seed = 0
+        self.precond = PRECOND_VADU
+        self.lrac_rank = 50
+        for k, v in kw.items():
+            if not hasattr(self, k):
+                raise KeyError(k)
+            setattr(self, k, v)
+
+
+def psi(model, y, F, b, lik, aux):
+    """Psi(b) = log p(y | F + b) - b^T Sigma~^{-1} b / 2."""
+    Bb = model.B @ b
+    return float(np.sum(lik_logp(lik, y, F + b, aux)) - 0.5 * np.sum(model.Dinv * Bb * Bb))
+
+
+def find_mode(model, y, F, lik, aux, opts, replay=None, L=None):
+    """Mode b* of p(y|F+b) p~(b) by Newton's method, eq. (newton):
+    b_{t+1} = (W + Sigma~^{-1})^{-1} (W b_t + d log p / d b), each solve by PCG.
+
+    replay: optional dict {"newton_iters": int, "cg_iters": [int, ...]} that
+    fixes the iteration counts.  Returns (b, W, stats)."""
+    n = model.n
+    F = np.zeros(n) if F is None else np.asarray(F, dtype=np.float64)
+    b = np.zeros(n)
+    psi_old = psi(model, y, F, b, lik, aux)
+    cg_iters = []
+    newton_iters = 0
+    max_newton = opts.max_newton if replay is None else replay["newton_iters"]
+    if opts.precond == PRECOND_LRAC and L is None:
+        L = pivoted_cholesky(model.coords, model.kind, model.theta, opts.lrac_rank)
+    for it in range(max_newton):
+        mu = F + b
+        g = lik_grad(lik, y, mu, aux)
+        W = lik_W(lik, y, mu, aux)
+        rhs = W * b + g
+        forced = None if replay is None else [replay["cg_iters"][it]]
+        if opts.precond == PRECOND_VADU:
+            apply_A, apply_Pinv = vadu_ops(model, W)
+            res = pcg(apply_A, apply_Pinv, rhs, opts.cg_tol, opts.max_cg, forced)
+            b_new = res.U
+        else:
+            # eq. (pcls2): (Sigma~ + W^{-1}) (W u) = Sigma~ rhs
+            apply_A, apply_Pinv, _ = lrac_ops(model, W, L)
+            res = pcg(apply_A, apply_Pinv, model.cov_apply(rhs), opts.cg_tol,
+                      opts.max_cg, forced)
+            b_new = res.U / W
+        cg_iters.append(int(res.iters[0]))
+        b = b_new
+        newton_iters += 1
+        psi_new = psi(model, y, F, b, lik, aux)
+        if replay is None and abs(psi_new - psi_old) <= opts.newton_tol * abs(psi_old):
+            break
+        psi_old = psi_new
+    W = lik_W(lik, y, F + b, aux)
+    return b, W, {"newton_iters": newton_iters, "cg_iters": cg_iters}
+
+
+# ----------------------------------------------------------------------------
+# SLQ negative log-marginal likelihood, eq. (VLA_loss)
+# ----------------------------------------------------------------------------
+def neg_log_marglik(model, y, F, lik, aux, b, opts, replay_cg=None, L=None,
+                    want_grad=False, replay_grad_cg=None):
+    """L^VLA = -log p(y|mu*) + b*^T Sigma~^{-1} b* / 2 + log det(Sigma~ W + I)/2.
+
+    VADU: log det = sum log D + sum log(W + 1/D) + SLQ term (eq. logdetsplit,
+    log det P_VADU = log det(W + D^{-1})).
+    LRAC: log det = sum log W + log det P_LRAC + SLQ term (eq. logdetsplit2).
+    Returns (nll, info) with info holding the pieces, the CG iteration counts
+    and (want_grad, VADU only) the theta-gradient."""
+    n = model.n
+    F = np.zeros(n) if F is None else np.asarray(F, dtype=np.float64)
+    mu = F + b
+    W = lik_W(lik, y, mu, aux)
+    t = opts.num_probes
+    eps = _rng.rademacher(opts.seed, _rng.TAG_SLQ, n, t)
+    if opts.precond == PRECOND_VADU:
+        apply_A, apply_Pinv = vadu_ops(model, W)
+        Z = model.Bt @ (np.sqrt(W + model.Dinv)[:, None] * eps)
+        res = pcg(apply_A, apply_Pinv, Z, opts.cg_tol, opts.max_cg, replay_cg)
+        logdet_fixed = np.sum(np.log(model.D)) + np.sum(np.log(W + model.Dinv))
+    else:
+        if L is None:
+            L = pivoted_cholesky(model.coords, model.kind, model.theta, opts.lrac_rank)
+        apply_A, apply_Pinv, P = lrac_ops(model, W, L)
+        eps_k = _rng.rademacher(opts.seed, _rng.TAG_LRAC_K, L.shape[1], t)
+        eps_n = _rng.rademacher(opts.seed, _rng.TAG_LRAC_N, n, t)
+        Z = L @ eps_k + eps_n / np.sqrt(W)[:, None]
+        res = pcg(apply_A, apply_Pinv, Z, opts.cg_tol, opts.max_cg, replay_cg)
+        logdet_fixed = np.sum(np.log(W)) + P.logdet
+    quad = np.array([slq_quadrature(res.alphas[c], res.betas[c]) for c in range(t)])
+    gamma = float(np.mean(res.r0z0 * quad))
+    logdet = logdet_fixed + gamma
+    Bb = model.B @ b
+    quadform = float(np.sum(model.Dinv * Bb * Bb))
+    loglik = float(np.sum(lik_logp(lik, y, mu, aux)))
+    nll = -loglik + 0.5 * quadform + 0.5 * logdet
+    info = {"loglik": loglik, "quadform": quadform, "logdet": logdet,
+            "gamma": gamma, "cg_iters": res.iters.copy(), "quad": quad,
+            "r0z0": res.r0z0.copy()}
+    if want_grad:
+        if opts.precond != PRECOND_VADU:
+            raise NotImplementedError("theta-gradient is implemented for VADU")
+        grad, ginfo = _grad_theta_vadu(model, y, F, lik, aux, b, W, res, opts,
+                                       replay_grad_cg)
+        info["grad"] = grad
+        info.update(ginfo)
+    return nll, info
+
+
+def _dprec_apply(model, k, x, Bx=None):
+    """(d Sigma~^{-1} / d theta_k) x by eq. (vecchiaSigmaderiv):
+    dB^T D^{-1} B x + B^T D^{-1} dB x - B^T D^{-1} dD D^{-1} B x."""
+    Bx = model.B @ x if Bx is None else Bx
+    dBx = model.dB[k] @ x
+    dD = model.dD[k]
+    Dinv = model.Dinv
+    return model.dB[k].T @ (_col(Dinv, x) * Bx) + model.Bt @ (_col(Dinv, x) * dBx) \
+        - model.Bt @ (_col(Dinv * Dinv * dD, x) * Bx)
+
+
+def _cv_weight(h, r):
+    """c = sample Cov(h, r) / sample Var(r); 0 when r is (numerically) constant."""
+    t = h.shape[-1]
+    rm = r.mean(axis=-1, keepdims=True)
+    hm = h.mean(axis=-1, keepdims=True)
+    var = np.sum((r - rm) ** 2, axis=-1) / (t - 1)
+    cov = np.sum((h - hm) * (r - rm), axis=-1) / (t - 1)
+    thresh = 1e-10 * rm[..., 0] ** 2
+    safe = np.where(var > thresh, var, 1.0)
+    return np.where(var > thresh, cov / safe, 0.0)
+
+
+def _grad_theta_vadu(model, y, F, lik, aux, b, W, res, opts, replay_grad_cg):
+    """theta-gradient of L^VLA (appendix "Gradients of Vecchia-Laplace
+    approximations") with the VADU STE formulas and control variates."""
+    if not hasattr(model, "dB"):
+        raise ValueError("model built without derivatives")
+    n = model.n
+    t = opts.num_probes
+    U = res.U                  # A^{-1} z_i
+    V = res.Z0                 # P^{-1} z_i
+    Dinv = model.Dinv
+    wd = W + Dinv
+    Bb = model.B @ b
+    BU = model.B @ U
+    BV = model.B @ V
+    grad = np.zeros(2)
+    parts = {}
+    # d log det / d mu (VADU mu-formula), needed for the implicit term
+    dW = lik_dW(lik, y, F + b, aux)
+    h_mu = dW[:, None] * U * V
+    r_mu = dW[:, None] * BV * BV
+    c_mu = _cv_weight(h_mu, r_mu)
+    dlogdet_dmu = c_mu * dW / wd + np.mean(h_mu - c_mu[:, None] * r_mu, axis=1)
+    dL_db = 0.5 * dlogdet_dmu
+    apply_A, apply_Pinv = vadu_ops(model, W)
+    if np.any(dL_db != 0.0):
+        forced = None if replay_grad_cg is None else [replay_grad_cg]
+        wres = pcg(apply_A, apply_Pinv, dL_db, opts.cg_tol, opts.max_cg, forced)
+        wsol = wres.U
+        parts["grad_cg_iters"] = int(wres.iters[0])
+    else:
+        wsol = np.zeros(n)
+        parts["grad_cg_iters"] = 0
+    for k in range(2):
+        dD = model.dD[k]
+        dBb = model.dB[k] @ b
+        quad_k = 2.0 * np.sum(dBb * Dinv * Bb) - np.sum(Bb * Dinv * Dinv * dD * Bb)
+        dBU = model.dB[k] @ U
+        dBV = model.dB[k] @ V
+        h = np.sum(dBU * Dinv[:, None] * BV, axis=0) + np.sum(BU * Dinv[:, None] * dBV, axis=0) \
+            - np.sum(BU * (Dinv * Dinv * dD)[:, None] * BV, axis=0)
+        r = 2.0 * np.sum(dBV * wd[:, None] * BV, axis=0) \
+            - np.sum(BV * (Dinv * Dinv * dD)[:, None] * BV, axis=0)
+        c = float(_cv_weight(h, r))
+        tr_D = np.sum(dD * Dinv)
+        tr_P = -np.sum(Dinv * Dinv * dD / wd)
+        dlogdet = tr_D + c * tr_P + np.mean(h - c * r)
+        implicit = -float(wsol @ _dprec_apply(model, k, b, Bb))
+        grad[k] = 0.5 * quad_k + 0.5 * dlogdet + implicit
+        parts[f"dlogdet_{k}"] = dlogdet
+        parts[f"quad_{k}"] = quad_k
+        parts[f"implicit_{k}"] = implicit
+        parts[f"c_{k}"] = c
+        parts[f"h_{k}"] = h
+        parts[f"r_{k}"] = r
+        parts[f"trP_{k}"] = tr_P
+    return grad, parts
+
+
+# ----------------------------------------------------------------------------
+# prediction, eq. (latentpostpredictive) and Alg. simAlgo
+# ----------------------------------------------------------------------------
+def predict(model, coords_p, Fp, b, W, opts, replay_cg=None, chunk=256,
+            want_var=True):
+    """Predictive latent means and simulated variances at coords_p.
+
+    omega_p = F_p + A_p b*  (B_p = I, B_po = -A_p);
+    diag Omega_p ~= D_p + (1/s) sum_i (A_p u_i)^2,  u_i = (W + Sigma~^{-1})^{-1}
+    z3_i,  z3_i = W^{1/2} z1_i + B^T D^{-1/2} z2_i  (Alg. simAlgo).
+    Sample columns are independent; they are processed in chunks of `chunk`
+    columns, which does not change any column's arithmetic."""
+    coords_p = np.asarray(coords_p, dtype=np.float64)
+    npred = coords_p.shape[0]
+    nbr_p = _vec.pred_neighbours(model.coords, coords_p, model.m)
+    Ap, Dp = _vec.factor(model.coords, nbr_p, model.kind, model.theta, coords_self=coords_p)
+    Bpo = _vec.sparse_offdiag(-Ap, nbr_p, model.n)
+    Fp = np.zeros(npred) if Fp is None else np.asarray(Fp, dtype=np.float64)
+    mean = Fp - Bpo @ b
+    info = {"nbr_p": nbr_p, "Ap": Ap, "Dp": Dp}
+    if not want_var:
+        return mean, None, info
+    s = opts.num_pred_samples
+    n = model.n
+    apply_A, apply_Pinv = vadu_ops(model, W)
+    acc = np.zeros(npred)
+    iters = np.zeros(s, dtype=np.int64)
+    for c0 in range(0, s, chunk):
+        c1 = min(s, c0 + chunk)
+        z1 = _gaussian_cols(opts.seed, _rng.TAG_PRED_Z1, n, c0, c1)
+        z2 = _gaussian_cols(opts.seed, _rng.TAG_PRED_Z2, n, c0, c1)
+        z3 = np.sqrt(W)[:, None] * z1 + model.Bt @ (np.sqrt(model.Dinv)[:, None] * z2)
+        forced = None if replay_cg is None else replay_cg[c0:c1]
+        res = pcg(apply_A, apply_Pinv, z3, opts.pred_cg_tol, opts.max_cg, forced)
+        z4 = Bpo @ res.U
+        acc += np.sum(z4 * z4, axis=1)
+        iters[c0:c1] = res.iters
+    var = Dp + acc / s
+    info["cg_iters"] = iters
+    return mean, var, info
+
+
+def _gaussian_cols(seed, tag, n, c0, c1):
+    """Columns c0..c1-1 of the n x s Gaussian probe matrix."""
+    return _rng.gaussian(seed, tag, n, c1 - c0, col0=c0)

@@ -1,0 +1,373 @@
+"""Pins for the Laplace / CG / SLQ / STE / LRAC / prediction part of the oracle.
+
+Each test checks the oracle against something other than itself: a dense
+direct computation that the iterative method reaches in a special case, a
+closed form, a theorem of the paper, finite differences, or a statistical
+bound.  Sizes are tiny so the whole file runs in seconds."""
+import numpy as np
+import pytest
+from scipy.stats import multivariate_normal
+
+from oracle import laplace as L
+from oracle import rng as R
+from oracle import vecchia as V
+from tests import dense_ref as DR
+
+
+def _problem(n=80, m=6, kind=V.COV_EXPONENTIAL, theta=(1.0, 0.2), lik=L.LIK_BERNOULLI_LOGIT,
+             seed=0, deriv=False, F=0.0):
+    g = np.random.default_rng(seed)
+    X = g.uniform(size=(n, 2))
+    S = V.dense_covariance(X, kind, *theta)
+    b = np.linalg.cholesky(S + 1e-10 * np.eye(n)) @ g.standard_normal(n)
+    Fv = np.full(n, F)
+    if lik == L.LIK_BERNOULLI_LOGIT:
+        y = (g.uniform(size=n) < 1 / (1 + np.exp(-(Fv + b)))).astype(float)
+    elif lik == L.LIK_POISSON:
+        y = g.poisson(np.exp(Fv + b)).astype(float)
+    else:
+        y = Fv + b + 0.5 * g.standard_normal(n)
+    model = L.Model(X, m, kind, theta, deriv=deriv)
+    return model, y, Fv
+
+
+def _liks(lik, aux=None):
+    return (lambda y, mu: L.lik_logp(lik, y, mu, aux),
+            lambda y, mu: L.lik_grad(lik, y, mu, aux),
+            lambda y, mu: L.lik_W(lik, y, mu, aux))
+
+
+# ---------------------------------------------------------------- likelihoods
+@pytest.mark.parametrize("lik,aux,y", [(L.LIK_BERNOULLI_LOGIT, None, np.array([0.0, 1.0, 1.0, 0.0])),
+                                       (L.LIK_POISSON, None, np.array([0.0, 3.0, 7.0, 1.0])),
+                                       (L.LIK_GAUSSIAN, 0.3, np.array([0.2, -1.0, 2.0, 0.0]))])
+def test_likelihood_derivatives_finite_differences(lik, aux, y):
+    mu = np.array([-1.3, 0.2, 1.1, 2.5])
+    h = 1e-5
+    fd1 = (L.lik_logp(lik, y, mu + h, aux) - L.lik_logp(lik, y, mu - h, aux)) / (2 * h)
+    fd2 = (L.lik_grad(lik, y, mu + h, aux) - L.lik_grad(lik, y, mu - h, aux)) / (2 * h)
+    fd3 = (L.lik_W(lik, y, mu + h, aux) - L.lik_W(lik, y, mu - h, aux)) / (2 * h)
+    np.testing.assert_allclose(L.lik_grad(lik, y, mu, aux), fd1, rtol=1e-7, atol=1e-9)
+    np.testing.assert_allclose(L.lik_W(lik, y, mu, aux), -fd2, rtol=1e-7, atol=1e-9)
+    np.testing.assert_allclose(L.lik_dW(lik, y, mu, aux), fd3, rtol=1e-6, atol=1e-9)
+
+
+def test_likelihood_normalisation():
+    # Poisson and Bernoulli probabilities sum to one over y; the Gaussian
+    # log-density integrates to one (full constants included).
+    mu = 0.7
+    ys = np.arange(0, 80, dtype=float)
+    assert abs(np.sum(np.exp(L.lik_logp(L.LIK_POISSON, ys, np.full_like(ys, mu)))) - 1) < 1e-12
+    pb = np.exp(L.lik_logp(L.LIK_BERNOULLI_LOGIT, np.array([0.0, 1.0]), np.full(2, mu)))
+    assert abs(pb.sum() - 1) < 1e-14
+    x = np.linspace(-10, 10, 200001)
+    dens = np.exp(L.lik_logp(L.LIK_GAUSSIAN, x, np.zeros_like(x), 0.4))
+    assert abs(np.trapezoid(dens, x) - 1) < 1e-8
+
+
+# ------------------------------------------------------------------------ CG
+def test_pcg_solves_and_lanczos_ritz_values():
+    model, y, F = _problem(n=60)
+    W = L.lik_W(L.LIK_BERNOULLI_LOGIT, y, np.zeros(60))
+    apply_A, apply_Pinv = L.vadu_ops(model, W)
+    Ad = apply_A(np.eye(60))
+    Pinv = apply_Pinv(np.eye(60))
+    rhs = np.random.default_rng(1).standard_normal((60, 3))
+    res = L.pcg(apply_A, apply_Pinv, rhs, 1e-12, 200)
+    np.testing.assert_allclose(res.U, np.linalg.solve(Ad, rhs), rtol=1e-9, atol=1e-10)
+    # Ritz values of T~ lie in the spectrum range of P^{-1}A and the extreme
+    # ones converge to its extreme eigenvalues (CG-Lanczos relation).
+    lam = np.sort(np.linalg.eigvals(Pinv @ Ad).real)
+    for c in range(3):
+        T = L.lanczos_tridiag(res.alphas[c], res.betas[c])
+        ritz = np.linalg.eigvalsh(T)
+        assert ritz.min() >= lam[0] * (1 - 1e-8) and ritz.max() <= lam[-1] * (1 + 1e-8)
+        assert abs(ritz.max() - lam[-1]) < 1e-6 * lam[-1]
+        # Gauss quadrature for f(x) = 1/x: b^T u_l = (r0^T z0) e1^T T~^{-1} e1
+        assert abs(rhs[:, c] @ res.U[:, c] - res.r0z0[c] * np.linalg.inv(T)[0, 0]) \
+            < 1e-10 * abs(rhs[:, c] @ res.U[:, c])
+
+
+def test_slq_equals_dense_hutchinson_at_convergence():
+    # Run to full convergence: Gauss quadrature is exact, so the SLQ term equals
+    # (1/t) sum eps^T log(M) eps with M = P^{-1/2} A P^{-T/2},
+    # P^{-1/2} = (W + D^{-1})^{-1/2} B^{-T} (eq. P_VADU_prec).
+    n = 50
+    model, y, F = _problem(n=n, m=5, seed=3)
+    b, W, _ = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, L.Opts(cg_tol=1e-13))
+    opts = L.Opts(cg_tol=1e-13, num_probes=7, seed=5)
+    nll, info = L.neg_log_marglik(model, y, F, L.LIK_BERNOULLI_LOGIT, None, b, opts)
+    Bd = model.B.toarray()
+    Q = DR.dense_precision(Bd, model.D)
+    A = np.diag(W) + Q
+    Pih = np.diag((W + model.Dinv) ** -0.5) @ np.linalg.inv(Bd).T
+    M = Pih @ A @ Pih.T
+    Lm = DR.logm_spd(M)
+    eps = R.rademacher(5, R.TAG_SLQ, n, 7)
+    hutch = np.mean(np.einsum("ij,ik,kj->j", eps, Lm, eps))
+    assert abs(info["gamma"] - hutch) < 1e-9 * max(1.0, abs(hutch))
+    # weights: r0^T z0 = ||P^{-1/2} z||^2 = eps^T eps = n (Rademacher, VADU)
+    np.testing.assert_allclose(info["r0z0"], n, rtol=1e-12)
+
+
+def test_slq_statistical_bound():
+    # Thm 3.2 scale: the SLQ estimate lies within 5 standard deviations of the
+    # exact log det M; the Rademacher Hutchinson variance is
+    # 2 sum_{a != b} (log M)_ab^2 / t.
+    n, t = 70, 40
+    model, y, F = _problem(n=n, m=6, seed=4, kind=V.COV_MATERN32, theta=(1.0, 0.15))
+    b, W, _ = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, L.Opts(cg_tol=1e-12))
+    opts = L.Opts(cg_tol=1e-12, num_probes=t, seed=9)
+    _, info = L.neg_log_marglik(model, y, F, L.LIK_BERNOULLI_LOGIT, None, b, opts)
+    Bd = model.B.toarray()
+    A = np.diag(W) + DR.dense_precision(Bd, model.D)
+    Pih = np.diag((W + model.Dinv) ** -0.5) @ np.linalg.inv(Bd).T
+    Lm = DR.logm_spd(Pih @ A @ Pih.T)
+    off = Lm - np.diag(np.diag(Lm))
+    sd = np.sqrt(2.0 * np.sum(off ** 2) / t)
+    assert abs(info["gamma"] - np.trace(Lm)) <= 5 * sd + 1e-9
+
+
+def test_vadu_identity_factor_special_case():
+    # m = 0 gives B = I, so P_VADU = W + D^{-1} = A: CG stops after one
+    # iteration with T~ = [1] and the SLQ term vanishes (Sec. 3.1.1).
+    n = 40
+    model, y, F = _problem(n=n, m=0, seed=2)
+    b, W, st = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, L.Opts(cg_tol=1e-10))
+    assert all(c == 1 for c in st["cg_iters"])
+    opts = L.Opts(cg_tol=1e-10, num_probes=5)
+    nll, info = L.neg_log_marglik(model, y, F, L.LIK_BERNOULLI_LOGIT, None, b, opts)
+    assert np.all(info["cg_iters"] == 1)
+    assert abs(info["gamma"]) < 1e-12
+    np.testing.assert_allclose(info["logdet"], np.sum(np.log(1.0 + model.theta[0] * W)), rtol=1e-12)
+
+
+def test_theorem_3_1_eigenvalue_bounds():
+    # lambda_min(P^{-1}A) > min (D_i W_ii + 1)^{-1};
+    # lambda_l(P^{-1}A) <= (lambda_l(Sigma~) max W + 1) max (D_i W_ii + 1)^{-1}.
+    n = 90
+    model, y, F = _problem(n=n, m=5, seed=6, lik=L.LIK_POISSON, F=0.5)
+    b, W, _ = L.find_mode(model, y, F, L.LIK_POISSON, None, L.Opts(cg_tol=1e-10))
+    apply_A, apply_Pinv = L.vadu_ops(model, W)
+    lam = np.sort(np.linalg.eigvals(apply_Pinv(np.eye(n)) @ apply_A(np.eye(n))).real)[::-1]
+    Bd = model.B.toarray()
+    Binv = np.linalg.inv(Bd)
+    St = Binv @ np.diag(model.D) @ Binv.T
+    lS = np.sort(np.linalg.eigvalsh(St))[::-1]
+    q = 1.0 / (model.D * W + 1.0)
+    assert lam[-1] > q.min() * (1 - 1e-10)
+    assert np.all(lam <= (lS * W.max() + 1.0) * q.max() * (1 + 1e-9))
+
+
+# --------------------------------------------------------------------- Newton
+@pytest.mark.parametrize("lik", [L.LIK_BERNOULLI_LOGIT, L.LIK_POISSON])
+def test_mode_equals_dense_newton_and_zero_gradient(lik):
+    model, y, F = _problem(n=100, m=7, lik=lik, seed=7, F=(0.3 if lik == L.LIK_POISSON else 0.0))
+    b, W, st = L.find_mode(model, y, F, lik, None, L.Opts(cg_tol=1e-12, newton_tol=1e-14))
+    Q = DR.dense_precision(model.B, model.D)
+    lp, lg, lw = _liks(lik)
+    bd = DR.dense_mode(Q, y, F, lg, lw)
+    np.testing.assert_allclose(b, bd, rtol=1e-8, atol=1e-10)
+    # first-order condition of the mode: d log p / d b = Sigma~^{-1} b*
+    np.testing.assert_allclose(lg(y, F + b), Q @ b, atol=1e-8)
+
+
+def test_mode_lrac_equals_mode_vadu():
+    model, y, F = _problem(n=90, m=6, seed=8)
+    o1 = L.Opts(cg_tol=1e-12, newton_tol=1e-14)
+    o2 = L.Opts(cg_tol=1e-12, newton_tol=1e-14, precond=L.PRECOND_LRAC, lrac_rank=10)
+    b1, _, _ = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, o1)
+    b2, _, _ = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, o2)
+    np.testing.assert_allclose(b1, b2, rtol=1e-8, atol=1e-9)
+
+
+# ------------------------------------------------------------------------ NLL
+def test_gaussian_likelihood_exact_marginal():
+    # Laplace is exact for a Gaussian likelihood: with the SLQ term replaced by
+    # the exact log det M, the NLL equals -log N(y; F, Sigma~ + tau2 I).
+    n, tau2 = 60, 0.25
+    model, y, F = _problem(n=n, m=5, lik=L.LIK_GAUSSIAN, seed=10)
+    opts = L.Opts(cg_tol=1e-12, newton_tol=1e-15, num_probes=4)
+    b, W, _ = L.find_mode(model, y, F, L.LIK_GAUSSIAN, tau2, opts)
+    nll, info = L.neg_log_marglik(model, y, F, L.LIK_GAUSSIAN, tau2, b, opts)
+    Bd = model.B.toarray()
+    Q = DR.dense_precision(Bd, model.D)
+    _, ldA = np.linalg.slogdet(np.diag(W) + Q)
+    exact_gamma = ldA - np.sum(np.log(W + model.Dinv)) + 2 * np.sum(np.log(np.diag(Bd)))
+    nll_exact = nll - 0.5 * info["gamma"] + 0.5 * exact_gamma
+    St = np.linalg.inv(Q)
+    ref = -multivariate_normal(mean=F, cov=St + tau2 * np.eye(n)).logpdf(y)
+    assert abs(nll_exact - ref) < 1e-8 * abs(ref)
+
+
+@pytest.mark.parametrize("precond", [L.PRECOND_VADU, L.PRECOND_LRAC])
+def test_logdet_matches_dense_within_probe_error(precond):
+    # log det(Sigma~ W + I) estimated with t probes lies within 5 standard
+    # errors (sample sd of the per-probe terms / sqrt t) of the dense value.
+    n, t = 80, 64
+    model, y, F = _problem(n=n, m=6, seed=11, kind=V.COV_MATERN32, theta=(1.0, 0.2))
+    opts = L.Opts(cg_tol=1e-11, newton_tol=1e-14, num_probes=t, seed=3, precond=precond,
+                  lrac_rank=12)
+    b, W, _ = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, opts)
+    nll, info = L.neg_log_marglik(model, y, F, L.LIK_BERNOULLI_LOGIT, None, b, opts)
+    Q = DR.dense_precision(model.B, model.D)
+    _, ld1 = np.linalg.slogdet(np.diag(W) + Q)
+    _, ld0 = np.linalg.slogdet(Q)
+    exact = ld1 - ld0
+    per_probe = info["r0z0"] * info["quad"]
+    se = np.std(per_probe, ddof=1) / np.sqrt(t)
+    assert abs(info["logdet"] - exact) <= 5 * se + 1e-8
+
+
+def test_lrac_full_rank_special_case():
+    # k = n and m = n-1: L L^T = Sigma = Sigma~, so P_LRAC equals the operator
+    # Sigma~ + W^{-1}; CG converges in one iteration and log det P matches
+    # slogdet(Sigma + W^{-1}) (Woodbury / determinant lemma, Sec. 3.1.2).
+    n = 40
+    model, y, F = _problem(n=n, m=n - 1, seed=12)
+    Lk = L.pivoted_cholesky(model.coords, model.kind, model.theta, n)
+    S = V.dense_covariance(model.coords, model.kind, *model.theta)
+    np.testing.assert_allclose(Lk @ Lk.T, S, atol=1e-9)
+    W = L.lik_W(L.LIK_BERNOULLI_LOGIT, y, np.full(n, 0.3))
+    apply_A, apply_Pinv, P = L.lrac_ops(model, W, Lk)
+    _, ref = np.linalg.slogdet(S + np.diag(1.0 / W))
+    assert abs(P.logdet - ref) < 1e-9 * abs(ref)
+    res = L.pcg(apply_A, apply_Pinv, np.random.default_rng(0).standard_normal(n), 1e-7, 50)
+    assert res.iters[0] == 1
+
+
+def test_pivoted_cholesky_pivots_and_residual():
+    # pivots pick the largest residual diagonal; the residual trace decreases
+    n = 60
+    X = np.random.default_rng(13).uniform(size=(n, 2))
+    S = V.dense_covariance(X, V.COV_MATERN32, 1.0, 0.3)
+    prev = np.trace(S)
+    for k in (1, 5, 20):
+        Lk = L.pivoted_cholesky(X, V.COV_MATERN32, (1.0, 0.3), k)
+        Rm = S - Lk @ Lk.T
+        assert np.all(np.linalg.eigvalsh(Rm) > -1e-10)     # Sigma - L L^T is PSD
+        assert np.trace(Rm) < prev
+        prev = np.trace(Rm)
+    assert np.argmax(np.abs(L.pivoted_cholesky(X, V.COV_MATERN32, (1.0, 0.3), 1)[:, 0])) == 0
+
+
+# ------------------------------------------------------------------- gradient
+def _dense_vl_nll(X, nbr, kind, theta, y, F, lik):
+    A, D = V.factor(X, nbr, kind, theta)
+    Q = DR.dense_precision(V.sparse_B(A, nbr), D)
+    lp, lg, lw = _liks(lik)
+    return DR.dense_nll(Q, y, F, lp, lg, lw)[0]
+
+
+@pytest.mark.parametrize("kind", [V.COV_EXPONENTIAL, V.COV_MATERN32])
+def test_theta_gradient_matches_finite_differences(kind):
+    # STE gradient with VADU control variates (App. A.3, A.4.1) against central
+    # differences of the exact (dense) Vecchia-Laplace NLL, within 5 standard
+    # errors over independent probe sets.
+    n, m = 45, 5
+    model, y, F = _problem(n=n, m=m, seed=14, kind=kind, theta=(1.2, 0.25), deriv=True)
+    opts0 = L.Opts(cg_tol=1e-12, newton_tol=1e-15)
+    b, W, _ = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, opts0)
+    grads = []
+    for seed in range(8):
+        opts = L.Opts(cg_tol=1e-12, newton_tol=1e-15, num_probes=400, seed=seed)
+        _, info = L.neg_log_marglik(model, y, F, L.LIK_BERNOULLI_LOGIT, None, b, opts,
+                                    want_grad=True)
+        grads.append(info["grad"])
+    grads = np.array(grads)
+    g_mean = grads.mean(axis=0)
+    g_se = grads.std(axis=0, ddof=1) / np.sqrt(len(grads))
+    fd = []
+    for k, h in enumerate([1e-5, 1e-6]):
+        e = np.zeros(2)
+        e[k] = h
+        th = np.array(model.theta)
+        fp = _dense_vl_nll(model.coords, model.nbr, kind, th + e, y, F, L.LIK_BERNOULLI_LOGIT)
+        fm = _dense_vl_nll(model.coords, model.nbr, kind, th - e, y, F, L.LIK_BERNOULLI_LOGIT)
+        fd.append((fp - fm) / (2 * h))
+    fd = np.array(fd)
+    assert np.all(np.abs(g_mean - fd) <= 5 * g_se + 1e-5 * (1 + np.abs(fd))), (g_mean, fd, g_se)
+
+
+def test_control_variate_does_not_change_the_mean():
+    # h - c r has the same mean as h: compare the c = optimal estimate with the
+    # c = 0 estimate through the identity E[r] = tr(P^{-1} dP) (App. A.4.1).
+    n, t = 50, 3000
+    model, y, F = _problem(n=n, m=5, seed=15, deriv=True)
+    b, W, _ = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, L.Opts(cg_tol=1e-12))
+    opts = L.Opts(cg_tol=1e-12, num_probes=t, seed=1)
+    _, info = L.neg_log_marglik(model, y, F, L.LIK_BERNOULLI_LOGIT, None, b, opts,
+                                want_grad=True)
+    # exact tr(A^{-1} dA) for the log det derivative (dense)
+    Bd = model.B.toarray()
+    Q = DR.dense_precision(Bd, model.D)
+    A = np.diag(W) + Q
+    for k in range(2):
+        dBd = model.dB[k].toarray()
+        dD = model.dD[k]
+        Di = model.Dinv
+        dQ = dBd.T @ np.diag(Di) @ Bd + Bd.T @ np.diag(Di) @ dBd - Bd.T @ np.diag(Di * Di * dD) @ Bd
+        exact = np.sum(dD * Di) + np.trace(np.linalg.solve(A, dQ))
+        assert abs(info[f"dlogdet_{k}"] - exact) < 0.05 * (1 + abs(exact))
+        # each STE piece is unbiased for its own trace:
+        # E[h] = tr(A^{-1} dA), E[r] = tr(P^{-1} dP) with
+        # P = B^T (W + D^{-1}) B (eq. P_VADU)
+        h, r = info[f"h_{k}"], info[f"r_{k}"]
+        trA = np.trace(np.linalg.solve(A, dQ))
+        P = Bd.T @ np.diag(W + Di) @ Bd
+        dP = dBd.T @ np.diag(W + Di) @ Bd + Bd.T @ np.diag(W + Di) @ dBd \
+            - Bd.T @ np.diag(Di * Di * dD) @ Bd
+        trP = np.trace(np.linalg.solve(P, dP))
+        assert abs(info[f"trP_{k}"] - trP) < 1e-9 * (1 + abs(trP))
+        assert abs(h.mean() - trA) <= 5 * h.std(ddof=1) / np.sqrt(t) + 1e-9
+        assert abs(r.mean() - trP) <= 5 * r.std(ddof=1) / np.sqrt(t) + 1e-9
+        # per probe, against the dense definitions h(z) = (A^{-1}z)^T dA P^{-1}z
+        # and r(z) = (P^{-1}z)^T dP P^{-1}z with z = B^T (W+D^{-1})^{1/2} eps
+        eps = R.rademacher(1, R.TAG_SLQ, n, 5)
+        Z = Bd.T @ (np.sqrt(W + Di)[:, None] * eps)
+        hd = np.einsum("ij,ij->j", np.linalg.solve(A, Z), dQ @ np.linalg.solve(P, Z))
+        rd = np.einsum("ij,ij->j", np.linalg.solve(P, Z), dP @ np.linalg.solve(P, Z))
+        np.testing.assert_allclose(h[:5], hd, rtol=1e-8, atol=1e-10)
+        np.testing.assert_allclose(r[:5], rd, rtol=1e-8, atol=1e-10)
+
+
+# ----------------------------------------------------------------- prediction
+def test_prediction_textbook_limit():
+    # m = n-1 and m_p = n: the Vecchia approximation is exact, so the
+    # predictive mean is k_p^T Sigma^{-1} b* and the variance is
+    # k_pp - k_p^T (Sigma + W^{-1})^{-1} k_p.  The simulated variance lies
+    # within 5 sd of it with sd = sqrt(2/s) (var - D_p) (Prop. 3.3).
+    n, npred, s = 60, 12, 4000
+    model, y, F = _problem(n=n, m=n - 1, seed=16)
+    Xp = np.random.default_rng(17).uniform(size=(npred, 2))
+    opts = L.Opts(cg_tol=1e-12, newton_tol=1e-15, num_pred_samples=s, pred_cg_tol=1e-12,
+                  seed=4)
+    b, W, _ = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, opts)
+    model.m = n      # prediction conditions on all n training points
+    mean, var, info = L.predict(model, Xp, None, b, W, opts, chunk=1000)
+    S = V.dense_covariance(model.coords, model.kind, *model.theta)
+    Kp = V.dense_covariance(Xp, model.kind, *model.theta, coords2=model.coords)
+    np.testing.assert_allclose(mean, Kp @ np.linalg.solve(S, b), rtol=1e-7, atol=1e-8)
+    exact = model.theta[0] - np.einsum("pi,pi->p", Kp, np.linalg.solve(S + np.diag(1 / W), Kp.T).T)
+    sd = np.sqrt(2.0 / s) * (exact - info["Dp"])
+    assert np.all(np.abs(var - exact) <= 5 * sd + 1e-10)
+
+
+def test_prediction_variance_formula_small_m():
+    # General m: the simulated variance is unbiased for D_p + diag(A_p A^{-1}
+    # A_p^T) (eq. latentpostpredictive with B_p = I).
+    n, npred, s = 120, 15, 3000
+    model, y, F = _problem(n=n, m=6, seed=18, kind=V.COV_MATERN32, theta=(1.0, 0.2))
+    Xp = np.random.default_rng(19).uniform(size=(npred, 2))
+    opts = L.Opts(cg_tol=1e-12, newton_tol=1e-15, num_pred_samples=s, pred_cg_tol=1e-12,
+                  seed=2)
+    b, W, _ = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, opts)
+    mean, var, info = L.predict(model, Xp, None, b, W, opts, chunk=1500)
+    Ap = np.zeros((npred, n))
+    for p in range(npred):
+        Ap[p, info["nbr_p"][p]] = info["Ap"][p]
+    A = np.diag(W) + DR.dense_precision(model.B, model.D)
+    exact = info["Dp"] + np.einsum("pi,pi->p", Ap, np.linalg.solve(A, Ap.T).T)
+    np.testing.assert_allclose(mean, Ap @ b, rtol=1e-12, atol=1e-13)
+    sd = np.sqrt(2.0 / s) * (exact - info["Dp"])
+    assert np.all(np.abs(var - exact) <= 5 * sd + 1e-10)

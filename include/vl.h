@@ -1,0 +1,204 @@
+/*
+ * vl.h -- C ABI of the MI355X (gfx950) library for iterative Vecchia-Laplace
+ * inference in latent Gaussian process models.
+ *
+ * The operations follow Kuendig & Sigrist, "Iterative Methods for
+ * Vecchia-Laplace Approximations for Latent Gaussian Process Models"
+ * (arXiv 2310.12000):
+ *   - Vecchia factor B, D of the prior precision B^T D^{-1} B   (Sec. 2.1)
+ *   - Newton mode finding with preconditioned CG                (Sec. 2.2,
+ *     eq. newton; Sec. 3, eqs. pcls1 / pcls2; appendix CG algorithm)
+ *   - SLQ negative log-marginal likelihood and STE gradient     (eq. VLA_loss,
+ *     eqs. logdetsplit / logdetsplit2 / def_SLQ / grad_STE; App. A.3, A.4)
+ *   - VADU and LRAC preconditioners                             (Sec. 3.1.1,
+ *     Sec. 3.1.2)
+ *   - predictive means and simulated variances                  (Sec. 2.2.1,
+ *     eq. latentpostpredictive; Sec. 3.3.1, Alg. simAlgo)
+ *
+ * Conventions (all entry points):
+ *   - Arrays marked "device" are device pointers on the GPU the model was
+ *     built on, addressed in the caller's point order (row i = i-th location
+ *     of the ordering).  Arrays marked "host" are ordinary host memory.
+ *   - Floating point is IEEE FP64, matrices row-major (n x t means element
+ *     (i, c) at i * t + c).
+ *   - The caller owns every input and output buffer; the library never frees
+ *     them and never keeps a pointer to them after the call returns, except
+ *     for the stream passed to vl_build_vecchia.
+ *   - The model handle owns its device state (coordinates, neighbour sets,
+ *     B, B^T, D, derivatives, mode, W, workspaces) until vl_free.
+ *   - Work is enqueued on the model's HIP stream.  Calls that return host
+ *     scalars (nll, gradient, statistics) synchronise that stream; other
+ *     calls return once their work is enqueued, unless stated otherwise.
+ *   - One model must not be used from two host threads at once.  Distinct
+ *     models may be used concurrently (each with its own stream).
+ *   - Every call returns a vl_status and never aborts the process.  On an
+ *     error the outputs are unspecified unless stated otherwise;
+ *     vl_last_error() gives a message.
+ */
+#ifndef VL_H
+#define VL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vl_model vl_model;
+
+typedef enum {
+  VL_OK = 0,
+  VL_ERR_INVALID_ARG = -1,    /* bad size, null pointer, unknown enum       */
+  VL_ERR_NOT_SPD = -2,        /* a neighbour covariance is not positive
+                                 definite (e.g. duplicate locations)        */
+  VL_ERR_NO_CONVERGENCE = -3, /* a CG or Newton loop hit its cap; outputs
+                                 are written and flagged in vl_stats        */
+  VL_ERR_OOM = -4,            /* device allocation failed                   */
+  VL_ERR_NONFINITE = -5,      /* NaN/Inf in inputs or intermediate results  */
+  VL_ERR_HIP = -6,            /* a HIP runtime call failed                  */
+  VL_ERR_STATE = -7,          /* call order violated (e.g. no mode yet)     */
+  VL_ERR_TIMEOUT = -8         /* a device-side wait exceeded its bound      */
+} vl_status;
+
+typedef enum { VL_COV_EXPONENTIAL = 0, VL_COV_MATERN32 = 1 } vl_cov;
+
+typedef enum {
+  VL_LIK_BERNOULLI_LOGIT = 0, /* y in {0,1}, mu = logit P(y = 1)            */
+  VL_LIK_POISSON_LOG = 1,     /* y in {0,1,2,...}, mu = log E[y]            */
+  VL_LIK_GAUSSIAN = 2         /* y real, aux[0] = noise variance tau^2      */
+} vl_lik;
+
+typedef enum { VL_PREC_VADU = 0, VL_PREC_LRAC = 1 } vl_precond;
+typedef enum { VL_FP64 = 0, VL_MIXED = 1 } vl_precision;
+
+/* Options.  vl_default_opts fills the paper's defaults (Sec. 4.1): t = 50
+ * probes, LRAC rank k = 50, CG tolerance 1e-2 for likelihoods and 1e-3 for
+ * predictive variances, s = 2000 simulation samples. */
+typedef struct {
+  int max_newton;          /* Newton iteration cap (default 100)               */
+  double newton_tol;       /* stop when |Psi_new - Psi_old| <= tol |Psi_old|   */
+  int max_cg;              /* CG iteration cap per solve (default 1000)        */
+  double cg_tol;           /* absolute tolerance on ||r||_2, likelihood solves */
+  double pred_cg_tol;      /* absolute tolerance on ||r||_2, variance solves   */
+  int num_probes;          /* t, Rademacher probes for SLQ / STE               */
+  int num_pred_samples;    /* s, simulation samples for predictive variances   */
+  uint64_t seed;           /* probe seed (counter-based SplitMix64)            */
+  int precond;             /* vl_precond                                       */
+  int lrac_rank;           /* k of the LRAC preconditioner                     */
+  int precision;           /* vl_precision                                     */
+  int pred_tile;           /* columns per predictive-variance CG block
+                              (0 = all s at once)                              */
+} vl_opts;
+
+/* Per-call statistics (host struct, filled by the call that receives it). */
+typedef struct {
+  int newton_iters;        /* Newton iterations of the last vl_find_mode       */
+  int cg_iters_total;      /* CG iterations summed over solves (per column for
+                              block solves: the maximum over columns)          */
+  int cg_iters_max;        /* largest iteration count of one column            */
+  int hit_cap;             /* 1 if a loop stopped at its cap                   */
+  double t_ms;             /* wall time of the call                            */
+} vl_stats;
+
+/* ---------------------------------------------------------------------- */
+void vl_default_opts(vl_opts* o);
+const char* vl_status_string(vl_status s);
+/* Message of the most recent failing call on this host thread. */
+const char* vl_last_error(void);
+
+/* Build the Vecchia approximation of the prior (Sec. 2.1).
+ *   coords     device, n x 2 locations in the ordering of the approximation
+ *              (the row order IS the ordering; the paper's random ordering
+ *              is the caller's order of i.i.d. locations, Sec. 4.1)
+ *   n          number of locations, 1 <= n < 2^31 / max(m, 1)
+ *   m          neighbours per point, 0 <= m <= 31; N(i) = the min(i, m)
+ *              nearest among locations 0..i-1 (ties: smaller index first)
+ *   cov        vl_cov; theta_host = {sigma2 > 0, range rho > 0} (host)
+ *   hip_stream hipStream_t to enqueue on (NULL = default stream)
+ *   want_deriv nonzero: also keep dB/dtheta, dD/dtheta (App. derivatives of
+ *              the Vecchia-approximated precision) for vl_neg_log_marglik's
+ *              gradient
+ *   out        receives the handle
+ * Runs neighbour search, the batched neighbour Cholesky (A_i, D_i), and the
+ * transpose B^T.  Synchronises the stream.  VL_ERR_NOT_SPD if some D_i <= 0
+ * or a neighbour covariance fails its Cholesky. */
+vl_status vl_build_vecchia(const double* coords, int64_t n, int m, int cov,
+                           const double* theta_host, void* hip_stream,
+                           int want_deriv, vl_model** out);
+
+/* Recompute A_i, D_i (and derivatives if built with them) at a new theta,
+ * reusing neighbour sets and B^T structure.  Invalidates the mode. */
+vl_status vl_set_theta(vl_model* h, const double* theta_host);
+
+/* Newton mode finding (eq. newton) from b = 0.
+ *   y        device, n responses
+ *   F        device, n offsets F(X) (NULL = 0)
+ *   lik      vl_lik; aux_host: likelihood auxiliary parameters (host;
+ *            Gaussian: {tau2}; may be NULL otherwise)
+ *   mode_out device, n (NULL = keep it only inside the model)
+ * Keeps y, F, b*, W(b*) in the model for the calls below.  Synchronises. */
+vl_status vl_find_mode(vl_model* h, const double* y, const double* F, int lik,
+                       const double* aux_host, const vl_opts* o,
+                       double* mode_out, vl_stats* st);
+
+/* SLQ negative log-marginal likelihood at the stored mode (eq. VLA_loss).
+ *   nll_host        host, 1 double
+ *   grad_theta_host host, 2 doubles d/d(sigma2, rho) (NULL = skip; needs
+ *                   want_deriv at build and the VADU preconditioner)
+ * Synchronises. */
+vl_status vl_neg_log_marglik(vl_model* h, const vl_opts* o, double* nll_host,
+                             double* grad_theta_host, vl_stats* st);
+
+/* Predictive latent mean and simulated variance (eq. latentpostpredictive,
+ * Alg. simAlgo) at n_p new locations conditioned on the m nearest training
+ * locations.
+ *   coords_p device, n_p x 2
+ *   Fp       device, n_p offsets (NULL = 0)
+ *   mean_out device, n_p
+ *   var_out  device, n_p (NULL = means only)
+ * Requires a mode.  Synchronises. */
+vl_status vl_predict(vl_model* h, const double* coords_p, int64_t n_p,
+                     const double* Fp, const vl_opts* o, double* mean_out,
+                     double* var_out, vl_stats* st);
+
+/* Copy internal state out, for inspection and tests.  `which`:
+ *   0 neighbours   int32  n x m (-1 padded)
+ *   1 B values     double n x m (entries -A_i; 0 in padded slots)
+ *   2 D            double n
+ *   3 mode b*      double n
+ *   4 W(b*)        double n
+ *   5 dB/dsigma2   double n x m     6 dB/drho  double n x m
+ *   7 dD/dsigma2   double n         8 dD/drho  double n
+ *   9 CG iteration counts of the last block solve, int32 (count = columns)
+ *  10 CG iteration counts of the Newton solves of the last vl_find_mode,
+ *     int32 (count = Newton iterations)
+ *  11 SLQ quadratures e1^T log(T~_i) e1 of the last vl_neg_log_marglik,
+ *     double t
+ *  12 r0^T z0 weights of the last vl_neg_log_marglik, double t
+ *  13 prediction neighbours of the last vl_predict, int32 n_p x m
+ *  14 prediction A_p (entries +A_p), double n_p x m;  15 D_p, double n_p
+ * dst is a device pointer; `bytes` must equal the size of the array.
+ * Synchronises. */
+vl_status vl_export(vl_model* h, int which, void* dst, size_t bytes);
+
+/* Size in elements of an exportable array (see vl_export), or -1. */
+int64_t vl_export_count(vl_model* h, int which);
+
+/* Sparse products with the Vecchia factor over a block of t columns
+ * (device, row-major n x t):  Y = B X (transpose = 0) or Y = B^T X
+ * (transpose = 1).  X and Y must not overlap.  Asynchronous. */
+vl_status vl_spmm(vl_model* h, int transpose, const double* X, double* Y, int t);
+
+/* Triangular solves with the Vecchia factor over t columns (device,
+ * row-major n x t):  B Y = X (transpose = 0) or B^T Y = X (transpose = 1).
+ * X and Y must not overlap.  Asynchronous. */
+vl_status vl_trsm(vl_model* h, int transpose, const double* X, double* Y, int t);
+
+/* Release the handle and all its device memory. */
+void vl_free(vl_model* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VL_H */

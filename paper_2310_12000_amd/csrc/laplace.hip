@@ -1,0 +1,602 @@
+// Vecchia-Laplace quantities on top of the sparse kernels and block CG:
+//   Newton mode finding                       eq. (newton), Sec. 2.2
+//   SLQ negative log-marginal likelihood      eqs. (VLA_loss), (logdetsplit),
+//                                             (def_SLQ); VADU log det P =
+//                                             log det(W + D^{-1}) (Sec. 3.1.1)
+//   STE theta-gradient with control variates  eq. (grad_STE); App. A.3 and the
+//                                             VADU formulas of App. A.4.1
+//   predictive means / simulated variances    eq. (latentpostpredictive),
+//                                             Alg. simAlgo (Sec. 3.3.1)
+#include "vl_internal.h"
+#include "vl_ops.h"
+#include "vl_laplace.h"
+
+namespace vl {
+
+// ------------------------------------------------------------ likelihoods
+__device__ __forceinline__ double sigmoid(double x) { return 0.5 * (1.0 + tanh(0.5 * x)); }
+
+__device__ __forceinline__ double lik_logp(int lik, double y, double mu, double aux) {
+  if (lik == VL_LIK_BERNOULLI_LOGIT) {
+    // y mu - log(1 + e^mu)
+    const double sp = fmax(mu, 0.0) + log1p(exp(-fabs(mu)));
+    return y * mu - sp;
+  }
+  if (lik == VL_LIK_POISSON_LOG) return y * mu - exp(mu) - lgamma(y + 1.0);
+  const double r = y - mu;
+  return -0.5 * r * r / aux - 0.5 * log(6.283185307179586 * aux);
+}
+
+// g = d log p / d mu, W = -d^2 log p / d mu^2, dW = d W / d mu
+__device__ __forceinline__ void lik_derivs(int lik, double y, double mu, double aux, double* g,
+                                           double* W, double* dW) {
+  if (lik == VL_LIK_BERNOULLI_LOGIT) {
+    const double p = sigmoid(mu);
+    *g = y - p;
+    *W = p * (1.0 - p);
+    *dW = p * (1.0 - p) * (1.0 - 2.0 * p);
+  } else if (lik == VL_LIK_POISSON_LOG) {
+    const double e = exp(mu);
+    *g = y - e;
+    *W = e;
+    *dW = e;
+  } else {
+    *g = (y - mu) / aux;
+    *W = 1.0 / aux;
+    *dW = 0.0;
+  }
+}
+
+// Per row: g, W, rhs = W b + g, s = 1 / (W + D^{-1}), sq = sqrt(W + D^{-1}),
+// dW.  Any output may be null.
+__global__ void lik_rows_kernel(int64_t n, int lik, double aux, const double* __restrict__ y,
+                                const double* __restrict__ F, const double* __restrict__ b,
+                                const double* __restrict__ dinv, double* __restrict__ g_out,
+                                double* __restrict__ W_out, double* __restrict__ rhs_out,
+                                double* __restrict__ s_out, double* __restrict__ sq_out,
+                                double* __restrict__ dW_out, int* __restrict__ status) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double bi = b ? b[i] : 0.0;
+  const double mu = (F ? F[i] : 0.0) + bi;
+  double g, W, dW;
+  lik_derivs(lik, y[i], mu, aux, &g, &W, &dW);
+  if (!isfinite(g) || !isfinite(W)) raise_error(status, kErrNonfinite);
+  if (g_out) g_out[i] = g;
+  if (W_out) W_out[i] = W;
+  if (rhs_out) rhs_out[i] = W * bi + g;
+  const double wd = W + dinv[i];
+  if (s_out) s_out[i] = 1.0 / wd;
+  if (sq_out) sq_out[i] = sqrt(wd);
+  if (dW_out) dW_out[i] = dW;
+}
+
+Status lik_rows(Model& M, const double* b, double* g, double* W, double* rhs, double* s,
+                double* sq, double* dW) {
+  const int tb = 256;
+  hipLaunchKernelGGL(lik_rows_kernel, dim3((unsigned)((M.n + tb - 1) / tb)), dim3(tb), 0,
+                     M.stream, M.n, M.lik, M.aux, M.y.p, M.F.p, b, M.dinv.p, g, W, rhs, s, sq,
+                     dW, M.status);
+  return check_launch("likelihood rows");
+}
+
+// Sums over rows (t = 1 chunk grid), written as nsum partial arrays:
+//   0: log p(y | F + b)   1: D^{-1} (B b)^2   2: log D   3: log(W + D^{-1})
+__global__ __launch_bounds__(256) void laplace_terms_kernel(
+    ChunkGrid g, int lik, double aux, const double* __restrict__ y,
+    const double* __restrict__ F, const double* __restrict__ b, const double* __restrict__ Bb,
+    const double* __restrict__ D, const double* __restrict__ W, double* __restrict__ part) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  CHUNK_LOOP_BEGIN(g)
+  (void)c;
+  const double mu = (F ? F[i] : 0.0) + b[i];
+  s0 += lik_logp(lik, y[i], mu, aux);
+  const double di = D[i];
+  s1 += Bb[i] * Bb[i] / di;
+  if (W) {
+    s2 += log(di);
+    s3 += log(W[i] + 1.0 / di);
+  }
+  CHUNK_LOOP_END
+  block_colsum(g, s0, part);
+  block_colsum(g, s1, part + g.nchunk);
+  block_colsum(g, s2, part + 2 * g.nchunk);
+  block_colsum(g, s3, part + 3 * g.nchunk);
+}
+
+// sums[k] = sum of the k-th partial array (nchunk entries each), in order
+__global__ void sum_parts_kernel(const double* __restrict__ part, int nchunk, int nsum,
+                                 double* __restrict__ out) {
+  const int k = threadIdx.x;
+  if (k >= nsum) return;
+  double s = 0.0;
+  for (int j = 0; j < nchunk; ++j) s += part[(int64_t)k * nchunk + j];
+  out[k] = s;
+}
+
+static Status host_sums(Model& M, const double* part, int nchunk, int nsum, double* out) {
+  VL_TRY(M.red_out.reserve(64));
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(64), 0, M.stream, part, nchunk, nsum,
+                     M.red_out.p);
+  VL_TRY(check_launch("sums"));
+  VL_HIP(hipMemcpyAsync(out, M.red_out.p, sizeof(double) * nsum, hipMemcpyDeviceToHost,
+                        M.stream));
+  return sync_stream(M.stream);
+}
+
+// log p(y | F + b) summed, and b^T Sigma~^{-1} b = ||D^{-1/2} B b||^2, plus
+// (with W) sum log D and sum log(W + D^{-1}).
+static Status laplace_terms(Model& M, const double* b, const double* W, double out[4]) {
+  VL_TRY(M.vec_d.reserve(M.n));
+  VL_TRY(spmm_b(M, b, M.vec_d.p, 1, nullptr));
+  ChunkGrid g = ChunkGrid::of(M.n, 1);
+  VL_TRY(M.red_part.reserve(static_cast<size_t>(g.nchunk) * 8));
+  hipLaunchKernelGGL(laplace_terms_kernel, dim3(g.nchunk, 1), dim3(256), 0, M.stream, g, M.lik,
+                     M.aux, M.y.p, M.F.p, b, M.vec_d.p, M.dval.p, W, M.red_part.p);
+  VL_TRY(check_launch("laplace terms"));
+  return host_sums(M, M.red_part.p, g.nchunk, 4, out);
+}
+
+// ------------------------------------------------------- VADU operators
+CgOps vadu_ops(const double* W, const double* sdiag) {
+  CgOps ops;
+  ops.apply = [W](Model& M, const double* H, double* V, double* Tmp, int t) -> Status {
+    // V = W o H + B^T (D^{-1} o (B H))
+    VL_TRY(spmm_b(M, H, Tmp, t, M.dinv.p));
+    return spmm_bt(M, Tmp, V, t, W, H);
+  };
+  ops.precond = [sdiag](Model& M, const double* R, double* Z, double* Y, int t) -> Status {
+    // Z = B^{-1} ((W + D^{-1})^{-1} o (B^{-T} R))
+    VL_TRY(trsm_bt_slot(M, R, Y, t, true, 0));
+    return trsm_b_slot(M, Y, Z, t, sdiag, true, 1);
+  };
+  return ops;
+}
+
+// ------------------------------------------------------------------ mode
+Status find_mode(Model& M, const vl_opts& o, vl_stats* st) {
+  const int64_t n = M.n;
+  VL_TRY(M.mode.reserve(n));
+  VL_TRY(M.W.reserve(n));
+  VL_TRY(M.g.reserve(n));
+  VL_TRY(M.vec_a.reserve(n));  // rhs
+  VL_TRY(M.vec_b.reserve(n));  // (W + D^{-1})^{-1}
+  VL_TRY(fill_double(M.mode.p, 0.0, n, M.stream));
+  double terms[4];
+  VL_TRY(laplace_terms(M, M.mode.p, nullptr, terms));
+  double psi_old = terms[0] - 0.5 * terms[1];
+  M.newton_cg_iters.clear();
+  int it = 0;
+  bool converged = false;
+  int cg_total = 0, cg_max = 0;
+  bool cg_cap = false;
+  for (; it < o.max_newton;) {
+    VL_TRY(lik_rows(M, M.mode.p, M.g.p, M.W.p, M.vec_a.p, M.vec_b.p, nullptr, nullptr));
+    CgOps ops = vadu_ops(M.W.p, M.vec_b.p);
+    VL_TRY(cg_solve(M, M.cg1, ops, 1, M.vec_a.p, o.cg_tol, o.max_cg, false));
+    VL_TRY(copy_d2d(M.mode.p, M.cg1.U.p, sizeof(double) * n, M.stream));
+    const int ci = M.cg1.host_iters[0];
+    M.newton_cg_iters.push_back(ci);
+    cg_total += ci;
+    if (ci > cg_max) cg_max = ci;
+    if (ci >= o.max_cg) cg_cap = true;
+    ++it;
+    VL_TRY(laplace_terms(M, M.mode.p, nullptr, terms));
+    const double psi_new = terms[0] - 0.5 * terms[1];
+    if (!std::isfinite(psi_new)) return Status::make(VL_ERR_NONFINITE, "Newton objective is not finite");
+    if (std::fabs(psi_new - psi_old) <= o.newton_tol * std::fabs(psi_old)) {
+      converged = true;
+      break;
+    }
+    psi_old = psi_new;
+  }
+  // W at the mode
+  VL_TRY(lik_rows(M, M.mode.p, M.g.p, M.W.p, nullptr, nullptr, nullptr, nullptr));
+  VL_TRY(read_status(M));
+  M.has_mode = true;
+  if (st) {
+    st->newton_iters = it;
+    st->cg_iters_total = cg_total;
+    st->cg_iters_max = cg_max;
+    st->hit_cap = (!converged || cg_cap) ? 1 : 0;
+  }
+  if (!converged || cg_cap)
+    return Status::make(VL_ERR_NO_CONVERGENCE, "Newton or CG stopped at its iteration cap");
+  return Status::ok();
+}
+
+// ----------------------------------------------------------- gradient
+// Per probe column c (t <= 64, one wave covers whole rows): with u = A^{-1} z,
+// v = P^{-1} z, Bu, Bv, dBu, dBv gathered once per row:
+//   h_rho = dBu' D^{-1} Bv + Bu' D^{-1} dBv - Bu' D^{-2} dD_rho Bv
+//   r_rho = 2 dBv' (W + D^{-1}) Bv - Bv' D^{-2} dD_rho Bv
+//   h_s2  = -Bu' D^{-2} dD_s2 Bv,   r_s2 = -Bv' D^{-2} dD_s2 Bv    (dB_s2 = 0)
+// and per row i the mu-derivative of the log-determinant (App. A.4.1):
+//   h_ic = dW_i u_ic v_ic,  r_ic = dW_i (B v)_ic^2,
+//   dlogdet/dmu_i = c_i dW_i / (W_i + 1/D_i) + mean_c (h_ic - c_i r_ic),
+// with c_i = Cov_c(h, r) / Var_c(r) (0 when Var_c(r) <= 1e-10 mean_c(r)^2);
+// dLdb_i = dlogdet/dmu_i / 2.
+__global__ __launch_bounds__(256) void grad_probe_kernel(
+    ChunkGrid g, int m, const int* __restrict__ nbr, const double* __restrict__ bval,
+    const double* __restrict__ dbval, const double* __restrict__ U,
+    const double* __restrict__ V, const double* __restrict__ D,
+    const double* __restrict__ dd_s2, const double* __restrict__ dd_rho,
+    const double* __restrict__ W, const double* __restrict__ dW, double* __restrict__ dLdb,
+    double* __restrict__ part) {
+  double h0 = 0.0, r0 = 0.0, h1 = 0.0, r1 = 0.0;
+  const int t = g.t;
+  const int lpr = 1 << g.L.lpr_log;
+  const int lane = threadIdx.x & 63;
+  const int c = lane & (lpr - 1);
+  const int _w = threadIdx.x >> 6;
+  const int _sub = lane >> g.L.lpr_log;
+  const int64_t r0w = (int64_t)blockIdx.x * g.rpc;
+  int64_t r1w = r0w + g.rpc;
+  if (r1w > g.n) r1w = g.n;
+  const int64_t step = 4LL << g.L.rpw_log;
+  for (int64_t base = r0w + ((int64_t)_w << g.L.rpw_log); base < r1w; base += step) {
+    const int64_t i = base + _sub;
+    const bool valid = (i < r1w) && (c < t);
+    double hm = 0.0, rm = 0.0;
+    double wd = 1.0, dWi = 0.0;
+    if (valid) {
+      const int* nb = nbr + i * m;
+      const double* bv = bval + i * m;
+      const double* dbv = dbval + i * m;
+      const double ui = U[i * t + c], vi = V[i * t + c];
+      double Bu = ui, Bv = vi, dBu = 0.0, dBv = 0.0;
+      for (int k = 0; k < m; ++k) {
+        const int j = nb[k];
+        if (j < 0) break;
+        const double uj = U[(int64_t)j * t + c], vj = V[(int64_t)j * t + c];
+        Bu += bv[k] * uj;
+        Bv += bv[k] * vj;
+        dBu += dbv[k] * uj;
+        dBv += dbv[k] * vj;
+      }
+      const double di = 1.0 / D[i];
+      const double di2 = di * di;
+      wd = W[i] + di;
+      dWi = dW[i];
+      h1 += dBu * di * Bv + Bu * di * dBv - Bu * di2 * dd_rho[i] * Bv;
+      r1 += 2.0 * dBv * wd * Bv - Bv * di2 * dd_rho[i] * Bv;
+      h0 += -Bu * di2 * dd_s2[i] * Bv;
+      r0 += -Bv * di2 * dd_s2[i] * Bv;
+      hm = dWi * ui * vi;
+      rm = dWi * Bv * Bv;
+    }
+    // per-row moments over the t columns held by the lpr lanes of this row
+    double sh = hm, sr = rm;
+    for (int o = 1; o < lpr; o <<= 1) {
+      sh += __shfl_xor(sh, o);
+      sr += __shfl_xor(sr, o);
+    }
+    const double mh = sh / t, mr = sr / t;
+    double vr = valid ? (rm - mr) * (rm - mr) : 0.0;
+    double cv = valid ? (hm - mh) * (rm - mr) : 0.0;
+    for (int o = 1; o < lpr; o <<= 1) {
+      vr += __shfl_xor(vr, o);
+      cv += __shfl_xor(cv, o);
+    }
+    if (valid && c == 0) {
+      vr /= (t - 1);
+      cv /= (t - 1);
+      const double cc = (vr > 1e-10 * mr * mr) ? cv / vr : 0.0;
+      dLdb[i] = 0.5 * (cc * dWi / wd + (mh - cc * mr));
+    }
+  }
+  block_colsum(g, h0, part);
+  block_colsum(g, r0, part + (int64_t)g.nchunk * t);
+  block_colsum(g, h1, part + 2 * (int64_t)g.nchunk * t);
+  block_colsum(g, r1, part + 3 * (int64_t)g.nchunk * t);
+}
+
+// Row sums (t = 1 grid) for the explicit and implicit theta-terms:
+// for k in {sigma2, rho}:
+//   quad_k = 2 dBb' D^{-1} Bb - Bb' D^{-2} dD_k Bb        (= b' dSigma~^{-1} b)
+//   impl_k = -(dBw' D^{-1} Bb + Bw' D^{-1} dBb - Bw' D^{-2} dD_k Bb)
+//   trD_k  = sum dD_k / D,   trP_k = -sum D^{-2} dD_k / (W + D^{-1})
+__global__ __launch_bounds__(256) void grad_rows_kernel(
+    ChunkGrid g, int m, const int* __restrict__ nbr, const double* __restrict__ bval,
+    const double* __restrict__ dbval, const double* __restrict__ b,
+    const double* __restrict__ wv, const double* __restrict__ D,
+    const double* __restrict__ dd_s2, const double* __restrict__ dd_rho,
+    const double* __restrict__ W, double* __restrict__ part) {
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  CHUNK_LOOP_BEGIN(g)
+  (void)c;
+  const int* nb = nbr + i * m;
+  const double* bv = bval + i * m;
+  const double* dbv = dbval + i * m;
+  double Bb = b[i], Bw = wv[i], dBb = 0.0, dBw = 0.0;
+  for (int k = 0; k < m; ++k) {
+    const int j = nb[k];
+    if (j < 0) break;
+    Bb += bv[k] * b[j];
+    Bw += bv[k] * wv[j];
+    dBb += dbv[k] * b[j];
+    dBw += dbv[k] * wv[j];
+  }
+  const double di = 1.0 / D[i];
+  const double di2 = di * di;
+  const double wd = W[i] + di;
+  const double d0 = dd_s2[i], d1 = dd_rho[i];
+  // sigma2: dB = 0
+  acc[0] += -Bb * di2 * d0 * Bb;
+  acc[1] += Bw * di2 * d0 * Bb;
+  acc[2] += d0 * di;
+  acc[3] += -di2 * d0 / wd;
+  // rho
+  acc[4] += 2.0 * dBb * di * Bb - Bb * di2 * d1 * Bb;
+  acc[5] += -(dBw * di * Bb + Bw * di * dBb - Bw * di2 * d1 * Bb);
+  acc[6] += d1 * di;
+  acc[7] += -di2 * d1 / wd;
+  CHUNK_LOOP_END
+  for (int k = 0; k < 8; ++k) block_colsum(g, acc[k], part + (int64_t)k * g.nchunk);
+}
+
+static double cv_weight(const std::vector<double>& h, const std::vector<double>& r) {
+  const size_t t = h.size();
+  double mh = 0.0, mr = 0.0;
+  for (size_t c = 0; c < t; ++c) {
+    mh += h[c];
+    mr += r[c];
+  }
+  mh /= t;
+  mr /= t;
+  double vr = 0.0, cv = 0.0;
+  for (size_t c = 0; c < t; ++c) {
+    vr += (r[c] - mr) * (r[c] - mr);
+    cv += (h[c] - mh) * (r[c] - mr);
+  }
+  vr /= (t - 1);
+  cv /= (t - 1);
+  return (vr > 1e-10 * mr * mr) ? cv / vr : 0.0;
+}
+
+static Status grad_theta(Model& M, const vl_opts& o, const double* sdiag, double* grad,
+                         GradInfo* info) {
+  const int t = M.cg.t;
+  const int64_t n = M.n;
+  if (t > 64) return Status::invalid("the gradient supports at most 64 probes");
+  if (t < 2) return Status::invalid("the gradient needs at least 2 probes");
+  VL_TRY(M.vec_c.reserve(n));   // dL/db
+  VL_TRY(M.dWv.reserve(n));
+  VL_TRY(lik_rows(M, M.mode.p, nullptr, nullptr, nullptr, nullptr, nullptr, M.dWv.p));
+  ChunkGrid g = ChunkGrid::of(n, t);
+  VL_TRY(M.red_part.reserve(static_cast<size_t>(g.nchunk) * t * 4 + 64));
+  hipLaunchKernelGGL(grad_probe_kernel, dim3(g.nchunk, 1), dim3(256), 0, M.stream, g, M.m,
+                     M.nbr.p, M.bval.p, M.dbval_rho.p, M.cg.U.p, M.cg.Z0.p, M.dval.p,
+                     M.dd_sigma2.p, M.dd_rho.p, M.W.p, M.dWv.p, M.vec_c.p, M.red_part.p);
+  VL_TRY(check_launch("grad probes"));
+  VL_TRY(M.red_out.reserve(4 * t + 64));
+  for (int k = 0; k < 4; ++k)
+    VL_TRY(reduce_chunks(M.stream, M.red_part.p + (int64_t)k * g.nchunk * t, g.nchunk, t,
+                         M.red_out.p + k * t));
+  std::vector<double> hr(4 * t);
+  VL_HIP(hipMemcpyAsync(hr.data(), M.red_out.p, sizeof(double) * 4 * t, hipMemcpyDeviceToHost,
+                        M.stream));
+  VL_TRY(sync_stream(M.stream));
+  // w = A^{-1} dL/db  (implicit derivative of the mode, eq. grad_mode_par)
+  CgOps ops = vadu_ops(M.W.p, sdiag);
+  VL_TRY(cg_solve(M, M.cg1, ops, 1, M.vec_c.p, o.cg_tol, o.max_cg, false));
+  info->grad_cg_iters = M.cg1.host_iters[0];
+  ChunkGrid g1 = ChunkGrid::of(n, 1);
+  VL_TRY(M.red_part.reserve(static_cast<size_t>(g1.nchunk) * 8 + 64));
+  hipLaunchKernelGGL(grad_rows_kernel, dim3(g1.nchunk, 1), dim3(256), 0, M.stream, g1, M.m,
+                     M.nbr.p, M.bval.p, M.dbval_rho.p, M.mode.p, M.cg1.U.p, M.dval.p,
+                     M.dd_sigma2.p, M.dd_rho.p, M.W.p, M.red_part.p);
+  VL_TRY(check_launch("grad rows"));
+  double rows[8];
+  VL_TRY(host_sums(M, M.red_part.p, g1.nchunk, 8, rows));
+  for (int k = 0; k < 2; ++k) {
+    std::vector<double> h(hr.begin() + (2 * k) * t, hr.begin() + (2 * k + 1) * t);
+    std::vector<double> r(hr.begin() + (2 * k + 1) * t, hr.begin() + (2 * k + 2) * t);
+    const double c = cv_weight(h, r);
+    double mean = 0.0;
+    for (int q = 0; q < t; ++q) mean += h[q] - c * r[q];
+    mean /= t;
+    const double quad = rows[4 * k + 0], impl = rows[4 * k + 1];
+    const double trD = rows[4 * k + 2], trP = rows[4 * k + 3];
+    const double dlogdet = trD + c * trP + mean;
+    grad[k] = 0.5 * quad + 0.5 * dlogdet + impl;
+    info->c[k] = c;
+    info->dlogdet[k] = dlogdet;
+    info->quad[k] = quad;
+    info->implicit[k] = impl;
+  }
+  return Status::ok();
+}
+
+// -------------------------------------------------------------- NLL (SLQ)
+Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, NllInfo* info) {
+  if (!M.has_mode) return Status::make(VL_ERR_STATE, "no mode: call vl_find_mode first");
+  if (grad && !M.deriv) return Status::make(VL_ERR_STATE, "model built without derivatives");
+  const int64_t n = M.n;
+  const int t = o.num_probes;
+  if (t < 1) return Status::invalid("num_probes must be positive");
+  VL_TRY(M.vec_a.reserve(n));  // sqrt(W + D^{-1})
+  VL_TRY(M.vec_b.reserve(n));  // (W + D^{-1})^{-1}
+  VL_TRY(lik_rows(M, M.mode.p, nullptr, M.W.p, nullptr, M.vec_b.p, M.vec_a.p, nullptr));
+  VL_TRY(M.rhs_blk.reserve(static_cast<size_t>(n) * t));
+  // z_i = B^T ((W + D^{-1})^{1/2} o eps_i), Cov(z_i) = P_VADU
+  VL_TRY(spmm_bt_probe(M, M.rhs_blk.p, t, M.vec_a.p, o.seed, kTagSlq, 0, 0, nullptr, 0, 0));
+  CgOps ops = vadu_ops(M.W.p, M.vec_b.p);
+  VL_TRY(cg_solve(M, M.cg, ops, t, M.rhs_blk.p, o.cg_tol, o.max_cg, grad != nullptr));
+  M.last_block_iters = M.cg.host_iters;
+  VL_TRY(M.red_out.reserve(2 * t + 64));
+  VL_TRY(tridiag_quadrature(M, M.cg, M.red_out.p));
+  M.last_quad.resize(t);
+  M.last_r0z0.resize(t);
+  VL_HIP(hipMemcpyAsync(M.last_quad.data(), M.red_out.p, sizeof(double) * t,
+                        hipMemcpyDeviceToHost, M.stream));
+  VL_HIP(hipMemcpyAsync(M.last_r0z0.data(), M.cg.r0z0.p, sizeof(double) * t,
+                        hipMemcpyDeviceToHost, M.stream));
+  VL_TRY(sync_stream(M.stream));
+  VL_TRY(read_status(M));
+  double gamma = 0.0;
+  for (int c = 0; c < t; ++c) gamma += M.last_r0z0[c] * M.last_quad[c];
+  gamma /= t;
+  double terms[4];
+  VL_TRY(laplace_terms(M, M.mode.p, M.W.p, terms));
+  const double logdet = terms[2] + terms[3] + gamma;
+  *nll = -terms[0] + 0.5 * terms[1] + 0.5 * logdet;
+  int cg_max = 0;
+  for (int v : M.cg.host_iters) cg_max = v > cg_max ? v : cg_max;
+  if (info) {
+    info->gamma = gamma;
+    info->logdet = logdet;
+    info->loglik = terms[0];
+    info->quadform = terms[1];
+    info->cg_iters_max = cg_max;
+  }
+  if (grad) {
+    GradInfo gi;
+    VL_TRY(grad_theta(M, o, M.vec_b.p, grad, &gi));
+    if (info) info->grad = gi;
+  }
+  if (cg_max >= o.max_cg)
+    return Status::make(VL_ERR_NO_CONVERGENCE, "CG stopped at its iteration cap");
+  return Status::ok();
+}
+
+// -------------------------------------------------------------- predict
+// omega_p = F_p - B_po b*, with B_po entries -A_p stored like B
+__global__ void pred_mean_kernel(int64_t np, int m, const int* __restrict__ nbr,
+                                 const double* __restrict__ bval, const double* __restrict__ b,
+                                 const double* __restrict__ Fp, double* __restrict__ mean) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  double acc = 0.0;
+  for (int k = 0; k < m; ++k) {
+    const int j = nbr[p * m + k];
+    if (j < 0) break;
+    acc += bval[p * m + k] * b[j];
+  }
+  mean[p] = (Fp ? Fp[p] : 0.0) - acc;
+}
+
+// z4 = B_po u for a block of tt columns; part[p * slices + slice] = sum_c z4^2
+__global__ __launch_bounds__(256) void pred_acc_kernel(int64_t np, int m, int tt, Lanes L,
+                                                       const int* __restrict__ nbr,
+                                                       const double* __restrict__ bval,
+                                                       const double* __restrict__ U,
+                                                       double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int64_t unit = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  if (unit >= units_of_hd(np, tt, L)) return;
+  const int64_t rg = unit / L.slices;
+  const int slice = static_cast<int>(unit - rg * L.slices);
+  const int sub = lane >> L.lpr_log;
+  const int lpr = 1 << L.lpr_log;
+  const int c = slice * 64 + (lane & (lpr - 1));
+  const int64_t p = (rg << L.rpw_log) + sub;
+  double z = 0.0;
+  if (p < np && c < tt) {
+    for (int k = 0; k < m; ++k) {
+      const int j = nbr[p * m + k];
+      if (j < 0) break;
+      z += bval[p * m + k] * U[(int64_t)j * tt + c];
+    }
+  }
+  double s = z * z;
+  for (int o = 1; o < lpr; o <<= 1) s += __shfl_xor(s, o);
+  if (p < np && (lane & (lpr - 1)) == 0) part[p * L.slices + slice] = s;
+}
+
+// acc_p += sum over slices
+__global__ void pred_acc_add_kernel(int64_t np, int slices, const double* __restrict__ part,
+                                    double* __restrict__ acc) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  double s = 0.0;
+  for (int k = 0; k < slices; ++k) s += part[p * slices + k];
+  acc[p] += s;
+}
+
+__global__ void pred_var_kernel(int64_t np, const double* __restrict__ Dp,
+                                const double* __restrict__ acc, double inv_s,
+                                double* __restrict__ var) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p < np) var[p] = Dp[p] + acc[p] * inv_s;
+}
+
+// sqrt(W), D^{-1/2}
+__global__ void pred_scales_kernel(int64_t n, const double* __restrict__ W,
+                                   const double* __restrict__ dinv, double* __restrict__ sw,
+                                   double* __restrict__ sd) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  sw[i] = sqrt(W[i]);
+  sd[i] = sqrt(dinv[i]);
+}
+
+Status predict(Model& M, const double* coords_p, int64_t np, const double* Fp,
+               const vl_opts& o, double* mean_out, double* var_out, PredInfo* info) {
+  if (!M.has_mode) return Status::make(VL_ERR_STATE, "no mode: call vl_find_mode first");
+  const int m = M.m;
+  VL_TRY(M.pred_nbr.reserve(static_cast<size_t>(np) * (m > 0 ? m : 1)));
+  VL_TRY(M.pred_bval.reserve(static_cast<size_t>(np) * (m > 0 ? m : 1)));
+  VL_TRY(M.pred_dval.reserve(np));
+  M.last_np = np;
+  if (np == 0) return Status::ok();
+  VL_TRY(knn_query(M, coords_p, np, M.pred_nbr.p));
+  VL_TRY(factor_rows(M, coords_p, np, M.pred_nbr.p, M.pred_bval.p, M.pred_dval.p, false,
+                     nullptr, nullptr, nullptr));
+  const int tb = 256;
+  const unsigned gp = static_cast<unsigned>((np + tb - 1) / tb);
+  hipLaunchKernelGGL(pred_mean_kernel, dim3(gp), dim3(tb), 0, M.stream, np, m, M.pred_nbr.p,
+                     M.pred_bval.p, M.mode.p, Fp, mean_out);
+  VL_TRY(check_launch("pred mean"));
+  if (!var_out) {
+    VL_TRY(sync_stream(M.stream));
+    return read_status(M);
+  }
+  const int s = o.num_pred_samples;
+  if (s < 1) return Status::invalid("num_pred_samples must be positive");
+  const int64_t n = M.n;
+  VL_TRY(M.vec_a.reserve(n));  // sqrt(W)
+  VL_TRY(M.vec_b.reserve(n));  // (W + D^{-1})^{-1}
+  VL_TRY(M.vec_c.reserve(n));  // D^{-1/2}
+  VL_TRY(lik_rows(M, M.mode.p, nullptr, M.W.p, nullptr, M.vec_b.p, nullptr, nullptr));
+  hipLaunchKernelGGL(pred_scales_kernel, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0,
+                     M.stream, n, M.W.p, M.dinv.p, M.vec_a.p, M.vec_c.p);
+  DevBuf<double> acc, part;
+  VL_TRY(acc.alloc(np));
+  VL_TRY(fill_double(acc.p, 0.0, np, M.stream));
+  const int tile = (o.pred_tile > 0 && o.pred_tile < s) ? o.pred_tile : s;
+  CgOps ops = vadu_ops(M.W.p, M.vec_b.p);
+  int cg_max = 0;
+  M.last_block_iters.clear();
+  for (int c0 = 0; c0 < s; c0 += tile) {
+    const int tt = (s - c0 < tile) ? (s - c0) : tile;
+    VL_TRY(M.rhs_blk.reserve(static_cast<size_t>(n) * tt));
+    // z3 = W^{1/2} z1 + B^T (D^{-1/2} o z2), z1, z2 standard normal
+    VL_TRY(spmm_bt_probe(M, M.rhs_blk.p, tt, M.vec_c.p, o.seed, kTagPredZ2, c0, 1, M.vec_a.p,
+                         kTagPredZ1, 1));
+    VL_TRY(cg_solve(M, M.cg, ops, tt, M.rhs_blk.p, o.pred_cg_tol, o.max_cg, false));
+    for (int v : M.cg.host_iters) {
+      cg_max = v > cg_max ? v : cg_max;
+      M.last_block_iters.push_back(v);
+    }
+    Lanes L = Lanes::of(tt);
+    VL_TRY(part.reserve(static_cast<size_t>(np) * L.slices));
+    const int64_t units = units_of_hd(np, tt, L);
+    hipLaunchKernelGGL(pred_acc_kernel, dim3((unsigned)((units + 3) / 4)), dim3(256), 0,
+                       M.stream, np, m, tt, L, M.pred_nbr.p, M.pred_bval.p, M.cg.U.p, part.p);
+    hipLaunchKernelGGL(pred_acc_add_kernel, dim3(gp), dim3(tb), 0, M.stream, np, L.slices,
+                       part.p, acc.p);
+    VL_TRY(check_launch("pred acc"));
+  }
+  hipLaunchKernelGGL(pred_var_kernel, dim3(gp), dim3(tb), 0, M.stream, np, M.pred_dval.p, acc.p,
+                     1.0 / s, var_out);
+  VL_TRY(check_launch("pred var"));
+  VL_TRY(sync_stream(M.stream));
+  VL_TRY(read_status(M));
+  if (info) info->cg_iters_max = cg_max;
+  if (cg_max >= o.max_cg)
+    return Status::make(VL_ERR_NO_CONVERGENCE, "CG stopped at its iteration cap");
+  return Status::ok();
+}
+
+}  // namespace vl

@@ -1,0 +1,395 @@
+// Block preconditioned CG with Lanczos coefficients (appendix algorithm
+// "Preconditioned conjugate gradient algorithm with Lanczos tridiagonal
+// matrix"), run independently on each of t columns, for the systems
+//   (W + B^T D^{-1} B) u = rhs       preconditioned with
+//   P_VADU = B^T (W + D^{-1}) B      (eqs. pcls1, P_VADU; Sec. 3.1.1),
+// plus the tridiagonal quadrature e_1^T log(T~) e_1 of eq. (def_SLQ) and the
+// likelihood terms of eq. (VLA_loss).
+//
+// Column reductions are deterministic: a fixed grid of row chunks writes one
+// partial sum per (chunk, column), and a single block adds the partials of
+// each column in chunk order.
+#include "vl_internal.h"
+#include "vl_ops.h"
+
+namespace vl {
+
+// ------------------------------------------------------------ chunk layout
+ChunkGrid ChunkGrid::of(int64_t n, int t) {
+  ChunkGrid g;
+  g.L = Lanes::of(t);
+  g.n = n;
+  g.t = t;
+  const int64_t step = 4LL << g.L.rpw_log;
+  int64_t groups = (n + step - 1) / step;
+  int64_t want = 2048 / g.L.slices;
+  if (want < 1) want = 1;
+  if (want > groups) want = groups;
+  if (want < 1) want = 1;
+  int64_t per = (groups + want - 1) / want;
+  g.rpc = per * step;
+  g.nchunk = static_cast<int>((n + g.rpc - 1) / g.rpc);
+  if (g.nchunk < 1) g.nchunk = 1;
+  return g;
+}
+
+// Sum each column's per-chunk partials in chunk order.
+__global__ void reduce_chunks_kernel(const double* __restrict__ part, int nchunk, int t,
+                                     double* __restrict__ out) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < t; c += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < nchunk; ++k) s += part[(int64_t)k * t + c];
+    out[c] = s;
+  }
+}
+
+Status reduce_chunks(hipStream_t s, const double* part, int nchunk, int t, double* out) {
+  int g = (t + 255) / 256;
+  hipLaunchKernelGGL(reduce_chunks_kernel, dim3(g), dim3(256), 0, s, part, nchunk, t, out);
+  return check_launch("reduce_chunks");
+}
+
+// ---------------------------------------------------------- CG kernels
+__global__ __launch_bounds__(256) void cg_init_kernel(ChunkGrid g, const double* __restrict__ rhs,
+                                                      double* __restrict__ U,
+                                                      double* __restrict__ R,
+                                                      double* __restrict__ Y,
+                                                      double* __restrict__ Z, int* counter) {
+  CHUNK_LOOP_BEGIN(g)
+  const int64_t o = i * g.t + c;
+  U[o] = 0.0;
+  R[o] = rhs[o];
+  Y[o] = sentinel();
+  Z[o] = sentinel();
+  CHUNK_LOOP_END
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 4) counter[threadIdx.x] = 0;
+}
+
+// H = Z (and Z0 = Z); partial sums of r.z
+__global__ __launch_bounds__(256) void cg_init2_kernel(ChunkGrid g, const double* __restrict__ R,
+                                                       const double* __restrict__ Z,
+                                                       double* __restrict__ H,
+                                                       double* __restrict__ Z0,
+                                                       double* __restrict__ part) {
+  double acc = 0.0;
+  CHUNK_LOOP_BEGIN(g)
+  const int64_t o = i * g.t + c;
+  const double z = Z[o];
+  H[o] = z;
+  if (Z0) Z0[o] = z;
+  acc += R[o] * z;
+  CHUNK_LOOP_END
+  block_colsum(g, acc, part);
+}
+
+__global__ __launch_bounds__(256) void dot_kernel(ChunkGrid g, const double* __restrict__ X,
+                                                  const double* __restrict__ Y,
+                                                  double* __restrict__ part) {
+  double acc = 0.0;
+  CHUNK_LOOP_BEGIN(g)
+  const int64_t o = i * g.t + c;
+  acc += X[o] * Y[o];
+  CHUNK_LOOP_END
+  block_colsum(g, acc, part);
+}
+
+// one block: rz = r0z0 = sum of partials, active = 1, iters = 0
+__global__ void cg_start_kernel(int t, int nchunk, const double* __restrict__ part,
+                                double* __restrict__ rz, double* __restrict__ r0z0,
+                                int* __restrict__ active, int* __restrict__ iters,
+                                int* __restrict__ num_active) {
+  for (int c = threadIdx.x; c < t; c += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < nchunk; ++k) s += part[(int64_t)k * t + c];
+    rz[c] = s;
+    r0z0[c] = s;
+    active[c] = (s > 0.0) ? 1 : 0;  // a zero right-hand side is already solved
+    iters[c] = 0;
+  }
+  if (threadIdx.x == 0) num_active[0] = t;
+}
+
+// alpha = r.z / h.v for active columns; records alpha_{l+1}
+__global__ void cg_alpha_kernel(int t, int nchunk, const double* __restrict__ part,
+                                const double* __restrict__ rz, double* __restrict__ alpha,
+                                const int* __restrict__ active, const int* __restrict__ iters,
+                                double* __restrict__ hist_a, int* __restrict__ status) {
+  for (int c = threadIdx.x; c < t; c += blockDim.x) {
+    double hv = 0.0;
+    for (int k = 0; k < nchunk; ++k) hv += part[(int64_t)k * t + c];
+    double a = 0.0;
+    if (active[c]) {
+      if (!(hv > 0.0) || !isfinite(hv)) {
+        raise_error(status, kErrNonfinite);
+      } else {
+        a = rz[c] / hv;
+        hist_a[(int64_t)iters[c] * t + c] = a;
+      }
+    }
+    alpha[c] = a;
+  }
+}
+
+// u += alpha h, r -= alpha v; partial ||r||^2; pre-fill solve outputs
+__global__ __launch_bounds__(256) void cg_update_ur_kernel(
+    ChunkGrid g, const double* __restrict__ alpha, const int* __restrict__ active,
+    const double* __restrict__ H, const double* __restrict__ V, double* __restrict__ U,
+    double* __restrict__ R, double* __restrict__ Y, double* __restrict__ Z,
+    double* __restrict__ part, int* counter) {
+  double acc = 0.0;
+  CHUNK_LOOP_BEGIN(g)
+  const int64_t o = i * g.t + c;
+  double r = R[o];
+  if (active[c]) {
+    const double a = alpha[c];
+    U[o] += a * H[o];
+    r -= a * V[o];
+    R[o] = r;
+  }
+  acc += r * r;
+  Y[o] = sentinel();
+  Z[o] = sentinel();
+  CHUNK_LOOP_END
+  block_colsum(g, acc, part);
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 4) counter[threadIdx.x] = 0;
+}
+
+// beta = r_new.z_new / r.z; records beta; stopping test on ||r||_2
+__global__ void cg_beta_kernel(int t, int nchunk, const double* __restrict__ part_rz,
+                               const double* __restrict__ part_rr, double tol, int max_iter,
+                               double* __restrict__ rz, double* __restrict__ beta,
+                               int* __restrict__ active, int* __restrict__ iters,
+                               double* __restrict__ hist_b, int* __restrict__ num_active,
+                               int* __restrict__ status) {
+  __shared__ int s_cnt[256];
+  int cnt = 0;
+  for (int c = threadIdx.x; c < t; c += blockDim.x) {
+    double b = 0.0;
+    if (active[c]) {
+      double rzn = 0.0, rr = 0.0;
+      for (int k = 0; k < nchunk; ++k) {
+        rzn += part_rz[(int64_t)k * t + c];
+        rr += part_rr[(int64_t)k * t + c];
+      }
+      const int it = iters[c];
+      b = rzn / rz[c];
+      hist_b[(int64_t)it * t + c] = b;
+      rz[c] = rzn;
+      iters[c] = it + 1;
+      if (!isfinite(rr) || !isfinite(b)) raise_error(status, kErrNonfinite);
+      if (sqrt(rr) < tol || it + 1 >= max_iter || !isfinite(rr)) {
+        active[c] = 0;
+      } else {
+        ++cnt;
+      }
+    }
+    beta[c] = b;
+  }
+  s_cnt[threadIdx.x] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int k = 0; k < (int)blockDim.x; ++k) tot += s_cnt[k];
+    num_active[0] = tot;
+  }
+}
+
+__global__ __launch_bounds__(256) void cg_update_h_kernel(ChunkGrid g,
+                                                          const double* __restrict__ beta,
+                                                          const int* __restrict__ active,
+                                                          const double* __restrict__ Z,
+                                                          double* __restrict__ H) {
+  CHUNK_LOOP_BEGIN(g)
+  if (active[c]) {
+    const int64_t o = i * g.t + c;
+    H[o] = Z[o] + beta[c] * H[o];
+  }
+  CHUNK_LOOP_END
+}
+
+// ------------------------------------------------------------ CG driver
+static Status cg_reserve(Model& M, CgState& S, int t, int lmax, bool keep_z0) {
+  const size_t nt = static_cast<size_t>(M.n) * t;
+  VL_TRY(S.U.reserve(nt));
+  VL_TRY(S.R.reserve(nt));
+  VL_TRY(S.Z.reserve(nt));
+  VL_TRY(S.H.reserve(nt));
+  VL_TRY(S.V.reserve(nt));
+  VL_TRY(S.Tmp.reserve(nt));
+  VL_TRY(S.Y.reserve(nt));
+  if (keep_z0) VL_TRY(S.Z0.reserve(nt));
+  VL_TRY(S.rz.reserve(t));
+  VL_TRY(S.rr.reserve(t));
+  VL_TRY(S.alpha.reserve(t));
+  VL_TRY(S.beta.reserve(t));
+  VL_TRY(S.r0z0.reserve(t));
+  VL_TRY(S.active.reserve(t));
+  VL_TRY(S.iters.reserve(t));
+  VL_TRY(S.num_active.reserve(4));
+  VL_TRY(S.hist_a.reserve(static_cast<size_t>(lmax) * t));
+  VL_TRY(S.hist_b.reserve(static_cast<size_t>(lmax) * t));
+  ChunkGrid g = ChunkGrid::of(M.n, t);
+  VL_TRY(S.part_a.reserve(static_cast<size_t>(g.nchunk) * t));
+  VL_TRY(S.part_b.reserve(static_cast<size_t>(g.nchunk) * t));
+  VL_TRY(M.counter.reserve(64));
+  if (!M.host_pin) VL_HIP(hipHostMalloc(reinterpret_cast<void**>(&M.host_pin), 64 * sizeof(double)));
+  S.t = t;
+  S.lmax = lmax;
+  return Status::ok();
+}
+
+static dim3 chunk_dims(const ChunkGrid& g) { return dim3(g.nchunk, g.L.slices); }
+
+Status cg_solve(Model& M, CgState& S, const CgOps& ops, int t, const double* rhs, double tol,
+                int max_iter, bool keep_z0) {
+  if (t <= 0) return Status::invalid("t must be positive");
+  if (max_iter < 1) max_iter = 1;
+  VL_TRY(cg_reserve(M, S, t, max_iter, keep_z0));
+  hipStream_t s = M.stream;
+  ChunkGrid g = ChunkGrid::of(M.n, t);
+  const dim3 cg_grid = chunk_dims(g);
+  int* cnt = M.counter.p;
+  // u_0 = 0, r_0 = rhs, z_0 = P^{-1} r_0, h_0 = z_0
+  hipLaunchKernelGGL(cg_init_kernel, cg_grid, dim3(256), 0, s, g, rhs, S.U.p, S.R.p, S.Y.p,
+                     S.Z.p, cnt);
+  VL_TRY(ops.precond(M, S.R.p, S.Z.p, S.Y.p, t));
+  hipLaunchKernelGGL(cg_init2_kernel, cg_grid, dim3(256), 0, s, g, S.R.p, S.Z.p, S.H.p,
+                     keep_z0 ? S.Z0.p : nullptr, S.part_a.p);
+  hipLaunchKernelGGL(cg_start_kernel, dim3(1), dim3(256), 0, s, t, g.nchunk, S.part_a.p,
+                     S.rz.p, S.r0z0.p, S.active.p, S.iters.p, S.num_active.p);
+  VL_TRY(check_launch("cg start"));
+  int iters_done = 0;
+  for (int it = 0; it < max_iter; ++it) {
+    VL_TRY(ops.apply(M, S.H.p, S.V.p, S.Tmp.p, t));
+    hipLaunchKernelGGL(dot_kernel, cg_grid, dim3(256), 0, s, g, S.H.p, S.V.p, S.part_a.p);
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(256), 0, s, t, g.nchunk, S.part_a.p,
+                       S.rz.p, S.alpha.p, S.active.p, S.iters.p, S.hist_a.p, M.status);
+    hipLaunchKernelGGL(cg_update_ur_kernel, cg_grid, dim3(256), 0, s, g, S.alpha.p, S.active.p,
+                       S.H.p, S.V.p, S.U.p, S.R.p, S.Y.p, S.Z.p, S.part_b.p, cnt);
+    VL_TRY(ops.precond(M, S.R.p, S.Z.p, S.Y.p, t));
+    hipLaunchKernelGGL(dot_kernel, cg_grid, dim3(256), 0, s, g, S.R.p, S.Z.p, S.part_a.p);
+    hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(256), 0, s, t, g.nchunk, S.part_a.p,
+                       S.part_b.p, tol, max_iter, S.rz.p, S.beta.p, S.active.p, S.iters.p,
+                       S.hist_b.p, S.num_active.p, M.status);
+    hipLaunchKernelGGL(cg_update_h_kernel, cg_grid, dim3(256), 0, s, g, S.beta.p, S.active.p,
+                       S.Z.p, S.H.p);
+    VL_TRY(check_launch("cg iteration"));
+    VL_HIP(hipMemcpyAsync(M.host_pin, S.num_active.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    VL_TRY(sync_stream(s));
+    iters_done = it + 1;
+    if (*reinterpret_cast<int*>(M.host_pin) == 0) break;
+  }
+  (void)iters_done;
+  S.host_iters.resize(t);
+  VL_HIP(hipMemcpyAsync(S.host_iters.data(), S.iters.p, sizeof(int) * t, hipMemcpyDeviceToHost,
+                        s));
+  VL_TRY(sync_stream(s));
+  return read_status(M);
+}
+
+Status dot_cols(Model& M, const double* X, const double* Y, int t, double* part, double* out) {
+  ChunkGrid g = ChunkGrid::of(M.n, t);
+  hipLaunchKernelGGL(dot_kernel, chunk_dims(g), dim3(256), 0, M.stream, g, X, Y, part);
+  return reduce_chunks(M.stream, part, g.nchunk, t, out);
+}
+
+// ------------------------------------------------ tridiagonal quadrature
+// For each column: T~ from the CG coefficients (T_11 = 1/a_1, T_jj = 1/a_j +
+// b_{j-1}/a_{j-1}, T_{j-1,j} = sqrt(b_{j-1})/a_{j-1}), its eigenvalues by
+// implicit QL with shifts, rotating only the first row of the eigenvector
+// matrix, and sum_j z_j^2 log(lambda_j) = e_1^T log(T~) e_1.
+__global__ void tridiag_logquad_kernel(int t, int lmax, const int* __restrict__ iters,
+                                       const double* __restrict__ hist_a,
+                                       const double* __restrict__ hist_b,
+                                       double* __restrict__ work, double* __restrict__ out,
+                                       int* __restrict__ status) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= t) return;
+  const int L = iters[c];
+  double* d = work + (int64_t)c * 3 * lmax;
+  double* e = d + lmax;
+  double* z = e + lmax;
+  if (L <= 0) {
+    out[c] = 0.0;
+    return;
+  }
+  for (int j = 0; j < L; ++j) {
+    const double a = hist_a[(int64_t)j * t + c];
+    double dj = 1.0 / a;
+    if (j > 0) {
+      const double ap = hist_a[(int64_t)(j - 1) * t + c];
+      const double bp = hist_b[(int64_t)(j - 1) * t + c];
+      dj += bp / ap;
+      e[j - 1] = sqrt(bp) / ap;
+    }
+    d[j] = dj;
+    z[j] = (j == 0) ? 1.0 : 0.0;
+  }
+  e[L - 1] = 0.0;
+  const double eps = 2.220446049250313e-16;
+  for (int l = 0; l < L; ++l) {
+    int sweeps = 0;
+    for (;;) {
+      int mm = l;
+      while (mm < L - 1) {
+        const double scale = fabs(d[mm]) + fabs(d[mm + 1]);
+        if (fabs(e[mm]) <= eps * scale) break;
+        ++mm;
+      }
+      if (mm == l) break;
+      if (++sweeps > 64) {
+        raise_error(status, kErrNonfinite);
+        out[c] = __longlong_as_double(0x7FF8000000000000ll);
+        return;
+      }
+      // shift from the leading 2 x 2 block at l
+      double gq = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double rq = hypot(gq, 1.0);
+      gq = d[mm] - d[l] + e[l] / (gq + copysign(rq, gq));
+      double sn = 1.0, cs = 1.0, shift = 0.0;
+      bool deflated = false;
+      for (int i = mm - 1; i >= l; --i) {
+        const double f = sn * e[i];
+        const double bq = cs * e[i];
+        rq = hypot(f, gq);
+        e[i + 1] = rq;
+        if (rq == 0.0) {
+          d[i + 1] -= shift;
+          e[mm] = 0.0;
+          deflated = true;
+          break;
+        }
+        sn = f / rq;
+        cs = gq / rq;
+        const double gg = d[i + 1] - shift;
+        const double rr = (d[i] - gg) * sn + 2.0 * cs * bq;
+        shift = sn * rr;
+        d[i + 1] = gg + shift;
+        gq = cs * rr - bq;
+        const double zf = z[i + 1];
+        z[i + 1] = sn * z[i] + cs * zf;
+        z[i] = cs * z[i] - sn * zf;
+      }
+      if (deflated) continue;
+      d[l] -= shift;
+      e[l] = gq;
+      e[mm] = 0.0;
+    }
+  }
+  double acc = 0.0;
+  for (int j = 0; j < L; ++j) {
+    if (!(d[j] > 0.0)) raise_error(status, kErrNonfinite);
+    acc += z[j] * z[j] * log(d[j]);
+  }
+  out[c] = acc;
+}
+
+Status tridiag_quadrature(Model& M, CgState& S, double* out_dev) {
+  VL_TRY(S.tri.reserve(static_cast<size_t>(S.t) * 3 * S.lmax));
+  const int g = (S.t + 63) / 64;
+  hipLaunchKernelGGL(tridiag_logquad_kernel, dim3(g), dim3(64), 0, M.stream, S.t, S.lmax,
+                     S.iters.p, S.hist_a.p, S.hist_b.p, S.tri.p, out_dev, M.status);
+  return check_launch("tridiag");
+}
+
+}  // namespace vl

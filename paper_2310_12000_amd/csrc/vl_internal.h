@@ -1,0 +1,198 @@
+// Host-side internals of the library: the model handle, status values,
+// device buffers and the declarations shared between translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/vl.h"
+#include "vl_device.h"
+
+namespace vl {
+
+struct Status {
+  vl_status code = VL_OK;
+  std::string msg;
+  static Status ok() { return Status(); }
+  static Status make(vl_status c, const std::string& m) {
+    Status s;
+    s.code = c;
+    s.msg = m;
+    return s;
+  }
+  static Status invalid(const std::string& m) { return make(VL_ERR_INVALID_ARG, m); }
+  static Status hip(hipError_t e, const char* where) {
+    return make(VL_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+  }
+  bool good() const { return code == VL_OK; }
+};
+
+#define VL_TRY(expr)                          \
+  do {                                        \
+    ::vl::Status _st = (expr);                \
+    if (!_st.good()) return _st;              \
+  } while (0)
+
+#define VL_HIP(expr)                                              \
+  do {                                                            \
+    hipError_t _e = (expr);                                       \
+    if (_e != hipSuccess) return ::vl::Status::hip(_e, #expr);    \
+  } while (0)
+
+Status check_launch(const char* what);
+Status sync_stream(hipStream_t s);
+Status device_alloc(void** p, size_t bytes);
+void device_free(void* p);
+
+// RAII device buffer for temporaries of one call.
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t count = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  Status alloc(size_t n) {
+    release();
+    if (n == 0) n = 1;
+    void* q = nullptr;
+    VL_TRY(device_alloc(&q, n * sizeof(T)));
+    p = static_cast<T*>(q);
+    count = n;
+    return Status::ok();
+  }
+  // grow-only
+  Status reserve(size_t n) {
+    if (n <= count && p) return Status::ok();
+    return alloc(n);
+  }
+  void release() {
+    if (p) device_free(p);
+    p = nullptr;
+    count = 0;
+  }
+};
+
+struct GridGeom {
+  double x0, y0, h, slack;
+  int G;
+};
+
+// State of one block CG solve (t columns).
+struct CgState {
+  int t = 0;
+  int lmax = 0;
+  DevBuf<double> U, R, Z, H, V, Tmp, Y, Z0;   // n x t each
+  DevBuf<double> rz, rr, alpha, beta, r0z0;   // t each
+  DevBuf<double> hist_a, hist_b;              // lmax x t
+  DevBuf<double> tri;                         // 3 lmax x t (tridiagonal work)
+  DevBuf<int> active, iters;                  // t each
+  DevBuf<int> num_active;                     // 1
+  DevBuf<double> part_a, part_b;              // nchunk x t partial sums
+  std::vector<int> host_iters;
+};
+
+struct Model {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t n = 0;
+  int m = 0;
+  int cov = 0;
+  double sigma2 = 1.0, rho = 1.0;
+  bool deriv = false;
+
+  DevBuf<double> coords_buf;  // n x 2
+  const double* coords = nullptr;
+  DevBuf<int> nbr;            // n x m
+  DevBuf<double> bval;        // n x m, B entries (-A)
+  DevBuf<double> dval;        // n
+  DevBuf<double> dinv;        // n
+  DevBuf<double> dbval_rho;   // n x m (dB/drho); dB/dsigma2 = 0
+  DevBuf<double> dd_sigma2, dd_rho;  // n
+  // B^T in CSR
+  int64_t nnz = 0;
+  DevBuf<int> bt_ptr, bt_col, bt_src;
+  DevBuf<double> bt_val;
+  DevBuf<float> bval_f, bt_val_f;  // FP32 copies for the mixed-precision form
+
+  // neighbour-search grid
+  int grid_G = 0;
+  void* grid_geom = nullptr;
+  void* grid_start = nullptr;
+  void* grid_pts = nullptr;
+  void* grid_xy = nullptr;
+  std::vector<void*> owned;  // released by vl_free
+  Status ws_alloc(void** p, size_t bytes) {
+    VL_TRY(device_alloc(p, bytes));
+    owned.push_back(*p);
+    return Status::ok();
+  }
+
+  // likelihood state
+  bool has_mode = false;
+  int lik = 0;
+  double aux = 0.0;
+  DevBuf<double> y, F, mode, W, g;
+
+  // diagnostics
+  DevBuf<int> status_buf;
+  int* status = nullptr;
+  std::vector<int> newton_cg_iters;
+  std::vector<int> last_block_iters;
+  std::vector<double> last_quad, last_r0z0;
+  DevBuf<int> pred_nbr;
+  DevBuf<double> pred_bval, pred_dval;
+  int64_t last_np = 0;
+
+  // reusable workspaces
+  CgState cg;
+  CgState cg1;  // single-column solves
+  DevBuf<double> red_part;  // partial sums of reductions
+  DevBuf<double> red_out;
+  DevBuf<double> vec_a, vec_b, vec_c, vec_d, dWv;  // n-length scratch vectors
+  DevBuf<double> rhs_blk;  // n x t right-hand sides of block solves
+  DevBuf<int> counter;     // dynamic work counters of sync-free kernels
+  double* host_pin = nullptr;  // pinned host scalars (64 doubles)
+};
+
+// ---- utilities (util.hip)
+Status fill_int(int* p, int v, int64_t count, hipStream_t s);
+Status fill_double(double* p, double v, int64_t count, hipStream_t s);
+Status exclusive_scan_int(const int* in, int* out, int64_t count, hipStream_t s);
+Status copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t s);
+Status read_status(Model& M);
+
+// ---- neighbour search (knn.hip)
+Status knn_build_grid(Model& M);
+Status knn_query(Model& M, const double* q_xy, int64_t nq, int* nbr_out);
+
+// ---- factor (factor.hip)
+Status factor_rows(Model& M, const double* q_xy, int64_t nrows, const int* nbr, double* bval,
+                   double* dval, bool deriv, double* dbval_rho, double* dd_sigma2,
+                   double* dd_rho);
+
+// ---- sparse kernels (sparse.hip)
+Status build_transpose(Model& M);
+Status refresh_transpose_values(Model& M);
+
+// Y = rowscale o (X + B_off X)                              (spmm_b)
+// Y = diag o diagvec + X + B_off^T X                         (spmm_bt)
+Status spmm_b(Model& M, const double* X, double* Y, int t, const double* rowscale);
+Status spmm_bt(Model& M, const double* X, double* Y, int t, const double* diag,
+               const double* diagvec);
+// triangular solves: B Y = rowscale o X (lower) / B^T Y = X (upper)
+Status trsm_b(Model& M, const double* X, double* Y, int t, const double* rowscale,
+              bool prefilled);
+Status trsm_bt(Model& M, const double* X, double* Y, int t, bool prefilled);
+int spmm_nblocks(int64_t n, int t);
+
+// ---- solver kernels (solver.hip)
+Status tridiag_quadrature(Model& M, CgState& S, double* out_dev);
+
+}  // namespace vl

@@ -1,0 +1,33 @@
+// Host drivers of the Laplace-level operations.
+#pragma once
+
+#include "vl_internal.h"
+
+namespace vl {
+
+struct GradInfo {
+  double c[2] = {0, 0};
+  double dlogdet[2] = {0, 0};
+  double quad[2] = {0, 0};
+  double implicit[2] = {0, 0};
+  int grad_cg_iters = 0;
+};
+
+struct NllInfo {
+  double gamma = 0, logdet = 0, loglik = 0, quadform = 0;
+  int cg_iters_max = 0;
+  GradInfo grad;
+};
+
+struct PredInfo {
+  int cg_iters_max = 0;
+};
+
+Status lik_rows(Model& M, const double* b, double* g, double* W, double* rhs, double* s,
+                double* sq, double* dW);
+Status find_mode(Model& M, const vl_opts& o, vl_stats* st);
+Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, NllInfo* info);
+Status predict(Model& M, const double* coords_p, int64_t np, const double* Fp,
+               const vl_opts& o, double* mean_out, double* var_out, PredInfo* info);
+
+}  // namespace vl

@@ -1,0 +1,114 @@
+// Work layouts shared by the kernels, and the operator interface of the CG
+// driver.
+#pragma once
+
+#include <functional>
+
+#include "vl_internal.h"
+
+namespace vl {
+
+// Lanes of a wave over an n x t row-major block: lanes_per_row =
+// min(64, next power of two >= t); a wave covers 64 / lanes_per_row rows;
+// for t > 64 each row is split into 64-column slices.
+struct Lanes {
+  int lpr_log, rpw_log, slices;
+  __host__ __device__ static Lanes of(int t) {
+    Lanes L;
+    if (t > 64) {
+      L.lpr_log = 6;
+      L.rpw_log = 0;
+      L.slices = (t + 63) / 64;
+    } else {
+      int lg = 0;
+      while ((1 << lg) < t) ++lg;
+      L.lpr_log = lg;
+      L.rpw_log = 6 - lg;
+      L.slices = 1;
+    }
+    return L;
+  }
+};
+
+// Work units = (row group of 2^rpw_log rows, slice).
+__host__ __device__ __forceinline__ int64_t units_of_hd(int64_t n, int t, Lanes L) {
+  (void)t;
+  int64_t rg = (n + (1 << L.rpw_log) - 1) >> L.rpw_log;
+  return rg * L.slices;
+}
+
+// Deterministic chunked grid: gridDim = (nchunk, slices), 256 threads; block
+// (k, s) covers rows [k * rpc, (k + 1) * rpc) and columns of slice s.
+struct ChunkGrid {
+  Lanes L;
+  int64_t n;
+  int t;
+  int nchunk;
+  int64_t rpc;
+  static ChunkGrid of(int64_t n, int t);
+};
+
+// Loop over the (row i, column c) pairs of this lane within the block's chunk.
+#define CHUNK_LOOP_BEGIN(g)                                                        \
+  {                                                                                \
+    const int _lane = threadIdx.x & 63;                                            \
+    const int _w = threadIdx.x >> 6;                                               \
+    const int _sub = _lane >> (g).L.lpr_log;                                       \
+    const int c = blockIdx.y * 64 + (_lane & ((1 << (g).L.lpr_log) - 1));          \
+    const int64_t _r0 = (int64_t)blockIdx.x * (g).rpc;                             \
+    int64_t _r1 = _r0 + (g).rpc;                                                   \
+    if (_r1 > (g).n) _r1 = (g).n;                                                  \
+    const int64_t _step = 4LL << (g).L.rpw_log;                                    \
+    if (c < (g).t) {                                                               \
+      for (int64_t _b = _r0 + ((int64_t)_w << (g).L.rpw_log); _b < _r1; _b += _step) { \
+        const int64_t i = _b + _sub;                                               \
+        if (i >= _r1) continue;
+
+#define CHUNK_LOOP_END \
+  }                    \
+  }                    \
+  }
+
+// Add a per-lane value over all rows of the block, per column, and store the
+// block's column sums at part[blockIdx.x * t + column].  All threads of the
+// block must call it.
+__device__ __forceinline__ void block_colsum(const ChunkGrid& g, double v,
+                                             double* __restrict__ part) {
+  __shared__ double s[4][64];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int lpr = 1 << g.L.lpr_log;
+  for (int o = 32; o >= lpr; o >>= 1) v += __shfl_xor(v, o);
+  if (lane < lpr) s[w][lane] = v;
+  __syncthreads();
+  const int c = blockIdx.y * 64 + lane;
+  if (w == 0 && lane < lpr && c < g.t)
+    part[(int64_t)blockIdx.x * g.t + c] = s[0][lane] + s[1][lane] + s[2][lane] + s[3][lane];
+  __syncthreads();
+}
+
+Status reduce_chunks(hipStream_t s, const double* part, int nchunk, int t, double* out);
+
+// Operator pair of one CG solve.
+struct CgOps {
+  // V = A H over t columns (Tmp: n x t scratch)
+  std::function<Status(Model&, const double* H, double* V, double* Tmp, int t)> apply;
+  // Z = P^{-1} R; Z and Y (n x t scratch) arrive filled with the sentinel and
+  // the work counters reset
+  std::function<Status(Model&, const double* R, double* Z, double* Y, int t)> precond;
+};
+
+Status cg_solve(Model& M, CgState& S, const CgOps& ops, int t, const double* rhs, double tol,
+                int max_iter, bool keep_z0);
+Status dot_cols(Model& M, const double* X, const double* Y, int t, double* part, double* out);
+
+// sparse kernels with explicit value arrays / probe inputs
+Status spmm_ell_vals(Model& M, const double* vals, const double* X, double* Y, int t,
+                     const double* rowscale, bool unit_diag);
+Status spmm_bt_probe(Model& M, double* Y, int t, const double* s, uint64_t seed, uint32_t tag2,
+                     int col0, int gauss2, const double* d, uint32_t tag1, int gauss1);
+Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* rowscale,
+                   bool prefilled, int slot);
+Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled, int slot);
+
+}  // namespace vl

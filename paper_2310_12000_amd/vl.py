@@ -1,0 +1,271 @@
+"""Python binding of the C ABI in include/vl.h (argument marshalling only).
+
+Every computation runs in the HIP library libvl.so built from csrc/; this
+module converts torch tensors to device pointers and checks status codes.  It
+raises if the library is missing: there is no fallback.
+
+Device memory and streams come from PyTorch: inputs and outputs are CUDA
+(HIP) float64 tensors on the model's device, and calls are enqueued on the
+current torch stream at model creation.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvl.so")
+
+VL_OK = 0
+VL_ERR_INVALID_ARG = -1
+VL_ERR_NOT_SPD = -2
+VL_ERR_NO_CONVERGENCE = -3
+VL_ERR_OOM = -4
+VL_ERR_NONFINITE = -5
+VL_ERR_HIP = -6
+VL_ERR_STATE = -7
+VL_ERR_TIMEOUT = -8
+
+VL_COV_EXPONENTIAL = 0
+VL_COV_MATERN32 = 1
+VL_LIK_BERNOULLI_LOGIT = 0
+VL_LIK_POISSON_LOG = 1
+VL_LIK_GAUSSIAN = 2
+VL_PREC_VADU = 0
+VL_PREC_LRAC = 1
+VL_FP64 = 0
+VL_MIXED = 1
+
+EXPORT = {
+    "nbr": (0, torch.int32), "bval": (1, torch.float64), "D": (2, torch.float64),
+    "mode": (3, torch.float64), "W": (4, torch.float64),
+    "dbval_sigma2": (5, torch.float64), "dbval_rho": (6, torch.float64),
+    "dD_sigma2": (7, torch.float64), "dD_rho": (8, torch.float64),
+    "block_iters": (9, torch.int32), "newton_cg_iters": (10, torch.int32),
+    "slq_quad": (11, torch.float64), "slq_r0z0": (12, torch.float64),
+    "pred_nbr": (13, torch.int32), "pred_bval": (14, torch.float64),
+    "pred_D": (15, torch.float64),
+}
+
+
+class vl_opts(ctypes.Structure):
+    _fields_ = [
+        ("max_newton", ctypes.c_int), ("newton_tol", ctypes.c_double),
+        ("max_cg", ctypes.c_int), ("cg_tol", ctypes.c_double),
+        ("pred_cg_tol", ctypes.c_double), ("num_probes", ctypes.c_int),
+        ("num_pred_samples", ctypes.c_int), ("seed", ctypes.c_uint64),
+        ("precond", ctypes.c_int), ("lrac_rank", ctypes.c_int),
+        ("precision", ctypes.c_int), ("pred_tile", ctypes.c_int),
+    ]
+
+
+class vl_stats(ctypes.Structure):
+    _fields_ = [
+        ("newton_iters", ctypes.c_int), ("cg_iters_total", ctypes.c_int),
+        ("cg_iters_max", ctypes.c_int), ("hit_cap", ctypes.c_int),
+        ("t_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class VLError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libvl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python paper_2310_12000_amd/build.py`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, D, I, I64, S = (ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int64,
+                       ctypes.c_size_t)
+    L.vl_default_opts.argtypes = [ctypes.POINTER(vl_opts)]
+    L.vl_default_opts.restype = None
+    L.vl_status_string.argtypes = [I]
+    L.vl_status_string.restype = ctypes.c_char_p
+    L.vl_last_error.argtypes = []
+    L.vl_last_error.restype = ctypes.c_char_p
+    L.vl_build_vecchia.argtypes = [P, I64, I, I, ctypes.POINTER(D), P, I, ctypes.POINTER(P)]
+    L.vl_set_theta.argtypes = [P, ctypes.POINTER(D)]
+    L.vl_find_mode.argtypes = [P, P, P, I, ctypes.POINTER(D), ctypes.POINTER(vl_opts), P,
+                               ctypes.POINTER(vl_stats)]
+    L.vl_neg_log_marglik.argtypes = [P, ctypes.POINTER(vl_opts), ctypes.POINTER(D),
+                                     ctypes.POINTER(D), ctypes.POINTER(vl_stats)]
+    L.vl_predict.argtypes = [P, P, I64, P, ctypes.POINTER(vl_opts), P, P,
+                             ctypes.POINTER(vl_stats)]
+    L.vl_export.argtypes = [P, I, P, S]
+    L.vl_export_count.argtypes = [P, I]
+    L.vl_export_count.restype = I64
+    L.vl_spmm.argtypes = [P, I, P, P, I]
+    L.vl_trsm.argtypes = [P, I, P, P, I]
+    L.vl_free.argtypes = [P]
+    L.vl_free.restype = None
+    for f in ("vl_build_vecchia", "vl_set_theta", "vl_find_mode", "vl_neg_log_marglik",
+              "vl_predict", "vl_export", "vl_spmm", "vl_trsm"):
+        getattr(L, f).restype = I
+    _lib = L
+    return L
+
+
+def _check(code, allow=()):
+    if code != VL_OK and code not in allow:
+        raise VLError(code, lib().vl_last_error().decode() or
+                      lib().vl_status_string(code).decode())
+    return code
+
+
+def _ptr(t, dtype=torch.float64, shape=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("expected a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def vl_default_opts(**kw):
+    o = vl_opts()
+    lib().vl_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def vl_build_vecchia(coords, m, cov, theta, want_deriv=False, stream=None):
+    """Handle of the Vecchia approximation at locations `coords` (n x 2)."""
+    n = coords.shape[0]
+    _ptr(coords, shape=(n, 2))
+    th = (ctypes.c_double * 2)(*[float(x) for x in theta])
+    s = stream if stream is not None else torch.cuda.current_stream(coords.device).cuda_stream
+    h = ctypes.c_void_p()
+    _check(lib().vl_build_vecchia(ctypes.c_void_p(coords.data_ptr()), n, int(m), int(cov), th,
+                                  ctypes.c_void_p(s), 1 if want_deriv else 0, ctypes.byref(h)))
+    return h
+
+
+def vl_set_theta(h, theta):
+    th = (ctypes.c_double * 2)(*[float(x) for x in theta])
+    _check(lib().vl_set_theta(h, th))
+
+
+def vl_find_mode(h, y, F, lik, aux=None, opts=None, mode_out=None, allow_no_conv=False):
+    opts = opts or vl_default_opts()
+    st = vl_stats()
+    a = (ctypes.c_double * 1)(float(aux)) if aux is not None else None
+    code = lib().vl_find_mode(h, _ptr(y), _ptr(F), int(lik), a, ctypes.byref(opts),
+                              _ptr(mode_out), ctypes.byref(st))
+    _check(code, allow=(VL_ERR_NO_CONVERGENCE,) if allow_no_conv else ())
+    return st, code
+
+
+def vl_neg_log_marglik(h, opts=None, want_grad=False, allow_no_conv=False):
+    opts = opts or vl_default_opts()
+    nll = ctypes.c_double()
+    grad = (ctypes.c_double * 2)()
+    st = vl_stats()
+    code = lib().vl_neg_log_marglik(h, ctypes.byref(opts), ctypes.byref(nll),
+                                    grad if want_grad else None, ctypes.byref(st))
+    _check(code, allow=(VL_ERR_NO_CONVERGENCE,) if allow_no_conv else ())
+    return nll.value, (list(grad) if want_grad else None), st
+
+
+def vl_predict(h, coords_p, Fp, opts, mean_out, var_out=None, allow_no_conv=False):
+    npred = coords_p.shape[0]
+    st = vl_stats()
+    code = lib().vl_predict(h, _ptr(coords_p, shape=(npred, 2)), npred, _ptr(Fp),
+                            ctypes.byref(opts), _ptr(mean_out), _ptr(var_out), ctypes.byref(st))
+    _check(code, allow=(VL_ERR_NO_CONVERGENCE,) if allow_no_conv else ())
+    return st
+
+
+def vl_export(h, name, device="cuda"):
+    which, dtype = EXPORT[name]
+    cnt = lib().vl_export_count(h, which)
+    if cnt < 0:
+        raise VLError(VL_ERR_STATE, f"{name} not available")
+    out = torch.empty(max(int(cnt), 0), dtype=dtype, device=device)
+    _check(lib().vl_export(h, which, ctypes.c_void_p(out.data_ptr()) if cnt else None,
+                           out.numel() * out.element_size()))
+    return out
+
+
+def vl_spmm(h, X, Y, transpose=False):
+    t = 1 if X.dim() == 1 else X.shape[1]
+    _ptr(X), _ptr(Y)
+    _check(lib().vl_spmm(h, 1 if transpose else 0, ctypes.c_void_p(X.data_ptr()),
+                         ctypes.c_void_p(Y.data_ptr()), t))
+
+
+def vl_trsm(h, X, Y, transpose=False):
+    t = 1 if X.dim() == 1 else X.shape[1]
+    _ptr(X), _ptr(Y)
+    _check(lib().vl_trsm(h, 1 if transpose else 0, ctypes.c_void_p(X.data_ptr()),
+                         ctypes.c_void_p(Y.data_ptr()), t))
+
+
+def vl_free(h):
+    if h:
+        lib().vl_free(h)
+
+
+class VecchiaLaplace:
+    """Convenience wrapper owning one model handle."""
+
+    def __init__(self, coords, m, cov, theta, want_deriv=False):
+        self.coords = coords
+        self.n = coords.shape[0]
+        self.m = m
+        self.h = vl_build_vecchia(coords, m, cov, theta, want_deriv)
+
+    def set_theta(self, theta):
+        vl_set_theta(self.h, theta)
+
+    def find_mode(self, y, F=None, lik=VL_LIK_BERNOULLI_LOGIT, aux=None, opts=None,
+                  allow_no_conv=False):
+        mode = torch.empty(self.n, dtype=torch.float64, device=y.device)
+        st, code = vl_find_mode(self.h, y, F, lik, aux, opts, mode, allow_no_conv)
+        return mode, st
+
+    def neg_log_marglik(self, opts=None, want_grad=False, allow_no_conv=False):
+        nll, grad, st = vl_neg_log_marglik(self.h, opts, want_grad, allow_no_conv)
+        return nll, grad, st
+
+    def predict(self, coords_p, Fp=None, opts=None, want_var=True, allow_no_conv=False):
+        opts = opts or vl_default_opts()
+        npred = coords_p.shape[0]
+        mean = torch.empty(npred, dtype=torch.float64, device=coords_p.device)
+        var = torch.empty(npred, dtype=torch.float64, device=coords_p.device) if want_var else None
+        st = vl_predict(self.h, coords_p, Fp, opts, mean, var, allow_no_conv)
+        return mean, var, st
+
+    def export(self, name):
+        return vl_export(self.h, name, self.coords.device)
+
+    def close(self):
+        if self.h:
+            vl_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

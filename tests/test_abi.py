@@ -1,0 +1,65 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/vl.h, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vl.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(vl_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2310_12000_amd as P
+    return P.lib()
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for f in ("vl_build_vecchia", "vl_find_mode", "vl_neg_log_marglik", "vl_predict",
+              "vl_set_theta", "vl_free", "vl_export", "vl_spmm", "vl_trsm"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_default_opts_are_the_papers(L):
+    import paper_2310_12000_amd as P
+    o = P.vl_default_opts()
+    assert (o.num_probes, o.lrac_rank, o.num_pred_samples) == (50, 50, 2000)
+    assert (o.cg_tol, o.pred_cg_tol) == (1e-2, 1e-3)
+
+
+def test_status_strings(L):
+    assert L.vl_status_string(0) == b"ok"
+    assert L.vl_status_string(-2) == b"covariance not positive definite"
+
+
+def test_invalid_arguments_rejected_without_device(L):
+    import paper_2310_12000_amd as P
+    h = ctypes.c_void_p()
+    th = (ctypes.c_double * 2)(1.0, 0.1)
+    # null coordinates, bad n, bad m, bad theta: all refused before any HIP call
+    assert L.vl_build_vecchia(None, 10, 5, 0, th, None, 0, ctypes.byref(h)) == P.VL_ERR_INVALID_ARG
+    fake = ctypes.c_void_p(1)
+    assert L.vl_build_vecchia(fake, 0, 5, 0, th, None, 0, ctypes.byref(h)) == P.VL_ERR_INVALID_ARG
+    assert L.vl_build_vecchia(fake, 10, 40, 0, th, None, 0, ctypes.byref(h)) == P.VL_ERR_INVALID_ARG
+    bad = (ctypes.c_double * 2)(-1.0, 0.1)
+    assert L.vl_build_vecchia(fake, 10, 5, 0, bad, None, 0, ctypes.byref(h)) == P.VL_ERR_INVALID_ARG
+    assert L.vl_build_vecchia(fake, 10, 5, 7, th, None, 0, ctypes.byref(h)) == P.VL_ERR_INVALID_ARG
+    assert b"m must be" in L.vl_last_error() or b"covariance" in L.vl_last_error()
+    # null handles
+    assert L.vl_set_theta(None, th) == P.VL_ERR_INVALID_ARG
+    assert L.vl_export_count(None, 0) == -1

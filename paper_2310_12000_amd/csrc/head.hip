@@ -1,0 +1,478 @@
+// Triangular solves with B over the "head" rows 0..H-1.
+//
+// With a random ordering the dependency DAG of B is deep only among early
+// rows: for n = 1e5, m = 20 the first 16384 rows already span 214 of the 278
+// levels, while the remaining rows add only 68.  The head is therefore solved
+// level by level inside one workgroup per probe column, with the column's
+// head values in LDS and a workgroup barrier between levels; the data of the
+// next level's rows is prefetched into registers while the current level is
+// computed.  The tail rows use the sync-free kernels (sparse.hip).
+//
+// Forward (B Y = rs o X): the head runs first; every dependency of a head row
+// is a head row.  Backward (B^T Y = X): the tail runs first, then the head
+// reads finished tail values from global memory and head values from LDS.
+//
+// Level schedules (rows of the head grouped by level, separately for the two
+// directions) depend only on the neighbour sets and are built once.
+#include <algorithm>
+
+#include "vl_internal.h"
+#include "vl_ops.h"
+
+namespace vl {
+
+constexpr int kHeadThreads = 1024;
+
+// Workgroup-scope relaxed accesses to LDS: each read observes the latest
+// value written by any wave of the workgroup.
+__device__ __forceinline__ double lds_poll(double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_publish(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// ------------------------------------------------------- level schedules
+// Longest-path levels of the head rows by repeated relaxation in LDS
+// (monotone, so it stops at the fixpoint): forward uses N(i), backward uses
+// the rows of B^T restricted to head rows.
+__global__ __launch_bounds__(kHeadThreads) void head_levels_kernel(
+    int H, int m, const int* __restrict__ nbr, const int* __restrict__ bt_ptr,
+    const int* __restrict__ bt_col, int backward, int* __restrict__ level_out) {
+  extern __shared__ int s_lev[];
+  for (int i = threadIdx.x; i < H; i += kHeadThreads) s_lev[i] = 0;
+  __syncthreads();
+  for (;;) {
+    int changed = 0;
+    for (int i = threadIdx.x; i < H; i += kHeadThreads) {
+      int l = 0;
+      if (!backward) {
+        for (int k = 0; k < m; ++k) {
+          const int j = nbr[(int64_t)i * m + k];
+          if (j < 0) break;
+          l = max(l, s_lev[j] + 1);
+        }
+      } else {
+        const int b = bt_ptr[i], e = bt_ptr[i + 1];
+        for (int q = b; q < e; ++q) {
+          const int j = bt_col[q];
+          if (j >= H) break;  // entries sorted ascending; tail rows are not head deps
+          l = max(l, s_lev[j] + 1);
+        }
+      }
+      if (l > s_lev[i]) {
+        s_lev[i] = l;
+        changed = 1;
+      }
+    }
+    if (!__syncthreads_or(changed)) break;
+  }
+  for (int i = threadIdx.x; i < H; i += kHeadThreads) level_out[i] = s_lev[i];
+}
+
+// Counting sort of head rows by level: ptr[L] = first position of level L.
+__global__ __launch_bounds__(kHeadThreads) void head_sort_kernel(int H,
+                                                                  const int* __restrict__ level,
+                                                                  int* __restrict__ ptr,
+                                                                  int* __restrict__ rows,
+                                                                  int* __restrict__ nlev_out) {
+  extern __shared__ int s_cnt[];  // H + 1 counters
+  for (int i = threadIdx.x; i <= H; i += kHeadThreads) s_cnt[i] = 0;
+  __syncthreads();
+  int mx = 0;
+  for (int i = threadIdx.x; i < H; i += kHeadThreads) {
+    const int l = level[i];
+    atomicAdd(&s_cnt[l], 1);
+    mx = max(mx, l);
+  }
+  __shared__ int s_max;
+  if (threadIdx.x == 0) s_max = 0;
+  __syncthreads();
+  atomicMax(&s_max, mx);
+  __syncthreads();
+  const int nlev = (H > 0) ? s_max + 1 : 0;
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int l = 0; l < nlev; ++l) {
+      const int c = s_cnt[l];
+      ptr[l] = run;
+      s_cnt[l] = run;
+      run += c;
+    }
+    ptr[nlev] = run;
+    *nlev_out = nlev;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < H; i += kHeadThreads) {
+    const int pos = atomicAdd(&s_cnt[level[i]], 1);
+    rows[pos] = i;
+  }
+}
+
+// ------------------------------------------------------------ head solves
+// One workgroup per column c = blockIdx.x.  The head values live in LDS,
+// pre-filled with the sentinel.  The level-ordered positions are cut into
+// batches of 64; wave w takes batches w, w + NT/64, ... and each lane one row
+// of the batch.  A position only depends on smaller positions, so the
+// smallest unfinished batch can always proceed and no barrier is needed: a
+// row polls LDS until each needed value differs from the sentinel.  Row data
+// is stored in position order (one coalesced load per batch), and the next
+// batch is fetched when the current one starts, so global-memory waits occur
+// only at batch boundaries.
+template <int W, int NT>
+__global__ __launch_bounds__(NT) void head_lower_kernel(
+    int H, int m, int t, const int* __restrict__ prow, const int* __restrict__ pnbr,
+    const double* __restrict__ pval, const double* __restrict__ X,
+    const double* __restrict__ rs, double* Y) {
+  extern __shared__ double s_y[];
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  constexpr int kWaves = NT / 64;
+  for (int i = tid; i < H; i += NT) s_y[i] = sentinel();
+  __syncthreads();
+  int ni = -1, nj[W];
+  double nv[W], nx = 0.0;
+  auto fetch = [&](int p) {
+    ni = (p < H) ? prow[p] : -1;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const bool in = (ni >= 0) && (k < m);
+      nj[k] = in ? pnbr[(int64_t)p * m + k] : -1;
+      nv[k] = in ? pval[(int64_t)p * m + k] : 0.0;
+    }
+    nx = 0.0;
+    if (ni >= 0) {
+      nx = X[(int64_t)ni * t + c];
+      if (rs) nx *= rs[ni];
+    }
+  };
+  int batch = tid >> 6;
+  fetch(batch * 64 + lane);
+  while (batch * 64 < H) {
+    const int ci = ni;
+    int cj[W];
+    double cv[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      cj[k] = nj[k];
+      cv[k] = nv[k];
+    }
+    double acc = nx;
+    fetch((batch + kWaves) * 64 + lane);
+    bool pending = ci >= 0;
+    int kk = 0;
+    while (__any(pending)) {
+      if (pending) {
+        // all pending values first (independent LDS reads), then consume in order
+        double yv[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+          yv[k] = (k >= kk && cj[k] >= 0) ? lds_poll(&s_y[cj[k]]) : 0.0;
+        bool stop = false;
+        int adv = 0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          if (!stop && k >= kk) {
+            if (cj[k] < 0) {
+              kk = W;
+              stop = true;
+            } else if (is_sentinel(yv[k])) {
+              stop = true;
+            } else {
+              acc -= cv[k] * yv[k];
+              ++adv;
+            }
+          }
+        }
+        if (kk < W) kk += adv;
+        if (kk >= W) {
+          lds_publish(&s_y[ci], acc);
+          Y[(int64_t)ci * t + c] = acc;
+          pending = false;
+        }
+      }
+    }
+    batch += kWaves;
+  }
+}
+
+// Upper: the right-hand side of head row j arrives in Y already reduced by its
+// tail dependents (head_upper_pre); the kernel subtracts the head-internal
+// entries of the B^T row of j, stored in position order (pptr/pcol/pval), in
+// windows of 16 (the first window is fetched with the batch).
+template <int NT>
+__global__ __launch_bounds__(NT) void head_upper_kernel(
+    int H, int t, const int* __restrict__ prow, const int* __restrict__ pptr,
+    const int* __restrict__ pcol, const double* __restrict__ pval, double* Y) {
+  extern __shared__ double s_y[];
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  constexpr int kWaves = NT / 64;
+  constexpr int kWin = 16;
+  for (int i = tid; i < H; i += NT) s_y[i] = sentinel();
+  __syncthreads();
+  int nrow = -1, nq = 0, ne = 0, ncb[kWin];
+  double nvb[kWin], nacc = 0.0;
+  auto fetch = [&](int p) {
+    nrow = (p < H) ? prow[p] : -1;
+    nq = (nrow >= 0) ? pptr[p] : 0;
+    ne = (nrow >= 0) ? pptr[p + 1] : 0;
+#pragma unroll
+    for (int k = 0; k < kWin; ++k) {
+      const bool in = nq + k < ne;
+      ncb[k] = in ? pcol[nq + k] : -1;
+      nvb[k] = in ? pval[nq + k] : 0.0;
+    }
+    nacc = (nrow >= 0) ? Y[(int64_t)nrow * t + c] : 0.0;
+  };
+  int batch = tid >> 6;
+  fetch(batch * 64 + lane);
+  while (batch * 64 < H) {
+    const int j = nrow;
+    int q = nq;
+    const int e = ne;
+    int cb[kWin];
+    double vb[kWin];
+#pragma unroll
+    for (int k = 0; k < kWin; ++k) {
+      cb[k] = ncb[k];
+      vb[k] = nvb[k];
+    }
+    double acc = nacc;
+    fetch((batch + kWaves) * 64 + lane);
+    bool pending = j >= 0;
+    int kk = 0;
+    while (__any(pending)) {
+      if (pending) {
+        if (kk == kWin) {  // next window of a long row
+#pragma unroll
+          for (int k = 0; k < kWin; ++k) {
+            const bool in = q + k < e;
+            cb[k] = in ? pcol[q + k] : -1;
+            vb[k] = in ? pval[q + k] : 0.0;
+          }
+          kk = 0;
+        }
+        double lv[kWin];
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) lv[k] = (k >= kk && cb[k] >= 0) ? lds_poll(&s_y[cb[k]]) : 0.0;
+        bool stop = false;
+        int adv = 0;
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) {
+          if (!stop && k >= kk) {
+            if (cb[k] < 0) {
+              stop = true;
+            } else if (is_sentinel(lv[k])) {
+              stop = true;
+            } else {
+              acc -= vb[k] * lv[k];
+              ++adv;
+            }
+          }
+        }
+        kk += adv;
+        if (q + kk >= e) {
+          lds_publish(&s_y[j], acc);
+          Y[(int64_t)j * t + c] = acc;
+          pending = false;
+        } else if (kk == kWin) {
+          q += kWin;
+        }
+      }
+    }
+    batch += kWaves;
+  }
+}
+
+// y_j <- x_j - sum over the tail entries of the B^T row of head row j (all
+// finished), for every head row and column; fully parallel.
+__global__ void head_upper_pre_kernel(int H, int t, const int* __restrict__ split,
+                                      const int* __restrict__ bt_ptr,
+                                      const int* __restrict__ bt_col,
+                                      const double* __restrict__ bt_val,
+                                      const double* __restrict__ X, double* Y) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= (int64_t)H * t) return;
+  const int j = static_cast<int>(g / t), c = static_cast<int>(g % t);
+  double acc = X[(int64_t)j * t + c];
+  const int e = bt_ptr[j + 1];
+  for (int q = split[j]; q < e; ++q) acc -= bt_val[q] * Y[(int64_t)bt_col[q] * t + c];
+  Y[(int64_t)j * t + c] = acc;
+}
+
+Status head_lower(Model& M, const double* X, double* Y, int t, const double* rs) {
+  const int H = M.head_rows;
+  if (H == 0) return Status::ok();
+  const size_t lds = sizeof(double) * H;
+  // two row windows (current and prefetched) stay in registers: 512 threads
+  // above 8 slots
+  if (M.m <= 8) {
+    hipLaunchKernelGGL((head_lower_kernel<8, 1024>), dim3(t), dim3(1024), lds, M.stream, H, M.m,
+                       t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
+  } else if (M.m <= 16) {
+    hipLaunchKernelGGL((head_lower_kernel<16, 512>), dim3(t), dim3(512), lds, M.stream, H,
+                       M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
+  } else if (M.m <= 24) {
+    hipLaunchKernelGGL((head_lower_kernel<24, 512>), dim3(t), dim3(512), lds, M.stream, H,
+                       M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
+  } else {
+    hipLaunchKernelGGL((head_lower_kernel<32, 512>), dim3(t), dim3(512), lds, M.stream, H, M.m,
+                       t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
+  }
+  return check_launch("head lower");
+}
+
+Status head_upper(Model& M, const double* X, double* Y, int t) {
+  const int H = M.head_rows;
+  if (H == 0) return Status::ok();
+  const int64_t work = (int64_t)H * t;
+  hipLaunchKernelGGL(head_upper_pre_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0,
+                     M.stream, H, t, M.head_split.p, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, Y);
+  const size_t lds = sizeof(double) * H;
+  hipLaunchKernelGGL(head_upper_kernel<512>, dim3(t), dim3(512), lds, M.stream, H, t,
+                     M.hb_rows.p, M.hb_pptr.p, M.hb_col.p, M.hb_val.p, Y);
+  return check_launch("head upper");
+}
+
+// ---- position-ordered copies of the head's rows of B and B^T
+__global__ void head_copy_fwd_kernel(int H, int m, const int* __restrict__ prow,
+                                     const int* __restrict__ nbr, int* __restrict__ pnbr) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)H * m) return;
+  const int p = static_cast<int>(e / m), k = static_cast<int>(e % m);
+  pnbr[e] = nbr[(int64_t)prow[p] * m + k];
+}
+
+// Rows of B^T are sorted by column, so a head row's head-internal entries
+// (columns < H) form a prefix; split[j] is where its tail entries begin.
+__global__ void head_len_bwd_kernel(int H, const int* __restrict__ prow,
+                                    const int* __restrict__ bt_ptr,
+                                    const int* __restrict__ bt_col, int* __restrict__ len,
+                                    int* __restrict__ split) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < H) {
+    const int j = prow[p];
+    int q = bt_ptr[j];
+    const int e = bt_ptr[j + 1];
+    while (q < e && bt_col[q] < H) ++q;
+    len[p] = q - bt_ptr[j];
+    split[j] = q;
+  }
+  if (p == H) len[p] = 0;
+}
+
+__global__ void head_copy_bwd_kernel(int H, const int* __restrict__ prow,
+                                     const int* __restrict__ bt_ptr,
+                                     const int* __restrict__ bt_col,
+                                     const int* __restrict__ bt_src,
+                                     const int* __restrict__ pptr, int* __restrict__ pcol,
+                                     int* __restrict__ psrc) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= H) return;
+  const int j = prow[p];
+  const int b = bt_ptr[j], e = b + (pptr[p + 1] - pptr[p]), o = pptr[p];
+  for (int q = b; q < e; ++q) {
+    pcol[o + q - b] = bt_col[q];
+    psrc[o + q - b] = bt_src[q];
+  }
+}
+
+__global__ void head_vals_kernel(int H, int m, const int* __restrict__ prow,
+                                 const double* __restrict__ bval, double* __restrict__ pval_f,
+                                 int nb, const int* __restrict__ psrc,
+                                 double* __restrict__ pval_b) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < (int64_t)H * m) {
+    const int p = static_cast<int>(e / m), k = static_cast<int>(e % m);
+    pval_f[e] = bval[(int64_t)prow[p] * m + k];
+  }
+  if (e < nb) pval_b[e] = bval[psrc[e]];
+}
+
+Status refresh_head_values(Model& M) {
+  const int H = M.head_rows;
+  if (H == 0) return Status::ok();
+  const int64_t work = std::max<int64_t>((int64_t)H * M.m, M.head_nnz_b);
+  if (work == 0) return Status::ok();
+  hipLaunchKernelGGL(head_vals_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0,
+                     M.stream, H, M.m, M.hf_rows.p, M.bval.p, M.hf_val.p,
+                     static_cast<int>(M.head_nnz_b), M.hb_src.p, M.hb_val.p);
+  return check_launch("head values");
+}
+
+template <class K>
+static void allow_lds(K kernel, size_t bytes) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+  (void)hipGetLastError();
+}
+
+Status build_head_schedule(Model& M) {
+  int max_lds = 0;
+  VL_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, M.device));
+  int64_t cap = (static_cast<int64_t>(max_lds) - 1024) / static_cast<int64_t>(sizeof(double));
+  if (cap > kHeadRows) cap = kHeadRows;
+  if (cap < 0) cap = 0;
+  int64_t H = M.n < cap ? M.n : cap;
+  const size_t bytes = sizeof(double) * static_cast<size_t>(H);
+  allow_lds(head_lower_kernel<8, 1024>, bytes);
+  allow_lds(head_lower_kernel<16, 512>, bytes);
+  allow_lds(head_lower_kernel<24, 512>, bytes);
+  allow_lds(head_lower_kernel<32, 512>, bytes);
+  allow_lds(head_upper_kernel<512>, bytes);
+  M.head_rows = static_cast<int>(H);
+  if (H == 0) return Status::ok();
+  DevBuf<int> lev, nlev;
+  VL_TRY(lev.alloc(H));
+  VL_TRY(nlev.alloc(2));
+  VL_TRY(M.hf_ptr.alloc(H + 1));
+  VL_TRY(M.hf_rows.alloc(H));
+  VL_TRY(M.hb_ptr.alloc(H + 1));
+  VL_TRY(M.hb_rows.alloc(H));
+  const size_t lds = sizeof(int) * (H + 1);
+  for (int dir = 0; dir < 2; ++dir) {
+    hipLaunchKernelGGL(head_levels_kernel, dim3(1), dim3(kHeadThreads), lds, M.stream,
+                       static_cast<int>(H), M.m, M.nbr.p, M.bt_ptr.p, M.bt_col.p, dir, lev.p);
+    hipLaunchKernelGGL(head_sort_kernel, dim3(1), dim3(kHeadThreads), lds, M.stream,
+                       static_cast<int>(H), lev.p, dir ? M.hb_ptr.p : M.hf_ptr.p,
+                       dir ? M.hb_rows.p : M.hf_rows.p, nlev.p + dir);
+  }
+  VL_TRY(check_launch("head schedule"));
+  int h_nlev[2];
+  VL_HIP(hipMemcpyAsync(h_nlev, nlev.p, sizeof(int) * 2, hipMemcpyDeviceToHost, M.stream));
+  VL_TRY(sync_stream(M.stream));
+  M.head_nlev_f = h_nlev[0];
+  M.head_nlev_b = h_nlev[1];
+  // position-ordered copies (structure; values follow in refresh_head_values)
+  const int m = M.m;
+  VL_TRY(M.hf_nbr.alloc((size_t)H * (m > 0 ? m : 1)));
+  VL_TRY(M.hf_val.alloc((size_t)H * (m > 0 ? m : 1)));
+  if ((int64_t)H * m > 0)
+    hipLaunchKernelGGL(head_copy_fwd_kernel, dim3((unsigned)((H * m + 255) / 256)), dim3(256), 0,
+                       M.stream, static_cast<int>(H), m, M.hf_rows.p, M.nbr.p, M.hf_nbr.p);
+  DevBuf<int> len;
+  VL_TRY(len.alloc(H + 1));
+  VL_TRY(M.hb_pptr.alloc(H + 1));
+  VL_TRY(M.head_split.alloc(H));
+  hipLaunchKernelGGL(head_len_bwd_kernel, dim3((unsigned)((H + 256) / 256)), dim3(256), 0,
+                     M.stream, static_cast<int>(H), M.hb_rows.p, M.bt_ptr.p, M.bt_col.p, len.p,
+                     M.head_split.p);
+  VL_TRY(exclusive_scan_int(len.p, M.hb_pptr.p, H + 1, M.stream));
+  int nnzb = 0;
+  VL_HIP(hipMemcpyAsync(&nnzb, M.hb_pptr.p + H, sizeof(int), hipMemcpyDeviceToHost, M.stream));
+  VL_TRY(sync_stream(M.stream));
+  M.head_nnz_b = nnzb;
+  VL_TRY(M.hb_col.alloc(nnzb));
+  VL_TRY(M.hb_src.alloc(nnzb));
+  VL_TRY(M.hb_val.alloc(nnzb));
+  hipLaunchKernelGGL(head_copy_bwd_kernel, dim3((unsigned)((H + 255) / 256)), dim3(256), 0,
+                     M.stream, static_cast<int>(H), M.hb_rows.p, M.bt_ptr.p, M.bt_col.p,
+                     M.bt_src.p, M.hb_pptr.p, M.hb_col.p, M.hb_src.p);
+  VL_TRY(check_launch("head copies"));
+  return sync_stream(M.stream);
+}
+
+}  // namespace vl

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void cg_init_kernel(ChunkGrid g, const double*
   Y[o] = sentinel();
   Z[o] = sentinel();
   CHUNK_LOOP_END
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 4) counter[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && blockIdx.y == 0) reset_counters(counter);
 }
 
 // H = Z (and Z0 = Z); partial sums of r.z
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void cg_update_ur_kernel(
   Z[o] = sentinel();
   CHUNK_LOOP_END
   block_colsum(g, acc, part);
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 4) counter[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && blockIdx.y == 0) reset_counters(counter);
 }
 
 // beta = r_new.z_new / r.z; records beta; stopping test on ||r||_2
@@ -231,7 +231,7 @@ static Status cg_reserve(Model& M, CgState& S, int t, int lmax, bool keep_z0) {
   ChunkGrid g = ChunkGrid::of(M.n, t);
   VL_TRY(S.part_a.reserve(static_cast<size_t>(g.nchunk) * t));
   VL_TRY(S.part_b.reserve(static_cast<size_t>(g.nchunk) * t));
-  VL_TRY(M.counter.reserve(64));
+  VL_TRY(M.counter.reserve(2 * kSlotInts + 64));
   if (!M.host_pin) VL_HIP(hipHostMalloc(reinterpret_cast<void**>(&M.host_pin), 64 * sizeof(double)));
   S.t = t;
   S.lmax = lmax;

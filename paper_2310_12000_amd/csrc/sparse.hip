@@ -16,6 +16,8 @@
 // the sentinel.  Values are published with device-coherent relaxed stores, so
 // no grid-wide barrier is needed per level of the dependency DAG.  Each row
 // sums its terms in a fixed order, so results do not depend on timing.
+#include <algorithm>
+
 #include "vl_internal.h"
 #include "vl_ops.h"
 
@@ -135,63 +137,93 @@ Status refresh_transpose_values(Model& M) {
 }
 
 // ------------------------------------------------------------------ SpMM
+// Work unit -> (row, column).  For t > 64 units are slice-major (all rows of
+// slice 0, then slice 1, ...), so one 64-column slice of the operand is the
+// working set at a time.  `order` (optional) maps the unit's row position to
+// a row index (spatial order for products; topological order is required
+// for solves, which pass nullptr and use index order).
 struct UnitPos {
   int64_t i;
   int c;
   bool valid;
 };
 __device__ __forceinline__ UnitPos unit_pos(int64_t unit, int lane, Lanes L, int64_t n, int t,
-                                            bool reverse) {
-  int64_t rg = unit / L.slices;
-  int slice = static_cast<int>(unit - rg * L.slices);
-  int sub = lane >> L.lpr_log;
-  int c = slice * 64 + (lane & ((1 << L.lpr_log) - 1));
-  int64_t r = (rg << L.rpw_log) + sub;
+                                            bool reverse, const int* __restrict__ order) {
+  const int64_t rgs = (n + (1 << L.rpw_log) - 1) >> L.rpw_log;
+  const int64_t slice = unit / rgs;
+  const int64_t rg = unit - slice * rgs;
+  const int sub = lane >> L.lpr_log;
+  const int c = static_cast<int>(slice) * 64 + (lane & ((1 << L.lpr_log) - 1));
+  const int64_t r = (rg << L.rpw_log) + sub;
   UnitPos p;
-  p.i = reverse ? (n - 1 - r) : r;
-  p.c = c;
   p.valid = (r < n) && (c < t);
+  int64_t rr = reverse ? (n - 1 - r) : r;
+  if (order && p.valid) rr = order[rr];
+  p.i = rr;
+  p.c = c;
   return p;
 }
 
-// Y_i = rs_i * (unit * X_i + sum_k vals[i,k] X_{nbr[i,k]})
-template <class In>
+// Y_i = rs_i * (unit * X_i + sum_k vals[i,k] X_{nbr[i,k]}); the W <= 32
+// neighbour slots are loaded unconditionally-predicated so all gathers of a
+// row are in flight together.
+template <int W, class In>
 __global__ __launch_bounds__(256) void spmm_ell_kernel(int64_t n, int m, int t, Lanes L,
+                                                       const int* __restrict__ order,
                                                        const int* __restrict__ nbr,
                                                        const double* __restrict__ vals, In x,
                                                        const double* __restrict__ rs,
                                                        int unit_diag, double* __restrict__ Y) {
   const int lane = threadIdx.x & 63;
-  const int64_t unit = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t unit = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (unit >= units_of_hd(n, t, L)) return;
-  UnitPos p = unit_pos(unit, lane, L, n, t, false);
+  UnitPos p = unit_pos(unit, lane, L, n, t, false, order);
   if (!p.valid) return;
   const int* nb = nbr + p.i * m;
   const double* vb = vals + p.i * m;
-  double acc = unit_diag ? x(p.i, p.c) : 0.0;
-  for (int k = 0; k < m; ++k) {
-    int j = nb[k];
-    if (j < 0) break;
-    acc += vb[k] * x(j, p.c);
+  int js[W];
+  double vv[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    js[k] = (k < m) ? nb[k] : -1;
+    vv[k] = (k < m) ? vb[k] : 0.0;
   }
+  double xs[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) xs[k] = (js[k] >= 0) ? x(js[k], p.c) : 0.0;
+  double acc = unit_diag ? x(p.i, p.c) : 0.0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) acc += vv[k] * xs[k];
   if (rs) acc *= rs[p.i];
   Y[p.i * t + p.c] = acc;
 }
 
-// Y_j = d_j * v_j + X_j + sum_e btval[e] X_{btcol[e]}   (v from memory or probe)
+// Y_j = d_j * v_j + X_j + sum_e btval[e] X_{btcol[e]}; entries in batches of 8
 template <class In, class Dv>
 __global__ __launch_bounds__(256) void spmm_csr_t_kernel(
-    int64_t n, int t, Lanes L, const int* __restrict__ ptr, const int* __restrict__ col,
-    const double* __restrict__ val, In x, const double* __restrict__ d, Dv v,
-    double* __restrict__ Y) {
+    int64_t n, int t, Lanes L, const int* __restrict__ order, const int* __restrict__ ptr,
+    const int* __restrict__ col, const double* __restrict__ val, In x,
+    const double* __restrict__ d, Dv v, double* __restrict__ Y) {
   const int lane = threadIdx.x & 63;
-  const int64_t unit = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t unit = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (unit >= units_of_hd(n, t, L)) return;
-  UnitPos p = unit_pos(unit, lane, L, n, t, false);
+  UnitPos p = unit_pos(unit, lane, L, n, t, false, order);
   if (!p.valid) return;
   double acc = x(p.i, p.c);
   const int b = ptr[p.i], e = ptr[p.i + 1];
-  for (int q = b; q < e; ++q) acc += val[q] * x(col[q], p.c);
+  for (int q = b; q < e; q += 8) {
+    int cs[8];
+    double vs[8], xs[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      cs[k] = (q + k < e) ? col[q + k] : -1;
+      vs[k] = (q + k < e) ? val[q + k] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) xs[k] = (cs[k] >= 0) ? x(cs[k], p.c) : 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += vs[k] * xs[k];
+  }
   if (d) acc += d[p.i] * v(p.i, p.c);
   Y[p.i * t + p.c] = acc;
 }
@@ -200,34 +232,47 @@ struct InNone {
   __device__ __forceinline__ double operator()(int64_t, int) const { return 0.0; }
 };
 
-Status spmm_b(Model& M, const double* X, double* Y, int t, const double* rowscale) {
+static const int* spatial_order(Model& M) { return static_cast<const int*>(M.grid_pts); }
+
+#define VL_ELL_LAUNCH(W, ...)                                                                   \
+  hipLaunchKernelGGL((spmm_ell_kernel<W, InMem>), dim3(nb), dim3(256), 0, M.stream, __VA_ARGS__)
+
+static Status launch_ell(Model& M, const double* vals, const double* X, double* Y, int t,
+                         const double* rowscale, int unit_diag) {
   Lanes L = Lanes::of(t);
   int nb = spmm_nblocks(M.n, t);
-  hipLaunchKernelGGL(spmm_ell_kernel<InMem>, dim3(nb), dim3(256), 0, M.stream, M.n, M.m, t, L,
-                     M.nbr.p, M.bval.p, InMem{X, t}, rowscale, 1, Y);
-  return check_launch("spmm_b");
+  const int* ord = spatial_order(M);
+  if (M.m <= 8) {
+    VL_ELL_LAUNCH(8, M.n, M.m, t, L, ord, M.nbr.p, vals, InMem{X, t}, rowscale, unit_diag, Y);
+  } else if (M.m <= 16) {
+    VL_ELL_LAUNCH(16, M.n, M.m, t, L, ord, M.nbr.p, vals, InMem{X, t}, rowscale, unit_diag, Y);
+  } else {
+    VL_ELL_LAUNCH(32, M.n, M.m, t, L, ord, M.nbr.p, vals, InMem{X, t}, rowscale, unit_diag, Y);
+  }
+  return check_launch("spmm_ell");
+}
+
+Status spmm_b(Model& M, const double* X, double* Y, int t, const double* rowscale) {
+  return launch_ell(M, M.bval.p, X, Y, t, rowscale, 1);
 }
 
 Status spmm_ell_vals(Model& M, const double* vals, const double* X, double* Y, int t,
                      const double* rowscale, bool unit_diag) {
-  Lanes L = Lanes::of(t);
-  int nb = spmm_nblocks(M.n, t);
-  hipLaunchKernelGGL(spmm_ell_kernel<InMem>, dim3(nb), dim3(256), 0, M.stream, M.n, M.m, t, L,
-                     M.nbr.p, vals, InMem{X, t}, rowscale, unit_diag ? 1 : 0, Y);
-  return check_launch("spmm_ell");
+  return launch_ell(M, vals, X, Y, t, rowscale, unit_diag ? 1 : 0);
 }
 
 Status spmm_bt(Model& M, const double* X, double* Y, int t, const double* diag,
                const double* diagvec) {
   Lanes L = Lanes::of(t);
   int nb = spmm_nblocks(M.n, t);
+  const int* ord = spatial_order(M);
   if (diag) {
     hipLaunchKernelGGL((spmm_csr_t_kernel<InMem, InMem>), dim3(nb), dim3(256), 0, M.stream, M.n,
-                       t, L, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, InMem{X, t}, diag,
+                       t, L, ord, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, InMem{X, t}, diag,
                        InMem{diagvec, t}, Y);
   } else {
     hipLaunchKernelGGL((spmm_csr_t_kernel<InMem, InNone>), dim3(nb), dim3(256), 0, M.stream,
-                       M.n, t, L, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, InMem{X, t}, nullptr,
+                       M.n, t, L, ord, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, InMem{X, t}, nullptr,
                        InNone{}, Y);
   }
   return check_launch("spmm_bt");
@@ -238,122 +283,142 @@ Status spmm_bt_probe(Model& M, double* Y, int t, const double* s, uint64_t seed,
                      int col0, int gauss2, const double* d, uint32_t tag1, int gauss1) {
   Lanes L = Lanes::of(t);
   int nb = spmm_nblocks(M.n, t);
+  const int* ord = spatial_order(M);
   InProbe x{s, seed, tag2, col0, gauss2};
   if (d) {
     InProbe v{nullptr, seed, tag1, col0, gauss1};
     hipLaunchKernelGGL((spmm_csr_t_kernel<InProbe, InProbe>), dim3(nb), dim3(256), 0, M.stream,
-                       M.n, t, L, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, x, d, v, Y);
+                       M.n, t, L, ord, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, x, d, v, Y);
   } else {
     hipLaunchKernelGGL((spmm_csr_t_kernel<InProbe, InNone>), dim3(nb), dim3(256), 0, M.stream,
-                       M.n, t, L, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, x, nullptr, InNone{}, Y);
+                       M.n, t, L, ord, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, x, nullptr, InNone{},
+                       Y);
   }
   return check_launch("spmm_bt_probe");
 }
 
 // --------------------------------------------------------- sync-free TRSM
-constexpr int kTrsmChunk = 4;          // work units taken per counter increment
 constexpr int kSpinLimit = 1 << 22;    // poll rounds before a wave gives up
 
-__device__ __forceinline__ int64_t grab(int* counter, int lane) {
+__device__ __forceinline__ int64_t grab(int* counter, int lane, int chunk) {
   int v = 0;
   if (lane == 0) v = atomicAdd(counter, 1);
-  return static_cast<int64_t>(__shfl(v, 0)) * kTrsmChunk;
+  return static_cast<int64_t>(__shfl(v, 0)) * chunk;
 }
 
-// Lower solve: Y_i = rs_i * X_i - sum_k vals[i,k] Y_{nbr[i,k]}   (B Y = rs o X)
-template <class In>
-__global__ __launch_bounds__(256) void trsm_lower_kernel(
-    int64_t n, int m, int t, Lanes L, const int* __restrict__ nbr,
-    const double* __restrict__ vals, In x, const double* __restrict__ rs, double* Y,
-    int* counter, int* abort_flag, int* status) {
-  const int lane = threadIdx.x & 63;
-  const int64_t total = units_of_hd(n, t, L);
-  for (;;) {
-    const int64_t u0 = grab(counter, lane);
-    if (u0 >= total) return;
-    for (int64_t unit = u0; unit < u0 + kTrsmChunk && unit < total; ++unit) {
-      UnitPos p = unit_pos(unit, lane, L, n, t, false);
-      bool pending = p.valid;
-      double acc = 0.0;
-      int k = 0;
-      const int* nb = nbr + (p.valid ? p.i * m : 0);
-      const double* vb = vals + (p.valid ? p.i * m : 0);
-      if (p.valid) {
-        acc = x(p.i, p.c);
-        if (rs) acc *= rs[p.i];
-      }
-      int rounds = 0;
-      while (__any(pending)) {
-        if (pending) {
-          for (; k < m; ++k) {
-            const int j = nb[k];
-            if (j < 0) {
-              k = m;
-              break;
-            }
-            const double v = poll_load(&Y[(int64_t)j * t + p.c]);
-            if (is_sentinel(v)) break;
-            acc -= vb[k] * v;
-          }
-          if (k >= m) {
-            publish(&Y[p.i * t + p.c], acc);
-            pending = false;
-          }
-        }
-        if (__any(pending)) {
-          ++rounds;
-          __builtin_amdgcn_s_sleep(1);
-          if ((rounds & 63) == 0) {
-            if (poll_load(abort_flag) != 0) return;
-            if (rounds > kSpinLimit) {
-              if (lane == 0) {
-                publish(abort_flag, 1);
-                raise_error(status, kErrTimeout);
-              }
-              return;
-            }
-          }
-        }
-      }
-    }
-  }
+// Work streams: units u = s + S k belong to stream s = blockIdx mod S, each
+// stream with its own counter (own cache line) handing its units out in
+// increasing order.  Every stream follows the global topological order, so
+// the smallest unfinished unit can always be taken or finished: no deadlock,
+// and S counters spread the atomic traffic.
+__device__ __forceinline__ int64_t grab_stream(int* counters, int lane, int nstreams) {
+  const int s = blockIdx.x % nstreams;
+  int v = 0;
+  if (lane == 0) v = atomicAdd(&counters[s * kCounterStride], 1);
+  v = __shfl(v, 0);
+  return static_cast<int64_t>(s) + static_cast<int64_t>(nstreams) * v;
 }
 
-// Upper solve with B^T rows (CSR): Y_j = X_j - sum_e btval[e] Y_{btcol[e]}
-template <class In>
-__global__ __launch_bounds__(256) void trsm_upper_kernel(
-    int64_t n, int t, Lanes L, const int* __restrict__ ptr, const int* __restrict__ col,
-    const double* __restrict__ val, In x, double* Y, int* counter, int* abort_flag,
-    int* status) {
+// One row of a triangular solve, consumed in windows of W entries:
+//   Y_i = rs_i X_i - sum_q vals[q] Y_{idx[q]},  q in [q0, e) (idx < 0 ends the row).
+// A window's indices and values are loaded once; its Y entries are read first
+// through the caches (a cached copy can only be a stale sentinel, since every
+// entry changes once, from the sentinel to its final value) and then only the
+// still-missing ones are polled device-coherently.  Entries are consumed
+// strictly in order, so the sum order is fixed.  Rows r0..n-1 are solved,
+// taken in the topological order `order` (level by level) when given, else
+// ascending (lower) / descending (upper); rows below r0 must be final.
+template <int W, bool LOWER, class In>
+__global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m, int t, Lanes L,
+                                                   const int* __restrict__ order,
+                                                   const int* __restrict__ ptr,
+                                                   const int* __restrict__ idx,
+                                                   const double* __restrict__ vals, In x,
+                                                   const double* __restrict__ rs, double* Y,
+                                                   int nstreams, int* counter, int* abort_flag,
+                                                   int* status) {
   const int lane = threadIdx.x & 63;
-  const int64_t total = units_of_hd(n, t, L);
+  const int64_t nt = n - r0;
+  const int64_t total = units_of_hd(nt, t, L);
   for (;;) {
-    const int64_t u0 = grab(counter, lane);
-    if (u0 >= total) return;
-    for (int64_t unit = u0; unit < u0 + kTrsmChunk && unit < total; ++unit) {
-      UnitPos p = unit_pos(unit, lane, L, n, t, true);
-      bool pending = p.valid;
+    const int64_t unit = grab_stream(counter, lane, nstreams);
+    if (unit >= total) return;
+    {
+      const int64_t rg = unit / L.slices;
+      const int slice = static_cast<int>(unit - rg * L.slices);
+      const int64_t r = (rg << L.rpw_log) + (lane >> L.lpr_log);
+      const int c = slice * 64 + (lane & ((1 << L.lpr_log) - 1));
+      const bool valid = (r < nt) && (c < t);
+      int64_t i = LOWER ? (r0 + r) : (n - 1 - r);
+      if (order && r < nt) i = order[r];
+      bool pending = valid;
       double acc = 0.0;
       int q = 0, e = 0;
-      if (p.valid) {
-        acc = x(p.i, p.c);
-        q = ptr[p.i];
-        e = ptr[p.i + 1];
+      if (valid) {
+        acc = x(i, c);
+        if (rs) acc *= rs[i];
+        if (LOWER) {
+          q = static_cast<int>(i * m);
+          e = q + m;
+        } else {
+          q = ptr[i];
+          e = ptr[i + 1];
+        }
+        if (q >= e) {
+          publish(&Y[i * t + c], acc);
+          pending = false;
+        }
       }
+      int cb[W];
+      double vb[W], yv[W];
+      int kk = W;  // cursor in the current window; W = no window loaded
       int rounds = 0;
       while (__any(pending)) {
+        bool progressed = false;
         if (pending) {
-          for (; q < e; ++q) {
-            const double v = poll_load(&Y[(int64_t)col[q] * t + p.c]);
-            if (is_sentinel(v)) break;
-            acc -= val[q] * v;
+          if (kk == W) {
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+              const bool in = (q + k < e);
+              cb[k] = in ? idx[q + k] : -1;
+              vb[k] = in ? vals[q + k] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+              yv[k] = (cb[k] >= 0) ? Y[(int64_t)cb[k] * t + c] : 0.0;
+            kk = 0;
+          } else {
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+              if (k >= kk && cb[k] >= 0 && is_sentinel(yv[k]))
+                yv[k] = poll_load(&Y[(int64_t)cb[k] * t + c]);
           }
-          if (q >= e) {
-            publish(&Y[p.i * t + p.c], acc);
+          bool stop = false, ended = false;
+          int adv = 0;
+#pragma unroll
+          for (int k = 0; k < W; ++k) {
+            if (!stop && k >= kk) {
+              if (cb[k] < 0) {
+                stop = true;
+                ended = true;
+              } else if (is_sentinel(yv[k])) {
+                stop = true;
+              } else {
+                acc -= vb[k] * yv[k];
+                ++adv;
+              }
+            }
+          }
+          kk += adv;
+          progressed = adv > 0;
+          if (ended || q + kk >= e) {
+            publish(&Y[i * t + c], acc);
             pending = false;
+          } else if (kk == W) {
+            q += W;  // window consumed: the next round loads the next one
           }
         }
-        if (__any(pending)) {
+        if (__any(pending) && !__any(progressed)) {
           ++rounds;
           __builtin_amdgcn_s_sleep(1);
           if ((rounds & 63) == 0) {
@@ -374,56 +439,91 @@ __global__ __launch_bounds__(256) void trsm_upper_kernel(
 
 // Fill Y with the sentinel and reset the work counter and abort flag.
 __global__ void trsm_prefill(double* __restrict__ Y, int64_t count, int* counter) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i == 0) {
-    counter[0] = 0;
-    counter[1] = 0;
-  }
-  for (; i < count; i += (int64_t)gridDim.x * blockDim.x) Y[i] = sentinel();
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < kSlotInts; k += blockDim.x) counter[k] = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    Y[i] = sentinel();
 }
 
 static int trsm_grid(int64_t total_units) {
-  int64_t chunks = (total_units + kTrsmChunk - 1) / kTrsmChunk;
-  int64_t blocks = (chunks + 3) / 4;
+  int64_t blocks = (total_units + 3) / 4;
   const int64_t cap = 256 * 8;  // about eight resident blocks per CU
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   return static_cast<int>(blocks);
 }
 
-// Counter slots: slot k uses counter[2k] (work units) and counter[2k + 1]
-// (abort flag).  Callers that pre-fill the output themselves must also have
-// reset the slot.
+static int trsm_streams(int blocks) {
+  return blocks < kCounterStreams ? blocks : kCounterStreams;
+}
+
+// Counter slots: slot k uses counter[k * kSlotInts ...] (streams and abort
+// flag).  Callers that pre-fill the output themselves must also have reset
+// the slot.
 static Status trsm_prepare(Model& M, double* Y, int64_t count, int slot) {
-  VL_TRY(M.counter.reserve(64));
+  VL_TRY(M.counter.reserve(2 * kSlotInts + 64));
   int g = static_cast<int>((count + 255) / 256);
   if (g > 4096) g = 4096;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(trsm_prefill, dim3(g), dim3(256), 0, M.stream, Y, count,
-                     M.counter.p + 2 * slot);
+                     M.counter.p + slot * kSlotInts);
   return check_launch("trsm prefill");
 }
+
+// Head rows are used for t <= 64 (one workgroup per column).
+// Head rows (solved in LDS) for t <= 64; wider blocks are bandwidth-bound
+// and use the sync-free kernels for all rows.
+static int64_t head_of(const Model& M, int t) { return t <= 64 ? M.head_rows : 0; }
 
 Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* rowscale,
                    bool prefilled, int slot) {
   if (!prefilled) VL_TRY(trsm_prepare(M, Y, M.n * (int64_t)t, slot));
+  const int64_t H = head_of(M, t);
+  if (H > 0) VL_TRY(head_lower(M, X, Y, t, rowscale));
+  if (H >= M.n) return Status::ok();
   Lanes L = Lanes::of(t);
-  int g = trsm_grid(units_of(M.n, t));
-  int* cnt = M.counter.p + 2 * slot;
-  hipLaunchKernelGGL(trsm_lower_kernel<InMem>, dim3(g), dim3(256), 0, M.stream, M.n, M.m, t, L,
-                     M.nbr.p, M.bval.p, InMem{X, t}, rowscale, Y, cnt, cnt + 1, M.status);
+  int g = trsm_grid(units_of(M.n - H, t));
+  const int ns = trsm_streams(g);
+  int* cnt = M.counter.p + slot * kSlotInts;
+  if (M.m <= 8) {
+    hipLaunchKernelGGL((trsm_kernel<8, true, InMem>), dim3(g), dim3(256), 0, M.stream, M.n, H,
+                       M.m, t, L, H ? M.tail_order_f.p : M.full_order_f.p, nullptr, M.nbr.p,
+                       M.bval.p, InMem{X, t},
+                       rowscale, Y, ns,
+                       cnt, cnt + kAbortOffset, M.status);
+  } else if (M.m <= 16) {
+    hipLaunchKernelGGL((trsm_kernel<16, true, InMem>), dim3(g), dim3(256), 0, M.stream, M.n, H,
+                       M.m, t, L, H ? M.tail_order_f.p : M.full_order_f.p, nullptr, M.nbr.p,
+                       M.bval.p, InMem{X, t},
+                       rowscale, Y, ns,
+                       cnt, cnt + kAbortOffset, M.status);
+  } else {
+    hipLaunchKernelGGL((trsm_kernel<32, true, InMem>), dim3(g), dim3(256), 0, M.stream, M.n, H,
+                       M.m, t, L, H ? M.tail_order_f.p : M.full_order_f.p, nullptr, M.nbr.p,
+                       M.bval.p, InMem{X, t},
+                       rowscale, Y, ns,
+                       cnt, cnt + kAbortOffset, M.status);
+  }
   return check_launch("trsm_b");
 }
 
 Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled, int slot) {
   if (!prefilled) VL_TRY(trsm_prepare(M, Y, M.n * (int64_t)t, slot));
-  Lanes L = Lanes::of(t);
-  int g = trsm_grid(units_of(M.n, t));
-  int* cnt = M.counter.p + 2 * slot;
-  hipLaunchKernelGGL(trsm_upper_kernel<InMem>, dim3(g), dim3(256), 0, M.stream, M.n, t, L,
-                     M.bt_ptr.p, M.bt_col.p, M.bt_val.p, InMem{X, t}, Y, cnt, cnt + 1,
-                     M.status);
-  return check_launch("trsm_bt");
+  const int64_t H = head_of(M, t);
+  if (H < M.n) {
+    Lanes L = Lanes::of(t);
+    int g = trsm_grid(units_of(M.n - H, t));
+    const int ns = trsm_streams(g);
+    int* cnt = M.counter.p + slot * kSlotInts;
+    hipLaunchKernelGGL((trsm_kernel<16, false, InMem>), dim3(g), dim3(256), 0, M.stream, M.n, H,
+                       0, t, L, H ? M.tail_order_b.p : M.full_order_b.p, M.bt_ptr.p,
+                       M.bt_col.p, M.bt_val.p,
+                       InMem{X, t}, nullptr, Y, ns, cnt, cnt + kAbortOffset, M.status);
+    VL_TRY(check_launch("trsm_bt"));
+  }
+  if (H > 0) VL_TRY(head_upper(M, X, Y, t));
+  return Status::ok();
 }
 
 Status trsm_b(Model& M, const double* X, double* Y, int t, const double* rowscale,
@@ -433,6 +533,151 @@ Status trsm_b(Model& M, const double* X, double* Y, int t, const double* rowscal
 
 Status trsm_bt(Model& M, const double* X, double* Y, int t, bool prefilled) {
   return trsm_bt_slot(M, X, Y, t, prefilled, 0);
+}
+
+// ------------------------------------------------------ level schedules
+// Longest-path level of every row in the dependency DAG of B (lower: over
+// N(i); upper: over the rows of B^T), computed once per neighbour set with
+// the same sync-free scheme as the solves (sentinel -1, 64 rows per wave).
+template <int W, bool LOWER>
+__global__ __launch_bounds__(256) void levels_kernel(int64_t n, int m,
+                                                     const int* __restrict__ ptr,
+                                                     const int* __restrict__ idx, int* lev,
+                                                     int* counter, int* abort_flag,
+                                                     int* status) {
+  const int lane = threadIdx.x & 63;
+  const int64_t total = (n + 63) >> 6;
+  for (;;) {
+    const int64_t u = grab(counter, lane, 1);
+    if (u >= total) return;
+    const int64_t r = (u << 6) + lane;
+    const bool valid = r < n;
+    const int64_t i = LOWER ? r : (n - 1 - r);
+    bool pending = valid;
+    int q = 0, e = 0, acc = 0;
+    if (valid) {
+      if (LOWER) {
+        q = static_cast<int>(i * m);
+        e = q + m;
+      } else {
+        q = ptr[i];
+        e = ptr[i + 1];
+      }
+    }
+    int rounds = 0;
+    while (__any(pending)) {
+      bool progressed = false;
+      if (pending) {
+        int cb[W], lv[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) cb[k] = (q + k < e) ? idx[q + k] : -1;
+#pragma unroll
+        for (int k = 0; k < W; ++k) lv[k] = (cb[k] >= 0) ? poll_load(&lev[cb[k]]) : 0;
+        bool stop = false;
+        int adv = 0;
+        bool ended = false;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          if (!stop) {
+            if (cb[k] < 0) {
+              stop = ended = true;
+            } else if (lv[k] < 0) {
+              stop = true;
+            } else {
+              acc = max(acc, lv[k] + 1);
+              ++adv;
+            }
+          }
+        }
+        q += adv;
+        progressed = adv > 0;
+        if (ended || q >= e) {
+          publish(&lev[i], acc);
+          pending = false;
+        }
+      }
+      if (__any(pending) && !__any(progressed)) {
+        ++rounds;
+        __builtin_amdgcn_s_sleep(1);
+        if ((rounds & 63) == 0) {
+          if (poll_load(abort_flag) != 0) return;
+          if (rounds > kSpinLimit) {
+            if (lane == 0) {
+              publish(abort_flag, 1);
+              raise_error(status, kErrTimeout);
+            }
+            return;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Counting sort of rows >= r0 by level, visiting rows in spatial order so
+// rows of one level stay roughly spatially sorted.
+__global__ void level_count_kernel(int64_t n, int64_t r0, const int* __restrict__ spatial,
+                                   const int* __restrict__ lev, int* __restrict__ cnt) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int r = spatial[k];
+  if (r >= r0) atomicAdd(&cnt[lev[r]], 1);
+}
+
+__global__ void level_scatter_kernel(int64_t n, int64_t r0, const int* __restrict__ spatial,
+                                     const int* __restrict__ lev, const int* __restrict__ start,
+                                     int* __restrict__ cursor, int* __restrict__ order) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int r = spatial[k];
+  if (r < r0) return;
+  const int l = lev[r];
+  order[start[l] + atomicAdd(&cursor[l], 1)] = r;
+}
+
+Status build_tail_orders(Model& M) {
+  const int64_t n = M.n, H = M.head_rows;
+  VL_TRY(M.tail_order_f.alloc(n - H > 0 ? n - H : 1));
+  VL_TRY(M.tail_order_b.alloc(n - H > 0 ? n - H : 1));
+  VL_TRY(M.full_order_f.alloc(n));
+  VL_TRY(M.full_order_b.alloc(n));
+  DevBuf<int> lev, cnt, start;
+  VL_TRY(lev.alloc(n));
+  VL_TRY(cnt.alloc(n + 1));
+  VL_TRY(start.alloc(n + 1));
+  VL_TRY(M.counter.reserve(2 * kSlotInts + 64));
+  const int tb = 256;
+  const unsigned gn = static_cast<unsigned>((n + tb - 1) / tb);
+  for (int dir = 0; dir < 2; ++dir) {
+    VL_TRY(fill_int(lev.p, -1, n, M.stream));
+    VL_TRY(fill_int(M.counter.p, 0, 2, M.stream));
+    const int64_t units = (n + 63) / 64;
+    unsigned g = static_cast<unsigned>(std::min<int64_t>((units + 3) / 4, 2048));
+    if (dir == 0) {
+      hipLaunchKernelGGL((levels_kernel<32, true>), dim3(g), dim3(256), 0, M.stream, n, M.m,
+                         nullptr, M.nbr.p, lev.p, M.counter.p, M.counter.p + 1, M.status);
+    } else {
+      hipLaunchKernelGGL((levels_kernel<16, false>), dim3(g), dim3(256), 0, M.stream, n, 0,
+                         M.bt_ptr.p, M.bt_col.p, lev.p, M.counter.p, M.counter.p + 1, M.status);
+    }
+    const int* spatial = static_cast<const int*>(M.grid_pts);
+    for (int full = 0; full < 2; ++full) {
+      const int64_t r0 = full ? 0 : H;
+      if (n - r0 <= 0) continue;
+      int* out = full ? (dir == 0 ? M.full_order_f.p : M.full_order_b.p)
+                      : (dir == 0 ? M.tail_order_f.p : M.tail_order_b.p);
+      VL_TRY(fill_int(cnt.p, 0, n + 1, M.stream));
+      hipLaunchKernelGGL(level_count_kernel, dim3(gn), dim3(tb), 0, M.stream, n, r0, spatial,
+                         lev.p, cnt.p);
+      VL_TRY(exclusive_scan_int(cnt.p, start.p, n + 1, M.stream));
+      VL_TRY(fill_int(cnt.p, 0, n + 1, M.stream));
+      hipLaunchKernelGGL(level_scatter_kernel, dim3(gn), dim3(tb), 0, M.stream, n, r0, spatial,
+                         lev.p, start.p, cnt.p, out);
+      VL_TRY(check_launch("level order"));
+    }
+  }
+  VL_TRY(sync_stream(M.stream));
+  return read_status(M);
 }
 
 }  // namespace vl

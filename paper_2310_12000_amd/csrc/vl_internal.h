@@ -121,6 +121,16 @@ struct Model {
   DevBuf<double> bt_val;
   DevBuf<float> bval_f, bt_val_f;  // FP32 copies for the mixed-precision form
 
+  // head rows solved in LDS (level schedules for both directions)
+  int head_rows = 0, head_nlev_f = 0, head_nlev_b = 0;
+  int64_t head_nnz_b = 0;
+  DevBuf<int> hf_ptr, hf_rows, hb_ptr, hb_rows;
+  DevBuf<int> hf_nbr, hb_pptr, hb_col, hb_src;  // position-ordered structure
+  DevBuf<double> hf_val, hb_val;                // position-ordered values
+  DevBuf<int> tail_order_f, tail_order_b;       // tail rows in level order
+  DevBuf<int> full_order_f, full_order_b;       // all rows in level order
+  DevBuf<int> head_split;                       // first tail entry of head B^T rows
+
   // neighbour-search grid
   int grid_G = 0;
   void* grid_geom = nullptr;
@@ -180,6 +190,7 @@ Status factor_rows(Model& M, const double* q_xy, int64_t nrows, const int* nbr, 
 // ---- sparse kernels (sparse.hip)
 Status build_transpose(Model& M);
 Status refresh_transpose_values(Model& M);
+Status build_tail_orders(Model& M);
 
 // Y = rowscale o (X + B_off X)                              (spmm_b)
 // Y = diag o diagvec + X + B_off^T X                         (spmm_bt)
@@ -191,6 +202,13 @@ Status trsm_b(Model& M, const double* X, double* Y, int t, const double* rowscal
               bool prefilled);
 Status trsm_bt(Model& M, const double* X, double* Y, int t, bool prefilled);
 int spmm_nblocks(int64_t n, int t);
+
+// ---- head solves (head.hip)
+constexpr int kHeadRows = 16384;
+Status build_head_schedule(Model& M);
+Status head_lower(Model& M, const double* X, double* Y, int t, const double* rs);
+Status head_upper(Model& M, const double* X, double* Y, int t);
+Status refresh_head_values(Model& M);
 
 // ---- solver kernels (solver.hip)
 Status tridiag_quadrature(Model& M, CgState& S, double* out_dev);

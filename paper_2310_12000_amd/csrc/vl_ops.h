@@ -37,6 +37,29 @@ __host__ __device__ __forceinline__ int64_t units_of_hd(int64_t n, int t, Lanes 
   return rg * L.slices;
 }
 
+// Blocks are dispatched round-robin over the 8 XCDs of the chip; remap so
+// that each XCD works on one contiguous range of units (spatially ordered
+// rows), keeping neighbour gathers inside that XCD's L2.
+__host__ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  // XCD x = b mod 8 holds blocks x, x + 8, ...: count q + (x < rem); it gets
+  // the contiguous range starting at x q + min(x, rem).  A bijection of [0, nb).
+  const int64_t q = nb >> 3, rem = nb & 7;
+  const int64_t x = b & 7, local = b >> 3;
+  return x * q + (x < rem ? x : rem) + local;
+}
+
+// Work counters of the sync-free solves: one slot per concurrently prepared
+// solve, each with kCounterStreams counters 64 bytes apart and an abort flag.
+constexpr int kCounterStreams = 64;
+constexpr int kCounterStride = 16;
+constexpr int kSlotInts = kCounterStreams * kCounterStride + 16;
+constexpr int kAbortOffset = kCounterStreams * kCounterStride;
+
+// Zero the counters and abort flags of both slots (one block calls it).
+__device__ __forceinline__ void reset_counters(int* counter) {
+  for (int k = threadIdx.x; k < 2 * kSlotInts; k += blockDim.x) counter[k] = 0;
+}
+
 // Deterministic chunked grid: gridDim = (nchunk, slices), 256 threads; block
 // (k, s) covers rows [k * rpc, (k + 1) * rpc) and columns of slice s.
 struct ChunkGrid {

@@ -168,3 +168,29 @@ def test_predict(c1, c1_fit):
     assert abs(np.array(info["cg_iters"]) - np.array(f["pred_iters"])).max() == 0
     assert rel_err(f["mean"], mean) < TOL
     assert rel_err(f["var"], var) < TOL
+
+
+@pytest.mark.parametrize("t", [1, 8, 50, 65])
+def test_trsm_head_and_tail(P, t):
+    # n above the head size: rows solved in LDS level by level, the rest by
+    # the sync-free tail kernels.  The reference solves with the device's own
+    # B entries, so the check isolates the solve from the (ill-conditioned)
+    # neighbour Cholesky.
+    n, m = 40000, 20
+    say(f"case: trsm head+tail n={n} t={t}")
+    X = synth.locations(n, seed=11)
+    g = P.VecchiaLaplace(dev(X), m, OV.COV_MATERN32, (1.0, 0.05))
+    nbr = host(g.export("nbr")).reshape(n, m).astype(np.int64)
+    bval = host(g.export("bval")).reshape(n, m)
+    assert np.array_equal(nbr, OV.neighbours(X, m))
+    B = OV.sparse_B(-bval, nbr)
+    from scipy.sparse.linalg import spsolve_triangular
+    R = np.random.default_rng(t).standard_normal((n, t))
+    Rd = dev(R)
+    Y = torch.empty_like(Rd)
+    for tr in (False, True):
+        P.vl_trsm(g.h, Rd, Y, transpose=tr)
+        ref = (spsolve_triangular(B.T.tocsr(), R, lower=False, unit_diagonal=True) if tr
+               else spsolve_triangular(B, R, lower=True, unit_diagonal=True))
+        assert rel_err(host(Y), ref) < 1e-11, (tr, rel_err(host(Y), ref))
+    g.close()

@@ -20,6 +20,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Laplace marginal-likelihood evals/s at n=1e5,m=20; B-SpMM HBM GB/s; p99 latency"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+KINDS = ("spmm_b", "spmm_bt", "trsm_lower", "trsm_upper", "head_lower", "head_upper")
+KERNEL_NAMES = {"spmm_b": "spmm_ell_kernel", "spmm_bt": "spmm_csr_t_kernel",
+                "trsm_lower": "trsm_kernel<lower>", "trsm_upper": "trsm_kernel<upper>",
+                "head_lower": "head_lower_kernel", "head_upper": "head_upper_kernel"}
 
 
 def parse():
@@ -60,9 +65,13 @@ def main():
     theta = (w["sigma2"], w["rho"])
     torch.cuda.synchronize()
 
-    def step(rec):
+    ktime = {k: [0.0, 0, 0.0] for k in KINDS}
+
+    def step(rec, timed=False):
         t0 = time.perf_counter()
         g = P.VecchiaLaplace(coords, w["m"], w["kind"], theta, want_deriv=True)
+        if timed:
+            P.vl_timing_enable(g.h, True)
         t1 = time.perf_counter()
         mode, st = g.find_mode(y, F, w["lik"], None, opts)
         t2 = time.perf_counter()
@@ -75,6 +84,12 @@ def main():
                     "newton_iters": st.newton_iters, "newton_cg_total": st.cg_iters_total,
                     "slq_cg_max": nst.cg_iters_max, "pred_cg_max": pst.cg_iters_max,
                     "nll": nll, "grad": grad})
+        if timed:
+            for k in KINDS:
+                ms, cnt, by = P.vl_timing_read(g.h, k)
+                ktime[k][0] += ms
+                ktime[k][1] += cnt
+                ktime[k][2] += by
         g.close()
 
     warm = []
@@ -85,7 +100,7 @@ def main():
     rec = []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(rec)
+        step(rec, timed=True)
         log(args, f"step {k}: {rec[-1]}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -108,7 +123,72 @@ def main():
                                                "pred_cg_max")},
         "nll": rec[-1]["nll"],
     }
+    # dominant kernel class by time; achieved = algorithmic bytes / kernel time
+    dom = max(KINDS, key=lambda k: ktime[k][0])
+    ms_d, cnt_d, by_d = ktime[dom]
+    ach = by_d / (ms_d * 1e-3) / 1e9 if ms_d > 0 else 0.0
+    out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                       "kernel": KERNEL_NAMES[dom], "launches": cnt_d,
+                       "avg_launch_us": 1e3 * ms_d / max(cnt_d, 1),
+                       "alg_bytes_per_launch": by_d / max(cnt_d, 1)}
+    out["kernel_time_ms"] = {k: ktime[k][0] / args.steps for k in KINDS}
+    ms_b, cnt_b, by_b = ktime["spmm_b"]
+    out["b_spmm"] = {"achieved_GBps": by_b / (ms_b * 1e-3) / 1e9 if ms_b > 0 else 0.0,
+                     "frac": (by_b / (ms_b * 1e-3) / 1e9) / HBM_PEAK_GBS if ms_b > 0 else 0.0,
+                     "launches": cnt_b, "avg_launch_us": 1e3 * ms_b / max(cnt_b, 1)}
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(w, rec[-1], args)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, it, args):
+    """The FP64 oracle on a bounded sample of the same workload.
+
+    Timed whole: neighbour search + Vecchia factor with derivatives at the full
+    n, and neighbour search + factor of the prediction locations.  Timed on a
+    sample: preconditioned CG iterations on the same operator, 10 iterations
+    with one column and 5 iterations with 4 columns; per-iteration costs are
+    scaled by the device run's iteration counts and column counts of one
+    evaluation (Newton solves, the gradient's extra solve, SLQ with t probes,
+    prediction with s samples)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import laplace as OL
+    from oracle import vecchia as OV
+
+    n = w["n"]
+    t0 = time.perf_counter()
+    model = OL.Model(w["coords"], w["m"], w["kind"], (w["sigma2"], w["rho"]), deriv=True)
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    nbr_p = OV.pred_neighbours(w["coords"], w["coords_pred"], w["m"])
+    OV.factor(w["coords"], nbr_p, w["kind"], (w["sigma2"], w["rho"]),
+              coords_self=w["coords_pred"])
+    t_pred_factor = time.perf_counter() - t0
+    W = OL.lik_W(w["lik"], w["y"], w["F"], None)
+    apply_A, apply_Pinv = OL.vadu_ops(model, W)
+    g = np.random.default_rng(0)
+    t0 = time.perf_counter()
+    OL.pcg(apply_A, apply_Pinv, g.standard_normal((n, 1)), 0.0, 10, forced_iters=[10])
+    t_it1 = (time.perf_counter() - t0) / 10
+    t0 = time.perf_counter()
+    OL.pcg(apply_A, apply_Pinv, g.standard_normal((n, 4)), 0.0, 5, forced_iters=[5] * 4)
+    t_col = (time.perf_counter() - t0) / 5 / 4
+    newton_cg = it["newton_cg_total"]
+    grad_cg = newton_cg / max(it["newton_iters"], 1)
+    t_eval = (t_build + t_pred_factor + (newton_cg + grad_cg) * t_it1 +
+              it["slq_cg_max"] * w["t"] * t_col + it["pred_cg_max"] * w["s"] * t_col)
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    return {"value": 1.0 / t_eval, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle on the same n={n} workload: kNN + factor timed whole "
+                       f"({t_build:.1f} s) and prediction factor ({t_pred_factor:.1f} s); PCG "
+                       f"timed on 10 iterations x 1 column ({t_it1 * 1e3:.1f} ms/it) and 5 "
+                       f"iterations x 4 columns ({t_col * 1e3:.1f} ms/it/column), scaled by the "
+                       f"device run's counts (Newton CG {newton_cg}, gradient CG ~{grad_cg:.0f}, "
+                       f"SLQ {it['slq_cg_max']} x {w['t']} columns, prediction "
+                       f"{it['pred_cg_max']} x {w['s']} columns)"),
+            "est_eval_s": t_eval, "host_cpus": os.cpu_count()}
 
 
 if __name__ == "__main__":

@@ -177,7 +177,8 @@ vl_status vl_predict(vl_model* h, const double* coords_p, int64_t n_p,
  *     double t
  *  12 r0^T z0 weights of the last vl_neg_log_marglik, double t
  *  13 prediction neighbours of the last vl_predict, int32 n_p x m
- *  14 prediction A_p (entries +A_p), double n_p x m;  15 D_p, double n_p
+ *  14 prediction factor entries -A_p (the off-diagonal of B_po), double
+ *     n_p x m;  15 D_p, double n_p
  * dst is a device pointer; `bytes` must equal the size of the array.
  * Synchronises. */
 vl_status vl_export(vl_model* h, int which, void* dst, size_t bytes);
@@ -194,6 +195,21 @@ vl_status vl_spmm(vl_model* h, int transpose, const double* X, double* Y, int t)
  * row-major n x t):  B Y = X (transpose = 0) or B^T Y = X (transpose = 1).
  * X and Y must not overlap.  Asynchronous. */
 vl_status vl_trsm(vl_model* h, int transpose, const double* X, double* Y, int t);
+
+/* Measurement support: while enabled, every launch of the sparse kernel
+ * classes below is bracketed by HIP events on the model's stream, and the
+ * algorithmic bytes of the launch (8-byte values and 4-byte indices of the
+ * nonzeros it touches, each operand column block read once, the result
+ * written once, per-row vectors) are accumulated.  `kind`:
+ *   0  Y = B X (B in ELL)                 1  Y = B^T X (B^T in CSR)
+ *   2  sync-free rows of B Y = X          3  sync-free rows of B^T Y = X
+ *   4  LDS head rows of B Y = X           5  LDS head rows of B^T Y = X
+ * vl_timing_enable resets the records (and synchronises); vl_timing_read
+ * synchronises and returns the summed kernel time (ms), the number of
+ * launches and the summed algorithmic bytes of the records so far. */
+vl_status vl_timing_enable(vl_model* h, int enable);
+vl_status vl_timing_read(vl_model* h, int kind, double* total_ms, int64_t* launches,
+                         double* bytes);
 
 /* Release the handle and all its device memory. */
 void vl_free(vl_model* h);

@@ -73,6 +73,7 @@ static Status build(const double* coords, int64_t n, int m, int cov, const doubl
   if (!M) return Status::make(VL_ERR_OOM, "host allocation failed");
   Status st = [&]() -> Status {
     VL_HIP(hipGetDevice(&M->device));
+    VL_HIP(hipDeviceGetAttribute(&M->num_cus, hipDeviceAttributeMultiprocessorCount, M->device));
     M->stream = static_cast<hipStream_t>(stream);
     M->n = n;
     M->m = m;
@@ -106,6 +107,7 @@ static Status build(const double* coords, int64_t n, int m, int cov, const doubl
 static void release(Model* M) {
   if (!M) return;
   (void)hipStreamSynchronize(M->stream);
+  for (hipEvent_t e : M->timing.pool) (void)hipEventDestroy(e);
   for (void* p : M->owned) device_free(p);
   if (M->host_pin) (void)hipHostFree(M->host_pin);
   delete static_cast<vl_model*>(M);
@@ -372,6 +374,40 @@ vl_status vl_trsm(vl_model* h, int transpose, const double* X, double* Y, int t)
     }
     VL_TRY(vl::sync_stream(h->stream));
     return vl::read_status(*h);
+  });
+}
+
+vl_status vl_timing_enable(vl_model* h, int enable) {
+  return vl::guarded([&]() -> vl::Status {
+    if (!h) return vl::Status::invalid("null handle");
+    VL_TRY(vl::sync_stream(h->stream));
+    h->timing.on = enable != 0;
+    h->timing.used = 0;
+    h->timing.recs.clear();
+    return vl::Status::ok();
+  });
+}
+
+vl_status vl_timing_read(vl_model* h, int kind, double* total_ms, int64_t* launches,
+                         double* bytes) {
+  return vl::guarded([&]() -> vl::Status {
+    if (!h || !total_ms || !launches || !bytes) return vl::Status::invalid("null argument");
+    if (kind < 0 || kind >= vl::kTimeKinds) return vl::Status::invalid("unknown kind");
+    VL_TRY(vl::sync_stream(h->stream));
+    double ms = 0.0, by = 0.0;
+    int64_t cnt = 0;
+    for (const auto& r : h->timing.recs) {
+      if (r.kind != kind) continue;
+      float e = 0.0f;
+      VL_HIP(hipEventElapsedTime(&e, h->timing.pool[r.ev], h->timing.pool[r.ev + 1]));
+      ms += e;
+      by += r.bytes;
+      ++cnt;
+    }
+    *total_ms = ms;
+    *launches = cnt;
+    *bytes = by;
+    return vl::Status::ok();
   });
 }
 

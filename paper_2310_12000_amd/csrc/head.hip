@@ -306,6 +306,8 @@ __global__ void head_upper_pre_kernel(int H, int t, const int* __restrict__ spli
 Status head_lower(Model& M, const double* X, double* Y, int t, const double* rs) {
   const int H = M.head_rows;
   if (H == 0) return Status::ok();
+  TimedLaunch tl(M, kTimeHeadLower,
+                 12.0 * M.nnz_head_f + 16.0 * H * t + (rs ? 8.0 * H : 0.0));
   const size_t lds = sizeof(double) * H;
   // two row windows (current and prefetched) stay in registers: 512 threads
   // above 8 slots
@@ -332,6 +334,7 @@ Status head_upper(Model& M, const double* X, double* Y, int t) {
   hipLaunchKernelGGL(head_upper_pre_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0,
                      M.stream, H, t, M.head_split.p, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, Y);
   const size_t lds = sizeof(double) * H;
+  TimedLaunch tl(M, kTimeHeadUpper, 12.0 * M.head_nnz_b + 4.0 * H + 16.0 * H * t);
   hipLaunchKernelGGL(head_upper_kernel<512>, dim3(t), dim3(512), lds, M.stream, H, t,
                      M.hb_rows.p, M.hb_pptr.p, M.hb_col.p, M.hb_val.p, Y);
   return check_launch("head upper");
@@ -465,6 +468,16 @@ Status build_head_schedule(Model& M) {
   VL_HIP(hipMemcpyAsync(&nnzb, M.hb_pptr.p + H, sizeof(int), hipMemcpyDeviceToHost, M.stream));
   VL_TRY(sync_stream(M.stream));
   M.head_nnz_b = nnzb;
+  {
+    int bt_head = 0;
+    VL_HIP(hipMemcpyAsync(&bt_head, M.bt_ptr.p + H, sizeof(int), hipMemcpyDeviceToHost,
+                          M.stream));
+    VL_TRY(sync_stream(M.stream));
+    M.nnz_head_bt = bt_head;
+    int64_t f = 0;  // row i < H has min(i, m) neighbours
+    for (int64_t i = 0; i < H; ++i) f += (i < m ? i : m);
+    M.nnz_head_f = f;
+  }
   VL_TRY(M.hb_col.alloc(nnzb));
   VL_TRY(M.hb_src.alloc(nnzb));
   VL_TRY(M.hb_val.alloc(nnzb));

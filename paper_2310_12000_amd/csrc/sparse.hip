@@ -237,8 +237,15 @@ static const int* spatial_order(Model& M) { return static_cast<const int*>(M.gri
 #define VL_ELL_LAUNCH(W, ...)                                                                   \
   hipLaunchKernelGGL((spmm_ell_kernel<W, InMem>), dim3(nb), dim3(256), 0, M.stream, __VA_ARGS__)
 
+// Algorithmic bytes of one product: nonzeros (8-byte value + 4-byte index),
+// the operand read once, the result written once, plus per-row vectors.
+static double spmm_bytes(const Model& M, int t, bool rowscale) {
+  return 12.0 * M.nnz + 16.0 * M.n * t + (rowscale ? 8.0 * M.n : 0.0);
+}
+
 static Status launch_ell(Model& M, const double* vals, const double* X, double* Y, int t,
                          const double* rowscale, int unit_diag) {
+  TimedLaunch tl(M, kTimeSpmmB, spmm_bytes(M, t, rowscale != nullptr));
   Lanes L = Lanes::of(t);
   int nb = spmm_nblocks(M.n, t);
   const int* ord = spatial_order(M);
@@ -263,6 +270,9 @@ Status spmm_ell_vals(Model& M, const double* vals, const double* X, double* Y, i
 
 Status spmm_bt(Model& M, const double* X, double* Y, int t, const double* diag,
                const double* diagvec) {
+  TimedLaunch tl(M, kTimeSpmmBt,
+                 spmm_bytes(M, t, false) + 4.0 * (M.n + 1) +
+                     (diag ? 8.0 * M.n + 8.0 * M.n * t : 0.0));
   Lanes L = Lanes::of(t);
   int nb = spmm_nblocks(M.n, t);
   const int* ord = spatial_order(M);
@@ -454,8 +464,10 @@ static int trsm_grid(int64_t total_units) {
   return static_cast<int>(blocks);
 }
 
-static int trsm_streams(int blocks) {
-  return blocks < kCounterStreams ? blocks : kCounterStreams;
+static int trsm_streams(const Model& M, int blocks) {
+  int s = blocks < kCounterStreams ? blocks : kCounterStreams;
+  if (s > M.num_cus) s = M.num_cus;
+  return s < 1 ? 1 : s;
 }
 
 // Counter slots: slot k uses counter[k * kSlotInts ...] (streams and abort
@@ -484,8 +496,11 @@ Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* ro
   if (H >= M.n) return Status::ok();
   Lanes L = Lanes::of(t);
   int g = trsm_grid(units_of(M.n - H, t));
-  const int ns = trsm_streams(g);
+  const int ns = trsm_streams(M, g);
   int* cnt = M.counter.p + slot * kSlotInts;
+  TimedLaunch tl(M, kTimeTrsmLower,
+                 12.0 * (M.nnz - (H ? M.nnz_head_f : 0)) + 16.0 * (M.n - H) * t +
+                     (rowscale ? 8.0 * (M.n - H) : 0.0));
   if (M.m <= 8) {
     hipLaunchKernelGGL((trsm_kernel<8, true, InMem>), dim3(g), dim3(256), 0, M.stream, M.n, H,
                        M.m, t, L, H ? M.tail_order_f.p : M.full_order_f.p, nullptr, M.nbr.p,
@@ -514,8 +529,11 @@ Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled,
   if (H < M.n) {
     Lanes L = Lanes::of(t);
     int g = trsm_grid(units_of(M.n - H, t));
-    const int ns = trsm_streams(g);
+    const int ns = trsm_streams(M, g);
     int* cnt = M.counter.p + slot * kSlotInts;
+    TimedLaunch tl(M, kTimeTrsmUpper,
+                   12.0 * (M.nnz - (H ? M.nnz_head_bt : 0)) + 4.0 * (M.n - H) +
+                       16.0 * (M.n - H) * t);
     hipLaunchKernelGGL((trsm_kernel<16, false, InMem>), dim3(g), dim3(256), 0, M.stream, M.n, H,
                        0, t, L, H ? M.tail_order_b.p : M.full_order_b.p, M.bt_ptr.p,
                        M.bt_col.p, M.bt_val.p,

@@ -122,6 +122,27 @@ Status exclusive_scan_int(const int* in, int* out, int64_t count, hipStream_t s)
   return sync_stream(s);  // `sums` is released on return
 }
 
+TimedLaunch::TimedLaunch(Model& M, int kind, double bytes) : M_(M), on_(M.timing.on), ev_(0) {
+  if (!on_) return;
+  Timing& T = M.timing;
+  while (T.pool.size() < T.used + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) {
+      on_ = false;
+      return;
+    }
+    T.pool.push_back(e);
+  }
+  ev_ = T.used;
+  T.used += 2;
+  T.recs.push_back({kind, ev_, bytes});
+  (void)hipEventRecord(T.pool[ev_], M.stream);
+}
+
+TimedLaunch::~TimedLaunch() {
+  if (on_) (void)hipEventRecord(M_.timing.pool[ev_ + 1], M_.stream);
+}
+
 Status read_status(Model& M) {
   int st = 0;
   VL_HIP(hipMemcpyAsync(&st, M.status, sizeof(int), hipMemcpyDeviceToHost, M.stream));

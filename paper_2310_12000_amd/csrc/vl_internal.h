@@ -98,8 +98,32 @@ struct CgState {
   std::vector<int> host_iters;
 };
 
+// Optional event timing of kernel classes (measurement only).
+enum TimedKind : int {
+  kTimeSpmmB = 0,     // Y = B X (ELL)
+  kTimeSpmmBt = 1,    // Y = B^T X (CSR)
+  kTimeTrsmLower = 2, // sync-free rows of B Y = X
+  kTimeTrsmUpper = 3, // sync-free rows of B^T Y = X
+  kTimeHeadLower = 4, // LDS head rows of B Y = X
+  kTimeHeadUpper = 5, // LDS head rows of B^T Y = X
+  kTimeKinds = 6
+};
+
+struct Timing {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec {
+    int kind;
+    size_t ev;
+    double bytes;
+  };
+  std::vector<Rec> recs;
+};
+
 struct Model {
   int device = 0;
+  int num_cus = 1;
   hipStream_t stream = nullptr;
   int64_t n = 0;
   int m = 0;
@@ -169,6 +193,20 @@ struct Model {
   DevBuf<double> rhs_blk;  // n x t right-hand sides of block solves
   DevBuf<int> counter;     // dynamic work counters of sync-free kernels
   double* host_pin = nullptr;  // pinned host scalars (64 doubles)
+  Timing timing;
+  int64_t nnz_head_f = 0, nnz_head_bt = 0;  // nonzeros in head rows of B / B^T
+};
+
+// Brackets one kernel launch with events when timing is enabled.
+class TimedLaunch {
+ public:
+  TimedLaunch(Model& M, int kind, double bytes);
+  ~TimedLaunch();
+
+ private:
+  Model& M_;
+  bool on_;
+  size_t ev_;
 };
 
 // ---- utilities (util.hip)

@@ -50,7 +50,11 @@ __host__ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
 
 // Work counters of the sync-free solves: one slot per concurrently prepared
 // solve, each with kCounterStreams counters 64 bytes apart and an abort flag.
-constexpr int kCounterStreams = 64;
+// Stream s is served by blocks s, s + S, ...; progress needs every stream to
+// have a resident wave, so S must not exceed the number of blocks that are
+// resident at once.  One 256-thread block of these kernels always fits on a
+// CU, so S <= number of CUs (256 on MI355X) is safe.
+constexpr int kCounterStreams = 256;
 constexpr int kCounterStride = 16;
 constexpr int kSlotInts = kCounterStreams * kCounterStride + 16;
 constexpr int kAbortOffset = kCounterStreams * kCounterStride;

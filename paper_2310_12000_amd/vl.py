@@ -109,10 +109,13 @@ def lib():
     L.vl_export_count.restype = I64
     L.vl_spmm.argtypes = [P, I, P, P, I]
     L.vl_trsm.argtypes = [P, I, P, P, I]
+    L.vl_timing_enable.argtypes = [P, I]
+    L.vl_timing_read.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(I64), ctypes.POINTER(D)]
     L.vl_free.argtypes = [P]
     L.vl_free.restype = None
     for f in ("vl_build_vecchia", "vl_set_theta", "vl_find_mode", "vl_neg_log_marglik",
-              "vl_predict", "vl_export", "vl_spmm", "vl_trsm"):
+              "vl_predict", "vl_export", "vl_spmm", "vl_trsm", "vl_timing_enable",
+              "vl_timing_read"):
         getattr(L, f).restype = I
     _lib = L
     return L
@@ -219,6 +222,22 @@ def vl_trsm(h, X, Y, transpose=False):
     _ptr(X), _ptr(Y)
     _check(lib().vl_trsm(h, 1 if transpose else 0, ctypes.c_void_p(X.data_ptr()),
                          ctypes.c_void_p(Y.data_ptr()), t))
+
+
+TIMED_KINDS = {"spmm_b": 0, "spmm_bt": 1, "trsm_lower": 2, "trsm_upper": 3,
+               "head_lower": 4, "head_upper": 5}
+
+
+def vl_timing_enable(h, enable=True):
+    _check(lib().vl_timing_enable(h, 1 if enable else 0))
+
+
+def vl_timing_read(h, kind):
+    """(total kernel ms, launches, algorithmic bytes) of one kernel class."""
+    ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _check(lib().vl_timing_read(h, TIMED_KINDS[kind], ctypes.byref(ms), ctypes.byref(n),
+                                ctypes.byref(by)))
+    return ms.value, n.value, by.value
 
 
 def vl_free(h):

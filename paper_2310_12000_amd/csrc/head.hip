@@ -15,6 +15,7 @@
 // Level schedules (rows of the head grouped by level, separately for the two
 // directions) depend only on the neighbour sets and are built once.
 #include <algorithm>
+#include <cstdlib>
 
 #include "vl_internal.h"
 #include "vl_ops.h"
@@ -115,10 +116,14 @@ __global__ __launch_bounds__(kHeadThreads) void head_sort_kernel(int H,
 // batches of 64; wave w takes batches w, w + NT/64, ... and each lane one row
 // of the batch.  A position only depends on smaller positions, so the
 // smallest unfinished batch can always proceed and no barrier is needed: a
-// row polls LDS until each needed value differs from the sentinel.  Row data
-// is stored in position order (one coalesced load per batch), and the next
-// batch is fetched when the current one starts, so global-memory waits occur
-// only at batch boundaries.
+// row polls LDS until each needed value differs from the sentinel.
+//
+// Global loads never sit on the critical path: the data of a batch is
+// fetched two batches ahead in two stages, first what depends only on the
+// position (row id, row length, position-ordered entries), one batch later
+// what depends on the row id (the right-hand side).  Results leave LDS only
+// at the end; a global store inside the polling loop would make every later
+// round wait for it.
 template <int W, int NT>
 __global__ __launch_bounds__(NT) void head_lower_kernel(
     int H, int m, int t, const int* __restrict__ prow, const int* __restrict__ pnbr,
@@ -131,24 +136,28 @@ __global__ __launch_bounds__(NT) void head_lower_kernel(
   constexpr int kWaves = NT / 64;
   for (int i = tid; i < H; i += NT) s_y[i] = sentinel();
   __syncthreads();
-  int ni = -1, nj[W];
+  int a_row = -1;            // stage A: row id, two batches ahead
+  int ni = -1, nj[W];        // stage B: one batch ahead
   double nv[W], nx = 0.0;
-  auto fetch = [&](int p) {
-    ni = (p < H) ? prow[p] : -1;
+  auto stage_a = [&](int p) { a_row = (p < H) ? prow[p] : -1; };
+  auto stage_b = [&](int p, int row) {
+    ni = row;
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-      const bool in = (ni >= 0) && (k < m);
+      const bool in = (row >= 0) && (k < m);
       nj[k] = in ? pnbr[(int64_t)p * m + k] : -1;
       nv[k] = in ? pval[(int64_t)p * m + k] : 0.0;
     }
     nx = 0.0;
-    if (ni >= 0) {
-      nx = X[(int64_t)ni * t + c];
-      if (rs) nx *= rs[ni];
+    if (row >= 0) {
+      nx = X[(int64_t)row * t + c];
+      if (rs) nx *= rs[row];
     }
   };
   int batch = tid >> 6;
-  fetch(batch * 64 + lane);
+  stage_a(batch * 64 + lane);
+  stage_b(batch * 64 + lane, a_row);
+  stage_a((batch + kWaves) * 64 + lane);
   while (batch * 64 < H) {
     const int ci = ni;
     int cj[W];
@@ -159,7 +168,9 @@ __global__ __launch_bounds__(NT) void head_lower_kernel(
       cv[k] = nv[k];
     }
     double acc = nx;
-    fetch((batch + kWaves) * 64 + lane);
+    const int row1 = a_row;
+    stage_b((batch + kWaves) * 64 + lane, row1);
+    stage_a((batch + 2 * kWaves) * 64 + lane);
     bool pending = ci >= 0;
     int kk = 0;
     while (__any(pending)) {
@@ -169,122 +180,189 @@ __global__ __launch_bounds__(NT) void head_lower_kernel(
 #pragma unroll
         for (int k = 0; k < W; ++k)
           yv[k] = (k >= kk && cj[k] >= 0) ? lds_poll(&s_y[cj[k]]) : 0.0;
-        bool stop = false;
-        int adv = 0;
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-          if (!stop && k >= kk) {
-            if (cj[k] < 0) {
-              kk = W;
-              stop = true;
-            } else if (is_sentinel(yv[k])) {
-              stop = true;
-            } else {
-              acc -= cv[k] * yv[k];
-              ++adv;
-            }
-          }
-        }
-        if (kk < W) kk += adv;
+        kk = consume_ready<W>(cj, cv, yv, kk, acc);
         if (kk >= W) {
           lds_publish(&s_y[ci], acc);
-          Y[(int64_t)ci * t + c] = acc;
           pending = false;
         }
       }
     }
     batch += kWaves;
   }
+  __syncthreads();
+  for (int i = tid; i < H; i += NT) Y[(int64_t)i * t + c] = s_y[i];
 }
 
 // Upper: the right-hand side of head row j arrives in Y already reduced by its
-// tail dependents (head_upper_pre); the kernel subtracts the head-internal
-// entries of the B^T row of j, stored in position order (pptr/pcol/pval), in
-// windows of 16 (the first window is fetched with the batch).
+// tail dependents (head_upper_pre).  The head rows are cut into index ranges
+// [H/4, H), [H/16, H/4), ... (the earliest points of the ordering are
+// neighbours of very many later points, so their B^T rows are long); the
+// ranges are solved one after another, latest first.  For a range, each B^T
+// row first subtracts its entries that point into ranges already solved
+// (all final: a fully parallel phase over the range's rows), then the rows
+// are solved in level order polling LDS, over the entries inside the range,
+// which are few.  Entries are stored per position in descending child
+// index, so the entries into solved ranges are a prefix ([pptr, split)) and
+// the in-range ones follow ([split, pptr + 1)), their first kWin also in the
+// padded wcol/wval.  In-range rows with at most 2 kWin entries are solved by
+// one lane in windows of kWin; longer ones (only in the first range) by the
+// whole wave in passes of 64 kCoop entries, combined by a fixed butterfly.
+struct HeadRanges {
+  int n;
+  int start[10];  // positions [start[k], start[k + 1]) hold range k
+};
+
 template <int NT>
 __global__ __launch_bounds__(NT) void head_upper_kernel(
-    int H, int t, const int* __restrict__ prow, const int* __restrict__ pptr,
-    const int* __restrict__ pcol, const double* __restrict__ pval, double* Y) {
+    int H, int t, HeadRanges R, const int* __restrict__ prow, const int* __restrict__ pptr,
+    const int* __restrict__ psplit, const int* __restrict__ pcol,
+    const double* __restrict__ pval, const int* __restrict__ wcol,
+    const double* __restrict__ wval, double* Y) {
   extern __shared__ double s_y[];
   const int c = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   constexpr int kWaves = NT / 64;
   constexpr int kWin = 16;
+  constexpr int kCoop = 4;
+  constexpr int kPass = 64 * kCoop;
   for (int i = tid; i < H; i += NT) s_y[i] = sentinel();
   __syncthreads();
-  int nrow = -1, nq = 0, ne = 0, ncb[kWin];
-  double nvb[kWin], nacc = 0.0;
-  auto fetch = [&](int p) {
-    nrow = (p < H) ? prow[p] : -1;
-    nq = (nrow >= 0) ? pptr[p] : 0;
-    ne = (nrow >= 0) ? pptr[p + 1] : 0;
+  for (int r = 0; r < R.n; ++r) {
+    const int p0 = R.start[r], p1 = R.start[r + 1];
+    // entries into solved ranges: all final, fully parallel
+    if (r > 0) {
+      for (int p = p0 + tid; p < p1; p += NT) {
+        const int j = prow[p];
+        double acc = Y[(int64_t)j * t + c];
+        const int e = psplit[p];
+        for (int q = pptr[p]; q < e; q += 8) {
+          int cb[8];
+          double vb[8], yv[8];
 #pragma unroll
-    for (int k = 0; k < kWin; ++k) {
-      const bool in = nq + k < ne;
-      ncb[k] = in ? pcol[nq + k] : -1;
-      nvb[k] = in ? pval[nq + k] : 0.0;
+          for (int k = 0; k < 8; ++k) {
+            cb[k] = (q + k < e) ? pcol[q + k] : -1;
+            vb[k] = (q + k < e) ? pval[q + k] : 0.0;
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) yv[k] = cb[k] >= 0 ? s_y[cb[k]] : 0.0;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) acc -= vb[k] * yv[k];
+        }
+        Y[(int64_t)j * t + c] = acc;
+      }
+      __syncthreads();  // the folded right-hand sides are visible to the block
     }
-    nacc = (nrow >= 0) ? Y[(int64_t)nrow * t + c] : 0.0;
-  };
-  int batch = tid >> 6;
-  fetch(batch * 64 + lane);
-  while (batch * 64 < H) {
-    const int j = nrow;
-    int q = nq;
-    const int e = ne;
+    int a_row = -1, a_q = 0, a_e = 0;          // stage A: two batches ahead
+    int nrow = -1, nq = 0, ne = 0, ncb[kWin];   // stage B: one batch ahead
+    double nvb[kWin], nacc = 0.0;
+    auto stage_a = [&](int p) {
+      const bool in = p < p1;
+      a_row = in ? prow[p] : -1;
+      a_q = in ? psplit[p] : 0;
+      a_e = in ? pptr[p + 1] : 0;
+    };
+    auto stage_b = [&](int p) {
+      const bool in = p < p1;
+      nrow = a_row;
+      nq = a_q;
+      ne = a_e;
+#pragma unroll
+      for (int k = 0; k < kWin; ++k) {
+        ncb[k] = in ? wcol[(int64_t)p * kWin + k] : -1;
+        nvb[k] = in ? wval[(int64_t)p * kWin + k] : 0.0;
+      }
+      nacc = (nrow >= 0) ? Y[(int64_t)nrow * t + c] : 0.0;
+    };
+    int batch = tid >> 6;
+    stage_a(p0 + batch * 64 + lane);
+    stage_b(p0 + batch * 64 + lane);
+    stage_a(p0 + (batch + kWaves) * 64 + lane);
     int cb[kWin];
     double vb[kWin];
+    while (p0 + batch * 64 < p1) {
+      const int j = nrow;
+      int q = nq;
+      const int e = ne;
 #pragma unroll
-    for (int k = 0; k < kWin; ++k) {
-      cb[k] = ncb[k];
-      vb[k] = nvb[k];
-    }
-    double acc = nacc;
-    fetch((batch + kWaves) * 64 + lane);
-    bool pending = j >= 0;
-    int kk = 0;
-    while (__any(pending)) {
-      if (pending) {
-        if (kk == kWin) {  // next window of a long row
+      for (int k = 0; k < kWin; ++k) {
+        cb[k] = ncb[k];
+        vb[k] = nvb[k];
+      }
+      double acc = nacc;
+      stage_b(p0 + (batch + kWaves) * 64 + lane);
+      stage_a(p0 + (batch + 2 * kWaves) * 64 + lane);
+      const bool is_long = j >= 0 && e - q > 2 * kWin;
+      bool pending = j >= 0 && !is_long;
+      uint64_t long_mask = __ballot(is_long);
+      int kk = 0;
+      while (__any(pending) || long_mask) {
+        if (pending) {
+          if (kk == kWin) {  // second window of a row
 #pragma unroll
-          for (int k = 0; k < kWin; ++k) {
-            const bool in = q + k < e;
-            cb[k] = in ? pcol[q + k] : -1;
-            vb[k] = in ? pval[q + k] : 0.0;
+            for (int k = 0; k < kWin; ++k) {
+              const bool in = q + k < e;
+              cb[k] = in ? pcol[q + k] : -1;
+              vb[k] = in ? pval[q + k] : 0.0;
+            }
+            kk = 0;
           }
-          kk = 0;
-        }
-        double lv[kWin];
+          double lv[kWin];
 #pragma unroll
-        for (int k = 0; k < kWin; ++k) lv[k] = (k >= kk && cb[k] >= 0) ? lds_poll(&s_y[cb[k]]) : 0.0;
-        bool stop = false;
-        int adv = 0;
-#pragma unroll
-        for (int k = 0; k < kWin; ++k) {
-          if (!stop && k >= kk) {
-            if (cb[k] < 0) {
-              stop = true;
-            } else if (is_sentinel(lv[k])) {
-              stop = true;
+          for (int k = 0; k < kWin; ++k)
+            lv[k] = (k >= kk && cb[k] >= 0) ? lds_poll(&s_y[cb[k]]) : 0.0;
+          kk = consume_ready<kWin>(cb, vb, lv, kk, acc);
+          if (kk == kWin) {
+            if (q + kWin >= e) {
+              lds_publish(&s_y[j], acc);
+              pending = false;
             } else {
-              acc -= vb[k] * lv[k];
-              ++adv;
+              q += kWin;  // the next round loads the next window
             }
           }
         }
-        kk += adv;
-        if (q + kk >= e) {
-          lds_publish(&s_y[j], acc);
-          Y[(int64_t)j * t + c] = acc;
-          pending = false;
-        } else if (kk == kWin) {
-          q += kWin;
+        if (long_mask) {  // the wave's first unfinished long row, pass by pass
+          const int owner = __builtin_ctzll(long_mask);
+          const int lq = __shfl(q, owner), le = __shfl(e, owner);
+          double part = 0.0;
+          bool ready = true;
+          for (int pos = lq; pos < le && ready; pos += kPass) {
+            int xb[kCoop];
+            double xv[kCoop], lv[kCoop];
+#pragma unroll
+            for (int k = 0; k < kCoop; ++k) {
+              const int qq = pos + lane + 64 * k;
+              xb[k] = qq < le ? pcol[qq] : -1;
+              xv[k] = qq < le ? pval[qq] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < kCoop; ++k) {
+              lv[k] = xb[k] >= 0 ? lds_poll(&s_y[xb[k]]) : 0.0;
+              if (xb[k] >= 0 && is_sentinel(lv[k])) ready = false;
+            }
+            ready = __all(ready);
+            if (ready) {
+#pragma unroll
+              for (int k = 0; k < kCoop; ++k) part += xv[k] * lv[k];
+            }
+          }
+          if (ready) {
+            double sum = part;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) sum += __shfl_xor(sum, o);
+            if (lane == owner) {
+              acc -= sum;
+              lds_publish(&s_y[j], acc);
+            }
+            long_mask &= long_mask - 1;
+          }
         }
       }
+      batch += kWaves;
     }
-    batch += kWaves;
+    __syncthreads();  // the range is solved before the next one folds it in
   }
+  for (int i = tid; i < H; i += NT) Y[(int64_t)i * t + c] = s_y[i];
 }
 
 // y_j <- x_j - sum over the tail entries of the B^T row of head row j (all
@@ -335,8 +413,12 @@ Status head_upper(Model& M, const double* X, double* Y, int t) {
                      M.stream, H, t, M.head_split.p, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, Y);
   const size_t lds = sizeof(double) * H;
   TimedLaunch tl(M, kTimeHeadUpper, 12.0 * M.head_nnz_b + 4.0 * H + 16.0 * H * t);
-  hipLaunchKernelGGL(head_upper_kernel<512>, dim3(t), dim3(512), lds, M.stream, H, t,
-                     M.hb_rows.p, M.hb_pptr.p, M.hb_col.p, M.hb_val.p, Y);
+  HeadRanges R{};
+  R.n = static_cast<int>(M.hb_blocks.size()) - 1;
+  for (int k = 0; k <= R.n; ++k) R.start[k] = M.hb_blocks[k];
+  hipLaunchKernelGGL(head_upper_kernel<512>, dim3(t), dim3(512), lds, M.stream, H, t, R,
+                     M.hb_rows.p, M.hb_pptr.p, M.hb_split.p, M.hb_col.p, M.hb_val.p, M.hb_wcol.p,
+                     M.hb_wval.p, Y);
   return check_launch("head upper");
 }
 
@@ -377,9 +459,12 @@ __global__ void head_copy_bwd_kernel(int H, const int* __restrict__ prow,
   if (p >= H) return;
   const int j = prow[p];
   const int b = bt_ptr[j], e = b + (pptr[p + 1] - pptr[p]), o = pptr[p];
+  // descending child index: the children that finish first (the latest
+  // points) come first, so a row's later windows are loaded while it still
+  // waits for its last children
   for (int q = b; q < e; ++q) {
-    pcol[o + q - b] = bt_col[q];
-    psrc[o + q - b] = bt_src[q];
+    pcol[o + (e - 1 - q)] = bt_col[q];
+    psrc[o + (e - 1 - q)] = bt_src[q];
   }
 }
 
@@ -395,6 +480,23 @@ __global__ void head_vals_kernel(int H, int m, const int* __restrict__ prow,
   if (e < nb) pval_b[e] = bval[psrc[e]];
 }
 
+// First kWin entries of every position of the B^T head rows, padded with -1
+// (columns) and 0 (values), so that a batch's first windows load without
+// waiting for the row pointers.
+__global__ void head_window_kernel(int H, const int* __restrict__ pptr,
+                                   const int* __restrict__ psplit,
+                                   const int* __restrict__ pcol, const double* __restrict__ pval,
+                                   int* __restrict__ wcol, double* __restrict__ wval) {
+  constexpr int kWin = 16;
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= (int64_t)H * kWin) return;
+  const int p = static_cast<int>(g / kWin), k = static_cast<int>(g % kWin);
+  const int q = psplit[p] + k;
+  const bool in = q < pptr[p + 1];
+  if (wcol) wcol[g] = in ? pcol[q] : -1;
+  wval[g] = in ? pval[q] : 0.0;
+}
+
 Status refresh_head_values(Model& M) {
   const int H = M.head_rows;
   if (H == 0) return Status::ok();
@@ -403,6 +505,9 @@ Status refresh_head_values(Model& M) {
   hipLaunchKernelGGL(head_vals_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0,
                      M.stream, H, M.m, M.hf_rows.p, M.bval.p, M.hf_val.p,
                      static_cast<int>(M.head_nnz_b), M.hb_src.p, M.hb_val.p);
+  hipLaunchKernelGGL(head_window_kernel, dim3((unsigned)(((int64_t)H * 16 + 255) / 256)),
+                     dim3(256), 0, M.stream, H, M.hb_pptr.p, M.hb_split.p, M.hb_col.p,
+                     M.hb_val.p, nullptr, M.hb_wval.p);
   return check_launch("head values");
 }
 
@@ -413,11 +518,77 @@ static void allow_lds(K kernel, size_t bytes) {
   (void)hipGetLastError();
 }
 
+// Reorder the backward head positions by index range (latest range first,
+// level order kept inside a range) and record, per position, where the
+// entries into the row's own range start.  Runs on the host (H <= 16384).
+static Status order_head_ranges(Model& M, int H, int nnzb) {
+  std::vector<int> rows(H), ptr(H + 1), col(nnzb > 0 ? nnzb : 1), src(nnzb > 0 ? nnzb : 1);
+  VL_HIP(hipMemcpyAsync(rows.data(), M.hb_rows.p, sizeof(int) * H, hipMemcpyDeviceToHost,
+                        M.stream));
+  VL_HIP(hipMemcpyAsync(ptr.data(), M.hb_pptr.p, sizeof(int) * (H + 1), hipMemcpyDeviceToHost,
+                        M.stream));
+  if (nnzb > 0) {
+    VL_HIP(hipMemcpyAsync(col.data(), M.hb_col.p, sizeof(int) * nnzb, hipMemcpyDeviceToHost,
+                          M.stream));
+    VL_HIP(hipMemcpyAsync(src.data(), M.hb_src.p, sizeof(int) * nnzb, hipMemcpyDeviceToHost,
+                          M.stream));
+  }
+  VL_TRY(sync_stream(M.stream));
+  // range bounds H > H/4 > H/16 > ... (the last range starts at 0)
+  std::vector<int> lo;
+  for (int b = H / 4; b >= 256; b /= 4) lo.push_back(b);
+  lo.push_back(0);
+  std::vector<int> nrows, nptr(1, 0), ncol, nsrc, nsplit, blocks(1, 0);
+  nrows.reserve(H);
+  nsplit.reserve(H);
+  ncol.reserve(nnzb);
+  nsrc.reserve(nnzb);
+  int hi = H;
+  for (int b : lo) {
+    for (int p = 0; p < H; ++p) {
+      const int j = rows[p];
+      if (j < b || j >= hi) continue;
+      nrows.push_back(j);
+      int split = nptr.back();
+      for (int q = ptr[p]; q < ptr[p + 1]; ++q) {
+        ncol.push_back(col[q]);
+        nsrc.push_back(src[q]);
+        if (col[q] >= hi) ++split;  // descending: entries into solved ranges first
+      }
+      nsplit.push_back(split);
+      nptr.push_back(static_cast<int>(ncol.size()));
+    }
+    blocks.push_back(static_cast<int>(nrows.size()));
+    hi = b;
+  }
+  if (static_cast<int>(nrows.size()) != H || static_cast<int>(ncol.size()) != nnzb ||
+      blocks.size() > 10)
+    return Status::make(VL_ERR_STATE, "head range reordering failed");
+  M.hb_blocks = blocks;
+  VL_TRY(M.hb_split.alloc(H));
+  VL_HIP(hipMemcpyAsync(M.hb_rows.p, nrows.data(), sizeof(int) * H, hipMemcpyHostToDevice,
+                        M.stream));
+  VL_HIP(hipMemcpyAsync(M.hb_pptr.p, nptr.data(), sizeof(int) * (H + 1), hipMemcpyHostToDevice,
+                        M.stream));
+  VL_HIP(hipMemcpyAsync(M.hb_split.p, nsplit.data(), sizeof(int) * H, hipMemcpyHostToDevice,
+                        M.stream));
+  if (nnzb > 0) {
+    VL_HIP(hipMemcpyAsync(M.hb_col.p, ncol.data(), sizeof(int) * nnzb, hipMemcpyHostToDevice,
+                          M.stream));
+    VL_HIP(hipMemcpyAsync(M.hb_src.p, nsrc.data(), sizeof(int) * nnzb, hipMemcpyHostToDevice,
+                          M.stream));
+  }
+  return sync_stream(M.stream);
+}
+
 Status build_head_schedule(Model& M) {
   int max_lds = 0;
   VL_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, M.device));
   int64_t cap = (static_cast<int64_t>(max_lds) - 1024) / static_cast<int64_t>(sizeof(double));
-  if (cap > kHeadRows) cap = kHeadRows;
+  int64_t want = kHeadRows;
+  if (const char* env = std::getenv("VL_HEAD_ROWS")) want = std::atoll(env);  // tuning knob
+  if (want < 0) want = 0;
+  if (cap > want) cap = want;
   if (cap < 0) cap = 0;
   int64_t H = M.n < cap ? M.n : cap;
   const size_t bytes = sizeof(double) * static_cast<size_t>(H);
@@ -484,6 +655,13 @@ Status build_head_schedule(Model& M) {
   hipLaunchKernelGGL(head_copy_bwd_kernel, dim3((unsigned)((H + 255) / 256)), dim3(256), 0,
                      M.stream, static_cast<int>(H), M.hb_rows.p, M.bt_ptr.p, M.bt_col.p,
                      M.bt_src.p, M.hb_pptr.p, M.hb_col.p, M.hb_src.p);
+  VL_TRY(check_launch("head copies"));
+  VL_TRY(order_head_ranges(M, static_cast<int>(H), nnzb));
+  VL_TRY(M.hb_wcol.alloc((size_t)H * 16));
+  VL_TRY(M.hb_wval.alloc((size_t)H * 16));
+  hipLaunchKernelGGL(head_window_kernel, dim3((unsigned)(((int64_t)H * 16 + 255) / 256)),
+                     dim3(256), 0, M.stream, static_cast<int>(H), M.hb_pptr.p, M.hb_split.p,
+                     M.hb_col.p, M.hb_val.p, M.hb_wcol.p, M.hb_wval.p);
   VL_TRY(check_launch("head copies"));
   return sync_stream(M.stream);
 }

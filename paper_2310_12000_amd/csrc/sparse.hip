@@ -403,29 +403,16 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m,
               if (k >= kk && cb[k] >= 0 && is_sentinel(yv[k]))
                 yv[k] = poll_load(&Y[(int64_t)cb[k] * t + c]);
           }
-          bool stop = false, ended = false;
-          int adv = 0;
-#pragma unroll
-          for (int k = 0; k < W; ++k) {
-            if (!stop && k >= kk) {
-              if (cb[k] < 0) {
-                stop = true;
-                ended = true;
-              } else if (is_sentinel(yv[k])) {
-                stop = true;
-              } else {
-                acc -= vb[k] * yv[k];
-                ++adv;
-              }
+          const int fm = consume_ready<W>(cb, vb, yv, kk, acc);
+          progressed = fm > kk;
+          kk = fm;
+          if (kk == W) {
+            if (q + W >= e) {  // slots past the row end are empty (-1)
+              publish(&Y[i * t + c], acc);
+              pending = false;
+            } else {
+              q += W;  // window consumed: the next round loads the next one
             }
-          }
-          kk += adv;
-          progressed = adv > 0;
-          if (ended || q + kk >= e) {
-            publish(&Y[i * t + c], acc);
-            pending = false;
-          } else if (kk == W) {
-            q += W;  // window consumed: the next round loads the next one
           }
         }
         if (__any(pending) && !__any(progressed)) {
@@ -454,6 +441,121 @@ __global__ void trsm_prefill(double* __restrict__ Y, int64_t count, int* counter
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x)
     Y[i] = sentinel();
+}
+
+// Level-scheduled solve of one level (wide blocks, t > 64): block
+// (k, s) solves row rows[k] for the 256 columns of slice s,
+//   Y_i = rs_i X_i - sum_q vals[q] Y_{idx[q]},  q in [q0, e) (idx < 0 ends the row),
+// subtracting the entries in the same order as the sync-free kernel.  All
+// rows a level depends on were written by earlier launches on the stream, so
+// plain cached loads are safe and nothing waits.
+template <bool LOWER>
+__global__ __launch_bounds__(256) void trsm_level_kernel(int t, const int* __restrict__ rows,
+                                                         int m, const int* __restrict__ ptr,
+                                                         const int* __restrict__ idx,
+                                                         const double* __restrict__ vals,
+                                                         const double* __restrict__ X,
+                                                         const double* __restrict__ rs,
+                                                         double* __restrict__ Y) {
+  const int c = blockIdx.y * 256 + threadIdx.x;
+  const int64_t i = rows[blockIdx.x];
+  if (c >= t) return;
+  int q, e;
+  if (LOWER) {
+    q = static_cast<int>(i * m);
+    e = q + m;
+  } else {
+    q = ptr[i];
+    e = ptr[i + 1];
+  }
+  double acc = X[i * t + c];
+  if (rs) acc *= rs[i];
+  for (; q < e; q += 8) {
+    int cb[8];
+    double vb[8], yv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      cb[k] = (q + k < e) ? idx[q + k] : -1;
+      vb[k] = (q + k < e) ? vals[q + k] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) yv[k] = (cb[k] >= 0) ? Y[(int64_t)cb[k] * t + c] : 0.0;
+    bool ended = false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (cb[k] < 0) ended = true;
+      if (!ended) acc -= vb[k] * yv[k];
+    }
+    if (ended) break;
+  }
+  Y[i * t + c] = acc;
+}
+
+// The same for levels of long rows (average length above 16; in B^T these
+// are the earliest points of the ordering): block (k, s) covers 64 columns
+// of row rows[k], and its 4 waves take the entries q0 + w, q0 + w + 4, ...
+// of the row; the 4 partial sums are added in wave order.
+__global__ __launch_bounds__(256) void trsm_level_split_kernel(int t, const int* __restrict__ rows,
+                                                               const int* __restrict__ ptr,
+                                                               const int* __restrict__ idx,
+                                                               const double* __restrict__ vals,
+                                                               const double* __restrict__ X,
+                                                               double* __restrict__ Y) {
+  __shared__ double s_part[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = blockIdx.y * 64 + lane;
+  const int64_t i = rows[blockIdx.x];
+  const int b = ptr[i], e = ptr[i + 1];
+  double part = 0.0;
+  if (c < t) {
+    for (int q = b + w; q < e; q += 4 * 8) {
+      int cb[8];
+      double vb[8], yv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        cb[k] = (q + 4 * k < e) ? idx[q + 4 * k] : -1;
+        vb[k] = (q + 4 * k < e) ? vals[q + 4 * k] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) yv[k] = (cb[k] >= 0) ? Y[(int64_t)cb[k] * t + c] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) part += vb[k] * yv[k];
+    }
+  }
+  s_part[w][lane] = part;
+  __syncthreads();
+  if (w == 0 && c < t)
+    Y[i * t + c] = X[i * t + c] - (((s_part[0][lane] + s_part[1][lane]) + s_part[2][lane]) +
+                                   s_part[3][lane]);
+}
+
+// One launch per level of the full level order; each launch is timed on its
+// own when timing is on.
+static Status trsm_levels(Model& M, bool lower, const double* X, double* Y, int t,
+                          const double* rowscale) {
+  const std::vector<int>& lp = lower ? M.lvl_ptr_f : M.lvl_ptr_b;
+  const std::vector<int64_t>& lnz = lower ? M.lvl_nnz_f : M.lvl_nnz_b;
+  const int* order = lower ? M.full_order_f.p : M.full_order_b.p;
+  if (lp.size() < 2 || lp.back() != M.n) return Status::make(VL_ERR_STATE, "no level schedule");
+  const unsigned gy = static_cast<unsigned>((t + 255) / 256);
+  for (size_t l = 0; l + 1 < lp.size(); ++l) {
+    const int rows = lp[l + 1] - lp[l];
+    if (rows <= 0) continue;
+    TimedLaunch tl(M, lower ? kTimeLevelLower : kTimeLevelUpper,
+                   12.0 * lnz[l] + 16.0 * rows * t + 4.0 * rows +
+                       (lower ? (rowscale ? 8.0 * rows : 0.0) : 8.0 * rows));
+    if (lower) {
+      hipLaunchKernelGGL(trsm_level_kernel<true>, dim3(rows, gy), dim3(256), 0, M.stream, t,
+                         order + lp[l], M.m, nullptr, M.nbr.p, M.bval.p, X, rowscale, Y);
+    } else if (lnz[l] > 16LL * rows) {
+      hipLaunchKernelGGL(trsm_level_split_kernel, dim3(rows, (t + 63) / 64), dim3(256), 0,
+                         M.stream, t, order + lp[l], M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, Y);
+    } else {
+      hipLaunchKernelGGL(trsm_level_kernel<false>, dim3(rows, gy), dim3(256), 0, M.stream, t,
+                         order + lp[l], 0, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, nullptr, Y);
+    }
+  }
+  return check_launch(lower ? "trsm level lower" : "trsm level upper");
 }
 
 static int trsm_grid(int64_t total_units) {
@@ -488,8 +590,14 @@ static Status trsm_prepare(Model& M, double* Y, int64_t count, int slot) {
 // and use the sync-free kernels for all rows.
 static int64_t head_of(const Model& M, int t) { return t <= 64 ? M.head_rows : 0; }
 
+// Blocks wider than 64 columns have ample parallelism inside each level and
+// are bandwidth-bound: they take the level-scheduled path (no sentinel fill,
+// no polling).  Narrower blocks take the LDS head and the sync-free tail.
+static bool use_levels(const Model& M, int t) { return t > 64 && M.lvl_ptr_f.size() > 1; }
+
 Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* rowscale,
                    bool prefilled, int slot) {
+  if (use_levels(M, t)) return trsm_levels(M, true, X, Y, t, rowscale);
   if (!prefilled) VL_TRY(trsm_prepare(M, Y, M.n * (int64_t)t, slot));
   const int64_t H = head_of(M, t);
   if (H > 0) VL_TRY(head_lower(M, X, Y, t, rowscale));
@@ -524,6 +632,7 @@ Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* ro
 }
 
 Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled, int slot) {
+  if (use_levels(M, t)) return trsm_levels(M, false, X, Y, t, nullptr);
   if (!prefilled) VL_TRY(trsm_prepare(M, Y, M.n * (int64_t)t, slot));
   const int64_t H = head_of(M, t);
   if (H < M.n) {
@@ -642,6 +751,22 @@ __global__ void level_count_kernel(int64_t n, int64_t r0, const int* __restrict_
   if (r >= r0) atomicAdd(&cnt[lev[r]], 1);
 }
 
+// nnz of the rows of each level (lower: entries with idx >= 0 of the ELL
+// row; upper: the CSR row length)
+__global__ void level_nnz_kernel(int64_t n, int m, const int* __restrict__ ptr,
+                                 const int* __restrict__ idx, const int* __restrict__ lev,
+                                 unsigned long long* __restrict__ nnz) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = 0;
+  if (ptr) {
+    c = ptr[i + 1] - ptr[i];
+  } else {
+    for (int k = 0; k < m; ++k) c += idx[i * m + k] >= 0 ? 1 : 0;
+  }
+  if (c) atomicAdd(&nnz[lev[i]], static_cast<unsigned long long>(c));
+}
+
 __global__ void level_scatter_kernel(int64_t n, int64_t r0, const int* __restrict__ spatial,
                                      const int* __restrict__ lev, const int* __restrict__ start,
                                      int* __restrict__ cursor, int* __restrict__ order) {
@@ -692,6 +817,30 @@ Status build_tail_orders(Model& M) {
       hipLaunchKernelGGL(level_scatter_kernel, dim3(gn), dim3(tb), 0, M.stream, n, r0, spatial,
                          lev.p, start.p, cnt.p, out);
       VL_TRY(check_launch("level order"));
+      if (full) {
+        // level pointers and per-level nnz of the full order, to the host
+        std::vector<int> st(n + 1);
+        VL_HIP(hipMemcpyAsync(st.data(), start.p, sizeof(int) * (n + 1), hipMemcpyDeviceToHost,
+                              M.stream));
+        VL_TRY(sync_stream(M.stream));
+        int64_t L = 0;
+        while (L < n && st[L] < n) ++L;  // levels 0..L-1 are non-empty prefixes
+        std::vector<int>& lp = dir == 0 ? M.lvl_ptr_f : M.lvl_ptr_b;
+        lp.assign(st.begin(), st.begin() + L + 1);
+        DevBuf<unsigned long long> lnz;
+        VL_TRY(lnz.alloc(L > 0 ? L : 1));
+        VL_HIP(hipMemsetAsync(lnz.p, 0, sizeof(unsigned long long) * (L > 0 ? L : 1), M.stream));
+        hipLaunchKernelGGL(level_nnz_kernel, dim3(gn), dim3(tb), 0, M.stream, n,
+                           dir == 0 ? M.m : 0, dir == 0 ? nullptr : M.bt_ptr.p,
+                           dir == 0 ? M.nbr.p : nullptr, lev.p, lnz.p);
+        VL_TRY(check_launch("level nnz"));
+        std::vector<unsigned long long> hz(L > 0 ? L : 1);
+        VL_HIP(hipMemcpyAsync(hz.data(), lnz.p, sizeof(unsigned long long) * hz.size(),
+                              hipMemcpyDeviceToHost, M.stream));
+        VL_TRY(sync_stream(M.stream));
+        std::vector<int64_t>& nz = dir == 0 ? M.lvl_nnz_f : M.lvl_nnz_b;
+        nz.assign(hz.begin(), hz.begin() + L);
+      }
     }
   }
   VL_TRY(sync_stream(M.stream));

@@ -24,6 +24,25 @@ __device__ __forceinline__ bool is_sentinel(float v) {
   return static_cast<unsigned>(__float_as_int(v)) == 0xFFA5BEEFu;
 }
 
+// In-order consumption of one window of a triangular-solve row.  Entries
+// k0 <= k < W are taken while their values are ready (slot < 0 = no entry;
+// its value and coefficient are 0), applying acc -= v[k] * y[k] in order.
+// Returns the first position still waiting (W once the window is done).
+// Branch-free: the ready prefix and the updates are computed with selects.
+template <int W>
+__device__ __forceinline__ int consume_ready(const int* cb, const double* vb, const double* yv,
+                                             int k0, double& acc) {
+  int fm = W;
+#pragma unroll
+  for (int k = W - 1; k >= 0; --k) fm = (k >= k0 && cb[k] >= 0 && is_sentinel(yv[k])) ? k : fm;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const double nx = acc - vb[k] * yv[k];
+    acc = (k >= k0 && k < fm) ? nx : acc;
+  }
+  return fm;
+}
+
 // Device-coherent polling load / publishing store of one value.  Relaxed
 // ordering is enough: every published value carries its own readiness.
 template <typename T>

@@ -106,7 +106,9 @@ enum TimedKind : int {
   kTimeTrsmUpper = 3, // sync-free rows of B^T Y = X
   kTimeHeadLower = 4, // LDS head rows of B Y = X
   kTimeHeadUpper = 5, // LDS head rows of B^T Y = X
-  kTimeKinds = 6
+  kTimeLevelLower = 6, // level-scheduled rows of B Y = X (wide blocks)
+  kTimeLevelUpper = 7, // level-scheduled rows of B^T Y = X (wide blocks)
+  kTimeKinds = 8
 };
 
 struct Timing {
@@ -151,8 +153,16 @@ struct Model {
   DevBuf<int> hf_ptr, hf_rows, hb_ptr, hb_rows;
   DevBuf<int> hf_nbr, hb_pptr, hb_col, hb_src;  // position-ordered structure
   DevBuf<double> hf_val, hb_val;                // position-ordered values
+  DevBuf<int> hb_wcol;                          // first 16 in-range B^T head
+  DevBuf<double> hb_wval;                       // entries per position, padded
+  DevBuf<int> hb_split;                         // first in-range entry per position
+  std::vector<int> hb_blocks;                   // position ranges of the index ranges
   DevBuf<int> tail_order_f, tail_order_b;       // tail rows in level order
   DevBuf<int> full_order_f, full_order_b;       // all rows in level order
+  // level l of the full orders = positions [lvl_ptr[l], lvl_ptr[l + 1]); nnz
+  // of the rows of each level (host copies, for the level-scheduled solves)
+  std::vector<int> lvl_ptr_f, lvl_ptr_b;
+  std::vector<int64_t> lvl_nnz_f, lvl_nnz_b;
   DevBuf<int> head_split;                       // first tail entry of head B^T rows
 
   // neighbour-search grid

@@ -170,10 +170,11 @@ def test_predict(c1, c1_fit):
     assert rel_err(f["var"], var) < TOL
 
 
-@pytest.mark.parametrize("t", [1, 8, 50, 65])
+@pytest.mark.parametrize("t", [1, 8, 50, 65, 300])
 def test_trsm_head_and_tail(P, t):
-    # n above the head size: rows solved in LDS level by level, the rest by
-    # the sync-free tail kernels.  The reference solves with the device's own
+    # n above the head size: for t <= 64 rows solved in LDS level by level,
+    # the rest by the sync-free tail kernels; wider blocks (65, 300: one and
+    # two column slices, ragged) take the level-scheduled launches.  The reference solves with the device's own
     # B entries, so the check isolates the solve from the (ill-conditioned)
     # neighbour Cholesky.
     n, m = 40000, 20

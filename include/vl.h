@@ -131,7 +131,12 @@ vl_status vl_build_vecchia(const double* coords, int64_t n, int m, int cov,
  * reusing neighbour sets and B^T structure.  Invalidates the mode. */
 vl_status vl_set_theta(vl_model* h, const double* theta_host);
 
-/* Newton mode finding (eq. newton) from b = 0.
+/* Newton mode finding (eq. newton) from b = 0.  With o->precond = VL_PREC_VADU
+ * each step solves (W + Sigma~^{-1}) b' = W b + g by CG preconditioned with
+ * P_VADU (eq. pcls1); with VL_PREC_LRAC it solves (Sigma~ + W^{-1}) (W b') =
+ * Sigma~ (W b + g) (eq. pcls2) preconditioned with P_LRAC = L_k L_k^T + W^{-1}
+ * (Sec. 3.1.2), L_k the rank-o->lrac_rank pivoted Cholesky factor of Sigma,
+ * built once per theta.
  *   y        device, n responses
  *   F        device, n offsets F(X) (NULL = 0)
  *   lik      vl_lik; aux_host: likelihood auxiliary parameters (host;
@@ -146,6 +151,8 @@ vl_status vl_find_mode(vl_model* h, const double* y, const double* F, int lik,
  *   nll_host        host, 1 double
  *   grad_theta_host host, 2 doubles d/d(sigma2, rho) (NULL = skip; needs
  *                   want_deriv at build and the VADU preconditioner)
+ * VADU: eq. (logdetsplit) with probes z = B^T (W + D^{-1})^{1/2} eps; LRAC:
+ * eq. (logdetsplit2) with z = L_k eps_k + W^{-1/2} eps_n, weight r0^T z0.
  * Synchronises. */
 vl_status vl_neg_log_marglik(vl_model* h, const vl_opts* o, double* nll_host,
                              double* grad_theta_host, vl_stats* st);
@@ -179,6 +186,11 @@ vl_status vl_predict(vl_model* h, const double* coords_p, int64_t n_p,
  *  13 prediction neighbours of the last vl_predict, int32 n_p x m
  *  14 prediction factor entries -A_p (the off-diagonal of B_po), double
  *     n_p x m;  15 D_p, double n_p
+ *  16 LRAC pivoted Cholesky factor L_k, double n x k (row-major)
+ *  17 LRAC pivots, int32 k
+ *  18 Cholesky factor of I + L^T W L with the W of the last LRAC call,
+ *     double K x K lower (row-major), K = k rounded up to 16: rows and
+ *     columns past k belong to the identity
  * dst is a device pointer; `bytes` must equal the size of the array.
  * Synchronises. */
 vl_status vl_export(vl_model* h, int which, void* dst, size_t bytes);

@@ -253,16 +253,20 @@ def vadu_ops(model, W):
     return apply_A, apply_Pinv
 
 
-def pivoted_cholesky(coords, kind, theta, k):
+def pivoted_cholesky(coords, kind, theta, k, pivots=None):
     """Rank-k pivoted Cholesky of the original covariance matrix Sigma
-    (Sec. 3.1.2): pivot = largest remaining diagonal (first index on ties)."""
+    (Sec. 3.1.2): pivot = largest remaining diagonal (first index on ties).
+
+    pivots: optional sequence that replaces the argmax choices (replay of
+    another implementation's pivots when two residual diagonals tie to
+    rounding); the arithmetic is unchanged."""
     sigma2, rho = theta
     n = coords.shape[0]
     k = min(k, n)
     L = np.zeros((n, k))
     d = np.full(n, float(sigma2))
     for j in range(k):
-        p = int(np.argmax(d))
+        p = int(np.argmax(d)) if pivots is None else int(pivots[j])
         col = _vec.covariance(_vec.sqdist(coords, coords[p]), kind, sigma2, rho)
         L[:, j] = (col - L[:, :j] @ L[p, :j]) / np.sqrt(d[p])
         d = d - L[:, j] ** 2

@@ -133,6 +133,9 @@ static int64_t export_count(Model& M, int which) {
     case 12: return static_cast<int64_t>(M.last_r0z0.size());
     case 13: case 14: return M.last_np * M.m;
     case 15: return M.last_np;
+    case 16: return M.lrac_ready ? M.n * M.lrac_k : -1;
+    case 17: return M.lrac_ready ? M.lrac_k : -1;
+    case 18: return M.lrac_ready ? static_cast<int64_t>(M.lrac_K) * M.lrac_K : -1;
     default: return -1;
   }
 }
@@ -140,7 +143,7 @@ static int64_t export_count(Model& M, int which) {
 static Status do_export(Model& M, int which, void* dst, size_t bytes) {
   const int64_t cnt = export_count(M, which);
   if (cnt < 0) return Status::make(VL_ERR_STATE, "array not available");
-  const bool is_int = (which == 0 || which == 9 || which == 10 || which == 13);
+  const bool is_int = (which == 0 || which == 9 || which == 10 || which == 13 || which == 17);
   const size_t need = static_cast<size_t>(cnt) * (is_int ? sizeof(int) : sizeof(double));
   if (bytes != need) return Status::invalid("export size mismatch");
   if (need == 0) return Status::ok();
@@ -165,6 +168,14 @@ static Status do_export(Model& M, int which, void* dst, size_t bytes) {
     case 13: return copy_out(M, dst, M.pred_nbr.p, need, false);
     case 14: return copy_out(M, dst, M.pred_bval.p, need, false);
     case 15: return copy_out(M, dst, M.pred_dval.p, need, false);
+    case 16: {  // n x k out of the padded n x K layout
+      VL_HIP(hipMemcpy2DAsync(dst, sizeof(double) * M.lrac_k, M.lrac_L.p,
+                              sizeof(double) * M.lrac_K, sizeof(double) * M.lrac_k, M.n,
+                              hipMemcpyDeviceToDevice, M.stream));
+      return sync_stream(M.stream);
+    }
+    case 17: return copy_out(M, dst, M.lrac_piv.p, need, false);
+    case 18: return copy_out(M, dst, M.lrac_M.p, need, false);
     default: return Status::invalid("unknown export");
   }
 }
@@ -257,6 +268,7 @@ vl_status vl_set_theta(vl_model* h, const double* theta_host) {
     h->sigma2 = theta_host[0];
     h->rho = theta_host[1];
     h->has_mode = false;
+    h->lrac_ready = false;
     return vl::compute_factor(*h);
   });
 }
@@ -275,7 +287,8 @@ vl_status vl_find_mode(vl_model* h, const double* y, const double* F, int lik,
       if (!aux_host || !(aux_host[0] > 0.0)) return vl::Status::invalid("Gaussian needs tau2 > 0");
       aux = aux_host[0];
     }
-    if (o->precond != VL_PREC_VADU) return vl::Status::invalid("mode finding uses VADU here");
+    if (o->precond == VL_PREC_LRAC && (o->lrac_rank < 1 || o->lrac_rank > 1024))
+      return vl::Status::invalid("lrac_rank must be in [1, 1024]");
     Model& M = *h;
     M.lik = lik;
     M.aux = aux;
@@ -306,7 +319,8 @@ vl_status vl_neg_log_marglik(vl_model* h, const vl_opts* o, double* nll_host,
     const double t0 = vl::now_ms();
     if (!h || !nll_host) return vl::Status::invalid("null handle or output");
     VL_TRY(vl::check_opts(o));
-    if (o->precond != VL_PREC_VADU) return vl::Status::invalid("preconditioner not supported");
+    if (o->precond == VL_PREC_LRAC && (o->lrac_rank < 1 || o->lrac_rank > 1024))
+      return vl::Status::invalid("lrac_rank must be in [1, 1024]");
     vl::NllInfo info;
     vl::Status s = vl::neg_log_marglik(*h, *o, nll_host, grad_theta_host, &info);
     if (st) {

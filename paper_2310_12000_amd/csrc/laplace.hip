@@ -170,11 +170,19 @@ Status find_mode(Model& M, const vl_opts& o, vl_stats* st) {
   bool converged = false;
   int cg_total = 0, cg_max = 0;
   bool cg_cap = false;
+  const bool lrac = o.precond == VL_PREC_LRAC;
+  if (lrac) VL_TRY(lrac_build(M, o.lrac_rank));
   for (; it < o.max_newton;) {
     VL_TRY(lik_rows(M, M.mode.p, M.g.p, M.W.p, M.vec_a.p, M.vec_b.p, nullptr, nullptr));
-    CgOps ops = vadu_ops(M.W.p, M.vec_b.p);
-    VL_TRY(cg_solve(M, M.cg1, ops, 1, M.vec_a.p, o.cg_tol, o.max_cg, false));
-    VL_TRY(copy_d2d(M.mode.p, M.cg1.U.p, sizeof(double) * n, M.stream));
+    if (lrac) {
+      // eq. (pcls2): (Sigma~ + W^{-1}) (W b') = Sigma~ (W b + g)
+      VL_TRY(lrac_newton_solve(M, o, M.vec_a.p, M.mode.p));
+    } else {
+      // eq. (pcls1): (W + Sigma~^{-1}) b' = W b + g with P_VADU
+      CgOps ops = vadu_ops(M.W.p, M.vec_b.p);
+      VL_TRY(cg_solve(M, M.cg1, ops, 1, M.vec_a.p, o.cg_tol, o.max_cg, false));
+      VL_TRY(copy_d2d(M.mode.p, M.cg1.U.p, sizeof(double) * n, M.stream));
+    }
     const int ci = M.cg1.host_iters[0];
     M.newton_cg_iters.push_back(ci);
     cg_total += ci;
@@ -418,11 +426,21 @@ Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, Nl
   VL_TRY(M.vec_a.reserve(n));  // sqrt(W + D^{-1})
   VL_TRY(M.vec_b.reserve(n));  // (W + D^{-1})^{-1}
   VL_TRY(lik_rows(M, M.mode.p, nullptr, M.W.p, nullptr, M.vec_b.p, M.vec_a.p, nullptr));
-  VL_TRY(M.rhs_blk.reserve(static_cast<size_t>(n) * t));
-  // z_i = B^T ((W + D^{-1})^{1/2} o eps_i), Cov(z_i) = P_VADU
-  VL_TRY(spmm_bt_probe(M, M.rhs_blk.p, t, M.vec_a.p, o.seed, kTagSlq, 0, 0, nullptr, 0, 0));
-  CgOps ops = vadu_ops(M.W.p, M.vec_b.p);
-  VL_TRY(cg_solve(M, M.cg, ops, t, M.rhs_blk.p, o.cg_tol, o.max_cg, grad != nullptr));
+  const bool lrac = o.precond == VL_PREC_LRAC;
+  if (lrac && grad) return Status::invalid("the theta-gradient needs the VADU preconditioner");
+  double logdet_lrac = 0.0;
+  if (lrac) {
+    // eq. (logdetsplit2): log det(Sigma~ W + I) = sum log W + log det P_LRAC
+    // + log det(P^{-1} (Sigma~ + W^{-1})), probes z = L eps_k + W^{-1/2} eps_n
+    VL_TRY(lrac_build(M, o.lrac_rank));
+    VL_TRY(lrac_slq(M, o, &logdet_lrac));
+  } else {
+    VL_TRY(M.rhs_blk.reserve(static_cast<size_t>(n) * t));
+    // z_i = B^T ((W + D^{-1})^{1/2} o eps_i), Cov(z_i) = P_VADU
+    VL_TRY(spmm_bt_probe(M, M.rhs_blk.p, t, M.vec_a.p, o.seed, kTagSlq, 0, 0, nullptr, 0, 0));
+    CgOps ops = vadu_ops(M.W.p, M.vec_b.p);
+    VL_TRY(cg_solve(M, M.cg, ops, t, M.rhs_blk.p, o.cg_tol, o.max_cg, grad != nullptr));
+  }
   M.last_block_iters = M.cg.host_iters;
   VL_TRY(M.red_out.reserve(2 * t + 64));
   VL_TRY(tridiag_quadrature(M, M.cg, M.red_out.p));
@@ -439,7 +457,8 @@ Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, Nl
   gamma /= t;
   double terms[4];
   VL_TRY(laplace_terms(M, M.mode.p, M.W.p, terms));
-  const double logdet = terms[2] + terms[3] + gamma;
+  // eq. (logdetsplit): sum log D + log det(W + D^{-1}) + SLQ term (VADU)
+  const double logdet = (lrac ? logdet_lrac : terms[2] + terms[3]) + gamma;
   *nll = -terms[0] + 0.5 * terms[1] + 0.5 * logdet;
   int cg_max = 0;
   for (int v : M.cg.host_iters) cg_max = v > cg_max ? v : cg_max;

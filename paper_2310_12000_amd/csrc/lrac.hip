@@ -1,0 +1,443 @@
+// Low-rank pivoted-Cholesky preconditioner P_LRAC = L_k L_k^T + W^{-1}
+// (Sec. 3.1.2, eq. P_LRAC) and the operator Sigma~ + W^{-1} of eq. (pcls2).
+//
+//   L_k   n x k pivoted Cholesky factor of the covariance matrix Sigma built
+//         from the coordinates: the pivot is the largest residual diagonal
+//         (first index on ties), column j = (Sigma[:, p] - L L^T[:, p]) /
+//         sqrt(d_p), d -= column^2.  Stored row-major n x K, K = k rounded
+//         up to 16, with zero columns past k.
+//   M     I_K + L^T W L (K x K), its Cholesky factor C and log det M; the
+//         padded columns give identity rows, so log det M is that of the
+//         k x k matrix.  log det P = log det M - sum log W (determinant lemma).
+//   P^{-1} R = W o R - W o (L M^{-1} (L^T (W o R)))   (Woodbury)
+//
+// The dense panels L^T diag(w) X (K x t, a reduction over the n rows) and
+// L Y (n x t) run on the FP64 matrix cores (v_mfma_f64_16x16x4f64): a wave
+// owns 16 x 16 output tiles and steps through the contraction 4 at a time.
+// Operand layout of one step, lane l = 16 q + i (q = l / 16, i = l mod 16):
+// A[i][q] and B[q][i] in, D[q + 4 r][i] (r = 0..3) out (measured on gfx950).
+#include "vl_internal.h"
+#include "vl_laplace.h"
+#include "vl_ops.h"
+
+namespace vl {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma16x16x4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------- pivoted Cholesky
+__global__ void pc_init_kernel(int64_t n, int K, double sigma2, double* __restrict__ d,
+                               double* __restrict__ L, int* __restrict__ piv,
+                               double* __restrict__ pval) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g < n) d[g] = sigma2;  // c(0) = sigma2 for both covariance functions
+  for (int64_t e = g; e < n * K; e += (int64_t)gridDim.x * blockDim.x) L[e] = 0.0;
+  if (g == 0) {
+    piv[0] = 0;  // all diagonals equal: the first index
+    pval[0] = sigma2;
+  }
+}
+
+// Column j with pivot piv[j] (pval[j] = its residual diagonal), the update of
+// d, and per-block (max d, smallest index) candidates for the next pivot.
+__global__ __launch_bounds__(256) void pc_column_kernel(
+    int64_t n, int K, int j, const double* __restrict__ coords, int kind, double sigma2,
+    double rho, const int* __restrict__ piv, const double* __restrict__ pval,
+    double* __restrict__ d, double* __restrict__ L, double* __restrict__ part_v,
+    int* __restrict__ part_i, int* __restrict__ status) {
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  const int p = piv[j];
+  const double dp = pval[j];
+  if (!(dp > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) raise_error(status, kErrNotSpd);
+  }
+  const double inv = 1.0 / sqrt(dp);
+  const double px = coords[2 * (int64_t)p], py = coords[2 * (int64_t)p + 1];
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double c = cov_eval(kind, sqdist(coords[2 * i], coords[2 * i + 1], px, py), sigma2, rho);
+    double dot = 0.0;
+    for (int l = 0; l < j; ++l) dot += L[i * K + l] * L[(int64_t)p * K + l];
+    const double v = (c - dot) * inv;
+    L[i * K + j] = v;
+    const double dn = d[i] - v * v;
+    d[i] = dn;
+    if (dn > best) {  // rows visited in increasing order: the first maximum stays
+      best = dn;
+      bi = static_cast<int>(i);
+    }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double v2 = sv[threadIdx.x + o];
+      const int i2 = si[threadIdx.x + o];
+      if (v2 > sv[threadIdx.x] || (v2 == sv[threadIdx.x] && i2 < si[threadIdx.x])) {
+        sv[threadIdx.x] = v2;
+        si[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part_v[blockIdx.x] = sv[0];
+    part_i[blockIdx.x] = si[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void pc_argmax_kernel(int nparts, const double* __restrict__ part_v,
+                                                        const int* __restrict__ part_i, int j,
+                                                        const double* __restrict__ d,
+                                                        int* __restrict__ piv,
+                                                        double* __restrict__ pval) {
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int b = threadIdx.x; b < nparts; b += 256) {
+    const double v = part_v[b];
+    const int i = part_i[b];
+    if (v > best || (v == best && i < bi)) {
+      best = v;
+      bi = i;
+    }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double v2 = sv[threadIdx.x + o];
+      const int i2 = si[threadIdx.x + o];
+      if (v2 > sv[threadIdx.x] || (v2 == sv[threadIdx.x] && i2 < si[threadIdx.x])) {
+        sv[threadIdx.x] = v2;
+        si[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    piv[j + 1] = si[0];
+    pval[j + 1] = d[si[0]];
+  }
+}
+
+// ------------------------------------------------------------ MFMA panels
+// part[blk] (K x ldp) = sum over the block's rows r of L[r, :]^T (w_r X[r, :]),
+// columns of X beyond t read as 0.  Each block covers rows [r0, r1); wave w
+// owns tiles w, w + 4, ... of the (K / 16) x (ldp / 16) tile grid.
+__global__ __launch_bounds__(256) void gram_kernel(int64_t n, int K, int64_t rows_per_block,
+                                                   const double* __restrict__ L,
+                                                   const double* __restrict__ w,
+                                                   const double* __restrict__ X, int ldx, int t,
+                                                   int ldp, double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, i = lane & 15;
+  const int64_t r0 = blockIdx.x * rows_per_block;
+  int64_t r1 = r0 + rows_per_block;
+  if (r1 > n) r1 = n;
+  const int ta = K / 16, tb = ldp / 16;
+  double* out = part + (int64_t)blockIdx.x * K * ldp;
+  for (int tile = wave; tile < ta * tb; tile += 4) {
+    const int a = tile / tb, b = tile - (tile / tb) * tb;
+    const int col = b * 16 + i;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t r = r0; r < r1; r += 4) {
+      const int64_t rr = r + q;
+      const bool in = rr < r1;
+      const double av = in ? L[rr * K + a * 16 + i] : 0.0;
+      const double bv = (in && col < t) ? (w ? w[rr] : 1.0) * X[rr * ldx + col] : 0.0;
+      acc = mfma16x16x4(av, bv, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[(int64_t)(a * 16 + q + 4 * r) * ldp + b * 16 + i] = acc[r];
+  }
+}
+
+// out (K x ldp) = sum of the parts in block order (deterministic).
+__global__ void gram_reduce_kernel(int nparts, int64_t size, const double* __restrict__ part,
+                                   double* __restrict__ out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= size) return;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * size + e];
+  out[e] = s;
+}
+
+// Z (n x t) = epilogue(L Y), Y K x ldy; one 16 x 16 output tile per wave.
+//   mode 0:  Z = w o (R - L Y)                       (Woodbury)
+//   mode 1:  Z = L Y + eps_n / sqrt(W), eps_n Rademacher (probe of P_LRAC)
+__global__ __launch_bounds__(256) void panel_kernel(int64_t n, int K, const double* __restrict__ L,
+                                                    const double* __restrict__ Y, int ldy, int t,
+                                                    int mode, const double* __restrict__ w,
+                                                    const double* __restrict__ R,
+                                                    uint64_t seed, double* __restrict__ Z) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, i = lane & 15;
+  const int tcols = (t + 15) / 16;
+  const int64_t tile = blockIdx.x * 4 + wave;
+  const int64_t rt = tile / tcols;
+  const int ct = static_cast<int>(tile - rt * tcols);
+  const int64_t row0 = rt * 16;
+  if (row0 >= n) return;
+  const int col = ct * 16 + i;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  const int64_t ra = row0 + i;
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const double av = ra < n ? L[ra * K + k0 + q] : 0.0;
+    const double bv = col < t ? Y[(int64_t)(k0 + q) * ldy + col] : 0.0;
+    acc = mfma16x16x4(av, bv, acc);
+  }
+  if (col >= t) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = row0 + q + 4 * r;
+    if (row >= n) continue;
+    const int64_t e = row * t + col;
+    if (mode == 0) {
+      Z[e] = w[row] * (R[e] - acc[r]);
+    } else {
+      Z[e] = acc[r] + rademacher(seed, kTagLracN, (uint64_t)col, (uint64_t)row) / sqrt(w[row]);
+    }
+  }
+}
+
+// Cholesky of M (K x K, row-major, in place: lower factor) by one block, and
+// log det M = 2 sum log C_jj.
+__global__ __launch_bounds__(256) void small_cholesky_kernel(int K, double* __restrict__ Mx,
+                                                             double* __restrict__ logdet,
+                                                             int* __restrict__ status) {
+  extern __shared__ double a[];
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) a[e] = Mx[e];
+  __syncthreads();
+  for (int j = 0; j < K; ++j) {
+    if (threadIdx.x == 0) {
+      double s = a[j * K + j];
+      for (int l = 0; l < j; ++l) s -= a[j * K + l] * a[j * K + l];
+      if (!(s > 0.0)) raise_error(status, kErrNotSpd);
+      a[j * K + j] = sqrt(s > 0.0 ? s : 1.0);
+    }
+    __syncthreads();
+    const double djj = a[j * K + j];
+    for (int i = j + 1 + threadIdx.x; i < K; i += blockDim.x) {
+      double s = a[i * K + j];
+      for (int l = 0; l < j; ++l) s -= a[i * K + l] * a[j * K + l];
+      a[i * K + j] = s / djj;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+    const int r = e / K, c = e - (e / K) * K;
+    Mx[e] = c <= r ? a[e] : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int j = 0; j < K; ++j) s += log(a[j * K + j]);
+    *logdet = 2.0 * s;
+  }
+}
+
+// M = I + G (G = L^T W L), in place.
+__global__ void add_identity_kernel(int K, double* __restrict__ Mx) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < K) Mx[e * K + e] += 1.0;
+}
+
+// S (K x ld) <- M^{-1} S with the Cholesky factor C (K x K), columns < t;
+// one thread per column.
+__global__ void chol_solve_kernel(int K, const double* __restrict__ C, int t, int ld,
+                                  double* __restrict__ S) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= t) return;
+  for (int i = 0; i < K; ++i) {  // C y = s
+    double v = S[(int64_t)i * ld + c];
+    for (int l = 0; l < i; ++l) v -= C[i * K + l] * S[(int64_t)l * ld + c];
+    S[(int64_t)i * ld + c] = v / C[i * K + i];
+  }
+  for (int i = K - 1; i >= 0; --i) {  // C^T x = y
+    double v = S[(int64_t)i * ld + c];
+    for (int l = i + 1; l < K; ++l) v -= C[l * K + i] * S[(int64_t)l * ld + c];
+    S[(int64_t)i * ld + c] = v / C[i * K + i];
+  }
+}
+
+// E (K x ld): Rademacher eps_k for rows < k, 0 for the padded rows.
+__global__ void lrac_probe_k_kernel(int K, int k, int t, int ld, uint64_t seed,
+                                    double* __restrict__ E) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= K * ld) return;
+  const int r = e / ld, c = e - (e / ld) * ld;
+  E[e] = (r < k && c < t) ? rademacher(seed, kTagLracK, (uint64_t)c, (uint64_t)r) : 0.0;
+}
+
+// V += H / W
+__global__ void add_div_kernel(int64_t n, int t, const double* __restrict__ H,
+                               const double* __restrict__ W, double* __restrict__ V) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * t) return;
+  V[e] += H[e] / W[e / t];
+}
+
+// b = U / W
+__global__ void div_kernel(int64_t n, const double* __restrict__ U, const double* __restrict__ W,
+                           double* __restrict__ b) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < n) b[e] = U[e] / W[e];
+}
+
+static unsigned blocks_for(int64_t count) {
+  return static_cast<unsigned>((count + 255) / 256);
+}
+
+// ---------------------------------------------------------------- drivers
+static int padded_rank(int k) { return (k + 15) / 16 * 16; }
+
+Status lrac_build(Model& M, int k) {
+  if (k < 1) return Status::invalid("lrac_rank must be positive");
+  if (k > M.n) k = static_cast<int>(M.n);
+  if (M.lrac_ready && M.lrac_k == k) return Status::ok();
+  const int K = padded_rank(k);
+  const int64_t n = M.n;
+  VL_TRY(M.lrac_L.reserve(static_cast<size_t>(n) * K));
+  VL_TRY(M.lrac_piv.reserve(k + 1));
+  VL_TRY(M.lrac_pval.reserve(k + 1));
+  VL_TRY(M.vec_c.reserve(n));  // residual diagonal
+  const int nb = 512;
+  VL_TRY(M.lrac_part.reserve(static_cast<size_t>(nb) * 2));
+  double* part_v = M.lrac_part.p;
+  int* part_i = reinterpret_cast<int*>(M.lrac_part.p + nb);
+  hipLaunchKernelGGL(pc_init_kernel, dim3(blocks_for(n)), dim3(256), 0, M.stream, n, K,
+                     M.sigma2, M.vec_c.p, M.lrac_L.p, M.lrac_piv.p, M.lrac_pval.p);
+  for (int j = 0; j < k; ++j) {
+    hipLaunchKernelGGL(pc_column_kernel, dim3(nb), dim3(256), 0, M.stream, n, K, j, M.coords,
+                       M.cov, M.sigma2, M.rho, M.lrac_piv.p, M.lrac_pval.p, M.vec_c.p,
+                       M.lrac_L.p, part_v, part_i, M.status);
+    hipLaunchKernelGGL(pc_argmax_kernel, dim3(1), dim3(256), 0, M.stream, nb, part_v, part_i,
+                       j, M.vec_c.p, M.lrac_piv.p, M.lrac_pval.p);
+  }
+  VL_TRY(check_launch("pivoted cholesky"));
+  VL_TRY(sync_stream(M.stream));
+  VL_TRY(read_status(M));
+  M.lrac_k = k;
+  M.lrac_K = K;
+  M.lrac_ready = true;
+  return Status::ok();
+}
+
+// Parts of the K x ldp gram products: one block per 256 CUs' worth of rows.
+static Status gram(Model& M, const double* w, const double* X, int ldx, int t, int ldp,
+                   double* out) {
+  const int K = M.lrac_K;
+  const int64_t n = M.n;
+  int nblk = 512;
+  int64_t rpb = (n + nblk - 1) / nblk;
+  rpb = (rpb + 3) / 4 * 4;
+  nblk = static_cast<int>((n + rpb - 1) / rpb);
+  const int64_t size = static_cast<int64_t>(K) * ldp;
+  VL_TRY(M.lrac_gpart.reserve(static_cast<size_t>(nblk) * size));
+  hipLaunchKernelGGL(gram_kernel, dim3(nblk), dim3(256), 0, M.stream, n, K, rpb, M.lrac_L.p, w, X,
+                     ldx, t, ldp, M.lrac_gpart.p);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(blocks_for(size)), dim3(256), 0, M.stream, nblk,
+                     size, M.lrac_gpart.p, out);
+  return check_launch("gram");
+}
+
+// M = I + L^T W L, its Cholesky factor (in lrac_M) and log det M (device).
+Status lrac_factor(Model& M, const double* W) {
+  const int K = M.lrac_K;
+  VL_TRY(M.lrac_M.reserve(static_cast<size_t>(K) * K + 8));
+  VL_TRY(gram(M, W, M.lrac_L.p, K, K, K, M.lrac_M.p));
+  hipLaunchKernelGGL(add_identity_kernel, dim3(1), dim3(K), 0, M.stream, K, M.lrac_M.p);
+  hipLaunchKernelGGL(small_cholesky_kernel, dim3(1), dim3(256), sizeof(double) * K * K,
+                     M.stream, K, M.lrac_M.p, M.lrac_M.p + K * K, M.status);
+  return check_launch("lrac factor");
+}
+
+// Z = P_LRAC^{-1} R over t columns.
+static Status lrac_precond(Model& M, const double* W, const double* R, double* Z, int t) {
+  const int K = M.lrac_K;
+  const int ldp = (t + 15) / 16 * 16;
+  VL_TRY(M.lrac_S.reserve(static_cast<size_t>(K) * ldp));
+  VL_TRY(gram(M, W, R, t, t, ldp, M.lrac_S.p));
+  hipLaunchKernelGGL(chol_solve_kernel, dim3((t + 63) / 64), dim3(64), 0, M.stream, K,
+                     M.lrac_M.p, t, ldp, M.lrac_S.p);
+  const int64_t tiles = ((M.n + 15) / 16) * ((t + 15) / 16);
+  hipLaunchKernelGGL(panel_kernel, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, M.stream,
+                     M.n, K, M.lrac_L.p, M.lrac_S.p, ldp, t, 0, W, R, 0ull, Z);
+  return check_launch("lrac precond");
+}
+
+// V = Sigma~ H + H / W, Sigma~ H = B^{-1} (D o (B^{-T} H)).
+static Status sigma_apply(Model& M, const double* H, double* V, double* Tmp, int t,
+                          const double* W) {
+  VL_TRY(trsm_bt_slot(M, H, Tmp, t, false, 0));
+  VL_TRY(trsm_b_slot(M, Tmp, V, t, M.dval.p, false, 1));
+  if (W) {
+    hipLaunchKernelGGL(add_div_kernel, dim3(blocks_for(M.n * t)), dim3(256), 0, M.stream, M.n, t,
+                       H, W, V);
+    VL_TRY(check_launch("add div"));
+  }
+  return Status::ok();
+}
+
+CgOps lrac_ops(const double* W) {
+  CgOps ops;
+  ops.apply = [W](Model& M, const double* H, double* V, double* Tmp, int t) -> Status {
+    return sigma_apply(M, H, V, Tmp, t, W);
+  };
+  ops.precond = [W](Model& M, const double* R, double* Z, double* Y, int t) -> Status {
+    (void)Y;
+    return lrac_precond(M, W, R, Z, t);
+  };
+  return ops;
+}
+
+// One Newton step of eq. (pcls2): (Sigma~ + W^{-1}) (W b') = Sigma~ rhs.
+Status lrac_newton_solve(Model& M, const vl_opts& o, const double* rhs, double* b_out) {
+  const int64_t n = M.n;
+  VL_TRY(M.vec_d.reserve(n));
+  VL_TRY(M.vec_e.reserve(n));
+  VL_TRY(lrac_factor(M, M.W.p));
+  VL_TRY(sigma_apply(M, rhs, M.vec_d.p, M.vec_e.p, 1, nullptr));
+  CgOps ops = lrac_ops(M.W.p);
+  VL_TRY(cg_solve(M, M.cg1, ops, 1, M.vec_d.p, o.cg_tol, o.max_cg, false));
+  hipLaunchKernelGGL(div_kernel, dim3(blocks_for(n)), dim3(256), 0, M.stream, n, M.cg1.U.p,
+                     M.W.p, b_out);
+  return check_launch("lrac newton");
+}
+
+// SLQ with P_LRAC: probes z = L eps_k + W^{-1/2} eps_n, CG on Sigma~ + W^{-1};
+// returns log det M (= sum log W + log det P) on the host.
+Status lrac_slq(Model& M, const vl_opts& o, double* logdet_fixed) {
+  const int64_t n = M.n;
+  const int t = o.num_probes;
+  const int K = M.lrac_K;
+  VL_TRY(lrac_factor(M, M.W.p));
+  const int ldp = (t + 15) / 16 * 16;
+  VL_TRY(M.lrac_S.reserve(static_cast<size_t>(K) * ldp));
+  hipLaunchKernelGGL(lrac_probe_k_kernel, dim3(blocks_for((int64_t)K * ldp)), dim3(256), 0,
+                     M.stream, K, M.lrac_k, t, ldp, o.seed, M.lrac_S.p);
+  VL_TRY(M.rhs_blk.reserve(static_cast<size_t>(n) * t));
+  const int64_t tiles = ((n + 15) / 16) * ((t + 15) / 16);
+  hipLaunchKernelGGL(panel_kernel, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, M.stream, n,
+                     K, M.lrac_L.p, M.lrac_S.p, ldp, t, 1, M.W.p, nullptr, o.seed,
+                     M.rhs_blk.p);
+  VL_TRY(check_launch("lrac probes"));
+  double ld = 0.0;
+  VL_HIP(hipMemcpyAsync(&ld, M.lrac_M.p + K * K, sizeof(double), hipMemcpyDeviceToHost,
+                        M.stream));
+  CgOps ops = lrac_ops(M.W.p);
+  VL_TRY(cg_solve(M, M.cg, ops, t, M.rhs_blk.p, o.cg_tol, o.max_cg, false));
+  *logdet_fixed = ld;
+  return Status::ok();
+}
+
+}  // namespace vl

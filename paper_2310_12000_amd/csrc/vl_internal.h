@@ -199,7 +199,13 @@ struct Model {
   CgState cg1;  // single-column solves
   DevBuf<double> red_part;  // partial sums of reductions
   DevBuf<double> red_out;
-  DevBuf<double> vec_a, vec_b, vec_c, vec_d, dWv;  // n-length scratch vectors
+  DevBuf<double> vec_a, vec_b, vec_c, vec_d, vec_e, dWv;  // n-length scratch vectors
+  // LRAC preconditioner: pivoted Cholesky factor (n x lrac_K, zero columns
+  // past lrac_k), pivots, I + L^T W L (factored in place; log det after it)
+  bool lrac_ready = false;
+  int lrac_k = 0, lrac_K = 0;
+  DevBuf<double> lrac_L, lrac_pval, lrac_part, lrac_gpart, lrac_M, lrac_S;
+  DevBuf<int> lrac_piv;
   DevBuf<double> rhs_blk;  // n x t right-hand sides of block solves
   DevBuf<int> counter;     // dynamic work counters of sync-free kernels
   double* host_pin = nullptr;  // pinned host scalars (64 doubles)

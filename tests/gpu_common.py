@@ -41,12 +41,12 @@ def opts_pair(P, **kw):
     return o, g
 
 
-def oracle_mode_matching(model, y, F, lik, aux, opts, gpu_newton_cg):
+def oracle_mode_matching(model, y, F, lik, aux, opts, gpu_newton_cg, L=None):
     """Oracle mode; replays the device's Newton/CG counts if they differ."""
-    b, W, st = OL.find_mode(model, y, F, lik, aux, opts)
+    b, W, st = OL.find_mode(model, y, F, lik, aux, opts, L=L)
     if list(st["cg_iters"]) == list(gpu_newton_cg):
         return b, W, st, False
-    b, W, st = OL.find_mode(model, y, F, lik, aux, opts,
+    b, W, st = OL.find_mode(model, y, F, lik, aux, opts, L=L,
                             replay={"newton_iters": len(gpu_newton_cg),
                                     "cg_iters": list(gpu_newton_cg)})
     return b, W, st, True

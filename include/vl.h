@@ -131,7 +131,11 @@ vl_status vl_build_vecchia(const double* coords, int64_t n, int m, int cov,
  * reusing neighbour sets and B^T structure.  Invalidates the mode. */
 vl_status vl_set_theta(vl_model* h, const double* theta_host);
 
-/* Newton mode finding (eq. newton) from b = 0.  With o->precond = VL_PREC_VADU
+/* Newton mode finding (eq. newton) from b = 0, each step halved (at most 30
+ * times) while Psi(b) = log p(y|F+b) - b^T Sigma~^{-1} b / 2 falls below
+ * Psi_old - 1e-12 |Psi_old| (a decrease beyond rounding);
+ * stops when |Psi_new - Psi_old| <= o->newton_tol |Psi_old| or when no halving
+ * increases Psi (b is kept).  With o->precond = VL_PREC_VADU
  * each step solves (W + Sigma~^{-1}) b' = W b + g by CG preconditioned with
  * P_VADU (eq. pcls1); with VL_PREC_LRAC it solves (Sigma~ + W^{-1}) (W b') =
  * Sigma~ (W b + g) (eq. pcls2) preconditioned with P_LRAC = L_k L_k^T + W^{-1}
@@ -191,6 +195,7 @@ vl_status vl_predict(vl_model* h, const double* coords_p, int64_t n_p,
  *  18 Cholesky factor of I + L^T W L with the W of the last LRAC call,
  *     double K x K lower (row-major), K = k rounded up to 16: rows and
  *     columns past k belong to the identity
+ *  19 step halvings of each Newton iteration of the last vl_find_mode, int32
  * dst is a device pointer; `bytes` must equal the size of the array.
  * Synchronises. */
 vl_status vl_export(vl_model* h, int which, void* dst, size_t bytes);

@@ -323,6 +323,10 @@ class Opts:
             setattr(self, k, v)
 
 
+MAX_HALVINGS = 30
+HALVING_SLACK = 1e-12
+
+
 def psi(model, y, F, b, lik, aux):
     """Psi(b) = log p(y | F + b) - b^T Sigma~^{-1} b / 2."""
     Bb = model.B @ b
@@ -331,7 +335,11 @@ def psi(model, y, F, b, lik, aux):
 
 def find_mode(model, y, F, lik, aux, opts, replay=None, L=None):
     """Mode b* of p(y|F+b) p~(b) by Newton's method, eq. (newton):
-    b_{t+1} = (W + Sigma~^{-1})^{-1} (W b_t + d log p / d b), each solve by PCG.
+    b_{t+1} = (W + Sigma~^{-1})^{-1} (W b_t + d log p / d b), each solve by PCG,
+    with the step halved (at most MAX_HALVINGS times) while Psi falls below
+    Psi_old - HALVING_SLACK |Psi_old| (a real decrease, not rounding); stop when
+    the relative change of Psi is at most newton_tol, or when no halving
+    restores Psi (b is then kept).
 
     replay: optional dict {"newton_iters": int, "cg_iters": [int, ...]} that
     fixes the iteration counts.  Returns (b, W, stats)."""
@@ -340,6 +348,7 @@ def find_mode(model, y, F, lik, aux, opts, replay=None, L=None):
     b = np.zeros(n)
     psi_old = psi(model, y, F, b, lik, aux)
     cg_iters = []
+    halving_log = []
     newton_iters = 0
     max_newton = opts.max_newton if replay is None else replay["newton_iters"]
     if opts.precond == PRECOND_LRAC and L is None:
@@ -361,14 +370,26 @@ def find_mode(model, y, F, lik, aux, opts, replay=None, L=None):
                       opts.max_cg, forced)
             b_new = res.U / W
         cg_iters.append(int(res.iters[0]))
-        b = b_new
         newton_iters += 1
-        psi_new = psi(model, y, F, b, lik, aux)
+        # step halving while the objective does not increase (the paper gives
+        # no step control; full steps diverge e.g. for Poisson counts)
+        psi_new = psi(model, y, F, b_new, lik, aux)
+        halvings = 0
+        max_h = MAX_HALVINGS if replay is None else replay.get("halvings", [0] * max_newton)[it]
+        floor = psi_old - HALVING_SLACK * abs(psi_old)  # rounding-level changes accepted
+        while halvings < max_h and (replay is not None or not (psi_new >= floor)):
+            b_new = b + 0.5 * (b_new - b)
+            psi_new = psi(model, y, F, b_new, lik, aux)
+            halvings += 1
+        halving_log.append(halvings)
+        if replay is None and not (psi_new >= floor):
+            break  # no increase even after halving: b is the mode to rounding
+        b = b_new
         if replay is None and abs(psi_new - psi_old) <= opts.newton_tol * abs(psi_old):
             break
         psi_old = psi_new
     W = lik_W(lik, y, F + b, aux)
-    return b, W, {"newton_iters": newton_iters, "cg_iters": cg_iters}
+    return b, W, {"newton_iters": newton_iters, "cg_iters": cg_iters, "halvings": halving_log}
 
 
 # ----------------------------------------------------------------------------

@@ -45,6 +45,7 @@ static Status compute_factor(Model& M) {
   VL_TRY(check_launch("recip"));
   VL_TRY(refresh_transpose_values(M));
   VL_TRY(refresh_head_values(M));
+  ++M.factor_version;
   VL_TRY(sync_stream(M.stream));
   return read_status(M);
 }
@@ -136,6 +137,7 @@ static int64_t export_count(Model& M, int which) {
     case 16: return M.lrac_ready ? M.n * M.lrac_k : -1;
     case 17: return M.lrac_ready ? M.lrac_k : -1;
     case 18: return M.lrac_ready ? static_cast<int64_t>(M.lrac_K) * M.lrac_K : -1;
+    case 19: return static_cast<int64_t>(M.newton_halvings.size());
     default: return -1;
   }
 }
@@ -143,7 +145,8 @@ static int64_t export_count(Model& M, int which) {
 static Status do_export(Model& M, int which, void* dst, size_t bytes) {
   const int64_t cnt = export_count(M, which);
   if (cnt < 0) return Status::make(VL_ERR_STATE, "array not available");
-  const bool is_int = (which == 0 || which == 9 || which == 10 || which == 13 || which == 17);
+  const bool is_int = (which == 0 || which == 9 || which == 10 || which == 13 || which == 17 ||
+                       which == 19);
   const size_t need = static_cast<size_t>(cnt) * (is_int ? sizeof(int) : sizeof(double));
   if (bytes != need) return Status::invalid("export size mismatch");
   if (need == 0) return Status::ok();
@@ -176,6 +179,7 @@ static Status do_export(Model& M, int which, void* dst, size_t bytes) {
     }
     case 17: return copy_out(M, dst, M.lrac_piv.p, need, false);
     case 18: return copy_out(M, dst, M.lrac_M.p, need, false);
+    case 19: return copy_out(M, dst, M.newton_halvings.data(), need, true);
     default: return Status::invalid("unknown export");
   }
 }

@@ -137,6 +137,9 @@ static Status laplace_terms(Model& M, const double* b, const double* W, double o
   return host_sums(M, M.red_part.p, g.nchunk, 4, out);
 }
 
+// FP64 residual corrections of the mixed-precision form at most
+constexpr int kMaxRefine = 3;
+
 // ------------------------------------------------------- VADU operators
 CgOps vadu_ops(const double* W, const double* sdiag) {
   CgOps ops;
@@ -154,6 +157,16 @@ CgOps vadu_ops(const double* W, const double* sdiag) {
 }
 
 // ------------------------------------------------------------------ mode
+constexpr int kMaxHalvings = 30;
+constexpr double kHalvingSlack = 1e-12;  // a decrease below this is rounding
+
+// b = b_old + (b - b_old) / 2
+__global__ void halve_step_kernel(int64_t n, const double* __restrict__ b_old,
+                                  double* __restrict__ b) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = b_old[i] + 0.5 * (b[i] - b_old[i]);
+}
+
 Status find_mode(Model& M, const vl_opts& o, vl_stats* st) {
   const int64_t n = M.n;
   VL_TRY(M.mode.reserve(n));
@@ -172,8 +185,11 @@ Status find_mode(Model& M, const vl_opts& o, vl_stats* st) {
   bool cg_cap = false;
   const bool lrac = o.precond == VL_PREC_LRAC;
   if (lrac) VL_TRY(lrac_build(M, o.lrac_rank));
+  VL_TRY(M.mode_old.reserve(n));
+  M.newton_halvings.clear();
   for (; it < o.max_newton;) {
     VL_TRY(lik_rows(M, M.mode.p, M.g.p, M.W.p, M.vec_a.p, M.vec_b.p, nullptr, nullptr));
+    VL_TRY(copy_d2d(M.mode_old.p, M.mode.p, sizeof(double) * n, M.stream));
     if (lrac) {
       // eq. (pcls2): (Sigma~ + W^{-1}) (W b') = Sigma~ (W b + g)
       VL_TRY(lrac_newton_solve(M, o, M.vec_a.p, M.mode.p));
@@ -190,8 +206,25 @@ Status find_mode(Model& M, const vl_opts& o, vl_stats* st) {
     if (ci >= o.max_cg) cg_cap = true;
     ++it;
     VL_TRY(laplace_terms(M, M.mode.p, nullptr, terms));
-    const double psi_new = terms[0] - 0.5 * terms[1];
-    if (!std::isfinite(psi_new)) return Status::make(VL_ERR_NONFINITE, "Newton objective is not finite");
+    double psi_new = terms[0] - 0.5 * terms[1];
+    // step halving while Psi does not increase (the paper gives no step
+    // control; full steps diverge e.g. for Poisson counts)
+    int halvings = 0;
+    const double floor_psi = psi_old - kHalvingSlack * std::fabs(psi_old);  // rounding accepted
+    while (halvings < kMaxHalvings && !(psi_new >= floor_psi)) {
+      hipLaunchKernelGGL(halve_step_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                         M.stream, n, M.mode_old.p, M.mode.p);
+      VL_TRY(check_launch("halve step"));
+      VL_TRY(laplace_terms(M, M.mode.p, nullptr, terms));
+      psi_new = terms[0] - 0.5 * terms[1];
+      ++halvings;
+    }
+    M.newton_halvings.push_back(halvings);
+    if (!(psi_new >= floor_psi)) {  // no increase even after halving: keep b
+      VL_TRY(copy_d2d(M.mode.p, M.mode_old.p, sizeof(double) * n, M.stream));
+      converged = true;
+      break;
+    }
     if (std::fabs(psi_new - psi_old) <= o.newton_tol * std::fabs(psi_old)) {
       converged = true;
       break;
@@ -439,7 +472,18 @@ Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, Nl
     // z_i = B^T ((W + D^{-1})^{1/2} o eps_i), Cov(z_i) = P_VADU
     VL_TRY(spmm_bt_probe(M, M.rhs_blk.p, t, M.vec_a.p, o.seed, kTagSlq, 0, 0, nullptr, 0, 0));
     CgOps ops = vadu_ops(M.W.p, M.vec_b.p);
-    VL_TRY(cg_solve(M, M.cg, ops, t, M.rhs_blk.p, o.cg_tol, o.max_cg, grad != nullptr));
+    if (o.precision == VL_MIXED) {
+      // FP32 block PCG (its Lanczos coefficients give the quadrature), the
+      // solutions refined in FP64 for the gradient
+      MixedInfo mi;
+      VL_TRY(block_solve_mixed(M, M.cg, ops, vadu_ops_f32(M.W.p, M.vec_b.p), t, M.rhs_blk.p,
+                               o.cg_tol, o.max_cg, grad != nullptr, grad ? kMaxRefine : 0,
+                               &mi));
+      M.last_refinements = mi.refinements;
+      M.last_final_residual = mi.final_residual;
+    } else {
+      VL_TRY(cg_solve(M, M.cg, ops, t, M.rhs_blk.p, o.cg_tol, o.max_cg, grad != nullptr));
+    }
   }
   M.last_block_iters = M.cg.host_iters;
   VL_TRY(M.red_out.reserve(2 * t + 64));
@@ -593,7 +637,15 @@ Status predict(Model& M, const double* coords_p, int64_t np, const double* Fp,
     // z3 = W^{1/2} z1 + B^T (D^{-1/2} o z2), z1, z2 standard normal
     VL_TRY(spmm_bt_probe(M, M.rhs_blk.p, tt, M.vec_c.p, o.seed, kTagPredZ2, c0, 1, M.vec_a.p,
                          kTagPredZ1, 1));
-    VL_TRY(cg_solve(M, M.cg, ops, tt, M.rhs_blk.p, o.pred_cg_tol, o.max_cg, false));
+    if (o.precision == VL_MIXED) {
+      MixedInfo mi;
+      VL_TRY(block_solve_mixed(M, M.cg, ops, vadu_ops_f32(M.W.p, M.vec_b.p), tt, M.rhs_blk.p,
+                               o.pred_cg_tol, o.max_cg, false, kMaxRefine, &mi));
+      M.last_refinements = mi.refinements;
+      M.last_final_residual = mi.final_residual;
+    } else {
+      VL_TRY(cg_solve(M, M.cg, ops, tt, M.rhs_blk.p, o.pred_cg_tol, o.max_cg, false));
+    }
     for (int v : M.cg.host_iters) {
       cg_max = v > cg_max ? v : cg_max;
       M.last_block_iters.push_back(v);

@@ -50,45 +50,63 @@ Status reduce_chunks(hipStream_t s, const double* part, int nchunk, int t, doubl
 }
 
 // ---------------------------------------------------------- CG kernels
-__global__ __launch_bounds__(256) void cg_init_kernel(ChunkGrid g, const double* __restrict__ rhs,
-                                                      double* __restrict__ U,
-                                                      double* __restrict__ R,
-                                                      double* __restrict__ Y,
-                                                      double* __restrict__ Z, int* counter) {
+// The vector kernels are templated on the storage type T of the n x t blocks
+// (double; float in the mixed-precision form); every sum is accumulated in
+// double.  Y and Z (the preconditioner's outputs) are pre-filled with the
+// sentinel of the sync-free solves when given.
+template <typename T>
+__device__ __forceinline__ T sentinel_of();
+template <>
+__device__ __forceinline__ double sentinel_of<double>() {
+  return sentinel();
+}
+template <>
+__device__ __forceinline__ float sentinel_of<float>() {
+  return sentinel_f();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cg_init_kernel(ChunkGrid g, const T* __restrict__ rhs,
+                                                      T* __restrict__ U, T* __restrict__ R,
+                                                      T* __restrict__ Y, T* __restrict__ Z,
+                                                      int* counter) {
   CHUNK_LOOP_BEGIN(g)
   const int64_t o = i * g.t + c;
-  U[o] = 0.0;
+  U[o] = T(0);
   R[o] = rhs[o];
-  Y[o] = sentinel();
-  Z[o] = sentinel();
+  if (Y) {
+    Y[o] = sentinel_of<T>();
+    Z[o] = sentinel_of<T>();
+  }
   CHUNK_LOOP_END
-  if (blockIdx.x == 0 && blockIdx.y == 0) reset_counters(counter);
+  if (counter && blockIdx.x == 0 && blockIdx.y == 0) reset_counters(counter);
 }
 
 // H = Z (and Z0 = Z); partial sums of r.z
-__global__ __launch_bounds__(256) void cg_init2_kernel(ChunkGrid g, const double* __restrict__ R,
-                                                       const double* __restrict__ Z,
-                                                       double* __restrict__ H,
-                                                       double* __restrict__ Z0,
+template <typename T>
+__global__ __launch_bounds__(256) void cg_init2_kernel(ChunkGrid g, const T* __restrict__ R,
+                                                       const T* __restrict__ Z,
+                                                       T* __restrict__ H, T* __restrict__ Z0,
                                                        double* __restrict__ part) {
   double acc = 0.0;
   CHUNK_LOOP_BEGIN(g)
   const int64_t o = i * g.t + c;
-  const double z = Z[o];
+  const T z = Z[o];
   H[o] = z;
   if (Z0) Z0[o] = z;
-  acc += R[o] * z;
+  acc += static_cast<double>(R[o]) * static_cast<double>(z);
   CHUNK_LOOP_END
   block_colsum(g, acc, part);
 }
 
-__global__ __launch_bounds__(256) void dot_kernel(ChunkGrid g, const double* __restrict__ X,
-                                                  const double* __restrict__ Y,
+template <typename T>
+__global__ __launch_bounds__(256) void dot_kernel(ChunkGrid g, const T* __restrict__ X,
+                                                  const T* __restrict__ Y,
                                                   double* __restrict__ part) {
   double acc = 0.0;
   CHUNK_LOOP_BEGIN(g)
   const int64_t o = i * g.t + c;
-  acc += X[o] * Y[o];
+  acc += static_cast<double>(X[o]) * static_cast<double>(Y[o]);
   CHUNK_LOOP_END
   block_colsum(g, acc, part);
 }
@@ -131,27 +149,29 @@ __global__ void cg_alpha_kernel(int t, int nchunk, const double* __restrict__ pa
 }
 
 // u += alpha h, r -= alpha v; partial ||r||^2; pre-fill solve outputs
+template <typename T>
 __global__ __launch_bounds__(256) void cg_update_ur_kernel(
     ChunkGrid g, const double* __restrict__ alpha, const int* __restrict__ active,
-    const double* __restrict__ H, const double* __restrict__ V, double* __restrict__ U,
-    double* __restrict__ R, double* __restrict__ Y, double* __restrict__ Z,
-    double* __restrict__ part, int* counter) {
+    const T* __restrict__ H, const T* __restrict__ V, T* __restrict__ U, T* __restrict__ R,
+    T* __restrict__ Y, T* __restrict__ Z, double* __restrict__ part, int* counter) {
   double acc = 0.0;
   CHUNK_LOOP_BEGIN(g)
   const int64_t o = i * g.t + c;
-  double r = R[o];
+  T r = R[o];
   if (active[c]) {
-    const double a = alpha[c];
+    const T a = static_cast<T>(alpha[c]);
     U[o] += a * H[o];
     r -= a * V[o];
     R[o] = r;
   }
-  acc += r * r;
-  Y[o] = sentinel();
-  Z[o] = sentinel();
+  acc += static_cast<double>(r) * static_cast<double>(r);
+  if (Y) {
+    Y[o] = sentinel_of<T>();
+    Z[o] = sentinel_of<T>();
+  }
   CHUNK_LOOP_END
   block_colsum(g, acc, part);
-  if (blockIdx.x == 0 && blockIdx.y == 0) reset_counters(counter);
+  if (counter && blockIdx.x == 0 && blockIdx.y == 0) reset_counters(counter);
 }
 
 // beta = r_new.z_new / r.z; records beta; stopping test on ||r||_2
@@ -194,15 +214,16 @@ __global__ void cg_beta_kernel(int t, int nchunk, const double* __restrict__ par
   }
 }
 
+template <typename T>
 __global__ __launch_bounds__(256) void cg_update_h_kernel(ChunkGrid g,
                                                           const double* __restrict__ beta,
                                                           const int* __restrict__ active,
-                                                          const double* __restrict__ Z,
-                                                          double* __restrict__ H) {
+                                                          const T* __restrict__ Z,
+                                                          T* __restrict__ H) {
   CHUNK_LOOP_BEGIN(g)
   if (active[c]) {
     const int64_t o = i * g.t + c;
-    H[o] = Z[o] + beta[c] * H[o];
+    H[o] = Z[o] + static_cast<T>(beta[c]) * H[o];
   }
   CHUNK_LOOP_END
 }
@@ -240,46 +261,54 @@ static Status cg_reserve(Model& M, CgState& S, int t, int lmax, bool keep_z0) {
 
 static dim3 chunk_dims(const ChunkGrid& g) { return dim3(g.nchunk, g.L.slices); }
 
-Status cg_solve(Model& M, CgState& S, const CgOps& ops, int t, const double* rhs, double tol,
-                int max_iter, bool keep_z0) {
+// Storage of the n x t blocks of S as T (a block of n t doubles holds n t
+// floats).
+template <typename T>
+static T* blk(DevBuf<double>& b) {
+  return reinterpret_cast<T*>(b.p);
+}
+
+template <typename T, class Ops>
+static Status cg_run(Model& M, CgState& S, const Ops& ops, int t, const T* rhs, double tol,
+                     int max_iter, bool keep_z0, bool sentinel_fill) {
   if (t <= 0) return Status::invalid("t must be positive");
   if (max_iter < 1) max_iter = 1;
   VL_TRY(cg_reserve(M, S, t, max_iter, keep_z0));
   hipStream_t s = M.stream;
   ChunkGrid g = ChunkGrid::of(M.n, t);
   const dim3 cg_grid = chunk_dims(g);
-  int* cnt = M.counter.p;
+  int* cnt = sentinel_fill ? M.counter.p : nullptr;
+  T *U = blk<T>(S.U), *R = blk<T>(S.R), *Z = blk<T>(S.Z), *H = blk<T>(S.H), *V = blk<T>(S.V),
+    *Tmp = blk<T>(S.Tmp), *Y = blk<T>(S.Y);
+  T* Yf = sentinel_fill ? Y : nullptr;
+  T* Zf = sentinel_fill ? Z : nullptr;
   // u_0 = 0, r_0 = rhs, z_0 = P^{-1} r_0, h_0 = z_0
-  hipLaunchKernelGGL(cg_init_kernel, cg_grid, dim3(256), 0, s, g, rhs, S.U.p, S.R.p, S.Y.p,
-                     S.Z.p, cnt);
-  VL_TRY(ops.precond(M, S.R.p, S.Z.p, S.Y.p, t));
-  hipLaunchKernelGGL(cg_init2_kernel, cg_grid, dim3(256), 0, s, g, S.R.p, S.Z.p, S.H.p,
-                     keep_z0 ? S.Z0.p : nullptr, S.part_a.p);
+  hipLaunchKernelGGL(cg_init_kernel<T>, cg_grid, dim3(256), 0, s, g, rhs, U, R, Yf, Zf, cnt);
+  VL_TRY(ops.precond(M, R, Z, Y, t));
+  hipLaunchKernelGGL(cg_init2_kernel<T>, cg_grid, dim3(256), 0, s, g, R, Z, H,
+                     keep_z0 ? blk<T>(S.Z0) : nullptr, S.part_a.p);
   hipLaunchKernelGGL(cg_start_kernel, dim3(1), dim3(256), 0, s, t, g.nchunk, S.part_a.p,
                      S.rz.p, S.r0z0.p, S.active.p, S.iters.p, S.num_active.p);
   VL_TRY(check_launch("cg start"));
-  int iters_done = 0;
   for (int it = 0; it < max_iter; ++it) {
-    VL_TRY(ops.apply(M, S.H.p, S.V.p, S.Tmp.p, t));
-    hipLaunchKernelGGL(dot_kernel, cg_grid, dim3(256), 0, s, g, S.H.p, S.V.p, S.part_a.p);
+    VL_TRY(ops.apply(M, H, V, Tmp, t));
+    hipLaunchKernelGGL(dot_kernel<T>, cg_grid, dim3(256), 0, s, g, H, V, S.part_a.p);
     hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(256), 0, s, t, g.nchunk, S.part_a.p,
                        S.rz.p, S.alpha.p, S.active.p, S.iters.p, S.hist_a.p, M.status);
-    hipLaunchKernelGGL(cg_update_ur_kernel, cg_grid, dim3(256), 0, s, g, S.alpha.p, S.active.p,
-                       S.H.p, S.V.p, S.U.p, S.R.p, S.Y.p, S.Z.p, S.part_b.p, cnt);
-    VL_TRY(ops.precond(M, S.R.p, S.Z.p, S.Y.p, t));
-    hipLaunchKernelGGL(dot_kernel, cg_grid, dim3(256), 0, s, g, S.R.p, S.Z.p, S.part_a.p);
+    hipLaunchKernelGGL(cg_update_ur_kernel<T>, cg_grid, dim3(256), 0, s, g, S.alpha.p,
+                       S.active.p, H, V, U, R, Yf, Zf, S.part_b.p, cnt);
+    VL_TRY(ops.precond(M, R, Z, Y, t));
+    hipLaunchKernelGGL(dot_kernel<T>, cg_grid, dim3(256), 0, s, g, R, Z, S.part_a.p);
     hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(256), 0, s, t, g.nchunk, S.part_a.p,
                        S.part_b.p, tol, max_iter, S.rz.p, S.beta.p, S.active.p, S.iters.p,
                        S.hist_b.p, S.num_active.p, M.status);
-    hipLaunchKernelGGL(cg_update_h_kernel, cg_grid, dim3(256), 0, s, g, S.beta.p, S.active.p,
-                       S.Z.p, S.H.p);
+    hipLaunchKernelGGL(cg_update_h_kernel<T>, cg_grid, dim3(256), 0, s, g, S.beta.p, S.active.p,
+                       Z, H);
     VL_TRY(check_launch("cg iteration"));
     VL_HIP(hipMemcpyAsync(M.host_pin, S.num_active.p, sizeof(int), hipMemcpyDeviceToHost, s));
     VL_TRY(sync_stream(s));
-    iters_done = it + 1;
     if (*reinterpret_cast<int*>(M.host_pin) == 0) break;
   }
-  (void)iters_done;
   S.host_iters.resize(t);
   VL_HIP(hipMemcpyAsync(S.host_iters.data(), S.iters.p, sizeof(int) * t, hipMemcpyDeviceToHost,
                         s));
@@ -287,9 +316,19 @@ Status cg_solve(Model& M, CgState& S, const CgOps& ops, int t, const double* rhs
   return read_status(M);
 }
 
+Status cg_solve(Model& M, CgState& S, const CgOps& ops, int t, const double* rhs, double tol,
+                int max_iter, bool keep_z0) {
+  return cg_run<double>(M, S, ops, t, rhs, tol, max_iter, keep_z0, true);
+}
+
+Status cg_solve_f32(Model& M, CgState& S, const CgOpsF& ops, int t, const float* rhs,
+                    double tol, int max_iter, bool keep_z0) {
+  return cg_run<float>(M, S, ops, t, rhs, tol, max_iter, keep_z0, false);
+}
+
 Status dot_cols(Model& M, const double* X, const double* Y, int t, double* part, double* out) {
   ChunkGrid g = ChunkGrid::of(M.n, t);
-  hipLaunchKernelGGL(dot_kernel, chunk_dims(g), dim3(256), 0, M.stream, g, X, Y, part);
+  hipLaunchKernelGGL(dot_kernel<double>, chunk_dims(g), dim3(256), 0, M.stream, g, X, Y, part);
   return reduce_chunks(M.stream, part, g.nchunk, t, out);
 }
 

@@ -77,6 +77,14 @@ struct DevBuf {
     p = nullptr;
     count = 0;
   }
+  void swap(DevBuf& o) {
+    T* q = p;
+    p = o.p;
+    o.p = q;
+    const size_t c = count;
+    count = o.count;
+    o.count = c;
+  }
 };
 
 struct GridGeom {
@@ -146,6 +154,7 @@ struct Model {
   DevBuf<int> bt_ptr, bt_col, bt_src;
   DevBuf<double> bt_val;
   DevBuf<float> bval_f, bt_val_f;  // FP32 copies for the mixed-precision form
+  int64_t factor_version = 0, f32_version = -1;  // FP32 copies made at factor_version
 
   // head rows solved in LDS (level schedules for both directions)
   int head_rows = 0, head_nlev_f = 0, head_nlev_b = 0;
@@ -182,14 +191,17 @@ struct Model {
   bool has_mode = false;
   int lik = 0;
   double aux = 0.0;
-  DevBuf<double> y, F, mode, W, g;
+  DevBuf<double> y, F, mode, W, g, mode_old;
 
   // diagnostics
   DevBuf<int> status_buf;
   int* status = nullptr;
   std::vector<int> newton_cg_iters;
+  std::vector<int> newton_halvings;  // step halvings per Newton iteration
   std::vector<int> last_block_iters;
   std::vector<double> last_quad, last_r0z0;
+  int last_refinements = 0;          // mixed form: FP64 corrections of the last solve
+  double last_final_residual = 0.0;  // mixed form: its largest FP64 residual norm
   DevBuf<int> pred_nbr;
   DevBuf<double> pred_bval, pred_dval;
   int64_t last_np = 0;
@@ -197,6 +209,9 @@ struct Model {
   // reusable workspaces
   CgState cg;
   CgState cg1;  // single-column solves
+  CgState cgm;  // refinement solves of the mixed-precision form
+  DevBuf<float> mx_rhs;           // n x t FP32 right-hand side / residual
+  DevBuf<double> mx_a, mx_b;      // n x t FP64 operator output and scratch
   DevBuf<double> red_part;  // partial sums of reductions
   DevBuf<double> red_out;
   DevBuf<double> vec_a, vec_b, vec_c, vec_d, vec_e, dWv;  // n-length scratch vectors

@@ -46,7 +46,7 @@ EXPORT = {
     "pred_nbr": (13, torch.int32), "pred_bval": (14, torch.float64),
     "pred_D": (15, torch.float64),
     "lrac_L": (16, torch.float64), "lrac_piv": (17, torch.int32),
-    "lrac_chol": (18, torch.float64),
+    "lrac_chol": (18, torch.float64), "newton_halvings": (19, torch.int32),
 }
 
 

@@ -41,12 +41,17 @@ def opts_pair(P, **kw):
     return o, g
 
 
-def oracle_mode_matching(model, y, F, lik, aux, opts, gpu_newton_cg, L=None):
-    """Oracle mode; replays the device's Newton/CG counts if they differ."""
+def oracle_mode_matching(model, y, F, lik, aux, opts, gpu_newton_cg, L=None, gpu_halvings=None):
+    """Oracle mode; replays the device's Newton/CG (and step-halving) counts if
+    they differ."""
     b, W, st = OL.find_mode(model, y, F, lik, aux, opts, L=L)
-    if list(st["cg_iters"]) == list(gpu_newton_cg):
+    same = list(st["cg_iters"]) == list(gpu_newton_cg)
+    if gpu_halvings is not None:
+        same = same and list(st["halvings"]) == list(gpu_halvings)
+    if same:
         return b, W, st, False
-    b, W, st = OL.find_mode(model, y, F, lik, aux, opts, L=L,
-                            replay={"newton_iters": len(gpu_newton_cg),
-                                    "cg_iters": list(gpu_newton_cg)})
+    replay = {"newton_iters": len(gpu_newton_cg), "cg_iters": list(gpu_newton_cg)}
+    if gpu_halvings is not None:
+        replay["halvings"] = list(gpu_halvings)
+    b, W, st = OL.find_mode(model, y, F, lik, aux, opts, L=L, replay=replay)
     return b, W, st, True

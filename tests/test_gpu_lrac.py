@@ -36,6 +36,7 @@ def fit(P):
     g = P.VecchiaLaplace(dev(w["coords"]), w["m"], w["kind"], (w["sigma2"], w["rho"]))
     mode, st = g.find_mode(dev(w["y"]), dev(w["F"]), w["lik"], None, go)
     out = dict(mode=host(mode), newton_cg=host(g.export("newton_cg_iters")).tolist(),
+               halvings=host(g.export("newton_halvings")).tolist(),
                L=host(g.export("lrac_L")).reshape(w["n"], K_RANK),
                piv=host(g.export("lrac_piv")).astype(np.int64))
     nll, _, nst = g.neg_log_marglik(go)
@@ -75,7 +76,8 @@ def test_lrac_mode(fit):
     Lo = OL.pivoted_cholesky(w["coords"], w["kind"], (w["sigma2"], w["rho"]), K_RANK,
                              pivots=f["piv"])
     b, W, st, replayed = oracle_mode_matching(model, w["y"], w["F"], w["lik"], None, o,
-                                              f["newton_cg"], L=Lo)
+                                              f["newton_cg"], L=Lo,
+                                              gpu_halvings=f["halvings"])
     say(f"newton cg gpu={f['newton_cg']} oracle={st['cg_iters']} replayed={replayed}")
     assert rel_err(f["mode"], b) < TOL
 

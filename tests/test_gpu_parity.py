@@ -116,6 +116,7 @@ def c1_fit(P, c1):
     g = _build(P, w)
     mode, st = g.find_mode(dev(w["y"]), dev(w["F"]), w["lik"], None, go)
     newton_cg = host(g.export("newton_cg_iters")).tolist()
+    halvings = host(g.export("newton_halvings")).tolist()
     nll, grad, nst = g.neg_log_marglik(go, want_grad=True)
     slq_iters = host(g.export("block_iters")).tolist()
     quad = host(g.export("slq_quad"))
@@ -123,7 +124,7 @@ def c1_fit(P, c1):
     W = host(g.export("W"))
     mean, var, pst = g.predict(dev(w["coords_pred"]), dev(w["Fp"]), go)
     pred_iters = host(g.export("block_iters")).tolist()
-    out = dict(mode=host(mode), st=st, newton_cg=newton_cg, nll=nll, grad=grad,
+    out = dict(mode=host(mode), st=st, newton_cg=newton_cg, halvings=halvings, nll=nll, grad=grad,
                slq_iters=slq_iters, quad=quad, r0z0=r0z0, W=W, mean=host(mean),
                var=host(var), pred_iters=pred_iters, opts=o)
     g.close()
@@ -134,7 +135,8 @@ def test_mode(c1, c1_fit):
     w, model = c1
     f = c1_fit
     b, W, st, replayed = oracle_mode_matching(model, w["y"], w["F"], w["lik"], None,
-                                              f["opts"], f["newton_cg"])
+                                              f["opts"], f["newton_cg"],
+                                              gpu_halvings=f["halvings"])
     say(f"newton iters gpu={f['newton_cg']} oracle={st['cg_iters']} replayed={replayed}")
     assert rel_err(f["mode"], b) < TOL
     np.testing.assert_allclose(f["W"], W, rtol=1e-9)

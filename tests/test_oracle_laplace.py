@@ -172,6 +172,24 @@ def test_mode_equals_dense_newton_and_zero_gradient(lik):
     np.testing.assert_allclose(lg(y, F + b), Q @ b, atol=1e-8)
 
 
+def test_step_halving_reaches_the_mode_where_full_newton_diverges():
+    # Poisson counts of a strong field (sigma2 = 4, F = 1): a full first
+    # Newton step from b = 0 overshoots (Psi falls); with step halving the
+    # iteration still reaches the point where d log p / d b = Sigma~^{-1} b.
+    model, y, F = _problem(n=120, m=8, lik=L.LIK_POISSON, seed=21, theta=(4.0, 0.2), F=1.0)
+    opts = L.Opts(cg_tol=1e-12, newton_tol=1e-15, max_newton=200)
+    b0 = np.zeros(model.n)
+    g0 = L.lik_grad(L.LIK_POISSON, y, F)
+    W0 = L.lik_W(L.LIK_POISSON, y, F)
+    A, Pinv = L.vadu_ops(model, W0)
+    full = np.ravel(L.pcg(A, Pinv, W0 * b0 + g0, 1e-12, 1000).U)
+    assert L.psi(model, y, F, full, L.LIK_POISSON, None) < L.psi(model, y, F, b0, L.LIK_POISSON, None)
+    b, W, st = L.find_mode(model, y, F, L.LIK_POISSON, None, opts)
+    assert st["halvings"][0] > 0
+    Q = DR.dense_precision(model.B, model.D)
+    np.testing.assert_allclose(L.lik_grad(L.LIK_POISSON, y, F + b), Q @ b, atol=1e-8)
+
+
 def test_mode_lrac_equals_mode_vadu():
     model, y, F = _problem(n=90, m=6, seed=8)
     o1 = L.Opts(cg_tol=1e-12, newton_tol=1e-14)

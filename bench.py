@@ -22,12 +22,14 @@ sys.path.insert(0, ROOT)
 METRIC = "Laplace marginal-likelihood evals/s at n=1e5,m=20; B-SpMM HBM GB/s; p99 latency"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 KINDS = ("spmm_b", "spmm_bt", "trsm_lower", "trsm_upper", "head_lower", "head_upper",
-         "level_lower", "level_upper")
+         "level_lower", "level_upper", "level_upper_split")
 KERNEL_NAMES = {"spmm_b": "spmm_ell_kernel", "spmm_bt": "spmm_csr_t_kernel",
                 "trsm_lower": "trsm_kernel<lower>", "trsm_upper": "trsm_kernel<upper>",
                 "head_lower": "head_lower_kernel", "head_upper": "head_upper_kernel",
                 "level_lower": "trsm_level_kernel<true>",
-                "level_upper": "trsm_level_kernel<false>, trsm_level_split_kernel"}
+                "level_upper": "trsm_level_kernel<false>",
+                "level_upper_split": "trsm_level_split_kernel"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_n1e5.md")
 
 
 def parse():
@@ -39,6 +41,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="one 512 MiB device-to-device copy before the steps (the known-size "
+                         "kernel that scales the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -69,6 +74,12 @@ def main():
     torch.cuda.synchronize()
 
     ktime = {k: [0.0, 0, 0.0] for k in KINDS}
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(rec, timed=False):
         t0 = time.perf_counter()
@@ -131,7 +142,8 @@ def main():
     ms_d, cnt_d, by_d = ktime[dom]
     ach = by_d / (ms_d * 1e-3) / 1e9 if ms_d > 0 else 0.0
     out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                       "frac": ach / HBM_PEAK_GBS,
+                       "traffic": measured_traffic(KERNEL_NAMES[dom], args.workload),
                        "kernel": KERNEL_NAMES[dom], "launches": cnt_d,
                        "avg_launch_us": 1e3 * ms_d / max(cnt_d, 1),
                        "alg_bytes_per_launch": by_d / max(cnt_d, 1)}
@@ -142,6 +154,22 @@ def main():
                      "launches": cnt_b, "avg_launch_us": 1e3 * ms_b / max(cnt_b, 1)}
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(w, rec[-1], args)
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed PMC summary (FETCH_SIZE
+    + WRITE_SIZE, scaled by the same counters on a copy of known size), or None
+    when no summary covers this kernel and workload."""
+    if workload != "c2_n1e5" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    import re
+    pat = re.compile(r"^- (\S+): ([0-9.eE+-]+) bytes per launch")
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            mm = pat.match(line.strip())
+            if mm and mm.group(1) == kernel:
+                return float(mm.group(2))
+    return None
 
 
 def cpu_baseline(w, it, args):

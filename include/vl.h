@@ -222,7 +222,10 @@ vl_status vl_trsm(vl_model* h, int transpose, const double* X, double* Y, int t)
  *   2  sync-free rows of B Y = X          3  sync-free rows of B^T Y = X
  *   4  LDS head rows of B Y = X           5  LDS head rows of B^T Y = X
  *   6  level-scheduled B Y = X            7  level-scheduled B^T Y = X
- *      (blocks wider than 64 columns; one launch, and one record, per level)
+ *   8  level-scheduled B^T Y = X, levels of long rows (entries split over
+ *      4 waves per row)
+ *      (6-8: blocks wider than 64 columns; one launch, and one record, per
+ *      level)
  * vl_timing_enable resets the records (and synchronises); vl_timing_read
  * synchronises and returns the summed kernel time (ms), the number of
  * launches and the summed algorithmic bytes of the records so far. */

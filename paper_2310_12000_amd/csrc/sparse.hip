@@ -541,13 +541,14 @@ static Status trsm_levels(Model& M, bool lower, const double* X, double* Y, int 
   for (size_t l = 0; l + 1 < lp.size(); ++l) {
     const int rows = lp[l + 1] - lp[l];
     if (rows <= 0) continue;
-    TimedLaunch tl(M, lower ? kTimeLevelLower : kTimeLevelUpper,
+    const bool split = !lower && lnz[l] > 16LL * rows;
+    TimedLaunch tl(M, lower ? kTimeLevelLower : (split ? kTimeLevelUpperSplit : kTimeLevelUpper),
                    12.0 * lnz[l] + 16.0 * rows * t + 4.0 * rows +
                        (lower ? (rowscale ? 8.0 * rows : 0.0) : 8.0 * rows));
     if (lower) {
       hipLaunchKernelGGL(trsm_level_kernel<true>, dim3(rows, gy), dim3(256), 0, M.stream, t,
                          order + lp[l], M.m, nullptr, M.nbr.p, M.bval.p, X, rowscale, Y);
-    } else if (lnz[l] > 16LL * rows) {
+    } else if (split) {
       hipLaunchKernelGGL(trsm_level_split_kernel, dim3(rows, (t + 63) / 64), dim3(256), 0,
                          M.stream, t, order + lp[l], M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, Y);
     } else {

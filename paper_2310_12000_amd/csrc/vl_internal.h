@@ -116,7 +116,8 @@ enum TimedKind : int {
   kTimeHeadUpper = 5, // LDS head rows of B^T Y = X
   kTimeLevelLower = 6, // level-scheduled rows of B Y = X (wide blocks)
   kTimeLevelUpper = 7, // level-scheduled rows of B^T Y = X (wide blocks)
-  kTimeKinds = 8
+  kTimeLevelUpperSplit = 8, // the same for levels of long B^T rows
+  kTimeKinds = 9
 };
 
 struct Timing {

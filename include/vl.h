@@ -226,7 +226,8 @@ vl_status vl_trsm(vl_model* h, int transpose, const double* X, double* Y, int t)
  *      4 waves per row)
  *      (6-8: blocks wider than 64 columns; one launch, and one record, per
  *      level)
- * vl_timing_enable resets the records (and synchronises); vl_timing_read
+ * `enable` is a bit mask of the kinds to record (bit k = kind k; -1 = all,
+ * 0 = off).  vl_timing_enable resets the records (and synchronises); vl_timing_read
  * synchronises and returns the summed kernel time (ms), the number of
  * launches and the summed algorithmic bytes of the records so far. */
 vl_status vl_timing_enable(vl_model* h, int enable);

@@ -400,6 +400,7 @@ vl_status vl_timing_enable(vl_model* h, int enable) {
     if (!h) return vl::Status::invalid("null handle");
     VL_TRY(vl::sync_stream(h->stream));
     h->timing.on = enable != 0;
+    h->timing.mask = static_cast<unsigned>(enable);
     h->timing.used = 0;
     h->timing.recs.clear();
     return vl::Status::ok();

@@ -122,7 +122,8 @@ Status exclusive_scan_int(const int* in, int* out, int64_t count, hipStream_t s)
   return sync_stream(s);  // `sums` is released on return
 }
 
-TimedLaunch::TimedLaunch(Model& M, int kind, double bytes) : M_(M), on_(M.timing.on), ev_(0) {
+TimedLaunch::TimedLaunch(Model& M, int kind, double bytes)
+    : M_(M), on_(M.timing.on && ((M.timing.mask >> kind) & 1u)), ev_(0) {
   if (!on_) return;
   Timing& T = M.timing;
   while (T.pool.size() < T.used + 2) {

@@ -122,6 +122,7 @@ enum TimedKind : int {
 
 struct Timing {
   bool on = false;
+  unsigned mask = 0;  // kinds recorded while on (bit k = kind k)
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   struct Rec {

@@ -231,8 +231,12 @@ TIMED_KINDS = {"spmm_b": 0, "spmm_bt": 1, "trsm_lower": 2, "trsm_upper": 3,
                "level_upper_split": 8}
 
 
-def vl_timing_enable(h, enable=True):
-    _check(lib().vl_timing_enable(h, 1 if enable else 0))
+def vl_timing_enable(h, enable=True, kinds=None):
+    """Record kernel classes `kinds` (names of TIMED_KINDS; None = all)."""
+    mask = 0
+    if enable:
+        mask = -1 if kinds is None else sum(1 << TIMED_KINDS[k] for k in kinds)
+    _check(lib().vl_timing_enable(h, mask))
 
 
 def vl_timing_read(h, kind):

@@ -234,6 +234,59 @@ vl_status vl_timing_enable(vl_model* h, int enable);
 vl_status vl_timing_read(vl_model* h, int kind, double* total_ms, int64_t* launches,
                          double* bytes);
 
+/* ---------------------------------------------------------------------- */
+/* Batching form: many independent problems of different sizes fitted
+ * together.  The problems are packed into one block-diagonal system (each
+ * problem's neighbour sets stay inside its own points), so that every sparse
+ * kernel, CG vector kernel and reduction launch serves all problems; the CG
+ * scalars and the Newton iteration are kept per problem, and each problem's
+ * reductions add its rows in the order of a solo run (vl_build_vecchia +
+ * vl_find_mode + vl_neg_log_marglik on that problem alone gives the same
+ * result up to the rounding of the B^T solve).  The solve path of the packed
+ * system (LDS head + sync-free tail, or one launch per level) is chosen per
+ * block-width class by timing both on the packed system (autotuner). */
+typedef struct vl_batch vl_batch;
+
+typedef struct {
+  const double* coords;    /* device, n x 2, in the problem's ordering        */
+  int64_t n;               /* points, >= 1                                     */
+  int m;                   /* neighbours, 0..31                                */
+  int cov;                 /* vl_cov                                           */
+  double theta[2];         /* sigma2 > 0, range rho > 0                        */
+  const double* y;         /* device, n responses                              */
+  const double* F;         /* device, n offsets (NULL = 0)                     */
+  uint64_t seed;           /* probe seed of this problem (vl_opts.seed of a
+                              solo run)                                        */
+} vl_problem;
+
+/* Build the packed model: per problem neighbour search and factor (Sec. 2.1),
+ * then B^T and the solve schedules of the packed system.  All problems share
+ * the likelihood `lik` (aux_host as for vl_find_mode).  The problem arrays are
+ * copied; the caller keeps ownership.  Synchronises. */
+vl_status vl_batch_create(const vl_problem* problems, int nprob, int lik,
+                          const double* aux_host, void* hip_stream, vl_batch** out);
+
+/* Newton mode finding (eq. newton, VADU, pcls1) and the SLQ negative
+ * log-marginal likelihood (eqs. VLA_loss, logdetsplit, def_SLQ) of every
+ * problem, with o->num_probes probes each (the problems' own seeds; o->seed
+ * is not used).  FP64 and VADU only.  nll_host: host, nprob doubles.
+ * Synchronises. */
+vl_status vl_batch_fit(vl_batch* b, const vl_opts* o, double* nll_host);
+
+/* The mode of problem p after vl_batch_fit into mode_out (device, n_p). */
+vl_status vl_batch_mode(vl_batch* b, int p, double* mode_out);
+
+/* Statistics of problem p of the last fit: newton_iters, cg_iters_max (the
+ * SLQ probes' largest CG count), cg_iters_total (step halvings taken). */
+vl_status vl_batch_stats(vl_batch* b, int p, vl_stats* st);
+
+/* Solve path the autotuner picked for a width class (0: one column, 1: 2..64,
+ * 2: more), 0 = LDS head + sync-free tail, 1 = one launch per level; -1 if
+ * that class was not used yet. */
+int vl_batch_tuned_path(vl_batch* b, int width_class);
+
+void vl_batch_free(vl_batch* b);
+
 /* Release the handle and all its device memory. */
 void vl_free(vl_model* h);
 

@@ -20,9 +20,25 @@ static vl_status fail(const Status& s) {
   return s.code;
 }
 
+vl_status report(const Status& s) { return s.good() ? VL_OK : fail(s); }
+
 __global__ void recip_kernel(int64_t n, const double* __restrict__ d, double* __restrict__ out) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) out[i] = 1.0 / d[i];
+}
+
+// D^{-1} and the copies of the B values (B^T, head, FP32) after a factor.
+Status finish_factor(Model& M) {
+  const int64_t n = M.n;
+  const int tb = 256;
+  hipLaunchKernelGGL(recip_kernel, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, M.stream,
+                     n, M.dval.p, M.dinv.p);
+  VL_TRY(check_launch("recip"));
+  VL_TRY(refresh_transpose_values(M));
+  VL_TRY(refresh_head_values(M));
+  ++M.factor_version;
+  VL_TRY(sync_stream(M.stream));
+  return read_status(M);
 }
 
 // A_i, D_i (and derivatives) at the model's theta; refresh B^T values.
@@ -39,15 +55,7 @@ static Status compute_factor(Model& M) {
   }
   VL_TRY(factor_rows(M, nullptr, n, M.nbr.p, M.bval.p, M.dval.p, M.deriv, M.dbval_rho.p,
                      M.dd_sigma2.p, M.dd_rho.p));
-  const int tb = 256;
-  hipLaunchKernelGGL(recip_kernel, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, M.stream,
-                     n, M.dval.p, M.dinv.p);
-  VL_TRY(check_launch("recip"));
-  VL_TRY(refresh_transpose_values(M));
-  VL_TRY(refresh_head_values(M));
-  ++M.factor_version;
-  VL_TRY(sync_stream(M.stream));
-  return read_status(M);
+  return finish_factor(M);
 }
 
 static Status check_theta(const double* theta) {

@@ -104,6 +104,36 @@ __global__ __launch_bounds__(256) void laplace_terms_kernel(
   block_colsum(g, s3, part + 3 * g.nchunk);
 }
 
+// The same per chunk of a row-chunk table (batching form).
+__global__ __launch_bounds__(256) void seg_terms_kernel(
+    SegArgs a, int nchunk, int lik, double aux, const double* __restrict__ y,
+    const double* __restrict__ F, const double* __restrict__ b, const double* __restrict__ Bb,
+    const double* __restrict__ D, const double* __restrict__ W, double* __restrict__ part) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  SEG_LOOP_BEGIN(a)
+  (void)c;
+  const double mu = (F ? F[i] : 0.0) + b[i];
+  s0 += lik_logp(lik, y[i], mu, aux);
+  const double di = D[i];
+  s1 += Bb[i] * Bb[i] / di;
+  if (W) {
+    s2 += log(di);
+    s3 += log(W[i] + 1.0 / di);
+  }
+  SEG_LOOP_END
+  seg_colsum(a, s0, part);
+  seg_colsum(a, s1, part + nchunk);
+  seg_colsum(a, s2, part + 2 * nchunk);
+  seg_colsum(a, s3, part + 3 * nchunk);
+}
+
+Status seg_terms_launch(Model& M, SegArgs a, int nchunk, const double* b, const double* Bb,
+                        const double* W, double* part) {
+  hipLaunchKernelGGL(seg_terms_kernel, dim3(nchunk, 1), dim3(256), 0, M.stream, a, nchunk, M.lik,
+                     M.aux, M.y.p, M.F.p, b, Bb, M.dval.p, W, part);
+  return check_launch("seg terms");
+}
+
 // sums[k] = sum of the k-th partial array (nchunk entries each), in order
 __global__ void sum_parts_kernel(const double* __restrict__ part, int nchunk, int nsum,
                                  double* __restrict__ out) {

@@ -457,7 +457,7 @@ __global__ __launch_bounds__(256) void trsm_level_kernel(int t, const int* __res
                                                          const double* __restrict__ X,
                                                          const double* __restrict__ rs,
                                                          double* __restrict__ Y) {
-  const int c = blockIdx.y * 256 + threadIdx.x;
+  const int c = blockIdx.y * blockDim.x + threadIdx.x;
   const int64_t i = rows[blockIdx.x];
   if (c >= t) return;
   int q, e;
@@ -537,7 +537,8 @@ static Status trsm_levels(Model& M, bool lower, const double* X, double* Y, int 
   const std::vector<int64_t>& lnz = lower ? M.lvl_nnz_f : M.lvl_nnz_b;
   const int* order = lower ? M.full_order_f.p : M.full_order_b.p;
   if (lp.size() < 2 || lp.back() != M.n) return Status::make(VL_ERR_STATE, "no level schedule");
-  const unsigned gy = static_cast<unsigned>((t + 255) / 256);
+  const int tb = t <= 64 ? 64 : 256;  // threads (columns) per block
+  const unsigned gy = static_cast<unsigned>((t + tb - 1) / tb);
   for (size_t l = 0; l + 1 < lp.size(); ++l) {
     const int rows = lp[l + 1] - lp[l];
     if (rows <= 0) continue;
@@ -546,13 +547,13 @@ static Status trsm_levels(Model& M, bool lower, const double* X, double* Y, int 
                    12.0 * lnz[l] + 16.0 * rows * t + 4.0 * rows +
                        (lower ? (rowscale ? 8.0 * rows : 0.0) : 8.0 * rows));
     if (lower) {
-      hipLaunchKernelGGL(trsm_level_kernel<true>, dim3(rows, gy), dim3(256), 0, M.stream, t,
+      hipLaunchKernelGGL(trsm_level_kernel<true>, dim3(rows, gy), dim3(tb), 0, M.stream, t,
                          order + lp[l], M.m, nullptr, M.nbr.p, M.bval.p, X, rowscale, Y);
     } else if (split) {
       hipLaunchKernelGGL(trsm_level_split_kernel, dim3(rows, (t + 63) / 64), dim3(256), 0,
                          M.stream, t, order + lp[l], M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, Y);
     } else {
-      hipLaunchKernelGGL(trsm_level_kernel<false>, dim3(rows, gy), dim3(256), 0, M.stream, t,
+      hipLaunchKernelGGL(trsm_level_kernel<false>, dim3(rows, gy), dim3(tb), 0, M.stream, t,
                          order + lp[l], 0, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, nullptr, Y);
     }
   }
@@ -594,7 +595,9 @@ static int64_t head_of(const Model& M, int t) { return t <= 64 ? M.head_rows : 0
 // Blocks wider than 64 columns have ample parallelism inside each level and
 // are bandwidth-bound: they take the level-scheduled path (no sentinel fill,
 // no polling).  Narrower blocks take the LDS head and the sync-free tail.
-static bool use_levels(const Model& M, int t) { return t > 64 && M.lvl_ptr_f.size() > 1; }
+static bool use_levels(const Model& M, int t) {
+  return (t > 64 || M.force_levels) && M.lvl_ptr_f.size() > 1;
+}
 
 Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* rowscale,
                    bool prefilled, int slot) {

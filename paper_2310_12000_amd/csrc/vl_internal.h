@@ -157,6 +157,7 @@ struct Model {
   DevBuf<double> bt_val;
   DevBuf<float> bval_f, bt_val_f;  // FP32 copies for the mixed-precision form
   int64_t factor_version = 0, f32_version = -1;  // FP32 copies made at factor_version
+  bool force_levels = false;  // level-scheduled solves for every block width (autotuner)
 
   // head rows solved in LDS (level schedules for both directions)
   int head_rows = 0, head_nlev_f = 0, head_nlev_b = 0;
@@ -229,6 +230,9 @@ struct Model {
   Timing timing;
   int64_t nnz_head_f = 0, nnz_head_bt = 0;  // nonzeros in head rows of B / B^T
 };
+
+// Records the message of a failed status for vl_last_error (api.hip).
+vl_status report(const Status& s);
 
 // Brackets one kernel launch with events when timing is enabled.
 class TimedLaunch {

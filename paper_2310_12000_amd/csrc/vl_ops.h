@@ -116,6 +116,50 @@ __device__ __forceinline__ void block_colsum(const ChunkGrid& g, double v,
 
 Status reduce_chunks(hipStream_t s, const double* part, int nchunk, int t, double* out);
 
+// Row chunks given by a table (the batching form): block (k, s) covers rows
+// [r0[k], r1[k]) of the problem prob[k] and columns of slice s, visited in
+// the same lane pattern as CHUNK_LOOP.
+struct SegArgs {
+  Lanes L;
+  int t;
+  const int* prob;
+  const int* r0;
+  const int* r1;
+};
+
+// Rows (i, column c) of this lane in the block's chunk, in the same pattern
+// as a solo run's chunk (so sums come out in the same order).
+#define SEG_LOOP_BEGIN(a)                                                            \
+  {                                                                                  \
+    const int _lane = threadIdx.x & 63;                                              \
+    const int _w = threadIdx.x >> 6;                                                 \
+    const int _sub = _lane >> (a).L.lpr_log;                                         \
+    const int c = blockIdx.y * 64 + (_lane & ((1 << (a).L.lpr_log) - 1));            \
+    const int64_t _r0 = (a).r0[blockIdx.x];                                          \
+    const int64_t _r1 = (a).r1[blockIdx.x];                                          \
+    const int64_t _step = 4LL << (a).L.rpw_log;                                      \
+    if (c < (a).t) {                                                                 \
+      for (int64_t _b = _r0 + ((int64_t)_w << (a).L.rpw_log); _b < _r1; _b += _step) { \
+        const int64_t i = _b + _sub;                                                 \
+        if (i >= _r1) continue;
+
+#define SEG_LOOP_END \
+  }                  \
+  }                  \
+  }
+
+__device__ __forceinline__ void seg_colsum(const SegArgs& a, double v, double* part) {
+  ChunkGrid g;
+  g.L = a.L;
+  g.t = a.t;
+  block_colsum(g, v, part);
+}
+
+// Per chunk of the table (t = 1): log p(y | F + b), D^{-1} (B b)^2, log D,
+// log(W + D^{-1}) as four partial arrays of nchunk entries (laplace.hip).
+Status seg_terms_launch(Model& M, SegArgs a, int nchunk, const double* b, const double* Bb,
+                        const double* W, double* part);
+
 // Operator pair of one CG solve.
 struct CgOps {
   // V = A H over t columns (Tmp: n x t scratch)

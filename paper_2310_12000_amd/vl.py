@@ -72,6 +72,14 @@ class vl_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class vl_problem(ctypes.Structure):
+    _fields_ = [
+        ("coords", ctypes.c_void_p), ("n", ctypes.c_int64), ("m", ctypes.c_int),
+        ("cov", ctypes.c_int), ("theta", ctypes.c_double * 2), ("y", ctypes.c_void_p),
+        ("F", ctypes.c_void_p), ("seed", ctypes.c_uint64),
+    ]
+
+
 class VLError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{msg} (status {code})")
@@ -115,9 +123,19 @@ def lib():
     L.vl_timing_read.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(I64), ctypes.POINTER(D)]
     L.vl_free.argtypes = [P]
     L.vl_free.restype = None
+    L.vl_batch_create.argtypes = [ctypes.POINTER(vl_problem), I, I, ctypes.POINTER(D), P,
+                                  ctypes.POINTER(P)]
+    L.vl_batch_fit.argtypes = [P, ctypes.POINTER(vl_opts), ctypes.POINTER(D)]
+    L.vl_batch_mode.argtypes = [P, I, P]
+    L.vl_batch_stats.argtypes = [P, I, ctypes.POINTER(vl_stats)]
+    L.vl_batch_tuned_path.argtypes = [P, I]
+    L.vl_batch_tuned_path.restype = I
+    L.vl_batch_free.argtypes = [P]
+    L.vl_batch_free.restype = None
     for f in ("vl_build_vecchia", "vl_set_theta", "vl_find_mode", "vl_neg_log_marglik",
               "vl_predict", "vl_export", "vl_spmm", "vl_trsm", "vl_timing_enable",
-              "vl_timing_read"):
+              "vl_timing_read", "vl_batch_create", "vl_batch_fit", "vl_batch_mode",
+              "vl_batch_stats"):
         getattr(L, f).restype = I
     _lib = L
     return L
@@ -288,6 +306,68 @@ class VecchiaLaplace:
     def close(self):
         if self.h:
             vl_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class VecchiaLaplaceBatch:
+    """Many problems fitted together (vl_batch_*).  `problems`: list of dicts
+    with coords (n x 2), y, F (or None), m, cov, theta, seed -- device tensors
+    or arrays convertible to them."""
+
+    def __init__(self, problems, lik=VL_LIK_BERNOULLI_LOGIT, aux=None, device="cuda"):
+        self._keep = []
+        arr = (vl_problem * len(problems))()
+        for k, p in enumerate(problems):
+            c = torch.as_tensor(p["coords"], dtype=torch.float64, device=device).contiguous()
+            y = torch.as_tensor(p["y"], dtype=torch.float64, device=device).contiguous()
+            F = p.get("F")
+            F = None if F is None else torch.as_tensor(F, dtype=torch.float64,
+                                                       device=device).contiguous()
+            self._keep += [c, y, F]
+            arr[k].coords = c.data_ptr()
+            arr[k].n = c.shape[0]
+            arr[k].m = int(p["m"])
+            arr[k].cov = int(p["cov"])
+            arr[k].theta[0], arr[k].theta[1] = float(p["theta"][0]), float(p["theta"][1])
+            arr[k].y = y.data_ptr()
+            arr[k].F = F.data_ptr() if F is not None else None
+            arr[k].seed = int(p.get("seed", 0))
+        self.sizes = [int(arr[k].n) for k in range(len(problems))]
+        self.device = device
+        h = ctypes.c_void_p()
+        a = (ctypes.c_double * 1)(float(aux)) if aux is not None else None
+        _check(lib().vl_batch_create(arr, len(problems), lik, a, None, ctypes.byref(h)))
+        self.h = h
+        self._keep = []
+
+    def fit(self, opts=None):
+        opts = opts or vl_default_opts()
+        out = (ctypes.c_double * len(self.sizes))()
+        _check(lib().vl_batch_fit(self.h, ctypes.byref(opts), out))
+        return list(out)
+
+    def mode(self, p):
+        out = torch.empty(self.sizes[p], dtype=torch.float64, device=self.device)
+        _check(lib().vl_batch_mode(self.h, p, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def stats(self, p):
+        st = vl_stats()
+        _check(lib().vl_batch_stats(self.h, p, ctypes.byref(st)))
+        return st
+
+    def tuned_path(self, width_class):
+        return lib().vl_batch_tuned_path(self.h, width_class)
+
+    def close(self):
+        if self.h:
+            lib().vl_batch_free(self.h)
             self.h = None
 
     def __del__(self):

@@ -287,6 +287,54 @@ int vl_batch_tuned_path(vl_batch* b, int width_class);
 
 void vl_batch_free(vl_batch* b);
 
+/* ---------------------------------------------------------------------- */
+/* Serving form: a continuous-batching loop of fit + predict requests.
+ * Requests are queued in arrival order and admitted when one of `slots`
+ * worker slots is free and the request's HBM estimate (vl_request_bytes)
+ * fits into the budget next to the running requests; a finishing request
+ * frees its slot and budget at once, so waiting requests join while others
+ * still run.  Each slot runs its request on its own HIP stream and model
+ * (vl_build_vecchia, vl_find_mode, vl_neg_log_marglik, vl_predict with the
+ * server's options and the request's seed); requests overlap on the device,
+ * and a request's results do not depend on the others. */
+typedef struct vl_server vl_server;
+
+typedef struct {
+  const double* coords;    /* device, n x 2                                    */
+  int64_t n;
+  int m;
+  int cov;                 /* vl_cov                                           */
+  double theta[2];
+  const double* y;         /* device, n                                        */
+  const double* F;         /* device, n (NULL = 0)                             */
+  int lik;                 /* vl_lik                                           */
+  double aux;              /* Gaussian noise variance (other likelihoods: 0)  */
+  uint64_t seed;           /* probe seed                                       */
+  const double* coords_p;  /* device, n_p x 2 (n_p = 0: no prediction)        */
+  int64_t n_p;
+  const double* Fp;        /* device, n_p (NULL = 0)                           */
+  double* mean_out;        /* device, n_p                                      */
+  double* var_out;         /* device, n_p (NULL = means only)                  */
+} vl_request;
+
+/* Start `slots` (1..64) worker threads on the current device. */
+vl_status vl_server_create(int slots, double hbm_budget_bytes, const vl_opts* o,
+                           vl_server** out);
+/* Queue a request (non-blocking, thread-safe); the caller keeps its buffers
+ * alive and untouched until vl_server_wait returns for its ticket. */
+vl_status vl_server_submit(vl_server* s, const vl_request* r, int64_t* ticket);
+/* Block until the request finished; nll_out (host) gets its negative
+ * log-marginal likelihood, st its statistics (t_ms = submit-to-done latency),
+ * queue_ms the time it waited for admission.  Returns the request's status. */
+vl_status vl_server_wait(vl_server* s, int64_t ticket, double* nll_out, vl_stats* st,
+                         double* queue_ms);
+/* Largest admitted HBM estimate and largest number of requests running at once. */
+vl_status vl_server_info(vl_server* s, double* peak_bytes, int* peak_running);
+/* The HBM estimate admission uses for a request (bytes). */
+double vl_request_bytes(const vl_request* r, const vl_opts* o);
+/* Drop waiting requests, finish running ones, stop the workers. */
+void vl_server_free(vl_server* s);
+
 /* Release the handle and all its device memory. */
 void vl_free(vl_model* h);
 

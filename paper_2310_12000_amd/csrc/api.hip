@@ -22,6 +22,8 @@ static vl_status fail(const Status& s) {
 
 vl_status report(const Status& s) { return s.good() ? VL_OK : fail(s); }
 
+Model* model_of(vl_model* h) { return h; }
+
 __global__ void recip_kernel(int64_t n, const double* __restrict__ d, double* __restrict__ out) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) out[i] = 1.0 / d[i];

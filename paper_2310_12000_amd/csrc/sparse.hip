@@ -571,6 +571,7 @@ static int trsm_grid(int64_t total_units) {
 static int trsm_streams(const Model& M, int blocks) {
   int s = blocks < kCounterStreams ? blocks : kCounterStreams;
   if (s > M.num_cus) s = M.num_cus;
+  if (M.max_streams > 0 && s > M.max_streams) s = M.max_streams;
   return s < 1 ? 1 : s;
 }
 

@@ -136,6 +136,11 @@ struct Timing {
 struct Model {
   int device = 0;
   int num_cus = 1;
+  // Work streams of a sync-free solve at most (0 = no cap).  Solves of
+  // models that run concurrently on one GPU together need every stream of
+  // every solve to keep a resident wave: their caps must add up to at most
+  // the CU count (the serving loop sets CUs / slots).
+  int max_streams = 0;
   hipStream_t stream = nullptr;
   int64_t n = 0;
   int m = 0;

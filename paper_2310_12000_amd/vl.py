@@ -80,6 +80,16 @@ class vl_problem(ctypes.Structure):
     ]
 
 
+class vl_request(ctypes.Structure):
+    _fields_ = [
+        ("coords", ctypes.c_void_p), ("n", ctypes.c_int64), ("m", ctypes.c_int),
+        ("cov", ctypes.c_int), ("theta", ctypes.c_double * 2), ("y", ctypes.c_void_p),
+        ("F", ctypes.c_void_p), ("lik", ctypes.c_int), ("aux", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("coords_p", ctypes.c_void_p), ("n_p", ctypes.c_int64),
+        ("Fp", ctypes.c_void_p), ("mean_out", ctypes.c_void_p), ("var_out", ctypes.c_void_p),
+    ]
+
+
 class VLError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{msg} (status {code})")
@@ -132,10 +142,20 @@ def lib():
     L.vl_batch_tuned_path.restype = I
     L.vl_batch_free.argtypes = [P]
     L.vl_batch_free.restype = None
+    L.vl_server_create.argtypes = [I, D, ctypes.POINTER(vl_opts), ctypes.POINTER(P)]
+    L.vl_server_submit.argtypes = [P, ctypes.POINTER(vl_request), ctypes.POINTER(I64)]
+    L.vl_server_wait.argtypes = [P, I64, ctypes.POINTER(D), ctypes.POINTER(vl_stats),
+                                 ctypes.POINTER(D)]
+    L.vl_server_info.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I)]
+    L.vl_request_bytes.argtypes = [ctypes.POINTER(vl_request), ctypes.POINTER(vl_opts)]
+    L.vl_request_bytes.restype = D
+    L.vl_server_free.argtypes = [P]
+    L.vl_server_free.restype = None
     for f in ("vl_build_vecchia", "vl_set_theta", "vl_find_mode", "vl_neg_log_marglik",
               "vl_predict", "vl_export", "vl_spmm", "vl_trsm", "vl_timing_enable",
               "vl_timing_read", "vl_batch_create", "vl_batch_fit", "vl_batch_mode",
-              "vl_batch_stats"):
+              "vl_batch_stats", "vl_server_create", "vl_server_submit", "vl_server_wait",
+              "vl_server_info"):
         getattr(L, f).restype = I
     _lib = L
     return L
@@ -368,6 +388,79 @@ class VecchiaLaplaceBatch:
     def close(self):
         if self.h:
             lib().vl_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop (vl_server_*).  submit() takes a dict
+    with coords, y, F, m, cov, theta, lik, seed and optionally coords_p, Fp;
+    it returns a ticket; wait(ticket) returns (nll, mean, var, stats,
+    queue_ms) with mean/var as device tensors."""
+
+    def __init__(self, slots, hbm_budget_bytes, opts=None, device="cuda"):
+        self.opts = opts or vl_default_opts()
+        h = ctypes.c_void_p()
+        _check(lib().vl_server_create(int(slots), float(hbm_budget_bytes),
+                                      ctypes.byref(self.opts), ctypes.byref(h)))
+        self.h = h
+        self.device = device
+        self._live = {}
+
+    def _request(self, r):
+        t = lambda x: (None if x is None else
+                       torch.as_tensor(x, dtype=torch.float64, device=self.device).contiguous())
+        keep = dict(coords=t(r["coords"]), y=t(r["y"]), F=t(r.get("F")),
+                    coords_p=t(r.get("coords_p")), Fp=t(r.get("Fp")))
+        n_p = 0 if keep["coords_p"] is None else keep["coords_p"].shape[0]
+        keep["mean"] = torch.empty(n_p, dtype=torch.float64, device=self.device)
+        keep["var"] = torch.empty(n_p, dtype=torch.float64, device=self.device)
+        q = vl_request()
+        ptr = lambda x: None if x is None else x.data_ptr()
+        q.coords, q.n, q.m, q.cov = ptr(keep["coords"]), keep["coords"].shape[0], int(r["m"]), \
+            int(r["cov"])
+        q.theta[0], q.theta[1] = float(r["theta"][0]), float(r["theta"][1])
+        q.y, q.F, q.lik, q.aux = ptr(keep["y"]), ptr(keep["F"]), int(r["lik"]), \
+            float(r.get("aux", 0.0))
+        q.seed = int(r.get("seed", 0))
+        q.coords_p, q.n_p, q.Fp = ptr(keep["coords_p"]), n_p, ptr(keep["Fp"])
+        q.mean_out = ptr(keep["mean"]) if n_p else None
+        q.var_out = ptr(keep["var"]) if n_p else None
+        return q, keep
+
+    def request_bytes(self, r):
+        q, _ = self._request(r)
+        return lib().vl_request_bytes(ctypes.byref(q), ctypes.byref(self.opts))
+
+    def submit(self, r):
+        q, keep = self._request(r)
+        torch.cuda.synchronize()
+        tk = ctypes.c_int64()
+        _check(lib().vl_server_submit(self.h, ctypes.byref(q), ctypes.byref(tk)))
+        self._live[tk.value] = keep
+        return tk.value
+
+    def wait(self, ticket):
+        nll, st, qms = ctypes.c_double(), vl_stats(), ctypes.c_double()
+        code = lib().vl_server_wait(self.h, ticket, ctypes.byref(nll), ctypes.byref(st),
+                                    ctypes.byref(qms))
+        keep = self._live.pop(ticket)
+        _check(code, allow=(VL_ERR_NO_CONVERGENCE,))
+        return nll.value, keep["mean"], keep["var"], st.as_dict(), qms.value
+
+    def info(self):
+        b, r = ctypes.c_double(), ctypes.c_int()
+        _check(lib().vl_server_info(self.h, ctypes.byref(b), ctypes.byref(r)))
+        return b.value, r.value
+
+    def close(self):
+        if self.h:
+            lib().vl_server_free(self.h)
             self.h = None
 
     def __del__(self):

@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the mixed-precision, batching and serving measurements")
+    ap.add_argument("--batch-problems", type=int, default=32)
+    ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="one 512 MiB device-to-device copy before the steps (the known-size "
                          "kernel that scales the HBM byte counters)")
@@ -169,8 +173,128 @@ def main():
     out["b_spmm"] = {"achieved_GBps": by_b / (ms_b * 1e-3) / 1e9 if ms_b > 0 else 0.0,
                      "frac": (by_b / (ms_b * 1e-3) / 1e9) / HBM_PEAK_GBS if ms_b > 0 else 0.0,
                      "launches": cnt_b, "avg_launch_us": 1e3 * ms_b / max(cnt_b, 1)}
+    if not args.no_forms:
+        out["forms"] = {
+            "mixed": form_mixed(P, torch, w, coords, y, F, coords_p, Fp, theta, opts, rec, args),
+            "batch": form_batch(P, torch, synth, args),
+            "serving": form_serving(P, torch, synth, args),
+        }
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(w, rec[-1], args)
     print(json.dumps(out), flush=True)
+
+
+def form_mixed(P, torch, w, coords, y, F, coords_p, Fp, theta, opts, rec, args):
+    """The same evaluation with FP32 blocks and sparse kernels (FP64 sums and
+    refinement), against the FP64 run of the same inputs and probes."""
+    import copy
+    om = copy.copy(opts)
+    om.precision = P.VL_MIXED
+    res = {}
+    for name, o in (("fp64", opts), ("mixed", om)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = P.VecchiaLaplace(coords, w["m"], w["kind"], theta, want_deriv=True)
+        g.find_mode(y, F, w["lik"], None, o)
+        nll, grad, _ = g.neg_log_marglik(o, want_grad=True)
+        mean, var, _ = g.predict(coords_p, Fp, o)
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0, nll, grad, mean.cpu().numpy(), var.cpu().numpy())
+        g.close()
+    import numpy as np
+    f, m = res["fp64"], res["mixed"]
+    rel = lambda a, b: float(np.max(np.abs(np.asarray(a) - np.asarray(b))) /
+                             max(np.max(np.abs(np.asarray(b))), 1e-300))
+    log(args, f"mixed: {m[0]:.2f} s vs fp64 {f[0]:.2f} s")
+    return {"evals_per_s": 1.0 / m[0], "fp64_evals_per_s": 1.0 / f[0],
+            "speedup": f[0] / m[0], "nll_rel_err_vs_fp64": abs(m[1] - f[1]) / abs(f[1]),
+            "var_rel_err_vs_fp64": rel(m[4], f[4]), "mean_rel_err_vs_fp64": rel(m[3], f[3]),
+            "grad_rel_err_vs_fp64": rel(m[2], f[2]),
+            "note": "same workload and probes; FP32 blocks and B values, FP64 sums, FP64 "
+                    "refinement of the solutions (errors against the FP64 GPU path, which "
+                    "matches the FP64 oracle to 1e-9)"}
+
+
+def form_batch(P, torch, synth, args):
+    """Uneven problems (n log-uniform, m in {10, 20, 30}, exponential or
+    Matern-3/2, range U(0.02, 0.2), Bernoulli-logit, 32 probes) fitted
+    together, against solo runs of a sample of them.  The library's batch
+    limit (32 problems, 65536 rows) caps the sizes at n in [1e3, 2e3]."""
+    probs = synth.batch_problems(count=args.batch_problems, seed=args.seed, n_lo=1000,
+                                 n_hi=2000)
+    o = P.vl_default_opts(num_probes=32, cg_tol=1e-2)
+    items = [dict(coords=p["coords"], y=p["y"], F=p["F"], m=p["m"], cov=p["kind"],
+                  theta=(p["sigma2"], p["rho"]), seed=1000 + k) for k, p in enumerate(probs)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = P.VecchiaLaplaceBatch(items)
+    t1 = time.perf_counter()
+    nll = b.fit(o)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    paths = [b.tuned_path(c) for c in range(2)]
+    b.close()
+    # solo runs of every 4th problem, scaled to all problems by their sizes
+    sample = list(range(0, len(probs), 4))
+    ts = 0.0
+    for k in sample:
+        p = probs[k]
+        o.seed = 1000 + k
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        g = P.VecchiaLaplace(torch.as_tensor(p["coords"], device="cuda"), p["m"], p["kind"],
+                             (p["sigma2"], p["rho"]))
+        g.find_mode(torch.as_tensor(p["y"], device="cuda"), torch.as_tensor(p["F"], device="cuda"),
+                    p["lik"], None, o)
+        g.neg_log_marglik(o)
+        torch.cuda.synchronize()
+        ts += time.perf_counter() - s0
+        g.close()
+    n_all = sum(p["n"] for p in probs)
+    n_s = sum(probs[k]["n"] for k in sample)
+    solo_est = ts * n_all / n_s
+    log(args, f"batch: build {t1 - t0:.2f} s fit {t2 - t1:.2f} s; solo estimate {solo_est:.2f} s")
+    return {"problems": len(probs), "total_n": n_all, "build_s": t1 - t0, "fit_s": t2 - t1,
+            "problems_per_s": len(probs) / (t2 - t0),
+            "solo_estimate_s": solo_est, "speedup_vs_solo": solo_est / (t2 - t0),
+            "solo_sample": len(sample), "autotuned_paths": {"t=1": paths[0], "t=32": paths[1]},
+            "all_finite": bool(all(map(lambda v: v == v, nll)))}
+
+
+def form_serving(P, torch, synth, args):
+    """Fit + predict requests arriving as a Poisson process at 100 req/s (n
+    log-uniform in [2e3, 2e5], 1e3..2e4 test points, m = 20, Bernoulli or
+    Poisson), served by the continuous-batching loop with 4 slots under a
+    200 GB HBM budget; t = 50 probes, s = 2000 samples in tiles of 500."""
+    import numpy as np
+    reqs = synth.serving_requests(args.serve_requests, seed=args.seed)
+    o = P.vl_default_opts(num_probes=50, num_pred_samples=2000, pred_tile=500, cg_tol=1e-2,
+                          pred_cg_tol=1e-3)
+    srv = P.Server(4, 200e9, o)
+    items = [dict(coords=r["coords"], y=r["y"], F=r["F"], m=r["m"], cov=r["kind"],
+                  theta=(r["sigma2"], r["rho"]), lik=r["lik"], seed=500 + k,
+                  coords_p=r["coords_pred"], Fp=r["Fp"]) for k, r in enumerate(reqs)]
+    t0 = time.perf_counter()
+    tickets = []
+    for r, it in zip(reqs, items):
+        delay = r["arrival"] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(it))
+    lat = []
+    for tk in tickets:
+        nll, mean, var, st, qms = srv.wait(tk)
+        lat.append(st["t_ms"])
+    wall = time.perf_counter() - t0
+    peak_bytes, peak_running = srv.info()
+    srv.close()
+    lat = np.array(lat)
+    log(args, f"serving: {len(reqs)} requests in {wall:.2f} s; p50 {np.percentile(lat, 50):.0f} ms "
+              f"p99 {np.percentile(lat, 99):.0f} ms")
+    return {"requests": len(reqs), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "req_per_s": len(reqs) / wall,
+            "slots": 4, "hbm_budget_gb": 200, "peak_running": peak_running,
+            "peak_admitted_gb": peak_bytes / 1e9,
+            "n_range": [int(min(r["n"] for r in reqs)), int(max(r["n"] for r in reqs))]}
 
 
 def measured_traffic(kernel, workload):

@@ -260,7 +260,9 @@ typedef struct {
 } vl_problem;
 
 /* Build the packed model: per problem neighbour search and factor (Sec. 2.1),
- * then B^T and the solve schedules of the packed system.  All problems share
+ * then B^T and the solve schedules of the packed system.  At most 32 problems
+ * and 65536 rows in total (VL_ERR_INVALID_ARG above): a 256-problem batch of
+ * 3.2e6 rows faulted the GPU and the cause is not yet found.  All problems share
  * the likelihood `lik` (aux_host as for vl_find_mode).  The problem arrays are
  * copied; the caller keeps ownership.  Synchronises. */
 vl_status vl_batch_create(const vl_problem* problems, int nprob, int lik,

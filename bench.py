@@ -174,11 +174,13 @@ def main():
                      "frac": (by_b / (ms_b * 1e-3) / 1e9) / HBM_PEAK_GBS if ms_b > 0 else 0.0,
                      "launches": cnt_b, "avg_launch_us": 1e3 * ms_b / max(cnt_b, 1)}
     if not args.no_forms:
-        out["forms"] = {
-            "mixed": form_mixed(P, torch, w, coords, y, F, coords_p, Fp, theta, opts, rec, args),
-            "batch": form_batch(P, torch, synth, args),
-            "serving": form_serving(P, torch, synth, args),
-        }
+        out["forms"] = {}
+        for name, fn in (("mixed", lambda: form_mixed(P, torch, w, coords, y, F, coords_p, Fp,
+                                                       theta, opts, rec, args)),
+                         ("batch", lambda: form_batch(P, torch, synth, args)),
+                         ("serving", lambda: form_serving(P, torch, synth, args))):
+            print(f"form: {name}", file=sys.stderr, flush=True)
+            out["forms"][name] = fn()
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(w, rec[-1], args)
     print(json.dumps(out), flush=True)
 

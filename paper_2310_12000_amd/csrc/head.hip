@@ -591,7 +591,10 @@ Status build_head_schedule(Model& M) {
   if (cap > want) cap = want;
   if (cap < 0) cap = 0;
   int64_t H = M.n < cap ? M.n : cap;
-  const size_t bytes = sizeof(double) * static_cast<size_t>(H);
+  // the kernels' LDS limit is a property of the kernel, shared by every model
+  // in the process: always raise it to the largest head, so that a model
+  // built later with a smaller head never lowers it under another's launches
+  const size_t bytes = sizeof(double) * static_cast<size_t>(cap);
   allow_lds(head_lower_kernel<8, 1024>, bytes);
   allow_lds(head_lower_kernel<16, 512>, bytes);
   allow_lds(head_lower_kernel<24, 512>, bytes);

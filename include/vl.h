@@ -86,7 +86,10 @@ typedef struct {
   uint64_t seed;           /* probe seed (counter-based SplitMix64)            */
   int precond;             /* vl_precond                                       */
   int lrac_rank;           /* k of the LRAC preconditioner                     */
-  int precision;           /* vl_precision                                     */
+  int precision;           /* vl_precision; VL_MIXED runs the preconditioner
+                              solves of the block solves (SLQ, prediction) in
+                              FP32 (FP32 B values and blocks, FP64 sums) inside
+                              the FP64 PCG; Newton stays FP64                  */
   int pred_tile;           /* columns per predictive-variance CG block
                               (0 = all s at once)                              */
 } vl_opts;

@@ -7,6 +7,8 @@
 //                                             VADU formulas of App. A.4.1
 //   predictive means / simulated variances    eq. (latentpostpredictive),
 //                                             Alg. simAlgo (Sec. 3.3.1)
+#include <algorithm>
+
 #include "vl_internal.h"
 #include "vl_ops.h"
 #include "vl_laplace.h"
@@ -167,9 +169,6 @@ static Status laplace_terms(Model& M, const double* b, const double* W, double o
   return host_sums(M, M.red_part.p, g.nchunk, 4, out);
 }
 
-// FP64 residual corrections of the mixed-precision form at most
-constexpr int kMaxRefine = 3;
-
 // ------------------------------------------------------- VADU operators
 CgOps vadu_ops(const double* W, const double* sdiag) {
   CgOps ops;
@@ -183,6 +182,9 @@ CgOps vadu_ops(const double* W, const double* sdiag) {
     VL_TRY(trsm_bt_slot(M, R, Y, t, true, 0));
     return trsm_b_slot(M, Y, Z, t, sdiag, true, 1);
   };
+  // the sync-free solves (t <= 64) need the sentinel fill; the level-scheduled
+  // ones do not
+  ops.needs_fill = [](const Model& M, int t) { return !(t > 64 || M.force_levels); };
   return ops;
 }
 
@@ -501,19 +503,10 @@ Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, Nl
     VL_TRY(M.rhs_blk.reserve(static_cast<size_t>(n) * t));
     // z_i = B^T ((W + D^{-1})^{1/2} o eps_i), Cov(z_i) = P_VADU
     VL_TRY(spmm_bt_probe(M, M.rhs_blk.p, t, M.vec_a.p, o.seed, kTagSlq, 0, 0, nullptr, 0, 0));
-    CgOps ops = vadu_ops(M.W.p, M.vec_b.p);
-    if (o.precision == VL_MIXED) {
-      // FP32 block PCG (its Lanczos coefficients give the quadrature), the
-      // solutions refined in FP64 for the gradient
-      MixedInfo mi;
-      VL_TRY(block_solve_mixed(M, M.cg, ops, vadu_ops_f32(M.W.p, M.vec_b.p), t, M.rhs_blk.p,
-                               o.cg_tol, o.max_cg, grad != nullptr, grad ? kMaxRefine : 0,
-                               &mi));
-      M.last_refinements = mi.refinements;
-      M.last_final_residual = mi.final_residual;
-    } else {
-      VL_TRY(cg_solve(M, M.cg, ops, t, M.rhs_blk.p, o.cg_tol, o.max_cg, grad != nullptr));
-    }
+    // mixed form: FP32 preconditioner solves inside the FP64 block PCG
+    CgOps ops = o.precision == VL_MIXED ? vadu_ops_mixed(M.W.p, M.vec_b.p)
+                                        : vadu_ops(M.W.p, M.vec_b.p);
+    VL_TRY(cg_solve(M, M.cg, ops, t, M.rhs_blk.p, o.cg_tol, o.max_cg, grad != nullptr));
   }
   M.last_block_iters = M.cg.host_iters;
   VL_TRY(M.red_out.reserve(2 * t + 64));
@@ -658,7 +651,9 @@ Status predict(Model& M, const double* coords_p, int64_t np, const double* Fp,
   VL_TRY(acc.alloc(np));
   VL_TRY(fill_double(acc.p, 0.0, np, M.stream));
   const int tile = (o.pred_tile > 0 && o.pred_tile < s) ? o.pred_tile : s;
-  CgOps ops = vadu_ops(M.W.p, M.vec_b.p);
+  // mixed form: FP32 preconditioner solves inside the FP64 block PCG
+  CgOps ops = o.precision == VL_MIXED ? vadu_ops_mixed(M.W.p, M.vec_b.p)
+                                      : vadu_ops(M.W.p, M.vec_b.p);
   int cg_max = 0;
   M.last_block_iters.clear();
   for (int c0 = 0; c0 < s; c0 += tile) {
@@ -667,15 +662,7 @@ Status predict(Model& M, const double* coords_p, int64_t np, const double* Fp,
     // z3 = W^{1/2} z1 + B^T (D^{-1/2} o z2), z1, z2 standard normal
     VL_TRY(spmm_bt_probe(M, M.rhs_blk.p, tt, M.vec_c.p, o.seed, kTagPredZ2, c0, 1, M.vec_a.p,
                          kTagPredZ1, 1));
-    if (o.precision == VL_MIXED) {
-      MixedInfo mi;
-      VL_TRY(block_solve_mixed(M, M.cg, ops, vadu_ops_f32(M.W.p, M.vec_b.p), tt, M.rhs_blk.p,
-                               o.pred_cg_tol, o.max_cg, false, kMaxRefine, &mi));
-      M.last_refinements = mi.refinements;
-      M.last_final_residual = mi.final_residual;
-    } else {
-      VL_TRY(cg_solve(M, M.cg, ops, tt, M.rhs_blk.p, o.pred_cg_tol, o.max_cg, false));
-    }
+    VL_TRY(cg_solve(M, M.cg, ops, tt, M.rhs_blk.p, o.pred_cg_tol, o.max_cg, false));
     for (int v : M.cg.host_iters) {
       cg_max = v > cg_max ? v : cg_max;
       M.last_block_iters.push_back(v);

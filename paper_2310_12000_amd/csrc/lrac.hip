@@ -397,6 +397,7 @@ CgOps lrac_ops(const double* W) {
     (void)Y;
     return lrac_precond(M, W, R, Z, t);
   };
+  ops.needs_fill = [](const Model&, int) { return false; };
   return ops;
 }
 

@@ -318,12 +318,8 @@ static Status cg_run(Model& M, CgState& S, const Ops& ops, int t, const T* rhs, 
 
 Status cg_solve(Model& M, CgState& S, const CgOps& ops, int t, const double* rhs, double tol,
                 int max_iter, bool keep_z0) {
-  return cg_run<double>(M, S, ops, t, rhs, tol, max_iter, keep_z0, true);
-}
-
-Status cg_solve_f32(Model& M, CgState& S, const CgOpsF& ops, int t, const float* rhs,
-                    double tol, int max_iter, bool keep_z0) {
-  return cg_run<float>(M, S, ops, t, rhs, tol, max_iter, keep_z0, false);
+  const bool fill = ops.needs_fill ? ops.needs_fill(M, t) : true;
+  return cg_run<double>(M, S, ops, t, rhs, tol, max_iter, keep_z0, fill);
 }
 
 Status dot_cols(Model& M, const double* X, const double* Y, int t, double* part, double* out) {

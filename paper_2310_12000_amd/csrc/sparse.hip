@@ -228,6 +228,147 @@ __global__ __launch_bounds__(256) void spmm_csr_t_kernel(
   Y[p.i * t + p.c] = acc;
 }
 
+// Wide blocks (t > 64): block (r, s) computes row order[r] for the 256 VEC
+// columns of slice s; the row's indices and values are uniform over the block
+// (scalar loads), and each thread gathers VEC consecutive columns of every
+// neighbour row at once.  The sums run in the same order as the kernels
+// above (unit diagonal first, then the entries in stored order).
+template <int VEC>
+struct VecT;
+template <>
+struct VecT<1> {
+  typedef double T;
+};
+template <>
+struct VecT<2> {
+  typedef double2 T;
+};
+
+template <int VEC>
+__device__ __forceinline__ void vload(const double* p, double* v) {
+  if (VEC == 2) {
+    const double2 q = *reinterpret_cast<const double2*>(p);
+    v[0] = q.x;
+    v[1] = q.y;
+  } else {
+    v[0] = p[0];
+  }
+}
+template <int VEC>
+__device__ __forceinline__ void vstore(double* p, const double* v) {
+  if (VEC == 2) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  } else {
+    p[0] = v[0];
+  }
+}
+
+template <int VEC>
+__global__ __launch_bounds__(256) void spmm_ell_wide_kernel(int64_t n, int m, int t,
+                                                            const int* __restrict__ order,
+                                                            const int* __restrict__ nbr,
+                                                            const double* __restrict__ vals,
+                                                            const double* __restrict__ X,
+                                                            const double* __restrict__ rs,
+                                                            int unit_diag, double* __restrict__ Y) {
+  const int64_t r = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t i = order ? order[r] : r;
+  const int c = (blockIdx.y * 256 + threadIdx.x) * VEC;
+  if (c >= t) return;
+  double acc[VEC];
+  if (unit_diag) {
+    vload<VEC>(X + i * t + c, acc);
+  } else {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = 0.0;
+  }
+  const int* nb = nbr + i * m;
+  const double* vb = vals + i * m;
+  for (int k0 = 0; k0 < m; k0 += 8) {
+    int js[8];
+    double vv[8], xs[8][VEC];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      js[k] = (k0 + k < m) ? nb[k0 + k] : -1;
+      vv[k] = (k0 + k < m) ? vb[k0 + k] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (js[k] >= 0) {
+        vload<VEC>(X + (int64_t)js[k] * t + c, xs[k]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) xs[k][v] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[v] += vv[k] * xs[k][v];
+  }
+  if (rs) {
+    const double s = rs[i];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] *= s;
+  }
+  vstore<VEC>(Y + i * t + c, acc);
+}
+
+template <int VEC, bool DIAG>
+__global__ __launch_bounds__(256) void spmm_csr_t_wide_kernel(
+    int64_t n, int t, const int* __restrict__ order, const int* __restrict__ ptr,
+    const int* __restrict__ col, const double* __restrict__ val, const double* __restrict__ X,
+    const double* __restrict__ d, const double* __restrict__ V, double* __restrict__ Y) {
+  const int64_t r = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t i = order ? order[r] : r;
+  const int c = (blockIdx.y * 256 + threadIdx.x) * VEC;
+  if (c >= t) return;
+  double acc[VEC];
+  vload<VEC>(X + i * t + c, acc);
+  const int b = ptr[i], e = ptr[i + 1];
+  for (int q = b; q < e; q += 8) {
+    int cs[8];
+    double vs[8], xs[8][VEC];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      cs[k] = (q + k < e) ? col[q + k] : -1;
+      vs[k] = (q + k < e) ? val[q + k] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (cs[k] >= 0) {
+        vload<VEC>(X + (int64_t)cs[k] * t + c, xs[k]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) xs[k][v] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[v] += vs[k] * xs[k][v];
+  }
+  if (DIAG) {
+    double vv[VEC];
+    vload<VEC>(V + i * t + c, vv);
+    const double di = d[i];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] += di * vv[v];
+  }
+  vstore<VEC>(Y + i * t + c, acc);
+}
+
+// double2 accesses need even t and 16-byte aligned blocks
+static bool vec2_ok(int t, const void* a, const void* b, const void* c = nullptr) {
+  auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+  return t % 2 == 0 && al(a) && al(b) && (c == nullptr || al(c));
+}
+
+static dim3 wide_grid(int64_t n, int t, int vec) {
+  const int cols = 256 * vec;
+  return dim3(static_cast<unsigned>(n), static_cast<unsigned>((t + cols - 1) / cols));
+}
+
 struct InNone {
   __device__ __forceinline__ double operator()(int64_t, int) const { return 0.0; }
 };
@@ -246,6 +387,17 @@ static double spmm_bytes(const Model& M, int t, bool rowscale) {
 static Status launch_ell(Model& M, const double* vals, const double* X, double* Y, int t,
                          const double* rowscale, int unit_diag) {
   TimedLaunch tl(M, kTimeSpmmB, spmm_bytes(M, t, rowscale != nullptr));
+  if (t > 64) {
+    const int* ord = spatial_order(M);
+    if (vec2_ok(t, X, Y)) {
+      hipLaunchKernelGGL(spmm_ell_wide_kernel<2>, wide_grid(M.n, t, 2), dim3(256), 0, M.stream,
+                         M.n, M.m, t, ord, M.nbr.p, vals, X, rowscale, unit_diag, Y);
+    } else {
+      hipLaunchKernelGGL(spmm_ell_wide_kernel<1>, wide_grid(M.n, t, 1), dim3(256), 0, M.stream,
+                         M.n, M.m, t, ord, M.nbr.p, vals, X, rowscale, unit_diag, Y);
+    }
+    return check_launch("spmm_ell wide");
+  }
   Lanes L = Lanes::of(t);
   int nb = spmm_nblocks(M.n, t);
   const int* ord = spatial_order(M);
@@ -273,6 +425,25 @@ Status spmm_bt(Model& M, const double* X, double* Y, int t, const double* diag,
   TimedLaunch tl(M, kTimeSpmmBt,
                  spmm_bytes(M, t, false) + 4.0 * (M.n + 1) +
                      (diag ? 8.0 * M.n + 8.0 * M.n * t : 0.0));
+  if (t > 64) {
+    const int* ord = spatial_order(M);
+    const int vec = vec2_ok(t, X, Y, diag ? diagvec : nullptr) ? 2 : 1;
+    const dim3 gw = wide_grid(M.n, t, vec);
+    if (vec == 2 && diag) {
+      hipLaunchKernelGGL((spmm_csr_t_wide_kernel<2, true>), gw, dim3(256), 0, M.stream, M.n, t,
+                         ord, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, diag, diagvec, Y);
+    } else if (vec == 2) {
+      hipLaunchKernelGGL((spmm_csr_t_wide_kernel<2, false>), gw, dim3(256), 0, M.stream, M.n, t,
+                         ord, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, nullptr, nullptr, Y);
+    } else if (diag) {
+      hipLaunchKernelGGL((spmm_csr_t_wide_kernel<1, true>), gw, dim3(256), 0, M.stream, M.n, t,
+                         ord, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, diag, diagvec, Y);
+    } else {
+      hipLaunchKernelGGL((spmm_csr_t_wide_kernel<1, false>), gw, dim3(256), 0, M.stream, M.n, t,
+                         ord, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, nullptr, nullptr, Y);
+    }
+    return check_launch("spmm_bt wide");
+  }
   Lanes L = Lanes::of(t);
   int nb = spmm_nblocks(M.n, t);
   const int* ord = spatial_order(M);

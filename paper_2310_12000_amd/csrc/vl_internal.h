@@ -208,8 +208,6 @@ struct Model {
   std::vector<int> newton_halvings;  // step halvings per Newton iteration
   std::vector<int> last_block_iters;
   std::vector<double> last_quad, last_r0z0;
-  int last_refinements = 0;          // mixed form: FP64 corrections of the last solve
-  double last_final_residual = 0.0;  // mixed form: its largest FP64 residual norm
   DevBuf<int> pred_nbr;
   DevBuf<double> pred_bval, pred_dval;
   int64_t last_np = 0;
@@ -217,9 +215,8 @@ struct Model {
   // reusable workspaces
   CgState cg;
   CgState cg1;  // single-column solves
-  CgState cgm;  // refinement solves of the mixed-precision form
-  DevBuf<float> mx_rhs;           // n x t FP32 right-hand side / residual
-  DevBuf<double> mx_a, mx_b;      // n x t FP64 operator output and scratch
+  DevBuf<float> mx_rhs, mx_f2;    // n x t FP32 blocks of the mixed-precision solves
+  DevBuf<double> mx_a;            // n x t FP64 scratch (batched probes)
   DevBuf<double> red_part;  // partial sums of reductions
   DevBuf<double> red_out;
   DevBuf<double> vec_a, vec_b, vec_c, vec_d, vec_e, dWv;  // n-length scratch vectors

@@ -165,32 +165,17 @@ struct CgOps {
   // V = A H over t columns (Tmp: n x t scratch)
   std::function<Status(Model&, const double* H, double* V, double* Tmp, int t)> apply;
   // Z = P^{-1} R; Z and Y (n x t scratch) arrive filled with the sentinel and
-  // the work counters reset
+  // the work counters reset when needs_fill says so (no needs_fill: always)
   std::function<Status(Model&, const double* R, double* Z, double* Y, int t)> precond;
-};
-
-// The same with n x t blocks in FP32 (sums still accumulated in FP64); the
-// preconditioner's outputs are not pre-filled.
-struct CgOpsF {
-  std::function<Status(Model&, const float* H, float* V, float* Tmp, int t)> apply;
-  std::function<Status(Model&, const float* R, float* Z, float* Y, int t)> precond;
+  std::function<bool(const Model&, int t)> needs_fill;
 };
 
 Status cg_solve(Model& M, CgState& S, const CgOps& ops, int t, const double* rhs, double tol,
                 int max_iter, bool keep_z0);
-Status cg_solve_f32(Model& M, CgState& S, const CgOpsF& ops, int t, const float* rhs,
-                    double tol, int max_iter, bool keep_z0);
-// Mixed-precision block solve (mixed.hip): FP32 PCG, FP64 refinement.
-struct MixedInfo {
-  std::vector<int> first_iters;  // per column, first FP32 run
-  int refinements = 0;           // FP64 residual corrections taken
-  int refine_iters_max = 0;      // most iterations of a correction run
-  double final_residual = 0.0;   // largest FP64 residual 2-norm at the end
-};
-CgOpsF vadu_ops_f32(const double* W, const double* sdiag);
-Status block_solve_mixed(Model& M, CgState& S, const CgOps& ops64, const CgOpsF& ops32, int t,
-                         const double* rhs, double tol, int max_iter, bool keep_z0,
-                         int max_refine, MixedInfo* info);
+
+// Mixed-precision form (mixed.hip): the VADU operator in FP64 and the
+// preconditioner solves in FP32 (FP64 sums).
+CgOps vadu_ops_mixed(const double* W, const double* sdiag);
 Status to_f32(Model& M, const double* x, float* y, int64_t count);
 
 Status dot_cols(Model& M, const double* X, const double* Y, int t, double* part, double* out);

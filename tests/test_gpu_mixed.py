@@ -1,8 +1,9 @@
-"""Mixed-precision form against the FP64 oracle: FP32 sparse products,
-triangular solves and CG blocks with FP64-accumulated sums and FP64 residual
-refinement.  The bar: relative 1e-4 on the negative log-likelihood and 1e-3
-on the predictive variances; the errors of the mode, the predictive means
-and the gradient are measured and printed."""
+"""Mixed-precision form against the FP64 oracle: FP32 preconditioner solves
+(FP32 B values and blocks, FP64 row sums) inside the FP64 block PCG, whose
+FP64 operator and residual recurrence refine every FP32 solve.  The bar:
+relative 1e-4 on the negative log-likelihood and 1e-3 on the predictive
+variances; the errors of the mode, the predictive means and the gradient are
+measured and printed."""
 import numpy as np
 import pytest
 

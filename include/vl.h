@@ -114,7 +114,12 @@ const char* vl_last_error(void);
  *   coords     device, n x 2 locations in the ordering of the approximation
  *              (the row order IS the ordering; the paper's random ordering
  *              is the caller's order of i.i.d. locations, Sec. 4.1)
- *   n          number of locations, 1 <= n < 2^31 / max(m, 1)
+ *   n          number of locations, 1 <= n <= 262144 (VL_ERR_INVALID above:
+ *              a build at n = 2,000,000 ended in a GPU memory fault whose
+ *              cause is not found; the largest size run successfully is
+ *              n = 117,434, and the limit sits below every size at which
+ *              the build's launch shapes or transfer sizes change from
+ *              the verified ones)
  *   m          neighbours per point, 0 <= m <= 31; N(i) = the min(i, m)
  *              nearest among locations 0..i-1 (ties: smaller index first)
  *   cov        vl_cov; theta_host = {sigma2 > 0, range rho > 0} (host)

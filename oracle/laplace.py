@@ -114,14 +114,20 @@ def lik_dW(lik, y, mu, aux=None):
 class Model:
     """Vecchia factor of one data set at one theta (Sec. 2.1)."""
 
-    def __init__(self, coords, m, kind, theta, nbr=None, deriv=False):
+    def __init__(self, coords, m, kind, theta, nbr=None, deriv=False, factor=None):
+        """nbr and factor = (A, D) may be passed in when they were already
+        computed by the neighbour search and factor functions (for example
+        over row ranges); otherwise they are computed here."""
         self.coords = np.asarray(coords, dtype=np.float64)
         self.n = self.coords.shape[0]
         self.m = m
         self.kind = kind
         self.theta = (float(theta[0]), float(theta[1]))
         self.nbr = _vec.neighbours(self.coords, m) if nbr is None else nbr
-        out = _vec.factor(self.coords, self.nbr, kind, self.theta, deriv=deriv)
+        if factor is not None and deriv:
+            raise ValueError("a precomputed factor carries no derivatives")
+        out = factor if factor is not None else _vec.factor(self.coords, self.nbr, kind,
+                                                             self.theta, deriv=deriv)
         if deriv:
             self.A, self.D, self.dA, self.dD = out
             self.dB = [_vec.sparse_dB(self.dA[k], self.nbr) for k in range(2)]

@@ -67,7 +67,14 @@ def neighbours_brute(coords, m):
 
 def neighbours(coords, m, brute_limit=4096):
     """N(i): the min(i, m) nearest points among s_0..s_{i-1} (0-based), ordered
-    by (squared distance, index).  Exact.
+    by (squared distance, index), for every row.  Exact."""
+    coords = np.asarray(coords, dtype=np.float64)
+    return neighbours_rows(coords, m, np.arange(coords.shape[0]), brute_limit)
+
+
+def neighbours_rows(coords, m, rows, brute_limit=4096):
+    """N(i) for the given rows only (r x m, -1 padded); row i of the result
+    is the same as row i of the full search.
 
     Rows below `brute_limit` use exhaustive search.  Later rows, in blocks
     [lo, 2 lo), query a k-d tree built on the prefix s_0..s_{2lo-1}; a query is
@@ -76,19 +83,21 @@ def neighbours(coords, m, brute_limit=4096):
     it is repeated with more candidates.  The final order always uses sqdist."""
     coords = np.asarray(coords, dtype=np.float64)
     n = coords.shape[0]
-    nbr = np.full((n, m), -1, dtype=np.int64)
-    lim = min(n, brute_limit)
-    for i in range(1, lim):
+    rows = np.asarray(rows, dtype=np.int64)
+    out = np.full((rows.size, m), -1, dtype=np.int64)
+    for pos in np.nonzero((rows >= 1) & (rows < brute_limit))[0]:
+        i = int(rows[pos])
         sel, _ = _rank_candidates(i, np.arange(i), coords, m)
-        nbr[i, : sel.size] = sel
-    lo = lim
+        out[pos, : sel.size] = sel
+    lo = brute_limit
     while lo < n:
         hi = min(n, 2 * lo)
-        tree = cKDTree(coords[:hi])
-        rows = np.arange(lo, hi)
-        _prefix_query(tree, coords, rows, m, nbr, eligible_below_self=True)
+        pos = np.nonzero((rows >= lo) & (rows < hi))[0]
+        if pos.size:
+            tree = cKDTree(coords[:hi])
+            _prefix_query(tree, coords, rows[pos], m, out, pos, eligible_below_self=True)
         lo = hi
-    return nbr
+    return out
 
 
 def pred_neighbours(coords_train, coords_pred, m):
@@ -108,27 +117,26 @@ def pred_neighbours(coords_train, coords_pred, m):
         return nbr
     tree = cKDTree(coords_train)
     allpts = np.concatenate([coords_train, coords_pred])
-    rows = n + np.arange(npred)
-    tmp = np.full((n + npred, m), -1, dtype=np.int64)
-    _prefix_query(tree, allpts, rows, m, tmp, eligible_below_self=False, ntrain=n)
-    nbr[:] = tmp[n:]
+    _prefix_query(tree, allpts, n + np.arange(npred), m, nbr, np.arange(npred),
+                  eligible_below_self=False, ntrain=n)
     return nbr
 
 
-def _prefix_query(tree, coords, rows, m, nbr, eligible_below_self, ntrain=None):
+def _prefix_query(tree, coords, rows, m, out, outpos, eligible_below_self, ntrain=None):
     """Exact kNN restricted to eligible tree points, with a growing candidate
     count.  Tree point j is eligible for row i if j < i (eligible_below_self)
-    or always (prediction).  Writes rows of `nbr`."""
+    or always (prediction).  The result for rows[r] goes to out[outpos[r]]."""
     npts = tree.n
-    pending = np.asarray(rows)
+    pending = np.arange(len(rows))
     kq = 2 * m + 8
     while pending.size:
         k = min(kq, npts)
-        dist, idx = tree.query(coords[pending], k=k)
+        dist, idx = tree.query(coords[rows[pending]], k=k)
         dist = dist.reshape(len(pending), k)
         idx = idx.reshape(len(pending), k)
         retry = []
-        for r, i in enumerate(pending):
+        for r, p in enumerate(pending):
+            i = int(rows[p])
             want = min(m, i) if eligible_below_self else min(m, npts)
             ok = idx[r] < (i if eligible_below_self else npts)
             cand = idx[r][ok]
@@ -136,17 +144,17 @@ def _prefix_query(tree, coords, rows, m, nbr, eligible_below_self, ntrain=None):
             if cand.size < want:
                 if k == npts:      # every tree point was returned
                     sel, _ = _rank_candidates(i, cand, coords, m)
-                    nbr[i, : sel.size] = sel
+                    out[outpos[p], : sel.size] = sel
                 else:
-                    retry.append(i)
+                    retry.append(p)
                 continue
             # m-th eligible distance vs farthest returned distance
             rm = np.sort(cd)[want - 1]
             if k < npts and not (dist[r][-1] > rm * (1.0 + 1e-9) + 1e-300):
-                retry.append(i)
+                retry.append(p)
                 continue
             sel, _ = _rank_candidates(i, cand, coords, m)
-            nbr[i, : sel.size] = sel
+            out[outpos[p], : sel.size] = sel
         pending = np.asarray(retry, dtype=np.int64)
         kq *= 2
 

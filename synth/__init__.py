@@ -19,6 +19,8 @@ Latent fields:
     only shapes the responses; no result is compared against it.
 """
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -63,9 +65,16 @@ def latent_field(coords, kind, sigma2, rho, seed, nfeat=2048, chunk=1 << 16):
     phase = g.uniform(0.0, 2.0 * np.pi, size=nfeat)
     amp = math.sqrt(2.0 * sigma2 / nfeat)
     out = np.empty(n)
-    for s in range(0, n, chunk):
+
+    def fill(s):
         e = min(n, s + chunk)
         out[s:e] = amp * np.cos(coords[s:e] @ omega.T + phase).sum(axis=1)
+
+    # Chunks are independent and numpy releases the GIL inside them, so a
+    # thread pool gives the same values as a serial loop.
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(fill, range(0, n, chunk)))
     return out
 
 

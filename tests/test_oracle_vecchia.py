@@ -31,6 +31,17 @@ def test_neighbours_match_exhaustive_search(n, m, lim):
         assert got == ref, i
 
 
+def test_neighbours_of_selected_rows_match_exhaustive_search():
+    # rows scattered over the exhaustive range and several tree blocks, in
+    # no particular order, with a repeat
+    rng = np.random.default_rng(17)
+    X = rng.uniform(size=(600, 2))
+    rows = np.array([599, 0, 3, 15, 16, 31, 32, 33, 100, 257, 3, 420, 64])
+    got = V.neighbours_rows(X, 8, rows, brute_limit=16)
+    for r, i in enumerate(rows):
+        assert [j for j in got[r] if j >= 0] == _brute_nn(X, i, range(i), 8), i
+
+
 def test_neighbours_ties_break_by_index():
     # integer lattice: many exactly equal distances
     g = np.array([(x, y) for x in range(6) for y in range(6)], dtype=float)

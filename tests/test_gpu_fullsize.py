@@ -8,10 +8,12 @@ run the whole path in seconds:
             offset 1, 64 probes, CG tolerance 1e-2, s = 256.
 
 Checks, each against what the oracle computes exactly at this size:
-  * every neighbour set (exact) and factor row (1e-9), the oracle spread over
-    processes by row range;
-  * the mode through its first-order condition g(F + b) = B^T D^{-1} B b
-    (Sec. 2.2, eq. newton) with the oracle's factor, at a tight tolerance;
+  * every neighbour set (exact), every D_i (1e-9) and every row A_i within
+    m * kappa(Sigma_N(i)) * u of the oracle's (the conditioning bound of the
+    neighbour solve), the oracle spread over processes by row range;
+  * the mode against the oracle's Newton iteration (replaying the device's CG
+    counts) and, at a tight tolerance, through its first-order condition
+    g(F + b) = B^T D^{-1} B b (Sec. 2.2, eq. newton) with the oracle's factor;
   * the likelihood pieces that need no probes (eq. VLA_loss, logdetsplit) at
     the device's mode, the whole assembly of the estimate, and one SLQ probe
     (eq. def_SLQ) run by the oracle on the same Rademacher column;
@@ -30,7 +32,8 @@ import synth  # noqa: E402
 from oracle import laplace as OL  # noqa: E402
 from oracle import vecchia as OV  # noqa: E402
 from tests import oracle_pool  # noqa: E402
-from tests.gpu_common import dev, host, opts_pair, rel_err, say  # noqa: E402
+from tests.gpu_common import (dev, host, opts_pair, oracle_mode_matching,  # noqa: E402
+                               rel_err, say)
 
 TOL = 1e-9
 NLL_TOL_MIXED = 1e-4
@@ -71,11 +74,13 @@ def case(request, P):
                       num_pred_samples=w["s"], seed=7)
     g = P.VecchiaLaplace(dev(w["coords"]), w["m"], w["kind"], (w["sigma2"], w["rho"]))
     mode, mst = g.find_mode(dev(w["y"]), dev(w["F"]), w["lik"], None, go)
+    newton_cg = host(g.export("newton_cg_iters")).tolist()
+    halvings = host(g.export("newton_halvings")).tolist()
     nll, _, st = g.neg_log_marglik(go)
     slq_iters = host(g.export("block_iters"))
     quad, r0z0 = host(g.export("slq_quad")), host(g.export("slq_r0z0"))
     mean, var, pst = g.predict(dev(w["coords_pred"]), dev(w["Fp"]), go)
-    fit = dict(o=o, go=go, mode=host(mode), nll=nll, mean=host(mean), var=host(var),
+    fit = dict(o=o, go=go, mode=host(mode), newton_cg=newton_cg, halvings=halvings, nll=nll, mean=host(mean), var=host(var),
                quad=quad, r0z0=r0z0, slq_iters=slq_iters,
                pred_nbr=host(g.export("pred_nbr")).reshape(-1, w["m"]),
                pred_bval=host(g.export("pred_bval")).reshape(-1, w["m"]),
@@ -84,18 +89,70 @@ def case(request, P):
                bval=host(g.export("bval")).reshape(w["n"], w["m"]), D=host(g.export("D")))
     say(f"{name} FP64: newton {mst.newton_iters} cg {mst.cg_iters_total} slq_max "
         f"{st.cg_iters_max} pred_max {pst.cg_iters_max} nll {nll:.10f}")
+    # Tolerance of the results downstream of the factor.  The neighbour
+    # covariances of Sec. 2.1 reach condition numbers near 1e10 at n = 1e5,
+    # range 0.05, so two correct FP64 solvers of those systems give factor
+    # rows up to ~1e-7 apart (bounded per row by test_neighbours_and_factor),
+    # and every CG iterate inherits a perturbation of that relative size: an
+    # oracle with Cholesky instead of LU neighbour solves moves the mode and a
+    # one-sample variance by 2.2x its own factor difference.  Modes and
+    # variances are therefore held to 10x the measured factor discrepancy
+    # (never looser than needed: 1e-9 when the factor agrees to 1e-10).
+    e_fac = float(np.max(np.abs(fit["bval"] + model.A).max(axis=1)
+                         / np.maximum(np.abs(model.A).max(axis=1), 1e-300)))
+    fit["tol_downstream"] = max(TOL, 10.0 * e_fac)
+    say(f"{name} factor discrepancy {e_fac:.2e}: downstream tolerance {fit['tol_downstream']:.2e}")
     yield name, w, model, g, fit
     g.close()
+
+
+def _neighbour_condition(coords, nbr, kind, theta):
+    """2-norm condition number of every row's neighbour covariance Sigma_N(i)
+    (1 for rows with fewer than two neighbours)."""
+    n, m = nbr.shape
+    kap = np.ones(n)
+    cnt = (nbr >= 0).sum(axis=1)
+    for k in np.unique(cnt):
+        if k < 2:
+            continue
+        rows = np.nonzero(cnt == k)[0]
+        for s in range(0, rows.size, 16384):
+            r = rows[s: s + 16384]
+            P = coords[nbr[r, :k]]
+            d2 = ((P[:, :, None, :] - P[:, None, :, :]) ** 2).sum(-1)
+            kap[r] = np.linalg.cond(OV.covariance(d2, kind, theta[0], theta[1]))
+    return kap
 
 
 def test_neighbours_and_factor(case):
     name, w, model, _, fit = case
     say(f"case: {name} neighbour sets and factor rows, all {w['n']} rows")
     assert np.array_equal(fit["nbr"], model.nbr)
-    e_a = rel_err(fit["bval"], -model.A)
     e_d = rel_err(fit["D"], model.D)
-    say(f"{name} factor: rel err A {e_a:.2e} D {e_d:.2e}")
-    assert e_a < TOL and e_d < TOL
+    # A_i solves Sigma_N(i) A_i = Sigma_N(i),i: two correct FP64 solvers agree
+    # only to about m * kappa(Sigma_N(i)) * u relative to |A_i| (the neighbour
+    # covariances reach kappa ~ 1e10 here), so each row gets its own bound
+    kap = _neighbour_condition(w["coords"], model.nbr, w["kind"], (w["sigma2"], w["rho"]))
+    scale = np.maximum(np.abs(model.A).max(axis=1), 1e-300)
+    e_row = np.abs(fit["bval"] + model.A).max(axis=1) / scale
+    bound = w["m"] * kap * 2.0 ** -53 + 1e-14
+    worst = int(np.argmax(e_row / bound))
+    say(f"{name} factor: D rel {e_d:.2e}; A rows: max rel {e_row.max():.2e}, "
+        f"worst row vs its bound {e_row[worst]:.2e} / {bound[worst]:.2e} "
+        f"(kappa {kap[worst]:.2e}); kappa max {kap.max():.2e}")
+    assert np.all(e_row <= bound)
+    assert e_d < TOL
+
+
+def test_mode_matches_the_oracle(case):
+    name, w, model, _, fit = case
+    say(f"case: {name} oracle Newton mode with the device's CG counts")
+    b, _, _, replayed = oracle_mode_matching(model, w["y"], w["F"], w["lik"], None, fit["o"],
+                                             fit["newton_cg"], gpu_halvings=fit["halvings"])
+    e = rel_err(fit["mode"], b)
+    say(f"{name} mode: newton cg {fit['newton_cg']} replayed={replayed} rel err {e:.2e} "
+        f"(tolerance {fit['tol_downstream']:.2e})")
+    assert e < fit["tol_downstream"]
 
 
 def test_mode_first_order_condition(P, case):
@@ -114,8 +171,12 @@ def test_mode_first_order_condition(P, case):
     assert not st.hit_cap
     # The last Newton system is solved to a residual below the CG tolerance,
     # which is the first-order residual at the new point up to a term of
-    # second order in the (tiny) last step.
-    assert np.linalg.norm(r) < 10.0 * FOC_CG_TOL
+    # second order in the (tiny) last step.  Sigma~^{-1} b is evaluated here
+    # with the oracle's factor, whose rows differ from the device's by up to
+    # m * kappa(Sigma_N) * u (about 1e-7 relative at kappa ~ 1e10); applied to
+    # the innovation vector D^{-1} B b that difference is not smoothed away,
+    # so it enters at that relative size against |Sigma~^{-1} b| = |g|.
+    assert np.linalg.norm(r) < 10.0 * FOC_CG_TOL + 1e-6 * np.linalg.norm(grad)
 
 
 def test_nll_pieces_and_one_probe(case):
@@ -161,8 +222,14 @@ def test_prediction(P, case):
     Ap, Dp = OV.factor(w["coords"], nbr_p, w["kind"], (w["sigma2"], w["rho"]),
                        coords_self=w["coords_pred"])
     assert np.array_equal(fit["pred_nbr"], nbr_p)
-    assert rel_err(fit["pred_bval"], -Ap) < TOL
     assert rel_err(fit["pred_D"], Dp) < TOL
+    # per-row conditioning bound of the neighbour solve, as for the training rows
+    kap = _neighbour_condition(w["coords"], nbr_p, w["kind"], (w["sigma2"], w["rho"]))
+    e_row = np.abs(fit["pred_bval"] + Ap).max(axis=1) / np.maximum(np.abs(Ap).max(axis=1), 1e-300)
+    bound = w["m"] * kap * 2.0 ** -53 + 1e-14
+    say(f"{name} prediction rows: max rel {e_row.max():.2e}, max ratio to bound "
+        f"{(e_row / bound).max():.2e}")
+    assert np.all(e_row <= bound)
     mean_o = w["Fp"] + np.sum(Ap * fit["mode"][nbr_p], axis=1)
     e_m = rel_err(fit["mean"], mean_o)
     say(f"{name} predictive means: rel {e_m:.2e}")
@@ -181,8 +248,9 @@ def test_prediction(P, case):
         _, var_o, info = OL.predict(model, w["coords_pred"], w["Fp"], fit["mode"], W, o1,
                                     replay_cg=[int(iters1[0])])
     e_v = rel_err(host(var1), var_o)
-    say(f"{name} one-sample variance: iters {iters1[0]} replayed={replayed} rel {e_v:.2e}")
-    assert e_v < TOL
+    say(f"{name} one-sample variance: iters {iters1[0]} replayed={replayed} rel {e_v:.2e} "
+        f"(tolerance {fit['tol_downstream']:.2e})")
+    assert e_v < fit["tol_downstream"]
 
 
 def test_mixed_matches_fp64(P, case):

@@ -177,13 +177,17 @@ def test_trsm_head_and_tail(P, t):
     # n above the head size: for t <= 64 rows solved in LDS level by level,
     # the rest by the sync-free tail kernels; wider blocks (65, 300: one and
     # two column slices, ragged) take the level-scheduled launches.  The
-    # reference solves with the oracle's factor.
+    # reference solves with the oracle's factor.  The range (0.005, about the
+    # spacing of the points) keeps every neighbour covariance well conditioned,
+    # so the two factors agree to rounding and the comparison isolates the
+    # solve; the neighbour sets, and with them the dependency DAG the kernels
+    # schedule, do not depend on the range.
     n, m = 40000, 20
     say(f"case: trsm head+tail n={n} t={t}")
     X = synth.locations(n, seed=11)
-    g = P.VecchiaLaplace(dev(X), m, OV.COV_MATERN32, (1.0, 0.05))
+    g = P.VecchiaLaplace(dev(X), m, OV.COV_MATERN32, (1.0, 0.005))
     nbr = OV.neighbours(X, m)
-    A, _ = OV.factor(X, nbr, OV.COV_MATERN32, (1.0, 0.05))
+    A, _ = OV.factor(X, nbr, OV.COV_MATERN32, (1.0, 0.005))
     assert np.array_equal(host(g.export("nbr")).reshape(n, m), nbr)
     assert rel_err(host(g.export("bval")).reshape(n, m), -A) < TOL
     B = OV.sparse_B(A, nbr)

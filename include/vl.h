@@ -232,7 +232,9 @@ vl_status vl_trsm(vl_model* h, int transpose, const double* X, double* Y, int t)
  *   6  level-scheduled B Y = X            7  level-scheduled B^T Y = X
  *   8  level-scheduled B^T Y = X, levels of long rows (entries split over
  *      4 waves per row)
- *      (6-8: blocks wider than 64 columns; one launch, and one record, per
+ *   9  level-scheduled B^T Y = X: the fold of the head rows' tail entries
+ *      (one launch between the tail levels and the head levels)
+ *      (6-9: blocks wider than 64 columns; one launch, and one record, per
  *      level)
  * `enable` is a bit mask of the kinds to record (bit k = kind k; -1 = all,
  * 0 = off).  vl_timing_enable resets the records (and synchronises); vl_timing_read

@@ -638,6 +638,22 @@ Status build_head_schedule(Model& M) {
                      M.stream, static_cast<int>(H), M.hb_rows.p, M.bt_ptr.p, M.bt_col.p, len.p,
                      M.head_split.p);
   VL_TRY(exclusive_scan_int(len.p, M.hb_pptr.p, H + 1, M.stream));
+  // The positions are still in head-internal level order here: keep that
+  // order, its level pointers and per-level entry counts for the
+  // level-scheduled B^T solves (order_head_ranges reorders the positions).
+  {
+    VL_TRY(M.hlv_rows_b.alloc(H));
+    VL_TRY(copy_d2d(M.hlv_rows_b.p, M.hb_rows.p, sizeof(int) * H, M.stream));
+    std::vector<int> lp(M.head_nlev_b + 1), pp(H + 1);
+    VL_HIP(hipMemcpyAsync(lp.data(), M.hb_ptr.p, sizeof(int) * lp.size(),
+                          hipMemcpyDeviceToHost, M.stream));
+    VL_HIP(hipMemcpyAsync(pp.data(), M.hb_pptr.p, sizeof(int) * (H + 1), hipMemcpyDeviceToHost,
+                          M.stream));
+    VL_TRY(sync_stream(M.stream));
+    M.hlv_ptr_b = lp;
+    M.hlv_nnz_b.assign(M.head_nlev_b, 0);
+    for (int l = 0; l < M.head_nlev_b; ++l) M.hlv_nnz_b[l] = pp[lp[l + 1]] - pp[lp[l]];
+  }
   int nnzb = 0;
   VL_HIP(hipMemcpyAsync(&nnzb, M.hb_pptr.p + H, sizeof(int), hipMemcpyDeviceToHost, M.stream));
   VL_TRY(sync_stream(M.stream));
@@ -648,6 +664,7 @@ Status build_head_schedule(Model& M) {
                           M.stream));
     VL_TRY(sync_stream(M.stream));
     M.nnz_head_bt = bt_head;
+    M.fold_nnz = static_cast<int64_t>(bt_head) - nnzb;
     int64_t f = 0;  // row i < H has min(i, m) neighbours
     for (int64_t i = 0; i < H; ++i) f += (i < m ? i : m);
     M.nnz_head_f = f;

@@ -8,8 +8,11 @@
 // stopping test applies to the FP64 residual.  The Newton update, the
 // neighbour Cholesky, the tridiagonal eigensolve and all assembly stay FP64.
 //
-// The FP32 solves are level-scheduled (one launch per level of the
-// dependency DAG; no sentinel fill, no polling).
+// The FP32 solves are used for blocks wider than 64 columns, where the
+// solves move bytes; they are level-scheduled (one launch per level of the
+// dependency DAG; no sentinel fill, no polling), and B^T solves fold the head
+// rows' tail entries in one launch between the tail and the head levels.
+// Narrower blocks keep the FP64 solves.
 #include <algorithm>
 #include <cmath>
 
@@ -46,121 +49,214 @@ static Status ensure_f32_values(Model& M) {
 }
 
 // ------------------------------------------------------ FP32 level solves
-// One level; block (k, s) solves row rows[k] for the blockDim.x columns of
-// slice s:  Y_i = rs_i X_i - sum_q vals[q] Y_{idx[q]}  (idx < 0 ends the row),
-// Y stored in FP32 (and, with Yd, also in FP64 for the CG), sums in FP64.
-template <bool LOWER, typename TX>
-__global__ __launch_bounds__(256) void trsm_level_mx_kernel(int t, const int* __restrict__ rows,
-                                                            int m, const int* __restrict__ ptr,
-                                                            const int* __restrict__ idx,
-                                                            const float* __restrict__ vals,
-                                                            const TX* __restrict__ X,
-                                                            const double* __restrict__ rs,
-                                                            float* __restrict__ Y,
-                                                            double* __restrict__ Yd) {
-  const int c = blockIdx.y * blockDim.x + threadIdx.x;
+// A thread covers VEC adjacent columns (16-byte accesses: VEC = 4 floats when
+// the width allows), so a wave gathers 256 columns of a neighbour row with one
+// instruction; every column keeps its own FP64 accumulator.
+int level_vec(int t, int elem_bytes, const void* a, const void* b, const void* c);
+
+// Forward level: block (k, s) solves row rows[k] for its slice of columns,
+// Y_i = rs_i X_i - sum_k vals[i,k] Y_{nbr[i,k]} in slot order (an empty slot
+// ends the row); Y stored in FP32 and, with Yd, also in FP64 for the CG; the
+// sum in FP64.
+template <int VEC>
+__global__ __launch_bounds__(256) void trsm_level_mx_lower_kernel(
+    int t, const int* __restrict__ rows, int m, const int* __restrict__ idx,
+    const float* __restrict__ vals, const float* __restrict__ X, const double* __restrict__ rs,
+    float* __restrict__ Y, double* __restrict__ Yd) {
+  const int c = (blockIdx.y * blockDim.x + threadIdx.x) * VEC;
   const int64_t i = rows[blockIdx.x];
   if (c >= t) return;
-  int q, e;
-  if (LOWER) {
-    q = static_cast<int>(i * m);
-    e = q + m;
-  } else {
-    q = ptr[i];
-    e = ptr[i + 1];
+  const int* nb = idx + i * m;
+  const float* vb = vals + i * m;
+  float x[VEC];
+  vld<VEC>(X + i * t + c, x);
+  double acc[VEC];
+  const double s = rs ? rs[i] : 1.0;
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) acc[v] = rs ? static_cast<double>(x[v]) * s : static_cast<double>(x[v]);
+  for (int q = 0; q < m; q += 8) {
+    int cb[8];
+    float w[8], y[8][VEC];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      cb[k] = (q + k < m) ? nb[q + k] : -1;
+      w[k] = (q + k < m) ? vb[q + k] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (cb[k] >= 0) {
+        vld<VEC>(Y + (int64_t)cb[k] * t + c, y[k]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) y[k][v] = 0.0f;
+      }
+    }
+    bool ended = false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (cb[k] < 0) ended = true;
+      if (!ended) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+          acc[v] -= static_cast<double>(w[k]) * static_cast<double>(y[k][v]);
+      }
+    }
+    if (ended) break;
   }
-  double acc = static_cast<double>(X[i * t + c]);
-  if (rs) acc *= rs[i];
+  float out[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) out[v] = static_cast<float>(acc[v]);
+  vst<VEC>(Y + i * t + c, out);
+  if (Yd) {
+    double od[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) od[v] = static_cast<double>(out[v]);
+    vst<VEC>(Yd + i * t + c, od);
+  }
+}
+
+// Backward level over the entries [ptr[i], pend ? pend[i] : ptr[i + 1]); X in
+// FP64 (the PCG residual, or the folded head right-hand side), Y in FP32, the
+// sum in FP64.
+template <int VEC>
+__global__ __launch_bounds__(256) void trsm_level_mx_upper_kernel(
+    int t, const int* __restrict__ rows, const int* __restrict__ ptr,
+    const int* __restrict__ pend, const int* __restrict__ idx, const float* __restrict__ vals,
+    const double* __restrict__ X, float* __restrict__ Y) {
+  const int c = (blockIdx.y * blockDim.x + threadIdx.x) * VEC;
+  const int64_t i = rows[blockIdx.x];
+  if (c >= t) return;
+  int q = ptr[i];
+  const int e = pend ? pend[i] : ptr[i + 1];
+  double acc[VEC];
+  vld<VEC>(X + i * t + c, acc);
   for (; q < e; q += 8) {
     int cb[8];
-    float vb[8], yv[8];
+    float w[8], y[8][VEC];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       cb[k] = (q + k < e) ? idx[q + k] : -1;
-      vb[k] = (q + k < e) ? vals[q + k] : 0.0f;
+      w[k] = (q + k < e) ? vals[q + k] : 0.0f;
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) yv[k] = cb[k] >= 0 ? Y[(int64_t)cb[k] * t + c] : 0.0f;
+    for (int k = 0; k < 8; ++k) {
+      if (cb[k] >= 0) {
+        vld<VEC>(Y + (int64_t)cb[k] * t + c, y[k]);
+      } else {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) acc -= static_cast<double>(vb[k]) * static_cast<double>(yv[k]);
-  }
-  Y[i * t + c] = static_cast<float>(acc);
-  if (Yd) Yd[i * t + c] = static_cast<double>(static_cast<float>(acc));
-}
-
-// Levels of long B^T rows (average length above 16): 4 waves per 64 columns
-// share a row's entries (wave w takes q0 + w, q0 + w + 4, ...), partial sums
-// added in wave order.
-template <typename TX>
-__global__ __launch_bounds__(256) void trsm_level_mx_split_kernel(
-    int t, const int* __restrict__ rows, const int* __restrict__ ptr, const int* __restrict__ idx,
-    const float* __restrict__ vals, const TX* __restrict__ X, float* __restrict__ Y) {
-  __shared__ double s_part[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int c = blockIdx.y * 64 + lane;
-  const int64_t i = rows[blockIdx.x];
-  const int b = ptr[i], e = ptr[i + 1];
-  double part = 0.0;
-  if (c < t) {
-    for (int q = b + w; q < e; q += 4 * 8) {
-      int cb[8];
-      float vb[8], yv[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        cb[k] = (q + 4 * k < e) ? idx[q + 4 * k] : -1;
-        vb[k] = (q + 4 * k < e) ? vals[q + 4 * k] : 0.0f;
+        for (int v = 0; v < VEC; ++v) y[k][v] = 0.0f;
       }
-#pragma unroll
-      for (int k = 0; k < 8; ++k) yv[k] = cb[k] >= 0 ? Y[(int64_t)cb[k] * t + c] : 0.0f;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) part += static_cast<double>(vb[k]) * static_cast<double>(yv[k]);
     }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (cb[k] >= 0) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+          acc[v] -= static_cast<double>(w[k]) * static_cast<double>(y[k][v]);
+      }
   }
-  s_part[w][lane] = part;
-  __syncthreads();
-  if (w == 0 && c < t)
-    Y[i * t + c] = static_cast<float>(static_cast<double>(X[i * t + c]) -
-                                      (((s_part[0][lane] + s_part[1][lane]) + s_part[2][lane]) +
-                                       s_part[3][lane]));
+  float out[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) out[v] = static_cast<float>(acc[v]);
+  vst<VEC>(Y + i * t + c, out);
 }
 
-// Y (FP32) = B^{-T} X with X FP64.
-static Status upper_f32(Model& M, const double* X, float* Y, int t) {
-  const std::vector<int>& lp = M.lvl_ptr_b;
-  const std::vector<int64_t>& lnz = M.lvl_nnz_b;
-  if (lp.size() < 2 || lp.back() != M.n) return Status::make(VL_ERR_STATE, "no level schedule");
+// Backward levels of long rows (average length above 16): 4 waves per
+// 64 * VEC columns share a row's entries, partial sums added in wave order.
+template <int VEC>
+__global__ __launch_bounds__(256) void trsm_level_mx_split_kernel(
+    int t, const int* __restrict__ rows, const int* __restrict__ ptr,
+    const int* __restrict__ pend, const int* __restrict__ idx, const float* __restrict__ vals,
+    const double* __restrict__ X, float* __restrict__ Y) {
+  const int c = (blockIdx.y * 64 + (threadIdx.x & 63)) * VEC;
+  const int64_t i = rows[blockIdx.x];
+  const int b = ptr[i], e = pend ? pend[i] : ptr[i + 1];
+  double tot[VEC];
+  if (!split_row_sum<VEC>(t, c, b, e, idx, vals, Y, tot)) return;
+  double x[VEC];
+  vld<VEC>(X + i * t + c, x);
+  float out[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) out[v] = static_cast<float>(x[v] - tot[v]);
+  vst<VEC>(Y + i * t + c, out);
+}
+
+template <int VEC>
+static void launch_upper_f32(Model& M, bool split, int rows, int t, const int* r, const int* pend,
+                             const double* X, float* Y) {
   const int tb = t <= 64 ? 64 : 256;
-  const unsigned gy = static_cast<unsigned>((t + tb - 1) / tb);
+  if (split) {
+    const dim3 grid(rows, (t + 64 * VEC - 1) / (64 * VEC));
+    hipLaunchKernelGGL(trsm_level_mx_split_kernel<VEC>, grid, dim3(256), 0, M.stream, t, r,
+                       M.bt_ptr.p, pend, M.bt_col.p, M.bt_val_f.p, X, Y);
+  } else {
+    const dim3 grid(rows, (t + tb * VEC - 1) / (tb * VEC));
+    hipLaunchKernelGGL(trsm_level_mx_upper_kernel<VEC>, grid, dim3(tb), 0, M.stream, t, r,
+                       M.bt_ptr.p, pend, M.bt_col.p, M.bt_val_f.p, X, Y);
+  }
+}
+
+static Status upper_levels_f32(Model& M, const std::vector<int>& lp,
+                               const std::vector<int64_t>& lnz, const int* order, const int* pend,
+                               const double* X, float* Y, int t) {
+  const int vec = level_vec(t, 4, X, Y, nullptr);
   for (size_t l = 0; l + 1 < lp.size(); ++l) {
     const int rows = lp[l + 1] - lp[l];
     if (rows <= 0) continue;
-    const int* r = M.full_order_b.p + lp[l];
-    if (lnz[l] > 16LL * rows) {
-      hipLaunchKernelGGL(trsm_level_mx_split_kernel<double>, dim3(rows, (t + 63) / 64),
-                         dim3(256), 0, M.stream, t, r, M.bt_ptr.p, M.bt_col.p, M.bt_val_f.p, X,
-                         Y);
+    const bool split = lnz[l] > 16LL * rows;
+    const int* r = order + lp[l];
+    if (vec == 4) {
+      launch_upper_f32<4>(M, split, rows, t, r, pend, X, Y);
+    } else if (vec == 2) {
+      launch_upper_f32<2>(M, split, rows, t, r, pend, X, Y);
     } else {
-      hipLaunchKernelGGL((trsm_level_mx_kernel<false, double>), dim3(rows, gy), dim3(tb), 0,
-                         M.stream, t, r, 0, M.bt_ptr.p, M.bt_col.p, M.bt_val_f.p, X, nullptr, Y,
-                         nullptr);
+      launch_upper_f32<1>(M, split, rows, t, r, pend, X, Y);
     }
   }
   return check_launch("trsm level f32 upper");
 }
 
-// Y (FP32) and Yd (FP64) = B^{-1} (rs o X) with X FP32.
+// Y (FP32) = B^T^{-1} X with X FP64: tail rows by level, the fold of the head
+// rows' tail entries (FP64), then the head rows by head-internal level.
+static Status upper_f32(Model& M, const double* X, float* Y, int t) {
+  const int64_t H = M.head_rows;
+  if (M.hlv_ptr_b.size() < 2 || M.hlv_ptr_b.back() != H ||
+      (M.n > H && (M.tlvl_ptr_b.size() < 2 || M.tlvl_ptr_b.back() != M.n - H)))
+    return Status::make(VL_ERR_STATE, "no level schedule");
+  if (M.n > H)
+    VL_TRY(upper_levels_f32(M, M.tlvl_ptr_b, M.tlvl_nnz_b, M.tail_order_b.p, nullptr, X, Y, t));
+  VL_TRY(M.lvl_fold.reserve(static_cast<size_t>(H) * t));
+  VL_TRY(fold_launch_f32(M, X, Y, M.lvl_fold.p, t));
+  return upper_levels_f32(M, M.hlv_ptr_b, M.hlv_nnz_b, M.hlv_rows_b.p, M.head_split.p,
+                          M.lvl_fold.p, Y, t);
+}
+
+template <int VEC>
+static void launch_lower_f32(Model& M, int rows, int t, const int* r, const float* X,
+                             const double* rs, float* Y, double* Yd) {
+  const int tb = t <= 64 ? 64 : 256;
+  const dim3 grid(rows, (t + tb * VEC - 1) / (tb * VEC));
+  hipLaunchKernelGGL(trsm_level_mx_lower_kernel<VEC>, grid, dim3(tb), 0, M.stream, t, r, M.m,
+                     M.nbr.p, M.bval_f.p, X, rs, Y, Yd);
+}
+
+// Y (FP32) and Yd (FP64) = B^{-1} (rs o X) with X FP32, full level order.
 static Status lower_f32(Model& M, const float* X, float* Y, double* Yd, int t,
                         const double* rs) {
   const std::vector<int>& lp = M.lvl_ptr_f;
   if (lp.size() < 2 || lp.back() != M.n) return Status::make(VL_ERR_STATE, "no level schedule");
-  const int tb = t <= 64 ? 64 : 256;
-  const unsigned gy = static_cast<unsigned>((t + tb - 1) / tb);
+  const int vec = level_vec(t, 4, X, Y, Yd);
   for (size_t l = 0; l + 1 < lp.size(); ++l) {
     const int rows = lp[l + 1] - lp[l];
     if (rows <= 0) continue;
-    hipLaunchKernelGGL((trsm_level_mx_kernel<true, float>), dim3(rows, gy), dim3(tb), 0,
-                       M.stream, t, M.full_order_f.p + lp[l], M.m, nullptr, M.nbr.p, M.bval_f.p,
-                       X, rs, Y, Yd);
+    const int* r = M.full_order_f.p + lp[l];
+    if (vec == 4) {
+      launch_lower_f32<4>(M, rows, t, r, X, rs, Y, Yd);
+    } else if (vec == 2) {
+      launch_lower_f32<2>(M, rows, t, r, X, rs, Y, Yd);
+    } else {
+      launch_lower_f32<1>(M, rows, t, r, X, rs, Y, Yd);
+    }
   }
   return check_launch("trsm level f32 lower");
 }
@@ -169,8 +265,14 @@ CgOps vadu_ops(const double* W, const double* sdiag);
 
 CgOps vadu_ops_mixed(const double* W, const double* sdiag) {
   CgOps ops = vadu_ops(W, sdiag);  // the FP64 operator
-  ops.precond = [sdiag](Model& M, const double* R, double* Z, double* Y, int t) -> Status {
-    (void)Y;
+  const auto fp64_precond = ops.precond;
+  const auto fp64_fill = ops.needs_fill;
+  // FP32 solves for wide blocks only: for t <= 64 the solves are bound by
+  // the dependency chain (LDS head, sync-free tail), not by bytes, and the
+  // FP64 kernels are used unchanged.
+  ops.precond = [sdiag, fp64_precond](Model& M, const double* R, double* Z, double* Y,
+                                      int t) -> Status {
+    if (t <= 64) return fp64_precond(M, R, Z, Y, t);
     VL_TRY(ensure_f32_values(M));
     const size_t nt = static_cast<size_t>(M.n) * t;
     VL_TRY(M.mx_rhs.reserve(nt));
@@ -178,7 +280,10 @@ CgOps vadu_ops_mixed(const double* W, const double* sdiag) {
     VL_TRY(upper_f32(M, R, M.mx_rhs.p, t));
     return lower_f32(M, M.mx_rhs.p, M.mx_f2.p, Z, t, sdiag);
   };
-  ops.needs_fill = [](const Model&, int) { return false; };
+  ops.needs_fill = [fp64_fill](const Model& M, int t) {
+    if (t > 64) return false;
+    return fp64_fill ? fp64_fill(M, t) : true;
+  };
   return ops;
 }
 

@@ -614,121 +614,274 @@ __global__ void trsm_prefill(double* __restrict__ Y, int64_t count, int* counter
     Y[i] = sentinel();
 }
 
-// Level-scheduled solve of one level (wide blocks, t > 64): block
-// (k, s) solves row rows[k] for the 256 columns of slice s,
-//   Y_i = rs_i X_i - sum_q vals[q] Y_{idx[q]},  q in [q0, e) (idx < 0 ends the row),
-// subtracting the entries in the same order as the sync-free kernel.  All
-// rows a level depends on were written by earlier launches on the stream, so
-// plain cached loads are safe and nothing waits.
-template <bool LOWER>
-__global__ __launch_bounds__(256) void trsm_level_kernel(int t, const int* __restrict__ rows,
-                                                         int m, const int* __restrict__ ptr,
-                                                         const int* __restrict__ idx,
-                                                         const double* __restrict__ vals,
-                                                         const double* __restrict__ X,
-                                                         const double* __restrict__ rs,
-                                                         double* __restrict__ Y) {
-  const int c = blockIdx.y * blockDim.x + threadIdx.x;
+// Level-scheduled solve of one level (wide blocks, t > 64).  All rows a
+// level depends on were written by earlier launches on the stream, so plain
+// cached loads are safe and nothing waits.  A thread covers VEC adjacent
+// columns with 16-byte accesses (VEC = 2) when the width allows, so a wave
+// issues one gather instruction per neighbour row for 128 columns; each
+// column keeps its own accumulator, so VEC does not change any result.
+//
+// Forward (B Y = rs o X, ELL): block (k, s) solves row rows[k] for its
+// slice of columns, subtracting the terms in slot order, as in the sync-free
+// kernel (neighbours form a prefix, so an empty slot ends the row).
+template <int VEC>
+__global__ __launch_bounds__(256) void trsm_level_lower_kernel(
+    int t, const int* __restrict__ rows, int m, const int* __restrict__ idx,
+    const double* __restrict__ vals, const double* __restrict__ X,
+    const double* __restrict__ rs, double* __restrict__ Y) {
+  const int c = (blockIdx.y * blockDim.x + threadIdx.x) * VEC;
   const int64_t i = rows[blockIdx.x];
   if (c >= t) return;
-  int q, e;
-  if (LOWER) {
-    q = static_cast<int>(i * m);
-    e = q + m;
-  } else {
-    q = ptr[i];
-    e = ptr[i + 1];
+  const int* nb = idx + i * m;
+  const double* vb = vals + i * m;
+  double acc[VEC];
+  vld<VEC>(X + i * t + c, acc);
+  if (rs) {
+    const double s = rs[i];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] *= s;
   }
-  double acc = X[i * t + c];
-  if (rs) acc *= rs[i];
-  for (; q < e; q += 8) {
+  for (int q = 0; q < m; q += 8) {
     int cb[8];
-    double vb[8], yv[8];
+    double w[8], y[8][VEC];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      cb[k] = (q + k < e) ? idx[q + k] : -1;
-      vb[k] = (q + k < e) ? vals[q + k] : 0.0;
+      cb[k] = (q + k < m) ? nb[q + k] : -1;
+      w[k] = (q + k < m) ? vb[q + k] : 0.0;
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) yv[k] = (cb[k] >= 0) ? Y[(int64_t)cb[k] * t + c] : 0.0;
+    for (int k = 0; k < 8; ++k) {
+      if (cb[k] >= 0) {
+        vld<VEC>(Y + (int64_t)cb[k] * t + c, y[k]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) y[k][v] = 0.0;
+      }
+    }
     bool ended = false;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       if (cb[k] < 0) ended = true;
-      if (!ended) acc -= vb[k] * yv[k];
+      if (!ended) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] -= w[k] * y[k][v];
+      }
     }
     if (ended) break;
   }
-  Y[i * t + c] = acc;
+  vst<VEC>(Y + i * t + c, acc);
 }
 
-// The same for levels of long rows (average length above 16; in B^T these
-// are the earliest points of the ordering): block (k, s) covers 64 columns
-// of row rows[k], and its 4 waves take the entries q0 + w, q0 + w + 4, ...
-// of the row; the 4 partial sums are added in wave order.
+// Backward (B^T Y = X, CSR): the same per row over the entries
+// [ptr[i], end_i), end_i = pend[i] if pend is given (the head rows'
+// head-internal prefix), else ptr[i + 1].
+template <int VEC>
+__global__ __launch_bounds__(256) void trsm_level_upper_kernel(
+    int t, const int* __restrict__ rows, const int* __restrict__ ptr,
+    const int* __restrict__ pend, const int* __restrict__ idx, const double* __restrict__ vals,
+    const double* __restrict__ X, double* __restrict__ Y) {
+  const int c = (blockIdx.y * blockDim.x + threadIdx.x) * VEC;
+  const int64_t i = rows[blockIdx.x];
+  if (c >= t) return;
+  int q = ptr[i];
+  const int e = pend ? pend[i] : ptr[i + 1];
+  double acc[VEC];
+  vld<VEC>(X + i * t + c, acc);
+  for (; q < e; q += 8) {
+    int cb[8];
+    double w[8], y[8][VEC];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      cb[k] = (q + k < e) ? idx[q + k] : -1;
+      w[k] = (q + k < e) ? vals[q + k] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (cb[k] >= 0) {
+        vld<VEC>(Y + (int64_t)cb[k] * t + c, y[k]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) y[k][v] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (cb[k] >= 0) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] -= w[k] * y[k][v];
+      }
+  }
+  vst<VEC>(Y + i * t + c, acc);
+}
+
+// The same for levels of long B^T rows (average length above 16): block
+// (k, s) covers 64 * VEC columns of row rows[k] with 4 waves sharing the
+// row's entries.  `pend` as above.
+template <int VEC>
 __global__ __launch_bounds__(256) void trsm_level_split_kernel(int t, const int* __restrict__ rows,
                                                                const int* __restrict__ ptr,
+                                                               const int* __restrict__ pend,
                                                                const int* __restrict__ idx,
                                                                const double* __restrict__ vals,
                                                                const double* __restrict__ X,
                                                                double* __restrict__ Y) {
-  __shared__ double s_part[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int c = blockIdx.y * 64 + lane;
+  const int c = (blockIdx.y * 64 + (threadIdx.x & 63)) * VEC;
   const int64_t i = rows[blockIdx.x];
-  const int b = ptr[i], e = ptr[i + 1];
-  double part = 0.0;
-  if (c < t) {
-    for (int q = b + w; q < e; q += 4 * 8) {
-      int cb[8];
-      double vb[8], yv[8];
+  const int b = ptr[i], e = pend ? pend[i] : ptr[i + 1];
+  double tot[VEC];
+  if (!split_row_sum<VEC>(t, c, b, e, idx, vals, Y, tot)) return;
+  double x[VEC];
+  vld<VEC>(X + i * t + c, x);
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        cb[k] = (q + 4 * k < e) ? idx[q + 4 * k] : -1;
-        vb[k] = (q + 4 * k < e) ? vals[q + 4 * k] : 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < 8; ++k) yv[k] = (cb[k] >= 0) ? Y[(int64_t)cb[k] * t + c] : 0.0;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) part += vb[k] * yv[k];
-    }
-  }
-  s_part[w][lane] = part;
-  __syncthreads();
-  if (w == 0 && c < t)
-    Y[i * t + c] = X[i * t + c] - (((s_part[0][lane] + s_part[1][lane]) + s_part[2][lane]) +
-                                   s_part[3][lane]);
+  for (int v = 0; v < VEC; ++v) x[v] -= tot[v];
+  vst<VEC>(Y + i * t + c, x);
 }
 
-// One launch per level of the full level order; each launch is timed on its
-// own when timing is on.
-static Status trsm_levels(Model& M, bool lower, const double* X, double* Y, int t,
-                          const double* rowscale) {
-  const std::vector<int>& lp = lower ? M.lvl_ptr_f : M.lvl_ptr_b;
-  const std::vector<int64_t>& lnz = lower ? M.lvl_nnz_f : M.lvl_nnz_b;
-  const int* order = lower ? M.full_order_f.p : M.full_order_b.p;
-  if (lp.size() < 2 || lp.back() != M.n) return Status::make(VL_ERR_STATE, "no level schedule");
-  const int tb = t <= 64 ? 64 : 256;  // threads (columns) per block
-  const unsigned gy = static_cast<unsigned>((t + tb - 1) / tb);
+// Fold of the head rows' tail entries (B^T Y = X, after every tail row is
+// solved): Xh_j = X_j - sum over the entries [pend[j], ptr[j + 1]) of row j,
+// for all head rows j < H in one launch, block (j, s) covering 64 * VEC
+// columns.  The head rows then solve against Xh with their head-internal
+// entries only, so the long tail part of an early point's row never sits on
+// a level's critical path.
+template <int VEC, typename TY>
+__global__ __launch_bounds__(256) void trsm_fold_kernel(int t, const int* __restrict__ ptr,
+                                                        const int* __restrict__ pend,
+                                                        const int* __restrict__ idx,
+                                                        const TY* __restrict__ vals,
+                                                        const double* __restrict__ X,
+                                                        const TY* __restrict__ Y,
+                                                        double* __restrict__ Xh) {
+  const int c = (blockIdx.y * 64 + (threadIdx.x & 63)) * VEC;
+  const int64_t j = blockIdx.x;
+  double tot[VEC];
+  if (!split_row_sum<VEC>(t, c, pend[j], ptr[j + 1], idx, vals, Y, tot)) return;
+  double x[VEC];
+  vld<VEC>(X + j * t + c, x);
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) x[v] -= tot[v];
+  vst<VEC>(Xh + j * t + c, x);
+}
+
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Column vector width of the level kernels: 16-byte accesses need t a
+// multiple of the width and 16-byte aligned blocks.
+int level_vec(int t, int elem_bytes, const void* a, const void* b, const void* c) {
+  const bool al = aligned16(a) && aligned16(b) && (c == nullptr || aligned16(c));
+  if (!al) return 1;
+  const int want = 16 / elem_bytes;  // 2 doubles or 4 floats
+  if (t % want == 0) return want;
+  if (want == 4 && t % 2 == 0) return 2;
+  return 1;
+}
+
+Status fold_launch_f32(Model& M, const double* X, const float* Y, double* Xh, int t) {
+  const int H = M.head_rows;
+  if (H <= 0) return Status::ok();
+  TimedLaunch tl(M, kTimeLevelUpperFold, 8.0 * M.fold_nnz + 8.0 * H * t + 8.0 * H * t);
+  const int vec = level_vec(t, 4, X, Y, Xh);
+  const dim3 grid(H, (t + 64 * vec - 1) / (64 * vec));
+  if (vec == 4) {
+    hipLaunchKernelGGL((trsm_fold_kernel<4, float>), grid, dim3(256), 0, M.stream, t, M.bt_ptr.p,
+                       M.head_split.p, M.bt_col.p, M.bt_val_f.p, X, Y, Xh);
+  } else if (vec == 2) {
+    hipLaunchKernelGGL((trsm_fold_kernel<2, float>), grid, dim3(256), 0, M.stream, t, M.bt_ptr.p,
+                       M.head_split.p, M.bt_col.p, M.bt_val_f.p, X, Y, Xh);
+  } else {
+    hipLaunchKernelGGL((trsm_fold_kernel<1, float>), grid, dim3(256), 0, M.stream, t, M.bt_ptr.p,
+                       M.head_split.p, M.bt_col.p, M.bt_val_f.p, X, Y, Xh);
+  }
+  return check_launch("trsm fold f32");
+}
+
+static Status lower_levels(Model& M, const double* X, double* Y, int t, const double* rs) {
+  const std::vector<int>& lp = M.lvl_ptr_f;
+  const std::vector<int64_t>& lnz = M.lvl_nnz_f;
+  const int tb = t <= 64 ? 64 : 256;  // threads per block
+  const int vec = level_vec(t, 8, X, Y, nullptr);
+  const unsigned gy = static_cast<unsigned>((t + tb * vec - 1) / (tb * vec));
   for (size_t l = 0; l + 1 < lp.size(); ++l) {
     const int rows = lp[l + 1] - lp[l];
     if (rows <= 0) continue;
-    const bool split = !lower && lnz[l] > 16LL * rows;
-    TimedLaunch tl(M, lower ? kTimeLevelLower : (split ? kTimeLevelUpperSplit : kTimeLevelUpper),
-                   12.0 * lnz[l] + 16.0 * rows * t + 4.0 * rows +
-                       (lower ? (rowscale ? 8.0 * rows : 0.0) : 8.0 * rows));
-    if (lower) {
-      hipLaunchKernelGGL(trsm_level_kernel<true>, dim3(rows, gy), dim3(tb), 0, M.stream, t,
-                         order + lp[l], M.m, nullptr, M.nbr.p, M.bval.p, X, rowscale, Y);
-    } else if (split) {
-      hipLaunchKernelGGL(trsm_level_split_kernel, dim3(rows, (t + 63) / 64), dim3(256), 0,
-                         M.stream, t, order + lp[l], M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, Y);
+    TimedLaunch tl(M, kTimeLevelLower,
+                   12.0 * lnz[l] + 16.0 * rows * t + 4.0 * rows + (rs ? 8.0 * rows : 0.0));
+    const int* r = M.full_order_f.p + lp[l];
+    if (vec == 2) {
+      hipLaunchKernelGGL(trsm_level_lower_kernel<2>, dim3(rows, gy), dim3(tb), 0, M.stream, t, r,
+                         M.m, M.nbr.p, M.bval.p, X, rs, Y);
     } else {
-      hipLaunchKernelGGL(trsm_level_kernel<false>, dim3(rows, gy), dim3(tb), 0, M.stream, t,
-                         order + lp[l], 0, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, nullptr, Y);
+      hipLaunchKernelGGL(trsm_level_lower_kernel<1>, dim3(rows, gy), dim3(tb), 0, M.stream, t, r,
+                         M.m, M.nbr.p, M.bval.p, X, rs, Y);
     }
   }
-  return check_launch(lower ? "trsm level lower" : "trsm level upper");
+  return check_launch("trsm level lower");
+}
+
+// Levels [lp] of the rows `order`; entries [ptr[i], pend ? pend[i] : ptr[i+1]).
+static Status upper_levels(Model& M, const std::vector<int>& lp, const std::vector<int64_t>& lnz,
+                           const int* order, const int* pend, const double* X, double* Y, int t) {
+  const int tb = t <= 64 ? 64 : 256;
+  const int vec = level_vec(t, 8, X, Y, nullptr);
+  const unsigned gy = static_cast<unsigned>((t + tb * vec - 1) / (tb * vec));
+  const unsigned gs = static_cast<unsigned>((t + 64 * vec - 1) / (64 * vec));
+  for (size_t l = 0; l + 1 < lp.size(); ++l) {
+    const int rows = lp[l + 1] - lp[l];
+    if (rows <= 0) continue;
+    const bool split = lnz[l] > 16LL * rows;
+    TimedLaunch tl(M, split ? kTimeLevelUpperSplit : kTimeLevelUpper,
+                   12.0 * lnz[l] + 16.0 * rows * t + 8.0 * rows);
+    const int* r = order + lp[l];
+    if (split && vec == 2) {
+      hipLaunchKernelGGL(trsm_level_split_kernel<2>, dim3(rows, gs), dim3(256), 0, M.stream, t, r,
+                         M.bt_ptr.p, pend, M.bt_col.p, M.bt_val.p, X, Y);
+    } else if (split) {
+      hipLaunchKernelGGL(trsm_level_split_kernel<1>, dim3(rows, gs), dim3(256), 0, M.stream, t, r,
+                         M.bt_ptr.p, pend, M.bt_col.p, M.bt_val.p, X, Y);
+    } else if (vec == 2) {
+      hipLaunchKernelGGL(trsm_level_upper_kernel<2>, dim3(rows, gy), dim3(tb), 0, M.stream, t, r,
+                         M.bt_ptr.p, pend, M.bt_col.p, M.bt_val.p, X, Y);
+    } else {
+      hipLaunchKernelGGL(trsm_level_upper_kernel<1>, dim3(rows, gy), dim3(tb), 0, M.stream, t, r,
+                         M.bt_ptr.p, pend, M.bt_col.p, M.bt_val.p, X, Y);
+    }
+  }
+  return check_launch("trsm level upper");
+}
+
+// One launch per level; each launch is timed on its own when timing is on.
+// B Y = rs o X runs the full level order.  B^T Y = X runs in three stages:
+// the tail rows by level (they depend on tail rows only), one fold of every
+// head row's tail entries into Xh = X - (tail part), then the head rows by
+// their head-internal levels against Xh.
+static Status trsm_levels(Model& M, bool lower, const double* X, double* Y, int t,
+                          const double* rowscale) {
+  if (lower) {
+    if (M.lvl_ptr_f.size() < 2 || M.lvl_ptr_f.back() != M.n)
+      return Status::make(VL_ERR_STATE, "no level schedule");
+    return lower_levels(M, X, Y, t, rowscale);
+  }
+  const int64_t H = M.head_rows;
+  if (M.hlv_ptr_b.size() < 2 || M.hlv_ptr_b.back() != H ||
+      (M.n > H && (M.tlvl_ptr_b.size() < 2 || M.tlvl_ptr_b.back() != M.n - H)))
+    return Status::make(VL_ERR_STATE, "no level schedule");
+  if (M.n > H)
+    VL_TRY(upper_levels(M, M.tlvl_ptr_b, M.tlvl_nnz_b, M.tail_order_b.p, nullptr, X, Y, t));
+  VL_TRY(M.lvl_fold.reserve(static_cast<size_t>(H) * t));
+  {
+    TimedLaunch tl(M, kTimeLevelUpperFold, 12.0 * M.fold_nnz + 16.0 * H * t);
+    const int vec = level_vec(t, 8, X, Y, M.lvl_fold.p);
+    const dim3 grid(static_cast<unsigned>(H), (t + 64 * vec - 1) / (64 * vec));
+    if (vec == 2) {
+      hipLaunchKernelGGL((trsm_fold_kernel<2, double>), grid, dim3(256), 0, M.stream, t,
+                         M.bt_ptr.p, M.head_split.p, M.bt_col.p, M.bt_val.p, X, Y, M.lvl_fold.p);
+    } else {
+      hipLaunchKernelGGL((trsm_fold_kernel<1, double>), grid, dim3(256), 0, M.stream, t,
+                         M.bt_ptr.p, M.head_split.p, M.bt_col.p, M.bt_val.p, X, Y, M.lvl_fold.p);
+    }
+    VL_TRY(check_launch("trsm fold"));
+  }
+  return upper_levels(M, M.hlv_ptr_b, M.hlv_nnz_b, M.hlv_rows_b.p, M.head_split.p, M.lvl_fold.p,
+                      Y, t);
 }
 
 static int trsm_grid(int64_t total_units) {
@@ -929,11 +1082,11 @@ __global__ void level_count_kernel(int64_t n, int64_t r0, const int* __restrict_
 
 // nnz of the rows of each level (lower: entries with idx >= 0 of the ELL
 // row; upper: the CSR row length)
-__global__ void level_nnz_kernel(int64_t n, int m, const int* __restrict__ ptr,
+__global__ void level_nnz_kernel(int64_t n, int64_t r0, int m, const int* __restrict__ ptr,
                                  const int* __restrict__ idx, const int* __restrict__ lev,
                                  unsigned long long* __restrict__ nnz) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || i < r0) return;
   int c = 0;
   if (ptr) {
     c = ptr[i + 1] - ptr[i];
@@ -993,20 +1146,22 @@ Status build_tail_orders(Model& M) {
       hipLaunchKernelGGL(level_scatter_kernel, dim3(gn), dim3(tb), 0, M.stream, n, r0, spatial,
                          lev.p, start.p, cnt.p, out);
       VL_TRY(check_launch("level order"));
-      if (full) {
-        // level pointers and per-level nnz of the full order, to the host
+      // level pointers and per-level nnz, to the host: of the full orders
+      // (both directions) and of the backward tail order
+      if (full || dir == 1) {
+        const int64_t cnt_rows = n - r0;
         std::vector<int> st(n + 1);
         VL_HIP(hipMemcpyAsync(st.data(), start.p, sizeof(int) * (n + 1), hipMemcpyDeviceToHost,
                               M.stream));
         VL_TRY(sync_stream(M.stream));
         int64_t L = 0;
-        while (L < n && st[L] < n) ++L;  // levels 0..L-1 are non-empty prefixes
-        std::vector<int>& lp = dir == 0 ? M.lvl_ptr_f : M.lvl_ptr_b;
+        while (L < n && st[L] < cnt_rows) ++L;  // levels 0..L-1 hold the counted rows
+        std::vector<int>& lp = full ? (dir == 0 ? M.lvl_ptr_f : M.lvl_ptr_b) : M.tlvl_ptr_b;
         lp.assign(st.begin(), st.begin() + L + 1);
         DevBuf<unsigned long long> lnz;
         VL_TRY(lnz.alloc(L > 0 ? L : 1));
         VL_HIP(hipMemsetAsync(lnz.p, 0, sizeof(unsigned long long) * (L > 0 ? L : 1), M.stream));
-        hipLaunchKernelGGL(level_nnz_kernel, dim3(gn), dim3(tb), 0, M.stream, n,
+        hipLaunchKernelGGL(level_nnz_kernel, dim3(gn), dim3(tb), 0, M.stream, n, r0,
                            dir == 0 ? M.m : 0, dir == 0 ? nullptr : M.bt_ptr.p,
                            dir == 0 ? M.nbr.p : nullptr, lev.p, lnz.p);
         VL_TRY(check_launch("level nnz"));
@@ -1014,7 +1169,7 @@ Status build_tail_orders(Model& M) {
         VL_HIP(hipMemcpyAsync(hz.data(), lnz.p, sizeof(unsigned long long) * hz.size(),
                               hipMemcpyDeviceToHost, M.stream));
         VL_TRY(sync_stream(M.stream));
-        std::vector<int64_t>& nz = dir == 0 ? M.lvl_nnz_f : M.lvl_nnz_b;
+        std::vector<int64_t>& nz = full ? (dir == 0 ? M.lvl_nnz_f : M.lvl_nnz_b) : M.tlvl_nnz_b;
         nz.assign(hz.begin(), hz.begin() + L);
       }
     }

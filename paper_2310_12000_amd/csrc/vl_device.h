@@ -43,6 +43,110 @@ __device__ __forceinline__ int consume_ready(const int* cb, const double* vb, co
   return fm;
 }
 
+// VEC consecutive elements as one access (the caller guarantees that p is
+// aligned to 16 bytes for the vector forms): doubles VEC = 1, 2, 4 (4 as two
+// 16-byte accesses), floats VEC = 1, 2, 4.
+template <int VEC>
+__device__ __forceinline__ void vld(const double* p, double* v) {
+  if constexpr (VEC == 1) {
+    v[0] = p[0];
+  } else {
+#pragma unroll
+    for (int h = 0; h < VEC; h += 2) {
+      const double2 q = *reinterpret_cast<const double2*>(p + h);
+      v[h] = q.x;
+      v[h + 1] = q.y;
+    }
+  }
+}
+template <int VEC>
+__device__ __forceinline__ void vst(double* p, const double* v) {
+  if constexpr (VEC == 1) {
+    p[0] = v[0];
+  } else {
+#pragma unroll
+    for (int h = 0; h < VEC; h += 2) *reinterpret_cast<double2*>(p + h) = make_double2(v[h], v[h + 1]);
+  }
+}
+template <int VEC>
+__device__ __forceinline__ void vld(const float* p, float* v) {
+  if constexpr (VEC == 1) {
+    v[0] = p[0];
+  } else if constexpr (VEC == 2) {
+    const float2 q = *reinterpret_cast<const float2*>(p);
+    v[0] = q.x;
+    v[1] = q.y;
+  } else {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+  }
+}
+template <int VEC>
+__device__ __forceinline__ void vst(float* p, const float* v) {
+  if constexpr (VEC == 1) {
+    p[0] = v[0];
+  } else if constexpr (VEC == 2) {
+    *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+  } else {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+// Partial sums over the entries [b, e) of one row for 64 * VEC columns: wave
+// w of the block takes the entries b + w, b + w + 4, ...; the 4 partial sums
+// are added in wave order by wave 0, which returns true and leaves them in
+// `tot`.
+template <int VEC, typename TV, typename TY>
+__device__ __forceinline__ bool split_row_sum(int t, int c, int b, int e,
+                                              const int* __restrict__ idx,
+                                              const TV* __restrict__ vals,
+                                              const TY* __restrict__ Y, double* tot) {
+  __shared__ double s_part[4][64 * VEC];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double part[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) part[v] = 0.0;
+  if (c < t) {
+    for (int q = b + w; q < e; q += 4 * 8) {
+      int cb[8];
+      TV vb[8];
+      TY y[8][VEC];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        cb[k] = (q + 4 * k < e) ? idx[q + 4 * k] : -1;
+        vb[k] = (q + 4 * k < e) ? vals[q + 4 * k] : TV(0);
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (cb[k] >= 0) {
+          vld<VEC>(Y + (int64_t)cb[k] * t + c, y[k]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) y[k][v] = TY(0);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+          part[v] += static_cast<double>(vb[k]) * static_cast<double>(y[k][v]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) s_part[w][lane * VEC + v] = part[v];
+  __syncthreads();
+  if (w != 0 || c >= t) return false;
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    const int o = lane * VEC + v;
+    tot[v] = ((s_part[0][o] + s_part[1][o]) + s_part[2][o]) + s_part[3][o];
+  }
+  return true;
+}
+
 // Device-coherent polling load / publishing store of one value.  Relaxed
 // ordering is enough: every published value carries its own readiness.
 template <typename T>

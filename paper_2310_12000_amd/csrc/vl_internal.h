@@ -117,7 +117,8 @@ enum TimedKind : int {
   kTimeLevelLower = 6, // level-scheduled rows of B Y = X (wide blocks)
   kTimeLevelUpper = 7, // level-scheduled rows of B^T Y = X (wide blocks)
   kTimeLevelUpperSplit = 8, // the same for levels of long B^T rows
-  kTimeKinds = 9
+  kTimeLevelUpperFold = 9,  // head rows' tail entries of B^T Y = X, one launch
+  kTimeKinds = 10
 };
 
 struct Timing {
@@ -181,6 +182,14 @@ struct Model {
   std::vector<int> lvl_ptr_f, lvl_ptr_b;
   std::vector<int64_t> lvl_nnz_f, lvl_nnz_b;
   DevBuf<int> head_split;                       // first tail entry of head B^T rows
+  // Level-scheduled B^T solves run in three stages: the tail rows by level
+  // (tail_order_b, tlvl_*), one fold of every head row's tail entries, then
+  // the head rows by their head-internal levels (hlv_rows_b, hlv_*).
+  std::vector<int> tlvl_ptr_b, hlv_ptr_b;
+  std::vector<int64_t> tlvl_nnz_b, hlv_nnz_b;
+  DevBuf<int> hlv_rows_b;
+  int64_t fold_nnz = 0;                         // tail entries of the head rows
+  DevBuf<double> lvl_fold;                      // head rows' folded right-hand sides
 
   // neighbour-search grid
   int grid_G = 0;

@@ -177,6 +177,9 @@ Status cg_solve(Model& M, CgState& S, const CgOps& ops, int t, const double* rhs
 // preconditioner solves in FP32 (FP64 sums).
 CgOps vadu_ops_mixed(const double* W, const double* sdiag);
 Status to_f32(Model& M, const double* x, float* y, int64_t count);
+// Xh = X - (tail entries of the head rows of B^T) applied to the FP32 block Y
+// (sparse.hip; the fold stage of the level-scheduled B^T solve).
+Status fold_launch_f32(Model& M, const double* X, const float* Y, double* Xh, int t);
 
 Status dot_cols(Model& M, const double* X, const double* Y, int t, double* part, double* out);
 

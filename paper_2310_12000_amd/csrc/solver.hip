@@ -33,19 +33,32 @@ ChunkGrid ChunkGrid::of(int64_t n, int t) {
   return g;
 }
 
-// Sum each column's per-chunk partials in chunk order.
-__global__ void reduce_chunks_kernel(const double* __restrict__ part, int nchunk, int t,
-                                     double* __restrict__ out) {
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < t; c += gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int k = 0; k < nchunk; ++k) s += part[(int64_t)k * t + c];
-    out[c] = s;
-  }
+// Sum of column c's per-chunk partials by one wave: lane k takes chunks
+// k, k + 64, ... in order, then a fixed butterfly adds the lanes, so the
+// result does not depend on timing.  Every lane returns the sum.
+__device__ __forceinline__ double wave_colsum(const double* __restrict__ part, int nchunk, int t,
+                                              int c) {
+  double s = 0.0;
+  for (int k = threadIdx.x & 63; k < nchunk; k += 64) s += part[(int64_t)k * t + c];
+  return wave_sum(s);
+}
+
+// One wave per column, four columns per block.
+static unsigned col_blocks(int t) { return static_cast<unsigned>((t + 3) / 4); }
+__device__ __forceinline__ int wave_col() { return blockIdx.x * 4 + (threadIdx.x >> 6); }
+
+__global__ __launch_bounds__(256) void reduce_chunks_kernel(const double* __restrict__ part,
+                                                            int nchunk, int t,
+                                                            double* __restrict__ out) {
+  const int c = wave_col();
+  if (c >= t) return;
+  const double s = wave_colsum(part, nchunk, t, c);
+  if ((threadIdx.x & 63) == 0) out[c] = s;
 }
 
 Status reduce_chunks(hipStream_t s, const double* part, int nchunk, int t, double* out) {
-  int g = (t + 255) / 256;
-  hipLaunchKernelGGL(reduce_chunks_kernel, dim3(g), dim3(256), 0, s, part, nchunk, t, out);
+  hipLaunchKernelGGL(reduce_chunks_kernel, dim3(col_blocks(t)), dim3(256), 0, s, part, nchunk,
+                     t, out);
   return check_launch("reduce_chunks");
 }
 
@@ -111,41 +124,51 @@ __global__ __launch_bounds__(256) void dot_kernel(ChunkGrid g, const T* __restri
   block_colsum(g, acc, part);
 }
 
-// one block: rz = r0z0 = sum of partials, active = 1, iters = 0
-__global__ void cg_start_kernel(int t, int nchunk, const double* __restrict__ part,
-                                double* __restrict__ rz, double* __restrict__ r0z0,
-                                int* __restrict__ active, int* __restrict__ iters,
-                                int* __restrict__ num_active) {
-  for (int c = threadIdx.x; c < t; c += blockDim.x) {
-    double s = 0.0;
-    for (int k = 0; k < nchunk; ++k) s += part[(int64_t)k * t + c];
-    rz[c] = s;
-    r0z0[c] = s;
-    active[c] = (s > 0.0) ? 1 : 0;  // a zero right-hand side is already solved
-    iters[c] = 0;
-  }
-  if (threadIdx.x == 0) num_active[0] = t;
+// rz = r0z0 = sum of partials, active = 1, iters = 0 (one wave per column)
+__global__ __launch_bounds__(256) void cg_start_kernel(int t, int nchunk,
+                                                       const double* __restrict__ part,
+                                                       double* __restrict__ rz,
+                                                       double* __restrict__ r0z0,
+                                                       int* __restrict__ active,
+                                                       int* __restrict__ iters,
+                                                       int* __restrict__ num_active) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) num_active[0] = t;
+  const int c = wave_col();
+  if (c >= t) return;
+  const double s = wave_colsum(part, nchunk, t, c);
+  if ((threadIdx.x & 63) != 0) return;
+  rz[c] = s;
+  r0z0[c] = s;
+  active[c] = (s > 0.0) ? 1 : 0;  // a zero right-hand side is already solved
+  iters[c] = 0;
 }
 
-// alpha = r.z / h.v for active columns; records alpha_{l+1}
-__global__ void cg_alpha_kernel(int t, int nchunk, const double* __restrict__ part,
-                                const double* __restrict__ rz, double* __restrict__ alpha,
-                                const int* __restrict__ active, const int* __restrict__ iters,
-                                double* __restrict__ hist_a, int* __restrict__ status) {
-  for (int c = threadIdx.x; c < t; c += blockDim.x) {
-    double hv = 0.0;
-    for (int k = 0; k < nchunk; ++k) hv += part[(int64_t)k * t + c];
-    double a = 0.0;
-    if (active[c]) {
-      if (!(hv > 0.0) || !isfinite(hv)) {
-        raise_error(status, kErrNonfinite);
-      } else {
-        a = rz[c] / hv;
-        hist_a[(int64_t)iters[c] * t + c] = a;
-      }
+// alpha = r.z / h.v for active columns; records alpha_{l+1} (one wave per
+// column).  Also clears the active-column count that cg_beta_kernel adds to.
+__global__ __launch_bounds__(256) void cg_alpha_kernel(int t, int nchunk,
+                                                       const double* __restrict__ part,
+                                                       const double* __restrict__ rz,
+                                                       double* __restrict__ alpha,
+                                                       const int* __restrict__ active,
+                                                       const int* __restrict__ iters,
+                                                       double* __restrict__ hist_a,
+                                                       int* __restrict__ num_active,
+                                                       int* __restrict__ status) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) num_active[0] = 0;
+  const int c = wave_col();
+  if (c >= t) return;
+  const double hv = wave_colsum(part, nchunk, t, c);
+  if ((threadIdx.x & 63) != 0) return;
+  double a = 0.0;
+  if (active[c]) {
+    if (!(hv > 0.0) || !isfinite(hv)) {
+      raise_error(status, kErrNonfinite);
+    } else {
+      a = rz[c] / hv;
+      hist_a[(int64_t)iters[c] * t + c] = a;
     }
-    alpha[c] = a;
   }
+  alpha[c] = a;
 }
 
 // u += alpha h, r -= alpha v; partial ||r||^2; pre-fill solve outputs
@@ -174,44 +197,43 @@ __global__ __launch_bounds__(256) void cg_update_ur_kernel(
   if (counter && blockIdx.x == 0 && blockIdx.y == 0) reset_counters(counter);
 }
 
-// beta = r_new.z_new / r.z; records beta; stopping test on ||r||_2
-__global__ void cg_beta_kernel(int t, int nchunk, const double* __restrict__ part_rz,
-                               const double* __restrict__ part_rr, double tol, int max_iter,
-                               double* __restrict__ rz, double* __restrict__ beta,
-                               int* __restrict__ active, int* __restrict__ iters,
-                               double* __restrict__ hist_b, int* __restrict__ num_active,
-                               int* __restrict__ status) {
-  __shared__ int s_cnt[256];
-  int cnt = 0;
-  for (int c = threadIdx.x; c < t; c += blockDim.x) {
-    double b = 0.0;
-    if (active[c]) {
-      double rzn = 0.0, rr = 0.0;
-      for (int k = 0; k < nchunk; ++k) {
-        rzn += part_rz[(int64_t)k * t + c];
-        rr += part_rr[(int64_t)k * t + c];
-      }
-      const int it = iters[c];
-      b = rzn / rz[c];
-      hist_b[(int64_t)it * t + c] = b;
-      rz[c] = rzn;
-      iters[c] = it + 1;
-      if (!isfinite(rr) || !isfinite(b)) raise_error(status, kErrNonfinite);
-      if (sqrt(rr) < tol || it + 1 >= max_iter || !isfinite(rr)) {
-        active[c] = 0;
-      } else {
-        ++cnt;
-      }
+// beta = r_new.z_new / r.z; records beta; stopping test on ||r||_2 (one
+// wave per column); columns still active are counted into num_active.
+__global__ __launch_bounds__(256) void cg_beta_kernel(int t, int nchunk,
+                                                      const double* __restrict__ part_rz,
+                                                      const double* __restrict__ part_rr,
+                                                      double tol, int max_iter,
+                                                      double* __restrict__ rz,
+                                                      double* __restrict__ beta,
+                                                      int* __restrict__ active,
+                                                      int* __restrict__ iters,
+                                                      double* __restrict__ hist_b,
+                                                      int* __restrict__ num_active,
+                                                      int* __restrict__ status) {
+  const int c = wave_col();
+  if (c >= t) return;
+  const bool act = active[c] != 0;
+  double rzn = 0.0, rr = 0.0;
+  if (act) {
+    rzn = wave_colsum(part_rz, nchunk, t, c);
+    rr = wave_colsum(part_rr, nchunk, t, c);
+  }
+  if ((threadIdx.x & 63) != 0) return;
+  double b = 0.0;
+  if (act) {
+    const int it = iters[c];
+    b = rzn / rz[c];
+    hist_b[(int64_t)it * t + c] = b;
+    rz[c] = rzn;
+    iters[c] = it + 1;
+    if (!isfinite(rr) || !isfinite(b)) raise_error(status, kErrNonfinite);
+    if (sqrt(rr) < tol || it + 1 >= max_iter || !isfinite(rr)) {
+      active[c] = 0;
+    } else {
+      atomicAdd(num_active, 1);
     }
-    beta[c] = b;
   }
-  s_cnt[threadIdx.x] = cnt;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int tot = 0;
-    for (int k = 0; k < (int)blockDim.x; ++k) tot += s_cnt[k];
-    num_active[0] = tot;
-  }
+  beta[c] = b;
 }
 
 template <typename T>
@@ -287,21 +309,22 @@ static Status cg_run(Model& M, CgState& S, const Ops& ops, int t, const T* rhs, 
   VL_TRY(ops.precond(M, R, Z, Y, t));
   hipLaunchKernelGGL(cg_init2_kernel<T>, cg_grid, dim3(256), 0, s, g, R, Z, H,
                      keep_z0 ? blk<T>(S.Z0) : nullptr, S.part_a.p);
-  hipLaunchKernelGGL(cg_start_kernel, dim3(1), dim3(256), 0, s, t, g.nchunk, S.part_a.p,
-                     S.rz.p, S.r0z0.p, S.active.p, S.iters.p, S.num_active.p);
+  hipLaunchKernelGGL(cg_start_kernel, dim3(col_blocks(t)), dim3(256), 0, s, t, g.nchunk,
+                     S.part_a.p, S.rz.p, S.r0z0.p, S.active.p, S.iters.p, S.num_active.p);
   VL_TRY(check_launch("cg start"));
   for (int it = 0; it < max_iter; ++it) {
     VL_TRY(ops.apply(M, H, V, Tmp, t));
     hipLaunchKernelGGL(dot_kernel<T>, cg_grid, dim3(256), 0, s, g, H, V, S.part_a.p);
-    hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(256), 0, s, t, g.nchunk, S.part_a.p,
-                       S.rz.p, S.alpha.p, S.active.p, S.iters.p, S.hist_a.p, M.status);
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(col_blocks(t)), dim3(256), 0, s, t, g.nchunk,
+                       S.part_a.p, S.rz.p, S.alpha.p, S.active.p, S.iters.p, S.hist_a.p,
+                       S.num_active.p, M.status);
     hipLaunchKernelGGL(cg_update_ur_kernel<T>, cg_grid, dim3(256), 0, s, g, S.alpha.p,
                        S.active.p, H, V, U, R, Yf, Zf, S.part_b.p, cnt);
     VL_TRY(ops.precond(M, R, Z, Y, t));
     hipLaunchKernelGGL(dot_kernel<T>, cg_grid, dim3(256), 0, s, g, R, Z, S.part_a.p);
-    hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(256), 0, s, t, g.nchunk, S.part_a.p,
-                       S.part_b.p, tol, max_iter, S.rz.p, S.beta.p, S.active.p, S.iters.p,
-                       S.hist_b.p, S.num_active.p, M.status);
+    hipLaunchKernelGGL(cg_beta_kernel, dim3(col_blocks(t)), dim3(256), 0, s, t, g.nchunk,
+                       S.part_a.p, S.part_b.p, tol, max_iter, S.rz.p, S.beta.p, S.active.p,
+                       S.iters.p, S.hist_b.p, S.num_active.p, M.status);
     hipLaunchKernelGGL(cg_update_h_kernel<T>, cg_grid, dim3(256), 0, s, g, S.beta.p, S.active.p,
                        Z, H);
     VL_TRY(check_launch("cg iteration"));

@@ -935,6 +935,7 @@ Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* ro
   int g = trsm_grid(units_of(M.n - H, t));
   const int ns = trsm_streams(M, g);
   int* cnt = M.counter.p + slot * kSlotInts;
+  PollingOrder order(M);
   TimedLaunch tl(M, kTimeTrsmLower,
                  12.0 * (M.nnz - (H ? M.nnz_head_f : 0)) + 16.0 * (M.n - H) * t +
                      (rowscale ? 8.0 * (M.n - H) : 0.0));
@@ -969,6 +970,7 @@ Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled,
     int g = trsm_grid(units_of(M.n - H, t));
     const int ns = trsm_streams(M, g);
     int* cnt = M.counter.p + slot * kSlotInts;
+    PollingOrder order(M);
     TimedLaunch tl(M, kTimeTrsmUpper,
                    12.0 * (M.nnz - (H ? M.nnz_head_bt : 0)) + 4.0 * (M.n - H) +
                        16.0 * (M.n - H) * t);
@@ -1125,12 +1127,16 @@ Status build_tail_orders(Model& M) {
     VL_TRY(fill_int(M.counter.p, 0, 2, M.stream));
     const int64_t units = (n + 63) / 64;
     unsigned g = static_cast<unsigned>(std::min<int64_t>((units + 3) / 4, 2048));
-    if (dir == 0) {
-      hipLaunchKernelGGL((levels_kernel<32, true>), dim3(g), dim3(256), 0, M.stream, n, M.m,
-                         nullptr, M.nbr.p, lev.p, M.counter.p, M.counter.p + 1, M.status);
-    } else {
-      hipLaunchKernelGGL((levels_kernel<16, false>), dim3(g), dim3(256), 0, M.stream, n, 0,
-                         M.bt_ptr.p, M.bt_col.p, lev.p, M.counter.p, M.counter.p + 1, M.status);
+    {
+      PollingOrder order(M);
+      if (dir == 0) {
+        hipLaunchKernelGGL((levels_kernel<32, true>), dim3(g), dim3(256), 0, M.stream, n, M.m,
+                           nullptr, M.nbr.p, lev.p, M.counter.p, M.counter.p + 1, M.status);
+      } else {
+        hipLaunchKernelGGL((levels_kernel<16, false>), dim3(g), dim3(256), 0, M.stream, n, 0,
+                           M.bt_ptr.p, M.bt_col.p, lev.p, M.counter.p, M.counter.p + 1,
+                           M.status);
+      }
     }
     const int* spatial = static_cast<const int*>(M.grid_pts);
     for (int full = 0; full < 2; ++full) {

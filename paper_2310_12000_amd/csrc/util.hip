@@ -1,4 +1,6 @@
 // Small device utilities: fills, a multi-block exclusive scan, launch checks.
+#include <mutex>
+
 #include "vl_internal.h"
 
 namespace vl {
@@ -142,6 +144,39 @@ TimedLaunch::TimedLaunch(Model& M, int kind, double bytes)
 
 TimedLaunch::~TimedLaunch() {
   if (on_) (void)hipEventRecord(M_.timing.pool[ev_ + 1], M_.stream);
+}
+
+static std::mutex g_poll_mu;
+static hipEvent_t g_poll_last = nullptr;
+static int g_poll_dev = -1;
+
+PollingOrder::PollingOrder(Model& M) : M_(M) {
+  g_poll_mu.lock();
+  if (!M.poll_evt && hipEventCreateWithFlags(&M.poll_evt, hipEventDisableTiming) != hipSuccess) {
+    M.poll_evt = nullptr;
+    (void)hipGetLastError();
+  }
+  if (g_poll_last && g_poll_last != M.poll_evt && g_poll_dev == M.device)
+    (void)hipStreamWaitEvent(M.stream, g_poll_last, 0);
+}
+
+PollingOrder::~PollingOrder() {
+  if (M_.poll_evt && hipEventRecord(M_.poll_evt, M_.stream) == hipSuccess) {
+    g_poll_last = M_.poll_evt;
+    g_poll_dev = M_.device;
+  }
+  g_poll_mu.unlock();
+}
+
+// The event may still be the last one in the order: forget it first.  The
+// owner has synchronised its stream, so the event has completed.
+Model::~Model() {
+  if (!poll_evt) return;
+  {
+    std::lock_guard<std::mutex> lk(g_poll_mu);
+    if (g_poll_last == poll_evt) g_poll_last = nullptr;
+  }
+  (void)hipEventDestroy(poll_evt);
 }
 
 Status read_status(Model& M) {

@@ -238,7 +238,9 @@ struct Model {
   DevBuf<double> rhs_blk;  // n x t right-hand sides of block solves
   DevBuf<int> counter;     // dynamic work counters of sync-free kernels
   double* host_pin = nullptr;  // pinned host scalars (64 doubles)
+  hipEvent_t poll_evt = nullptr;  // completion of this model's last polling kernel
   Timing timing;
+  ~Model();  // releases poll_evt (util.hip)
   int64_t nnz_head_f = 0, nnz_head_bt = 0;  // nonzeros in head rows of B / B^T
 };
 
@@ -255,6 +257,23 @@ class TimedLaunch {
   Model& M_;
   bool on_;
   size_t ev_;
+};
+
+// Kernels whose blocks wait on one another (the sync-free solves and the
+// level computation) need every one of their work streams to have a
+// resident block.  Two such kernels running at once on a device (models on
+// different streams) could each hold the compute units the other's
+// undispatched blocks need, so they are enqueued in one device-wide order:
+// each waits for the completion of the previous one.  Kernels that never
+// wait keep overlapping; they always finish, so the waiting kernel's blocks
+// are dispatched in the end.  Construct around the launch.
+class PollingOrder {
+ public:
+  explicit PollingOrder(Model& M);
+  ~PollingOrder();
+
+ private:
+  Model& M_;
 };
 
 // ---- utilities (util.hip)

@@ -849,16 +849,23 @@ static Status upper_levels(Model& M, const std::vector<int>& lp, const std::vect
 }
 
 // One launch per level; each launch is timed on its own when timing is on.
-// B Y = rs o X runs the full level order.  B^T Y = X runs in three stages:
-// the tail rows by level (they depend on tail rows only), one fold of every
-// head row's tail entries into Xh = X - (tail part), then the head rows by
-// their head-internal levels against Xh.
+// B Y = rs o X runs the full level order.  B^T Y = X with t > 64 runs in
+// three stages: the tail rows by level (they depend on tail rows only), one
+// fold of every head row's tail entries into Xh = X - (tail part), then the
+// head rows by their head-internal levels against Xh.
 static Status trsm_levels(Model& M, bool lower, const double* X, double* Y, int t,
                           const double* rowscale) {
   if (lower) {
     if (M.lvl_ptr_f.size() < 2 || M.lvl_ptr_f.back() != M.n)
       return Status::make(VL_ERR_STATE, "no level schedule");
     return lower_levels(M, X, Y, t, rowscale);
+  }
+  // Narrow blocks (t <= 64, when the level path is forced): the fold would
+  // leave most lanes of its launch idle, so the full level order is used.
+  if (t <= 64) {
+    if (M.lvl_ptr_b.size() < 2 || M.lvl_ptr_b.back() != M.n)
+      return Status::make(VL_ERR_STATE, "no level schedule");
+    return upper_levels(M, M.lvl_ptr_b, M.lvl_nnz_b, M.full_order_b.p, nullptr, X, Y, t);
   }
   const int64_t H = M.head_rows;
   if (M.hlv_ptr_b.size() < 2 || M.hlv_ptr_b.back() != H ||

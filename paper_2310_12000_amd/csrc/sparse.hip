@@ -164,9 +164,8 @@ __device__ __forceinline__ UnitPos unit_pos(int64_t unit, int lane, Lanes L, int
   return p;
 }
 
-// Y_i = rs_i * (unit * X_i + sum_k vals[i,k] X_{nbr[i,k]}); the W <= 32
-// neighbour slots are loaded unconditionally-predicated so all gathers of a
-// row are in flight together.
+// Y_i = rs_i * (unit * X_i + sum_k vals[i,k] X_{nbr[i,k]}) over the W >= m
+// neighbour slots (empty slots add zero).
 template <int W, class In>
 __global__ __launch_bounds__(256) void spmm_ell_kernel(int64_t n, int m, int t, Lanes L,
                                                        const int* __restrict__ order,
@@ -181,19 +180,23 @@ __global__ __launch_bounds__(256) void spmm_ell_kernel(int64_t n, int m, int t, 
   if (!p.valid) return;
   const int* nb = nbr + p.i * m;
   const double* vb = vals + p.i * m;
-  int js[W];
-  double vv[W];
-#pragma unroll
-  for (int k = 0; k < W; ++k) {
-    js[k] = (k < m) ? nb[k] : -1;
-    vv[k] = (k < m) ? vb[k] : 0.0;
-  }
-  double xs[W];
-#pragma unroll
-  for (int k = 0; k < W; ++k) xs[k] = (js[k] >= 0) ? x(js[k], p.c) : 0.0;
   double acc = unit_diag ? x(p.i, p.c) : 0.0;
+  // neighbour slots in chunks of 8: a chunk's gathers are in flight together
+  // and the register footprint stays small enough for full occupancy
+#pragma unroll 1
+  for (int k0 = 0; k0 < W && k0 < m; k0 += 8) {
+    int js[8];
+    double vv[8], xs[8];
 #pragma unroll
-  for (int k = 0; k < W; ++k) acc += vv[k] * xs[k];
+    for (int k = 0; k < 8; ++k) {
+      js[k] = (k0 + k < m) ? nb[k0 + k] : -1;
+      vv[k] = (k0 + k < m) ? vb[k0 + k] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) xs[k] = (js[k] >= 0) ? x(js[k], p.c) : 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += vv[k] * xs[k];
+  }
   if (rs) acc *= rs[p.i];
   Y[p.i * t + p.c] = acc;
 }

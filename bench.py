@@ -196,7 +196,8 @@ def main():
     if not args.no_forms:
         out["forms"] = {}
         for name, fn in (("mixed", lambda: form_mixed(P, torch, w, coords, y, F, coords_p, Fp,
-                                                       theta, opts, rec, args)),
+                                                       theta, opts, args)),
+                         ("mixed_c3_shape", lambda: form_mixed_c3(P, torch, synth, args)),
                          ("batch", lambda: form_batch(P, torch, synth, args)),
                          ("serving", lambda: form_serving(P, torch, synth, args))):
             print(f"form: {name}", file=sys.stderr, flush=True)
@@ -205,11 +206,11 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def form_mixed(P, torch, w, coords, y, F, coords_p, Fp, theta, opts, rec, args):
+def form_mixed(P, torch, w, coords, y, F, coords_p, Fp, theta, opts, args, grad=True):
     """The same evaluation in the mixed form (FP32 preconditioner solves with
-    FP64 sums inside the FP64 PCG, for blocks wider than 64 columns: here the
-    prediction's s = 2000 columns), against the FP64 run of the same inputs and
-    probes."""
+    FP64 sums inside the FP64 PCG, for blocks wider than 64 columns: the
+    prediction's sample block), against the FP64 run of the same inputs and
+    probes; per-phase times of both."""
     import copy
     om = copy.copy(opts)
     om.precision = P.VL_MIXED
@@ -217,26 +218,48 @@ def form_mixed(P, torch, w, coords, y, F, coords_p, Fp, theta, opts, rec, args):
     for name, o in (("fp64", opts), ("mixed", om)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        g = P.VecchiaLaplace(coords, w["m"], w["kind"], theta, want_deriv=True)
+        g = P.VecchiaLaplace(coords, w["m"], w["kind"], theta, want_deriv=grad)
         g.find_mode(y, F, w["lik"], None, o)
-        nll, grad, _ = g.neg_log_marglik(o, want_grad=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        nll, gr, _ = g.neg_log_marglik(o, want_grad=grad)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
         mean, var, _ = g.predict(coords_p, Fp, o)
         torch.cuda.synchronize()
-        res[name] = (time.perf_counter() - t0, nll, grad, mean.cpu().numpy(), var.cpu().numpy())
+        t3 = time.perf_counter()
+        res[name] = (t3 - t0, nll, gr, mean.cpu().numpy(), var.cpu().numpy(),
+                     {"build_mode_s": t1 - t0, "nll_s": t2 - t1, "predict_s": t3 - t2})
         g.close()
     import numpy as np
     f, m = res["fp64"], res["mixed"]
     rel = lambda a, b: float(np.max(np.abs(np.asarray(a) - np.asarray(b))) /
                              max(np.max(np.abs(np.asarray(b))), 1e-300))
     log(args, f"mixed: {m[0]:.2f} s vs fp64 {f[0]:.2f} s")
-    return {"evals_per_s": 1.0 / m[0], "fp64_evals_per_s": 1.0 / f[0],
-            "speedup": f[0] / m[0], "nll_rel_err_vs_fp64": abs(m[1] - f[1]) / abs(f[1]),
-            "var_rel_err_vs_fp64": rel(m[4], f[4]), "mean_rel_err_vs_fp64": rel(m[3], f[3]),
-            "grad_rel_err_vs_fp64": rel(m[2], f[2]),
-            "note": "same workload and probes; FP32 preconditioner solves (FP32 B values and "
-                    "blocks, FP64 sums) inside the FP64 PCG for blocks wider than 64 columns "
-                    "(the prediction); blocks of at most 64 columns keep the FP64 solves. "
-                    "Errors against the FP64 GPU path"}
+    out = {"evals_per_s": 1.0 / m[0], "fp64_evals_per_s": 1.0 / f[0],
+           "speedup": f[0] / m[0], "phases_s": {"fp64": f[5], "mixed": m[5]},
+           "nll_rel_err_vs_fp64": abs(m[1] - f[1]) / abs(f[1]),
+           "var_rel_err_vs_fp64": rel(m[4], f[4]), "mean_rel_err_vs_fp64": rel(m[3], f[3])}
+    if grad:
+        out["grad_rel_err_vs_fp64"] = rel(m[2], f[2])
+    return out
+
+
+def form_mixed_c3(P, torch, synth, args):
+    """The mixed form on the shape of the n = 2e6 precision workload (Matern-3/2
+    range 0.02, m = 20, Poisson with offset 1, 64 probes, CG tolerance 1e-2,
+    10,000 test points, s = 256) at n = 2e5, the largest size this library
+    runs."""
+    w = synth.make("c3_n2e6", seed=args.seed, n=200000)
+    d = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    opts = P.vl_default_opts(cg_tol=w["cg_tol"], pred_cg_tol=w["pred_cg_tol"],
+                             num_probes=w["t"], num_pred_samples=w["s"], seed=args.seed)
+    out = form_mixed(P, torch, w, d(w["coords"]), d(w["y"]), d(w["F"]), d(w["coords_pred"]),
+                     d(w["Fp"]), (w["sigma2"], w["rho"]), opts, args, grad=False)
+    out["workload"] = ("n=200000 (the 2e6 workload's shape), Matern-3/2 rho=0.02, m=20, Poisson "
+                       "with offset 1, t=64, CG tol 1e-2, 10000 test points, s=256; one eval = "
+                       "build + mode + NLL + predict")
+    return out
 
 
 def form_batch(P, torch, synth, args):

@@ -19,12 +19,14 @@ Plain FP64 NumPy/SciPy, following the paper step by step:
   predict          eq. (latentpostpredictive) with B_p = I and the simulation
                    algorithm (Sec. 3.3.1, Alg. simAlgo)
 
-Readings of silent or ambiguous points (all listed in the design doc):
+Readings of silent or ambiguous points:
   * CG stops when the unpreconditioned residual 2-norm is below `cg_tol`
     (absolute), u_0 = 0, at most `max_cg` iterations.
-  * Newton starts at b = 0, takes full steps and stops when
+  * Newton starts at b = 0 and stops when
     |Psi_new - Psi_old| <= newton_tol * |Psi_old|, Psi(b) = log p(y|F+b)
-    - b^T Sigma~^{-1} b / 2; W for the marginal likelihood is taken at the
+    - b^T Sigma~^{-1} b / 2; a step that lowers Psi by more than
+    HALVING_SLACK |Psi| is halved, at most MAX_HALVINGS times (no halving can
+    help: keep b and stop); W for the marginal likelihood is taken at the
     final mode.
   * SLQ uses Rademacher probes eps; for VADU z = B^T (W+D^{-1})^{1/2} eps so
     that Cov(z) = P; the weight ||P^{-1/2} z||^2 is r_0^T z_0 of the CG run

@@ -14,7 +14,7 @@ Derivatives of A_i and D_i with respect to the covariance parameters follow the
 appendix "Derivatives of the Vecchia-approximated precision and covariance
 matrices".
 
-Readings where the paper is silent (also listed in the design doc):
+Readings where the paper is silent:
   * N(i) is sorted by (squared distance, index); squared distance is
     dx*dx + dy*dy evaluated as two products and one sum (no fused multiply-add).
   * For i <= m+1, N(i) is all earlier points.

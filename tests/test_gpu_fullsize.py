@@ -5,7 +5,8 @@ run the whole path in seconds:
             50 probes, CG tolerance 1e-3, 10,000 test points, s = 2000
             (the configuration the throughput is measured on);
   c3_n2e6   n = 2,000,000, Matern-3/2 range 0.02, m = 20, Poisson with
-            offset 1, 64 probes, CG tolerance 1e-2, s = 256.
+            offset 1, 64 probes, CG tolerance 1e-2, s = 256 (skipped, see
+            below), and the same shape at n = 200,000.
 
 Checks, each against what the oracle computes exactly at this size:
   * every neighbour set (exact), every D_i (1e-9) and every row A_i within
@@ -45,9 +46,15 @@ C3_FAULT = ("the library refuses n above 262,144: a build at n = 2,000,000 ended
             "at this size shows no out-of-bounds access); this case stays off the GPU until "
             "the cause is shown")
 WORKLOADS = [
-    pytest.param("c2_n1e5", id="c2_n1e5"),
-    pytest.param("c3_n2e6", id="c3_n2e6", marks=pytest.mark.skip(reason=C3_FAULT)),
+    pytest.param(("c2_n1e5", {}), id="c2_n1e5"),
+    # the n = 2e6 workload's shape at the largest size the library runs
+    pytest.param(("c3_n2e6", {"n": 200000}), id="c3_shape_n2e5"),
+    pytest.param(("c3_n2e6", {}), id="c3_n2e6", marks=pytest.mark.skip(reason=C3_FAULT)),
 ]
+# The oracle's Newton iteration replaying the device's CG counts takes
+# minutes at the n = 2e5 shape (about 2100 CG iterations); the first-order
+# condition checks that mode instead.
+SLOW_ORACLE_MODE = {"c3_shape_n2e5"}
 
 
 @pytest.fixture(scope="module")
@@ -61,9 +68,10 @@ def P():
 
 @pytest.fixture(scope="module", params=WORKLOADS)
 def case(request, P):
-    name = request.param
+    base, over = request.param
+    name = base if not over else f"{base} n={over['n']}"
     say(f"case: {name} inputs")
-    w = synth.make(name, seed=5)
+    w = synth.make(base, seed=5, **over)
     say(f"case: {name} oracle neighbours and factor over row ranges")
     nbr, A, D = oracle_pool.neighbours_and_factor(w["coords"], w["m"], w["kind"],
                                                   (w["sigma2"], w["rho"]))
@@ -144,8 +152,10 @@ def test_neighbours_and_factor(case):
     assert e_d < TOL
 
 
-def test_mode_matches_the_oracle(case):
+def test_mode_matches_the_oracle(request, case):
     name, w, model, _, fit = case
+    if request.node.callspec.id in SLOW_ORACLE_MODE:
+        pytest.skip("oracle Newton takes minutes here; the first-order condition test covers it")
     say(f"case: {name} oracle Newton mode with the device's CG counts")
     b, _, _, replayed = oracle_mode_matching(model, w["y"], w["F"], w["lik"], None, fit["o"],
                                              fit["newton_cg"], gpu_halvings=fit["halvings"])

@@ -63,3 +63,15 @@ def test_invalid_arguments_rejected_without_device(L):
     # null handles
     assert L.vl_set_theta(None, th) == P.VL_ERR_INVALID_ARG
     assert L.vl_export_count(None, 0) == -1
+
+
+def test_sizes_above_the_verified_limit_are_refused(L):
+    # n above 262,144 is refused before any device work (see include/vl.h:
+    # a larger build ended in a GPU fault whose cause is not found)
+    import paper_2310_12000_amd as P
+    h = ctypes.c_void_p()
+    th = (ctypes.c_double * 2)(1.0, 0.1)
+    fake = ctypes.c_void_p(1)
+    assert L.vl_build_vecchia(fake, 262145, 20, 1, th, None, 0,
+                              ctypes.byref(h)) == P.VL_ERR_INVALID_ARG
+    assert b"verified limit" in L.vl_last_error()

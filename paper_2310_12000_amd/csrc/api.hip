@@ -37,6 +37,7 @@ Status finish_factor(Model& M) {
                      n, M.dval.p, M.dinv.p);
   VL_TRY(check_launch("recip"));
   VL_TRY(refresh_transpose_values(M));
+  VL_TRY(refresh_group_values(M));
   VL_TRY(refresh_head_values(M));
   ++M.factor_version;
   VL_TRY(sync_stream(M.stream));
@@ -106,6 +107,7 @@ static Status build(const double* coords, int64_t n, int m, int cov, const doubl
     VL_TRY(knn_build_grid(*M));
     VL_TRY(knn_query(*M, nullptr, n, M->nbr.p));
     VL_TRY(build_transpose(*M));
+    VL_TRY(build_groups(*M));
     VL_TRY(build_head_schedule(*M));
     VL_TRY(build_tail_orders(*M));
     VL_TRY(compute_factor(*M));

@@ -390,6 +390,8 @@ static double spmm_bytes(const Model& M, int t, bool rowscale) {
 static Status launch_ell(Model& M, const double* vals, const double* X, double* Y, int t,
                          const double* rowscale, int unit_diag) {
   TimedLaunch tl(M, kTimeSpmmB, spmm_bytes(M, t, rowscale != nullptr));
+  if (unit_diag && vals == M.bval.p && group_spmm_ok(M, t))
+    return spmm_group_b(M, X, Y, t, rowscale);
   if (t > 64) {
     const int* ord = spatial_order(M);
     if (vec2_ok(t, X, Y)) {
@@ -428,6 +430,7 @@ Status spmm_bt(Model& M, const double* X, double* Y, int t, const double* diag,
   TimedLaunch tl(M, kTimeSpmmBt,
                  spmm_bytes(M, t, false) + 4.0 * (M.n + 1) +
                      (diag ? 8.0 * M.n + 8.0 * M.n * t : 0.0));
+  if (group_spmm_ok(M, t)) return spmm_group_bt(M, X, Y, t, diag, diagvec);
   if (t > 64) {
     const int* ord = spatial_order(M);
     const int vec = vec2_ok(t, X, Y, diag ? diagvec : nullptr) ? 2 : 1;

@@ -92,6 +92,36 @@ struct GridGeom {
   int G;
 };
 
+// Grouped form of B or B^T for products over blocks of many columns: rows
+// in groups of kGroupRows consecutive positions of the spatial order; per
+// group the sorted union of the columns its rows touch (padded), and a dense
+// kGroupRows-wide weight column per union entry.
+#ifndef VL_GROUP_ROWS
+#define VL_GROUP_ROWS 4
+#endif
+constexpr int kGroupRows = VL_GROUP_ROWS;
+#ifndef VL_GROUP_MIN_T
+#define VL_GROUP_MIN_T 32
+#endif
+constexpr int kGroupMinT = VL_GROUP_MIN_T;  // block widths that use them
+constexpr int kGroupMaxT = 64;
+struct GroupOp {
+  DevBuf<int> ptr;    // groups + 1 padded union offsets
+  DevBuf<int> col;    // union columns, ascending per group
+  DevBuf<int> cnt;    // union length per group before padding
+  DevBuf<double> w;   // union entries x kGroupRows weights
+  DevBuf<int> pos;    // per B entry (i, k): its index in w, -1 for empty slots
+  int64_t cols = 0;   // padded union entries in all
+  void reset() {
+    ptr.release();
+    col.release();
+    cnt.release();
+    w.release();
+    pos.release();
+    cols = 0;
+  }
+};
+
 // State of one block CG solve (t columns).
 struct CgState {
   int t = 0;
@@ -190,6 +220,11 @@ struct Model {
   DevBuf<int> hlv_rows_b;
   int64_t fold_nnz = 0;                         // tail entries of the head rows
   DevBuf<double> lvl_fold;                      // head rows' folded right-hand sides
+  // grouped products for wide blocks (group.hip); off when a group would
+  // gather more columns than its build can sort
+  bool grp_ok = false;
+  int64_t grp_count = 0;
+  GroupOp grp_b, grp_bt;
 
   // neighbour-search grid
   int grid_G = 0;
@@ -307,6 +342,14 @@ Status trsm_b(Model& M, const double* X, double* Y, int t, const double* rowscal
               bool prefilled);
 Status trsm_bt(Model& M, const double* X, double* Y, int t, bool prefilled);
 int spmm_nblocks(int64_t n, int t);
+
+// ---- grouped products (group.hip)
+Status build_groups(Model& M);
+Status refresh_group_values(Model& M);
+bool group_spmm_ok(const Model& M, int t);
+Status spmm_group_b(Model& M, const double* X, double* Y, int t, const double* rs);
+Status spmm_group_bt(Model& M, const double* X, double* Y, int t, const double* d,
+                     const double* V);
 
 // ---- head solves (head.hip)
 constexpr int kHeadRows = 16384;

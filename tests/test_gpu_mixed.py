@@ -1,9 +1,8 @@
 """Mixed-precision form against the FP64 oracle: FP32 preconditioner solves
 (FP32 B values and blocks, FP64 row sums) inside the FP64 block PCG, whose
 FP64 operator and residual recurrence refine every FP32 solve, for blocks
-wider than 64 columns (narrower blocks keep the FP64 solves); the
-prediction solves use the flexible beta.  Probe and sample counts are chosen
-above 64 so that the FP32 solves run.  The bar: relative 1e-4 on the negative
+wider than 64 columns (narrower blocks keep the FP64 solves).  Probe and
+sample counts are chosen above 64 so that the FP32 solves run.  The bar: relative 1e-4 on the negative
 log-likelihood and 1e-3 on the predictive variances; the errors of the mode,
 the predictive means and the gradient are measured and printed."""
 import numpy as np

@@ -1,4 +1,5 @@
 // C ABI of the library (declared in include/vl.h).
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -39,6 +40,7 @@ Status finish_factor(Model& M) {
   VL_TRY(refresh_transpose_values(M));
   VL_TRY(refresh_group_values(M));
   VL_TRY(refresh_head_values(M));
+  VL_TRY(dense_factor(M));
   ++M.factor_version;
   VL_TRY(sync_stream(M.stream));
   return read_status(M);
@@ -108,6 +110,9 @@ static Status build(const double* coords, int64_t n, int m, int cov, const doubl
     VL_TRY(knn_query(*M, nullptr, n, M->nbr.p));
     VL_TRY(build_transpose(*M));
     VL_TRY(build_groups(*M));
+    M->dense_rows = kDenseRows;
+    if (const char* env = std::getenv("VL_DENSE_ROWS")) M->dense_rows = std::atoi(env);  // tuning knob
+    if (M->dense_rows < 0) M->dense_rows = 0;
     VL_TRY(build_head_schedule(*M));
     VL_TRY(build_tail_orders(*M));
     VL_TRY(compute_factor(*M));

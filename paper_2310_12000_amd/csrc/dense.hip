@@ -1,0 +1,279 @@
+// The leading K x K block of B as an explicit dense inverse, for the
+// triangular solves of narrow blocks (t <= 64).
+//
+// B is unit lower triangular and row i < K only involves columns < K, so the
+// first K unknowns of B y = x are y_K = G x_K with G = B_KK^{-1}, and those
+// of B^T y = x are y_K = G^T (x_K - B_RK^T y_R), where R are the rows
+// K..n-1, solved first.  With a random ordering the earliest points carry
+// most of the dependency depth of the head: at n = 1e5, m = 20 the first
+// 16384 rows span 214 levels, the rows 2048..16383 on their own only 71.
+// Taking the first K = 2048 rows out of the latency-bound LDS head solve and
+// applying G instead (16.8 MB of FP64 per application, read at bandwidth by
+// the whole chip) removes two thirds of its critical path.
+//
+// G is computed once per factor (Sec. 2.1: B changes with the covariance
+// parameters) by forward substitution of B_KK G = I, column by column, and
+// kept in both orientations: Gf[c K + i] = G_ic (columns contiguous) for
+// G x, Gb[i K + c] = G_ic (rows contiguous) for G^T x.
+#include "vl_internal.h"
+#include "vl_ops.h"
+
+namespace vl {
+
+constexpr int kDenseCols = 8;  // columns of G per workgroup of the inverse
+
+// Columns c0..c0+7 of G in LDS; lane = (column cl, part q).  Part q sums the
+// slots q, q + 8, q + 16, q + 24 of row i; the eight parts meet by a
+// butterfly, and row i is final before row i + 1 reads it (one wave: its LDS
+// accesses complete in order).  Slot data does not depend on G and is
+// fetched one row ahead.
+__global__ __launch_bounds__(64) void dense_inverse_kernel(int K, int m,
+                                                            const int* __restrict__ nbr,
+                                                            const double* __restrict__ bval,
+                                                            double* __restrict__ Gf,
+                                                            double* __restrict__ Gb) {
+  extern __shared__ double s_g[];  // kDenseCols x K
+  const int lane = threadIdx.x, cl = lane >> 3, q = lane & 7;
+  const int c0 = blockIdx.x * kDenseCols;
+  const int c = c0 + cl;
+  for (int k = lane; k < kDenseCols * K; k += 64) s_g[k] = 0.0;
+  __syncthreads();
+  double* g = s_g + cl * K;
+  int nj[4];
+  double nw[4];
+  auto fetch = [&](int i) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = q + 8 * u;
+      const bool in = i < K && k < m;
+      nj[u] = in ? nbr[(int64_t)i * m + k] : -1;
+      nw[u] = in ? bval[(int64_t)i * m + k] : 0.0;
+    }
+  };
+  fetch(c0);
+  for (int i = c0; i < K; ++i) {
+    int cj[4];
+    double cw[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      cj[u] = nj[u];
+      cw[u] = nw[u];
+    }
+    fetch(i + 1);
+    // g_j = 0 for j < c (never written), so earlier columns add nothing
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (cj[u] >= 0) s += cw[u] * g[cj[u]];
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    s += __shfl_xor(s, 4);
+    if (q == 0 && c < K && i >= c) g[i] = (i == c ? 1.0 : 0.0) - s;
+  }
+  __syncthreads();
+  for (int k = lane; k < kDenseCols * K; k += 64) {
+    const int cc = c0 + k / K, i = k % K;
+    if (cc < K) Gf[(int64_t)cc * K + i] = s_g[k];
+  }
+  for (int k = lane; k < kDenseCols * K; k += 64) {
+    const int i = k / kDenseCols, u = k % kDenseCols;
+    if (c0 + u < K) Gb[(int64_t)i * K + c0 + u] = s_g[u * K + i];
+  }
+}
+
+// out[r, c] = sum_s A[s K + r] v(s, c), v(s, c) = V[s t + c] (times rs[s]
+// when given).  A is zero outside the triangle, so for the 64 rows of a row
+// chunk the sum runs over s < end of the chunk (LOWER: A = Gf, out = G v) or
+// s >= start of the chunk (A = Gb, out = G^T v).  The s range is cut into
+// segments of kSeg: block (chunk x, segment y, column chunk z) stages its
+// segment of v in LDS, its 8 waves take 32 steps each (16 loads of A in
+// flight for one column, 8 for eight), meet in LDS in wave order and write
+// one partial; a second kernel adds the partials of a chunk in segment
+// order.  Every value of A is read once per column chunk, and the sums are
+// deterministic.
+constexpr int kSeg = 256;
+constexpr int kApplyWaves = 8;
+
+__host__ __device__ __forceinline__ int seg_lo(int chunk, bool lower) {
+  return lower ? 0 : (chunk * 64) / kSeg;
+}
+__host__ __device__ __forceinline__ int seg_hi(int chunk, int K, bool lower) {
+  const int end = lower ? min(K, chunk * 64 + 64) : K;
+  return (end + kSeg - 1) / kSeg;
+}
+
+template <int TC, bool LOWER>
+__global__ __launch_bounds__(64 * kApplyWaves) void dense_part_kernel(
+    int K, int t, const double* __restrict__ A, const double* __restrict__ V,
+    const double* __restrict__ rs, double* __restrict__ part) {
+  __shared__ double s_v[kSeg][TC];
+  __shared__ double s_red[kApplyWaves][TC][64];
+  const int chunk = blockIdx.x, g = blockIdx.y;
+  if (g < seg_lo(chunk, LOWER) || g >= seg_hi(chunk, K, LOWER)) return;  // uniform
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r = chunk * 64 + lane;
+  const int c0 = blockIdx.z * TC;
+  const int s_lo = max(g * kSeg, LOWER ? 0 : chunk * 64);
+  const int s_hi = min((g + 1) * kSeg, LOWER ? min(K, chunk * 64 + 64) : K);
+  for (int e = threadIdx.x; e < kSeg * TC; e += 64 * kApplyWaves) {
+    const int s = g * kSeg + e / TC, c = c0 + e % TC;
+    double v = 0.0;
+    if (s >= s_lo && s < s_hi && c < t) v = V[(int64_t)s * t + c] * (rs ? rs[s] : 1.0);
+    s_v[e / TC][e % TC] = v;
+  }
+  __syncthreads();
+  double acc[TC];
+#pragma unroll
+  for (int cc = 0; cc < TC; ++cc) acc[cc] = 0.0;
+  constexpr int kStep = kSeg / kApplyWaves;  // 32
+  constexpr int kU = TC == 1 ? 16 : 8;  // loads in flight (registers for 8 columns)
+  const int sa = g * kSeg + wave * kStep;
+#pragma unroll 1
+  for (int h = 0; h < kStep; h += kU) {
+    double a[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int s = sa + h + u;
+      a[u] = (s >= s_lo && s < s_hi && r < K) ? A[(int64_t)s * K + r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int sl = wave * kStep + h + u;
+#pragma unroll
+      for (int cc = 0; cc < TC; ++cc) acc[cc] += a[u] * s_v[sl][cc];
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < TC; ++cc) s_red[wave][cc][lane] = acc[cc];
+  __syncthreads();
+  if (wave == 0 && r < K) {
+#pragma unroll
+    for (int cc = 0; cc < TC; ++cc) {
+      if (c0 + cc >= t) break;
+      double v = s_red[0][cc][lane];
+      for (int w = 1; w < kApplyWaves; ++w) v += s_red[w][cc][lane];
+      part[((int64_t)g * K + r) * t + c0 + cc] = v;
+    }
+  }
+}
+
+template <bool LOWER>
+__global__ void dense_reduce_kernel(int K, int t, const double* __restrict__ part,
+                                    double* __restrict__ out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)K * t) return;
+  const int r = static_cast<int>(e / t);
+  const int chunk = r / 64;
+  double v = 0.0;
+  for (int g = seg_lo(chunk, LOWER); g < seg_hi(chunk, K, LOWER); ++g)
+    v += part[(int64_t)g * K * t + e];
+  out[e] = v;
+}
+
+// xp[j, c] = Y[j, c] - sum of the B^T entries of row j < K whose child lies
+// in K..H-1 (entries [lo[j], split[j]): children sorted ascending, those
+// from H on were subtracted before the head solve).  One wave per row, lanes
+// over entries, a fixed butterfly per column.
+__global__ __launch_bounds__(256) void dense_fold_kernel(int K, int t, const int* __restrict__ lo,
+                                                         const int* __restrict__ split,
+                                                         const int* __restrict__ bt_col,
+                                                         const double* __restrict__ bt_val,
+                                                         const double* __restrict__ Y,
+                                                         double* __restrict__ xp) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= K) return;
+  const int b = lo[j], e = split[j];
+  for (int c = 0; c < t; ++c) {
+    double part = 0.0;
+    for (int q = b + lane; q < e; q += 64) part += bt_val[q] * Y[(int64_t)bt_col[q] * t + c];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) part += __shfl_xor(part, o);
+    if (lane == 0) xp[(int64_t)j * t + c] = Y[(int64_t)j * t + c] - part;
+  }
+}
+
+// lo[j] = first B^T entry of row j < K with child >= K.
+__global__ void dense_lo_kernel(int K, const int* __restrict__ bt_ptr,
+                                const int* __restrict__ bt_col, int* __restrict__ lo) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= K) return;
+  int a = bt_ptr[j], b = bt_ptr[j + 1];
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (bt_col[mid] < K) {
+      a = mid + 1;
+    } else {
+      b = mid;
+    }
+  }
+  lo[j] = a;
+}
+
+Status build_dense(Model& M) {
+  const int K = M.dense_rows;
+  if (K <= 0) return Status::ok();
+  const size_t kk = static_cast<size_t>(K) * K;
+  VL_TRY(M.dense_gf.alloc(kk));
+  VL_TRY(M.dense_gb.alloc(kk));
+  VL_TRY(M.dense_lo.alloc(K));
+  hipLaunchKernelGGL(dense_lo_kernel, dim3((K + 255) / 256), dim3(256), 0, M.stream, K,
+                     M.bt_ptr.p, M.bt_col.p, M.dense_lo.p);
+  const size_t lds = sizeof(double) * kDenseCols * K;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(dense_inverse_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  (void)hipGetLastError();
+  VL_TRY(check_launch("dense block"));
+  return sync_stream(M.stream);
+}
+
+Status dense_factor(Model& M) {
+  const int K = M.dense_rows;
+  if (K <= 0) return Status::ok();
+  const size_t lds = sizeof(double) * kDenseCols * K;
+  hipLaunchKernelGGL(dense_inverse_kernel, dim3((K + kDenseCols - 1) / kDenseCols), dim3(64), lds,
+                     M.stream, K, M.m, M.nbr.p, M.bval.p, M.dense_gf.p, M.dense_gb.p);
+  return check_launch("dense inverse");
+}
+
+template <bool LOWER>
+static Status launch_apply(Model& M, const double* A, const double* V, const double* rs,
+                           double* out, int t) {
+  const int K = M.dense_rows;
+  const int nseg = (K + kSeg - 1) / kSeg;
+  VL_TRY(M.dense_part.reserve(static_cast<size_t>(nseg) * K * t));
+  const unsigned gx = static_cast<unsigned>((K + 63) / 64);
+  if (t == 1) {
+    hipLaunchKernelGGL((dense_part_kernel<1, LOWER>), dim3(gx, nseg, 1), dim3(64 * kApplyWaves),
+                       0, M.stream, K, t, A, V, rs, M.dense_part.p);
+  } else {
+    hipLaunchKernelGGL((dense_part_kernel<8, LOWER>), dim3(gx, nseg, (t + 7) / 8),
+                       dim3(64 * kApplyWaves), 0, M.stream, K, t, A, V, rs, M.dense_part.p);
+  }
+  const int64_t kt = static_cast<int64_t>(K) * t;
+  hipLaunchKernelGGL(dense_reduce_kernel<LOWER>, dim3(static_cast<unsigned>((kt + 255) / 256)),
+                     dim3(256), 0, M.stream, K, t, M.dense_part.p, out);
+  return check_launch("dense apply");
+}
+
+static double apply_bytes(const Model& M, int t) {
+  const double K = M.dense_rows;
+  return 8.0 * K * (K + 1) / 2.0 + 16.0 * K * t;
+}
+
+Status dense_lower(Model& M, const double* X, double* Y, int t, const double* rs) {
+  TimedLaunch tl(M, kTimeHeadLower, apply_bytes(M, t));
+  return launch_apply<true>(M, M.dense_gf.p, X, rs, Y, t);
+}
+
+Status dense_upper(Model& M, double* Y, int t) {
+  const int K = M.dense_rows;
+  TimedLaunch tl(M, kTimeHeadUpper, apply_bytes(M, t));
+  VL_TRY(M.dense_xp.reserve(static_cast<size_t>(K) * t));
+  hipLaunchKernelGGL(dense_fold_kernel, dim3((K + 3) / 4), dim3(256), 0, M.stream, K, t,
+                     M.dense_lo.p, M.head_split.p, M.bt_col.p, M.bt_val.p, Y, M.dense_xp.p);
+  return launch_apply<false>(M, M.dense_gb.p, M.dense_xp.p, nullptr, Y, t);
+}
+
+}  // namespace vl

@@ -34,24 +34,27 @@ __device__ __forceinline__ void lds_publish(double* p, double v) {
 }
 
 // ------------------------------------------------------- level schedules
-// Longest-path levels of the head rows by repeated relaxation in LDS
+// Longest-path levels of the head rows K..H-1 by repeated relaxation in LDS
 // (monotone, so it stops at the fixpoint): forward uses N(i), backward uses
-// the rows of B^T restricted to head rows.
+// the rows of B^T restricted to head rows.  Rows below K are solved apart
+// (a dense block) and count as known: they get level -1, and forward
+// dependencies on them are dropped (backward rows K..H-1 only depend on
+// later rows).
 __global__ __launch_bounds__(kHeadThreads) void head_levels_kernel(
-    int H, int m, const int* __restrict__ nbr, const int* __restrict__ bt_ptr,
+    int H, int K, int m, const int* __restrict__ nbr, const int* __restrict__ bt_ptr,
     const int* __restrict__ bt_col, int backward, int* __restrict__ level_out) {
   extern __shared__ int s_lev[];
   for (int i = threadIdx.x; i < H; i += kHeadThreads) s_lev[i] = 0;
   __syncthreads();
   for (;;) {
     int changed = 0;
-    for (int i = threadIdx.x; i < H; i += kHeadThreads) {
+    for (int i = K + threadIdx.x; i < H; i += kHeadThreads) {
       int l = 0;
       if (!backward) {
         for (int k = 0; k < m; ++k) {
           const int j = nbr[(int64_t)i * m + k];
           if (j < 0) break;
-          l = max(l, s_lev[j] + 1);
+          if (j >= K) l = max(l, s_lev[j] + 1);
         }
       } else {
         const int b = bt_ptr[i], e = bt_ptr[i + 1];
@@ -68,10 +71,11 @@ __global__ __launch_bounds__(kHeadThreads) void head_levels_kernel(
     }
     if (!__syncthreads_or(changed)) break;
   }
-  for (int i = threadIdx.x; i < H; i += kHeadThreads) level_out[i] = s_lev[i];
+  for (int i = threadIdx.x; i < H; i += kHeadThreads) level_out[i] = i < K ? -1 : s_lev[i];
 }
 
-// Counting sort of head rows by level: ptr[L] = first position of level L.
+// Counting sort of head rows by level: ptr[L] = first position of level L;
+// rows with level -1 get no position.
 __global__ __launch_bounds__(kHeadThreads) void head_sort_kernel(int H,
                                                                   const int* __restrict__ level,
                                                                   int* __restrict__ ptr,
@@ -81,17 +85,20 @@ __global__ __launch_bounds__(kHeadThreads) void head_sort_kernel(int H,
   for (int i = threadIdx.x; i <= H; i += kHeadThreads) s_cnt[i] = 0;
   __syncthreads();
   int mx = 0;
+  int any = 0;
   for (int i = threadIdx.x; i < H; i += kHeadThreads) {
     const int l = level[i];
+    if (l < 0) continue;
     atomicAdd(&s_cnt[l], 1);
     mx = max(mx, l);
+    any = 1;
   }
   __shared__ int s_max;
-  if (threadIdx.x == 0) s_max = 0;
+  if (threadIdx.x == 0) s_max = -1;
   __syncthreads();
-  atomicMax(&s_max, mx);
+  if (any) atomicMax(&s_max, mx);
   __syncthreads();
-  const int nlev = (H > 0) ? s_max + 1 : 0;
+  const int nlev = s_max + 1;
   if (threadIdx.x == 0) {
     int run = 0;
     for (int l = 0; l < nlev; ++l) {
@@ -105,12 +112,23 @@ __global__ __launch_bounds__(kHeadThreads) void head_sort_kernel(int H,
   }
   __syncthreads();
   for (int i = threadIdx.x; i < H; i += kHeadThreads) {
+    if (level[i] < 0) continue;
     const int pos = atomicAdd(&s_cnt[level[i]], 1);
     rows[pos] = i;
   }
 }
 
 // ------------------------------------------------------------ head solves
+#ifndef VL_HEAD_BACKOFF
+#define VL_HEAD_BACKOFF 0
+#endif
+// A wave whose poll round moved no lane forward sleeps briefly, leaving the
+// LDS to the waves on the critical path.
+__device__ __forceinline__ void head_backoff(bool moved) {
+  if (VL_HEAD_BACKOFF > 0 && !__any(moved)) __builtin_amdgcn_s_sleep(VL_HEAD_BACKOFF);
+}
+
+
 // One workgroup per column c = blockIdx.x.  The head values live in LDS,
 // pre-filled with the sentinel.  The level-ordered positions are cut into
 // batches of 64; wave w takes batches w, w + NT/64, ... and each lane one row
@@ -126,20 +144,22 @@ __global__ __launch_bounds__(kHeadThreads) void head_sort_kernel(int H,
 // round wait for it.
 template <int W, int NT>
 __global__ __launch_bounds__(NT) void head_lower_kernel(
-    int H, int m, int t, const int* __restrict__ prow, const int* __restrict__ pnbr,
-    const double* __restrict__ pval, const double* __restrict__ X,
+    int H, int P, int K, int m, int t, const int* __restrict__ prow,
+    const int* __restrict__ pnbr, const double* __restrict__ pval, const double* __restrict__ X,
     const double* __restrict__ rs, double* Y) {
   extern __shared__ double s_y[];
   const int c = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   constexpr int kWaves = NT / 64;
-  for (int i = tid; i < H; i += NT) s_y[i] = sentinel();
+  // rows below K are already solved in Y (the dense block); the P positions
+  // hold rows K..H-1
+  for (int i = tid; i < H; i += NT) s_y[i] = i < K ? Y[(int64_t)i * t + c] : sentinel();
   __syncthreads();
   int a_row = -1;            // stage A: row id, two batches ahead
   int ni = -1, nj[W];        // stage B: one batch ahead
   double nv[W], nx = 0.0;
-  auto stage_a = [&](int p) { a_row = (p < H) ? prow[p] : -1; };
+  auto stage_a = [&](int p) { a_row = (p < P) ? prow[p] : -1; };
   auto stage_b = [&](int p, int row) {
     ni = row;
 #pragma unroll
@@ -158,7 +178,7 @@ __global__ __launch_bounds__(NT) void head_lower_kernel(
   stage_a(batch * 64 + lane);
   stage_b(batch * 64 + lane, a_row);
   stage_a((batch + kWaves) * 64 + lane);
-  while (batch * 64 < H) {
+  while (batch * 64 < P) {
     const int ci = ni;
     int cj[W];
     double cv[W];
@@ -174,18 +194,22 @@ __global__ __launch_bounds__(NT) void head_lower_kernel(
     bool pending = ci >= 0;
     int kk = 0;
     while (__any(pending)) {
+      bool moved = false;
       if (pending) {
         // all pending values first (independent LDS reads), then consume in order
         double yv[W];
 #pragma unroll
         for (int k = 0; k < W; ++k)
           yv[k] = (k >= kk && cj[k] >= 0) ? lds_poll(&s_y[cj[k]]) : 0.0;
-        kk = consume_ready<W>(cj, cv, yv, kk, acc);
+        const int k1 = consume_ready<W>(cj, cv, yv, kk, acc);
+        moved = k1 != kk;
+        kk = k1;
         if (kk >= W) {
           lds_publish(&s_y[ci], acc);
           pending = false;
         }
       }
+      head_backoff(moved);
     }
     batch += kWaves;
   }
@@ -214,7 +238,7 @@ struct HeadRanges {
 
 template <int NT>
 __global__ __launch_bounds__(NT) void head_upper_kernel(
-    int H, int t, HeadRanges R, const int* __restrict__ prow, const int* __restrict__ pptr,
+    int H, int K, int t, HeadRanges R, const int* __restrict__ prow, const int* __restrict__ pptr,
     const int* __restrict__ psplit, const int* __restrict__ pcol,
     const double* __restrict__ pval, const int* __restrict__ wcol,
     const double* __restrict__ wval, double* Y) {
@@ -297,6 +321,7 @@ __global__ __launch_bounds__(NT) void head_upper_kernel(
       uint64_t long_mask = __ballot(is_long);
       int kk = 0;
       while (__any(pending) || long_mask) {
+        bool moved = false;
         if (pending) {
           if (kk == kWin) {  // second window of a row
 #pragma unroll
@@ -311,7 +336,9 @@ __global__ __launch_bounds__(NT) void head_upper_kernel(
 #pragma unroll
           for (int k = 0; k < kWin; ++k)
             lv[k] = (k >= kk && cb[k] >= 0) ? lds_poll(&s_y[cb[k]]) : 0.0;
-          kk = consume_ready<kWin>(cb, vb, lv, kk, acc);
+          const int k1 = consume_ready<kWin>(cb, vb, lv, kk, acc);
+          moved = k1 != kk;
+          kk = k1;
           if (kk == kWin) {
             if (q + kWin >= e) {
               lds_publish(&s_y[j], acc);
@@ -355,14 +382,17 @@ __global__ __launch_bounds__(NT) void head_upper_kernel(
               lds_publish(&s_y[j], acc);
             }
             long_mask &= long_mask - 1;
+            moved = true;
           }
         }
+        head_backoff(moved);
       }
       batch += kWaves;
     }
     __syncthreads();  // the range is solved before the next one folds it in
   }
-  for (int i = tid; i < H; i += NT) Y[(int64_t)i * t + c] = s_y[i];
+  // rows below K are solved afterwards (the dense block) from Y's folded values
+  for (int i = K + tid; i < H; i += NT) Y[(int64_t)i * t + c] = s_y[i];
 }
 
 // y_j <- x_j - sum over the tail entries of the B^T row of head row j (all
@@ -384,23 +414,26 @@ __global__ void head_upper_pre_kernel(int H, int t, const int* __restrict__ spli
 Status head_lower(Model& M, const double* X, double* Y, int t, const double* rs) {
   const int H = M.head_rows;
   if (H == 0) return Status::ok();
+  const int K = M.dense_rows, P = M.head_pos;
+  if (K > 0) VL_TRY(dense_lower(M, X, Y, t, rs));  // rows 0..K-1
+  if (P == 0) return Status::ok();
   TimedLaunch tl(M, kTimeHeadLower,
                  12.0 * M.nnz_head_f + 16.0 * H * t + (rs ? 8.0 * H : 0.0));
   const size_t lds = sizeof(double) * H;
   // two row windows (current and prefetched) stay in registers: 512 threads
   // above 8 slots
   if (M.m <= 8) {
-    hipLaunchKernelGGL((head_lower_kernel<8, 1024>), dim3(t), dim3(1024), lds, M.stream, H, M.m,
-                       t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
+    hipLaunchKernelGGL((head_lower_kernel<8, 1024>), dim3(t), dim3(1024), lds, M.stream, H, P, K,
+                       M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
   } else if (M.m <= 16) {
-    hipLaunchKernelGGL((head_lower_kernel<16, 512>), dim3(t), dim3(512), lds, M.stream, H,
+    hipLaunchKernelGGL((head_lower_kernel<16, 512>), dim3(t), dim3(512), lds, M.stream, H, P, K,
                        M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
   } else if (M.m <= 24) {
-    hipLaunchKernelGGL((head_lower_kernel<24, 512>), dim3(t), dim3(512), lds, M.stream, H,
+    hipLaunchKernelGGL((head_lower_kernel<24, 512>), dim3(t), dim3(512), lds, M.stream, H, P, K,
                        M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
   } else {
-    hipLaunchKernelGGL((head_lower_kernel<32, 512>), dim3(t), dim3(512), lds, M.stream, H, M.m,
-                       t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
+    hipLaunchKernelGGL((head_lower_kernel<32, 512>), dim3(t), dim3(512), lds, M.stream, H, P, K,
+                       M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
   }
   return check_launch("head lower");
 }
@@ -408,17 +441,22 @@ Status head_lower(Model& M, const double* X, double* Y, int t, const double* rs)
 Status head_upper(Model& M, const double* X, double* Y, int t) {
   const int H = M.head_rows;
   if (H == 0) return Status::ok();
+  const int K = M.dense_rows, P = M.head_pos;
   const int64_t work = (int64_t)H * t;
   hipLaunchKernelGGL(head_upper_pre_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0,
                      M.stream, H, t, M.head_split.p, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, Y);
-  const size_t lds = sizeof(double) * H;
-  TimedLaunch tl(M, kTimeHeadUpper, 12.0 * M.head_nnz_b + 4.0 * H + 16.0 * H * t);
-  HeadRanges R{};
-  R.n = static_cast<int>(M.hb_blocks.size()) - 1;
-  for (int k = 0; k <= R.n; ++k) R.start[k] = M.hb_blocks[k];
-  hipLaunchKernelGGL(head_upper_kernel<512>, dim3(t), dim3(512), lds, M.stream, H, t, R,
-                     M.hb_rows.p, M.hb_pptr.p, M.hb_split.p, M.hb_col.p, M.hb_val.p, M.hb_wcol.p,
-                     M.hb_wval.p, Y);
+  if (P > 0) {
+    const size_t lds = sizeof(double) * H;
+    TimedLaunch tl(M, kTimeHeadUpper, 12.0 * M.head_nnz_b + 4.0 * H + 16.0 * H * t);
+    HeadRanges R{};
+    R.n = static_cast<int>(M.hb_blocks.size()) - 1;
+    for (int k = 0; k <= R.n; ++k) R.start[k] = M.hb_blocks[k];
+    hipLaunchKernelGGL(head_upper_kernel<512>, dim3(t), dim3(512), lds, M.stream, H, K, t, R,
+                       M.hb_rows.p, M.hb_pptr.p, M.hb_split.p, M.hb_col.p, M.hb_val.p,
+                       M.hb_wcol.p, M.hb_wval.p, Y);
+    VL_TRY(check_launch("head upper"));
+  }
+  if (K > 0) VL_TRY(dense_upper(M, Y, t));  // rows 0..K-1, after every later row
   return check_launch("head upper");
 }
 
@@ -433,20 +471,22 @@ __global__ void head_copy_fwd_kernel(int H, int m, const int* __restrict__ prow,
 
 // Rows of B^T are sorted by column, so a head row's head-internal entries
 // (columns < H) form a prefix; split[j] is where its tail entries begin.
-__global__ void head_len_bwd_kernel(int H, const int* __restrict__ prow,
+// Lengths are taken for the P positions; split (optional) is written for
+// their rows.
+__global__ void head_len_bwd_kernel(int H, int P, const int* __restrict__ prow,
                                     const int* __restrict__ bt_ptr,
                                     const int* __restrict__ bt_col, int* __restrict__ len,
                                     int* __restrict__ split) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < H) {
+  if (p < P) {
     const int j = prow[p];
     int q = bt_ptr[j];
     const int e = bt_ptr[j + 1];
     while (q < e && bt_col[q] < H) ++q;
     len[p] = q - bt_ptr[j];
-    split[j] = q;
+    if (split) split[j] = q;
   }
-  if (p == H) len[p] = 0;
+  if (p == P) len[p] = 0;
 }
 
 __global__ void head_copy_bwd_kernel(int H, const int* __restrict__ prow,
@@ -498,15 +538,15 @@ __global__ void head_window_kernel(int H, const int* __restrict__ pptr,
 }
 
 Status refresh_head_values(Model& M) {
-  const int H = M.head_rows;
-  if (H == 0) return Status::ok();
-  const int64_t work = std::max<int64_t>((int64_t)H * M.m, M.head_nnz_b);
+  const int P = M.head_pos;
+  if (M.head_rows == 0 || P == 0) return Status::ok();
+  const int64_t work = std::max<int64_t>((int64_t)P * M.m, M.head_nnz_b);
   if (work == 0) return Status::ok();
   hipLaunchKernelGGL(head_vals_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0,
-                     M.stream, H, M.m, M.hf_rows.p, M.bval.p, M.hf_val.p,
+                     M.stream, P, M.m, M.hf_rows.p, M.bval.p, M.hf_val.p,
                      static_cast<int>(M.head_nnz_b), M.hb_src.p, M.hb_val.p);
-  hipLaunchKernelGGL(head_window_kernel, dim3((unsigned)(((int64_t)H * 16 + 255) / 256)),
-                     dim3(256), 0, M.stream, H, M.hb_pptr.p, M.hb_split.p, M.hb_col.p,
+  hipLaunchKernelGGL(head_window_kernel, dim3((unsigned)(((int64_t)P * 16 + 255) / 256)),
+                     dim3(256), 0, M.stream, P, M.hb_pptr.p, M.hb_split.p, M.hb_col.p,
                      M.hb_val.p, nullptr, M.hb_wval.p);
   return check_launch("head values");
 }
@@ -518,14 +558,16 @@ static void allow_lds(K kernel, size_t bytes) {
   (void)hipGetLastError();
 }
 
-// Reorder the backward head positions by index range (latest range first,
-// level order kept inside a range) and record, per position, where the
-// entries into the row's own range start.  Runs on the host (H <= 16384).
-static Status order_head_ranges(Model& M, int H, int nnzb) {
-  std::vector<int> rows(H), ptr(H + 1), col(nnzb > 0 ? nnzb : 1), src(nnzb > 0 ? nnzb : 1);
-  VL_HIP(hipMemcpyAsync(rows.data(), M.hb_rows.p, sizeof(int) * H, hipMemcpyDeviceToHost,
+// Reorder the P backward head positions by index range of their rows
+// (latest range first, level order kept inside a range) and record, per
+// position, where the entries into the row's own range start.  Runs on the
+// host (H <= 16384).
+static Status order_head_ranges(Model& M, int H, int P, int nnzb) {
+  std::vector<int> rows(P > 0 ? P : 1), ptr(P + 1), col(nnzb > 0 ? nnzb : 1),
+      src(nnzb > 0 ? nnzb : 1);
+  VL_HIP(hipMemcpyAsync(rows.data(), M.hb_rows.p, sizeof(int) * P, hipMemcpyDeviceToHost,
                         M.stream));
-  VL_HIP(hipMemcpyAsync(ptr.data(), M.hb_pptr.p, sizeof(int) * (H + 1), hipMemcpyDeviceToHost,
+  VL_HIP(hipMemcpyAsync(ptr.data(), M.hb_pptr.p, sizeof(int) * (P + 1), hipMemcpyDeviceToHost,
                         M.stream));
   if (nnzb > 0) {
     VL_HIP(hipMemcpyAsync(col.data(), M.hb_col.p, sizeof(int) * nnzb, hipMemcpyDeviceToHost,
@@ -539,13 +581,13 @@ static Status order_head_ranges(Model& M, int H, int nnzb) {
   for (int b = H / 4; b >= 256; b /= 4) lo.push_back(b);
   lo.push_back(0);
   std::vector<int> nrows, nptr(1, 0), ncol, nsrc, nsplit, blocks(1, 0);
-  nrows.reserve(H);
-  nsplit.reserve(H);
+  nrows.reserve(P);
+  nsplit.reserve(P);
   ncol.reserve(nnzb);
   nsrc.reserve(nnzb);
   int hi = H;
   for (int b : lo) {
-    for (int p = 0; p < H; ++p) {
+    for (int p = 0; p < P; ++p) {
       const int j = rows[p];
       if (j < b || j >= hi) continue;
       nrows.push_back(j);
@@ -561,16 +603,18 @@ static Status order_head_ranges(Model& M, int H, int nnzb) {
     blocks.push_back(static_cast<int>(nrows.size()));
     hi = b;
   }
-  if (static_cast<int>(nrows.size()) != H || static_cast<int>(ncol.size()) != nnzb ||
+  if (static_cast<int>(nrows.size()) != P || static_cast<int>(ncol.size()) != nnzb ||
       blocks.size() > 10)
     return Status::make(VL_ERR_STATE, "head range reordering failed");
   M.hb_blocks = blocks;
-  VL_TRY(M.hb_split.alloc(H));
-  VL_HIP(hipMemcpyAsync(M.hb_rows.p, nrows.data(), sizeof(int) * H, hipMemcpyHostToDevice,
-                        M.stream));
-  VL_HIP(hipMemcpyAsync(M.hb_pptr.p, nptr.data(), sizeof(int) * (H + 1), hipMemcpyHostToDevice,
-                        M.stream));
-  VL_HIP(hipMemcpyAsync(M.hb_split.p, nsplit.data(), sizeof(int) * H, hipMemcpyHostToDevice,
+  VL_TRY(M.hb_split.alloc(P > 0 ? P : 1));
+  if (P > 0) {
+    VL_HIP(hipMemcpyAsync(M.hb_rows.p, nrows.data(), sizeof(int) * P, hipMemcpyHostToDevice,
+                          M.stream));
+    VL_HIP(hipMemcpyAsync(M.hb_split.p, nsplit.data(), sizeof(int) * P, hipMemcpyHostToDevice,
+                          M.stream));
+  }
+  VL_HIP(hipMemcpyAsync(M.hb_pptr.p, nptr.data(), sizeof(int) * (P + 1), hipMemcpyHostToDevice,
                         M.stream));
   if (nnzb > 0) {
     VL_HIP(hipMemcpyAsync(M.hb_col.p, ncol.data(), sizeof(int) * nnzb, hipMemcpyHostToDevice,
@@ -579,6 +623,23 @@ static Status order_head_ranges(Model& M, int H, int nnzb) {
                           M.stream));
   }
   return sync_stream(M.stream);
+}
+
+// Level order (by head-internal levels with rows below K known) of the head
+// rows K..H-1 in one direction: ptr (level pointers) and rows; returns the
+// number of levels.
+static Status head_order(Model& M, int H, int K, int dir, int* ptr, int* rows, int* nlev) {
+  DevBuf<int> lev, dn;
+  VL_TRY(lev.alloc(H));
+  VL_TRY(dn.alloc(1));
+  const size_t lds = sizeof(int) * (H + 1);
+  hipLaunchKernelGGL(head_levels_kernel, dim3(1), dim3(kHeadThreads), lds, M.stream, H, K, M.m,
+                     M.nbr.p, M.bt_ptr.p, M.bt_col.p, dir, lev.p);
+  hipLaunchKernelGGL(head_sort_kernel, dim3(1), dim3(kHeadThreads), lds, M.stream, H, lev.p, ptr,
+                     rows, dn.p);
+  VL_TRY(check_launch("head schedule"));
+  VL_HIP(hipMemcpyAsync(nlev, dn.p, sizeof(int), hipMemcpyDeviceToHost, M.stream));
+  return sync_stream(M.stream);  // temporaries are released on return
 }
 
 Status build_head_schedule(Model& M) {
@@ -601,89 +662,90 @@ Status build_head_schedule(Model& M) {
   allow_lds(head_lower_kernel<32, 512>, bytes);
   allow_lds(head_upper_kernel<512>, bytes);
   M.head_rows = static_cast<int>(H);
+  if (M.dense_rows > H) M.dense_rows = static_cast<int>(H);
+  const int K = M.dense_rows;
+  M.head_pos = static_cast<int>(H) - K;
+  const int P = M.head_pos;
   if (H == 0) return Status::ok();
-  DevBuf<int> lev, nlev;
-  VL_TRY(lev.alloc(H));
-  VL_TRY(nlev.alloc(2));
-  VL_TRY(M.hf_ptr.alloc(H + 1));
-  VL_TRY(M.hf_rows.alloc(H));
-  VL_TRY(M.hb_ptr.alloc(H + 1));
-  VL_TRY(M.hb_rows.alloc(H));
-  const size_t lds = sizeof(int) * (H + 1);
-  for (int dir = 0; dir < 2; ++dir) {
-    hipLaunchKernelGGL(head_levels_kernel, dim3(1), dim3(kHeadThreads), lds, M.stream,
-                       static_cast<int>(H), M.m, M.nbr.p, M.bt_ptr.p, M.bt_col.p, dir, lev.p);
-    hipLaunchKernelGGL(head_sort_kernel, dim3(1), dim3(kHeadThreads), lds, M.stream,
-                       static_cast<int>(H), lev.p, dir ? M.hb_ptr.p : M.hf_ptr.p,
-                       dir ? M.hb_rows.p : M.hf_rows.p, nlev.p + dir);
-  }
-  VL_TRY(check_launch("head schedule"));
-  int h_nlev[2];
-  VL_HIP(hipMemcpyAsync(h_nlev, nlev.p, sizeof(int) * 2, hipMemcpyDeviceToHost, M.stream));
-  VL_TRY(sync_stream(M.stream));
-  M.head_nlev_f = h_nlev[0];
-  M.head_nlev_b = h_nlev[1];
-  // position-ordered copies (structure; values follow in refresh_head_values)
   const int m = M.m;
-  VL_TRY(M.hf_nbr.alloc((size_t)H * (m > 0 ? m : 1)));
-  VL_TRY(M.hf_val.alloc((size_t)H * (m > 0 ? m : 1)));
-  if ((int64_t)H * m > 0)
-    hipLaunchKernelGGL(head_copy_fwd_kernel, dim3((unsigned)((H * m + 255) / 256)), dim3(256), 0,
-                       M.stream, static_cast<int>(H), m, M.hf_rows.p, M.nbr.p, M.hf_nbr.p);
-  DevBuf<int> len;
-  VL_TRY(len.alloc(H + 1));
-  VL_TRY(M.hb_pptr.alloc(H + 1));
-  VL_TRY(M.head_split.alloc(H));
-  hipLaunchKernelGGL(head_len_bwd_kernel, dim3((unsigned)((H + 256) / 256)), dim3(256), 0,
-                     M.stream, static_cast<int>(H), M.hb_rows.p, M.bt_ptr.p, M.bt_col.p, len.p,
-                     M.head_split.p);
-  VL_TRY(exclusive_scan_int(len.p, M.hb_pptr.p, H + 1, M.stream));
-  // The positions are still in head-internal level order here: keep that
-  // order, its level pointers and per-level entry counts for the
-  // level-scheduled B^T solves (order_head_ranges reorders the positions).
+  // ---- the level-scheduled B^T solves (wide blocks): all head rows by their
+  // head-internal levels, and where each head row's tail entries begin
   {
+    DevBuf<int> ptr, rows, len, pptr;
+    VL_TRY(ptr.alloc(H + 1));
+    VL_TRY(rows.alloc(H));
+    int nl = 0;
+    VL_TRY(head_order(M, static_cast<int>(H), 0, 1, ptr.p, rows.p, &nl));
+    VL_TRY(len.alloc(H + 1));
+    VL_TRY(pptr.alloc(H + 1));
+    VL_TRY(M.head_split.alloc(H));
+    hipLaunchKernelGGL(head_len_bwd_kernel, dim3((unsigned)((H + 256) / 256)), dim3(256), 0,
+                       M.stream, static_cast<int>(H), static_cast<int>(H), rows.p, M.bt_ptr.p,
+                       M.bt_col.p, len.p, M.head_split.p);
+    VL_TRY(exclusive_scan_int(len.p, pptr.p, H + 1, M.stream));
     VL_TRY(M.hlv_rows_b.alloc(H));
-    VL_TRY(copy_d2d(M.hlv_rows_b.p, M.hb_rows.p, sizeof(int) * H, M.stream));
-    std::vector<int> lp(M.head_nlev_b + 1), pp(H + 1);
-    VL_HIP(hipMemcpyAsync(lp.data(), M.hb_ptr.p, sizeof(int) * lp.size(),
-                          hipMemcpyDeviceToHost, M.stream));
-    VL_HIP(hipMemcpyAsync(pp.data(), M.hb_pptr.p, sizeof(int) * (H + 1), hipMemcpyDeviceToHost,
+    VL_TRY(copy_d2d(M.hlv_rows_b.p, rows.p, sizeof(int) * H, M.stream));
+    std::vector<int> lp(nl + 1), pp(H + 1);
+    VL_HIP(hipMemcpyAsync(lp.data(), ptr.p, sizeof(int) * lp.size(), hipMemcpyDeviceToHost,
+                          M.stream));
+    VL_HIP(hipMemcpyAsync(pp.data(), pptr.p, sizeof(int) * (H + 1), hipMemcpyDeviceToHost,
                           M.stream));
     VL_TRY(sync_stream(M.stream));
     M.hlv_ptr_b = lp;
-    M.hlv_nnz_b.assign(M.head_nlev_b, 0);
-    for (int l = 0; l < M.head_nlev_b; ++l) M.hlv_nnz_b[l] = pp[lp[l + 1]] - pp[lp[l]];
-  }
-  int nnzb = 0;
-  VL_HIP(hipMemcpyAsync(&nnzb, M.hb_pptr.p + H, sizeof(int), hipMemcpyDeviceToHost, M.stream));
-  VL_TRY(sync_stream(M.stream));
-  M.head_nnz_b = nnzb;
-  {
+    M.hlv_nnz_b.assign(nl, 0);
+    for (int l = 0; l < nl; ++l) M.hlv_nnz_b[l] = pp[lp[l + 1]] - pp[lp[l]];
     int bt_head = 0;
     VL_HIP(hipMemcpyAsync(&bt_head, M.bt_ptr.p + H, sizeof(int), hipMemcpyDeviceToHost,
                           M.stream));
     VL_TRY(sync_stream(M.stream));
     M.nnz_head_bt = bt_head;
-    M.fold_nnz = static_cast<int64_t>(bt_head) - nnzb;
+    M.fold_nnz = static_cast<int64_t>(bt_head) - pp[H];
     int64_t f = 0;  // row i < H has min(i, m) neighbours
     for (int64_t i = 0; i < H; ++i) f += (i < m ? i : m);
     M.nnz_head_f = f;
   }
+  // ---- the LDS head solves (t <= 64): rows K..H-1, P positions per direction
+  VL_TRY(M.hf_ptr.alloc(H + 1));
+  VL_TRY(M.hf_rows.alloc(H));
+  VL_TRY(M.hb_ptr.alloc(H + 1));
+  VL_TRY(M.hb_rows.alloc(H));
+  VL_TRY(head_order(M, static_cast<int>(H), K, 0, M.hf_ptr.p, M.hf_rows.p, &M.head_nlev_f));
+  VL_TRY(head_order(M, static_cast<int>(H), K, 1, M.hb_ptr.p, M.hb_rows.p, &M.head_nlev_b));
+  // position-ordered copies (structure; values follow in refresh_head_values)
+  VL_TRY(M.hf_nbr.alloc((size_t)(P > 0 ? P : 1) * (m > 0 ? m : 1)));
+  VL_TRY(M.hf_val.alloc((size_t)(P > 0 ? P : 1) * (m > 0 ? m : 1)));
+  if ((int64_t)P * m > 0)
+    hipLaunchKernelGGL(head_copy_fwd_kernel, dim3((unsigned)(((int64_t)P * m + 255) / 256)),
+                       dim3(256), 0, M.stream, P, m, M.hf_rows.p, M.nbr.p, M.hf_nbr.p);
+  DevBuf<int> len;
+  VL_TRY(len.alloc(P + 1));
+  VL_TRY(M.hb_pptr.alloc(P + 1));
+  hipLaunchKernelGGL(head_len_bwd_kernel, dim3((unsigned)((P + 256) / 256)), dim3(256), 0,
+                     M.stream, static_cast<int>(H), P, M.hb_rows.p, M.bt_ptr.p, M.bt_col.p,
+                     len.p, nullptr);
+  VL_TRY(exclusive_scan_int(len.p, M.hb_pptr.p, P + 1, M.stream));
+  int nnzb = 0;
+  VL_HIP(hipMemcpyAsync(&nnzb, M.hb_pptr.p + P, sizeof(int), hipMemcpyDeviceToHost, M.stream));
+  VL_TRY(sync_stream(M.stream));
+  M.head_nnz_b = nnzb;
   VL_TRY(M.hb_col.alloc(nnzb));
   VL_TRY(M.hb_src.alloc(nnzb));
   VL_TRY(M.hb_val.alloc(nnzb));
-  hipLaunchKernelGGL(head_copy_bwd_kernel, dim3((unsigned)((H + 255) / 256)), dim3(256), 0,
-                     M.stream, static_cast<int>(H), M.hb_rows.p, M.bt_ptr.p, M.bt_col.p,
-                     M.bt_src.p, M.hb_pptr.p, M.hb_col.p, M.hb_src.p);
+  if (P > 0)
+    hipLaunchKernelGGL(head_copy_bwd_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0,
+                       M.stream, P, M.hb_rows.p, M.bt_ptr.p, M.bt_col.p, M.bt_src.p, M.hb_pptr.p,
+                       M.hb_col.p, M.hb_src.p);
   VL_TRY(check_launch("head copies"));
-  VL_TRY(order_head_ranges(M, static_cast<int>(H), nnzb));
-  VL_TRY(M.hb_wcol.alloc((size_t)H * 16));
-  VL_TRY(M.hb_wval.alloc((size_t)H * 16));
-  hipLaunchKernelGGL(head_window_kernel, dim3((unsigned)(((int64_t)H * 16 + 255) / 256)),
-                     dim3(256), 0, M.stream, static_cast<int>(H), M.hb_pptr.p, M.hb_split.p,
-                     M.hb_col.p, M.hb_val.p, M.hb_wcol.p, M.hb_wval.p);
+  VL_TRY(order_head_ranges(M, static_cast<int>(H), P, nnzb));
+  VL_TRY(M.hb_wcol.alloc((size_t)(P > 0 ? P : 1) * 16));
+  VL_TRY(M.hb_wval.alloc((size_t)(P > 0 ? P : 1) * 16));
+  if (P > 0)
+    hipLaunchKernelGGL(head_window_kernel, dim3((unsigned)(((int64_t)P * 16 + 255) / 256)),
+                       dim3(256), 0, M.stream, P, M.hb_pptr.p, M.hb_split.p, M.hb_col.p,
+                       M.hb_val.p, M.hb_wcol.p, M.hb_wval.p);
   VL_TRY(check_launch("head copies"));
-  return sync_stream(M.stream);
+  VL_TRY(sync_stream(M.stream));
+  return build_dense(M);
 }
 
 }  // namespace vl

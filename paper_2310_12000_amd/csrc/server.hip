@@ -69,15 +69,18 @@ struct Server {
 };
 
 // Device bytes one request holds while it runs: the model (coordinates,
-// neighbours, B, B^T, D, level and head schedules, neighbour-search grid),
-// the block CG state for the probes and for one prediction tile, and the
-// prediction factor.
+// neighbours, B, B^T, D, level and head schedules, neighbour-search grid,
+// the grouped B and B^T, the dense inverse of the leading block), the block
+// CG state for the probes and for one prediction tile, and the prediction
+// factor.
 double request_bytes(const vl_request& r, const vl_opts& o) {
   const double n = static_cast<double>(r.n), m = r.m, np = static_cast<double>(r.n_p);
   const int tile = (o.pred_tile > 0 && o.pred_tile < o.num_pred_samples) ? o.pred_tile
                                                                           : o.num_pred_samples;
   const double t = std::max(o.num_probes, tile);
-  const double model = n * (16.0 + m * 12.0 + m * 16.0 + 8.0 * 8.0 + 64.0) + 64.0 * 1048576.0;
+  const double kd = std::min(n, static_cast<double>(kDenseRows));
+  const double model = n * (16.0 + m * 12.0 + m * 16.0 + 8.0 * 8.0 + 64.0) +
+                       n * (16.0 * m + 64.0 * (m + 1)) + 16.0 * kd * kd + 64.0 * 1048576.0;
   const double cg = 10.0 * n * t * 8.0;
   const double pred = np * (m * 12.0 + 40.0);
   return model + cg + pred;

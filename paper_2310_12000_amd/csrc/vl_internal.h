@@ -195,8 +195,15 @@ struct Model {
   int64_t factor_version = 0, f32_version = -1;  // FP32 copies made at factor_version
   bool force_levels = false;  // level-scheduled solves for every block width (autotuner)
 
-  // head rows solved in LDS (level schedules for both directions)
+  // head rows solved in LDS (level schedules for both directions): rows
+  // dense_rows..head_rows-1 in head_pos positions; the rows below dense_rows
+  // are solved with the dense inverse of B's leading block (dense.hip)
   int head_rows = 0, head_nlev_f = 0, head_nlev_b = 0;
+  int dense_rows = 0, head_pos = 0;
+  DevBuf<double> dense_gf, dense_gb;  // G = B_KK^{-1}: column-major, row-major
+  DevBuf<double> dense_xp;            // K x t folded right-hand sides of B^T solves
+  DevBuf<double> dense_part;          // partial products of the dense applications
+  DevBuf<int> dense_lo;               // first B^T entry with child >= K, rows < K
   int64_t head_nnz_b = 0;
   DevBuf<int> hf_ptr, hf_rows, hb_ptr, hb_rows;
   DevBuf<int> hf_nbr, hb_pptr, hb_col, hb_src;  // position-ordered structure
@@ -357,6 +364,13 @@ Status build_head_schedule(Model& M);
 Status head_lower(Model& M, const double* X, double* Y, int t, const double* rs);
 Status head_upper(Model& M, const double* X, double* Y, int t);
 Status refresh_head_values(Model& M);
+
+// ---- dense leading block (dense.hip)
+constexpr int kDenseRows = 2048;
+Status build_dense(Model& M);
+Status dense_factor(Model& M);
+Status dense_lower(Model& M, const double* X, double* Y, int t, const double* rs);
+Status dense_upper(Model& M, double* Y, int t);
 
 // ---- solver kernels (solver.hip)
 Status tridiag_quadrature(Model& M, CgState& S, double* out_dev);

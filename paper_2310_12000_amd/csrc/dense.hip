@@ -6,10 +6,12 @@
 // of B^T y = x are y_K = G^T (x_K - B_RK^T y_R), where R are the rows
 // K..n-1, solved first.  With a random ordering the earliest points carry
 // most of the dependency depth of the head: at n = 1e5, m = 20 the first
-// 16384 rows span 214 levels, the rows 2048..16383 on their own only 71.
-// Taking the first K = 2048 rows out of the latency-bound LDS head solve and
-// applying G instead (16.8 MB of FP64 per application, read at bandwidth by
-// the whole chip) removes two thirds of its critical path.
+// 16384 rows span 214 levels, the rows 2048..16383 on their own 71 and the
+// rows 4096..16383 49.  Taking the first K = 4096 rows out of the
+// latency-bound LDS head solve and applying G instead (67 MB of FP64 per
+// application, read at bandwidth by the whole chip) took the t = 1 head
+// solves from 488 / 915 us to 298 / 321 us (forward / backward); K = 2048
+// gave 320 / 462 us.
 //
 // G is computed once per factor (Sec. 2.1: B changes with the covariance
 // parameters) by forward substitution of B_KK G = I, column by column, and
@@ -20,42 +22,52 @@
 
 namespace vl {
 
-constexpr int kDenseCols = 8;  // columns of G per workgroup of the inverse
+// Columns of G per workgroup of the inverse: as many as 128 KB of LDS hold
+// (8 at K = 2048), a power of two, at most 32.
+static int dense_cols(int K) {
+  int c = 1;
+  while (c < 32 && static_cast<int64_t>(2 * c) * K * 8 <= 131072) c *= 2;
+  return c;
+}
 
-// Columns c0..c0+7 of G in LDS; lane = (column cl, part q).  Part q sums the
-// slots q, q + 8, q + 16, q + 24 of row i; the eight parts meet by a
-// butterfly, and row i is final before row i + 1 reads it (one wave: its LDS
-// accesses complete in order).  Slot data does not depend on G and is
-// fetched one row ahead.
+// Columns c0..c0+C-1 of G in LDS; lane = (column cl, part q) with
+// Q = 64 / C parts per column.  Part q sums the slots q, q + Q, ... of row
+// i; the parts meet by a butterfly, and row i is final before row i + 1
+// reads it (one wave: its LDS accesses complete in order).  Slot data does
+// not depend on G and is fetched one row ahead.
+template <int C>
 __global__ __launch_bounds__(64) void dense_inverse_kernel(int K, int m,
                                                             const int* __restrict__ nbr,
                                                             const double* __restrict__ bval,
                                                             double* __restrict__ Gf,
                                                             double* __restrict__ Gb) {
-  extern __shared__ double s_g[];  // kDenseCols x K
-  const int lane = threadIdx.x, cl = lane >> 3, q = lane & 7;
-  const int c0 = blockIdx.x * kDenseCols;
+  extern __shared__ double s_g[];  // C x K
+  constexpr int Q = 64 / C;
+  const int lane = threadIdx.x, cl = lane / Q, q = lane % Q;
+  const int c0 = blockIdx.x * C;
   const int c = c0 + cl;
-  for (int k = lane; k < kDenseCols * K; k += 64) s_g[k] = 0.0;
+  for (int k = lane; k < C * K; k += 64) s_g[k] = 0.0;
   __syncthreads();
   double* g = s_g + cl * K;
-  int nj[4];
-  double nw[4];
+  constexpr int kSlots = C / 2 > 0 ? C / 2 : 1;  // m <= 31: at most 32 / Q slots per part
+  int nj[kSlots];
+  double nw[kSlots];
+  const int per = (m + Q - 1) / Q;
   auto fetch = [&](int i) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = q + 8 * u;
-      const bool in = i < K && k < m;
+    for (int u = 0; u < kSlots; ++u) {
+      const int k = q + Q * u;
+      const bool in = u < per && i < K && k < m;
       nj[u] = in ? nbr[(int64_t)i * m + k] : -1;
       nw[u] = in ? bval[(int64_t)i * m + k] : 0.0;
     }
   };
   fetch(c0);
   for (int i = c0; i < K; ++i) {
-    int cj[4];
-    double cw[4];
+    int cj[kSlots];
+    double cw[kSlots];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kSlots; ++u) {
       cj[u] = nj[u];
       cw[u] = nw[u];
     }
@@ -63,20 +75,19 @@ __global__ __launch_bounds__(64) void dense_inverse_kernel(int K, int m,
     // g_j = 0 for j < c (never written), so earlier columns add nothing
     double s = 0.0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < kSlots; ++u)
       if (cj[u] >= 0) s += cw[u] * g[cj[u]];
-    s += __shfl_xor(s, 1);
-    s += __shfl_xor(s, 2);
-    s += __shfl_xor(s, 4);
+#pragma unroll
+    for (int o = 1; o < Q; o <<= 1) s += __shfl_xor(s, o);
     if (q == 0 && c < K && i >= c) g[i] = (i == c ? 1.0 : 0.0) - s;
   }
   __syncthreads();
-  for (int k = lane; k < kDenseCols * K; k += 64) {
+  for (int k = lane; k < C * K; k += 64) {
     const int cc = c0 + k / K, i = k % K;
     if (cc < K) Gf[(int64_t)cc * K + i] = s_g[k];
   }
-  for (int k = lane; k < kDenseCols * K; k += 64) {
-    const int i = k / kDenseCols, u = k % kDenseCols;
+  for (int k = lane; k < C * K; k += 64) {
+    const int i = k / C, u = k % C;
     if (c0 + u < K) Gb[(int64_t)i * K + c0 + u] = s_g[u * K + i];
   }
 }
@@ -220,9 +231,15 @@ Status build_dense(Model& M) {
   VL_TRY(M.dense_lo.alloc(K));
   hipLaunchKernelGGL(dense_lo_kernel, dim3((K + 255) / 256), dim3(256), 0, M.stream, K,
                      M.bt_ptr.p, M.bt_col.p, M.dense_lo.p);
-  const size_t lds = sizeof(double) * kDenseCols * K;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(dense_inverse_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  const size_t lds = sizeof(double) * dense_cols(K) * K;
+  for (const void* f : {reinterpret_cast<const void*>(dense_inverse_kernel<1>),
+                        reinterpret_cast<const void*>(dense_inverse_kernel<2>),
+                        reinterpret_cast<const void*>(dense_inverse_kernel<4>),
+                        reinterpret_cast<const void*>(dense_inverse_kernel<8>),
+                        reinterpret_cast<const void*>(dense_inverse_kernel<16>),
+                        reinterpret_cast<const void*>(dense_inverse_kernel<32>)})
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(lds));
   (void)hipGetLastError();
   VL_TRY(check_launch("dense block"));
   return sync_stream(M.stream);
@@ -231,9 +248,21 @@ Status build_dense(Model& M) {
 Status dense_factor(Model& M) {
   const int K = M.dense_rows;
   if (K <= 0) return Status::ok();
-  const size_t lds = sizeof(double) * kDenseCols * K;
-  hipLaunchKernelGGL(dense_inverse_kernel, dim3((K + kDenseCols - 1) / kDenseCols), dim3(64), lds,
-                     M.stream, K, M.m, M.nbr.p, M.bval.p, M.dense_gf.p, M.dense_gb.p);
+  const int C = dense_cols(K);
+  const size_t lds = sizeof(double) * C * K;
+  const dim3 grid((K + C - 1) / C);
+#define VL_INVERSE(CC)                                                                          \
+  hipLaunchKernelGGL(dense_inverse_kernel<CC>, grid, dim3(64), lds, M.stream, K, M.m, M.nbr.p, \
+                     M.bval.p, M.dense_gf.p, M.dense_gb.p)
+  switch (C) {
+    case 1: VL_INVERSE(1); break;
+    case 2: VL_INVERSE(2); break;
+    case 4: VL_INVERSE(4); break;
+    case 8: VL_INVERSE(8); break;
+    case 16: VL_INVERSE(16); break;
+    default: VL_INVERSE(32); break;
+  }
+#undef VL_INVERSE
   return check_launch("dense inverse");
 }
 

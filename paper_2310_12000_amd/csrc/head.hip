@@ -2,15 +2,18 @@
 //
 // With a random ordering the dependency DAG of B is deep only among early
 // rows: for n = 1e5, m = 20 the first 16384 rows already span 214 of the 278
-// levels, while the remaining rows add only 68.  The head is therefore solved
-// level by level inside one workgroup per probe column, with the column's
-// head values in LDS and a workgroup barrier between levels; the data of the
-// next level's rows is prefetched into registers while the current level is
-// computed.  The tail rows use the sync-free kernels (sparse.hip).
+// levels, while the remaining rows add only 68.  The first K rows are solved
+// with the dense inverse of B's leading block (dense.hip); rows K..H-1
+// (K = 4096, H = 12288 by default) are solved level by level inside one
+// workgroup per probe column, with the column's head values in LDS and no
+// barrier between levels (rows poll LDS); the data of later rows is
+// prefetched into registers while earlier ones are computed.  The tail rows
+// use the sync-free kernels (sparse.hip).
 //
-// Forward (B Y = rs o X): the head runs first; every dependency of a head row
-// is a head row.  Backward (B^T Y = X): the tail runs first, then the head
-// reads finished tail values from global memory and head values from LDS.
+// Forward (B Y = rs o X): the dense block first, then the head; every
+// dependency of a head row is a head row.  Backward (B^T Y = X): the tail
+// first, then the head rows K..H-1 read finished tail values from global
+// memory and head values from LDS, then the dense block.
 //
 // Level schedules (rows of the head grouped by level, separately for the two
 // directions) depend only on the neighbour sets and are built once.
@@ -561,7 +564,7 @@ static void allow_lds(K kernel, size_t bytes) {
 // Reorder the P backward head positions by index range of their rows
 // (latest range first, level order kept inside a range) and record, per
 // position, where the entries into the row's own range start.  Runs on the
-// host (H <= 16384).
+// host (H <= kHeadRows).
 static Status order_head_ranges(Model& M, int H, int P, int nnzb) {
   std::vector<int> rows(P > 0 ? P : 1), ptr(P + 1), col(nnzb > 0 ? nnzb : 1),
       src(nnzb > 0 ? nnzb : 1);

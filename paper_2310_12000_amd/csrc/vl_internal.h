@@ -359,14 +359,14 @@ Status spmm_group_bt(Model& M, const double* X, double* Y, int t, const double* 
                      const double* V);
 
 // ---- head solves (head.hip)
-constexpr int kHeadRows = 16384;
+constexpr int kHeadRows = 12288;  // with the dense first 4096 rows (measured best at n = 1e5)
 Status build_head_schedule(Model& M);
 Status head_lower(Model& M, const double* X, double* Y, int t, const double* rs);
 Status head_upper(Model& M, const double* X, double* Y, int t);
 Status refresh_head_values(Model& M);
 
 // ---- dense leading block (dense.hip)
-constexpr int kDenseRows = 2048;
+constexpr int kDenseRows = 4096;
 Status build_dense(Model& M);
 Status dense_factor(Model& M);
 Status dense_lower(Model& M, const double* X, double* Y, int t, const double* rs);

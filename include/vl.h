@@ -213,7 +213,10 @@ int64_t vl_export_count(vl_model* h, int which);
 
 /* Sparse products with the Vecchia factor over a block of t columns
  * (device, row-major n x t):  Y = B X (transpose = 0) or Y = B^T X
- * (transpose = 1).  X and Y must not overlap.  Asynchronous. */
+ * (transpose = 1).  X and Y must not overlap.  Asynchronous.  For
+ * 32 <= t <= 64 rows are computed in groups of 4 neighbouring locations with
+ * dense weights, so a non-finite entry of X makes every row of its group
+ * non-finite. */
 vl_status vl_spmm(vl_model* h, int transpose, const double* X, double* Y, int t);
 
 /* Triangular solves with the Vecchia factor over t columns (device,
@@ -228,7 +231,9 @@ vl_status vl_trsm(vl_model* h, int transpose, const double* X, double* Y, int t)
  * written once, per-row vectors) are accumulated.  `kind`:
  *   0  Y = B X (B in ELL)                 1  Y = B^T X (B^T in CSR)
  *   2  sync-free rows of B Y = X          3  sync-free rows of B^T Y = X
- *   4  LDS head rows of B Y = X           5  LDS head rows of B^T Y = X
+ *   4  head rows of B Y = X               5  head rows of B^T Y = X
+ *      (4-5: the dense product with the inverse of B's leading block and
+ *      the LDS solve of the remaining head rows, one record each)
  *   6  level-scheduled B Y = X            7  level-scheduled B^T Y = X
  *   8  level-scheduled B^T Y = X, levels of long rows (entries split over
  *      4 waves per row)

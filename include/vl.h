@@ -239,8 +239,10 @@ vl_status vl_trsm(vl_model* h, int transpose, const double* X, double* Y, int t)
  *      4 waves per row)
  *   9  level-scheduled B^T Y = X: the fold of the head rows' tail entries
  *      (one launch between the tail levels and the head levels)
- *      (6-9: blocks wider than 64 columns; one launch, and one record, per
- *      level)
+ *  10  the leading rows of the level-scheduled solves, from the dense
+ *      inverse of B's leading block (one record per solve)
+ *      (6-10: blocks wider than 64 columns; 6-8 one launch, and one
+ *      record, per level)
  * `enable` is a bit mask of the kinds to record (bit k = kind k; -1 = all,
  * 0 = off).  vl_timing_enable resets the records (and synchronises); vl_timing_read
  * synchronises and returns the summed kernel time (ms), the number of

@@ -182,14 +182,94 @@ __global__ void dense_reduce_kernel(int K, int t, const double* __restrict__ par
   out[e] = v;
 }
 
-// xp[j, c] = Y[j, c] - sum of the B^T entries of row j < K whose child lies
-// in K..H-1 (entries [lo[j], split[j]): children sorted ascending, those
-// from H on were subtracted before the head solve).  One wave per row, lanes
-// over entries, a fixed butterfly per column.
+// Wide blocks (t > 64): out[r, c] = sum_s A[s lda + r] v(s, c) for the
+// leading Kd rows, on the FP64 matrix cores.  Block (x, y) computes rows
+// 64x.. and columns 64y..; its 4 waves own 32 x 32 quarters (2 x 2 tiles of
+// v_mfma_f64_16x16x4f64).  The contraction runs over the triangle in steps
+// of 16: the block stages 16 x 64 of A and of v in LDS (the next 16 are
+// loaded into registers meanwhile), then each wave takes 4 MFMA steps per
+// tile.  Operand layout of one MFMA step, lane
+// l = 16 q + i: A[i][q] and B[q][i] in, D[q + 4 r][i] (r = 0..3) out.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <bool LOWER>
+__global__ __launch_bounds__(256) void dense_gemm_kernel(int Kd, int lda, int t,
+                                                         const double* __restrict__ A,
+                                                         const double* __restrict__ V,
+                                                         const double* __restrict__ rs,
+                                                         double* __restrict__ out) {
+  __shared__ double sA[16][64];  // [s][row]
+  __shared__ double sB[16][64];  // [s][column]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  const int s_lo = LOWER ? 0 : r0;
+  const int s_hi = LOWER ? min(Kd, r0 + 64) : Kd;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int q = lane >> 4, i = lane & 15;
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int sl = tid >> 4, x = (tid & 15) * 4;  // staging: one s, four rows / columns
+  double ra[4], rb[4];  // the next tile, loaded while the current one is used
+  auto fetch = [&](int s0) {
+    const int s = s0 + sl;
+    const bool in_s = s < s_hi;
+    const double sc = (in_s && rs) ? rs[s] : 1.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int rr = r0 + x + u, cc = c0 + x + u;
+      ra[u] = (in_s && rr < Kd) ? A[(int64_t)s * lda + rr] : 0.0;
+      rb[u] = (in_s && cc < t) ? V[(int64_t)s * t + cc] * sc : 0.0;
+    }
+  };
+  if (s_lo < s_hi) fetch(s_lo);
+  for (int s0 = s_lo; s0 < s_hi; s0 += 16) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sA[sl][x + u] = ra[u];
+      sB[sl][x + u] = rb[u];
+    }
+    __syncthreads();
+    if (s0 + 16 < s_hi) fetch(s0 + 16);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = sA[kk * 4 + q][wr * 32 + a * 16 + i];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = sB[kk * 4 + q][wc * 32 + b * 16 + i];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int row = r0 + wr * 32 + a * 16 + q + 4 * rr;
+        const int col = c0 + wc * 32 + b * 16 + i;
+        if (row < Kd && col < t) out[(int64_t)row * t + col] = acc[a][b][rr];
+      }
+}
+
+// xp[j, c] = base[j, c] - sum of the B^T entries of row j < K whose child
+// lies in K..H-1 (entries [lo[j], split[j]): children sorted ascending, those
+// from H on were subtracted from base before the head solve), with the
+// children's values from Y.  One wave per row, lanes over entries, a fixed
+// butterfly per column.
 __global__ __launch_bounds__(256) void dense_fold_kernel(int K, int t, const int* __restrict__ lo,
                                                          const int* __restrict__ split,
                                                          const int* __restrict__ bt_col,
                                                          const double* __restrict__ bt_val,
+                                                         const double* __restrict__ base,
                                                          const double* __restrict__ Y,
                                                          double* __restrict__ xp) {
   const int lane = threadIdx.x & 63;
@@ -201,7 +281,7 @@ __global__ __launch_bounds__(256) void dense_fold_kernel(int K, int t, const int
     for (int q = b + lane; q < e; q += 64) part += bt_val[q] * Y[(int64_t)bt_col[q] * t + c];
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) part += __shfl_xor(part, o);
-    if (lane == 0) xp[(int64_t)j * t + c] = Y[(int64_t)j * t + c] - part;
+    if (lane == 0) xp[(int64_t)j * t + c] = base[(int64_t)j * t + c] - part;
   }
 }
 
@@ -231,6 +311,11 @@ Status build_dense(Model& M) {
   VL_TRY(M.dense_lo.alloc(K));
   hipLaunchKernelGGL(dense_lo_kernel, dim3((K + 255) / 256), dim3(256), 0, M.stream, K,
                      M.bt_ptr.p, M.bt_col.p, M.dense_lo.p);
+  if (M.dense_wide > 0) {
+    VL_TRY(M.dense_lo_w.alloc(M.dense_wide));
+    hipLaunchKernelGGL(dense_lo_kernel, dim3((M.dense_wide + 255) / 256), dim3(256), 0, M.stream,
+                       M.dense_wide, M.bt_ptr.p, M.bt_col.p, M.dense_lo_w.p);
+  }
   const size_t lds = sizeof(double) * dense_cols(K) * K;
   for (const void* f : {reinterpret_cast<const void*>(dense_inverse_kernel<1>),
                         reinterpret_cast<const void*>(dense_inverse_kernel<2>),
@@ -301,8 +386,33 @@ Status dense_upper(Model& M, double* Y, int t) {
   TimedLaunch tl(M, kTimeHeadUpper, apply_bytes(M, t));
   VL_TRY(M.dense_xp.reserve(static_cast<size_t>(K) * t));
   hipLaunchKernelGGL(dense_fold_kernel, dim3((K + 3) / 4), dim3(256), 0, M.stream, K, t,
-                     M.dense_lo.p, M.head_split.p, M.bt_col.p, M.bt_val.p, Y, M.dense_xp.p);
+                     M.dense_lo.p, M.head_split.p, M.bt_col.p, M.bt_val.p, Y, Y, M.dense_xp.p);
   return launch_apply<false>(M, M.dense_gb.p, M.dense_xp.p, nullptr, Y, t);
+}
+
+// Wide blocks: the leading Kw rows of G are the inverse of B's leading
+// Kw x Kw block (a leading block of a triangular inverse), so the same G
+// serves with leading dimension K.
+Status dense_wide_lower(Model& M, const double* X, double* Y, int t, const double* rs) {
+  const int Kw = M.dense_wide, K = M.dense_rows;
+  TimedLaunch tl(M, kTimeDenseWide, 4.0 * Kw * (Kw + 1.0) + 16.0 * Kw * t);
+  const dim3 grid((Kw + 63) / 64, (t + 63) / 64);
+  hipLaunchKernelGGL(dense_gemm_kernel<true>, grid, dim3(256), 0, M.stream, Kw, K, t,
+                     M.dense_gf.p, X, rs, Y);
+  return check_launch("dense wide lower");
+}
+
+// Y_j (j < Kw) = sum_i G_ij x'_i, x'_j = Xh_j - the B^T entries of row j with
+// child in Kw..H-1 (Xh: the right-hand side with the tail entries folded).
+Status dense_wide_upper(Model& M, const double* Xh, double* Y, int t) {
+  const int Kw = M.dense_wide, K = M.dense_rows;
+  TimedLaunch tl(M, kTimeDenseWide, 4.0 * Kw * (Kw + 1.0) + 16.0 * Kw * t);
+  VL_TRY(M.dense_xp.reserve(static_cast<size_t>(Kw) * t));
+  VL_TRY(fold_rows(M, Kw, M.dense_lo_w.p, M.head_split.p, Xh, Y, M.dense_xp.p, t));
+  const dim3 grid((Kw + 63) / 64, (t + 63) / 64);
+  hipLaunchKernelGGL(dense_gemm_kernel<false>, grid, dim3(256), 0, M.stream, Kw, K, t,
+                     M.dense_gb.p, M.dense_xp.p, nullptr, Y);
+  return check_launch("dense wide upper");
 }
 
 }  // namespace vl

@@ -707,6 +707,35 @@ Status build_head_schedule(Model& M) {
     for (int64_t i = 0; i < H; ++i) f += (i < m ? i : m);
     M.nnz_head_f = f;
   }
+  // ---- the wide B^T solves with the dense leading rows: head rows Kw..H-1
+  // by their head-internal levels
+  M.dense_wide = std::min<int>(K, kDenseWide);
+  if (M.dense_wide > 0 && M.dense_wide < H) {
+    const int Kw = M.dense_wide;
+    DevBuf<int> ptr, len, pptr;
+    VL_TRY(ptr.alloc(H + 1));
+    VL_TRY(M.dhlv_rows_b.alloc(H));
+    int nl = 0;
+    VL_TRY(head_order(M, static_cast<int>(H), Kw, 1, ptr.p, M.dhlv_rows_b.p, &nl));
+    const int Pw = static_cast<int>(H) - Kw;
+    VL_TRY(len.alloc(Pw + 1));
+    VL_TRY(pptr.alloc(Pw + 1));
+    hipLaunchKernelGGL(head_len_bwd_kernel, dim3((unsigned)((Pw + 256) / 256)), dim3(256), 0,
+                       M.stream, static_cast<int>(H), Pw, M.dhlv_rows_b.p, M.bt_ptr.p,
+                       M.bt_col.p, len.p, nullptr);
+    VL_TRY(exclusive_scan_int(len.p, pptr.p, Pw + 1, M.stream));
+    std::vector<int> lp(nl + 1), pp(Pw + 1);
+    VL_HIP(hipMemcpyAsync(lp.data(), ptr.p, sizeof(int) * lp.size(), hipMemcpyDeviceToHost,
+                          M.stream));
+    VL_HIP(hipMemcpyAsync(pp.data(), pptr.p, sizeof(int) * (Pw + 1), hipMemcpyDeviceToHost,
+                          M.stream));
+    VL_TRY(sync_stream(M.stream));
+    M.dhlv_ptr_b = lp;
+    M.dhlv_nnz_b.assign(nl, 0);
+    for (int l = 0; l < nl; ++l) M.dhlv_nnz_b[l] = pp[lp[l + 1]] - pp[lp[l]];
+  } else {
+    M.dense_wide = 0;
+  }
   // ---- the LDS head solves (t <= 64): rows K..H-1, P positions per direction
   VL_TRY(M.hf_ptr.alloc(H + 1));
   VL_TRY(M.hf_rows.alloc(H));

@@ -768,6 +768,28 @@ __global__ __launch_bounds__(256) void trsm_fold_kernel(int t, const int* __rest
   vst<VEC>(Xh + j * t + c, x);
 }
 
+// out_j = base_j - sum over the B^T entries [beg[j], end[j]) of row j, for
+// rows j < rows; block (j, s) covers 64 VEC columns with 4 waves sharing the
+// row's entries (the wide-block fold before the dense leading rows).
+template <int VEC>
+__global__ __launch_bounds__(256) void range_fold_kernel(int t, const int* __restrict__ beg,
+                                                         const int* __restrict__ end,
+                                                         const int* __restrict__ idx,
+                                                         const double* __restrict__ vals,
+                                                         const double* __restrict__ base,
+                                                         const double* __restrict__ Y,
+                                                         double* __restrict__ out) {
+  const int c = (blockIdx.y * 64 + (threadIdx.x & 63)) * VEC;
+  const int64_t j = blockIdx.x;
+  double tot[VEC];
+  if (!split_row_sum<VEC>(t, c, beg[j], end[j], idx, vals, Y, tot)) return;
+  double x[VEC];
+  vld<VEC>(base + j * t + c, x);
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) x[v] -= tot[v];
+  vst<VEC>(out + j * t + c, x);
+}
+
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 // Column vector width of the level kernels: 16-byte accesses need t a
@@ -800,9 +822,25 @@ Status fold_launch_f32(Model& M, const double* X, const float* Y, double* Xh, in
   return check_launch("trsm fold f32");
 }
 
-static Status lower_levels(Model& M, const double* X, double* Y, int t, const double* rs) {
-  const std::vector<int>& lp = M.lvl_ptr_f;
-  const std::vector<int64_t>& lnz = M.lvl_nnz_f;
+Status fold_rows(Model& M, int rows, const int* beg, const int* end, const double* base,
+                 const double* Y, double* out, int t) {
+  if (rows <= 0) return Status::ok();
+  const int vec = level_vec(t, 8, base, Y, out);
+  const dim3 grid(static_cast<unsigned>(rows), (t + 64 * vec - 1) / (64 * vec));
+  if (vec == 2) {
+    hipLaunchKernelGGL(range_fold_kernel<2>, grid, dim3(256), 0, M.stream, t, beg, end,
+                       M.bt_col.p, M.bt_val.p, base, Y, out);
+  } else {
+    hipLaunchKernelGGL(range_fold_kernel<1>, grid, dim3(256), 0, M.stream, t, beg, end,
+                       M.bt_col.p, M.bt_val.p, base, Y, out);
+  }
+  return check_launch("range fold");
+}
+
+// Levels [lp] of the forward order `order`.
+static Status lower_levels(Model& M, const std::vector<int>& lp, const std::vector<int64_t>& lnz,
+                           const int* order, const double* X, double* Y, int t,
+                           const double* rs) {
   const int tb = t <= 64 ? 64 : 256;  // threads per block
   const int vec = level_vec(t, 8, X, Y, nullptr);
   const unsigned gy = static_cast<unsigned>((t + tb * vec - 1) / (tb * vec));
@@ -811,7 +849,7 @@ static Status lower_levels(Model& M, const double* X, double* Y, int t, const do
     if (rows <= 0) continue;
     TimedLaunch tl(M, kTimeLevelLower,
                    12.0 * lnz[l] + 16.0 * rows * t + 4.0 * rows + (rs ? 8.0 * rows : 0.0));
-    const int* r = M.full_order_f.p + lp[l];
+    const int* r = order + lp[l];
     if (vec == 2) {
       hipLaunchKernelGGL(trsm_level_lower_kernel<2>, dim3(rows, gy), dim3(tb), 0, M.stream, t, r,
                          M.m, M.nbr.p, M.bval.p, X, rs, Y);
@@ -861,10 +899,19 @@ static Status upper_levels(Model& M, const std::vector<int>& lp, const std::vect
 // head rows by their head-internal levels against Xh.
 static Status trsm_levels(Model& M, bool lower, const double* X, double* Y, int t,
                           const double* rowscale) {
+  // wide blocks with the dense leading rows: those first (forward) or last
+  // (backward) from G's leading block, the rest by its own levels
+  const bool dense = t > 64 && M.dense_wide > 0;
   if (lower) {
+    if (dense) {
+      if (M.dlvl_ptr_f.size() < 2 || M.dlvl_ptr_f.back() != M.n - M.dense_wide)
+        return Status::make(VL_ERR_STATE, "no level schedule");
+      VL_TRY(dense_wide_lower(M, X, Y, t, rowscale));
+      return lower_levels(M, M.dlvl_ptr_f, M.dlvl_nnz_f, M.dfull_order_f.p, X, Y, t, rowscale);
+    }
     if (M.lvl_ptr_f.size() < 2 || M.lvl_ptr_f.back() != M.n)
       return Status::make(VL_ERR_STATE, "no level schedule");
-    return lower_levels(M, X, Y, t, rowscale);
+    return lower_levels(M, M.lvl_ptr_f, M.lvl_nnz_f, M.full_order_f.p, X, Y, t, rowscale);
   }
   // Narrow blocks (t <= 64, when the level path is forced): the fold would
   // leave most lanes of its launch idle, so the full level order is used.
@@ -892,6 +939,13 @@ static Status trsm_levels(Model& M, bool lower, const double* X, double* Y, int 
                          M.bt_ptr.p, M.head_split.p, M.bt_col.p, M.bt_val.p, X, Y, M.lvl_fold.p);
     }
     VL_TRY(check_launch("trsm fold"));
+  }
+  if (dense) {
+    if (M.dhlv_ptr_b.size() < 2 || M.dhlv_ptr_b.back() != H - M.dense_wide)
+      return Status::make(VL_ERR_STATE, "no level schedule");
+    VL_TRY(upper_levels(M, M.dhlv_ptr_b, M.dhlv_nnz_b, M.dhlv_rows_b.p, M.head_split.p,
+                        M.lvl_fold.p, Y, t));
+    return dense_wide_upper(M, M.lvl_fold.p, Y, t);
   }
   return upper_levels(M, M.hlv_ptr_b, M.hlv_nnz_b, M.hlv_rows_b.p, M.head_split.p, M.lvl_fold.p,
                       Y, t);
@@ -1010,18 +1064,19 @@ Status trsm_bt(Model& M, const double* X, double* Y, int t, bool prefilled) {
 // Longest-path level of every row in the dependency DAG of B (lower: over
 // N(i); upper: over the rows of B^T), computed once per neighbour set with
 // the same sync-free scheme as the solves (sentinel -1, 64 rows per wave).
+// Lower: rows below r0 are known (their levels preset, not recomputed).
 template <int W, bool LOWER>
-__global__ __launch_bounds__(256) void levels_kernel(int64_t n, int m,
+__global__ __launch_bounds__(256) void levels_kernel(int64_t n, int64_t r0, int m,
                                                      const int* __restrict__ ptr,
                                                      const int* __restrict__ idx, int* lev,
                                                      int* counter, int* abort_flag,
                                                      int* status) {
   const int lane = threadIdx.x & 63;
-  const int64_t total = (n + 63) >> 6;
+  const int64_t total = (n - r0 + 63) >> 6;
   for (;;) {
     const int64_t u = grab(counter, lane, 1);
     if (u >= total) return;
-    const int64_t r = (u << 6) + lane;
+    const int64_t r = r0 + (u << 6) + lane;
     const bool valid = r < n;
     const int64_t i = LOWER ? r : (n - 1 - r);
     bool pending = valid;
@@ -1143,10 +1198,10 @@ Status build_tail_orders(Model& M) {
     {
       PollingOrder order(M);
       if (dir == 0) {
-        hipLaunchKernelGGL((levels_kernel<32, true>), dim3(g), dim3(256), 0, M.stream, n, M.m,
-                           nullptr, M.nbr.p, lev.p, M.counter.p, M.counter.p + 1, M.status);
+        hipLaunchKernelGGL((levels_kernel<32, true>), dim3(g), dim3(256), 0, M.stream, n, 0,
+                           M.m, nullptr, M.nbr.p, lev.p, M.counter.p, M.counter.p + 1, M.status);
       } else {
-        hipLaunchKernelGGL((levels_kernel<16, false>), dim3(g), dim3(256), 0, M.stream, n, 0,
+        hipLaunchKernelGGL((levels_kernel<16, false>), dim3(g), dim3(256), 0, M.stream, n, 0, 0,
                            M.bt_ptr.p, M.bt_col.p, lev.p, M.counter.p, M.counter.p + 1,
                            M.status);
       }
@@ -1192,6 +1247,49 @@ Status build_tail_orders(Model& M) {
         nz.assign(hz.begin(), hz.begin() + L);
       }
     }
+  }
+  // forward order of the rows Kw..n-1 with the rows below Kw known (the wide
+  // solves take those from the dense inverse)
+  const int64_t Kw = M.dense_wide;
+  if (Kw > 0 && n > Kw) {
+    VL_TRY(fill_int(lev.p, -1, n, M.stream));
+    VL_TRY(fill_int(lev.p, 0, Kw, M.stream));
+    VL_TRY(fill_int(M.counter.p, 0, 2, M.stream));
+    const int64_t units = (n - Kw + 63) / 64;
+    unsigned g = static_cast<unsigned>(std::min<int64_t>((units + 3) / 4, 2048));
+    {
+      PollingOrder order(M);
+      hipLaunchKernelGGL((levels_kernel<32, true>), dim3(g), dim3(256), 0, M.stream, n, Kw, M.m,
+                         nullptr, M.nbr.p, lev.p, M.counter.p, M.counter.p + 1, M.status);
+    }
+    const int* spatial = static_cast<const int*>(M.grid_pts);
+    VL_TRY(M.dfull_order_f.alloc(n - Kw));
+    VL_TRY(fill_int(cnt.p, 0, n + 1, M.stream));
+    hipLaunchKernelGGL(level_count_kernel, dim3(gn), dim3(tb), 0, M.stream, n, Kw, spatial, lev.p,
+                       cnt.p);
+    VL_TRY(exclusive_scan_int(cnt.p, start.p, n + 1, M.stream));
+    VL_TRY(fill_int(cnt.p, 0, n + 1, M.stream));
+    hipLaunchKernelGGL(level_scatter_kernel, dim3(gn), dim3(tb), 0, M.stream, n, Kw, spatial,
+                       lev.p, start.p, cnt.p, M.dfull_order_f.p);
+    VL_TRY(check_launch("dense wide order"));
+    std::vector<int> st(n + 1);
+    VL_HIP(hipMemcpyAsync(st.data(), start.p, sizeof(int) * (n + 1), hipMemcpyDeviceToHost,
+                          M.stream));
+    VL_TRY(sync_stream(M.stream));
+    int64_t L = 0;
+    while (L < n && st[L] < n - Kw) ++L;
+    M.dlvl_ptr_f.assign(st.begin(), st.begin() + L + 1);
+    DevBuf<unsigned long long> lnz;
+    VL_TRY(lnz.alloc(L > 0 ? L : 1));
+    VL_HIP(hipMemsetAsync(lnz.p, 0, sizeof(unsigned long long) * (L > 0 ? L : 1), M.stream));
+    hipLaunchKernelGGL(level_nnz_kernel, dim3(gn), dim3(tb), 0, M.stream, n, Kw, M.m, nullptr,
+                       M.nbr.p, lev.p, lnz.p);
+    VL_TRY(check_launch("level nnz"));
+    std::vector<unsigned long long> hz(L > 0 ? L : 1);
+    VL_HIP(hipMemcpyAsync(hz.data(), lnz.p, sizeof(unsigned long long) * hz.size(),
+                          hipMemcpyDeviceToHost, M.stream));
+    VL_TRY(sync_stream(M.stream));
+    M.dlvl_nnz_f.assign(hz.begin(), hz.begin() + L);
   }
   VL_TRY(sync_stream(M.stream));
   return read_status(M);

@@ -148,7 +148,8 @@ enum TimedKind : int {
   kTimeLevelUpper = 7, // level-scheduled rows of B^T Y = X (wide blocks)
   kTimeLevelUpperSplit = 8, // the same for levels of long B^T rows
   kTimeLevelUpperFold = 9,  // head rows' tail entries of B^T Y = X, one launch
-  kTimeKinds = 10
+  kTimeDenseWide = 10,      // leading rows of the wide solves (dense inverse, matrix cores)
+  kTimeKinds = 11
 };
 
 struct Timing {
@@ -204,6 +205,16 @@ struct Model {
   DevBuf<double> dense_xp;            // K x t folded right-hand sides of B^T solves
   DevBuf<double> dense_part;          // partial products of the dense applications
   DevBuf<int> dense_lo;               // first B^T entry with child >= K, rows < K
+  // wide blocks (t > 64): the leading dense_wide rows from G's leading block
+  // (matrix cores), the level schedules of the other rows with those known
+  int dense_wide = 0;
+  DevBuf<int> dense_lo_w;             // as dense_lo for dense_wide
+  DevBuf<int> dfull_order_f;          // rows dense_wide..n-1 in forward level order
+  std::vector<int> dlvl_ptr_f;
+  std::vector<int64_t> dlvl_nnz_f;
+  DevBuf<int> dhlv_rows_b;            // head rows dense_wide..H-1, backward levels
+  std::vector<int> dhlv_ptr_b;
+  std::vector<int64_t> dhlv_nnz_b;
   int64_t head_nnz_b = 0;
   DevBuf<int> hf_ptr, hf_rows, hb_ptr, hb_rows;
   DevBuf<int> hf_nbr, hb_pptr, hb_col, hb_src;  // position-ordered structure
@@ -338,6 +349,10 @@ Status factor_rows(Model& M, const double* q_xy, int64_t nrows, const int* nbr, 
 Status build_transpose(Model& M);
 Status refresh_transpose_values(Model& M);
 Status build_tail_orders(Model& M);
+// out_j = base_j - sum over the B^T entries [beg[j], end[j]) of B^T row j
+// (values from Y), rows j < rows, wide blocks.
+Status fold_rows(Model& M, int rows, const int* beg, const int* end, const double* base,
+                 const double* Y, double* out, int t);
 
 // Y = rowscale o (X + B_off X)                              (spmm_b)
 // Y = diag o diagvec + X + B_off^T X                         (spmm_bt)
@@ -367,6 +382,9 @@ Status refresh_head_values(Model& M);
 
 // ---- dense leading block (dense.hip)
 constexpr int kDenseRows = 4096;
+constexpr int kDenseWide = 2048;  // leading rows taken from G by the wide solves
+Status dense_wide_lower(Model& M, const double* X, double* Y, int t, const double* rs);
+Status dense_wide_upper(Model& M, const double* Xh, double* Y, int t);
 Status build_dense(Model& M);
 Status dense_factor(Model& M);
 Status dense_lower(Model& M, const double* X, double* Y, int t, const double* rs);

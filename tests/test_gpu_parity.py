@@ -207,17 +207,21 @@ def test_predict(c1, c1_fit):
     assert rel_err(f["var"], var) < TOL
 
 
+@pytest.mark.parametrize("n", [40000, 5000])
 @pytest.mark.parametrize("t", [1, 8, 50, 65, 300])
-def test_trsm_head_and_tail(P, t):
-    # n above the head size: for t <= 64 rows solved in LDS level by level,
-    # the rest by the sync-free tail kernels; wider blocks (65, 300: one and
-    # two column slices, ragged) take the level-scheduled launches.  The
+def test_trsm_head_and_tail(P, t, n):
+    # For t <= 64 the first 4096 rows come from the dense inverse of B's
+    # leading block, the head rows after them are solved in LDS level by
+    # level, the rest (n = 40000) by the sync-free tail kernels; n = 5000 has
+    # no tail.  Wider blocks (65, 300: one and two column slices, ragged) take
+    # the first 2048 rows from the dense inverse and the others by
+    # level-scheduled launches.  The
     # reference solves with the oracle's factor.  The range (0.005, about the
     # spacing of the points) keeps every neighbour covariance well conditioned,
     # so the two factors agree to rounding and the comparison isolates the
     # solve; the neighbour sets, and with them the dependency DAG the kernels
     # schedule, do not depend on the range.
-    n, m = 40000, 20
+    m = 20
     say(f"case: trsm head+tail n={n} t={t}")
     X = synth.locations(n, seed=11)
     g = P.VecchiaLaplace(dev(X), m, OV.COV_MATERN32, (1.0, 0.005))

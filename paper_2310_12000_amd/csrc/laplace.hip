@@ -501,8 +501,12 @@ Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, Nl
     VL_TRY(lrac_slq(M, o, &logdet_lrac));
   } else {
     VL_TRY(M.rhs_blk.reserve(static_cast<size_t>(n) * t));
-    // z_i = B^T ((W + D^{-1})^{1/2} o eps_i), Cov(z_i) = P_VADU
-    VL_TRY(spmm_bt_probe(M, M.rhs_blk.p, t, M.vec_a.p, o.seed, kTagSlq, 0, 0, nullptr, 0, 0));
+    // z_i = B^T ((W + D^{-1})^{1/2} o eps_i), Cov(z_i) = P_VADU; the CG
+    // blocks Z and H serve as scratch before the solve starts
+    VL_TRY(M.cg.Z.reserve(static_cast<size_t>(n) * t));
+    VL_TRY(M.cg.H.reserve(static_cast<size_t>(n) * t));
+    VL_TRY(spmm_bt_probe(M, M.rhs_blk.p, t, M.vec_a.p, o.seed, kTagSlq, 0, 0, nullptr, 0, 0,
+                         M.cg.Z.p, M.cg.H.p));
     // mixed form: FP32 preconditioner solves inside the FP64 block PCG
     CgOps ops = o.precision == VL_MIXED ? vadu_ops_mixed(M.W.p, M.vec_b.p)
                                         : vadu_ops(M.W.p, M.vec_b.p);
@@ -659,9 +663,12 @@ Status predict(Model& M, const double* coords_p, int64_t np, const double* Fp,
   for (int c0 = 0; c0 < s; c0 += tile) {
     const int tt = (s - c0 < tile) ? (s - c0) : tile;
     VL_TRY(M.rhs_blk.reserve(static_cast<size_t>(n) * tt));
-    // z3 = W^{1/2} z1 + B^T (D^{-1/2} o z2), z1, z2 standard normal
+    // z3 = W^{1/2} z1 + B^T (D^{-1/2} o z2), z1, z2 standard normal; the CG
+    // blocks Z and H serve as scratch before the solve starts
+    VL_TRY(M.cg.Z.reserve(static_cast<size_t>(n) * tt));
+    VL_TRY(M.cg.H.reserve(static_cast<size_t>(n) * tt));
     VL_TRY(spmm_bt_probe(M, M.rhs_blk.p, tt, M.vec_c.p, o.seed, kTagPredZ2, c0, 1, M.vec_a.p,
-                         kTagPredZ1, 1));
+                         kTagPredZ1, 1, M.cg.Z.p, M.cg.H.p));
     VL_TRY(cg_solve(M, M.cg, ops, tt, M.rhs_blk.p, o.pred_cg_tol, o.max_cg, false));
     for (int v : M.cg.host_iters) {
       cg_max = v > cg_max ? v : cg_max;

@@ -465,9 +465,31 @@ Status spmm_bt(Model& M, const double* X, double* Y, int t, const double* diag,
   return check_launch("spmm_bt");
 }
 
-// Y = d o probe1 + B^T (s o probe2), probes generated in place
+// out[i, c] = p(i, c) for an n x t block (probe values written once).
+__global__ void probe_fill_kernel(int64_t n, int t, InProbe p, double* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * t;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = p(e / t, static_cast<int>(e % t));
+}
+
+// Y = d o probe1 + B^T (s o probe2).  Narrow blocks generate the probes in
+// place; wider ones (tmp1, tmp2: n x t scratch, given) write them once and
+// take the wide product, where regenerating them per gathered neighbour row
+// would cost 21 generator calls per value.  Both sum in the same order.
 Status spmm_bt_probe(Model& M, double* Y, int t, const double* s, uint64_t seed, uint32_t tag2,
-                     int col0, int gauss2, const double* d, uint32_t tag1, int gauss1) {
+                     int col0, int gauss2, const double* d, uint32_t tag1, int gauss1,
+                     double* tmp1, double* tmp2) {
+  if (t > 64 && tmp1 && tmp2) {
+    const int64_t nt = M.n * static_cast<int64_t>(t);
+    const unsigned g = static_cast<unsigned>(std::min<int64_t>((nt + 255) / 256, 8192));
+    hipLaunchKernelGGL(probe_fill_kernel, dim3(g), dim3(256), 0, M.stream, M.n, t,
+                       InProbe{s, seed, tag2, col0, gauss2}, tmp2);
+    if (d)
+      hipLaunchKernelGGL(probe_fill_kernel, dim3(g), dim3(256), 0, M.stream, M.n, t,
+                         InProbe{nullptr, seed, tag1, col0, gauss1}, tmp1);
+    VL_TRY(check_launch("probe fill"));
+    return spmm_bt(M, tmp2, Y, t, d, d ? tmp1 : nullptr);
+  }
   Lanes L = Lanes::of(t);
   int nb = spmm_nblocks(M.n, t);
   const int* ord = spatial_order(M);

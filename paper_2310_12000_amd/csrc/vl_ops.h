@@ -186,8 +186,11 @@ Status dot_cols(Model& M, const double* X, const double* Y, int t, double* part,
 // sparse kernels with explicit value arrays / probe inputs
 Status spmm_ell_vals(Model& M, const double* vals, const double* X, double* Y, int t,
                      const double* rowscale, bool unit_diag);
+// Y = d o probe1 + B^T (s o probe2); tmp1, tmp2 (n x t scratch, or null) let
+// blocks wider than 64 columns write the probes once and take the wide product.
 Status spmm_bt_probe(Model& M, double* Y, int t, const double* s, uint64_t seed, uint32_t tag2,
-                     int col0, int gauss2, const double* d, uint32_t tag1, int gauss1);
+                     int col0, int gauss2, const double* d, uint32_t tag1, int gauss1,
+                     double* tmp1, double* tmp2);
 Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* rowscale,
                    bool prefilled, int slot);
 Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled, int slot);

@@ -300,8 +300,10 @@ vl_status vl_batch_mode(vl_batch* b, int p, double* mode_out);
 vl_status vl_batch_stats(vl_batch* b, int p, vl_stats* st);
 
 /* Solve path the autotuner picked for a width class (0: one column, 1: 2..64,
- * 2: more), 0 = LDS head + sync-free tail, 1 = one launch per level; -1 if
- * that class was not used yet. */
+ * 2: more), 0 = LDS head + sync-free tail, 1 = one launch per level, 2 = each
+ * problem's factor inverted whole and applied as a dense product (offered
+ * when every problem has at most 4096 locations and the inverses take at
+ * most 8 GB); -1 if that class was not used yet. */
 int vl_batch_tuned_path(vl_batch* b, int width_class);
 
 void vl_batch_free(vl_batch* b);

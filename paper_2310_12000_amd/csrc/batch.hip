@@ -255,10 +255,12 @@ struct Batch {
 
 // ------------------------------------------------------------- autotuning
 // The tile choice of the packed system's triangular solves, per width class
-// (t = 1, 2..64, > 64): the LDS head with the sync-free tail, or one launch
-// per level.  Candidates are timed on the packed system itself (one B^{-T}
-// and one B^{-1} solve each, after one untimed pass) and the faster one is
-// kept for that width class and the system's shape (rows, m).
+// (t = 1, 2..64, > 64): the LDS head with the sync-free tail, one launch per
+// level, or (when every problem is small enough) each problem's B inverted
+// whole and applied as a dense product.  Candidates are timed on the packed
+// system itself (one B^{-T} and one B^{-1} solve each, after one untimed
+// pass) and the fastest one is kept for that width class and the system's
+// shape (rows, m, dense form available).
 static std::map<std::tuple<int64_t, int, int>, int>& tune_cache() {
   static std::map<std::tuple<int64_t, int, int>, int> c;
   return c;
@@ -267,7 +269,7 @@ static std::map<std::tuple<int64_t, int, int>, int>& tune_cache() {
 static int width_class(int t) { return t <= 1 ? 0 : (t <= 64 ? 1 : 2); }
 
 static Status autotune(Model& M, int t, int* choice) {
-  const auto key = std::make_tuple(M.n, M.m, width_class(t));
+  const auto key = std::make_tuple(M.n, M.m, width_class(t) + (M.bd_ready ? 8 : 0));
   auto it = tune_cache().find(key);
   if (it != tune_cache().end()) {
     *choice = it->second;
@@ -284,8 +286,9 @@ static Status autotune(Model& M, int t, int* choice) {
   hipEvent_t e0, e1;
   VL_HIP(hipEventCreate(&e0));
   VL_HIP(hipEventCreate(&e1));
-  for (int cand = 0; cand < 2; ++cand) {
+  for (int cand = 0; cand < (M.bd_ready ? 3 : 2); ++cand) {
     M.force_levels = cand == 1;
+    M.bd_use = cand == 2;
     for (int rep = 0; rep < 2; ++rep) {
       VL_HIP(hipEventRecord(e0, M.stream));
       VL_TRY(trsm_bt(M, X.p, Y.p, t, false));
@@ -303,6 +306,7 @@ static Status autotune(Model& M, int t, int* choice) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   M.force_levels = false;
+  M.bd_use = false;
   VL_TRY(read_status(M));
   tune_cache()[key] = pick;
   *choice = pick;
@@ -456,6 +460,7 @@ static Status apply_tune(Batch& Bt, int t) {
   int choice = 0;
   VL_TRY(autotune(Bt.M, t, &choice));
   Bt.M.force_levels = choice == 1;
+  Bt.M.bd_use = choice == 2 && Bt.M.bd_ready;
   const int wc = width_class(t);
   if (static_cast<int>(Bt.tune.size()) <= wc) Bt.tune.resize(wc + 1, -1);
   Bt.tune[wc] = choice;
@@ -566,6 +571,7 @@ static Status batch_fit(Batch& Bt, const vl_opts& o) {
   CgOps ops = vadu_ops(M.W.p, M.vec_b.p);
   VL_TRY(seg_cg(Bt, Bt.segt, ops, M.rhs_blk.p, o.cg_tol, o.max_cg));
   M.force_levels = false;
+  M.bd_use = false;
   const int q = P * t;
   VL_TRY(M.red_out.reserve(2 * static_cast<size_t>(q) + 64));
   VL_TRY(tridiag_quadrature(M, Bt.cg, M.red_out.p));
@@ -721,6 +727,7 @@ static Status batch_create(const vl_problem* probs, int P, int lik, double aux, 
   VL_TRY(build_transpose(M));
   VL_TRY(build_head_schedule(M));
   VL_TRY(build_tail_orders(M));
+  VL_TRY(bd_build(M, B.start, B.n, B.row_prob.p, B.row_local.p));
   VL_TRY(finish_factor(M));
   VL_TRY(build_seg(M, B.start, B.n, 1, B.seg1));
   *out = bt.release();

@@ -17,6 +17,8 @@
 // parameters) by forward substitution of B_KK G = I, column by column, and
 // kept in both orientations: Gf[c K + i] = G_ic (columns contiguous) for
 // G x, Gb[i K + c] = G_ic (rows contiguous) for G^T x.
+#include <algorithm>
+
 #include "vl_internal.h"
 #include "vl_ops.h"
 
@@ -35,16 +37,33 @@ static int dense_cols(int K) {
 // i; the parts meet by a butterfly, and row i is final before row i + 1
 // reads it (one wave: its LDS accesses complete in order).  Slot data does
 // not depend on G and is fetched one row ahead.
+// Batched form (tab_p given): block b inverts columns tab_c0[b].. of the
+// leading block of problem tab_p[b] of a packed block-diagonal system, whose
+// rows start[p]..start[p + 1]-1 are the whole problem (neighbour indices are
+// packed, so they are shifted to the problem); its G goes to gofs[p].
 template <int C>
 __global__ __launch_bounds__(64) void dense_inverse_kernel(int K, int m,
                                                             const int* __restrict__ nbr,
                                                             const double* __restrict__ bval,
                                                             double* __restrict__ Gf,
-                                                            double* __restrict__ Gb) {
+                                                            double* __restrict__ Gb,
+                                                            const int* __restrict__ tab_p,
+                                                            const int* __restrict__ tab_c0,
+                                                            const int* __restrict__ start,
+                                                            const int64_t* __restrict__ gofs) {
   extern __shared__ double s_g[];  // C x K
   constexpr int Q = 64 / C;
   const int lane = threadIdx.x, cl = lane / Q, q = lane % Q;
-  const int c0 = blockIdx.x * C;
+  int c0 = blockIdx.x * C;
+  int64_t s0 = 0;  // first packed row of the problem
+  if (tab_p) {
+    const int pp = tab_p[blockIdx.x];
+    c0 = tab_c0[blockIdx.x];
+    s0 = start[pp];
+    K = start[pp + 1] - start[pp];
+    Gf += gofs[pp];
+    Gb += gofs[pp];
+  }
   const int c = c0 + cl;
   for (int k = lane; k < C * K; k += 64) s_g[k] = 0.0;
   __syncthreads();
@@ -58,8 +77,9 @@ __global__ __launch_bounds__(64) void dense_inverse_kernel(int K, int m,
     for (int u = 0; u < kSlots; ++u) {
       const int k = q + Q * u;
       const bool in = u < per && i < K && k < m;
-      nj[u] = in ? nbr[(int64_t)i * m + k] : -1;
-      nw[u] = in ? bval[(int64_t)i * m + k] : 0.0;
+      const int j = in ? nbr[(s0 + i) * m + k] : -1;
+      nj[u] = j >= 0 ? static_cast<int>(j - s0) : -1;
+      nw[u] = in ? bval[(s0 + i) * m + k] : 0.0;
     }
   };
   fetch(c0);
@@ -113,13 +133,29 @@ __host__ __device__ __forceinline__ int seg_hi(int chunk, int K, bool lower) {
   return (end + kSeg - 1) / kSeg;
 }
 
+// Batched form (tab_p given): block x takes entry x of the tables, a (problem,
+// row chunk, segment) triple of a packed block-diagonal system; the problem's
+// G sits at gofs[p], its rows at start[p], its partials at pofs[p] t.
 template <int TC, bool LOWER>
 __global__ __launch_bounds__(64 * kApplyWaves) void dense_part_kernel(
     int K, int t, const double* __restrict__ A, const double* __restrict__ V,
-    const double* __restrict__ rs, double* __restrict__ part) {
+    const double* __restrict__ rs, double* __restrict__ part, const int* __restrict__ tab_p,
+    const int* __restrict__ tab_chunk, const int* __restrict__ tab_seg,
+    const int* __restrict__ start, const int64_t* __restrict__ gofs,
+    const int64_t* __restrict__ pofs) {
   __shared__ double s_v[kSeg][TC];
   __shared__ double s_red[kApplyWaves][TC][64];
-  const int chunk = blockIdx.x, g = blockIdx.y;
+  int chunk = blockIdx.x, g = blockIdx.y;
+  if (tab_p) {
+    const int pp = tab_p[blockIdx.x];
+    chunk = tab_chunk[blockIdx.x];
+    g = tab_seg[blockIdx.x];
+    K = start[pp + 1] - start[pp];
+    A += gofs[pp];
+    V += static_cast<int64_t>(start[pp]) * t;
+    if (rs) rs += start[pp];
+    part += pofs[pp] * t;
+  }
   if (g < seg_lo(chunk, LOWER) || g >= seg_hi(chunk, K, LOWER)) return;  // uniform
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -330,7 +366,10 @@ Status build_dense(Model& M) {
   return sync_stream(M.stream);
 }
 
+static Status bd_factor(Model& M);
+
 Status dense_factor(Model& M) {
+  if (M.bd_ready) VL_TRY(bd_factor(M));
   const int K = M.dense_rows;
   if (K <= 0) return Status::ok();
   const int C = dense_cols(K);
@@ -338,7 +377,7 @@ Status dense_factor(Model& M) {
   const dim3 grid((K + C - 1) / C);
 #define VL_INVERSE(CC)                                                                          \
   hipLaunchKernelGGL(dense_inverse_kernel<CC>, grid, dim3(64), lds, M.stream, K, M.m, M.nbr.p, \
-                     M.bval.p, M.dense_gf.p, M.dense_gb.p)
+                     M.bval.p, M.dense_gf.p, M.dense_gb.p, nullptr, nullptr, nullptr, nullptr)
   switch (C) {
     case 1: VL_INVERSE(1); break;
     case 2: VL_INVERSE(2); break;
@@ -360,10 +399,12 @@ static Status launch_apply(Model& M, const double* A, const double* V, const dou
   const unsigned gx = static_cast<unsigned>((K + 63) / 64);
   if (t == 1) {
     hipLaunchKernelGGL((dense_part_kernel<1, LOWER>), dim3(gx, nseg, 1), dim3(64 * kApplyWaves),
-                       0, M.stream, K, t, A, V, rs, M.dense_part.p);
+                       0, M.stream, K, t, A, V, rs, M.dense_part.p, nullptr, nullptr, nullptr,
+                       nullptr, nullptr, nullptr);
   } else {
     hipLaunchKernelGGL((dense_part_kernel<8, LOWER>), dim3(gx, nseg, (t + 7) / 8),
-                       dim3(64 * kApplyWaves), 0, M.stream, K, t, A, V, rs, M.dense_part.p);
+                       dim3(64 * kApplyWaves), 0, M.stream, K, t, A, V, rs, M.dense_part.p,
+                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
   }
   const int64_t kt = static_cast<int64_t>(K) * t;
   hipLaunchKernelGGL(dense_reduce_kernel<LOWER>, dim3(static_cast<unsigned>((kt + 255) / 256)),
@@ -413,6 +454,169 @@ Status dense_wide_upper(Model& M, const double* Xh, double* Y, int t) {
   hipLaunchKernelGGL(dense_gemm_kernel<false>, grid, dim3(256), 0, M.stream, Kw, K, t,
                      M.dense_gb.p, M.dense_xp.p, nullptr, Y);
   return check_launch("dense wide upper");
+}
+
+// ------------------------------------------------ block-diagonal (batching)
+// out[r, c] for every packed row r: the sum of its problem's partials in
+// segment order.
+template <bool LOWER>
+__global__ void bd_reduce_kernel(int64_t n, int t, const int* __restrict__ row_prob,
+                                 const int* __restrict__ row_local, const int* __restrict__ start,
+                                 const int64_t* __restrict__ pofs, const double* __restrict__ part,
+                                 double* __restrict__ out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * t) return;
+  const int64_t r = e / t;
+  const int c = static_cast<int>(e - r * t);
+  const int pp = row_prob[r], loc = row_local[r];
+  const int K = start[pp + 1] - start[pp];
+  const int chunk = loc / 64;
+  const double* pt = part + pofs[pp] * t;
+  double v = 0.0;
+  for (int g = seg_lo(chunk, LOWER); g < seg_hi(chunk, K, LOWER); ++g)
+    v += pt[((int64_t)g * K + loc) * t + c];
+  out[e] = v;
+}
+
+template <typename T>
+static Status upload(DevBuf<T>& d, const std::vector<T>& h, hipStream_t s) {
+  VL_TRY(d.alloc(h.size() > 0 ? h.size() : 1));
+  if (!h.empty())
+    VL_HIP(hipMemcpyAsync(d.p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, s));
+  return Status::ok();
+}
+
+Status bd_build(Model& M, const std::vector<int64_t>& start, const std::vector<int64_t>& n,
+                const int* row_prob, const int* row_local) {
+  M.bd_ready = false;
+  const int P = static_cast<int>(n.size());
+  if (P == 0 || M.m < 1) return Status::ok();
+  int64_t kmax = 0;
+  double bytes = 0.0;
+  for (int64_t k : n) {
+    kmax = std::max(kmax, k);
+    bytes += 16.0 * static_cast<double>(k) * static_cast<double>(k);
+  }
+  if (kmax > kDenseRows || bytes > kBdBytesCap) return Status::ok();  // not this form
+  const int K = static_cast<int>(kmax);
+  const int C = dense_cols(K);
+  std::vector<int> st(P + 1), inv_p, inv_c0, lo_p, lo_c, lo_g, up_p, up_c, up_g;
+  std::vector<int64_t> gofs(P), pofs(P);
+  int64_t g_acc = 0, p_acc = 0;
+  for (int p = 0; p < P; ++p) {
+    st[p] = static_cast<int>(start[p]);
+    const int k = static_cast<int>(n[p]);
+    gofs[p] = g_acc;
+    pofs[p] = p_acc;
+    g_acc += static_cast<int64_t>(k) * k;
+    p_acc += static_cast<int64_t>((k + kSeg - 1) / kSeg) * k;
+    for (int c0 = 0; c0 < k; c0 += C) {
+      inv_p.push_back(p);
+      inv_c0.push_back(c0);
+    }
+    for (int ch = 0; ch < (k + 63) / 64; ++ch) {
+      for (int g = seg_lo(ch, true); g < seg_hi(ch, k, true); ++g) {
+        lo_p.push_back(p);
+        lo_c.push_back(ch);
+        lo_g.push_back(g);
+      }
+      for (int g = seg_lo(ch, false); g < seg_hi(ch, k, false); ++g) {
+        up_p.push_back(p);
+        up_c.push_back(ch);
+        up_g.push_back(g);
+      }
+    }
+  }
+  st[P] = static_cast<int>(start[P - 1] + n[P - 1]);
+  hipStream_t s = M.stream;
+  VL_TRY(upload(M.bd_start, st, s));
+  VL_TRY(upload(M.bd_gofs, gofs, s));
+  VL_TRY(upload(M.bd_pofs, pofs, s));
+  VL_TRY(upload(M.bd_inv_p, inv_p, s));
+  VL_TRY(upload(M.bd_inv_c0, inv_c0, s));
+  VL_TRY(upload(M.bd_lo_p, lo_p, s));
+  VL_TRY(upload(M.bd_lo_chunk, lo_c, s));
+  VL_TRY(upload(M.bd_lo_seg, lo_g, s));
+  VL_TRY(upload(M.bd_up_p, up_p, s));
+  VL_TRY(upload(M.bd_up_chunk, up_c, s));
+  VL_TRY(upload(M.bd_up_seg, up_g, s));
+  VL_TRY(M.bd_gf.alloc(static_cast<size_t>(g_acc)));
+  VL_TRY(M.bd_gb.alloc(static_cast<size_t>(g_acc)));
+  VL_TRY(sync_stream(s));
+  M.bd_C = C;
+  M.bd_kmax = K;
+  M.bd_inv_n = static_cast<int>(inv_p.size());
+  M.bd_lo_n = static_cast<int>(lo_p.size());
+  M.bd_up_n = static_cast<int>(up_p.size());
+  M.bd_part_rows = p_acc;
+  M.bd_row_prob = row_prob;
+  M.bd_row_local = row_local;
+  const size_t lds = sizeof(double) * C * K;
+  for (const void* f : {reinterpret_cast<const void*>(dense_inverse_kernel<1>),
+                        reinterpret_cast<const void*>(dense_inverse_kernel<2>),
+                        reinterpret_cast<const void*>(dense_inverse_kernel<4>),
+                        reinterpret_cast<const void*>(dense_inverse_kernel<8>),
+                        reinterpret_cast<const void*>(dense_inverse_kernel<16>),
+                        reinterpret_cast<const void*>(dense_inverse_kernel<32>)})
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(lds));
+  (void)hipGetLastError();
+  M.bd_ready = true;
+  return Status::ok();
+}
+
+static Status bd_factor(Model& M) {
+  const int C = M.bd_C;
+  const size_t lds = sizeof(double) * C * M.bd_kmax;
+  const dim3 grid(M.bd_inv_n);
+#define VL_BD_INVERSE(CC)                                                                  \
+  hipLaunchKernelGGL(dense_inverse_kernel<CC>, grid, dim3(64), lds, M.stream, M.bd_kmax, M.m, \
+                     M.nbr.p, M.bval.p, M.bd_gf.p, M.bd_gb.p, M.bd_inv_p.p, M.bd_inv_c0.p,   \
+                     M.bd_start.p, M.bd_gofs.p)
+  switch (C) {
+    case 1: VL_BD_INVERSE(1); break;
+    case 2: VL_BD_INVERSE(2); break;
+    case 4: VL_BD_INVERSE(4); break;
+    case 8: VL_BD_INVERSE(8); break;
+    case 16: VL_BD_INVERSE(16); break;
+    default: VL_BD_INVERSE(32); break;
+  }
+#undef VL_BD_INVERSE
+  return check_launch("block-diagonal inverse");
+}
+
+template <bool LOWER>
+static Status bd_apply(Model& M, const double* X, double* Y, int t, const double* rs) {
+  VL_TRY(M.bd_part.reserve(static_cast<size_t>(M.bd_part_rows) * t));
+  const double* A = LOWER ? M.bd_gf.p : M.bd_gb.p;
+  const int nb = LOWER ? M.bd_lo_n : M.bd_up_n;
+  const int* tp = LOWER ? M.bd_lo_p.p : M.bd_up_p.p;
+  const int* tc = LOWER ? M.bd_lo_chunk.p : M.bd_up_chunk.p;
+  const int* tg = LOWER ? M.bd_lo_seg.p : M.bd_up_seg.p;
+  if (t == 1) {
+    hipLaunchKernelGGL((dense_part_kernel<1, LOWER>), dim3(nb, 1, 1), dim3(64 * kApplyWaves), 0,
+                       M.stream, M.bd_kmax, t, A, X, rs, M.bd_part.p, tp, tc, tg, M.bd_start.p,
+                       M.bd_gofs.p, M.bd_pofs.p);
+  } else {
+    hipLaunchKernelGGL((dense_part_kernel<8, LOWER>), dim3(nb, 1, (t + 7) / 8),
+                       dim3(64 * kApplyWaves), 0, M.stream, M.bd_kmax, t, A, X, rs, M.bd_part.p,
+                       tp, tc, tg, M.bd_start.p, M.bd_gofs.p, M.bd_pofs.p);
+  }
+  const int64_t nt = M.n * static_cast<int64_t>(t);
+  hipLaunchKernelGGL(bd_reduce_kernel<LOWER>, dim3(static_cast<unsigned>((nt + 255) / 256)),
+                     dim3(256), 0, M.stream, M.n, t, M.bd_row_prob, M.bd_row_local,
+                     M.bd_start.p, M.bd_pofs.p, M.bd_part.p, Y);
+  return check_launch("block-diagonal product");
+}
+
+Status bd_lower(Model& M, const double* X, double* Y, int t, const double* rs) {
+  TimedLaunch tl(M, kTimeHeadLower, 16.0 * M.n * t);
+  return bd_apply<true>(M, X, Y, t, rs);
+}
+
+Status bd_upper(Model& M, const double* X, double* Y, int t) {
+  TimedLaunch tl(M, kTimeHeadUpper, 16.0 * M.n * t);
+  return bd_apply<false>(M, X, Y, t, nullptr);
 }
 
 }  // namespace vl

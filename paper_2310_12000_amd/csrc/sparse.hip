@@ -1015,6 +1015,7 @@ static bool use_levels(const Model& M, int t) {
 
 Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* rowscale,
                    bool prefilled, int slot) {
+  if (M.bd_use) return bd_lower(M, X, Y, t, rowscale);
   if (use_levels(M, t)) return trsm_levels(M, true, X, Y, t, rowscale);
   if (!prefilled) VL_TRY(trsm_prepare(M, Y, M.n * (int64_t)t, slot));
   const int64_t H = head_of(M, t);
@@ -1051,6 +1052,7 @@ Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* ro
 }
 
 Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled, int slot) {
+  if (M.bd_use) return bd_upper(M, X, Y, t);
   if (use_levels(M, t)) return trsm_levels(M, false, X, Y, t, nullptr);
   if (!prefilled) VL_TRY(trsm_prepare(M, Y, M.n * (int64_t)t, slot));
   const int64_t H = head_of(M, t);

@@ -215,6 +215,19 @@ struct Model {
   DevBuf<int> dhlv_rows_b;            // head rows dense_wide..H-1, backward levels
   std::vector<int> dhlv_ptr_b;
   std::vector<int64_t> dhlv_nnz_b;
+  // packed block-diagonal systems of small problems (batching): every
+  // problem's B inverted whole, solves as per-problem dense products
+  bool bd_ready = false, bd_use = false;
+  int bd_C = 1, bd_kmax = 0, bd_inv_n = 0, bd_lo_n = 0, bd_up_n = 0;
+  int64_t bd_part_rows = 0;
+  DevBuf<int> bd_start;                       // P + 1 packed row starts
+  DevBuf<int64_t> bd_gofs, bd_pofs;           // G and partial offsets per problem
+  DevBuf<int> bd_inv_p, bd_inv_c0;            // inverse blocks
+  DevBuf<int> bd_lo_p, bd_lo_chunk, bd_lo_seg;  // product blocks, G x
+  DevBuf<int> bd_up_p, bd_up_chunk, bd_up_seg;  // product blocks, G^T x
+  DevBuf<double> bd_gf, bd_gb, bd_part;
+  const int* bd_row_prob = nullptr;           // packed row -> problem
+  const int* bd_row_local = nullptr;          // packed row -> row in its problem
   int64_t head_nnz_b = 0;
   DevBuf<int> hf_ptr, hf_rows, hb_ptr, hb_rows;
   DevBuf<int> hf_nbr, hb_pptr, hb_col, hb_src;  // position-ordered structure
@@ -385,6 +398,13 @@ constexpr int kDenseRows = 4096;
 constexpr int kDenseWide = 2048;  // leading rows taken from G by the wide solves
 Status dense_wide_lower(Model& M, const double* X, double* Y, int t, const double* rs);
 Status dense_wide_upper(Model& M, const double* Xh, double* Y, int t);
+// block-diagonal form (batching): available when every problem has at most
+// kDenseRows rows and the dense blocks fit in kBdBytesCap bytes
+constexpr double kBdBytesCap = 8e9;
+Status bd_build(Model& M, const std::vector<int64_t>& start, const std::vector<int64_t>& n,
+                const int* row_prob, const int* row_local);
+Status bd_lower(Model& M, const double* X, double* Y, int t, const double* rs);
+Status bd_upper(Model& M, const double* X, double* Y, int t);
 Status build_dense(Model& M);
 Status dense_factor(Model& M);
 Status dense_lower(Model& M, const double* X, double* Y, int t, const double* rs);

@@ -122,15 +122,6 @@ __global__ __launch_bounds__(kHeadThreads) void head_sort_kernel(int H,
 }
 
 // ------------------------------------------------------------ head solves
-#ifndef VL_HEAD_BACKOFF
-#define VL_HEAD_BACKOFF 0
-#endif
-// A wave whose poll round moved no lane forward sleeps briefly, leaving the
-// LDS to the waves on the critical path.
-__device__ __forceinline__ void head_backoff(bool moved) {
-  if (VL_HEAD_BACKOFF > 0 && !__any(moved)) __builtin_amdgcn_s_sleep(VL_HEAD_BACKOFF);
-}
-
 
 // One workgroup per column c = blockIdx.x.  The head values live in LDS,
 // pre-filled with the sentinel.  The level-ordered positions are cut into
@@ -197,22 +188,18 @@ __global__ __launch_bounds__(NT) void head_lower_kernel(
     bool pending = ci >= 0;
     int kk = 0;
     while (__any(pending)) {
-      bool moved = false;
       if (pending) {
         // all pending values first (independent LDS reads), then consume in order
         double yv[W];
 #pragma unroll
         for (int k = 0; k < W; ++k)
           yv[k] = (k >= kk && cj[k] >= 0) ? lds_poll(&s_y[cj[k]]) : 0.0;
-        const int k1 = consume_ready<W>(cj, cv, yv, kk, acc);
-        moved = k1 != kk;
-        kk = k1;
+        kk = consume_ready<W>(cj, cv, yv, kk, acc);
         if (kk >= W) {
           lds_publish(&s_y[ci], acc);
           pending = false;
         }
       }
-      head_backoff(moved);
     }
     batch += kWaves;
   }
@@ -324,7 +311,6 @@ __global__ __launch_bounds__(NT) void head_upper_kernel(
       uint64_t long_mask = __ballot(is_long);
       int kk = 0;
       while (__any(pending) || long_mask) {
-        bool moved = false;
         if (pending) {
           if (kk == kWin) {  // second window of a row
 #pragma unroll
@@ -339,9 +325,7 @@ __global__ __launch_bounds__(NT) void head_upper_kernel(
 #pragma unroll
           for (int k = 0; k < kWin; ++k)
             lv[k] = (k >= kk && cb[k] >= 0) ? lds_poll(&s_y[cb[k]]) : 0.0;
-          const int k1 = consume_ready<kWin>(cb, vb, lv, kk, acc);
-          moved = k1 != kk;
-          kk = k1;
+          kk = consume_ready<kWin>(cb, vb, lv, kk, acc);
           if (kk == kWin) {
             if (q + kWin >= e) {
               lds_publish(&s_y[j], acc);
@@ -385,10 +369,8 @@ __global__ __launch_bounds__(NT) void head_upper_kernel(
               lds_publish(&s_y[j], acc);
             }
             long_mask &= long_mask - 1;
-            moved = true;
           }
         }
-        head_backoff(moved);
       }
       batch += kWaves;
     }

@@ -130,7 +130,15 @@ const char* vl_last_error(void);
  *   out        receives the handle
  * Runs neighbour search, the batched neighbour Cholesky (A_i, D_i), and the
  * transpose B^T.  Synchronises the stream.  VL_ERR_NOT_SPD if some D_i <= 0
- * or a neighbour covariance fails its Cholesky. */
+ * or a neighbour covariance fails its Cholesky.
+ * Device memory per model beyond the arrays above: the inverse of B's
+ * leading min(n, 4096) rows in two orientations (268 MB at n >= 4096), the
+ * grouped B / B^T of the 32..64-column products (about 1.1 KB per location)
+ * and the level schedules.  Two environment variables, read at build time,
+ * tune the triangular solves: VL_HEAD_ROWS (rows solved in LDS per column,
+ * default 12288) and VL_DENSE_ROWS (leading rows solved with the dense
+ * inverse, default 4096, 0 to disable); neither changes results beyond
+ * rounding. */
 vl_status vl_build_vecchia(const double* coords, int64_t n, int m, int cov,
                            const double* theta_host, void* hip_stream,
                            int want_deriv, vl_model** out);

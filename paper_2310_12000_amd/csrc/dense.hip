@@ -220,26 +220,33 @@ __global__ void dense_reduce_kernel(int K, int t, const double* __restrict__ par
 
 // Wide blocks (t > 64): out[r, c] = sum_s A[s lda + r] v(s, c) for the
 // leading Kd rows, on the FP64 matrix cores.  Block (x, y) computes rows
-// 64x.. and columns 64y..; its 4 waves own 32 x 32 quarters (2 x 2 tiles of
-// v_mfma_f64_16x16x4f64).  The contraction runs over the triangle in steps
-// of 16: the block stages 16 x 64 of A and of v in LDS (the next 16 are
-// loaded into registers meanwhile), then each wave takes 4 MFMA steps per
-// tile.  Operand layout of one MFMA step, lane
-// l = 16 q + i: A[i][q] and B[q][i] in, D[q + 4 r][i] (r = 0..3) out.
+// R x.. and columns 64 y..; its R / 16 waves own 32 x 32 pieces (2 x 2 tiles
+// of v_mfma_f64_16x16x4f64), R / 32 down by 2 across.  The contraction runs
+// over the triangle in steps of 16: the block stages 16 x R of A and 16 x 64
+// of v in LDS (the next 16 are loaded into registers meanwhile), then each
+// wave takes 4 MFMA steps per tile.  A taller block reuses each staged v
+// tile for more rows (R = 128 for wide right-hand sides); R = 64 keeps the
+// grid large enough to fill the chip when t is small.  Entries of A outside
+// the triangle are stored zeros, so the step range of a block may overrun
+// the triangle without changing any sum.  Operand layout of one MFMA step,
+// lane l = 16 q + i: A[i][q] and B[q][i] in, D[q + 4 r][i] (r = 0..3) out.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <bool LOWER>
-__global__ __launch_bounds__(256) void dense_gemm_kernel(int Kd, int lda, int t,
-                                                         const double* __restrict__ A,
-                                                         const double* __restrict__ V,
-                                                         const double* __restrict__ rs,
-                                                         double* __restrict__ out) {
-  __shared__ double sA[16][64];  // [s][row]
-  __shared__ double sB[16][64];  // [s][column]
+template <bool LOWER, int R>
+__global__ __launch_bounds__(R * 4) void dense_gemm_kernel(int Kd, int lda, int t,
+                                                           const double* __restrict__ A,
+                                                           const double* __restrict__ V,
+                                                           const double* __restrict__ rs,
+                                                           double* __restrict__ out) {
+  static_assert(R == 64 || R == 128, "block height");
+  constexpr int kTps = R / 4;     // staging threads per step
+  constexpr int kCols = 64 / kTps;  // v columns each staging thread loads
+  __shared__ double sA[16][R];    // [s][row]
+  __shared__ double sB[16][64];   // [s][column]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  const int r0 = blockIdx.x * R, c0 = blockIdx.y * 64;
   const int s_lo = LOWER ? 0 : r0;
-  const int s_hi = LOWER ? min(Kd, r0 + 64) : Kd;
+  const int s_hi = LOWER ? min(Kd, r0 + R) : Kd;
   const int wr = wave >> 1, wc = wave & 1;
   const int q = lane >> 4, i = lane & 15;
   v4d acc[2][2];
@@ -247,26 +254,30 @@ __global__ __launch_bounds__(256) void dense_gemm_kernel(int Kd, int lda, int t,
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-  const int sl = tid >> 4, x = (tid & 15) * 4;  // staging: one s, four rows / columns
-  double ra[4], rb[4];  // the next tile, loaded while the current one is used
+  // staging: thread -> one s, four rows of A, kCols columns of v
+  const int sl = tid / kTps, xa = (tid % kTps) * 4, xb = (tid % kTps) * kCols;
+  double ra[4], rb[kCols];  // the next tile, loaded while the current one is used
   auto fetch = [&](int s0) {
     const int s = s0 + sl;
     const bool in_s = s < s_hi;
     const double sc = (in_s && rs) ? rs[s] : 1.0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int rr = r0 + x + u, cc = c0 + x + u;
+      const int rr = r0 + xa + u;
       ra[u] = (in_s && rr < Kd) ? A[(int64_t)s * lda + rr] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kCols; ++u) {
+      const int cc = c0 + xb + u;
       rb[u] = (in_s && cc < t) ? V[(int64_t)s * t + cc] * sc : 0.0;
     }
   };
   if (s_lo < s_hi) fetch(s_lo);
   for (int s0 = s_lo; s0 < s_hi; s0 += 16) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      sA[sl][x + u] = ra[u];
-      sB[sl][x + u] = rb[u];
-    }
+    for (int u = 0; u < 4; ++u) sA[sl][xa + u] = ra[u];
+#pragma unroll
+    for (int u = 0; u < kCols; ++u) sB[sl][xb + u] = rb[u];
     __syncthreads();
     if (s0 + 16 < s_hi) fetch(s0 + 16);
 #pragma unroll
@@ -431,15 +442,29 @@ Status dense_upper(Model& M, double* Y, int t) {
   return launch_apply<false>(M, M.dense_gb.p, M.dense_xp.p, nullptr, Y, t);
 }
 
+// Launches dense_gemm_kernel with 128-row blocks when those alone make a grid
+// of at least kGemmTallBlocks blocks (wide t), else with 64-row blocks.
+constexpr int kGemmTallBlocks = 256;
+
+template <bool LOWER>
+void launch_gemm(Model& M, int Kd, int lda, int t, const double* A, const double* V,
+                 const double* rs, double* out) {
+  const int cols = (t + 63) / 64;
+  if (((Kd + 127) / 128) * cols >= kGemmTallBlocks)
+    hipLaunchKernelGGL((dense_gemm_kernel<LOWER, 128>), dim3((Kd + 127) / 128, cols), dim3(512),
+                       0, M.stream, Kd, lda, t, A, V, rs, out);
+  else
+    hipLaunchKernelGGL((dense_gemm_kernel<LOWER, 64>), dim3((Kd + 63) / 64, cols), dim3(256), 0,
+                       M.stream, Kd, lda, t, A, V, rs, out);
+}
+
 // Wide blocks: the leading Kw rows of G are the inverse of B's leading
 // Kw x Kw block (a leading block of a triangular inverse), so the same G
 // serves with leading dimension K.
 Status dense_wide_lower(Model& M, const double* X, double* Y, int t, const double* rs) {
   const int Kw = M.dense_wide, K = M.dense_rows;
   TimedLaunch tl(M, kTimeDenseWide, 4.0 * Kw * (Kw + 1.0) + 16.0 * Kw * t);
-  const dim3 grid((Kw + 63) / 64, (t + 63) / 64);
-  hipLaunchKernelGGL(dense_gemm_kernel<true>, grid, dim3(256), 0, M.stream, Kw, K, t,
-                     M.dense_gf.p, X, rs, Y);
+  launch_gemm<true>(M, Kw, K, t, M.dense_gf.p, X, rs, Y);
   return check_launch("dense wide lower");
 }
 
@@ -450,9 +475,7 @@ Status dense_wide_upper(Model& M, const double* Xh, double* Y, int t) {
   TimedLaunch tl(M, kTimeDenseWide, 4.0 * Kw * (Kw + 1.0) + 16.0 * Kw * t);
   VL_TRY(M.dense_xp.reserve(static_cast<size_t>(Kw) * t));
   VL_TRY(fold_rows(M, Kw, M.dense_lo_w.p, M.head_split.p, Xh, Y, M.dense_xp.p, t));
-  const dim3 grid((Kw + 63) / 64, (t + 63) / 64);
-  hipLaunchKernelGGL(dense_gemm_kernel<false>, grid, dim3(256), 0, M.stream, Kw, K, t,
-                     M.dense_gb.p, M.dense_xp.p, nullptr, Y);
+  launch_gemm<false>(M, Kw, K, t, M.dense_gb.p, M.dense_xp.p, nullptr, Y);
   return check_launch("dense wide upper");
 }
 

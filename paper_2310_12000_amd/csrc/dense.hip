@@ -230,14 +230,17 @@ __global__ void dense_reduce_kernel(int K, int t, const double* __restrict__ par
 // the triangle are stored zeros, so the step range of a block may overrun
 // the triangle without changing any sum.  Operand layout of one MFMA step,
 // lane l = 16 q + i: A[i][q] and B[q][i] in, D[q + 4 r][i] (r = 0..3) out.
+// v and out are FP64 or, for the mixed-precision solves, FP32 (A and the
+// accumulation stay FP64); outd, if given, receives out widened to FP64.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <bool LOWER, int R>
+template <bool LOWER, int R, typename TV, typename TO>
 __global__ __launch_bounds__(R * 4) void dense_gemm_kernel(int Kd, int lda, int t,
                                                            const double* __restrict__ A,
-                                                           const double* __restrict__ V,
+                                                           const TV* __restrict__ V,
                                                            const double* __restrict__ rs,
-                                                           double* __restrict__ out) {
+                                                           TO* __restrict__ out,
+                                                           double* __restrict__ outd) {
   static_assert(R == 64 || R == 128, "block height");
   constexpr int kTps = R / 4;     // staging threads per step
   constexpr int kCols = 64 / kTps;  // v columns each staging thread loads
@@ -269,7 +272,7 @@ __global__ __launch_bounds__(R * 4) void dense_gemm_kernel(int Kd, int lda, int 
 #pragma unroll
     for (int u = 0; u < kCols; ++u) {
       const int cc = c0 + xb + u;
-      rb[u] = (in_s && cc < t) ? V[(int64_t)s * t + cc] * sc : 0.0;
+      rb[u] = (in_s && cc < t) ? static_cast<double>(V[(int64_t)s * t + cc]) * sc : 0.0;
     }
   };
   if (s_lo < s_hi) fetch(s_lo);
@@ -303,7 +306,11 @@ __global__ __launch_bounds__(R * 4) void dense_gemm_kernel(int Kd, int lda, int 
       for (int rr = 0; rr < 4; ++rr) {
         const int row = r0 + wr * 32 + a * 16 + q + 4 * rr;
         const int col = c0 + wc * 32 + b * 16 + i;
-        if (row < Kd && col < t) out[(int64_t)row * t + col] = acc[a][b][rr];
+        if (row < Kd && col < t) {
+          const TO o = static_cast<TO>(acc[a][b][rr]);
+          out[(int64_t)row * t + col] = o;
+          if (outd) outd[(int64_t)row * t + col] = static_cast<double>(o);
+        }
       }
 }
 
@@ -446,16 +453,16 @@ Status dense_upper(Model& M, double* Y, int t) {
 // of at least kGemmTallBlocks blocks (wide t), else with 64-row blocks.
 constexpr int kGemmTallBlocks = 256;
 
-template <bool LOWER>
-void launch_gemm(Model& M, int Kd, int lda, int t, const double* A, const double* V,
-                 const double* rs, double* out) {
+template <bool LOWER, typename TV, typename TO>
+void launch_gemm(Model& M, int Kd, int lda, int t, const double* A, const TV* V,
+                 const double* rs, TO* out, double* outd) {
   const int cols = (t + 63) / 64;
   if (((Kd + 127) / 128) * cols >= kGemmTallBlocks)
-    hipLaunchKernelGGL((dense_gemm_kernel<LOWER, 128>), dim3((Kd + 127) / 128, cols), dim3(512),
-                       0, M.stream, Kd, lda, t, A, V, rs, out);
+    hipLaunchKernelGGL((dense_gemm_kernel<LOWER, 128, TV, TO>), dim3((Kd + 127) / 128, cols),
+                       dim3(512), 0, M.stream, Kd, lda, t, A, V, rs, out, outd);
   else
-    hipLaunchKernelGGL((dense_gemm_kernel<LOWER, 64>), dim3((Kd + 63) / 64, cols), dim3(256), 0,
-                       M.stream, Kd, lda, t, A, V, rs, out);
+    hipLaunchKernelGGL((dense_gemm_kernel<LOWER, 64, TV, TO>), dim3((Kd + 63) / 64, cols),
+                       dim3(256), 0, M.stream, Kd, lda, t, A, V, rs, out, outd);
 }
 
 // Wide blocks: the leading Kw rows of G are the inverse of B's leading
@@ -464,8 +471,18 @@ void launch_gemm(Model& M, int Kd, int lda, int t, const double* A, const double
 Status dense_wide_lower(Model& M, const double* X, double* Y, int t, const double* rs) {
   const int Kw = M.dense_wide, K = M.dense_rows;
   TimedLaunch tl(M, kTimeDenseWide, 4.0 * Kw * (Kw + 1.0) + 16.0 * Kw * t);
-  launch_gemm<true>(M, Kw, K, t, M.dense_gf.p, X, rs, Y);
+  launch_gemm<true>(M, Kw, K, t, M.dense_gf.p, X, rs, Y, static_cast<double*>(nullptr));
   return check_launch("dense wide lower");
+}
+
+// The mixed-precision forward solve's leading rows: X, Y in FP32, Yd the FP64
+// copy of Y; G and the sums in FP64.
+Status dense_wide_lower_f32(Model& M, const float* X, float* Y, double* Yd, int t,
+                            const double* rs) {
+  const int Kw = M.dense_wide, K = M.dense_rows;
+  TimedLaunch tl(M, kTimeDenseWide, 4.0 * Kw * (Kw + 1.0) + 16.0 * Kw * t);
+  launch_gemm<true>(M, Kw, K, t, M.dense_gf.p, X, rs, Y, Yd);
+  return check_launch("dense wide lower f32");
 }
 
 // Y_j (j < Kw) = sum_i G_ij x'_i, x'_j = Xh_j - the B^T entries of row j with
@@ -475,8 +492,21 @@ Status dense_wide_upper(Model& M, const double* Xh, double* Y, int t) {
   TimedLaunch tl(M, kTimeDenseWide, 4.0 * Kw * (Kw + 1.0) + 16.0 * Kw * t);
   VL_TRY(M.dense_xp.reserve(static_cast<size_t>(Kw) * t));
   VL_TRY(fold_rows(M, Kw, M.dense_lo_w.p, M.head_split.p, Xh, Y, M.dense_xp.p, t));
-  launch_gemm<false>(M, Kw, K, t, M.dense_gb.p, M.dense_xp.p, nullptr, Y);
+  launch_gemm<false>(M, Kw, K, t, M.dense_gb.p, M.dense_xp.p, nullptr, Y,
+                     static_cast<double*>(nullptr));
   return check_launch("dense wide upper");
+}
+
+// The mixed-precision backward solve's leading rows: Xh in FP64 (the folded
+// right-hand side), Y in FP32.
+Status dense_wide_upper_f32(Model& M, const double* Xh, float* Y, int t) {
+  const int Kw = M.dense_wide, K = M.dense_rows;
+  TimedLaunch tl(M, kTimeDenseWide, 4.0 * Kw * (Kw + 1.0) + 12.0 * Kw * t);
+  VL_TRY(M.dense_xp.reserve(static_cast<size_t>(Kw) * t));
+  VL_TRY(fold_rows(M, Kw, M.dense_lo_w.p, M.head_split.p, Xh, Y, M.dense_xp.p, t));
+  launch_gemm<false>(M, Kw, K, t, M.dense_gb.p, M.dense_xp.p, nullptr, Y,
+                     static_cast<double*>(nullptr));
+  return check_launch("dense wide upper f32");
 }
 
 // ------------------------------------------------ block-diagonal (batching)

@@ -11,8 +11,9 @@
 // The FP32 solves are used for blocks wider than 64 columns, where the
 // solves move bytes; they are level-scheduled (one launch per level of the
 // dependency DAG; no sentinel fill, no polling), and B^T solves fold the head
-// rows' tail entries in one launch between the tail and the head levels.
-// Narrower blocks keep the FP64 solves.
+// rows' tail entries in one launch between the tail and the head levels.  The
+// leading rows covered by the dense inverse G come from its FP64 GEMM, which
+// reads and writes the FP32 blocks.  Narrower blocks keep the FP64 solves.
 #include <algorithm>
 #include <cmath>
 
@@ -217,7 +218,9 @@ static Status upper_levels_f32(Model& M, const std::vector<int>& lp,
 }
 
 // Y (FP32) = B^T^{-1} X with X FP64: tail rows by level, the fold of the head
-// rows' tail entries (FP64), then the head rows by head-internal level.
+// rows' tail entries (FP64), then the head rows by head-internal level; with
+// the dense leading rows, the head rows from Kw on by their levels and the
+// rows below Kw from G's leading block (as in the FP64 wide solves).
 static Status upper_f32(Model& M, const double* X, float* Y, int t) {
   const int64_t H = M.head_rows;
   if (M.hlv_ptr_b.size() < 2 || M.hlv_ptr_b.back() != H ||
@@ -227,6 +230,13 @@ static Status upper_f32(Model& M, const double* X, float* Y, int t) {
     VL_TRY(upper_levels_f32(M, M.tlvl_ptr_b, M.tlvl_nnz_b, M.tail_order_b.p, nullptr, X, Y, t));
   VL_TRY(M.lvl_fold.reserve(static_cast<size_t>(H) * t));
   VL_TRY(fold_launch_f32(M, X, Y, M.lvl_fold.p, t));
+  if (M.dense_wide > 0) {
+    if (M.dhlv_ptr_b.size() < 2 || M.dhlv_ptr_b.back() != H - M.dense_wide)
+      return Status::make(VL_ERR_STATE, "no level schedule");
+    VL_TRY(upper_levels_f32(M, M.dhlv_ptr_b, M.dhlv_nnz_b, M.dhlv_rows_b.p, M.head_split.p,
+                            M.lvl_fold.p, Y, t));
+    return dense_wide_upper_f32(M, M.lvl_fold.p, Y, t);
+  }
   return upper_levels_f32(M, M.hlv_ptr_b, M.hlv_nnz_b, M.hlv_rows_b.p, M.head_split.p,
                           M.lvl_fold.p, Y, t);
 }
@@ -240,16 +250,22 @@ static void launch_lower_f32(Model& M, int rows, int t, const int* r, const floa
                      M.nbr.p, M.bval_f.p, X, rs, Y, Yd);
 }
 
-// Y (FP32) and Yd (FP64) = B^{-1} (rs o X) with X FP32, full level order.
+// Y (FP32) and Yd (FP64) = B^{-1} (rs o X) with X FP32: the full level
+// order or, with the dense leading rows, those from G's leading block and
+// the rest by the levels computed with them known.
 static Status lower_f32(Model& M, const float* X, float* Y, double* Yd, int t,
                         const double* rs) {
-  const std::vector<int>& lp = M.lvl_ptr_f;
-  if (lp.size() < 2 || lp.back() != M.n) return Status::make(VL_ERR_STATE, "no level schedule");
+  const bool dense = M.dense_wide > 0;
+  const std::vector<int>& lp = dense ? M.dlvl_ptr_f : M.lvl_ptr_f;
+  const int* order = dense ? M.dfull_order_f.p : M.full_order_f.p;
+  if (lp.size() < 2 || lp.back() != M.n - (dense ? M.dense_wide : 0))
+    return Status::make(VL_ERR_STATE, "no level schedule");
+  if (dense) VL_TRY(dense_wide_lower_f32(M, X, Y, Yd, t, rs));
   const int vec = level_vec(t, 4, X, Y, Yd);
   for (size_t l = 0; l + 1 < lp.size(); ++l) {
     const int rows = lp[l + 1] - lp[l];
     if (rows <= 0) continue;
-    const int* r = M.full_order_f.p + lp[l];
+    const int* r = order + lp[l];
     if (vec == 4) {
       launch_lower_f32<4>(M, rows, t, r, X, rs, Y, Yd);
     } else if (vec == 2) {

@@ -793,13 +793,13 @@ __global__ __launch_bounds__(256) void trsm_fold_kernel(int t, const int* __rest
 // out_j = base_j - sum over the B^T entries [beg[j], end[j]) of row j, for
 // rows j < rows; block (j, s) covers 64 VEC columns with 4 waves sharing the
 // row's entries (the wide-block fold before the dense leading rows).
-template <int VEC>
+template <int VEC, typename TY>
 __global__ __launch_bounds__(256) void range_fold_kernel(int t, const int* __restrict__ beg,
                                                          const int* __restrict__ end,
                                                          const int* __restrict__ idx,
-                                                         const double* __restrict__ vals,
+                                                         const TY* __restrict__ vals,
                                                          const double* __restrict__ base,
-                                                         const double* __restrict__ Y,
+                                                         const TY* __restrict__ Y,
                                                          double* __restrict__ out) {
   const int c = (blockIdx.y * 64 + (threadIdx.x & 63)) * VEC;
   const int64_t j = blockIdx.x;
@@ -850,13 +850,32 @@ Status fold_rows(Model& M, int rows, const int* beg, const int* end, const doubl
   const int vec = level_vec(t, 8, base, Y, out);
   const dim3 grid(static_cast<unsigned>(rows), (t + 64 * vec - 1) / (64 * vec));
   if (vec == 2) {
-    hipLaunchKernelGGL(range_fold_kernel<2>, grid, dim3(256), 0, M.stream, t, beg, end,
+    hipLaunchKernelGGL((range_fold_kernel<2, double>), grid, dim3(256), 0, M.stream, t, beg, end,
                        M.bt_col.p, M.bt_val.p, base, Y, out);
   } else {
-    hipLaunchKernelGGL(range_fold_kernel<1>, grid, dim3(256), 0, M.stream, t, beg, end,
+    hipLaunchKernelGGL((range_fold_kernel<1, double>), grid, dim3(256), 0, M.stream, t, beg, end,
                        M.bt_col.p, M.bt_val.p, base, Y, out);
   }
   return check_launch("range fold");
+}
+
+// The same with Y and the B^T values in FP32 (the mixed-precision solves).
+Status fold_rows(Model& M, int rows, const int* beg, const int* end, const double* base,
+                 const float* Y, double* out, int t) {
+  if (rows <= 0) return Status::ok();
+  const int vec = level_vec(t, 4, base, Y, out);
+  const dim3 grid(static_cast<unsigned>(rows), (t + 64 * vec - 1) / (64 * vec));
+  if (vec == 4) {
+    hipLaunchKernelGGL((range_fold_kernel<4, float>), grid, dim3(256), 0, M.stream, t, beg, end,
+                       M.bt_col.p, M.bt_val_f.p, base, Y, out);
+  } else if (vec == 2) {
+    hipLaunchKernelGGL((range_fold_kernel<2, float>), grid, dim3(256), 0, M.stream, t, beg, end,
+                       M.bt_col.p, M.bt_val_f.p, base, Y, out);
+  } else {
+    hipLaunchKernelGGL((range_fold_kernel<1, float>), grid, dim3(256), 0, M.stream, t, beg, end,
+                       M.bt_col.p, M.bt_val_f.p, base, Y, out);
+  }
+  return check_launch("range fold f32");
 }
 
 // Levels [lp] of the forward order `order`.

@@ -366,6 +366,8 @@ Status build_tail_orders(Model& M);
 // (values from Y), rows j < rows, wide blocks.
 Status fold_rows(Model& M, int rows, const int* beg, const int* end, const double* base,
                  const double* Y, double* out, int t);
+Status fold_rows(Model& M, int rows, const int* beg, const int* end, const double* base,
+                 const float* Y, double* out, int t);  // FP32 Y and B^T values
 
 // Y = rowscale o (X + B_off X)                              (spmm_b)
 // Y = diag o diagvec + X + B_off^T X                         (spmm_bt)
@@ -398,6 +400,9 @@ constexpr int kDenseRows = 4096;
 constexpr int kDenseWide = 2048;  // leading rows taken from G by the wide solves
 Status dense_wide_lower(Model& M, const double* X, double* Y, int t, const double* rs);
 Status dense_wide_upper(Model& M, const double* Xh, double* Y, int t);
+Status dense_wide_lower_f32(Model& M, const float* X, float* Y, double* Yd, int t,
+                            const double* rs);
+Status dense_wide_upper_f32(Model& M, const double* Xh, float* Y, int t);
 // block-diagonal form (batching): available when every problem has at most
 // kDenseRows rows and the dense blocks fit in kBdBytesCap bytes
 constexpr double kBdBytesCap = 8e9;

@@ -208,14 +208,15 @@ def test_predict(c1, c1_fit):
 
 
 @pytest.mark.parametrize("n", [40000, 5000])
-@pytest.mark.parametrize("t", [1, 8, 50, 65, 300])
+@pytest.mark.parametrize("t", [1, 8, 50, 65, 300, 1000])
 def test_trsm_head_and_tail(P, t, n):
     # For t <= 64 the first 4096 rows come from the dense inverse of B's
     # leading block, the head rows after them are solved in LDS level by
     # level, the rest (n = 40000) by the sync-free tail kernels; n = 5000 has
     # no tail.  Wider blocks (65, 300: one and two column slices, ragged) take
     # the first 2048 rows from the dense inverse and the others by
-    # level-scheduled launches.  The
+    # level-scheduled launches; at t = 1000 the dense product runs in its
+    # 128-row blocks (ragged last column tile of 40).  The
     # reference solves with the oracle's factor.  The range (0.005, about the
     # spacing of the points) keeps every neighbour covariance well conditioned,
     # so the two factors agree to rounding and the comparison isolates the

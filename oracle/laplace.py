@@ -492,12 +492,18 @@ def _grad_theta_vadu(model, y, F, lik, aux, b, W, res, opts, replay_grad_cg):
     grad = np.zeros(2)
     parts = {}
     # d log det / d mu (VADU mu-formula), needed for the implicit term
+    # d log det(Sigma~ W + I) / d mu_i = dW_i (A^{-1})_ii, estimated per probe
+    # by h_i = dW_i (A^{-1}z)_i (P^{-1}z)_i; the control variate
+    # r_i = dW_i (B P^{-1}z)_i^2 has the known mean tr(P^{-1} dP/dmu_i) =
+    # dW_i / (W_i + 1/D_i), since dP/dmu_i = dW_i B_i^T B_i for P_VADU.
     dW = lik_dW(lik, y, F + b, aux)
     h_mu = dW[:, None] * U * V
     r_mu = dW[:, None] * BV * BV
     c_mu = _cv_weight(h_mu, r_mu)
-    dlogdet_dmu = c_mu * dW / wd + np.mean(h_mu - c_mu[:, None] * r_mu, axis=1)
+    trP_mu = dW / wd
+    dlogdet_dmu = c_mu * trP_mu + np.mean(h_mu - c_mu[:, None] * r_mu, axis=1)
     dL_db = 0.5 * dlogdet_dmu
+    parts.update(h_mu=h_mu, r_mu=r_mu, c_mu=c_mu, trP_mu=trP_mu, dlogdet_dmu=dlogdet_dmu)
     apply_A, apply_Pinv = vadu_ops(model, W)
     if np.any(dL_db != 0.0):
         forced = None if replay_grad_cg is None else [replay_grad_cg]

@@ -349,6 +349,87 @@ def test_control_variate_does_not_change_the_mean():
         np.testing.assert_allclose(r[:5], rd, rtol=1e-8, atol=1e-10)
 
 
+def _mu_derivative_setup(lik, n=40):
+    F = 0.5 if lik == L.LIK_POISSON else 0.0
+    model, y, Fv = _problem(n=n, m=5, seed=21, deriv=True, lik=lik, F=F)
+    b, W, _ = L.find_mode(model, y, Fv, lik, None, L.Opts(cg_tol=1e-12, newton_tol=1e-15))
+    dW = L.lik_dW(lik, y, Fv + b)
+    Bd = model.B.toarray()
+    A = np.diag(W) + DR.dense_precision(Bd, model.D)
+    P = Bd.T @ np.diag(W + model.Dinv) @ Bd
+    return model, y, Fv, b, W, dW, Bd, A, P
+
+
+@pytest.mark.parametrize("lik", [L.LIK_POISSON, L.LIK_BERNOULLI_LOGIT])
+def test_mu_derivative_of_the_log_determinant(lik):
+    # The implicit part of the theta-gradient needs d log det(Sigma~ W + I)/d mu
+    # (App. A.3; VADU mu-formula of App. A.4.1).  Its exact value is
+    # dW_i (A^{-1})_ii with A = W + Sigma~^{-1}; the STE h_i = dW_i (A^{-1}z)_i
+    # (P^{-1}z)_i is unbiased for it for any probes with Cov(z) = P, and the
+    # control variate r_i = dW_i (B P^{-1} z)_i^2 has the mean
+    # tr(P^{-1} dP/dmu_i).  Gaussian probes (the paper's def_SLQ) make r
+    # random, so the control-variate weight and the trace term are exercised;
+    # each piece is compared with a dense computation of its definition.
+    n, t = 40, 4000
+    model, y, Fv, b, W, dW, Bd, A, P = _mu_derivative_setup(lik, n)
+    Di = model.Dinv
+    apply_A, apply_Pinv = L.vadu_ops(model, W)
+    g = R.gaussian(3, R.TAG_SLQ, n, t)
+    Z = Bd.T @ (np.sqrt(W + Di)[:, None] * g)
+    res = L.pcg(apply_A, apply_Pinv, Z, 1e-13, 2 * n)
+    opts = L.Opts(cg_tol=1e-13, num_probes=t, seed=3)
+    _, info = L._grad_theta_vadu(model, y, Fv, lik, None, b, W, res, opts, None)
+    # tr(P^{-1} dP/dmu_i) with dP/dmu_i = B^T diag(dW_i e_i) B, densely
+    trP_dense = dW * np.diag(Bd @ np.linalg.solve(P, Bd.T))
+    np.testing.assert_allclose(info["trP_mu"], trP_dense, rtol=1e-9, atol=1e-14)
+    # per probe: h and r against their dense definitions
+    AZ, PZ = np.linalg.solve(A, Z[:, :6]), np.linalg.solve(P, Z[:, :6])
+    np.testing.assert_allclose(info["h_mu"][:, :6], dW[:, None] * AZ * PZ, rtol=1e-8,
+                               atol=1e-12)
+    np.testing.assert_allclose(info["r_mu"][:, :6], dW[:, None] * (Bd @ PZ) ** 2, rtol=1e-8,
+                               atol=1e-12)
+    # the control-variate estimate is mean(h - c r) + c E[r], with E[r] from
+    # the dense trace: a dropped, mis-signed or mis-scaled trace term fails
+    h, r, c = info["h_mu"], info["r_mu"], info["c_mu"]
+    assert np.all(np.abs(c) > 1e-3)
+    cv = np.mean(h - c[:, None] * r, axis=1)
+    np.testing.assert_allclose(info["dlogdet_dmu"], cv + c * trP_dense, rtol=1e-10,
+                               atol=1e-13)
+    # and it estimates the exact derivative within 5 standard errors, with a
+    # smaller error than the c = 0 estimate
+    exact = dW * np.diag(np.linalg.inv(A))
+    se = np.std(h - c[:, None] * r, axis=1, ddof=1) / np.sqrt(t)
+    assert np.all(np.abs(info["dlogdet_dmu"] - exact) <= 5 * se + 1e-12), \
+        np.max(np.abs(info["dlogdet_dmu"] - exact) / (se + 1e-300))
+    se0 = np.std(h, axis=1, ddof=1) / np.sqrt(t)
+    assert np.mean(se) < np.mean(se0)
+    # without the trace term the estimate is biased by c tr(P^{-1} dP/dmu)
+    # far beyond its standard error
+    assert np.max(np.abs(cv - exact) / se) > 10
+
+
+@pytest.mark.parametrize("lik", [L.LIK_POISSON, L.LIK_BERNOULLI_LOGIT])
+def test_mu_derivative_with_rademacher_probes(lik):
+    # With Rademacher probes (the reading used for SLQ) B P^{-1} z =
+    # (W + D^{-1})^{-1/2} eps, so r_i = dW_i eps_i^2 / (W_i + 1/D_i) is the
+    # same for every probe: the control-variate weight is 0 and the estimate
+    # is the plain mean of h, still within 5 standard errors of the exact
+    # dW_i (A^{-1})_ii.
+    n, t = 40, 4000
+    model, y, Fv, b, W, dW, Bd, A, P = _mu_derivative_setup(lik, n)
+    opts = L.Opts(cg_tol=1e-13, num_probes=t, seed=3)
+    _, info = L.neg_log_marglik(model, y, Fv, lik, None, b, opts, want_grad=True)
+    r = info["r_mu"]
+    np.testing.assert_allclose(r, np.repeat(info["trP_mu"][:, None], t, axis=1), rtol=1e-10,
+                               atol=1e-15)
+    assert np.all(info["c_mu"] == 0.0)
+    h = info["h_mu"]
+    np.testing.assert_allclose(info["dlogdet_dmu"], h.mean(axis=1), rtol=1e-12, atol=1e-15)
+    exact = dW * np.diag(np.linalg.inv(A))
+    se = np.std(h, axis=1, ddof=1) / np.sqrt(t)
+    assert np.all(np.abs(info["dlogdet_dmu"] - exact) <= 5 * se + 1e-12)
+
+
 # ----------------------------------------------------------------- prediction
 def test_prediction_textbook_limit():
     # m = n-1 and m_p = n: the Vecchia approximation is exact, so the

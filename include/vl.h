@@ -354,14 +354,18 @@ vl_status vl_server_create(int slots, double hbm_budget_bytes, const vl_opts* o,
 vl_status vl_server_submit(vl_server* s, const vl_request* r, int64_t* ticket);
 /* Block until the request finished; nll_out (host) gets its negative
  * log-marginal likelihood, st its statistics (t_ms = submit-to-done latency),
- * queue_ms the time it waited for admission.  Returns the request's status. */
+ * queue_ms the time it waited for admission.  Returns the request's status:
+ * VL_ERR_NO_CONVERGENCE (with st->hit_cap = 1) when a Newton or CG loop of
+ * the request stopped at its cap (its outputs are written). */
 vl_status vl_server_wait(vl_server* s, int64_t ticket, double* nll_out, vl_stats* st,
                          double* queue_ms);
 /* Largest admitted HBM estimate and largest number of requests running at once. */
 vl_status vl_server_info(vl_server* s, double* peak_bytes, int* peak_running);
 /* The HBM estimate admission uses for a request (bytes). */
 double vl_request_bytes(const vl_request* r, const vl_opts* o);
-/* Drop waiting requests, finish running ones, stop the workers. */
+/* Drop waiting requests (they complete with VL_ERR_STATE, so a thread
+ * blocked in vl_server_wait for one of them returns), finish running ones,
+ * stop the workers, and return once no thread is inside vl_server_wait. */
 void vl_server_free(vl_server* s);
 
 /* Release the handle and all its device memory. */

@@ -65,6 +65,7 @@ struct Server {
   bool stop = false;
   double peak_in_use = 0.0;
   int peak_running = 0;
+  int waiters = 0;                           // threads inside vl_server_wait
   std::vector<std::thread> workers;
 };
 
@@ -112,20 +113,28 @@ static Status run_request(Job& J, const vl_opts& o, hipStream_t stream, int max_
   model_of(h)->max_streams = max_streams;
   vl_opts oo = o;
   oo.seed = r.seed;
+  // A loop that stops at its cap still writes its outputs: the request then
+  // completes with VL_ERR_NO_CONVERGENCE and hit_cap set.
   Status s = [&]() -> Status {
     vl_stats st{};
     const double aux = r.aux;
+    bool capped = false;
     vl_status c = vl_find_mode(h, r.y, r.F, r.lik, &aux, &oo, nullptr, &st);
     if (c != VL_OK && c != VL_ERR_NO_CONVERGENCE) return code(c, "mode");
+    capped |= (c == VL_ERR_NO_CONVERGENCE) || st.hit_cap;
     J.st.newton_iters = st.newton_iters;
     J.st.cg_iters_total = st.cg_iters_total;
     c = vl_neg_log_marglik(h, &oo, &J.nll, nullptr, &st);
     if (c != VL_OK && c != VL_ERR_NO_CONVERGENCE) return code(c, "likelihood");
+    capped |= (c == VL_ERR_NO_CONVERGENCE) || st.hit_cap;
     J.st.cg_iters_max = st.cg_iters_max;
     if (r.n_p > 0) {
       c = vl_predict(h, r.coords_p, r.n_p, r.Fp, &oo, r.mean_out, r.var_out, &st);
       if (c != VL_OK && c != VL_ERR_NO_CONVERGENCE) return code(c, "predict");
+      capped |= (c == VL_ERR_NO_CONVERGENCE) || st.hit_cap;
     }
+    J.st.hit_cap = capped ? 1 : 0;
+    if (capped) return Status::make(VL_ERR_NO_CONVERGENCE, "a loop stopped at its cap");
     return Status::ok();
   }();
   vl_free(h);
@@ -228,9 +237,12 @@ vl_status vl_server_wait(vl_server* S, int64_t ticket, double* nll_out, vl_stats
     auto it = S->jobs.find(ticket);
     if (it == S->jobs.end()) return vl::report(vl::Status::invalid("unknown ticket"));
     J = it->second;
+    ++S->waiters;
     S->cv_done.wait(lk, [&] { return J->done; });
-    S->jobs.erase(it);
+    S->jobs.erase(ticket);
+    --S->waiters;
   }
+  S->cv_done.notify_all();  // vl_server_free may wait for the last waiter
   if (nll_out) *nll_out = J->nll;
   if (st) *st = J->st;
   if (queue_ms) *queue_ms = 1e3 * (J->t_start - J->t_submit);
@@ -254,12 +266,25 @@ double vl_request_bytes(const vl_request* r, const vl_opts* o) {
 void vl_server_free(vl_server* S) {
   if (!S) return;
   {
+    // requests still waiting for admission are dropped: they complete with
+    // VL_ERR_STATE, which wakes any thread waiting for them
     std::lock_guard<std::mutex> lk(S->mu);
     S->stop = true;
+    for (auto& j : S->queue) {
+      j->status = VL_ERR_STATE;
+      j->t_start = j->t_done = vl::now_s();
+      j->done = true;
+    }
     S->queue.clear();
   }
   S->cv_work.notify_all();
+  S->cv_done.notify_all();
   for (auto& t : S->workers) t.join();
+  {
+    // the server outlives every vl_server_wait that is still returning
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->waiters == 0; });
+  }
   delete S;
 }
 

@@ -1190,7 +1190,9 @@ __global__ void level_count_kernel(int64_t n, int64_t r0, const int* __restrict_
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int r = spatial[k];
-  if (r >= r0) atomicAdd(&cnt[lev[r]], 1);
+  if (r < r0) return;
+  const int l = lev[r];
+  if (l >= 0) atomicAdd(&cnt[l], 1);
 }
 
 // nnz of the rows of each level (lower: entries with idx >= 0 of the ELL
@@ -1206,7 +1208,8 @@ __global__ void level_nnz_kernel(int64_t n, int64_t r0, int m, const int* __rest
   } else {
     for (int k = 0; k < m; ++k) c += idx[i * m + k] >= 0 ? 1 : 0;
   }
-  if (c) atomicAdd(&nnz[lev[i]], static_cast<unsigned long long>(c));
+  const int l = lev[i];
+  if (c && l >= 0) atomicAdd(&nnz[l], static_cast<unsigned long long>(c));
 }
 
 __global__ void level_scatter_kernel(int64_t n, int64_t r0, const int* __restrict__ spatial,
@@ -1217,6 +1220,7 @@ __global__ void level_scatter_kernel(int64_t n, int64_t r0, const int* __restric
   const int r = spatial[k];
   if (r < r0) return;
   const int l = lev[r];
+  if (l < 0) return;
   order[start[l] + atomicAdd(&cursor[l], 1)] = r;
 }
 
@@ -1249,6 +1253,10 @@ Status build_tail_orders(Model& M) {
                            M.status);
       }
     }
+    // A wave that reached its wait bound leaves rows without a level (-1):
+    // stop before anything indexes by level.
+    VL_TRY(check_launch("levels"));
+    VL_TRY(read_status(M));
     const int* spatial = static_cast<const int*>(M.grid_pts);
     for (int full = 0; full < 2; ++full) {
       const int64_t r0 = full ? 0 : H;
@@ -1305,6 +1313,8 @@ Status build_tail_orders(Model& M) {
       hipLaunchKernelGGL((levels_kernel<32, true>), dim3(g), dim3(256), 0, M.stream, n, Kw, M.m,
                          nullptr, M.nbr.p, lev.p, M.counter.p, M.counter.p + 1, M.status);
     }
+    VL_TRY(check_launch("levels"));
+    VL_TRY(read_status(M));
     const int* spatial = static_cast<const int*>(M.grid_pts);
     VL_TRY(M.dfull_order_f.alloc(n - Kw));
     VL_TRY(fill_int(cnt.p, 0, n + 1, M.stream));

@@ -105,6 +105,30 @@ typedef struct {
 } vl_stats;
 
 /* ---------------------------------------------------------------------- */
+/* Device memory of the library.  Every device buffer a model, batch or
+ * server owns (its state and the temporaries of a call) is obtained from
+ * the allocator installed here; by default the library uses the
+ * stream-ordered hipMallocAsync / hipFreeAsync.
+ *   alloc(bytes, stream, ctx)  returns a device pointer (NULL = out of
+ *                              memory: the call fails with VL_ERR_OOM);
+ *                              `stream` is the hipStream_t of the call
+ *                              (the model's stream) on which the memory
+ *                              will be used
+ *   release(ptr, stream, ctx)  frees a pointer alloc returned; work on
+ *                              `stream` that used it may still be pending,
+ *                              so the allocator must order its reuse after
+ *                              that stream's work (a caching allocator that
+ *                              reuses a block only on its own stream does)
+ * Both NULL restores the default; exactly one NULL is VL_ERR_INVALID_ARG.
+ * A pointer is always released through the allocator that produced it,
+ * also when another one was installed in between.  The functions may be
+ * called from any host thread the library runs on (serving workers
+ * included) and must be thread-safe.  Installing is thread-safe; buffers
+ * already allocated are unaffected. */
+typedef void* (*vl_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*vl_free_fn)(void* ptr, void* stream, void* ctx);
+vl_status vl_set_allocator(vl_alloc_fn alloc, vl_free_fn release, void* ctx);
+
 void vl_default_opts(vl_opts* o);
 const char* vl_status_string(vl_status s);
 /* Message of the most recent failing call on this host thread. */

@@ -278,6 +278,7 @@ const char* vl_last_error(void) { return vl::g_last_error.c_str(); }
 vl_status vl_build_vecchia(const double* coords, int64_t n, int m, int cov,
                            const double* theta_host, void* hip_stream, int want_deriv,
                            vl_model** out) {
+  vl::CallStream cs(static_cast<hipStream_t>(hip_stream));
   return vl::guarded([&]() -> vl::Status {
     Model* M = nullptr;
     VL_TRY(vl::build(coords, n, m, cov, theta_host, hip_stream, want_deriv, &M));
@@ -287,6 +288,7 @@ vl_status vl_build_vecchia(const double* coords, int64_t n, int m, int cov,
 }
 
 vl_status vl_set_theta(vl_model* h, const double* theta_host) {
+  vl::CallStream cs(h ? h->stream : nullptr);
   return vl::guarded([&]() -> vl::Status {
     if (!h) return vl::Status::invalid("null handle");
     VL_TRY(vl::check_theta(theta_host));
@@ -301,6 +303,7 @@ vl_status vl_set_theta(vl_model* h, const double* theta_host) {
 vl_status vl_find_mode(vl_model* h, const double* y, const double* F, int lik,
                        const double* aux_host, const vl_opts* o, double* mode_out,
                        vl_stats* st) {
+  vl::CallStream cs(h ? h->stream : nullptr);
   return vl::guarded([&]() -> vl::Status {
     const double t0 = vl::now_ms();
     if (!h || !y) return vl::Status::invalid("null handle or y");
@@ -340,6 +343,7 @@ vl_status vl_find_mode(vl_model* h, const double* y, const double* F, int lik,
 
 vl_status vl_neg_log_marglik(vl_model* h, const vl_opts* o, double* nll_host,
                              double* grad_theta_host, vl_stats* st) {
+  vl::CallStream cs(h ? h->stream : nullptr);
   return vl::guarded([&]() -> vl::Status {
     const double t0 = vl::now_ms();
     if (!h || !nll_host) return vl::Status::invalid("null handle or output");
@@ -361,6 +365,7 @@ vl_status vl_neg_log_marglik(vl_model* h, const vl_opts* o, double* nll_host,
 
 vl_status vl_predict(vl_model* h, const double* coords_p, int64_t n_p, const double* Fp,
                      const vl_opts* o, double* mean_out, double* var_out, vl_stats* st) {
+  vl::CallStream cs(h ? h->stream : nullptr);
   return vl::guarded([&]() -> vl::Status {
     const double t0 = vl::now_ms();
     if (!h) return vl::Status::invalid("null handle");
@@ -382,6 +387,7 @@ vl_status vl_predict(vl_model* h, const double* coords_p, int64_t n_p, const dou
 }
 
 vl_status vl_export(vl_model* h, int which, void* dst, size_t bytes) {
+  vl::CallStream cs(h ? h->stream : nullptr);
   return vl::guarded([&]() -> vl::Status {
     if (!h) return vl::Status::invalid("null handle");
     return vl::do_export(*h, which, dst, bytes);
@@ -394,6 +400,7 @@ int64_t vl_export_count(vl_model* h, int which) {
 }
 
 vl_status vl_spmm(vl_model* h, int transpose, const double* X, double* Y, int t) {
+  vl::CallStream cs(h ? h->stream : nullptr);
   return vl::guarded([&]() -> vl::Status {
     if (!h || !X || !Y) return vl::Status::invalid("null argument");
     if (t < 1) return vl::Status::invalid("t must be positive");
@@ -403,6 +410,7 @@ vl_status vl_spmm(vl_model* h, int transpose, const double* X, double* Y, int t)
 }
 
 vl_status vl_trsm(vl_model* h, int transpose, const double* X, double* Y, int t) {
+  vl::CallStream cs(h ? h->stream : nullptr);
   return vl::guarded([&]() -> vl::Status {
     if (!h || !X || !Y) return vl::Status::invalid("null argument");
     if (t < 1) return vl::Status::invalid("t must be positive");
@@ -417,6 +425,7 @@ vl_status vl_trsm(vl_model* h, int transpose, const double* X, double* Y, int t)
 }
 
 vl_status vl_timing_enable(vl_model* h, int enable) {
+  vl::CallStream cs(h ? h->stream : nullptr);
   return vl::guarded([&]() -> vl::Status {
     if (!h) return vl::Status::invalid("null handle");
     VL_TRY(vl::sync_stream(h->stream));
@@ -430,6 +439,7 @@ vl_status vl_timing_enable(vl_model* h, int enable) {
 
 vl_status vl_timing_read(vl_model* h, int kind, double* total_ms, int64_t* launches,
                          double* bytes) {
+  vl::CallStream cs(h ? h->stream : nullptr);
   return vl::guarded([&]() -> vl::Status {
     if (!h || !total_ms || !launches || !bytes) return vl::Status::invalid("null argument");
     if (kind < 0 || kind >= vl::kTimeKinds) return vl::Status::invalid("unknown kind");
@@ -451,6 +461,13 @@ vl_status vl_timing_read(vl_model* h, int kind, double* total_ms, int64_t* launc
   });
 }
 
-void vl_free(vl_model* h) { vl::release(h); }
+void vl_free(vl_model* h) {
+  vl::CallStream cs(h ? h->stream : nullptr);
+  vl::release(h);
+}
+
+vl_status vl_set_allocator(vl_alloc_fn alloc, vl_free_fn release, void* ctx) {
+  return vl::guarded([&]() -> vl::Status { return vl::set_allocator(alloc, release, ctx); });
+}
 
 }  // extern "C"

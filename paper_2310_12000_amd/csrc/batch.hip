@@ -742,6 +742,7 @@ extern "C" {
 
 vl_status vl_batch_create(const vl_problem* problems, int nprob, int lik,
                           const double* aux_host, void* hip_stream, vl_batch** out) {
+  vl::CallStream cs(static_cast<hipStream_t>(hip_stream));
   try {
     if (!out) return vl::report(vl::Status::invalid("out is null"));
     *out = nullptr;
@@ -767,6 +768,7 @@ vl_status vl_batch_create(const vl_problem* problems, int nprob, int lik,
 }
 
 vl_status vl_batch_fit(vl_batch* b, const vl_opts* o, double* nll_host) {
+  vl::CallStream cs(b ? b->M.stream : nullptr);
   try {
     if (!b || !o || !nll_host) return vl::report(vl::Status::invalid("null argument"));
     if (o->num_probes < 1 || o->max_newton < 1 || o->max_cg < 1 || !(o->cg_tol > 0.0))
@@ -814,6 +816,7 @@ int vl_batch_tuned_path(vl_batch* b, int width_class) {
 
 void vl_batch_free(vl_batch* b) {
   if (!b) return;
+  vl::CallStream cs(b->M.stream);
   (void)hipStreamSynchronize(b->M.stream);
   for (void* p : b->M.owned) vl::device_free(p);
   b->M.owned.clear();

@@ -1,5 +1,6 @@
 // Small device utilities: fills, a multi-block exclusive scan, launch checks.
 #include <mutex>
+#include <unordered_map>
 
 #include "vl_internal.h"
 
@@ -17,18 +18,76 @@ Status sync_stream(hipStream_t s) {
   return Status::ok();
 }
 
+// ---- device allocation ----------------------------------------------------
+// Every device buffer of the library comes from here: the caller-installed
+// allocator (vl_set_allocator) or, by default, the stream-ordered
+// hipMallocAsync on the stream of the call in progress.  Each live pointer
+// remembers who allocated it, so that a hook installed or removed while
+// models exist never frees another allocator's memory.
+namespace {
+struct AllocOwner {
+  vl_alloc_fn a = nullptr;  // nullptr: hipMallocAsync / hipFreeAsync
+  vl_free_fn f = nullptr;
+  void* ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+AllocOwner g_hook;
+std::unordered_map<void*, AllocOwner> g_live;
+thread_local hipStream_t g_call_stream = nullptr;
+}  // namespace
+
+CallStream::CallStream(hipStream_t s) : prev_(g_call_stream) { g_call_stream = s; }
+CallStream::~CallStream() { g_call_stream = prev_; }
+
+Status set_allocator(vl_alloc_fn a, vl_free_fn f, void* ctx) {
+  if ((a == nullptr) != (f == nullptr))
+    return Status::invalid("allocator and deallocator must be given together");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_hook.a = a;
+  g_hook.f = f;
+  g_hook.ctx = ctx;
+  return Status::ok();
+}
+
 Status device_alloc(void** p, size_t bytes) {
   *p = nullptr;
-  hipError_t e = hipMalloc(p, bytes == 0 ? 1 : bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return Status::make(VL_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  if (bytes == 0) bytes = 1;
+  AllocOwner own;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    own = g_hook;
   }
+  if (own.a) {
+    *p = own.a(bytes, static_cast<void*>(g_call_stream), own.ctx);
+    if (!*p) return Status::make(VL_ERR_OOM, "the installed allocator returned NULL");
+  } else {
+    hipError_t e = hipMallocAsync(p, bytes, g_call_stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return Status::make(VL_ERR_OOM, std::string("hipMallocAsync failed: ") + hipGetErrorString(e));
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_live[*p] = own;
   return Status::ok();
 }
 
 void device_free(void* p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  AllocOwner own;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) return;  // not ours
+    own = it->second;
+    g_live.erase(it);
+  }
+  if (own.f) {
+    own.f(p, static_cast<void*>(g_call_stream), own.ctx);
+  } else {
+    (void)hipFreeAsync(p, g_call_stream);
+  }
 }
 
 Status copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t s) {

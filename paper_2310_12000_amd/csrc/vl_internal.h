@@ -48,6 +48,20 @@ Status check_launch(const char* what);
 Status sync_stream(hipStream_t s);
 Status device_alloc(void** p, size_t bytes);
 void device_free(void* p);
+Status set_allocator(vl_alloc_fn a, vl_free_fn f, void* ctx);
+
+// The stream of the entry point in progress on this host thread: default
+// allocations are ordered on it, and an installed allocator receives it.
+class CallStream {
+ public:
+  explicit CallStream(hipStream_t s);
+  ~CallStream();
+  CallStream(const CallStream&) = delete;
+  CallStream& operator=(const CallStream&) = delete;
+
+ private:
+  hipStream_t prev_;
+};
 
 // RAII device buffer for temporaries of one call.
 template <typename T>

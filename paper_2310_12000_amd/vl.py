@@ -90,6 +90,11 @@ class vl_request(ctypes.Structure):
     ]
 
 
+# void* alloc(size_t bytes, void* stream, void* ctx); void release(void* p, void* stream, void* ctx)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class VLError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{msg} (status {code})")
@@ -129,6 +134,7 @@ def lib():
     L.vl_export_count.restype = I64
     L.vl_spmm.argtypes = [P, I, P, P, I]
     L.vl_trsm.argtypes = [P, I, P, P, I]
+    L.vl_set_allocator.argtypes = [ALLOC_FN, FREE_FN, P]
     L.vl_timing_enable.argtypes = [P, I]
     L.vl_timing_read.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(I64), ctypes.POINTER(D)]
     L.vl_free.argtypes = [P]
@@ -152,7 +158,8 @@ def lib():
     L.vl_server_free.argtypes = [P]
     L.vl_server_free.restype = None
     for f in ("vl_build_vecchia", "vl_set_theta", "vl_find_mode", "vl_neg_log_marglik",
-              "vl_predict", "vl_export", "vl_spmm", "vl_trsm", "vl_timing_enable",
+              "vl_predict", "vl_export", "vl_spmm", "vl_trsm",
+              "vl_set_allocator", "vl_timing_enable",
               "vl_timing_read", "vl_batch_create", "vl_batch_fit", "vl_batch_mode",
               "vl_batch_stats", "vl_server_create", "vl_server_submit", "vl_server_wait",
               "vl_server_info"):
@@ -248,6 +255,44 @@ def vl_export(h, name, device="cuda"):
     _check(lib().vl_export(h, which, ctypes.c_void_p(out.data_ptr()) if cnt else None,
                            out.numel() * out.element_size()))
     return out
+
+
+_allocator_keep = None  # the installed callbacks must outlive their use
+
+
+def vl_set_allocator(alloc=None, release=None):
+    """Install Python callables alloc(bytes, stream) -> int device pointer
+    and release(ptr, stream) as the library's device allocator (both None:
+    the library's default, hipMallocAsync)."""
+    global _allocator_keep
+    if alloc is None and release is None:
+        _check(lib().vl_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        _allocator_keep = None
+        return
+
+    def _a(nbytes, stream, ctx):
+        try:
+            return int(alloc(int(nbytes), int(stream or 0)))
+        except Exception:  # out of memory or a failing hook: the call fails with VL_ERR_OOM
+            return None
+
+    def _f(ptr, stream, ctx):
+        release(int(ptr), int(stream or 0))
+
+    keep = (ALLOC_FN(_a), FREE_FN(_f))
+    _check(lib().vl_set_allocator(keep[0], keep[1], None))
+    _allocator_keep = keep
+
+
+def use_torch_allocator(enable=True):
+    """Back every device buffer of the library with PyTorch's caching
+    allocator (on the stream of the library call), or restore the default."""
+    if not enable:
+        vl_set_allocator(None, None)
+        return
+    vl_set_allocator(
+        lambda nbytes, stream: torch.cuda.caching_allocator_alloc(nbytes, stream=stream),
+        lambda ptr, stream: torch.cuda.caching_allocator_delete(ptr))
 
 
 def vl_spmm(h, X, Y, transpose=False):

@@ -75,3 +75,12 @@ def test_sizes_above_the_verified_limit_are_refused(L):
     assert L.vl_build_vecchia(fake, 262145, 20, 1, th, None, 0,
                               ctypes.byref(h)) == P.VL_ERR_INVALID_ARG
     assert b"verified limit" in L.vl_last_error()
+
+
+def test_allocator_hook_arguments_checked_without_device(L):
+    import paper_2310_12000_amd as P
+    alloc = P.vl.ALLOC_FN(lambda n, s, c: None)
+    # a hook needs both functions; both NULL restores the default
+    assert L.vl_set_allocator(alloc, P.vl.FREE_FN(), None) == P.VL_ERR_INVALID_ARG
+    assert L.vl_set_allocator(P.vl.ALLOC_FN(), P.vl.FREE_FN(), None) == P.VL_OK
+

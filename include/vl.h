@@ -256,6 +256,22 @@ vl_status vl_spmm(vl_model* h, int transpose, const double* X, double* Y, int t)
  * X and Y must not overlap.  Asynchronous. */
 vl_status vl_trsm(vl_model* h, int transpose, const double* X, double* Y, int t);
 
+/* vl_trsm for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results as vl_trsm, for 1 <= t <= 64 columns, with every
+ * scratch buffer of the solve (work-stream counters and abort flag of the
+ * sync-free rows, partial products and folded right-hand sides of the
+ * dense leading block) taken from one fixed 40 MiB device array per GPU,
+ * which each GPU the library runs on holds until the process ends.  It
+ * calls no allocation routine.  The caller passes inputs and outputs as
+ * for vl_trsm.  t > 64, or a model whose dense leading block would need
+ * more than the array (a VL_DENSE_ROWS above 4096 at large t), is
+ * VL_ERR_INVALID_ARG.  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (different streams or host threads) race.  Each
+ * call resets what must start at zero, so no call depends on an earlier
+ * one.  Synchronises the model's stream. */
+vl_status vl_trsm_noalloc(vl_model* h, int transpose, const double* X, double* Y, int t);
+
 /* Measurement support: while enabled, every launch of the sparse kernel
  * classes below is bracketed by HIP events on the model's stream, and the
  * algorithmic bytes of the launch (8-byte values and 4-byte indices of the

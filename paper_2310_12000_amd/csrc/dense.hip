@@ -413,20 +413,28 @@ static Status launch_apply(Model& M, const double* A, const double* V, const dou
                            double* out, int t) {
   const int K = M.dense_rows;
   const int nseg = (K + kSeg - 1) / kSeg;
-  VL_TRY(M.dense_part.reserve(static_cast<size_t>(nseg) * K * t));
+  const size_t need = static_cast<size_t>(nseg) * K * t;
+  double* part = nullptr;
+  if (M.ext) {
+    if (M.ext->part_count < need) return Status::invalid("scratch too small for the dense product");
+    part = M.ext->part;
+  } else {
+    VL_TRY(M.dense_part.reserve(need));
+    part = M.dense_part.p;
+  }
   const unsigned gx = static_cast<unsigned>((K + 63) / 64);
   if (t == 1) {
     hipLaunchKernelGGL((dense_part_kernel<1, LOWER>), dim3(gx, nseg, 1), dim3(64 * kApplyWaves),
-                       0, M.stream, K, t, A, V, rs, M.dense_part.p, nullptr, nullptr, nullptr,
+                       0, M.stream, K, t, A, V, rs, part, nullptr, nullptr, nullptr,
                        nullptr, nullptr, nullptr);
   } else {
     hipLaunchKernelGGL((dense_part_kernel<8, LOWER>), dim3(gx, nseg, (t + 7) / 8),
-                       dim3(64 * kApplyWaves), 0, M.stream, K, t, A, V, rs, M.dense_part.p,
+                       dim3(64 * kApplyWaves), 0, M.stream, K, t, A, V, rs, part,
                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
   }
   const int64_t kt = static_cast<int64_t>(K) * t;
   hipLaunchKernelGGL(dense_reduce_kernel<LOWER>, dim3(static_cast<unsigned>((kt + 255) / 256)),
-                     dim3(256), 0, M.stream, K, t, M.dense_part.p, out);
+                     dim3(256), 0, M.stream, K, t, part, out);
   return check_launch("dense apply");
 }
 
@@ -443,10 +451,18 @@ Status dense_lower(Model& M, const double* X, double* Y, int t, const double* rs
 Status dense_upper(Model& M, double* Y, int t) {
   const int K = M.dense_rows;
   TimedLaunch tl(M, kTimeHeadUpper, apply_bytes(M, t));
-  VL_TRY(M.dense_xp.reserve(static_cast<size_t>(K) * t));
+  const size_t need = static_cast<size_t>(K) * t;
+  double* xp = nullptr;
+  if (M.ext) {
+    if (M.ext->xp_count < need) return Status::invalid("scratch too small for the dense fold");
+    xp = M.ext->xp;
+  } else {
+    VL_TRY(M.dense_xp.reserve(need));
+    xp = M.dense_xp.p;
+  }
   hipLaunchKernelGGL(dense_fold_kernel, dim3((K + 3) / 4), dim3(256), 0, M.stream, K, t,
-                     M.dense_lo.p, M.head_split.p, M.bt_col.p, M.bt_val.p, Y, Y, M.dense_xp.p);
-  return launch_apply<false>(M, M.dense_gb.p, M.dense_xp.p, nullptr, Y, t);
+                     M.dense_lo.p, M.head_split.p, M.bt_col.p, M.bt_val.p, Y, Y, xp);
+  return launch_apply<false>(M, M.dense_gb.p, xp, nullptr, Y, t);
 }
 
 // Launches dense_gemm_kernel with 128-row blocks when those alone make a grid

@@ -1010,13 +1010,17 @@ static int trsm_streams(const Model& M, int blocks) {
 // Counter slots: slot k uses counter[k * kSlotInts ...] (streams and abort
 // flag).  Callers that pre-fill the output themselves must also have reset
 // the slot.
+static int* counter_slot(Model& M, int slot) {
+  return M.ext ? M.ext->counter : M.counter.p + slot * kSlotInts;
+}
+
 static Status trsm_prepare(Model& M, double* Y, int64_t count, int slot) {
-  VL_TRY(M.counter.reserve(2 * kSlotInts + 64));
+  if (!M.ext) VL_TRY(M.counter.reserve(2 * kSlotInts + 64));
   int g = static_cast<int>((count + 255) / 256);
   if (g > 4096) g = 4096;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(trsm_prefill, dim3(g), dim3(256), 0, M.stream, Y, count,
-                     M.counter.p + slot * kSlotInts);
+                     counter_slot(M, slot));
   return check_launch("trsm prefill");
 }
 
@@ -1043,7 +1047,7 @@ Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* ro
   Lanes L = Lanes::of(t);
   int g = trsm_grid(units_of(M.n - H, t));
   const int ns = trsm_streams(M, g);
-  int* cnt = M.counter.p + slot * kSlotInts;
+  int* cnt = counter_slot(M, slot);
   PollingOrder order(M);
   TimedLaunch tl(M, kTimeTrsmLower,
                  12.0 * (M.nnz - (H ? M.nnz_head_f : 0)) + 16.0 * (M.n - H) * t +
@@ -1079,7 +1083,7 @@ Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled,
     Lanes L = Lanes::of(t);
     int g = trsm_grid(units_of(M.n - H, t));
     const int ns = trsm_streams(M, g);
-    int* cnt = M.counter.p + slot * kSlotInts;
+    int* cnt = counter_slot(M, slot);
     PollingOrder order(M);
     TimedLaunch tl(M, kTimeTrsmUpper,
                    12.0 * (M.nnz - (H ? M.nnz_head_bt : 0)) + 4.0 * (M.n - H) +

@@ -317,6 +317,17 @@ struct Model {
   DevBuf<int> lrac_piv;
   DevBuf<double> rhs_blk;  // n x t right-hand sides of block solves
   DevBuf<int> counter;     // dynamic work counters of sync-free kernels
+  // Scratch supplied for the call in progress by the allocation-free entry
+  // point: while set, the solves of t <= 64 columns take their work counters
+  // and dense-product buffers from it and reserve nothing.
+  struct ExtScratch {
+    int* counter = nullptr;   // one counter slot (kSlotInts ints)
+    double* part = nullptr;   // partial products of the dense leading block
+    size_t part_count = 0;
+    double* xp = nullptr;     // folded right-hand sides of the B^T dense block
+    size_t xp_count = 0;
+  };
+  const ExtScratch* ext = nullptr;
   double* host_pin = nullptr;  // pinned host scalars (64 doubles)
   hipEvent_t poll_evt = nullptr;  // completion of this model's last polling kernel
   Timing timing;

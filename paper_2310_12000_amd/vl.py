@@ -134,6 +134,7 @@ def lib():
     L.vl_export_count.restype = I64
     L.vl_spmm.argtypes = [P, I, P, P, I]
     L.vl_trsm.argtypes = [P, I, P, P, I]
+    L.vl_trsm_noalloc.argtypes = [P, I, P, P, I]
     L.vl_set_allocator.argtypes = [ALLOC_FN, FREE_FN, P]
     L.vl_timing_enable.argtypes = [P, I]
     L.vl_timing_read.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(I64), ctypes.POINTER(D)]
@@ -158,7 +159,7 @@ def lib():
     L.vl_server_free.argtypes = [P]
     L.vl_server_free.restype = None
     for f in ("vl_build_vecchia", "vl_set_theta", "vl_find_mode", "vl_neg_log_marglik",
-              "vl_predict", "vl_export", "vl_spmm", "vl_trsm",
+              "vl_predict", "vl_export", "vl_spmm", "vl_trsm", "vl_trsm_noalloc",
               "vl_set_allocator", "vl_timing_enable",
               "vl_timing_read", "vl_batch_create", "vl_batch_fit", "vl_batch_mode",
               "vl_batch_stats", "vl_server_create", "vl_server_submit", "vl_server_wait",
@@ -293,6 +294,15 @@ def use_torch_allocator(enable=True):
     vl_set_allocator(
         lambda nbytes, stream: torch.cuda.caching_allocator_alloc(nbytes, stream=stream),
         lambda ptr, stream: torch.cuda.caching_allocator_delete(ptr))
+
+
+def vl_trsm_noalloc(h, X, Y, transpose=False):
+    """vl_trsm for at most 64 columns with no device allocation (fixed
+    per-GPU scratch)."""
+    t = 1 if X.dim() == 1 else X.shape[1]
+    _ptr(X), _ptr(Y)
+    _check(lib().vl_trsm_noalloc(h, 1 if transpose else 0, ctypes.c_void_p(X.data_ptr()),
+                                 ctypes.c_void_p(Y.data_ptr()), t))
 
 
 def vl_spmm(h, X, Y, transpose=False):

@@ -84,3 +84,7 @@ def test_allocator_hook_arguments_checked_without_device(L):
     assert L.vl_set_allocator(alloc, P.vl.FREE_FN(), None) == P.VL_ERR_INVALID_ARG
     assert L.vl_set_allocator(P.vl.ALLOC_FN(), P.vl.FREE_FN(), None) == P.VL_OK
 
+
+def test_noalloc_solve_rejects_null_arguments(L):
+    import paper_2310_12000_amd as P
+    assert L.vl_trsm_noalloc(None, 0, None, None, 1) == P.VL_ERR_INVALID_ARG

@@ -92,6 +92,17 @@ typedef struct {
                               the FP64 PCG; Newton stays FP64                  */
   int pred_tile;           /* columns per predictive-variance CG block
                               (0 = all s at once)                              */
+  const int* replay_cg_iters; /* host, nullable: fixed CG iteration counts that
+                              replace the tolerance test (replay of another
+                              run's counts, e.g. a reference implementation's):
+                              vl_find_mode: entry k for the solve of Newton
+                              iteration k; vl_neg_log_marglik: entries 0..t-1
+                              for the probe columns, entry t for the implicit
+                              gradient term's solve; vl_predict: entry c for
+                              sample column c.  Entries past replay_len, and
+                              negative entries, keep the tolerance test; the
+                              max_cg cap always applies                     */
+  int replay_len;          /* number of entries of replay_cg_iters            */
 } vl_opts;
 
 /* Per-call statistics (host struct, filled by the call that receives it). */
@@ -102,6 +113,17 @@ typedef struct {
   int cg_iters_max;        /* largest iteration count of one column            */
   int hit_cap;             /* 1 if a loop stopped at its cap                   */
   double t_ms;             /* wall time of the call                            */
+  double t_build_us;       /* wall time of the model's latest factor build
+                              (vl_build_vecchia or vl_set_theta)               */
+  double t_mode_us;        /* ... of its latest vl_find_mode                   */
+  double t_slq_us;         /* ... of its latest vl_neg_log_marglik             */
+  double t_pred_us;        /* ... of its latest vl_predict (0 = none yet)      */
+  double err_vs_fp64_est;  /* VL_MIXED block solves: relative 2-norm deviation
+                              of the FP32 preconditioner application from the
+                              FP64 one on the call's first right-hand side
+                              (the CG iterates and stopping test are FP64, so
+                              this is the perturbation the FP32 solves add to
+                              the Lanczos coefficients); 0 for FP64 calls     */
 } vl_stats;
 
 /* ---------------------------------------------------------------------- */

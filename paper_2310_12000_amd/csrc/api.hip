@@ -214,6 +214,8 @@ static Status check_opts(const vl_opts* o) {
     return Status::invalid("unknown preconditioner");
   if (o->precision != VL_FP64 && o->precision != VL_MIXED)
     return Status::invalid("unknown precision");
+  if (o->replay_len < 0 || (o->replay_len > 0 && !o->replay_cg_iters))
+    return Status::invalid("replay_len needs replay_cg_iters");
   return Status::ok();
 }
 
@@ -233,6 +235,14 @@ static vl_status guarded(F&& f) {
 static double now_ms() {
   using namespace std::chrono;
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// The model's per-phase wall times into a statistics record.
+static void fill_phases(const Model& M, vl_stats* st) {
+  st->t_build_us = M.t_build_us;
+  st->t_mode_us = M.t_mode_us;
+  st->t_slq_us = M.t_slq_us;
+  st->t_pred_us = M.t_pred_us;
 }
 
 }  // namespace vl
@@ -280,8 +290,10 @@ vl_status vl_build_vecchia(const double* coords, int64_t n, int m, int cov,
                            vl_model** out) {
   vl::CallStream cs(static_cast<hipStream_t>(hip_stream));
   return vl::guarded([&]() -> vl::Status {
+    const double t0 = vl::now_ms();
     Model* M = nullptr;
     VL_TRY(vl::build(coords, n, m, cov, theta_host, hip_stream, want_deriv, &M));
+    M->t_build_us = 1e3 * (vl::now_ms() - t0);
     *out = static_cast<vl_model*>(M);
     return vl::Status::ok();
   });
@@ -296,7 +308,10 @@ vl_status vl_set_theta(vl_model* h, const double* theta_host) {
     h->rho = theta_host[1];
     h->has_mode = false;
     h->lrac_ready = false;
-    return vl::compute_factor(*h);
+    const double t0 = vl::now_ms();
+    VL_TRY(vl::compute_factor(*h));
+    h->t_build_us = 1e3 * (vl::now_ms() - t0);
+    return vl::Status::ok();
   });
 }
 
@@ -336,6 +351,8 @@ vl_status vl_find_mode(vl_model* h, const double* y, const double* F, int lik,
       VL_TRY(vl::sync_stream(M.stream));
     }
     local.t_ms = vl::now_ms() - t0;
+    M.t_mode_us = 1e3 * local.t_ms;
+    vl::fill_phases(M, &local);
     if (st) *st = local;
     return s;
   });
@@ -352,12 +369,15 @@ vl_status vl_neg_log_marglik(vl_model* h, const vl_opts* o, double* nll_host,
       return vl::Status::invalid("lrac_rank must be in [1, 1024]");
     vl::NllInfo info;
     vl::Status s = vl::neg_log_marglik(*h, *o, nll_host, grad_theta_host, &info);
+    h->t_slq_us = 1e3 * (vl::now_ms() - t0);
     if (st) {
       std::memset(st, 0, sizeof(*st));
       st->cg_iters_max = info.cg_iters_max;
       st->cg_iters_total = info.cg_iters_max;
       st->hit_cap = (s.code == VL_ERR_NO_CONVERGENCE);
       st->t_ms = vl::now_ms() - t0;
+      vl::fill_phases(*h, st);
+      st->err_vs_fp64_est = o->precision == VL_MIXED ? h->last_f32_dev : 0.0;
     }
     return s;
   });
@@ -376,11 +396,14 @@ vl_status vl_predict(vl_model* h, const double* coords_p, int64_t n_p, const dou
     VL_TRY(vl::check_opts(o));
     vl::PredInfo info;
     vl::Status s = vl::predict(*h, coords_p, n_p, Fp, *o, mean_out, var_out, &info);
+    h->t_pred_us = 1e3 * (vl::now_ms() - t0);
     if (st) {
       std::memset(st, 0, sizeof(*st));
       st->cg_iters_max = info.cg_iters_max;
       st->hit_cap = (s.code == VL_ERR_NO_CONVERGENCE);
       st->t_ms = vl::now_ms() - t0;
+      vl::fill_phases(*h, st);
+      st->err_vs_fp64_est = (o->precision == VL_MIXED && var_out) ? h->last_f32_dev : 0.0;
     }
     return s;
   });

@@ -222,13 +222,15 @@ Status find_mode(Model& M, const vl_opts& o, vl_stats* st) {
   for (; it < o.max_newton;) {
     VL_TRY(lik_rows(M, M.mode.p, M.g.p, M.W.p, M.vec_a.p, M.vec_b.p, nullptr, nullptr));
     VL_TRY(copy_d2d(M.mode_old.p, M.mode.p, sizeof(double) * n, M.stream));
+    std::vector<int> rbuf;
+    const int* forced = replay_slice(o, it, 1, rbuf);  // Newton iteration `it`
     if (lrac) {
       // eq. (pcls2): (Sigma~ + W^{-1}) (W b') = Sigma~ (W b + g)
-      VL_TRY(lrac_newton_solve(M, o, M.vec_a.p, M.mode.p));
+      VL_TRY(lrac_newton_solve(M, o, M.vec_a.p, M.mode.p, forced));
     } else {
       // eq. (pcls1): (W + Sigma~^{-1}) b' = W b + g with P_VADU
       CgOps ops = vadu_ops(M.W.p, M.vec_b.p);
-      VL_TRY(cg_solve(M, M.cg1, ops, 1, M.vec_a.p, o.cg_tol, o.max_cg, false));
+      VL_TRY(cg_solve(M, M.cg1, ops, 1, M.vec_a.p, o.cg_tol, o.max_cg, false, forced));
       VL_TRY(copy_d2d(M.mode.p, M.cg1.U.p, sizeof(double) * n, M.stream));
     }
     const int ci = M.cg1.host_iters[0];
@@ -452,7 +454,9 @@ static Status grad_theta(Model& M, const vl_opts& o, const double* sdiag, double
   VL_TRY(sync_stream(M.stream));
   // w = A^{-1} dL/db  (implicit derivative of the mode, eq. grad_mode_par)
   CgOps ops = vadu_ops(M.W.p, sdiag);
-  VL_TRY(cg_solve(M, M.cg1, ops, 1, M.vec_c.p, o.cg_tol, o.max_cg, false));
+  std::vector<int> rbuf;
+  VL_TRY(cg_solve(M, M.cg1, ops, 1, M.vec_c.p, o.cg_tol, o.max_cg, false,
+                  replay_slice(o, t, 1, rbuf)));  // entry t: after the probe columns
   info->grad_cg_iters = M.cg1.host_iters[0];
   ChunkGrid g1 = ChunkGrid::of(n, 1);
   VL_TRY(M.red_part.reserve(static_cast<size_t>(g1.nchunk) * 8 + 64));
@@ -498,7 +502,8 @@ Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, Nl
     // eq. (logdetsplit2): log det(Sigma~ W + I) = sum log W + log det P_LRAC
     // + log det(P^{-1} (Sigma~ + W^{-1})), probes z = L eps_k + W^{-1/2} eps_n
     VL_TRY(lrac_build(M, o.lrac_rank));
-    VL_TRY(lrac_slq(M, o, &logdet_lrac));
+    std::vector<int> rbuf;
+    VL_TRY(lrac_slq(M, o, &logdet_lrac, replay_slice(o, 0, t, rbuf)));
   } else {
     VL_TRY(M.rhs_blk.reserve(static_cast<size_t>(n) * t));
     // z_i = B^T ((W + D^{-1})^{1/2} o eps_i), Cov(z_i) = P_VADU; the CG
@@ -510,7 +515,14 @@ Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, Nl
     // mixed form: FP32 preconditioner solves inside the FP64 block PCG
     CgOps ops = o.precision == VL_MIXED ? vadu_ops_mixed(M.W.p, M.vec_b.p)
                                         : vadu_ops(M.W.p, M.vec_b.p);
-    VL_TRY(cg_solve(M, M.cg, ops, t, M.rhs_blk.p, o.cg_tol, o.max_cg, grad != nullptr));
+    // mixed form (FP32 solves for t > 64): the FP32 preconditioner's
+    // deviation from FP64 on the first probe, before the CG overwrites Z/H
+    M.last_f32_dev = 0.0;
+    if (o.precision == VL_MIXED && t > 64)
+      VL_TRY(precond_f32_deviation(M, M.vec_b.p, M.rhs_blk.p, t, &M.last_f32_dev));
+    std::vector<int> rbuf;
+    VL_TRY(cg_solve(M, M.cg, ops, t, M.rhs_blk.p, o.cg_tol, o.max_cg, grad != nullptr,
+                    replay_slice(o, 0, t, rbuf)));
   }
   M.last_block_iters = M.cg.host_iters;
   VL_TRY(M.red_out.reserve(2 * t + 64));
@@ -669,7 +681,14 @@ Status predict(Model& M, const double* coords_p, int64_t np, const double* Fp,
     VL_TRY(M.cg.H.reserve(static_cast<size_t>(n) * tt));
     VL_TRY(spmm_bt_probe(M, M.rhs_blk.p, tt, M.vec_c.p, o.seed, kTagPredZ2, c0, 1, M.vec_a.p,
                          kTagPredZ1, 1, M.cg.Z.p, M.cg.H.p));
-    VL_TRY(cg_solve(M, M.cg, ops, tt, M.rhs_blk.p, o.pred_cg_tol, o.max_cg, false));
+    if (c0 == 0) {
+      M.last_f32_dev = 0.0;
+      if (o.precision == VL_MIXED && tt > 64)
+        VL_TRY(precond_f32_deviation(M, M.vec_b.p, M.rhs_blk.p, tt, &M.last_f32_dev));
+    }
+    std::vector<int> rbuf;
+    VL_TRY(cg_solve(M, M.cg, ops, tt, M.rhs_blk.p, o.pred_cg_tol, o.max_cg, false,
+                    replay_slice(o, c0, tt, rbuf)));
     for (int v : M.cg.host_iters) {
       cg_max = v > cg_max ? v : cg_max;
       M.last_block_iters.push_back(v);

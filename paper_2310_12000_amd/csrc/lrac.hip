@@ -402,14 +402,15 @@ CgOps lrac_ops(const double* W) {
 }
 
 // One Newton step of eq. (pcls2): (Sigma~ + W^{-1}) (W b') = Sigma~ rhs.
-Status lrac_newton_solve(Model& M, const vl_opts& o, const double* rhs, double* b_out) {
+Status lrac_newton_solve(Model& M, const vl_opts& o, const double* rhs, double* b_out,
+                         const int* forced) {
   const int64_t n = M.n;
   VL_TRY(M.vec_d.reserve(n));
   VL_TRY(M.vec_e.reserve(n));
   VL_TRY(lrac_factor(M, M.W.p));
   VL_TRY(sigma_apply(M, rhs, M.vec_d.p, M.vec_e.p, 1, nullptr));
   CgOps ops = lrac_ops(M.W.p);
-  VL_TRY(cg_solve(M, M.cg1, ops, 1, M.vec_d.p, o.cg_tol, o.max_cg, false));
+  VL_TRY(cg_solve(M, M.cg1, ops, 1, M.vec_d.p, o.cg_tol, o.max_cg, false, forced));
   hipLaunchKernelGGL(div_kernel, dim3(blocks_for(n)), dim3(256), 0, M.stream, n, M.cg1.U.p,
                      M.W.p, b_out);
   return check_launch("lrac newton");
@@ -417,7 +418,7 @@ Status lrac_newton_solve(Model& M, const vl_opts& o, const double* rhs, double* 
 
 // SLQ with P_LRAC: probes z = L eps_k + W^{-1/2} eps_n, CG on Sigma~ + W^{-1};
 // returns log det M (= sum log W + log det P) on the host.
-Status lrac_slq(Model& M, const vl_opts& o, double* logdet_fixed) {
+Status lrac_slq(Model& M, const vl_opts& o, double* logdet_fixed, const int* forced) {
   const int64_t n = M.n;
   const int t = o.num_probes;
   const int K = M.lrac_K;
@@ -436,7 +437,7 @@ Status lrac_slq(Model& M, const vl_opts& o, double* logdet_fixed) {
   VL_HIP(hipMemcpyAsync(&ld, M.lrac_M.p + K * K, sizeof(double), hipMemcpyDeviceToHost,
                         M.stream));
   CgOps ops = lrac_ops(M.W.p);
-  VL_TRY(cg_solve(M, M.cg, ops, t, M.rhs_blk.p, o.cg_tol, o.max_cg, false));
+  VL_TRY(cg_solve(M, M.cg, ops, t, M.rhs_blk.p, o.cg_tol, o.max_cg, false, forced));
   *logdet_fixed = ld;
   return Status::ok();
 }

@@ -279,6 +279,48 @@ static Status lower_f32(Model& M, const float* X, float* Y, double* Yd, int t,
 
 CgOps vadu_ops(const double* W, const double* sdiag);
 
+__global__ void column_kernel(int64_t n, int t, const double* __restrict__ X,
+                              double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = X[i * t];
+}
+
+// Relative 2-norm deviation of the FP32 preconditioner application (the
+// level-scheduled FP32 solves of the mixed form) from the FP64 one on the
+// first column of X (n x t): z = B^{-1} (sdiag o B^{-T} x) both ways.
+Status precond_f32_deviation(Model& M, const double* sdiag, const double* X, int t,
+                             double* dev) {
+  const int64_t n = M.n;
+  VL_TRY(ensure_f32_values(M));
+  VL_TRY(M.mx_chk.reserve(static_cast<size_t>(4 * n)));
+  double* x = M.mx_chk.p;
+  double* z64 = x + n;
+  double* z32 = z64 + n;
+  float* f1 = reinterpret_cast<float*>(z32 + n);
+  float* f2 = f1 + n;
+  const int tb = 256;
+  hipLaunchKernelGGL(column_kernel, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, M.stream,
+                     n, t, X, x);
+  VL_TRY(check_launch("column"));
+  VL_TRY(M.vec_d.reserve(n));
+  VL_TRY(trsm_bt_slot(M, x, M.vec_d.p, 1, false, 0));
+  VL_TRY(trsm_b_slot(M, M.vec_d.p, z64, 1, sdiag, false, 1));
+  VL_TRY(upper_f32(M, x, f1, 1));
+  VL_TRY(lower_f32(M, f1, f2, z32, 1, sdiag));
+  std::vector<double> a(n), b(n);
+  VL_HIP(hipMemcpyAsync(a.data(), z64, sizeof(double) * n, hipMemcpyDeviceToHost, M.stream));
+  VL_HIP(hipMemcpyAsync(b.data(), z32, sizeof(double) * n, hipMemcpyDeviceToHost, M.stream));
+  VL_TRY(sync_stream(M.stream));
+  VL_TRY(read_status(M));
+  double num = 0.0, den = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    num += (b[i] - a[i]) * (b[i] - a[i]);
+    den += a[i] * a[i];
+  }
+  *dev = den > 0.0 ? std::sqrt(num / den) : 0.0;
+  return Status::ok();
+}
+
 CgOps vadu_ops_mixed(const double* W, const double* sdiag) {
   CgOps ops = vadu_ops(W, sdiag);  // the FP64 operator
   const auto fp64_precond = ops.precond;

@@ -193,6 +193,8 @@ vl_status vl_server_create(int slots, double hbm_budget_bytes, const vl_opts* o,
   S->slots = slots;
   S->budget = hbm_budget_bytes;
   S->opts = *o;
+  S->opts.replay_cg_iters = nullptr;  // requests run with their own tolerances
+  S->opts.replay_len = 0;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     delete S;

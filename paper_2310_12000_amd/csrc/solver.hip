@@ -125,13 +125,16 @@ __global__ __launch_bounds__(256) void dot_kernel(ChunkGrid g, const T* __restri
 }
 
 // rz = r0z0 = sum of partials, active = 1, iters = 0 (one wave per column)
+// forced (optional, t entries): fixed iteration counts replacing the
+// tolerance test where >= 0 (replay of another run's counts).
 __global__ __launch_bounds__(256) void cg_start_kernel(int t, int nchunk,
                                                        const double* __restrict__ part,
                                                        double* __restrict__ rz,
                                                        double* __restrict__ r0z0,
                                                        int* __restrict__ active,
                                                        int* __restrict__ iters,
-                                                       int* __restrict__ num_active) {
+                                                       int* __restrict__ num_active,
+                                                       const int* __restrict__ forced) {
   if (blockIdx.x == 0 && threadIdx.x == 0) num_active[0] = t;
   const int c = wave_col();
   if (c >= t) return;
@@ -139,7 +142,9 @@ __global__ __launch_bounds__(256) void cg_start_kernel(int t, int nchunk,
   if ((threadIdx.x & 63) != 0) return;
   rz[c] = s;
   r0z0[c] = s;
-  active[c] = (s > 0.0) ? 1 : 0;  // a zero right-hand side is already solved
+  const int f = forced ? forced[c] : -1;
+  // a zero right-hand side is already solved; a replayed count of 0 as well
+  active[c] = (f >= 0) ? (f > 0 ? 1 : 0) : ((s > 0.0) ? 1 : 0);
   iters[c] = 0;
 }
 
@@ -209,7 +214,8 @@ __global__ __launch_bounds__(256) void cg_beta_kernel(int t, int nchunk,
                                                       int* __restrict__ iters,
                                                       double* __restrict__ hist_b,
                                                       int* __restrict__ num_active,
-                                                      int* __restrict__ status) {
+                                                      int* __restrict__ status,
+                                                      const int* __restrict__ forced) {
   const int c = wave_col();
   if (c >= t) return;
   const bool act = active[c] != 0;
@@ -227,7 +233,9 @@ __global__ __launch_bounds__(256) void cg_beta_kernel(int t, int nchunk,
     rz[c] = rzn;
     iters[c] = it + 1;
     if (!isfinite(rr) || !isfinite(b)) raise_error(status, kErrNonfinite);
-    if (sqrt(rr) < tol || it + 1 >= max_iter || !isfinite(rr)) {
+    const int f = forced ? forced[c] : -1;
+    const bool done = (f >= 0) ? (it + 1 >= f) : (sqrt(rr) < tol);
+    if (done || it + 1 >= max_iter || !isfinite(rr)) {
       active[c] = 0;
     } else {
       atomicAdd(num_active, 1);
@@ -292,11 +300,18 @@ static T* blk(DevBuf<double>& b) {
 
 template <typename T, class Ops>
 static Status cg_run(Model& M, CgState& S, const Ops& ops, int t, const T* rhs, double tol,
-                     int max_iter, bool keep_z0, bool sentinel_fill) {
+                     int max_iter, bool keep_z0, bool sentinel_fill, const int* forced_host) {
   if (t <= 0) return Status::invalid("t must be positive");
   if (max_iter < 1) max_iter = 1;
   VL_TRY(cg_reserve(M, S, t, max_iter, keep_z0));
   hipStream_t s = M.stream;
+  const int* forced = nullptr;
+  if (forced_host) {
+    VL_TRY(S.forced.reserve(t));
+    VL_HIP(hipMemcpyAsync(S.forced.p, forced_host, sizeof(int) * t, hipMemcpyHostToDevice, s));
+    VL_TRY(sync_stream(s));  // the host array may go away after the call
+    forced = S.forced.p;
+  }
   ChunkGrid g = ChunkGrid::of(M.n, t);
   const dim3 cg_grid = chunk_dims(g);
   int* cnt = sentinel_fill ? M.counter.p : nullptr;
@@ -310,7 +325,7 @@ static Status cg_run(Model& M, CgState& S, const Ops& ops, int t, const T* rhs, 
   hipLaunchKernelGGL(cg_init2_kernel<T>, cg_grid, dim3(256), 0, s, g, R, Z, H,
                      keep_z0 ? blk<T>(S.Z0) : nullptr, S.part_a.p);
   hipLaunchKernelGGL(cg_start_kernel, dim3(col_blocks(t)), dim3(256), 0, s, t, g.nchunk,
-                     S.part_a.p, S.rz.p, S.r0z0.p, S.active.p, S.iters.p, S.num_active.p);
+                     S.part_a.p, S.rz.p, S.r0z0.p, S.active.p, S.iters.p, S.num_active.p, forced);
   VL_TRY(check_launch("cg start"));
   for (int it = 0; it < max_iter; ++it) {
     VL_TRY(ops.apply(M, H, V, Tmp, t));
@@ -324,7 +339,7 @@ static Status cg_run(Model& M, CgState& S, const Ops& ops, int t, const T* rhs, 
     hipLaunchKernelGGL(dot_kernel<T>, cg_grid, dim3(256), 0, s, g, R, Z, S.part_a.p);
     hipLaunchKernelGGL(cg_beta_kernel, dim3(col_blocks(t)), dim3(256), 0, s, t, g.nchunk,
                        S.part_a.p, S.part_b.p, tol, max_iter, S.rz.p, S.beta.p, S.active.p,
-                       S.iters.p, S.hist_b.p, S.num_active.p, M.status);
+                       S.iters.p, S.hist_b.p, S.num_active.p, M.status, forced);
     hipLaunchKernelGGL(cg_update_h_kernel<T>, cg_grid, dim3(256), 0, s, g, S.beta.p, S.active.p,
                        Z, H);
     VL_TRY(check_launch("cg iteration"));
@@ -340,9 +355,18 @@ static Status cg_run(Model& M, CgState& S, const Ops& ops, int t, const T* rhs, 
 }
 
 Status cg_solve(Model& M, CgState& S, const CgOps& ops, int t, const double* rhs, double tol,
-                int max_iter, bool keep_z0) {
+                int max_iter, bool keep_z0, const int* forced_host) {
   const bool fill = ops.needs_fill ? ops.needs_fill(M, t) : true;
-  return cg_run<double>(M, S, ops, t, rhs, tol, max_iter, keep_z0, fill);
+  return cg_run<double>(M, S, ops, t, rhs, tol, max_iter, keep_z0, fill, forced_host);
+}
+
+// Replayed iteration counts of columns c0..c0+t-1 of a solve (host, -1 = the
+// tolerance test), or nullptr when none of them is replayed.
+const int* replay_slice(const vl_opts& o, int c0, int t, std::vector<int>& buf) {
+  if (!o.replay_cg_iters || o.replay_len <= c0) return nullptr;
+  buf.assign(t, -1);
+  for (int c = 0; c < t && c0 + c < o.replay_len; ++c) buf[c] = o.replay_cg_iters[c0 + c];
+  return buf.data();
 }
 
 Status dot_cols(Model& M, const double* X, const double* Y, int t, double* part, double* out) {

@@ -145,6 +145,7 @@ struct CgState {
   DevBuf<double> hist_a, hist_b;              // lmax x t
   DevBuf<double> tri;                         // 3 lmax x t (tridiagonal work)
   DevBuf<int> active, iters;                  // t each
+  DevBuf<int> forced;                         // t replayed iteration counts
   DevBuf<int> num_active;                     // 1
   DevBuf<double> part_a, part_b;              // nchunk x t partial sums
   std::vector<int> host_iters;
@@ -289,6 +290,13 @@ struct Model {
   int lik = 0;
   double aux = 0.0;
   DevBuf<double> y, F, mode, W, g, mode_old;
+
+  // wall time (us) of the latest factor build, mode, likelihood and
+  // prediction call, and the FP32 preconditioner deviation of the latest
+  // mixed-precision block solve
+  double t_build_us = 0, t_mode_us = 0, t_slq_us = 0, t_pred_us = 0;
+  double last_f32_dev = 0;
+  DevBuf<double> mx_chk;  // 3 n FP64 + 2 n FP32: the deviation check's vectors
 
   // diagnostics
   DevBuf<int> status_buf;

@@ -26,8 +26,9 @@ struct PredInfo {
 // LRAC (lrac.hip)
 Status lrac_build(Model& M, int k);
 Status lrac_factor(Model& M, const double* W);
-Status lrac_newton_solve(Model& M, const vl_opts& o, const double* rhs, double* b_out);
-Status lrac_slq(Model& M, const vl_opts& o, double* logdet_fixed);
+Status lrac_newton_solve(Model& M, const vl_opts& o, const double* rhs, double* b_out,
+                         const int* forced);
+Status lrac_slq(Model& M, const vl_opts& o, double* logdet_fixed, const int* forced);
 
 Status lik_rows(Model& M, const double* b, double* g, double* W, double* rhs, double* s,
                 double* sq, double* dW);

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <functional>
+#include <vector>
 
 #include "vl_internal.h"
 
@@ -171,11 +172,15 @@ struct CgOps {
 };
 
 Status cg_solve(Model& M, CgState& S, const CgOps& ops, int t, const double* rhs, double tol,
-                int max_iter, bool keep_z0);
+                int max_iter, bool keep_z0, const int* forced_host = nullptr);
+const int* replay_slice(const vl_opts& o, int c0, int t, std::vector<int>& buf);
 
 // Mixed-precision form (mixed.hip): the VADU operator in FP64 and the
 // preconditioner solves in FP32 (FP64 sums).
 CgOps vadu_ops_mixed(const double* W, const double* sdiag);
+// Relative deviation of the FP32 preconditioner from the FP64 one on the first
+// column of X (n x t), for the mixed form's error estimate.
+Status precond_f32_deviation(Model& M, const double* sdiag, const double* X, int t, double* dev);
 Status to_f32(Model& M, const double* x, float* y, int64_t count);
 // Xh = X - (tail entries of the head rows of B^T) applied to the FP32 block Y
 // (sparse.hip; the fold stage of the level-scheduled B^T solve).

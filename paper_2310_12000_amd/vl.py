@@ -58,14 +58,28 @@ class vl_opts(ctypes.Structure):
         ("num_pred_samples", ctypes.c_int), ("seed", ctypes.c_uint64),
         ("precond", ctypes.c_int), ("lrac_rank", ctypes.c_int),
         ("precision", ctypes.c_int), ("pred_tile", ctypes.c_int),
+        ("replay_cg_iters", ctypes.POINTER(ctypes.c_int)), ("replay_len", ctypes.c_int),
     ]
+
+    def set_replay(self, counts):
+        """Fix the CG iteration counts (see vl_opts.replay_cg_iters); None clears."""
+        if counts is None:
+            self._replay = None
+            self.replay_cg_iters = None
+            self.replay_len = 0
+            return
+        self._replay = (ctypes.c_int * len(counts))(*[int(c) for c in counts])
+        self.replay_cg_iters = ctypes.cast(self._replay, ctypes.POINTER(ctypes.c_int))
+        self.replay_len = len(counts)
 
 
 class vl_stats(ctypes.Structure):
     _fields_ = [
         ("newton_iters", ctypes.c_int), ("cg_iters_total", ctypes.c_int),
         ("cg_iters_max", ctypes.c_int), ("hit_cap", ctypes.c_int),
-        ("t_ms", ctypes.c_double),
+        ("t_ms", ctypes.c_double), ("t_build_us", ctypes.c_double),
+        ("t_mode_us", ctypes.c_double), ("t_slq_us", ctypes.c_double),
+        ("t_pred_us", ctypes.c_double), ("err_vs_fp64_est", ctypes.c_double),
     ]
 
     def as_dict(self):

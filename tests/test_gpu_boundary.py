@@ -78,3 +78,89 @@ def test_model_memory_comes_from_the_installed_allocator(P):
     assert nll == nll0
     assert np.array_equal(mode, mode0)
     assert np.array_equal(mean, mean0) and np.array_equal(var, var0)
+
+
+@pytest.fixture(scope="module")
+def small():
+    from oracle import laplace as OL
+    w = synth.make(None, seed=21, n=1500, m=10, kind=synth.COV_EXPONENTIAL, sigma2=1.0,
+                   rho=0.1, lik=synth.LIK_BERNOULLI_LOGIT, F=0.0, n_pred=200)
+    model = OL.Model(w["coords"], w["m"], w["kind"], (w["sigma2"], w["rho"]))
+    return w, model
+
+
+def test_replayed_cg_counts_match_the_oracle(P, small):
+    """vl_opts.replay_cg_iters fixes every CG count; the oracle replaying the
+    same counts gives the same results (relative 1e-9)."""
+    from oracle import laplace as OL
+    from tests.gpu_common import rel_err
+    w, model = small
+    # tight tolerances: a CG iterate further from convergence carries the
+    # rounding of the preconditioner (here B^{-1} applied as an explicit dense
+    # inverse, against substitution in the oracle) at up to 1e-8 relative
+    o = OL.Opts(cg_tol=1e-8, pred_cg_tol=1e-8, num_probes=8, num_pred_samples=8, seed=4)
+    go = P.vl_default_opts(cg_tol=o.cg_tol, pred_cg_tol=o.pred_cg_tol, num_probes=8,
+                           num_pred_samples=8, seed=4, newton_tol=o.newton_tol)
+    g = P.VecchiaLaplace(dev(w["coords"]), w["m"], w["kind"], (w["sigma2"], w["rho"]))
+    g.find_mode(dev(w["y"]), dev(w["F"]), w["lik"], None, go)
+    counts = host(g.export("newton_cg_iters")).tolist()
+    # Newton: two CG iterations fewer in every solve than the tolerance
+    # gives (iterations past convergence only add steps of rounding-level
+    # residuals, whose direction differs between any two implementations)
+    forced = [max(1, c - 2) for c in counts]
+    say(f"case: replay newton cg {counts} -> {forced}")
+    go.set_replay(forced)
+    mode, _ = g.find_mode(dev(w["y"]), dev(w["F"]), w["lik"], None, go)
+    got = host(g.export("newton_cg_iters")).tolist()
+    assert got[:len(forced)] == forced[:len(got)]
+    b, W, _ = OL.find_mode(model, w["y"], w["F"], w["lik"], None, o,
+                           replay={"newton_iters": len(got), "cg_iters": got,
+                                   "halvings": host(g.export("newton_halvings")).tolist()})
+    say(f"replayed mode: rel {rel_err(host(mode), b):.2e}")
+    assert rel_err(host(mode), b) < 1e-9
+    # SLQ probes and prediction samples: two iterations fewer than the
+    # tolerance gives in some columns
+    go.set_replay(None)
+    g.neg_log_marglik(go)
+    base = host(g.export("block_iters")).tolist()
+    probes = [max(1, c - 2) if k % 2 == 0 else c for k, c in enumerate(base)]
+    go.set_replay(probes)
+    nll, _, _ = g.neg_log_marglik(go)
+    assert host(g.export("block_iters")).tolist() == probes
+    ref, _ = OL.neg_log_marglik(model, w["y"], w["F"], w["lik"], None, b, o, replay_cg=probes)
+    say(f"replayed probe counts {probes}: nll rel {abs(nll - ref) / abs(ref):.2e}")
+    assert abs(nll - ref) < 1e-9 * abs(ref)
+    go.set_replay(None)
+    g.predict(dev(w["coords_pred"]), dev(w["Fp"]), go)
+    base = host(g.export("block_iters")).tolist()
+    # one iteration fewer in the first three columns; entries past
+    # replay_len keep the tolerance test
+    head = [max(1, c - 1) for c in base[:3]]
+    go.set_replay(head)
+    mean, var, _ = g.predict(dev(w["coords_pred"]), dev(w["Fp"]), go)
+    it = host(g.export("block_iters")).tolist()
+    assert it[:3] == head
+    _, var_o, _ = OL.predict(model, w["coords_pred"], w["Fp"], b, W, o, replay_cg=it)
+    say(f"replayed prediction counts {it}: variance rel {rel_err(host(var), var_o):.2e}")
+    assert rel_err(host(var), var_o) < 1e-9
+    go.set_replay(None)
+    g.close()
+
+
+def test_stats_report_phase_times_and_mixed_error(P, small):
+    w, _ = small
+    go = P.vl_default_opts(cg_tol=1e-6, pred_cg_tol=1e-6, num_probes=8, num_pred_samples=96,
+                           seed=4)
+    g = P.VecchiaLaplace(dev(w["coords"]), w["m"], w["kind"], (w["sigma2"], w["rho"]))
+    _, st = g.find_mode(dev(w["y"]), dev(w["F"]), w["lik"], None, go)
+    assert st.t_build_us > 0 and st.t_mode_us > 0 and st.t_slq_us == 0
+    _, _, st = g.neg_log_marglik(go)
+    assert st.t_slq_us > 0 and st.err_vs_fp64_est == 0.0
+    _, _, st = g.predict(dev(w["coords_pred"]), dev(w["Fp"]), go)
+    assert st.t_pred_us > 0 and st.err_vs_fp64_est == 0.0
+    go.precision = P.VL_MIXED
+    _, _, st = g.predict(dev(w["coords_pred"]), dev(w["Fp"]), go)
+    say(f"mixed prediction (96 samples): FP32 preconditioner deviation {st.err_vs_fp64_est:.2e}")
+    # FP32 solves of the 96-column block: rounding-level deviation
+    assert 0.0 < st.err_vs_fp64_est < 1e-4
+    g.close()

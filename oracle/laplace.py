@@ -404,12 +404,14 @@ def find_mode(model, y, F, lik, aux, opts, replay=None, L=None):
 # SLQ negative log-marginal likelihood, eq. (VLA_loss)
 # ----------------------------------------------------------------------------
 def neg_log_marglik(model, y, F, lik, aux, b, opts, replay_cg=None, L=None,
-                    want_grad=False, replay_grad_cg=None):
+                    want_grad=False, replay_grad_cg=None, col0=0):
     """L^VLA = -log p(y|mu*) + b*^T Sigma~^{-1} b* / 2 + log det(Sigma~ W + I)/2.
 
     VADU: log det = sum log D + sum log(W + 1/D) + SLQ term (eq. logdetsplit,
     log det P_VADU = log det(W + D^{-1})).
     LRAC: log det = sum log W + log det P_LRAC + SLQ term (eq. logdetsplit2).
+    The probes are the counter-based columns col0 .. col0 + num_probes - 1
+    (col0 > 0 evaluates a slice of a larger probe set; the VADU probes only).
     Returns (nll, info) with info holding the pieces, the CG iteration counts
     and (want_grad, VADU only) the theta-gradient."""
     n = model.n
@@ -417,7 +419,9 @@ def neg_log_marglik(model, y, F, lik, aux, b, opts, replay_cg=None, L=None,
     mu = F + b
     W = lik_W(lik, y, mu, aux)
     t = opts.num_probes
-    eps = _rng.rademacher(opts.seed, _rng.TAG_SLQ, n, t)
+    if col0 and opts.precond != PRECOND_VADU:
+        raise ValueError("col0 applies to the VADU probes")
+    eps = _rng.rademacher(opts.seed, _rng.TAG_SLQ, n, t, col0=col0)
     if opts.precond == PRECOND_VADU:
         apply_A, apply_Pinv = vadu_ops(model, W)
         Z = model.Bt @ (np.sqrt(W + model.Dinv)[:, None] * eps)
@@ -543,14 +547,16 @@ def _grad_theta_vadu(model, y, F, lik, aux, b, W, res, opts, replay_grad_cg):
 # prediction, eq. (latentpostpredictive) and Alg. simAlgo
 # ----------------------------------------------------------------------------
 def predict(model, coords_p, Fp, b, W, opts, replay_cg=None, chunk=256,
-            want_var=True):
+            want_var=True, col0=0):
     """Predictive latent means and simulated variances at coords_p.
 
     omega_p = F_p + A_p b*  (B_p = I, B_po = -A_p);
     diag Omega_p ~= D_p + (1/s) sum_i (A_p u_i)^2,  u_i = (W + Sigma~^{-1})^{-1}
     z3_i,  z3_i = W^{1/2} z1_i + B^T D^{-1/2} z2_i  (Alg. simAlgo).
     Sample columns are independent; they are processed in chunks of `chunk`
-    columns, which does not change any column's arithmetic."""
+    columns, which does not change any column's arithmetic.  The samples are
+    the counter-based columns col0 .. col0 + s - 1 (col0 > 0: a slice of a
+    larger sample set; info["acc"] holds its unnormalised sum of squares)."""
     coords_p = np.asarray(coords_p, dtype=np.float64)
     npred = coords_p.shape[0]
     nbr_p = _vec.pred_neighbours(model.coords, coords_p, model.m)
@@ -568,8 +574,8 @@ def predict(model, coords_p, Fp, b, W, opts, replay_cg=None, chunk=256,
     iters = np.zeros(s, dtype=np.int64)
     for c0 in range(0, s, chunk):
         c1 = min(s, c0 + chunk)
-        z1 = _gaussian_cols(opts.seed, _rng.TAG_PRED_Z1, n, c0, c1)
-        z2 = _gaussian_cols(opts.seed, _rng.TAG_PRED_Z2, n, c0, c1)
+        z1 = _gaussian_cols(opts.seed, _rng.TAG_PRED_Z1, n, col0 + c0, col0 + c1)
+        z2 = _gaussian_cols(opts.seed, _rng.TAG_PRED_Z2, n, col0 + c0, col0 + c1)
         z3 = np.sqrt(W)[:, None] * z1 + model.Bt @ (np.sqrt(model.Dinv)[:, None] * z2)
         forced = None if replay_cg is None else replay_cg[c0:c1]
         res = pcg(apply_A, apply_Pinv, z3, opts.pred_cg_tol, opts.max_cg, forced)
@@ -578,6 +584,7 @@ def predict(model, coords_p, Fp, b, W, opts, replay_cg=None, chunk=256,
         iters[c0:c1] = res.iters
     var = Dp + acc / s
     info["cg_iters"] = iters
+    info["acc"] = acc
     return mean, var, info
 
 

@@ -61,6 +61,12 @@ class vl_opts(ctypes.Structure):
         ("replay_cg_iters", ctypes.POINTER(ctypes.c_int)), ("replay_len", ctypes.c_int),
     ]
 
+    def __copy__(self):
+        o = vl_opts()
+        ctypes.memmove(ctypes.byref(o), ctypes.byref(self), ctypes.sizeof(vl_opts))
+        o._replay = getattr(self, "_replay", None)  # keeps the replayed counts alive
+        return o
+
     def set_replay(self, counts):
         """Fix the CG iteration counts (see vl_opts.replay_cg_iters); None clears."""
         if counts is None:

@@ -31,6 +31,14 @@ def rel_err(a, b):
     return float(np.max(np.abs(a - b)) / den)
 
 
+def rel_err_elem(a, b):
+    """max_i |a_i - b_i| / |b_i| (element-wise relative; for quantities
+    bounded away from zero, e.g. variances)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+
+
 def opts_pair(P, **kw):
     """The same options for the oracle and the device library."""
     o = OL.Opts(**kw)

@@ -8,20 +8,26 @@ run the whole path in seconds:
             offset 1, 64 probes, CG tolerance 1e-2, s = 256 (skipped, see
             below), and the same shape at n = 200,000.
 
-Checks, each against what the oracle computes exactly at this size:
+Checks, each against what the oracle computes at this size from its own
+inputs (no device value enters an oracle computation; only the device's
+iteration counts are replayed):
   * every neighbour set (exact), every D_i (1e-9) and every row A_i within
     m * kappa(Sigma_N(i)) * u of the oracle's (the conditioning bound of the
     neighbour solve), the oracle spread over processes by row range;
   * the mode against the oracle's Newton iteration (replaying the device's CG
     counts) and, at a tight tolerance, through its first-order condition
     g(F + b) = B^T D^{-1} B b (Sec. 2.2, eq. newton) with the oracle's factor;
-  * the likelihood pieces that need no probes (eq. VLA_loss, logdetsplit) at
-    the device's mode, the whole assembly of the estimate, and one SLQ probe
-    (eq. def_SLQ) run by the oracle on the same Rademacher column;
+  * every SLQ probe's log-det term (eq. def_SLQ), run by the oracle on the
+    same Rademacher columns at the oracle's mode, and the likelihood
+    (eq. VLA_loss, logdetsplit) assembled from the oracle's pieces;
   * predictive rows and means at all test points (eq. latentpostpredictive)
-    and the simulated variance of one sample column (Alg. simAlgo);
+    and the simulated variances of a full tile of 64 sample columns
+    (Alg. simAlgo), element by element;
   * the mixed-precision form against the FP64 path: relative 1e-4 on the
     negative log-marginal likelihood and 1e-3 on the predictive variances.
+Results downstream of the factor are held to a bar fixed from the oracle
+alone: 10x the spread between the oracle's factor and a second FP64
+implementation of it (see the fixture).
 Each step prints what it checks before it runs."""
 import numpy as np
 import pytest
@@ -51,10 +57,6 @@ WORKLOADS = [
     pytest.param(("c3_n2e6", {"n": 200000}), id="c3_shape_n2e5"),
     pytest.param(("c3_n2e6", {}), id="c3_n2e6", marks=pytest.mark.skip(reason=C3_FAULT)),
 ]
-# The oracle's Newton iteration replaying the device's CG counts takes
-# minutes at the n = 2e5 shape (about 2100 CG iterations); the first-order
-# condition checks that mode instead.
-SLOW_ORACLE_MODE = {"c3_shape_n2e5"}
 
 
 @pytest.fixture(scope="module")
@@ -97,19 +99,33 @@ def case(request, P):
                bval=host(g.export("bval")).reshape(w["n"], w["m"]), D=host(g.export("D")))
     say(f"{name} FP64: newton {mst.newton_iters} cg {mst.cg_iters_total} slq_max "
         f"{st.cg_iters_max} pred_max {pst.cg_iters_max} nll {nll:.10f}")
-    # Tolerance of the results downstream of the factor.  The neighbour
-    # covariances of Sec. 2.1 reach condition numbers near 1e10 at n = 1e5,
-    # range 0.05, so two correct FP64 solvers of those systems give factor
-    # rows up to ~1e-7 apart (bounded per row by test_neighbours_and_factor),
-    # and every CG iterate inherits a perturbation of that relative size: an
-    # oracle with Cholesky instead of LU neighbour solves moves the mode and a
-    # one-sample variance by 2.2x its own factor difference.  Modes and
-    # variances are therefore held to 10x the measured factor discrepancy
-    # (never looser than needed: 1e-9 when the factor agrees to 1e-10).
-    e_fac = float(np.max(np.abs(fit["bval"] + model.A).max(axis=1)
-                         / np.maximum(np.abs(model.A).max(axis=1), 1e-300)))
-    fit["tol_downstream"] = max(TOL, 10.0 * e_fac)
-    say(f"{name} factor discrepancy {e_fac:.2e}: downstream tolerance {fit['tol_downstream']:.2e}")
+    # Tolerance of the results downstream of the factor, fixed from the oracle
+    # alone before any comparison.  The neighbour covariances of Sec. 2.1
+    # reach condition numbers near 1e10 here, so two correct FP64
+    # implementations of the factor (covariances evaluated in a different
+    # order, Cholesky instead of LU) give rows up to ~1e-7 apart, and every CG
+    # iterate inherits a perturbation of that relative size (the innovation
+    # vector D^{-1} B b is not smoothed): between the oracle and such a
+    # variant the mode and a variance move by about 2x the factor spread.
+    # Modes, likelihood, probes and variances are held to 10x the spread
+    # between the oracle and its Cholesky variant (never tighter than 1e-9).
+    say(f"case: {name} second FP64 factor (Cholesky, reordered covariances) for the tolerance")
+    A_ch, D_ch = oracle_pool.factor_cholesky(w["coords"], nbr.astype(np.int64), w["kind"],
+                                             (w["sigma2"], w["rho"]))
+    fit["variant"] = OL.Model(w["coords"], w["m"], w["kind"], (w["sigma2"], w["rho"]),
+                              nbr=nbr.astype(np.int64), factor=(A_ch, D_ch))
+    scale = np.maximum(np.abs(model.A).max(axis=1), 1e-300)
+    e_spread = float(np.max(np.abs(A_ch - model.A).max(axis=1) / scale))
+    fit["tol_downstream"] = max(TOL, 10.0 * e_spread)
+    e_fac = float(np.max(np.abs(fit["bval"] + model.A).max(axis=1) / scale))
+    say(f"{name} factor spread of two oracles {e_spread:.2e}: downstream tolerance "
+        f"{fit['tol_downstream']:.2e} (device factor vs oracle: {e_fac:.2e})")
+    # the oracle's own mode (replaying the device's Newton and CG counts):
+    # every later oracle computation takes its inputs from the oracle alone
+    say(f"case: {name} oracle Newton mode with the device's CG counts")
+    b_o, W_o, _, replayed = oracle_mode_matching(model, w["y"], w["F"], w["lik"], None, o,
+                                                 newton_cg, gpu_halvings=halvings)
+    fit["b_oracle"], fit["W_oracle"], fit["mode_replayed"] = b_o, W_o, replayed
     yield name, w, model, g, fit
     g.close()
 
@@ -152,16 +168,11 @@ def test_neighbours_and_factor(case):
     assert e_d < TOL
 
 
-def test_mode_matches_the_oracle(request, case):
+def test_mode_matches_the_oracle(case):
     name, w, model, _, fit = case
-    if request.node.callspec.id in SLOW_ORACLE_MODE:
-        pytest.skip("oracle Newton takes minutes here; the first-order condition test covers it")
-    say(f"case: {name} oracle Newton mode with the device's CG counts")
-    b, _, _, replayed = oracle_mode_matching(model, w["y"], w["F"], w["lik"], None, fit["o"],
-                                             fit["newton_cg"], gpu_halvings=fit["halvings"])
-    e = rel_err(fit["mode"], b)
-    say(f"{name} mode: newton cg {fit['newton_cg']} replayed={replayed} rel err {e:.2e} "
-        f"(tolerance {fit['tol_downstream']:.2e})")
+    e = rel_err(fit["mode"], fit["b_oracle"])
+    say(f"{name} mode: newton cg {fit['newton_cg']} replayed={fit['mode_replayed']} "
+        f"rel err {e:.2e} (tolerance {fit['tol_downstream']:.2e})")
     assert e < fit["tol_downstream"]
 
 
@@ -189,40 +200,39 @@ def test_mode_first_order_condition(P, case):
     assert np.linalg.norm(r) < 10.0 * FOC_CG_TOL + 1e-6 * np.linalg.norm(grad)
 
 
-def test_nll_pieces_and_one_probe(case):
+def test_nll_pieces_and_every_probe(case):
     name, w, model, _, fit = case
-    say(f"case: {name} NLL pieces at the device mode")
-    b = fit["mode"]
+    say(f"case: {name} NLL pieces at the oracle mode")
+    b = fit["b_oracle"]
+    tol = fit["tol_downstream"]
     mu = w["F"] + b
     W = OL.lik_W(w["lik"], w["y"], mu)
     loglik = float(np.sum(OL.lik_logp(w["lik"], w["y"], mu)))
     Bb = model.B @ b
     quadform = float(np.sum(model.Dinv * Bb * Bb))
     logdet_fixed = float(np.sum(np.log(model.D)) + np.sum(np.log(W + model.Dinv)))
-    # eq. def_SLQ with the device's per-probe quadratures
-    gamma = float(np.mean(fit["r0z0"] * fit["quad"]))
-    nll_o = -loglik + 0.5 * quadform + 0.5 * (logdet_fixed + gamma)
-    e = abs(fit["nll"] - nll_o) / abs(nll_o)
-    say(f"{name} NLL assembly: device {fit['nll']:.10f} oracle pieces {nll_o:.10f} rel {e:.2e}")
-    assert e < TOL
     # Rademacher probes with z = B^T (W + D^{-1})^{1/2} eps give r0'z0 = eps'eps = n
     e_r = rel_err(fit["r0z0"], np.full(w["t"], float(w["n"])))
     say(f"{name} SLQ weights r0'z0 vs n: rel {e_r:.2e}")
     assert e_r < 1e-8
-    # probe 0 run by the oracle: the probe columns are counter-based, so column
-    # 0 of a one-probe run is column 0 of the device's run
-    say(f"case: {name} SLQ probe 0 by the oracle")
-    o1 = OL.Opts(cg_tol=w["cg_tol"], num_probes=1, seed=7)
-    _, info = OL.neg_log_marglik(model, w["y"], w["F"], w["lik"], None, b, o1)
-    replayed = int(info["cg_iters"][0]) != int(fit["slq_iters"][0])
-    if replayed:
-        _, info = OL.neg_log_marglik(model, w["y"], w["F"], w["lik"], None, b, o1,
-                                     replay_cg=[int(fit["slq_iters"][0])])
-    e_q = abs(info["quad"][0] * info["r0z0"][0] - fit["quad"][0] * fit["r0z0"][0]) / abs(
-        info["quad"][0] * info["r0z0"][0])
-    say(f"{name} probe 0: iters {fit['slq_iters'][0]} replayed={replayed} "
-        f"log-det term rel {e_q:.2e}")
-    assert e_q < TOL
+    # every probe column run by the oracle (the probe columns are
+    # counter-based; slices of them run in parallel processes), replaying
+    # the device's per-column CG counts
+    say(f"case: {name} all {w['t']} SLQ probes by the oracle")
+    quad, r0z0, iters = oracle_pool.slq_columns(model, w["y"], w["F"], w["lik"], b, fit["o"],
+                                                w["t"], replay=[int(v) for v in fit["slq_iters"]])
+    term_o, term_d = quad * r0z0, fit["quad"] * fit["r0z0"]
+    e_q = float(np.max(np.abs(term_d - term_o) / np.abs(term_o)))
+    say(f"{name} probes: device iters {fit['slq_iters'].tolist()} log-det terms max rel "
+        f"{e_q:.2e} (tolerance {tol:.2e})")
+    assert np.array_equal(iters, fit["slq_iters"])
+    assert e_q < tol
+    # eq. def_SLQ and eq. VLA_loss assembled from the oracle's own pieces
+    gamma = float(np.mean(r0z0 * quad))
+    nll_o = -loglik + 0.5 * quadform + 0.5 * (logdet_fixed + gamma)
+    e = abs(fit["nll"] - nll_o) / abs(nll_o)
+    say(f"{name} NLL: device {fit['nll']:.10f} oracle {nll_o:.10f} rel {e:.2e}")
+    assert e < tol
 
 
 def test_prediction(P, case):
@@ -240,27 +250,36 @@ def test_prediction(P, case):
     say(f"{name} prediction rows: max rel {e_row.max():.2e}, max ratio to bound "
         f"{(e_row / bound).max():.2e}")
     assert np.all(e_row <= bound)
-    mean_o = w["Fp"] + np.sum(Ap * fit["mode"][nbr_p], axis=1)
+    tol = fit["tol_downstream"]
+    mean_o = w["Fp"] + np.sum(Ap * fit["b_oracle"][nbr_p], axis=1)
     e_m = rel_err(fit["mean"], mean_o)
-    say(f"{name} predictive means: rel {e_m:.2e}")
-    assert e_m < TOL
+    say(f"{name} predictive means: rel {e_m:.2e} (tolerance {tol:.2e})")
+    assert e_m < tol
     # D_p plus an average of squares: never below the conditional variance
     assert np.all(fit["var"] >= Dp * (1.0 - 1e-12))
-    # one simulation column end to end (Alg. simAlgo with s = 1)
-    say(f"case: {name} predictive variance of one sample column by the oracle")
-    o1, go1 = opts_pair(P, pred_cg_tol=w["pred_cg_tol"], num_pred_samples=1, seed=7)
-    _, var1, _ = g.predict(dev(w["coords_pred"]), dev(w["Fp"]), go1)
-    iters1 = host(g.export("block_iters"))
-    W = OL.lik_W(w["lik"], w["y"], w["F"] + fit["mode"])
-    _, var_o, info = OL.predict(model, w["coords_pred"], w["Fp"], fit["mode"], W, o1)
-    replayed = int(info["cg_iters"][0]) != int(iters1[0])
-    if replayed:
-        _, var_o, info = OL.predict(model, w["coords_pred"], w["Fp"], fit["mode"], W, o1,
-                                    replay_cg=[int(iters1[0])])
-    e_v = rel_err(host(var1), var_o)
-    say(f"{name} one-sample variance: iters {iters1[0]} replayed={replayed} rel {e_v:.2e} "
-        f"(tolerance {fit['tol_downstream']:.2e})")
-    assert e_v < fit["tol_downstream"]
+    # one full tile of 64 simulation columns end to end (Alg. simAlgo), the
+    # oracle's columns split over processes
+    say(f"case: {name} predictive variances of a 64-column sample tile by the oracle")
+    o64, go64 = opts_pair(P, pred_cg_tol=w["pred_cg_tol"], num_pred_samples=64, seed=7)
+    _, var64, _ = g.predict(dev(w["coords_pred"]), dev(w["Fp"]), go64)
+    iters64 = host(g.export("block_iters"))
+    var_o, it_o = oracle_pool.pred_columns(model, w["coords_pred"], w["Fp"], fit["b_oracle"],
+                                           fit["W_oracle"], o64, 64,
+                                           replay=[int(v) for v in iters64])
+    assert np.array_equal(it_o, iters64)
+    # the variances pass through about 300 CG iterations at the n = 2e6
+    # shape; their bar is 10x the spread between the oracle and its second
+    # implementation on this very output (same mode, same counts), when
+    # that exceeds the factor-based bar
+    var_v, _ = oracle_pool.pred_columns(fit["variant"], w["coords_pred"], w["Fp"],
+                                        fit["b_oracle"], fit["W_oracle"], o64, 64,
+                                        replay=[int(v) for v in iters64])
+    e_spread = float(np.max(np.abs(var_v - var_o) / var_o))
+    tol_v = max(tol, 10.0 * e_spread)
+    e_v = float(np.max(np.abs(host(var64) - var_o) / var_o))
+    say(f"{name} 64-sample variances: iters {iters64.min()}..{iters64.max()} elementwise rel "
+        f"{e_v:.2e} (two oracles {e_spread:.2e}, tolerance {tol_v:.2e})")
+    assert e_v < tol_v
 
 
 def test_mixed_matches_fp64(P, case):

@@ -16,7 +16,8 @@ pytestmark = pytest.mark.gpu
 import synth  # noqa: E402
 from oracle import laplace as OL  # noqa: E402
 from oracle import vecchia as OV  # noqa: E402
-from tests.gpu_common import dev, host, oracle_mode_matching, opts_pair, rel_err, say  # noqa: E402
+from tests.gpu_common import (dev, host, oracle_mode_matching, opts_pair, rel_err,  # noqa: E402
+                               rel_err_elem, say)
 
 TOL = 1e-9
 
@@ -190,9 +191,11 @@ def test_nll_and_gradient(c1, c1_fit):
         nll, info = OL.neg_log_marglik(model, w["y"], w["F"], w["lik"], None, b, f["opts"],
                                        replay_cg=f["slq_iters"], want_grad=True)
     np.testing.assert_allclose(f["r0z0"], info["r0z0"], rtol=1e-12)
-    assert rel_err(f["quad"], info["quad"]) < TOL
+    assert rel_err_elem(f["quad"], info["quad"]) < TOL
     assert abs(f["nll"] - nll) <= TOL * abs(nll)
-    np.testing.assert_allclose(f["grad"], info["grad"], rtol=TOL * 10, atol=TOL * np.abs(info["grad"]).max())
+    e_g = rel_err_elem(f["grad"], info["grad"])
+    say(f"gradient: device {f['grad']} oracle {info['grad']} rel {e_g:.2e}")
+    assert e_g < TOL
 
 
 def test_predict(c1, c1_fit):
@@ -204,7 +207,7 @@ def test_predict(c1, c1_fit):
                                  replay_cg=f["pred_iters"])
     assert abs(np.array(info["cg_iters"]) - np.array(f["pred_iters"])).max() == 0
     assert rel_err(f["mean"], mean) < TOL
-    assert rel_err(f["var"], var) < TOL
+    assert rel_err_elem(f["var"], var) < TOL
 
 
 @pytest.mark.parametrize("n", [40000, 5000])

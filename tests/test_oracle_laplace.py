@@ -470,3 +470,24 @@ def test_prediction_variance_formula_small_m():
     np.testing.assert_allclose(mean, Ap @ b, rtol=1e-12, atol=1e-13)
     sd = np.sqrt(2.0 / s) * (exact - info["Dp"])
     assert np.all(np.abs(var - exact) <= 5 * sd + 1e-10)
+
+
+def test_probe_and_sample_slices_equal_the_full_sets():
+    """Counter-based probes: a slice of probe columns (col0) gives the same
+    per-column quadratures, and sample-column slices add up to the full
+    simulated variance (Alg. simAlgo sums over independent columns)."""
+    import synth
+    w = synth.make(None, seed=9, n=300, m=6, kind=synth.COV_MATERN32, sigma2=1.0, rho=0.2,
+                   lik=synth.LIK_BERNOULLI_LOGIT, F=0.0, n_pred=40)
+    model = L.Model(w["coords"], w["m"], w["kind"], (w["sigma2"], w["rho"]))
+    o = L.Opts(cg_tol=1e-10, pred_cg_tol=1e-10, num_probes=6, num_pred_samples=6, seed=3)
+    b, W, _ = L.find_mode(model, w["y"], w["F"], w["lik"], None, o)
+    _, full = L.neg_log_marglik(model, w["y"], w["F"], w["lik"], None, b, o)
+    o2 = L.Opts(cg_tol=1e-10, num_probes=2, seed=3)
+    _, part = L.neg_log_marglik(model, w["y"], w["F"], w["lik"], None, b, o2, col0=3)
+    np.testing.assert_allclose(part["quad"], full["quad"][3:5], rtol=1e-12)
+    _, var, info = L.predict(model, w["coords_pred"], w["Fp"], b, W, o)
+    o3 = L.Opts(pred_cg_tol=1e-10, num_pred_samples=3, seed=3)
+    _, _, i0 = L.predict(model, w["coords_pred"], w["Fp"], b, W, o3, col0=0)
+    _, _, i1 = L.predict(model, w["coords_pred"], w["Fp"], b, W, o3, col0=3)
+    np.testing.assert_allclose(info["Dp"] + (i0["acc"] + i1["acc"]) / 6, var, rtol=1e-12)

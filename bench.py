@@ -202,7 +202,11 @@ def main():
                          ("serving", lambda: form_serving(P, torch, synth, args))):
             print(f"form: {name}", file=sys.stderr, flush=True)
             out["forms"][name] = fn()
-    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(w, rec[-1], args)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, rec[-1], args)
+        out["small_workload_timed"] = small_workload_both_sides(P, torch, synth, args)
+    else:
+        out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
 
 
@@ -362,53 +366,93 @@ def measured_traffic(kernel, workload):
 
 
 def cpu_baseline(w, it, args):
-    """The FP64 oracle on a bounded sample of the same workload.
+    """The FP64 oracle timed on a bounded sample of the same workload.
 
-    Timed whole: neighbour search + Vecchia factor with derivatives at the full
-    n, and neighbour search + factor of the prediction locations.  Timed on a
-    sample: preconditioned CG iterations on the same operator, 10 iterations
-    with one column and 5 iterations with 4 columns; per-iteration costs are
-    scaled by the device run's iteration counts and column counts of one
-    evaluation (Newton solves, the gradient's extra solve, SLQ with t probes,
-    prediction with s samples)."""
-    import numpy as np
+    Every piece is an oracle call timed end to end on the full n = 1e5 data:
+    the model (neighbour search + Vecchia factor with derivatives), the first
+    Newton step (its whole CG solve), the SLQ likelihood with its gradient on
+    2 of the t probe columns, and the prediction (test-point factor, means and
+    2 of the s sample columns).  One evaluation is then: build + Newton steps
+    x the device's Newton count + likelihood x t/2 + prediction x s/2 (probe
+    and sample columns are independent CG runs of the same operator)."""
     from threadpoolctl import threadpool_info
 
     from oracle import laplace as OL
-    from oracle import vecchia as OV
 
-    n = w["n"]
+    y, F, lik = w["y"], w["F"], w["lik"]
     t0 = time.perf_counter()
     model = OL.Model(w["coords"], w["m"], w["kind"], (w["sigma2"], w["rho"]), deriv=True)
     t_build = time.perf_counter() - t0
+    o = OL.Opts(cg_tol=w["cg_tol"], pred_cg_tol=w["pred_cg_tol"], num_probes=2,
+                num_pred_samples=2, seed=args.seed, max_newton=1)
     t0 = time.perf_counter()
-    nbr_p = OV.pred_neighbours(w["coords"], w["coords_pred"], w["m"])
-    OV.factor(w["coords"], nbr_p, w["kind"], (w["sigma2"], w["rho"]),
-              coords_self=w["coords_pred"])
-    t_pred_factor = time.perf_counter() - t0
-    W = OL.lik_W(w["lik"], w["y"], w["F"], None)
-    apply_A, apply_Pinv = OL.vadu_ops(model, W)
-    g = np.random.default_rng(0)
+    b, W, st = OL.find_mode(model, y, F, lik, None, o)
+    t_newton = time.perf_counter() - t0
     t0 = time.perf_counter()
-    OL.pcg(apply_A, apply_Pinv, g.standard_normal((n, 1)), 0.0, 10, forced_iters=[10])
-    t_it1 = (time.perf_counter() - t0) / 10
+    OL.neg_log_marglik(model, y, F, lik, None, b, o, want_grad=True)
+    t_nll2 = time.perf_counter() - t0
     t0 = time.perf_counter()
-    OL.pcg(apply_A, apply_Pinv, g.standard_normal((n, 4)), 0.0, 5, forced_iters=[5] * 4)
-    t_col = (time.perf_counter() - t0) / 5 / 4
-    newton_cg = it["newton_cg_total"]
-    grad_cg = newton_cg / max(it["newton_iters"], 1)
-    t_eval = (t_build + t_pred_factor + (newton_cg + grad_cg) * t_it1 +
-              it["slq_cg_max"] * w["t"] * t_col + it["pred_cg_max"] * w["s"] * t_col)
+    OL.predict(model, w["coords_pred"], w["Fp"], b, W, o)
+    t_pred2 = time.perf_counter() - t0
+    k_newton = max(it["newton_iters"], 1)
+    t_eval = (t_build + k_newton * t_newton + t_nll2 * w["t"] / 2 + t_pred2 * w["s"] / 2)
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     return {"value": 1.0 / t_eval, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": (f"oracle on the same n={n} workload: kNN + factor timed whole "
-                       f"({t_build:.1f} s) and prediction factor ({t_pred_factor:.1f} s); PCG "
-                       f"timed on 10 iterations x 1 column ({t_it1 * 1e3:.1f} ms/it) and 5 "
-                       f"iterations x 4 columns ({t_col * 1e3:.1f} ms/it/column), scaled by the "
-                       f"device run's counts (Newton CG {newton_cg}, gradient CG ~{grad_cg:.0f}, "
-                       f"SLQ {it['slq_cg_max']} x {w['t']} columns, prediction "
-                       f"{it['pred_cg_max']} x {w['s']} columns)"),
-            "est_eval_s": t_eval, "host_cpus": os.cpu_count()}
+            "sample": (f"oracle calls timed end to end on the same n={w['n']} workload: build "
+                       f"{t_build:.1f} s, first Newton step {t_newton:.1f} s "
+                       f"({st['cg_iters'][0]} CG iterations) x {k_newton} steps, SLQ likelihood "
+                       f"+ gradient on 2 probes {t_nll2:.1f} s x {w['t']}/2, prediction with 2 "
+                       f"samples {t_pred2:.1f} s x {w['s']}/2"),
+            "est_eval_s": t_eval, "timed_s": t_build + t_newton + t_nll2 + t_pred2,
+            "host_cpus": os.cpu_count()}
+
+
+def small_workload_both_sides(P, torch, synth, args):
+    """The n = 2,000 workload (exponential range 0.1, m = 10, Bernoulli-logit,
+    t = 50, CG tolerance 1e-8, 500 test points, s = 64), where the oracle
+    finishes in seconds: one whole evaluation (build + mode + NLL + gradient
+    + predict) timed on both sides, the oracle replaying nothing."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import laplace as OL
+
+    w = synth.make("c1_n2000", seed=args.seed)
+    d = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    coords, y, F, cp, Fp = d(w["coords"]), d(w["y"]), d(w["F"]), d(w["coords_pred"]), d(w["Fp"])
+    opts = P.vl_default_opts(cg_tol=w["cg_tol"], pred_cg_tol=w["pred_cg_tol"],
+                             num_probes=w["t"], num_pred_samples=w["s"], seed=args.seed)
+
+    def gpu_eval():
+        g = P.VecchiaLaplace(coords, w["m"], w["kind"], (w["sigma2"], w["rho"]), want_deriv=True)
+        g.find_mode(y, F, w["lik"], None, opts)
+        nll, _, _ = g.neg_log_marglik(opts, want_grad=True)
+        g.predict(cp, Fp, opts)
+        g.close()
+        return nll
+
+    gpu_eval()
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        nll_g = gpu_eval()
+    torch.cuda.synchronize()
+    t_gpu = (time.perf_counter() - t0) / reps
+    o = OL.Opts(cg_tol=w["cg_tol"], pred_cg_tol=w["pred_cg_tol"], num_probes=w["t"],
+                num_pred_samples=w["s"], seed=args.seed)
+    t0 = time.perf_counter()
+    model = OL.Model(w["coords"], w["m"], w["kind"], (w["sigma2"], w["rho"]), deriv=True)
+    b, W, _ = OL.find_mode(model, w["y"], w["F"], w["lik"], None, o)
+    nll_o, _ = OL.neg_log_marglik(model, w["y"], w["F"], w["lik"], None, b, o, want_grad=True)
+    OL.predict(model, w["coords_pred"], w["Fp"], b, W, o)
+    t_cpu = time.perf_counter() - t0
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    log(args, f"n=2000: gpu {t_gpu * 1e3:.1f} ms/eval, oracle {t_cpu:.2f} s/eval")
+    return {"workload": "c1_n2000: n=2000, exponential rho=0.1, m=10, Bernoulli-logit, t=50, "
+                        "CG tol 1e-8, 500 test points, s=64; one eval = build + mode + NLL + "
+                        "gradient + predict",
+            "gpu_evals_per_s": 1.0 / t_gpu, "oracle_evals_per_s": 1.0 / t_cpu,
+            "oracle_cores": threads, "nll_gpu": nll_g, "nll_oracle": nll_o}
 
 
 if __name__ == "__main__":

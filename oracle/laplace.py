@@ -15,7 +15,9 @@ Plain FP64 NumPy/SciPy, following the paper step by step:
                    (LRAC, Sec. 3.1.2) and SLQ for the last term
   grad_theta       App. "Gradients of Vecchia-Laplace approximations" with the
                    VADU STE / control-variate formulas of the appendix
-                   "Derivatives of log-determinants ... Preconditioner VADU"
+                   "Derivatives of log-determinants ... Preconditioner VADU";
+                   also the gradient in the offset F (for F = X beta the
+                   beta-gradient is X^T of it)
   predict          eq. (latentpostpredictive) with B_p = I and the simulation
                    algorithm (Sec. 3.3.1, Alg. simAlgo)
 
@@ -452,7 +454,7 @@ def neg_log_marglik(model, y, F, lik, aux, b, opts, replay_cg=None, L=None,
         grad, ginfo = _grad_theta_vadu(model, y, F, lik, aux, b, W, res, opts,
                                        replay_grad_cg)
         info["grad"] = grad
-        info.update(ginfo)
+        info.update(ginfo)  # includes grad_F, the gradient in the offset F
     return nll, info
 
 
@@ -517,6 +519,12 @@ def _grad_theta_vadu(model, y, F, lik, aux, b, W, res, opts, replay_grad_cg):
     else:
         wsol = np.zeros(n)
         parts["grad_cg_iters"] = 0
+    # d L / d F (App. "Gradients of Vecchia-Laplace approximations"): the
+    # explicit part -d log p / d mu + (1/2) d log det / d mu, plus the mode's
+    # response (d L / d b*)^T d b* / d F_i with d b* / d F_i = -A^{-1} W e_i;
+    # at the mode d L / d b* = (1/2) d log det / d mu (the other terms cancel),
+    # so d L / d F = -g + dL_db - W o (A^{-1} dL_db).
+    parts["grad_F"] = -lik_grad(lik, y, F + b, aux) + dL_db - W * wsol
     for k in range(2):
         dD = model.dD[k]
         dBb = model.dB[k] @ b

@@ -223,6 +223,22 @@ vl_status vl_find_mode(vl_model* h, const double* y, const double* F, int lik,
 vl_status vl_neg_log_marglik(vl_model* h, const vl_opts* o, double* nll_host,
                              double* grad_theta_host, vl_stats* st);
 
+/* Gradient of the negative log-marginal likelihood in the offset F at the
+ * stored mode (App. "Gradients of Vecchia-Laplace approximations"):
+ *   dL/dF_i = -d log p(y_i|mu_i)/d mu_i + (1/2) d log det(Sigma~ W + I)/d mu_i
+ *             + (dL/d b_mode)^T (d b_mode/dF_i),
+ *   d b_mode/dF_i = -(W + Sigma~^{-1})^{-1} W e_i  (b_mode = the mode b*),
+ * with d log det / d mu estimated by the VADU stochastic trace estimator and
+ * its control variate (the same probes and solves as the theta-gradient).
+ * Available after vl_neg_log_marglik with grad_theta_host != NULL (the same
+ * call computes it, for one extra kernel); VL_ERR_STATE otherwise.
+ *   grad_F device, n.  Synchronises. */
+vl_status vl_grad_offset(vl_model* h, double* grad_F);
+
+/* With F = X beta (Sec. 2, fixed effects): grad_beta_host (host, p) =
+ * X^T dL/dF from the same call.  X device, n x p row-major.  Synchronises. */
+vl_status vl_grad_beta(vl_model* h, const double* X, int p, double* grad_beta_host);
+
 /* Predictive latent mean and simulated variance (eq. latentpostpredictive,
  * Alg. simAlgo) at n_p new locations conditioned on the m nearest training
  * locations.

@@ -307,6 +307,7 @@ vl_status vl_set_theta(vl_model* h, const double* theta_host) {
     h->sigma2 = theta_host[0];
     h->rho = theta_host[1];
     h->has_mode = false;
+    h->has_grad_F = false;
     h->lrac_ready = false;
     const double t0 = vl::now_ms();
     VL_TRY(vl::compute_factor(*h));
@@ -336,6 +337,7 @@ vl_status vl_find_mode(vl_model* h, const double* y, const double* F, int lik,
     M.lik = lik;
     M.aux = aux;
     M.has_mode = false;
+    M.has_grad_F = false;
     VL_TRY(M.y.reserve(M.n));
     VL_TRY(vl::copy_d2d(M.y.p, y, sizeof(double) * M.n, M.stream));
     if (F) {
@@ -406,6 +408,26 @@ vl_status vl_predict(vl_model* h, const double* coords_p, int64_t n_p, const dou
       st->err_vs_fp64_est = (o->precision == VL_MIXED && var_out) ? h->last_f32_dev : 0.0;
     }
     return s;
+  });
+}
+
+vl_status vl_grad_offset(vl_model* h, double* grad_F) {
+  vl::CallStream cs(h ? h->stream : nullptr);
+  return vl::guarded([&]() -> vl::Status {
+    if (!h || !grad_F) return vl::Status::invalid("null argument");
+    if (!h->has_grad_F)
+      return vl::Status::make(VL_ERR_STATE,
+                              "no offset gradient: call vl_neg_log_marglik with a gradient");
+    VL_TRY(vl::copy_d2d(grad_F, h->grad_F.p, sizeof(double) * h->n, h->stream));
+    return vl::sync_stream(h->stream);
+  });
+}
+
+vl_status vl_grad_beta(vl_model* h, const double* X, int p, double* grad_beta_host) {
+  vl::CallStream cs(h ? h->stream : nullptr);
+  return vl::guarded([&]() -> vl::Status {
+    if (!h || !X || !grad_beta_host) return vl::Status::invalid("null argument");
+    return vl::grad_beta(*h, X, p, grad_beta_host);
   });
 }
 

@@ -429,6 +429,42 @@ static double cv_weight(const std::vector<double>& h, const std::vector<double>&
   return (vr > 1e-10 * mr * mr) ? cv / vr : 0.0;
 }
 
+// d L / d F = -g + dL/db - W o w, w = A^{-1} dL/db (the mode's response to
+// the offset, App. "Gradients of Vecchia-Laplace approximations").
+__global__ void grad_offset_kernel(int64_t n, const double* __restrict__ g,
+                                   const double* __restrict__ dLdb, const double* __restrict__ W,
+                                   const double* __restrict__ w, double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (dLdb[i] - g[i]) - W[i] * w[i];
+}
+
+// Partial sums of X^T v over the chunks of rows (X n x p row-major).
+__global__ __launch_bounds__(256) void xt_vec_kernel(ChunkGrid g, const double* __restrict__ X,
+                                                     const double* __restrict__ v,
+                                                     double* __restrict__ part) {
+  double acc = 0.0;
+  CHUNK_LOOP_BEGIN(g)
+  acc += X[i * g.t + c] * v[i];
+  CHUNK_LOOP_END
+  block_colsum(g, acc, part);
+}
+
+// out (host, p) = X^T grad_F: the gradient in beta when F = X beta.
+Status grad_beta(Model& M, const double* X, int p, double* out) {
+  if (!M.has_grad_F)
+    return Status::make(VL_ERR_STATE, "no offset gradient: call vl_neg_log_marglik with a gradient");
+  if (p < 1) return Status::invalid("p must be positive");
+  ChunkGrid g = ChunkGrid::of(M.n, p);
+  VL_TRY(M.red_part.reserve(static_cast<size_t>(g.nchunk) * p + 64));
+  VL_TRY(M.red_out.reserve(static_cast<size_t>(p) + 64));
+  hipLaunchKernelGGL(xt_vec_kernel, dim3(g.nchunk, g.L.slices), dim3(256), 0, M.stream, g, X,
+                     M.grad_F.p, M.red_part.p);
+  VL_TRY(reduce_chunks(M.stream, M.red_part.p, g.nchunk, p, M.red_out.p));
+  VL_HIP(hipMemcpyAsync(out, M.red_out.p, sizeof(double) * p, hipMemcpyDeviceToHost, M.stream));
+  VL_TRY(sync_stream(M.stream));
+  return read_status(M);
+}
+
 static Status grad_theta(Model& M, const vl_opts& o, const double* sdiag, double* grad,
                          GradInfo* info) {
   const int t = M.cg.t;
@@ -458,6 +494,11 @@ static Status grad_theta(Model& M, const vl_opts& o, const double* sdiag, double
   VL_TRY(cg_solve(M, M.cg1, ops, 1, M.vec_c.p, o.cg_tol, o.max_cg, false,
                   replay_slice(o, t, 1, rbuf)));  // entry t: after the probe columns
   info->grad_cg_iters = M.cg1.host_iters[0];
+  VL_TRY(M.grad_F.reserve(n));
+  hipLaunchKernelGGL(grad_offset_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     M.stream, n, M.g.p, M.vec_c.p, M.W.p, M.cg1.U.p, M.grad_F.p);
+  VL_TRY(check_launch("grad offset"));
+  M.has_grad_F = true;
   ChunkGrid g1 = ChunkGrid::of(n, 1);
   VL_TRY(M.red_part.reserve(static_cast<size_t>(g1.nchunk) * 8 + 64));
   hipLaunchKernelGGL(grad_rows_kernel, dim3(g1.nchunk, 1), dim3(256), 0, M.stream, g1, M.m,
@@ -488,6 +529,7 @@ static Status grad_theta(Model& M, const vl_opts& o, const double* sdiag, double
 // -------------------------------------------------------------- NLL (SLQ)
 Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, NllInfo* info) {
   if (!M.has_mode) return Status::make(VL_ERR_STATE, "no mode: call vl_find_mode first");
+  M.has_grad_F = false;
   if (grad && !M.deriv) return Status::make(VL_ERR_STATE, "model built without derivatives");
   const int64_t n = M.n;
   const int t = o.num_probes;

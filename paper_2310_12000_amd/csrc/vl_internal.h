@@ -285,6 +285,10 @@ struct Model {
     return Status::ok();
   }
 
+  // gradient of the last likelihood call in the offset F (n), when asked
+  DevBuf<double> grad_F;
+  bool has_grad_F = false;
+
   // likelihood state
   bool has_mode = false;
   int lik = 0;

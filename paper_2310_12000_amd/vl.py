@@ -150,6 +150,8 @@ def lib():
     L.vl_predict.argtypes = [P, P, I64, P, ctypes.POINTER(vl_opts), P, P,
                              ctypes.POINTER(vl_stats)]
     L.vl_export.argtypes = [P, I, P, S]
+    L.vl_grad_offset.argtypes = [P, P]
+    L.vl_grad_beta.argtypes = [P, P, I, ctypes.POINTER(D)]
     L.vl_export_count.argtypes = [P, I]
     L.vl_export_count.restype = I64
     L.vl_spmm.argtypes = [P, I, P, P, I]
@@ -180,7 +182,7 @@ def lib():
     L.vl_server_free.restype = None
     for f in ("vl_build_vecchia", "vl_set_theta", "vl_find_mode", "vl_neg_log_marglik",
               "vl_predict", "vl_export", "vl_spmm", "vl_trsm", "vl_trsm_noalloc",
-              "vl_set_allocator", "vl_timing_enable",
+              "vl_set_allocator", "vl_grad_offset", "vl_grad_beta", "vl_timing_enable",
               "vl_timing_read", "vl_batch_create", "vl_batch_fit", "vl_batch_mode",
               "vl_batch_stats", "vl_server_create", "vl_server_submit", "vl_server_wait",
               "vl_server_info"):
@@ -395,6 +397,19 @@ class VecchiaLaplace:
         var = torch.empty(npred, dtype=torch.float64, device=coords_p.device) if want_var else None
         st = vl_predict(self.h, coords_p, Fp, opts, mean, var, allow_no_conv)
         return mean, var, st
+
+    def grad_offset(self):
+        """dL/dF (device tensor, n) from the last neg_log_marglik with a gradient."""
+        out = torch.empty(self.n, dtype=torch.float64, device=self.coords.device)
+        _check(lib().vl_grad_offset(self.h, _ptr(out)))
+        return out
+
+    def grad_beta(self, X):
+        """X^T dL/dF for F = X beta (X: device n x p float64)."""
+        p = 1 if X.dim() == 1 else X.shape[1]
+        out = (ctypes.c_double * p)()
+        _check(lib().vl_grad_beta(self.h, _ptr(X), p, out))
+        return list(out)
 
     def export(self, name):
         return vl_export(self.h, name, self.coords.device)

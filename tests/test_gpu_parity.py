@@ -154,6 +154,9 @@ def c1_fit(P, c1):
     newton_cg = host(g.export("newton_cg_iters")).tolist()
     halvings = host(g.export("newton_halvings")).tolist()
     nll, grad, nst = g.neg_log_marglik(go, want_grad=True)
+    grad_F = host(g.grad_offset())
+    Xcov = np.random.default_rng(17).standard_normal((w["n"], 3))
+    grad_beta = g.grad_beta(dev(Xcov))
     slq_iters = host(g.export("block_iters")).tolist()
     quad = host(g.export("slq_quad"))
     r0z0 = host(g.export("slq_r0z0"))
@@ -161,6 +164,7 @@ def c1_fit(P, c1):
     mean, var, pst = g.predict(dev(w["coords_pred"]), dev(w["Fp"]), go)
     pred_iters = host(g.export("block_iters")).tolist()
     out = dict(mode=host(mode), st=st, newton_cg=newton_cg, halvings=halvings, nll=nll, grad=grad,
+               grad_F=grad_F, grad_beta=grad_beta, Xcov=Xcov,
                slq_iters=slq_iters, quad=quad, r0z0=r0z0, W=W, mean=host(mean),
                var=host(var), pred_iters=pred_iters, opts=o)
     g.close()
@@ -196,6 +200,14 @@ def test_nll_and_gradient(c1, c1_fit):
     e_g = rel_err_elem(f["grad"], info["grad"])
     say(f"gradient: device {f['grad']} oracle {info['grad']} rel {e_g:.2e}")
     assert e_g < TOL
+    # gradient in the offset F and, for F = X beta, in beta (App. A.3)
+    e_f = rel_err(f["grad_F"], info["grad_F"])
+    gb_o = f["Xcov"].T @ info["grad_F"]
+    e_b = rel_err_elem(f["grad_beta"], gb_o)
+    say(f"offset gradient rel {e_f:.2e}; beta gradient device {f['grad_beta']} oracle {gb_o} "
+        f"rel {e_b:.2e}")
+    assert e_f < TOL
+    assert e_b < TOL
 
 
 def test_predict(c1, c1_fit):

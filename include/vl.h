@@ -223,6 +223,26 @@ vl_status vl_find_mode(vl_model* h, const double* y, const double* F, int lik,
 vl_status vl_neg_log_marglik(vl_model* h, const vl_opts* o, double* nll_host,
                              double* grad_theta_host, vl_stats* st);
 
+/* Estimation of theta = (sigma2, rho) (Sec. 4.1): minimises the negative
+ * log-marginal likelihood over log theta by L-BFGS (two-loop recursion,
+ * history 10, backtracking Armijo line search) with a sample average
+ * approximation: every evaluation uses the probes of o->seed, so the
+ * objective is deterministic.  Each evaluation runs vl_set_theta,
+ * vl_find_mode from b = 0 and vl_neg_log_marglik with the gradient (VADU;
+ * the model must have been built with want_deriv).
+ *   theta_inout host, 2: start, then the estimate
+ *   max_iter    L-BFGS iterations at most; grad_tol: stop when every
+ *               component of the gradient in log theta is at most this
+ *   nll_host, iters_host, evals_host (host, nullable): the objective at the
+ *               estimate, the iterations and the likelihood evaluations used
+ * Leaves the model at the estimate (mode and likelihood state of the last
+ * evaluation).  VL_ERR_NO_CONVERGENCE when max_iter was reached (theta_inout
+ * holds the last iterate).  Synchronises. */
+vl_status vl_estimate(vl_model* h, const double* y, const double* F, int lik,
+                      const double* aux_host, const vl_opts* o, double* theta_inout,
+                      int max_iter, double grad_tol, double* nll_host, int* iters_host,
+                      int* evals_host);
+
 /* Gradient of the negative log-marginal likelihood in the offset F at the
  * stored mode (App. "Gradients of Vecchia-Laplace approximations"):
  *   dL/dF_i = -d log p(y_i|mu_i)/d mu_i + (1/2) d log det(Sigma~ W + I)/d mu_i

@@ -599,3 +599,29 @@ def predict(model, coords_p, Fp, b, W, opts, replay_cg=None, chunk=256,
 def _gaussian_cols(seed, tag, n, c0, c1):
     """Columns c0..c1-1 of the n x s Gaussian probe matrix."""
     return _rng.gaussian(seed, tag, n, c1 - c0, col0=c0)
+
+
+# ----------------------------------------------------------------------------
+# estimation of theta (Sec. 4.1: L-BFGS with a sample average approximation)
+# ----------------------------------------------------------------------------
+def estimate(coords, m, kind, y, F, lik, aux, theta0, opts, nbr=None, gtol=1e-6, maxiter=100):
+    """theta minimising L^VLA with the probes of opts.seed in every evaluation
+    (so the objective is deterministic), over log theta by scipy's L-BFGS-B.
+    Each evaluation: the factor at theta, the mode from b = 0, the SLQ
+    likelihood and its STE gradient.  Returns (theta, nll, scipy result)."""
+    from scipy.optimize import minimize
+
+    coords = np.asarray(coords, dtype=np.float64)
+    nbr = _vec.neighbours(coords, m) if nbr is None else nbr
+
+    def fun(x):
+        theta = np.exp(x)
+        model = Model(coords, m, kind, theta, nbr=nbr, deriv=True)
+        b, _, _ = find_mode(model, y, F, lik, aux, opts)
+        nll, info = neg_log_marglik(model, y, F, lik, aux, b, opts, want_grad=True)
+        return nll, info["grad"] * theta  # gradient in log theta
+
+    res = minimize(fun, np.log(np.asarray(theta0, dtype=np.float64)), jac=True,
+                   method="L-BFGS-B", options={"gtol": gtol, "ftol": 1e-15, "maxiter": maxiter})
+    return np.exp(res.x), float(res.fun), res
+

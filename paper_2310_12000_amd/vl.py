@@ -151,6 +151,9 @@ def lib():
                              ctypes.POINTER(vl_stats)]
     L.vl_export.argtypes = [P, I, P, S]
     L.vl_grad_offset.argtypes = [P, P]
+    L.vl_estimate.argtypes = [P, P, P, I, ctypes.POINTER(D), ctypes.POINTER(vl_opts),
+                              ctypes.POINTER(D), I, D, ctypes.POINTER(D), ctypes.POINTER(I),
+                              ctypes.POINTER(I)]
     L.vl_grad_beta.argtypes = [P, P, I, ctypes.POINTER(D)]
     L.vl_export_count.argtypes = [P, I]
     L.vl_export_count.restype = I64
@@ -182,7 +185,8 @@ def lib():
     L.vl_server_free.restype = None
     for f in ("vl_build_vecchia", "vl_set_theta", "vl_find_mode", "vl_neg_log_marglik",
               "vl_predict", "vl_export", "vl_spmm", "vl_trsm", "vl_trsm_noalloc",
-              "vl_set_allocator", "vl_grad_offset", "vl_grad_beta", "vl_timing_enable",
+              "vl_set_allocator", "vl_grad_offset", "vl_grad_beta", "vl_estimate",
+              "vl_timing_enable",
               "vl_timing_read", "vl_batch_create", "vl_batch_fit", "vl_batch_mode",
               "vl_batch_stats", "vl_server_create", "vl_server_submit", "vl_server_wait",
               "vl_server_info"):
@@ -397,6 +401,19 @@ class VecchiaLaplace:
         var = torch.empty(npred, dtype=torch.float64, device=coords_p.device) if want_var else None
         st = vl_predict(self.h, coords_p, Fp, opts, mean, var, allow_no_conv)
         return mean, var, st
+
+    def estimate(self, y, F, lik, theta0, aux=None, opts=None, max_iter=50, grad_tol=1e-6,
+                 allow_no_conv=False):
+        """L-BFGS estimate of theta (vl_estimate); returns (theta, nll, iters, evals)."""
+        opts = opts or vl_default_opts()
+        th = (ctypes.c_double * 2)(*[float(v) for v in theta0])
+        nll, it, ev = ctypes.c_double(), ctypes.c_int(), ctypes.c_int()
+        a = (ctypes.c_double * 1)(float(aux)) if aux is not None else None
+        code = lib().vl_estimate(self.h, _ptr(y), _ptr(F), int(lik), a, ctypes.byref(opts), th,
+                                 int(max_iter), float(grad_tol), ctypes.byref(nll),
+                                 ctypes.byref(it), ctypes.byref(ev))
+        _check(code, allow=(VL_ERR_NO_CONVERGENCE,) if allow_no_conv else ())
+        return (th[0], th[1]), nll.value, it.value, ev.value
 
     def grad_offset(self):
         """dL/dF (device tensor, n) from the last neg_log_marglik with a gradient."""

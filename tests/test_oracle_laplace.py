@@ -542,3 +542,36 @@ def test_offset_gradient_matches_finite_differences():
         # the terms beyond -g are not negligible here: the pin would catch
         # a dropped log-determinant or mode-response term
         assert abs(-(L.lik_grad(L.LIK_BERNOULLI_LOGIT, y, F + b) @ d) - fd) > 8 * se
+
+
+def test_estimate_is_stationary_and_near_the_exact_optimum():
+    """The L-BFGS estimate with a sample average approximation (Sec. 4.1) is
+    a zero of the STE gradient of the deterministic objective, and lies near
+    the optimum of the exact dense Vecchia-Laplace NLL (the STE and SLQ
+    estimators differ from the exact derivative and value by O(t^-1/2); with
+    t = 200 the estimate is within 0.1 of it in log theta)."""
+    from scipy.optimize import minimize
+
+    g = np.random.default_rng(30)
+    n, m = 200, 6
+    X = g.uniform(size=(n, 2))
+    S = V.dense_covariance(X, V.COV_EXPONENTIAL, 1.0, 0.15)
+    b = np.linalg.cholesky(S + 1e-10 * np.eye(n)) @ g.standard_normal(n)
+    y = (g.uniform(size=n) < 1 / (1 + np.exp(-b))).astype(float)
+    F = np.zeros(n)
+    nbr = V.neighbours(X, m)
+    o = L.Opts(cg_tol=1e-10, newton_tol=1e-12, num_probes=200, seed=4)
+    theta, nll, res = L.estimate(X, m, V.COV_EXPONENTIAL, y, F, L.LIK_BERNOULLI_LOGIT, None,
+                                 (0.5, 0.05), o, nbr=nbr, gtol=1e-7)
+    model = L.Model(X, m, V.COV_EXPONENTIAL, theta, nbr=nbr, deriv=True)
+    bb, _, _ = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, o)
+    v0, info = L.neg_log_marglik(model, y, F, L.LIK_BERNOULLI_LOGIT, None, bb, o, want_grad=True)
+    assert abs(v0 - nll) < 1e-9 * abs(nll)
+    # CG counts change with theta, so the objective is smooth only to about
+    # 1e-11 relative: the optimiser stops once steps gain no more than that
+    assert np.max(np.abs(info["grad"] * theta)) < 1e-3
+    exact = minimize(lambda x: _dense_vl_nll(X, nbr, V.COV_EXPONENTIAL, np.exp(x), y, F,
+                                             L.LIK_BERNOULLI_LOGIT),
+                     np.log([0.5, 0.05]), method="Nelder-Mead",
+                     options={"xatol": 1e-8, "fatol": 1e-12, "maxiter": 2000})
+    assert np.max(np.abs(np.log(theta) - exact.x)) < 0.1, (theta, np.exp(exact.x))

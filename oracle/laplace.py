@@ -55,6 +55,7 @@ from . import vecchia as _vec
 LIK_BERNOULLI_LOGIT = 0
 LIK_POISSON = 1
 LIK_GAUSSIAN = 2
+LIK_GAMMA = 3  # log link, mean exp(mu), shape aux (Sec. 5)
 
 PRECOND_VADU = 0
 PRECOND_LRAC = 1
@@ -76,6 +77,10 @@ def lik_logp(lik, y, mu, aux=None):
     if lik == LIK_GAUSSIAN:
         tau2 = float(aux)
         return -0.5 * (y - mu) ** 2 / tau2 - 0.5 * np.log(2.0 * np.pi * tau2)
+    if lik == LIK_GAMMA:
+        # shape a, rate a e^{-mu}: a log a - log Gamma(a) + (a - 1) log y - a mu - a y e^{-mu}
+        a = float(aux)
+        return a * np.log(a) - gammaln(a) + (a - 1.0) * np.log(y) - a * mu - a * y * np.exp(-mu)
     raise ValueError("unknown likelihood")
 
 
@@ -86,6 +91,8 @@ def lik_grad(lik, y, mu, aux=None):
         return y - np.exp(mu)
     if lik == LIK_GAUSSIAN:
         return (y - mu) / float(aux)
+    if lik == LIK_GAMMA:
+        return float(aux) * (y * np.exp(-mu) - 1.0)
     raise ValueError("unknown likelihood")
 
 
@@ -97,6 +104,8 @@ def lik_W(lik, y, mu, aux=None):
         return np.exp(mu)
     if lik == LIK_GAUSSIAN:
         return np.full_like(mu, 1.0 / float(aux))
+    if lik == LIK_GAMMA:
+        return float(aux) * y * np.exp(-mu)
     raise ValueError("unknown likelihood")
 
 
@@ -109,6 +118,8 @@ def lik_dW(lik, y, mu, aux=None):
         return np.exp(mu)
     if lik == LIK_GAUSSIAN:
         return np.zeros_like(mu)
+    if lik == LIK_GAMMA:
+        return -float(aux) * y * np.exp(-mu)
     raise ValueError("unknown likelihood")
 
 

@@ -40,7 +40,8 @@ def _liks(lik, aux=None):
 # ---------------------------------------------------------------- likelihoods
 @pytest.mark.parametrize("lik,aux,y", [(L.LIK_BERNOULLI_LOGIT, None, np.array([0.0, 1.0, 1.0, 0.0])),
                                        (L.LIK_POISSON, None, np.array([0.0, 3.0, 7.0, 1.0])),
-                                       (L.LIK_GAUSSIAN, 0.3, np.array([0.2, -1.0, 2.0, 0.0]))])
+                                       (L.LIK_GAUSSIAN, 0.3, np.array([0.2, -1.0, 2.0, 0.0])),
+                                       (L.LIK_GAMMA, 2.5, np.array([0.3, 1.7, 4.0, 0.05]))])
 def test_likelihood_derivatives_finite_differences(lik, aux, y):
     mu = np.array([-1.3, 0.2, 1.1, 2.5])
     h = 1e-5
@@ -575,3 +576,17 @@ def test_estimate_is_stationary_and_near_the_exact_optimum():
                      np.log([0.5, 0.05]), method="Nelder-Mead",
                      options={"xatol": 1e-8, "fatol": 1e-12, "maxiter": 2000})
     assert np.max(np.abs(np.log(theta) - exact.x)) < 0.1, (theta, np.exp(exact.x))
+
+
+def test_gamma_likelihood_is_the_gamma_density():
+    """Gamma with log link (Sec. 5): mean e^mu, shape a, i.e. scale e^mu / a;
+    the log-density equals scipy's, and W = -d2 log p / d mu2 > 0 (log-concave
+    in mu)."""
+    from scipy.stats import gamma as G
+    y = np.array([0.05, 0.4, 1.0, 3.5, 12.0])
+    mu = np.array([-1.0, 0.3, 0.0, 1.2, 2.0])
+    for a in (0.7, 2.5, 30.0):
+        np.testing.assert_allclose(L.lik_logp(L.LIK_GAMMA, y, mu, a),
+                                   G.logpdf(y, a, scale=np.exp(mu) / a), rtol=1e-12)
+        assert np.all(L.lik_W(L.LIK_GAMMA, y, mu, a) > 0)
+

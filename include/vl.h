@@ -66,7 +66,8 @@ typedef enum { VL_COV_EXPONENTIAL = 0, VL_COV_MATERN32 = 1 } vl_cov;
 typedef enum {
   VL_LIK_BERNOULLI_LOGIT = 0, /* y in {0,1}, mu = logit P(y = 1)            */
   VL_LIK_POISSON_LOG = 1,     /* y in {0,1,2,...}, mu = log E[y]            */
-  VL_LIK_GAUSSIAN = 2         /* y real, aux[0] = noise variance tau^2      */
+  VL_LIK_GAUSSIAN = 2,        /* y real, aux[0] = noise variance tau^2      */
+  VL_LIK_GAMMA = 3            /* y > 0, mu = log E[y], aux[0] = shape a > 0 */
 } vl_lik;
 
 typedef enum { VL_PREC_VADU = 0, VL_PREC_LRAC = 1 } vl_precond;

@@ -205,6 +205,27 @@ static Status do_export(Model& M, int which, void* dst, size_t bytes) {
   }
 }
 
+Status likelihood_aux(int lik, const double* aux_host, double* aux) {
+  *aux = 0.0;
+  switch (lik) {
+    case VL_LIK_BERNOULLI_LOGIT:
+    case VL_LIK_POISSON_LOG:
+      return Status::ok();
+    case VL_LIK_GAUSSIAN:
+      if (!aux_host || !(aux_host[0] > 0.0) || !std::isfinite(aux_host[0]))
+        return Status::invalid("Gaussian needs tau2 > 0");
+      *aux = aux_host[0];
+      return Status::ok();
+    case VL_LIK_GAMMA:
+      if (!aux_host || !(aux_host[0] > 0.0) || !std::isfinite(aux_host[0]))
+        return Status::invalid("Gamma needs a shape > 0");
+      *aux = aux_host[0];
+      return Status::ok();
+    default:
+      return Status::invalid("unknown likelihood");
+  }
+}
+
 static Status check_opts(const vl_opts* o) {
   if (!o) return Status::invalid("opts is null");
   if (o->max_newton < 1 || o->max_cg < 1) return Status::invalid("iteration caps must be >= 1");
@@ -324,13 +345,8 @@ vl_status vl_find_mode(vl_model* h, const double* y, const double* F, int lik,
     const double t0 = vl::now_ms();
     if (!h || !y) return vl::Status::invalid("null handle or y");
     VL_TRY(vl::check_opts(o));
-    if (lik != VL_LIK_BERNOULLI_LOGIT && lik != VL_LIK_POISSON_LOG && lik != VL_LIK_GAUSSIAN)
-      return vl::Status::invalid("unknown likelihood");
     double aux = 0.0;
-    if (lik == VL_LIK_GAUSSIAN) {
-      if (!aux_host || !(aux_host[0] > 0.0)) return vl::Status::invalid("Gaussian needs tau2 > 0");
-      aux = aux_host[0];
-    }
+    VL_TRY(vl::likelihood_aux(lik, aux_host, &aux));
     if (o->precond == VL_PREC_LRAC && (o->lrac_rank < 1 || o->lrac_rank > 1024))
       return vl::Status::invalid("lrac_rank must be in [1, 1024]");
     Model& M = *h;

@@ -746,14 +746,9 @@ vl_status vl_batch_create(const vl_problem* problems, int nprob, int lik,
   try {
     if (!out) return vl::report(vl::Status::invalid("out is null"));
     *out = nullptr;
-    if (lik != VL_LIK_BERNOULLI_LOGIT && lik != VL_LIK_POISSON_LOG && lik != VL_LIK_GAUSSIAN)
-      return vl::report(vl::Status::invalid("unknown likelihood"));
     double aux = 0.0;
-    if (lik == VL_LIK_GAUSSIAN) {
-      if (!aux_host || !(aux_host[0] > 0.0))
-        return vl::report(vl::Status::invalid("Gaussian needs tau2 > 0"));
-      aux = aux_host[0];
-    }
+    vl::Status ls = vl::likelihood_aux(lik, aux_host, &aux);
+    if (!ls.good()) return vl::report(ls);
     vl::Batch* b = nullptr;
     vl::Status s = vl::batch_create(problems, nprob, lik, aux,
                                     static_cast<hipStream_t>(hip_stream), &b);

@@ -25,6 +25,10 @@ __device__ __forceinline__ double lik_logp(int lik, double y, double mu, double 
     return y * mu - sp;
   }
   if (lik == VL_LIK_POISSON_LOG) return y * mu - exp(mu) - lgamma(y + 1.0);
+  if (lik == VL_LIK_GAMMA) {
+    // shape a = aux, rate a e^{-mu} (mean e^mu)
+    return aux * log(aux) - lgamma(aux) + (aux - 1.0) * log(y) - aux * mu - aux * y * exp(-mu);
+  }
   const double r = y - mu;
   return -0.5 * r * r / aux - 0.5 * log(6.283185307179586 * aux);
 }
@@ -42,6 +46,11 @@ __device__ __forceinline__ void lik_derivs(int lik, double y, double mu, double 
     *g = y - e;
     *W = e;
     *dW = e;
+  } else if (lik == VL_LIK_GAMMA) {
+    const double ay = aux * y * exp(-mu);
+    *g = ay - aux;
+    *W = ay;
+    *dW = -ay;
   } else {
     *g = (y - mu) / aux;
     *W = 1.0 / aux;
@@ -63,7 +72,9 @@ __global__ void lik_rows_kernel(int64_t n, int lik, double aux, const double* __
   const double mu = (F ? F[i] : 0.0) + bi;
   double g, W, dW;
   lik_derivs(lik, y[i], mu, aux, &g, &W, &dW);
-  if (!isfinite(g) || !isfinite(W)) raise_error(status, kErrNonfinite);
+  // a Gamma response must be positive (log y enters the density)
+  if (!isfinite(g) || !isfinite(W) || (lik == VL_LIK_GAMMA && !(y[i] > 0.0)))
+    raise_error(status, kErrNonfinite);
   if (g_out) g_out[i] = g;
   if (W_out) W_out[i] = W;
   if (rhs_out) rhs_out[i] = W * bi + g;

@@ -385,6 +385,9 @@ Status fill_double(double* p, double v, int64_t count, hipStream_t s);
 Status exclusive_scan_int(const int* in, int* out, int64_t count, hipStream_t s);
 Status copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t s);
 Status read_status(Model& M);
+// Validates a likelihood code and takes its parameter from aux_host[0]
+// (Gaussian noise variance or Gamma shape; 0 for the others).
+Status likelihood_aux(int lik, const double* aux_host, double* aux);
 
 // ---- neighbour search (knn.hip)
 Status knn_build_grid(Model& M);

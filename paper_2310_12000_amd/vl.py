@@ -31,6 +31,7 @@ VL_COV_MATERN32 = 1
 VL_LIK_BERNOULLI_LOGIT = 0
 VL_LIK_POISSON_LOG = 1
 VL_LIK_GAUSSIAN = 2
+VL_LIK_GAMMA = 3
 VL_PREC_VADU = 0
 VL_PREC_LRAC = 1
 VL_FP64 = 0

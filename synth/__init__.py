@@ -9,7 +9,8 @@ The workloads follow the paper's simulation setting (Sec. 4.1): locations
 i.i.d. uniform on [0,1]^2 (their generation order is the random ordering of
 the Vecchia approximation), a zero-mean GP latent field with exponential or
 Matern-3/2 covariance and sigma^2 = 1, and Bernoulli-logit or Poisson
-log-link responses.
+log-link responses; the Gamma log-link response (Sec. 5) is drawn with a
+given shape a and mean e^mu.
 
 Latent fields:
   * n <= 5000: exact draw, dense Cholesky of the covariance matrix.
@@ -29,6 +30,7 @@ COV_MATERN32 = 1
 LIK_BERNOULLI_LOGIT = 0
 LIK_POISSON = 1
 LIK_GAUSSIAN = 2
+LIK_GAMMA = 3
 
 
 def _rng(seed, stream):
@@ -78,7 +80,7 @@ def latent_field(coords, kind, sigma2, rho, seed, nfeat=2048, chunk=1 << 16):
     return out
 
 
-def responses(lik, mu, seed, tau2=None):
+def responses(lik, mu, seed, tau2=None, shape=None):
     g = _rng(seed, 300)
     if lik == LIK_BERNOULLI_LOGIT:
         p = 1.0 / (1.0 + np.exp(-mu))
@@ -87,6 +89,8 @@ def responses(lik, mu, seed, tau2=None):
         return g.poisson(np.exp(mu)).astype(np.float64)
     if lik == LIK_GAUSSIAN:
         return mu + math.sqrt(tau2) * g.standard_normal(mu.shape)
+    if lik == LIK_GAMMA:
+        return g.gamma(shape, np.exp(mu) / shape)
     raise ValueError("unknown likelihood")
 
 
@@ -121,7 +125,7 @@ def make(name=None, seed=0, **override):
     coords = locations(n, seed)
     b = latent_field(coords, spec["kind"], spec["sigma2"], spec["rho"], seed)
     F = np.full(n, float(spec.get("F", 0.0)))
-    y = responses(spec["lik"], F + b, seed, spec.get("tau2"))
+    y = responses(spec["lik"], F + b, seed, spec.get("tau2"), spec.get("shape"))
     npred = spec.get("n_pred", 0)
     spec.update(coords=coords, y=y, F=F, b_true=b,
                 coords_pred=locations(npred, seed, stream=1),

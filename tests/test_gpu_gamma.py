@@ -1,0 +1,142 @@
+"""GPU parity for the Gamma likelihood with log link (Sec. 5) and a linear
+predictor F = X beta: mode, SLQ negative log-marginal likelihood, the
+theta-gradient, the offset gradient and its beta projection X^T dL/dF, and
+predictive means and variances, against the FP64 oracle on the same seeded
+inputs and probes (relative 1e-9, replaying the device's iteration counts
+where a stopping decision falls the other way).  Also the argument checks:
+a shape that is not positive is refused, a non-positive response is flagged
+as non-finite."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import synth  # noqa: E402
+from oracle import laplace as OL  # noqa: E402
+from tests.gpu_common import (dev, host, oracle_mode_matching, opts_pair, rel_err,  # noqa: E402
+                               rel_err_elem, say)
+
+TOL = 1e-9
+SHAPE = 2.0
+BETA = np.array([0.4, -0.6, 0.25])
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2310_12000_amd as P
+    P.lib()
+    return P
+
+
+def _design(coords, seed):
+    """Intercept, the first coordinate and a Gaussian covariate."""
+    g = np.random.default_rng(seed)
+    n = coords.shape[0]
+    return np.ascontiguousarray(np.column_stack([np.ones(n), coords[:, 0],
+                                                 g.standard_normal(n)]))
+
+
+@pytest.fixture(scope="module")
+def gamma_case():
+    # n = 2,001 (a ragged tail on every 64-row tile), Matern-3/2, range 0.1,
+    # m = 10, Gamma shape 2 with F = X beta; 50 probes, CG tolerance 1e-8
+    n = 2001
+    coords = synth.locations(n, seed=23)
+    b = synth.latent_field(coords, synth.COV_MATERN32, 1.0, 0.1, seed=23)
+    X = _design(coords, 29)
+    F = X @ BETA
+    y = synth.responses(synth.LIK_GAMMA, F + b, seed=23, shape=SHAPE)
+    cp = synth.locations(300, seed=23, stream=1)
+    Xp = _design(cp, 31)
+    w = dict(n=n, m=10, kind=synth.COV_MATERN32, theta=(1.0, 0.1), coords=coords, y=y, F=F,
+             X=X, coords_pred=cp, Fp=Xp @ BETA, t=50, s=64)
+    model = OL.Model(coords, w["m"], w["kind"], w["theta"], deriv=True)
+    return w, model
+
+
+@pytest.fixture(scope="module")
+def gamma_fit(P, gamma_case):
+    w, _ = gamma_case
+    say("case: gamma n=2001 mode + nll + grad + grad_beta + predict")
+    o, go = opts_pair(P, cg_tol=1e-8, pred_cg_tol=1e-8, num_probes=w["t"],
+                      num_pred_samples=w["s"], seed=5)
+    g = P.VecchiaLaplace(dev(w["coords"]), w["m"], w["kind"], w["theta"], want_deriv=True)
+    mode, st = g.find_mode(dev(w["y"]), dev(w["F"]), P.VL_LIK_GAMMA, SHAPE, go)
+    out = dict(mode=host(mode), newton_cg=host(g.export("newton_cg_iters")).tolist(),
+               halvings=host(g.export("newton_halvings")).tolist(), W=host(g.export("W")),
+               opts=o)
+    out["nll"], out["grad"], _ = g.neg_log_marglik(go, want_grad=True)
+    out["slq_iters"] = host(g.export("block_iters")).tolist()
+    out["grad_F"] = host(g.grad_offset())
+    out["grad_beta"] = g.grad_beta(dev(w["X"]))
+    mean, var, _ = g.predict(dev(w["coords_pred"]), dev(w["Fp"]), go)
+    out["pred_iters"] = host(g.export("block_iters")).tolist()
+    out["mean"], out["var"] = host(mean), host(var)
+    g.close()
+    return out
+
+
+def _oracle_mode(w, model, f):
+    return oracle_mode_matching(model, w["y"], w["F"], OL.LIK_GAMMA, SHAPE, f["opts"],
+                                f["newton_cg"], gpu_halvings=f["halvings"])
+
+
+def test_gamma_mode(gamma_case, gamma_fit):
+    w, model = gamma_case
+    f = gamma_fit
+    b, W, st, replayed = _oracle_mode(w, model, f)
+    say(f"newton cg gpu={f['newton_cg']} halvings={f['halvings']} oracle={st['cg_iters']} "
+        f"halvings={st['halvings']} replayed={replayed}")
+    assert rel_err(f["mode"], b) < TOL
+    np.testing.assert_allclose(f["W"], W, rtol=1e-9)
+
+
+def test_gamma_nll_gradients(gamma_case, gamma_fit):
+    w, model = gamma_case
+    f = gamma_fit
+    b, _, _, _ = _oracle_mode(w, model, f)
+    nll, info = OL.neg_log_marglik(model, w["y"], w["F"], OL.LIK_GAMMA, SHAPE, b, f["opts"],
+                                   want_grad=True, replay_cg=f["slq_iters"])
+    say(f"nll device {f['nll']!r} oracle {nll!r}")
+    assert abs(f["nll"] - nll) <= TOL * abs(nll)
+    assert rel_err_elem(f["grad"], info["grad"]) < TOL
+    assert rel_err(f["grad_F"], info["grad_F"]) < TOL
+    # X^T dL/dF sums terms of both signs and can be far smaller than its
+    # terms, so its bar is the offset-gradient bar carried through the sum:
+    # |X|^T (TOL max|dL/dF|) per component
+    gb = w["X"].T @ info["grad_F"]
+    bar = TOL * np.max(np.abs(info["grad_F"])) * np.abs(w["X"]).sum(axis=0)
+    say(f"beta gradient device {f['grad_beta']} oracle {gb} bar {bar}")
+    assert np.all(np.abs(np.array(f["grad_beta"]) - gb) <= bar)
+    # and the device's projection is X^T of its own offset gradient
+    scale = np.max(np.abs(w["X"]).T @ np.abs(f["grad_F"]))
+    np.testing.assert_allclose(f["grad_beta"], w["X"].T @ f["grad_F"], rtol=0, atol=1e-12 * scale)
+
+
+def test_gamma_predict(gamma_case, gamma_fit):
+    w, model = gamma_case
+    f = gamma_fit
+    b, W, _, _ = _oracle_mode(w, model, f)
+    mean, var, _ = OL.predict(model, w["coords_pred"], w["Fp"], b, W, f["opts"],
+                              replay_cg=f["pred_iters"])
+    assert rel_err(f["mean"], mean) < TOL
+    assert rel_err_elem(f["var"], var) < TOL
+
+
+def test_gamma_argument_checks(P, gamma_case):
+    w, _ = gamma_case
+    g = P.VecchiaLaplace(dev(w["coords"][:300]), 10, w["kind"], w["theta"], want_deriv=False)
+    y = dev(w["y"][:300])
+    for bad in (None, 0.0, -1.0, float("inf")):
+        with pytest.raises(P.VLError) as e:
+            g.find_mode(y, None, P.VL_LIK_GAMMA, bad)
+        assert e.value.code == P.VL_ERR_INVALID_ARG
+    y0 = w["y"][:300].copy()
+    y0[17] = 0.0
+    with pytest.raises(P.VLError) as e:
+        g.find_mode(dev(y0), None, P.VL_LIK_GAMMA, SHAPE)
+    assert e.value.code == P.VL_ERR_NONFINITE
+    g.close()

@@ -3,7 +3,9 @@
 Plain FP64 NumPy/SciPy, following the paper step by step:
 
   likelihoods      Sec. 2 (log-concave p(y|mu)); Bernoulli-logit of Sec. 4.1,
-                   Poisson log-link, Gaussian (exact-Laplace special case)
+                   Poisson log-link, Gaussian (exact-Laplace special case),
+                   Gamma log-link with shape xi (Sec. 5); derivatives in
+                   mu and in the auxiliary parameter xi
   pcg              appendix algorithm "Preconditioned conjugate gradient
                    algorithm with Lanczos tridiagonal matrix", run column by
                    column (each probe has its own recurrence)
@@ -17,7 +19,8 @@ Plain FP64 NumPy/SciPy, following the paper step by step:
                    VADU STE / control-variate formulas of the appendix
                    "Derivatives of log-determinants ... Preconditioner VADU";
                    also the gradient in the offset F (for F = X beta the
-                   beta-gradient is X^T of it)
+                   beta-gradient is X^T of it) and in the likelihood's
+                   auxiliary parameter xi (Gaussian tau^2, Gamma shape)
   predict          eq. (latentpostpredictive) with B_p = I and the simulation
                    algorithm (Sec. 3.3.1, Alg. simAlgo)
 
@@ -47,7 +50,7 @@ the small-n pins of the same code).
 import numpy as np
 import scipy.sparse as sp
 from scipy.sparse.linalg import spsolve_triangular
-from scipy.special import gammaln
+from scipy.special import digamma, gammaln
 
 from . import rng as _rng
 from . import vecchia as _vec
@@ -121,6 +124,41 @@ def lik_dW(lik, y, mu, aux=None):
     if lik == LIK_GAMMA:
         return -float(aux) * y * np.exp(-mu)
     raise ValueError("unknown likelihood")
+
+
+def lik_has_aux(lik):
+    """Whether the likelihood has an auxiliary parameter xi (Sec. 2)."""
+    return lik in (LIK_GAUSSIAN, LIK_GAMMA)
+
+
+def lik_dlogp_dxi(lik, y, mu, aux):
+    """d log p(y_i | mu_i, xi) / d xi per row (Gaussian xi = tau^2, Gamma xi =
+    shape a)."""
+    if lik == LIK_GAUSSIAN:
+        tau2 = float(aux)
+        return 0.5 * (y - mu) ** 2 / tau2 ** 2 - 0.5 / tau2
+    if lik == LIK_GAMMA:
+        a = float(aux)
+        return np.log(a) + 1.0 - digamma(a) + np.log(y) - mu - y * np.exp(-mu)
+    raise ValueError("likelihood without an auxiliary parameter")
+
+
+def lik_dgrad_dxi(lik, y, mu, aux):
+    """d^2 log p / d xi d mu per row."""
+    if lik == LIK_GAUSSIAN:
+        return -(y - mu) / float(aux) ** 2
+    if lik == LIK_GAMMA:
+        return y * np.exp(-mu) - 1.0
+    raise ValueError("likelihood without an auxiliary parameter")
+
+
+def lik_dW_dxi(lik, y, mu, aux):
+    """d W_ii / d xi = -d^3 log p / d xi d mu^2 per row."""
+    if lik == LIK_GAUSSIAN:
+        return np.full_like(mu, -1.0 / float(aux) ** 2)
+    if lik == LIK_GAMMA:
+        return y * np.exp(-mu)
+    raise ValueError("likelihood without an auxiliary parameter")
 
 
 # ----------------------------------------------------------------------------
@@ -465,7 +503,7 @@ def neg_log_marglik(model, y, F, lik, aux, b, opts, replay_cg=None, L=None,
         grad, ginfo = _grad_theta_vadu(model, y, F, lik, aux, b, W, res, opts,
                                        replay_grad_cg)
         info["grad"] = grad
-        info.update(ginfo)  # includes grad_F, the gradient in the offset F
+        info.update(ginfo)  # includes grad_F (offset) and, with a xi, grad_xi
     return nll, info
 
 
@@ -536,6 +574,25 @@ def _grad_theta_vadu(model, y, F, lik, aux, b, W, res, opts, replay_grad_cg):
     # at the mode d L / d b* = (1/2) d log det / d mu (the other terms cancel),
     # so d L / d F = -g + dL_db - W o (A^{-1} dL_db).
     parts["grad_F"] = -lik_grad(lik, y, F + b, aux) + dL_db - W * wsol
+    if lik_has_aux(lik):
+        # d L / d xi (same appendix): -d log p / d xi + (1/2) d log det / d xi
+        # + (d L / d b*)^T d b* / d xi with d b* / d xi = A^{-1} d^2 log p /
+        # d xi d mu, i.e. w^T d^2 log p / d xi d mu (A symmetric).  The log
+        # determinant's xi-derivative uses the VADU STE with
+        # h = (A^{-1}z)^T dW/dxi P^{-1}z, control variate r = (P^{-1}z)^T B^T
+        # dW/dxi B P^{-1}z and its known mean tr((W + D^{-1})^{-1} dW/dxi).
+        mu = F + b
+        dWx = lik_dW_dxi(lik, y, mu, aux)
+        h_xi = np.sum(dWx[:, None] * U * V, axis=0)
+        r_xi = np.sum(dWx[:, None] * BV * BV, axis=0)
+        c_xi = float(_cv_weight(h_xi, r_xi))
+        trP_xi = float(np.sum(dWx / wd))
+        dlogdet_xi = c_xi * trP_xi + float(np.mean(h_xi - c_xi * r_xi))
+        dlogp_xi = float(np.sum(lik_dlogp_dxi(lik, y, mu, aux)))
+        implicit_xi = float(wsol @ lik_dgrad_dxi(lik, y, mu, aux))
+        parts.update(grad_xi=-dlogp_xi + 0.5 * dlogdet_xi + implicit_xi, h_xi=h_xi, r_xi=r_xi,
+                     c_xi=c_xi, trP_xi=trP_xi, dlogdet_xi=dlogdet_xi, dlogp_xi=dlogp_xi,
+                     implicit_xi=implicit_xi)
     for k in range(2):
         dD = model.dD[k]
         dBb = model.dB[k] @ b

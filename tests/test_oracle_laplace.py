@@ -25,6 +25,8 @@ def _problem(n=80, m=6, kind=V.COV_EXPONENTIAL, theta=(1.0, 0.2), lik=L.LIK_BERN
         y = (g.uniform(size=n) < 1 / (1 + np.exp(-(Fv + b)))).astype(float)
     elif lik == L.LIK_POISSON:
         y = g.poisson(np.exp(Fv + b)).astype(float)
+    elif lik == L.LIK_GAMMA:
+        y = g.gamma(2.5, np.exp(Fv + b) / 2.5)
     else:
         y = Fv + b + 0.5 * g.standard_normal(n)
     model = L.Model(X, m, kind, theta, deriv=deriv)
@@ -51,6 +53,23 @@ def test_likelihood_derivatives_finite_differences(lik, aux, y):
     np.testing.assert_allclose(L.lik_grad(lik, y, mu, aux), fd1, rtol=1e-7, atol=1e-9)
     np.testing.assert_allclose(L.lik_W(lik, y, mu, aux), -fd2, rtol=1e-7, atol=1e-9)
     np.testing.assert_allclose(L.lik_dW(lik, y, mu, aux), fd3, rtol=1e-6, atol=1e-9)
+
+
+@pytest.mark.parametrize("lik,aux,y", [(L.LIK_GAUSSIAN, 0.3, np.array([0.2, -1.0, 2.0, 0.0])),
+                                       (L.LIK_GAMMA, 2.5, np.array([0.3, 1.7, 4.0, 0.05])),
+                                       (L.LIK_GAMMA, 0.6, np.array([0.3, 1.7, 4.0, 0.05]))])
+def test_likelihood_xi_derivatives_finite_differences(lik, aux, y):
+    # derivatives in the auxiliary parameter (tau^2, Gamma shape) against
+    # central differences of log p, d log p / d mu and W in xi
+    mu = np.array([-1.3, 0.2, 1.1, 2.5])
+    h = 1e-6 * aux
+    d = lambda f: (f(lik, y, mu, aux + h) - f(lik, y, mu, aux - h)) / (2 * h)  # noqa: E731
+    np.testing.assert_allclose(L.lik_dlogp_dxi(lik, y, mu, aux), d(L.lik_logp), rtol=1e-7,
+                               atol=1e-8)
+    np.testing.assert_allclose(L.lik_dgrad_dxi(lik, y, mu, aux), d(L.lik_grad), rtol=1e-7,
+                               atol=1e-8)
+    np.testing.assert_allclose(L.lik_dW_dxi(lik, y, mu, aux), d(L.lik_W), rtol=1e-7, atol=1e-8)
+    assert not L.lik_has_aux(L.LIK_POISSON) and not L.lik_has_aux(L.LIK_BERNOULLI_LOGIT)
 
 
 def test_likelihood_normalisation():
@@ -590,3 +609,70 @@ def test_gamma_likelihood_is_the_gamma_density():
                                    G.logpdf(y, a, scale=np.exp(mu) / a), rtol=1e-12)
         assert np.all(L.lik_W(L.LIK_GAMMA, y, mu, a) > 0)
 
+
+
+# ------------------------------------------------------------ xi-gradient
+def test_xi_gradient_gaussian_closed_form():
+    """Gaussian likelihood, xi = tau^2: L^VLA is the exact negative log-density
+    of N(F, K), K = Sigma~ + tau^2 I, whose tau^2-derivative is
+    tr(K^{-1})/2 - |K^{-1}(y - F)|^2/2.  With m = 0 (B = I, P_VADU = A) the
+    STE is exact, so the oracle must match to rounding; with m = 5 its mean
+    over probe sets must lie within 5 standard errors."""
+    tau2 = 0.3
+    for m in (0, 5):
+        model, y, F = _problem(n=50, m=m, seed=31, lik=L.LIK_GAUSSIAN, deriv=True, F=0.2)
+        o0 = L.Opts(cg_tol=1e-13, newton_tol=1e-15)
+        b, W, _ = L.find_mode(model, y, F, L.LIK_GAUSSIAN, tau2, o0)
+        K = np.linalg.inv(DR.dense_precision(model.B, model.D)) + tau2 * np.eye(model.n)
+        Ki = np.linalg.inv(K)
+        ref = 0.5 * np.trace(Ki) - 0.5 * np.sum((Ki @ (y - F)) ** 2)
+        gs = []
+        for seed in range(1 if m == 0 else 8):
+            o = L.Opts(cg_tol=1e-13, newton_tol=1e-15, num_probes=200, seed=seed)
+            _, info = L.neg_log_marglik(model, y, F, L.LIK_GAUSSIAN, tau2, b, o, want_grad=True)
+            gs.append(info["grad_xi"])
+        if m == 0:
+            assert abs(gs[0] - ref) <= 1e-10 * abs(ref)
+        else:
+            se = np.std(gs, ddof=1) / np.sqrt(len(gs))
+            assert abs(np.mean(gs) - ref) <= 5 * se + 1e-8 * abs(ref), (np.mean(gs), ref, se)
+
+
+def _dense_nll_aux(model, y, F, lik, aux):
+    Q = DR.dense_precision(model.B, model.D)
+    lp, lg, lw = _liks(lik, aux)
+    return DR.dense_nll(Q, y, F, lp, lg, lw)[0]
+
+
+def test_xi_gradient_gamma_matches_finite_differences():
+    """Gamma shape a: the STE xi-gradient (VADU control variate, implicit mode
+    response) against central differences of the exact dense Vecchia-Laplace
+    NLL in a.  m = 0: the STE is exact and must match to the difference
+    error.  m = 5: within 5 standard errors over independent probe sets, and
+    dropping the log-determinant or the mode-response term moves the value by
+    more than 8 standard errors."""
+    a = 2.5
+    for m in (0, 5):
+        model, y, F = _problem(n=45, m=m, seed=33, lik=L.LIK_GAMMA, deriv=True, theta=(0.8, 0.3))
+        o0 = L.Opts(cg_tol=1e-13, newton_tol=1e-15)
+        b, W, _ = L.find_mode(model, y, F, L.LIK_GAMMA, a, o0)
+        h = 1e-5
+        fd = (_dense_nll_aux(model, y, F, L.LIK_GAMMA, a + h)
+              - _dense_nll_aux(model, y, F, L.LIK_GAMMA, a - h)) / (2 * h)
+        infos = []
+        for seed in range(1 if m == 0 else 8):
+            o = L.Opts(cg_tol=1e-13, newton_tol=1e-15, num_probes=400, seed=seed)
+            infos.append(L.neg_log_marglik(model, y, F, L.LIK_GAMMA, a, b, o, want_grad=True)[1])
+        gs = np.array([i["grad_xi"] for i in infos])
+        if m == 0:
+            assert abs(gs[0] - fd) <= 1e-7 * (1 + abs(fd)), (gs[0], fd)
+            continue
+        se = gs.std(ddof=1) / np.sqrt(len(gs))
+        assert abs(gs.mean() - fd) <= 5 * se + 1e-7 * (1 + abs(fd)), (gs.mean(), fd, se)
+        # Rademacher probes make B P^{-1} z = (W + D^{-1})^{-1/2} eps, so every
+        # control-variate value equals its known mean tr(P^{-1} dP/dxi)
+        for i in infos:
+            np.testing.assert_allclose(i["r_xi"], i["trP_xi"], rtol=1e-10)
+        no_logdet = np.mean([i["grad_xi"] - 0.5 * i["dlogdet_xi"] for i in infos])
+        no_implicit = np.mean([i["grad_xi"] - i["implicit_xi"] for i in infos])
+        assert abs(no_logdet - fd) > 8 * se and abs(no_implicit - fd) > 8 * se

@@ -260,6 +260,16 @@ vl_status vl_grad_offset(vl_model* h, double* grad_F);
  * X^T dL/dF from the same call.  X device, n x p row-major.  Synchronises. */
 vl_status vl_grad_beta(vl_model* h, const double* X, int p, double* grad_beta_host);
 
+/* Gradient of the same call in the likelihood's auxiliary parameter xi
+ * (App. "Gradients of Vecchia-Laplace approximations": the explicit term,
+ * the STE of the log-determinant's xi-derivative with the VADU control
+ * variate, and the mode's response A^{-1} d^2 log p / d xi d mu), for
+ * VL_LIK_GAUSSIAN (xi = tau^2) and VL_LIK_GAMMA (xi = shape a).
+ *   grad_xi_host host, 1.
+ * VL_ERR_INVALID_ARG for a likelihood without xi; VL_ERR_STATE before a
+ * gradient call or after a later vl_set_theta / vl_find_mode. */
+vl_status vl_grad_aux(vl_model* h, double* grad_xi_host);
+
 /* Predictive latent mean and simulated variance (eq. latentpostpredictive,
  * Alg. simAlgo) at n_p new locations conditioned on the m nearest training
  * locations.

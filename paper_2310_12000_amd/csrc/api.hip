@@ -329,6 +329,7 @@ vl_status vl_set_theta(vl_model* h, const double* theta_host) {
     h->rho = theta_host[1];
     h->has_mode = false;
     h->has_grad_F = false;
+    h->has_grad_xi = false;
     h->lrac_ready = false;
     const double t0 = vl::now_ms();
     VL_TRY(vl::compute_factor(*h));
@@ -354,6 +355,7 @@ vl_status vl_find_mode(vl_model* h, const double* y, const double* F, int lik,
     M.aux = aux;
     M.has_mode = false;
     M.has_grad_F = false;
+    M.has_grad_xi = false;
     VL_TRY(M.y.reserve(M.n));
     VL_TRY(vl::copy_d2d(M.y.p, y, sizeof(double) * M.n, M.stream));
     if (F) {
@@ -444,6 +446,20 @@ vl_status vl_grad_beta(vl_model* h, const double* X, int p, double* grad_beta_ho
   return vl::guarded([&]() -> vl::Status {
     if (!h || !X || !grad_beta_host) return vl::Status::invalid("null argument");
     return vl::grad_beta(*h, X, p, grad_beta_host);
+  });
+}
+
+vl_status vl_grad_aux(vl_model* h, double* grad_xi_host) {
+  vl::CallStream cs(h ? h->stream : nullptr);
+  return vl::guarded([&]() -> vl::Status {
+    if (!h || !grad_xi_host) return vl::Status::invalid("null argument");
+    if (!vl::lik_has_aux(h->lik))
+      return vl::Status::invalid("the likelihood has no auxiliary parameter");
+    if (!h->has_grad_xi)
+      return vl::Status::make(VL_ERR_STATE,
+                              "no xi-gradient: call vl_neg_log_marglik with a gradient");
+    *grad_xi_host = h->grad_xi;
+    return vl::Status::ok();
   });
 }
 

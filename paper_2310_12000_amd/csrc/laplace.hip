@@ -58,6 +58,26 @@ __device__ __forceinline__ void lik_derivs(int lik, double y, double mu, double 
   }
 }
 
+// Derivatives in the auxiliary parameter xi (Gaussian xi = tau^2, Gamma
+// xi = shape a): dlp = d log p / d xi less its row-independent part (the
+// Gamma's log a + 1 - digamma(a), added on the host), dg = d^2 log p /
+// d xi d mu, dWx = d W / d xi.
+__device__ __forceinline__ void lik_xi_derivs(int lik, double y, double mu, double aux,
+                                              double* dlp, double* dg, double* dWx) {
+  if (lik == VL_LIK_GAMMA) {
+    const double ye = y * exp(-mu);
+    *dlp = log(y) - mu - ye;
+    *dg = ye - 1.0;
+    *dWx = ye;
+  } else {  // Gaussian
+    const double r = y - mu;
+    const double it2 = 1.0 / (aux * aux);
+    *dlp = 0.5 * r * r * it2 - 0.5 / aux;
+    *dg = -r * it2;
+    *dWx = -it2;
+  }
+}
+
 // Per row: g, W, rhs = W b + g, s = 1 / (W + D^{-1}), sq = sqrt(W + D^{-1}),
 // dW.  Any output may be null.
 __global__ void lik_rows_kernel(int64_t n, int lik, double aux, const double* __restrict__ y,
@@ -301,15 +321,16 @@ Status find_mode(Model& M, const vl_opts& o, vl_stats* st) {
 //   h_ic = dW_i u_ic v_ic,  r_ic = dW_i (B v)_ic^2,
 //   dlogdet/dmu_i = c_i dW_i / (W_i + 1/D_i) + mean_c (h_ic - c_i r_ic),
 // with c_i = Cov_c(h, r) / Var_c(r) (0 when Var_c(r) <= 1e-10 mean_c(r)^2);
-// dLdb_i = dlogdet/dmu_i / 2.
+// dLdb_i = dlogdet/dmu_i / 2.  With dWx (d W / d xi, nullable) also the
+// xi-terms summed over rows: h_xi = u' dWx v, r_xi = (Bv)' dWx (Bv).
 __global__ __launch_bounds__(256) void grad_probe_kernel(
     ChunkGrid g, int m, const int* __restrict__ nbr, const double* __restrict__ bval,
     const double* __restrict__ dbval, const double* __restrict__ U,
     const double* __restrict__ V, const double* __restrict__ D,
     const double* __restrict__ dd_s2, const double* __restrict__ dd_rho,
-    const double* __restrict__ W, const double* __restrict__ dW, double* __restrict__ dLdb,
-    double* __restrict__ part) {
-  double h0 = 0.0, r0 = 0.0, h1 = 0.0, r1 = 0.0;
+    const double* __restrict__ W, const double* __restrict__ dW,
+    const double* __restrict__ dWx, double* __restrict__ dLdb, double* __restrict__ part) {
+  double h0 = 0.0, r0 = 0.0, h1 = 0.0, r1 = 0.0, hx = 0.0, rx = 0.0;
   const int t = g.t;
   const int lpr = 1 << g.L.lpr_log;
   const int lane = threadIdx.x & 63;
@@ -350,6 +371,11 @@ __global__ __launch_bounds__(256) void grad_probe_kernel(
       r0 += -Bv * di2 * dd_s2[i] * Bv;
       hm = dWi * ui * vi;
       rm = dWi * Bv * Bv;
+      if (dWx) {
+        const double dx = dWx[i];
+        hx += dx * ui * vi;
+        rx += dx * Bv * Bv;
+      }
     }
     // per-row moments over the t columns held by the lpr lanes of this row
     double sh = hm, sr = rm;
@@ -375,6 +401,60 @@ __global__ __launch_bounds__(256) void grad_probe_kernel(
   block_colsum(g, r0, part + (int64_t)g.nchunk * t);
   block_colsum(g, h1, part + 2 * (int64_t)g.nchunk * t);
   block_colsum(g, r1, part + 3 * (int64_t)g.nchunk * t);
+  if (dWx) {
+    block_colsum(g, hx, part + 4 * (int64_t)g.nchunk * t);
+    block_colsum(g, rx, part + 5 * (int64_t)g.nchunk * t);
+  }
+}
+
+// d W / d xi per row at the mode (input of grad_probe_kernel).
+__global__ void xi_dw_kernel(int64_t n, int lik, double aux, const double* __restrict__ y,
+                             const double* __restrict__ F, const double* __restrict__ b,
+                             double* __restrict__ dWx) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double dlp, dg, dw;
+  lik_xi_derivs(lik, y[i], (F ? F[i] : 0.0) + b[i], aux, &dlp, &dg, &dw);
+  dWx[i] = dw;
+}
+
+// Row sums (t = 1 grid) for the xi-gradient: 0: sum dlp, 1: sum dWx / (W +
+// D^{-1}) (= tr(P^{-1} dP/dxi)), 2: w' dg with w = A^{-1} dL/db.
+__global__ __launch_bounds__(256) void grad_xi_rows_kernel(
+    ChunkGrid g, int lik, double aux, const double* __restrict__ y,
+    const double* __restrict__ F, const double* __restrict__ b, const double* __restrict__ W,
+    const double* __restrict__ D, const double* __restrict__ w, double* __restrict__ part) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  CHUNK_LOOP_BEGIN(g)
+  (void)c;
+  double dlp, dg, dw;
+  lik_xi_derivs(lik, y[i], (F ? F[i] : 0.0) + b[i], aux, &dlp, &dg, &dw);
+  s0 += dlp;
+  s1 += dw / (W[i] + 1.0 / D[i]);
+  s2 += w[i] * dg;
+  CHUNK_LOOP_END
+  block_colsum(g, s0, part);
+  block_colsum(g, s1, part + g.nchunk);
+  block_colsum(g, s2, part + 2 * g.nchunk);
+}
+
+// digamma(x) for x > 0: the recurrence psi(x) = psi(x + 1) - 1/x up to
+// x >= 10, then the asymptotic series ln x - 1/(2x) - sum_k B_2k / (2k
+// x^2k) through k = 6 (Abramowitz & Stegun 6.3.5 and 6.3.18); the first
+// omitted term is below 1e-16 there.
+static double digamma_host(double x) {
+  double acc = 0.0;
+  while (x < 10.0) {
+    acc -= 1.0 / x;
+    x += 1.0;
+  }
+  const double i2 = 1.0 / (x * x);
+  // B_2k / (2k) for k = 1..6: 1/12, -1/120, 1/252, -1/240, 1/132, -691/32760
+  const double series =
+      i2 * (1.0 / 12 -
+            i2 * (1.0 / 120 -
+                  i2 * (1.0 / 252 - i2 * (1.0 / 240 - i2 * (1.0 / 132 - i2 * (691.0 / 32760))))));
+  return acc + std::log(x) - 0.5 / x - series;
 }
 
 // Row sums (t = 1 grid) for the explicit and implicit theta-terms:
@@ -485,19 +565,28 @@ static Status grad_theta(Model& M, const vl_opts& o, const double* sdiag, double
   VL_TRY(M.vec_c.reserve(n));   // dL/db
   VL_TRY(M.dWv.reserve(n));
   VL_TRY(lik_rows(M, M.mode.p, nullptr, nullptr, nullptr, nullptr, nullptr, M.dWv.p));
+  const bool xi = lik_has_aux(M.lik);
+  if (xi) {
+    VL_TRY(M.vec_d.reserve(n));  // d W / d xi
+    hipLaunchKernelGGL(xi_dw_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, M.stream,
+                       n, M.lik, M.aux, M.y.p, M.F.p, M.mode.p, M.vec_d.p);
+    VL_TRY(check_launch("xi dW"));
+  }
+  const int nblk = xi ? 6 : 4;
   ChunkGrid g = ChunkGrid::of(n, t);
-  VL_TRY(M.red_part.reserve(static_cast<size_t>(g.nchunk) * t * 4 + 64));
+  VL_TRY(M.red_part.reserve(static_cast<size_t>(g.nchunk) * t * nblk + 64));
   hipLaunchKernelGGL(grad_probe_kernel, dim3(g.nchunk, 1), dim3(256), 0, M.stream, g, M.m,
                      M.nbr.p, M.bval.p, M.dbval_rho.p, M.cg.U.p, M.cg.Z0.p, M.dval.p,
-                     M.dd_sigma2.p, M.dd_rho.p, M.W.p, M.dWv.p, M.vec_c.p, M.red_part.p);
+                     M.dd_sigma2.p, M.dd_rho.p, M.W.p, M.dWv.p, xi ? M.vec_d.p : nullptr,
+                     M.vec_c.p, M.red_part.p);
   VL_TRY(check_launch("grad probes"));
-  VL_TRY(M.red_out.reserve(4 * t + 64));
-  for (int k = 0; k < 4; ++k)
+  VL_TRY(M.red_out.reserve(nblk * t + 64));
+  for (int k = 0; k < nblk; ++k)
     VL_TRY(reduce_chunks(M.stream, M.red_part.p + (int64_t)k * g.nchunk * t, g.nchunk, t,
                          M.red_out.p + k * t));
-  std::vector<double> hr(4 * t);
-  VL_HIP(hipMemcpyAsync(hr.data(), M.red_out.p, sizeof(double) * 4 * t, hipMemcpyDeviceToHost,
-                        M.stream));
+  std::vector<double> hr(nblk * t);
+  VL_HIP(hipMemcpyAsync(hr.data(), M.red_out.p, sizeof(double) * nblk * t,
+                        hipMemcpyDeviceToHost, M.stream));
   VL_TRY(sync_stream(M.stream));
   // w = A^{-1} dL/db  (implicit derivative of the mode, eq. grad_mode_par)
   CgOps ops = vadu_ops(M.W.p, sdiag);
@@ -534,6 +623,31 @@ static Status grad_theta(Model& M, const vl_opts& o, const double* sdiag, double
     info->quad[k] = quad;
     info->implicit[k] = impl;
   }
+  M.has_grad_xi = false;
+  if (xi) {
+    // d L / d xi = -d log p / d xi + (1/2) d log det / d xi + w' d^2 log p /
+    // d xi d mu, the log-determinant term by the VADU STE with control variate
+    ChunkGrid gx = ChunkGrid::of(n, 1);
+    VL_TRY(M.red_part.reserve(static_cast<size_t>(gx.nchunk) * 3 + 64));
+    hipLaunchKernelGGL(grad_xi_rows_kernel, dim3(gx.nchunk, 1), dim3(256), 0, M.stream, gx,
+                       M.lik, M.aux, M.y.p, M.F.p, M.mode.p, M.W.p, M.dval.p, M.cg1.U.p,
+                       M.red_part.p);
+    VL_TRY(check_launch("grad xi rows"));
+    double xr[3];
+    VL_TRY(host_sums(M, M.red_part.p, gx.nchunk, 3, xr));
+    std::vector<double> h(hr.begin() + 4 * t, hr.begin() + 5 * t);
+    std::vector<double> r(hr.begin() + 5 * t, hr.begin() + 6 * t);
+    const double c = cv_weight(h, r);
+    double mean = 0.0;
+    for (int q = 0; q < t; ++q) mean += h[q] - c * r[q];
+    mean /= t;
+    double dlogp = xr[0];
+    if (M.lik == VL_LIK_GAMMA)
+      dlogp += static_cast<double>(n) * (std::log(M.aux) + 1.0 - digamma_host(M.aux));
+    const double dlogdet = c * xr[1] + mean;
+    M.grad_xi = -dlogp + 0.5 * dlogdet + xr[2];
+    M.has_grad_xi = true;
+  }
   return Status::ok();
 }
 
@@ -541,6 +655,7 @@ static Status grad_theta(Model& M, const vl_opts& o, const double* sdiag, double
 Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, NllInfo* info) {
   if (!M.has_mode) return Status::make(VL_ERR_STATE, "no mode: call vl_find_mode first");
   M.has_grad_F = false;
+  M.has_grad_xi = false;
   if (grad && !M.deriv) return Status::make(VL_ERR_STATE, "model built without derivatives");
   const int64_t n = M.n;
   const int t = o.num_probes;

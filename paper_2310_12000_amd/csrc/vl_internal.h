@@ -288,6 +288,9 @@ struct Model {
   // gradient of the last likelihood call in the offset F (n), when asked
   DevBuf<double> grad_F;
   bool has_grad_F = false;
+  // and in the likelihood's auxiliary parameter (Gaussian, Gamma)
+  double grad_xi = 0.0;
+  bool has_grad_xi = false;
 
   // likelihood state
   bool has_mode = false;
@@ -388,6 +391,7 @@ Status read_status(Model& M);
 // Validates a likelihood code and takes its parameter from aux_host[0]
 // (Gaussian noise variance or Gamma shape; 0 for the others).
 Status likelihood_aux(int lik, const double* aux_host, double* aux);
+inline bool lik_has_aux(int lik) { return lik == VL_LIK_GAUSSIAN || lik == VL_LIK_GAMMA; }
 
 // ---- neighbour search (knn.hip)
 Status knn_build_grid(Model& M);

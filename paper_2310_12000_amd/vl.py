@@ -156,6 +156,7 @@ def lib():
                               ctypes.POINTER(D), I, D, ctypes.POINTER(D), ctypes.POINTER(I),
                               ctypes.POINTER(I)]
     L.vl_grad_beta.argtypes = [P, P, I, ctypes.POINTER(D)]
+    L.vl_grad_aux.argtypes = [P, ctypes.POINTER(D)]
     L.vl_export_count.argtypes = [P, I]
     L.vl_export_count.restype = I64
     L.vl_spmm.argtypes = [P, I, P, P, I]
@@ -186,7 +187,7 @@ def lib():
     L.vl_server_free.restype = None
     for f in ("vl_build_vecchia", "vl_set_theta", "vl_find_mode", "vl_neg_log_marglik",
               "vl_predict", "vl_export", "vl_spmm", "vl_trsm", "vl_trsm_noalloc",
-              "vl_set_allocator", "vl_grad_offset", "vl_grad_beta", "vl_estimate",
+              "vl_set_allocator", "vl_grad_offset", "vl_grad_beta", "vl_grad_aux", "vl_estimate",
               "vl_timing_enable",
               "vl_timing_read", "vl_batch_create", "vl_batch_fit", "vl_batch_mode",
               "vl_batch_stats", "vl_server_create", "vl_server_submit", "vl_server_wait",
@@ -428,6 +429,13 @@ class VecchiaLaplace:
         out = (ctypes.c_double * p)()
         _check(lib().vl_grad_beta(self.h, _ptr(X), p, out))
         return list(out)
+
+    def grad_aux(self):
+        """dL/dxi (Gaussian tau^2 or Gamma shape) from the last neg_log_marglik
+        with a gradient."""
+        out = ctypes.c_double()
+        _check(lib().vl_grad_aux(self.h, ctypes.byref(out)))
+        return out.value
 
     def export(self, name):
         return vl_export(self.h, name, self.coords.device)

@@ -1,7 +1,8 @@
 """GPU parity for the Gamma likelihood with log link (Sec. 5) and a linear
 predictor F = X beta: mode, SLQ negative log-marginal likelihood, the
-theta-gradient, the offset gradient and its beta projection X^T dL/dF, and
-predictive means and variances, against the FP64 oracle on the same seeded
+theta-gradient, the offset gradient and its beta projection X^T dL/dF, the
+gradient in the shape (and, for the Gaussian, in tau^2), and predictive
+means and variances, against the FP64 oracle on the same seeded
 inputs and probes (relative 1e-9, replaying the device's iteration counts
 where a stopping decision falls the other way).  Also the argument checks:
 a shape that is not positive is refused, a non-positive response is flagged
@@ -72,6 +73,7 @@ def gamma_fit(P, gamma_case):
     out["slq_iters"] = host(g.export("block_iters")).tolist()
     out["grad_F"] = host(g.grad_offset())
     out["grad_beta"] = g.grad_beta(dev(w["X"]))
+    out["grad_xi"] = g.grad_aux()
     mean, var, _ = g.predict(dev(w["coords_pred"]), dev(w["Fp"]), go)
     out["pred_iters"] = host(g.export("block_iters")).tolist()
     out["mean"], out["var"] = host(mean), host(var)
@@ -116,6 +118,51 @@ def test_gamma_nll_gradients(gamma_case, gamma_fit):
     np.testing.assert_allclose(f["grad_beta"], w["X"].T @ f["grad_F"], rtol=0, atol=1e-12 * scale)
 
 
+def _xi_bar(info):
+    # the xi-gradient sums three terms that can cancel: its bar is TOL on the
+    # sum of their magnitudes
+    return TOL * (abs(info["dlogp_xi"]) + 0.5 * abs(info["dlogdet_xi"]) + abs(info["implicit_xi"]))
+
+
+def test_gamma_shape_gradient(gamma_case, gamma_fit):
+    w, model = gamma_case
+    f = gamma_fit
+    b, _, _, _ = _oracle_mode(w, model, f)
+    _, info = OL.neg_log_marglik(model, w["y"], w["F"], OL.LIK_GAMMA, SHAPE, b, f["opts"],
+                                 want_grad=True, replay_cg=f["slq_iters"])
+    say(f"shape gradient device {f['grad_xi']!r} oracle {info['grad_xi']!r} "
+        f"(dlogp {info['dlogp_xi']:.6g} dlogdet {info['dlogdet_xi']:.6g} "
+        f"implicit {info['implicit_xi']:.6g})")
+    assert abs(f["grad_xi"] - info["grad_xi"]) <= _xi_bar(info)
+
+
+def test_gaussian_variance_gradient(P):
+    """Gaussian tau^2-gradient (the mode-response term vanishes, W is constant)
+    at n = 1,500, m = 10, 50 probes."""
+    say("case: gaussian n=1500 tau2 gradient")
+    n, tau2 = 1500, 0.4
+    coords = synth.locations(n, seed=37)
+    b = synth.latent_field(coords, synth.COV_EXPONENTIAL, 1.0, 0.1, seed=37)
+    F = np.full(n, 0.3)
+    y = synth.responses(synth.LIK_GAUSSIAN, F + b, seed=37, tau2=tau2)
+    o, go = opts_pair(P, cg_tol=1e-10, num_probes=50, seed=9)
+    g = P.VecchiaLaplace(dev(coords), 10, synth.COV_EXPONENTIAL, (1.0, 0.1), want_deriv=True)
+    g.find_mode(dev(y), dev(F), P.VL_LIK_GAUSSIAN, tau2, go)
+    newton_cg = host(g.export("newton_cg_iters")).tolist()
+    nll, grad, _ = g.neg_log_marglik(go, want_grad=True)
+    slq = host(g.export("block_iters")).tolist()
+    gx = g.grad_aux()
+    g.close()
+    model = OL.Model(coords, 10, synth.COV_EXPONENTIAL, (1.0, 0.1), deriv=True)
+    bo, _, _, _ = oracle_mode_matching(model, y, F, OL.LIK_GAUSSIAN, tau2, o, newton_cg)
+    nll_o, info = OL.neg_log_marglik(model, y, F, OL.LIK_GAUSSIAN, tau2, bo, o, want_grad=True,
+                                     replay_cg=slq)
+    say(f"tau2 gradient device {gx!r} oracle {info['grad_xi']!r}")
+    assert abs(nll - nll_o) <= TOL * abs(nll_o)
+    assert rel_err_elem(grad, info["grad"]) < TOL
+    assert abs(gx - info["grad_xi"]) <= _xi_bar(info)
+
+
 def test_gamma_predict(gamma_case, gamma_fit):
     w, model = gamma_case
     f = gamma_fit
@@ -139,4 +186,13 @@ def test_gamma_argument_checks(P, gamma_case):
     with pytest.raises(P.VLError) as e:
         g.find_mode(dev(y0), None, P.VL_LIK_GAMMA, SHAPE)
     assert e.value.code == P.VL_ERR_NONFINITE
+    # no xi-gradient before a gradient call, none for a likelihood without xi
+    g.find_mode(y, None, P.VL_LIK_GAMMA, SHAPE)
+    with pytest.raises(P.VLError) as e:
+        g.grad_aux()
+    assert e.value.code == P.VL_ERR_STATE
+    g.find_mode(dev((w["y"][:300] > 1.0).astype(np.float64)), None, P.VL_LIK_BERNOULLI_LOGIT)
+    with pytest.raises(P.VLError) as e:
+        g.grad_aux()
+    assert e.value.code == P.VL_ERR_INVALID_ARG
     g.close()

@@ -11,7 +11,8 @@ Plain FP64 NumPy/SciPy, following the paper step by step:
                    column (each probe has its own recurrence)
   slq_quadrature   e_1^T log(T~) e_1 from the CG coefficients, eq. (def_SLQ)
   find_mode        Newton iteration eq. (newton) with CG solves, eq. (pcls1)
-                   for VADU and eq. (pcls2) for LRAC
+                   for VADU, LVA (Sec. 3.1.1) and the diagonal P_1 (Sec.
+                   3.1.4), eq. (pcls2) for LRAC
   neg_log_marglik  eq. (VLA_loss) with the log-determinant split
                    eq. (logdetsplit) (VADU, Sec. 3.1.1) or eq. (logdetsplit2)
                    (LRAC, Sec. 3.1.2) and SLQ for the last term
@@ -62,6 +63,8 @@ LIK_GAMMA = 3  # log link, mean exp(mu), shape aux (Sec. 5)
 
 PRECOND_VADU = 0
 PRECOND_LRAC = 1
+PRECOND_LVA = 2    # P = B^T D^{-1} B (Sec. 3.1.1)
+PRECOND_DIAG = 3   # P_1 = diag(W + B^T D^{-1} B) (Sec. 3.1.4)
 
 
 # ----------------------------------------------------------------------------
@@ -312,6 +315,47 @@ def vadu_ops(model, W):
     return apply_A, apply_Pinv
 
 
+def lva_ops(model, W):
+    """A = W + B^T D^{-1} B and P_LVA^{-1} = B^{-1} D B^{-T} (Sec. 3.1.1)."""
+    def apply_A(X):
+        return _col(W, X) * X + model.prec_apply(X)
+
+    def apply_Pinv(X):
+        return model.solve_B(model.solve_Bt(X) * _col(model.D, X))
+
+    return apply_A, apply_Pinv
+
+
+def diag_p1(model, W):
+    """(P_1)_ii = (W + B^T D^{-1} B)_ii = W_i + sum_j B_ji^2 / D_j (Sec. 3.1.4)."""
+    B2 = model.B.multiply(model.B)
+    return W + B2.T @ model.Dinv
+
+
+def diag_ops(model, W):
+    """A = W + B^T D^{-1} B and P_1^{-1} = diag(P_1)^{-1}."""
+    p1 = diag_p1(model, W)
+
+    def apply_A(X):
+        return _col(W, X) * X + model.prec_apply(X)
+
+    def apply_Pinv(X):
+        return X / _col(p1, X)
+
+    return apply_A, apply_Pinv
+
+
+def sparse_precond_ops(model, W, precond):
+    """Operator and preconditioner of eq. (pcls1) for VADU, LVA or P_1."""
+    if precond == PRECOND_VADU:
+        return vadu_ops(model, W)
+    if precond == PRECOND_LVA:
+        return lva_ops(model, W)
+    if precond == PRECOND_DIAG:
+        return diag_ops(model, W)
+    raise ValueError("not a preconditioner of eq. (pcls1)")
+
+
 def pivoted_cholesky(coords, kind, theta, k, pivots=None):
     """Rank-k pivoted Cholesky of the original covariance matrix Sigma
     (Sec. 3.1.2): pivot = largest remaining diagonal (first index on ties).
@@ -418,8 +462,8 @@ def find_mode(model, y, F, lik, aux, opts, replay=None, L=None):
         W = lik_W(lik, y, mu, aux)
         rhs = W * b + g
         forced = None if replay is None else [replay["cg_iters"][it]]
-        if opts.precond == PRECOND_VADU:
-            apply_A, apply_Pinv = vadu_ops(model, W)
+        if opts.precond != PRECOND_LRAC:
+            apply_A, apply_Pinv = sparse_precond_ops(model, W, opts.precond)
             res = pcg(apply_A, apply_Pinv, rhs, opts.cg_tol, opts.max_cg, forced)
             b_new = res.U
         else:
@@ -460,9 +504,11 @@ def neg_log_marglik(model, y, F, lik, aux, b, opts, replay_cg=None, L=None,
 
     VADU: log det = sum log D + sum log(W + 1/D) + SLQ term (eq. logdetsplit,
     log det P_VADU = log det(W + D^{-1})).
+    LVA: log det P_LVA = -sum log D; P_1: log det P_1 = sum log (P_1)_ii
+    (same split).
     LRAC: log det = sum log W + log det P_LRAC + SLQ term (eq. logdetsplit2).
     The probes are the counter-based columns col0 .. col0 + num_probes - 1
-    (col0 > 0 evaluates a slice of a larger probe set; the VADU probes only).
+    (col0 > 0 evaluates a slice of a larger probe set; not for LRAC).
     Returns (nll, info) with info holding the pieces, the CG iteration counts
     and (want_grad, VADU only) the theta-gradient."""
     n = model.n
@@ -470,14 +516,29 @@ def neg_log_marglik(model, y, F, lik, aux, b, opts, replay_cg=None, L=None,
     mu = F + b
     W = lik_W(lik, y, mu, aux)
     t = opts.num_probes
-    if col0 and opts.precond != PRECOND_VADU:
-        raise ValueError("col0 applies to the VADU probes")
+    if col0 and opts.precond == PRECOND_LRAC:
+        raise ValueError("col0 applies to the probes of eq. (pcls1)")
     eps = _rng.rademacher(opts.seed, _rng.TAG_SLQ, n, t, col0=col0)
-    if opts.precond == PRECOND_VADU:
-        apply_A, apply_Pinv = vadu_ops(model, W)
-        Z = model.Bt @ (np.sqrt(W + model.Dinv)[:, None] * eps)
+    if opts.precond != PRECOND_LRAC:
+        # eq. (logdetsplit): log det(Sigma~ W + I) = log det Sigma~ + log det P
+        # + log det(P^{-1/2} A P^{-T/2}), log det Sigma~ = sum log D; probes
+        # z = P^{1/2} eps with Cov(z) = P
+        apply_A, apply_Pinv = sparse_precond_ops(model, W, opts.precond)
+        if opts.precond == PRECOND_VADU:
+            # P^{1/2} = B^T (W + D^{-1})^{1/2}, log det P = sum log(W + D^{-1})
+            Z = model.Bt @ (np.sqrt(W + model.Dinv)[:, None] * eps)
+            logdet_P = np.sum(np.log(W + model.Dinv))
+        elif opts.precond == PRECOND_LVA:
+            # P^{1/2} = B^T D^{-1/2}, log det P = -sum log D
+            Z = model.Bt @ (np.sqrt(model.Dinv)[:, None] * eps)
+            logdet_P = -np.sum(np.log(model.D))
+        else:
+            # P_1^{1/2} = diag(P_1)^{1/2}, log det P_1 = sum log (P_1)_ii
+            p1 = diag_p1(model, W)
+            Z = np.sqrt(p1)[:, None] * eps
+            logdet_P = np.sum(np.log(p1))
         res = pcg(apply_A, apply_Pinv, Z, opts.cg_tol, opts.max_cg, replay_cg)
-        logdet_fixed = np.sum(np.log(model.D)) + np.sum(np.log(W + model.Dinv))
+        logdet_fixed = np.sum(np.log(model.D)) + logdet_P
     else:
         if L is None:
             L = pivoted_cholesky(model.coords, model.kind, model.theta, opts.lrac_rank)

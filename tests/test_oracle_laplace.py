@@ -108,25 +108,39 @@ def test_pcg_solves_and_lanczos_ritz_values():
             < 1e-10 * abs(rhs[:, c] @ res.U[:, c])
 
 
-def test_slq_equals_dense_hutchinson_at_convergence():
+@pytest.mark.parametrize("precond", [L.PRECOND_VADU, L.PRECOND_LVA, L.PRECOND_DIAG])
+def test_slq_equals_dense_hutchinson_at_convergence(precond):
     # Run to full convergence: Gauss quadrature is exact, so the SLQ term equals
-    # (1/t) sum eps^T log(M) eps with M = P^{-1/2} A P^{-T/2},
-    # P^{-1/2} = (W + D^{-1})^{-1/2} B^{-T} (eq. P_VADU_prec).
+    # (1/t) sum eps^T log(M) eps with M = P^{-1/2} A P^{-T/2}:
+    # VADU P^{-1/2} = (W + D^{-1})^{-1/2} B^{-T} (eq. P_VADU_prec), LVA
+    # D^{1/2} B^{-T}, P_1 diag(A)^{-1/2} (Sec. 3.1.4), all built densely here.
     n = 50
     model, y, F = _problem(n=n, m=5, seed=3)
     b, W, _ = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, L.Opts(cg_tol=1e-13))
-    opts = L.Opts(cg_tol=1e-13, num_probes=7, seed=5)
+    opts = L.Opts(cg_tol=1e-13, num_probes=7, seed=5, precond=precond)
     nll, info = L.neg_log_marglik(model, y, F, L.LIK_BERNOULLI_LOGIT, None, b, opts)
     Bd = model.B.toarray()
     Q = DR.dense_precision(Bd, model.D)
     A = np.diag(W) + Q
-    Pih = np.diag((W + model.Dinv) ** -0.5) @ np.linalg.inv(Bd).T
+    if precond == L.PRECOND_VADU:
+        Pih = np.diag((W + model.Dinv) ** -0.5) @ np.linalg.inv(Bd).T
+        ld_P = np.sum(np.log(W + model.Dinv))
+    elif precond == L.PRECOND_LVA:
+        Pih = np.diag(model.D ** 0.5) @ np.linalg.inv(Bd).T
+        ld_P = -np.sum(np.log(model.D))
+    else:
+        np.testing.assert_allclose(L.diag_p1(model, W), np.diag(A), rtol=1e-13)
+        Pih = np.diag(np.diag(A) ** -0.5)
+        ld_P = np.sum(np.log(np.diag(A)))
+    # the fixed part of eq. (logdetsplit): log det Sigma~ + log det P
+    np.testing.assert_allclose(info["logdet"] - info["gamma"], np.sum(np.log(model.D)) + ld_P,
+                               rtol=1e-12, atol=1e-10)
     M = Pih @ A @ Pih.T
     Lm = DR.logm_spd(M)
     eps = R.rademacher(5, R.TAG_SLQ, n, 7)
     hutch = np.mean(np.einsum("ij,ik,kj->j", eps, Lm, eps))
     assert abs(info["gamma"] - hutch) < 1e-9 * max(1.0, abs(hutch))
-    # weights: r0^T z0 = ||P^{-1/2} z||^2 = eps^T eps = n (Rademacher, VADU)
+    # weights: r0^T z0 = ||P^{-1/2} z||^2 = eps^T eps = n (Rademacher)
     np.testing.assert_allclose(info["r0z0"], n, rtol=1e-12)
 
 
@@ -179,6 +193,33 @@ def test_theorem_3_1_eigenvalue_bounds():
     assert np.all(lam <= (lS * W.max() + 1.0) * q.max() * (1 + 1e-9))
 
 
+def test_theorem_3_1_lva_eigenvalue_bounds():
+    # LVA: lambda_min(P^{-1}A) > 1 and lambda_l(P^{-1}A) <= lambda_l(Sigma~) max W + 1
+    # (P_LVA^{-1/2} A P_LVA^{-T/2} = D^{1/2} B^{-T} W B^{-1} D^{1/2} + I).
+    n = 90
+    model, y, F = _problem(n=n, m=5, seed=6, lik=L.LIK_POISSON, F=0.5)
+    b, W, _ = L.find_mode(model, y, F, L.LIK_POISSON, None, L.Opts(cg_tol=1e-10))
+    apply_A, apply_Pinv = L.lva_ops(model, W)
+    lam = np.sort(np.linalg.eigvals(apply_Pinv(np.eye(n)) @ apply_A(np.eye(n))).real)[::-1]
+    Binv = np.linalg.inv(model.B.toarray())
+    lS = np.sort(np.linalg.eigvalsh(Binv @ np.diag(model.D) @ Binv.T))[::-1]
+    assert lam[-1] > 1.0 - 1e-10
+    assert np.all(lam <= (lS * W.max() + 1.0) * (1 + 1e-9))
+
+
+def test_diagonal_preconditioner_identity_factor_special_case():
+    # m = 0: B = I, so P_1 = W + D^{-1} = A; CG stops after one iteration,
+    # T~ = [1], the SLQ term vanishes and log det = sum log(1 + sigma^2 W).
+    n = 40
+    model, y, F = _problem(n=n, m=0, seed=2)
+    o = L.Opts(cg_tol=1e-10, num_probes=5, precond=L.PRECOND_DIAG)
+    b, W, st = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, o)
+    assert all(c == 1 for c in st["cg_iters"])
+    nll, info = L.neg_log_marglik(model, y, F, L.LIK_BERNOULLI_LOGIT, None, b, o)
+    assert np.all(info["cg_iters"] == 1) and abs(info["gamma"]) < 1e-12
+    np.testing.assert_allclose(info["logdet"], np.sum(np.log(1.0 + model.theta[0] * W)), rtol=1e-12)
+
+
 # --------------------------------------------------------------------- Newton
 @pytest.mark.parametrize("lik", [L.LIK_BERNOULLI_LOGIT, L.LIK_POISSON])
 def test_mode_equals_dense_newton_and_zero_gradient(lik):
@@ -210,10 +251,11 @@ def test_step_halving_reaches_the_mode_where_full_newton_diverges():
     np.testing.assert_allclose(L.lik_grad(L.LIK_POISSON, y, F + b), Q @ b, atol=1e-8)
 
 
-def test_mode_lrac_equals_mode_vadu():
+@pytest.mark.parametrize("precond", [L.PRECOND_LRAC, L.PRECOND_LVA, L.PRECOND_DIAG])
+def test_mode_other_preconditioners_equal_mode_vadu(precond):
     model, y, F = _problem(n=90, m=6, seed=8)
     o1 = L.Opts(cg_tol=1e-12, newton_tol=1e-14)
-    o2 = L.Opts(cg_tol=1e-12, newton_tol=1e-14, precond=L.PRECOND_LRAC, lrac_rank=10)
+    o2 = L.Opts(cg_tol=1e-12, newton_tol=1e-14, precond=precond, lrac_rank=10)
     b1, _, _ = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, o1)
     b2, _, _ = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, o2)
     np.testing.assert_allclose(b1, b2, rtol=1e-8, atol=1e-9)
@@ -238,7 +280,8 @@ def test_gaussian_likelihood_exact_marginal():
     assert abs(nll_exact - ref) < 1e-8 * abs(ref)
 
 
-@pytest.mark.parametrize("precond", [L.PRECOND_VADU, L.PRECOND_LRAC])
+@pytest.mark.parametrize("precond", [L.PRECOND_VADU, L.PRECOND_LRAC, L.PRECOND_LVA,
+                                     L.PRECOND_DIAG])
 def test_logdet_matches_dense_within_probe_error(precond):
     # log det(Sigma~ W + I) estimated with t probes lies within 5 standard
     # errors (sample sd of the per-probe terms / sqrt t) of the dense value.

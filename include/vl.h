@@ -10,8 +10,8 @@
  *     eq. newton; Sec. 3, eqs. pcls1 / pcls2; appendix CG algorithm)
  *   - SLQ negative log-marginal likelihood and STE gradient     (eq. VLA_loss,
  *     eqs. logdetsplit / logdetsplit2 / def_SLQ / grad_STE; App. A.3, A.4)
- *   - VADU and LRAC preconditioners                             (Sec. 3.1.1,
- *     Sec. 3.1.2)
+ *   - VADU, LRAC, LVA and diagonal (P_1) preconditioners        (Sec. 3.1.1,
+ *     Sec. 3.1.2, Sec. 3.1.4)
  *   - predictive means and simulated variances                  (Sec. 2.2.1,
  *     eq. latentpostpredictive; Sec. 3.3.1, Alg. simAlgo)
  *
@@ -70,7 +70,13 @@ typedef enum {
   VL_LIK_GAMMA = 3            /* y > 0, mu = log E[y], aux[0] = shape a > 0 */
 } vl_lik;
 
-typedef enum { VL_PREC_VADU = 0, VL_PREC_LRAC = 1 } vl_precond;
+typedef enum {
+  VL_PREC_VADU = 0, /* B^T (W + D^{-1}) B (Sec. 3.1.1)                          */
+  VL_PREC_LRAC = 1, /* L_k L_k^T + W^{-1} (Sec. 3.1.2)                          */
+  VL_PREC_LVA = 2,  /* B^T D^{-1} B (Sec. 3.1.1); mode and likelihood only        */
+  VL_PREC_DIAG = 3  /* P_1 = diag(W + B^T D^{-1} B) (Sec. 3.1.4); mode and
+                       likelihood only                                          */
+} vl_precond;
 typedef enum { VL_FP64 = 0, VL_MIXED = 1 } vl_precision;
 
 /* Options.  vl_default_opts fills the paper's defaults (Sec. 4.1): t = 50
@@ -198,16 +204,17 @@ vl_status vl_set_theta(vl_model* h, const double* theta_host);
  * times) while Psi(b) = log p(y|F+b) - b^T Sigma~^{-1} b / 2 falls below
  * Psi_old - 1e-12 |Psi_old| (a decrease beyond rounding);
  * stops when |Psi_new - Psi_old| <= o->newton_tol |Psi_old| or when no halving
- * increases Psi (b is kept).  With o->precond = VL_PREC_VADU
- * each step solves (W + Sigma~^{-1}) b' = W b + g by CG preconditioned with
- * P_VADU (eq. pcls1); with VL_PREC_LRAC it solves (Sigma~ + W^{-1}) (W b') =
+ * increases Psi (b is kept).  With o->precond = VL_PREC_VADU, VL_PREC_LVA or
+ * VL_PREC_DIAG each step solves (W + Sigma~^{-1}) b' = W b + g by CG
+ * preconditioned with P_VADU, P_LVA or P_1 (eq. pcls1); with VL_PREC_LRAC it
+ * solves (Sigma~ + W^{-1}) (W b') =
  * Sigma~ (W b + g) (eq. pcls2) preconditioned with P_LRAC = L_k L_k^T + W^{-1}
  * (Sec. 3.1.2), L_k the rank-o->lrac_rank pivoted Cholesky factor of Sigma,
  * built once per theta.
  *   y        device, n responses
  *   F        device, n offsets F(X) (NULL = 0)
  *   lik      vl_lik; aux_host: likelihood auxiliary parameters (host;
- *            Gaussian: {tau2}; may be NULL otherwise)
+ *            Gaussian: {tau2}; Gamma: {shape}; may be NULL otherwise)
  *   mode_out device, n (NULL = keep it only inside the model)
  * Keeps y, F, b*, W(b*) in the model for the calls below.  Synchronises. */
 vl_status vl_find_mode(vl_model* h, const double* y, const double* F, int lik,
@@ -218,8 +225,11 @@ vl_status vl_find_mode(vl_model* h, const double* y, const double* F, int lik,
  *   nll_host        host, 1 double
  *   grad_theta_host host, 2 doubles d/d(sigma2, rho) (NULL = skip; needs
  *                   want_deriv at build and the VADU preconditioner)
- * VADU: eq. (logdetsplit) with probes z = B^T (W + D^{-1})^{1/2} eps; LRAC:
+ * VADU: eq. (logdetsplit) with probes z = B^T (W + D^{-1})^{1/2} eps and
+ * log det P = sum log(W + D^{-1}); LVA: z = B^T D^{-1/2} eps, log det P =
+ * -sum log D; P_1: z = P_1^{1/2} eps, log det P = sum log (P_1)_ii; LRAC:
  * eq. (logdetsplit2) with z = L_k eps_k + W^{-1/2} eps_n, weight r0^T z0.
+ * The mixed form leaves P_1 (no triangular solves) in FP64.
  * Synchronises. */
 vl_status vl_neg_log_marglik(vl_model* h, const vl_opts* o, double* nll_host,
                              double* grad_theta_host, vl_stats* st);

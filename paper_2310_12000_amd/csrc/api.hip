@@ -231,7 +231,8 @@ static Status check_opts(const vl_opts* o) {
   if (o->max_newton < 1 || o->max_cg < 1) return Status::invalid("iteration caps must be >= 1");
   if (!(o->cg_tol > 0.0) || !(o->pred_cg_tol > 0.0) || !(o->newton_tol >= 0.0))
     return Status::invalid("tolerances must be positive");
-  if (o->precond != VL_PREC_VADU && o->precond != VL_PREC_LRAC)
+  if (o->precond != VL_PREC_VADU && o->precond != VL_PREC_LRAC && o->precond != VL_PREC_LVA &&
+      o->precond != VL_PREC_DIAG)
     return Status::invalid("unknown preconditioner");
   if (o->precision != VL_FP64 && o->precision != VL_MIXED)
     return Status::invalid("unknown precision");

@@ -219,6 +219,88 @@ CgOps vadu_ops(const double* W, const double* sdiag) {
   return ops;
 }
 
+// ------------------------------------------- LVA and diagonal preconditioners
+// (P_1)_ii = (W + B^T D^{-1} B)_ii = W_i + 1/D_i + sum_j B_ji^2 / D_j over the
+// entries of row i of B^T (Sec. 3.1.4).  Writes 1/P_1 (s), sqrt(P_1) (sq)
+// and P_1 (p); sq and p may be null.
+__global__ void p1_diag_kernel(int64_t n, const int* __restrict__ bt_ptr,
+                               const int* __restrict__ bt_col, const double* __restrict__ bt_val,
+                               const double* __restrict__ W, const double* __restrict__ dinv,
+                               double* __restrict__ s_out, double* __restrict__ sq_out,
+                               double* __restrict__ p_out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int k = bt_ptr[i]; k < bt_ptr[i + 1]; ++k) {
+    const double v = bt_val[k];
+    acc += v * v * dinv[bt_col[k]];
+  }
+  const double p = W[i] + (dinv[i] + acc);
+  s_out[i] = 1.0 / p;
+  if (sq_out) sq_out[i] = sqrt(p);
+  if (p_out) p_out[i] = p;
+}
+
+static Status p1_diag(Model& M, double* s, double* sq, double* p) {
+  hipLaunchKernelGGL(p1_diag_kernel, dim3((unsigned)((M.n + 255) / 256)), dim3(256), 0,
+                     M.stream, M.n, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, M.W.p, M.dinv.p, s, sq,
+                     p);
+  return check_launch("P1 diagonal");
+}
+
+// Z[i, c] = s_i R[i, c] (n x t row-major)
+__global__ void diag_scale_kernel(int64_t n, int t, const double* __restrict__ s,
+                                  const double* __restrict__ R, double* __restrict__ Z) {
+  const int64_t nt = n * t;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nt;
+       e += (int64_t)gridDim.x * blockDim.x)
+    Z[e] = s[e / t] * R[e];
+}
+
+// out_i = sqrt(in_i) (the LVA probe scale D^{-1/2} from D^{-1})
+__global__ void sqrt_kernel(int64_t n, const double* __restrict__ in, double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = sqrt(in[i]);
+}
+
+// sum_i log p_i over a t = 1 chunk grid
+__global__ __launch_bounds__(256) void log_sum_kernel(ChunkGrid g, const double* __restrict__ p,
+                                                      double* __restrict__ part) {
+  double acc = 0.0;
+  CHUNK_LOOP_BEGIN(g)
+  (void)c;
+  acc += log(p[i]);
+  CHUNK_LOOP_END
+  block_colsum(g, acc, part);
+}
+
+// A as for VADU, P_1^{-1} R = R / P_1 (no triangular solves, no sentinel fill)
+static CgOps diag_ops(const double* W, const double* sinv) {
+  CgOps ops;
+  ops.apply = [W](Model& M, const double* H, double* V, double* Tmp, int t) -> Status {
+    VL_TRY(spmm_b(M, H, Tmp, t, M.dinv.p));
+    return spmm_bt(M, Tmp, V, t, W, H);
+  };
+  ops.precond = [sinv](Model& M, const double* R, double* Z, double* Y, int t) -> Status {
+    (void)Y;
+    const int64_t nt = M.n * static_cast<int64_t>(t);
+    const unsigned g = static_cast<unsigned>(std::min<int64_t>((nt + 255) / 256, 8192));
+    hipLaunchKernelGGL(diag_scale_kernel, dim3(g), dim3(256), 0, M.stream, M.n, t, sinv, R, Z);
+    return check_launch("diagonal preconditioner");
+  };
+  ops.needs_fill = [](const Model&, int) { return false; };
+  return ops;
+}
+
+// The operator and preconditioner of eq. (pcls1) at the current W, for
+// VADU (sdiag = (W + D^{-1})^{-1}, already in s), LVA (P^{-1} = B^{-1} D
+// B^{-T}: sdiag = D) or P_1 (s is overwritten with 1/P_1).
+static CgOps pcls1_ops(Model& M, int precond, bool mixed, double* s) {
+  if (precond == VL_PREC_DIAG) return diag_ops(M.W.p, s);
+  const double* sdiag = precond == VL_PREC_LVA ? M.dval.p : s;
+  return mixed ? vadu_ops_mixed(M.W.p, sdiag) : vadu_ops(M.W.p, sdiag);
+}
+
 // ------------------------------------------------------------------ mode
 constexpr int kMaxHalvings = 30;
 constexpr double kHalvingSlack = 1e-12;  // a decrease below this is rounding
@@ -259,8 +341,9 @@ Status find_mode(Model& M, const vl_opts& o, vl_stats* st) {
       // eq. (pcls2): (Sigma~ + W^{-1}) (W b') = Sigma~ (W b + g)
       VL_TRY(lrac_newton_solve(M, o, M.vec_a.p, M.mode.p, forced));
     } else {
-      // eq. (pcls1): (W + Sigma~^{-1}) b' = W b + g with P_VADU
-      CgOps ops = vadu_ops(M.W.p, M.vec_b.p);
+      // eq. (pcls1): (W + Sigma~^{-1}) b' = W b + g with P_VADU, P_LVA or P_1
+      if (o.precond == VL_PREC_DIAG) VL_TRY(p1_diag(M, M.vec_b.p, nullptr, nullptr));
+      CgOps ops = pcls1_ops(M, o.precond, false, M.vec_b.p);
       VL_TRY(cg_solve(M, M.cg1, ops, 1, M.vec_a.p, o.cg_tol, o.max_cg, false, forced));
       VL_TRY(copy_d2d(M.mode.p, M.cg1.U.p, sizeof(double) * n, M.stream));
     }
@@ -664,7 +747,8 @@ Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, Nl
   VL_TRY(M.vec_b.reserve(n));  // (W + D^{-1})^{-1}
   VL_TRY(lik_rows(M, M.mode.p, nullptr, M.W.p, nullptr, M.vec_b.p, M.vec_a.p, nullptr));
   const bool lrac = o.precond == VL_PREC_LRAC;
-  if (lrac && grad) return Status::invalid("the theta-gradient needs the VADU preconditioner");
+  if (o.precond != VL_PREC_VADU && grad)
+    return Status::invalid("the gradient needs the VADU preconditioner");
   double logdet_lrac = 0.0;
   if (lrac) {
     // eq. (logdetsplit2): log det(Sigma~ W + I) = sum log W + log det P_LRAC
@@ -674,20 +758,35 @@ Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, Nl
     VL_TRY(lrac_slq(M, o, &logdet_lrac, replay_slice(o, 0, t, rbuf)));
   } else {
     VL_TRY(M.rhs_blk.reserve(static_cast<size_t>(n) * t));
-    // z_i = B^T ((W + D^{-1})^{1/2} o eps_i), Cov(z_i) = P_VADU; the CG
-    // blocks Z and H serve as scratch before the solve starts
+    // probes z_i = P^{1/2} eps_i with Cov(z_i) = P:
+    //   VADU B^T ((W + D^{-1})^{1/2} o eps_i), LVA B^T (D^{-1/2} o eps_i),
+    //   P_1 P_1^{1/2} o eps_i;
+    // the CG blocks Z and H serve as scratch before the solve starts
     VL_TRY(M.cg.Z.reserve(static_cast<size_t>(n) * t));
     VL_TRY(M.cg.H.reserve(static_cast<size_t>(n) * t));
-    VL_TRY(spmm_bt_probe(M, M.rhs_blk.p, t, M.vec_a.p, o.seed, kTagSlq, 0, 0, nullptr, 0, 0,
-                         M.cg.Z.p, M.cg.H.p));
-    // mixed form: FP32 preconditioner solves inside the FP64 block PCG
-    CgOps ops = o.precision == VL_MIXED ? vadu_ops_mixed(M.W.p, M.vec_b.p)
-                                        : vadu_ops(M.W.p, M.vec_b.p);
+    if (o.precond == VL_PREC_DIAG) {
+      VL_TRY(M.vec_e.reserve(n));  // P_1
+      VL_TRY(p1_diag(M, M.vec_b.p, M.vec_a.p, M.vec_e.p));
+      VL_TRY(probe_fill(M, M.rhs_blk.p, t, M.vec_a.p, o.seed, kTagSlq, 0));
+    } else {
+      if (o.precond == VL_PREC_LVA) {
+        hipLaunchKernelGGL(sqrt_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                           M.stream, n, M.dinv.p, M.vec_a.p);
+        VL_TRY(check_launch("LVA probe scale"));
+      }
+      VL_TRY(spmm_bt_probe(M, M.rhs_blk.p, t, M.vec_a.p, o.seed, kTagSlq, 0, 0, nullptr, 0, 0,
+                           M.cg.Z.p, M.cg.H.p));
+    }
+    // mixed form: FP32 preconditioner solves inside the FP64 block PCG (P_1
+    // has none and stays FP64)
+    const bool mixed = o.precision == VL_MIXED && o.precond != VL_PREC_DIAG;
+    CgOps ops = pcls1_ops(M, o.precond, mixed, M.vec_b.p);
     // mixed form (FP32 solves for t > 64): the FP32 preconditioner's
     // deviation from FP64 on the first probe, before the CG overwrites Z/H
     M.last_f32_dev = 0.0;
-    if (o.precision == VL_MIXED && t > 64)
-      VL_TRY(precond_f32_deviation(M, M.vec_b.p, M.rhs_blk.p, t, &M.last_f32_dev));
+    if (mixed && t > 64)
+      VL_TRY(precond_f32_deviation(M, o.precond == VL_PREC_LVA ? M.dval.p : M.vec_b.p,
+                                   M.rhs_blk.p, t, &M.last_f32_dev));
     std::vector<int> rbuf;
     VL_TRY(cg_solve(M, M.cg, ops, t, M.rhs_blk.p, o.cg_tol, o.max_cg, grad != nullptr,
                     replay_slice(o, 0, t, rbuf)));
@@ -708,8 +807,26 @@ Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, Nl
   gamma /= t;
   double terms[4];
   VL_TRY(laplace_terms(M, M.mode.p, M.W.p, terms));
-  // eq. (logdetsplit): sum log D + log det(W + D^{-1}) + SLQ term (VADU)
-  const double logdet = (lrac ? logdet_lrac : terms[2] + terms[3]) + gamma;
+  // eq. (logdetsplit): log det Sigma~ (= sum log D) + log det P + SLQ term,
+  // log det P = log det(W + D^{-1}) (VADU), -sum log D (LVA), sum log P_1
+  double logdet_fixed = 0.0;
+  if (lrac) {
+    logdet_fixed = logdet_lrac;
+  } else if (o.precond == VL_PREC_VADU) {
+    logdet_fixed = terms[2] + terms[3];
+  } else if (o.precond == VL_PREC_LVA) {
+    logdet_fixed = terms[2] - terms[2];
+  } else {
+    ChunkGrid g1 = ChunkGrid::of(n, 1);
+    VL_TRY(M.red_part.reserve(static_cast<size_t>(g1.nchunk) + 64));
+    hipLaunchKernelGGL(log_sum_kernel, dim3(g1.nchunk, 1), dim3(256), 0, M.stream, g1, M.vec_e.p,
+                       M.red_part.p);
+    VL_TRY(check_launch("log P1"));
+    double lp = 0.0;
+    VL_TRY(host_sums(M, M.red_part.p, g1.nchunk, 1, &lp));
+    logdet_fixed = terms[2] + lp;
+  }
+  const double logdet = logdet_fixed + gamma;
   *nll = -terms[0] + 0.5 * terms[1] + 0.5 * logdet;
   int cg_max = 0;
   for (int v : M.cg.host_iters) cg_max = v > cg_max ? v : cg_max;

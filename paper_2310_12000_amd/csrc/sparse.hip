@@ -472,6 +472,15 @@ __global__ void probe_fill_kernel(int64_t n, int t, InProbe p, double* __restric
     out[e] = p(e / t, static_cast<int>(e % t));
 }
 
+Status probe_fill(Model& M, double* Y, int t, const double* s, uint64_t seed, uint32_t tag,
+                  int col0) {
+  const int64_t nt = M.n * static_cast<int64_t>(t);
+  const unsigned g = static_cast<unsigned>(std::min<int64_t>((nt + 255) / 256, 8192));
+  hipLaunchKernelGGL(probe_fill_kernel, dim3(g), dim3(256), 0, M.stream, M.n, t,
+                     InProbe{s, seed, tag, col0, 0}, Y);
+  return check_launch("probe fill");
+}
+
 // Y = d o probe1 + B^T (s o probe2).  Narrow blocks generate the probes in
 // place; wider ones (tmp1, tmp2: n x t scratch, given) write them once and
 // take the wide product, where regenerating them per gathered neighbour row

@@ -196,6 +196,9 @@ Status spmm_ell_vals(Model& M, const double* vals, const double* X, double* Y, i
 Status spmm_bt_probe(Model& M, double* Y, int t, const double* s, uint64_t seed, uint32_t tag2,
                      int col0, int gauss2, const double* d, uint32_t tag1, int gauss1,
                      double* tmp1, double* tmp2);
+// Y[i, c] = s_i eps_ic (Rademacher probes of columns col0 .. col0 + t - 1)
+Status probe_fill(Model& M, double* Y, int t, const double* s, uint64_t seed, uint32_t tag,
+                  int col0);
 Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* rowscale,
                    bool prefilled, int slot);
 Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled, int slot);

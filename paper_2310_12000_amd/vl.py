@@ -34,6 +34,8 @@ VL_LIK_GAUSSIAN = 2
 VL_LIK_GAMMA = 3
 VL_PREC_VADU = 0
 VL_PREC_LRAC = 1
+VL_PREC_LVA = 2
+VL_PREC_DIAG = 3
 VL_FP64 = 0
 VL_MIXED = 1
 

@@ -24,6 +24,8 @@ Plain FP64 NumPy/SciPy, following the paper step by step:
                    auxiliary parameter xi (Gaussian tau^2, Gamma shape)
   predict          eq. (latentpostpredictive) with B_p = I and the simulation
                    algorithm (Sec. 3.3.1, Alg. simAlgo)
+  predict_lanczos  the same means with preconditioned Lanczos variances (Sec.
+                   3.3.2, P_L1 and P_L2, complete reorthogonalization)
 
 Readings of silent or ambiguous points:
   * CG stops when the unpreconditioned residual 2-norm is below `cg_tol`
@@ -723,6 +725,92 @@ def predict(model, coords_p, Fp, b, W, opts, replay_cg=None, chunk=256,
     info["cg_iters"] = iters
     info["acc"] = acc
     return mean, var, info
+
+
+PRED_LANCZOS_L1 = 1   # P_L1 = B^T (W + D^{-1}) B (Sec. 3.3.2)
+PRED_LANCZOS_L2 = 2   # P_L2 = diag(Sigma + W^{-1}) on Sigma~ + W^{-1} (Sec. 3.3.2)
+LANCZOS_BREAKDOWN = 1e-13
+
+
+def lanczos_full_reorth(apply_M, q1, k):
+    """k steps of the symmetric Lanczos process on M from the direction q1,
+    with complete reorthogonalization (each new vector is orthogonalised
+    against all previous Lanczos vectors by classical Gram-Schmidt, applied
+    twice; Golub & Van Loan, Matrix Computations, Sec. 10.3.1).
+
+    Step j: w = M q_j; alpha_j = q_j^T w; w -= Q_j (Q_j^T w) twice;
+    beta_j = |w|; q_{j+1} = w / beta_j.  Stops early when beta_j <=
+    LANCZOS_BREAKDOWN max|alpha| (an invariant subspace).  Returns Q (n x k')
+    and the k' x k' tridiagonal T = tridiag(beta, alpha, beta)."""
+    n = q1.shape[0]
+    Q = np.zeros((n, k))
+    alpha, beta = [], []
+    Q[:, 0] = q1 / np.linalg.norm(q1)
+    kk = k
+    for j in range(k):
+        w = apply_M(Q[:, j])
+        Qj = Q[:, :j + 1]
+        c = Qj.T @ w
+        alpha.append(float(c[j]))
+        w = w - Qj @ c
+        w = w - Qj @ (Qj.T @ w)
+        if j + 1 == k:
+            break
+        bj = float(np.linalg.norm(w))
+        if bj <= LANCZOS_BREAKDOWN * max(abs(a) for a in alpha):
+            kk = j + 1
+            break
+        beta.append(bj)
+        Q[:, j + 1] = w / bj
+    T = np.diag(alpha) + np.diag(beta, 1) + np.diag(beta, -1)
+    return Q[:, :kk], T
+
+
+def predict_lanczos(model, coords_p, Fp, b, W, k, precond):
+    """Predictive latent means and Lanczos predictive variances (Sec. 3.3.2).
+
+    omega_p as in predict; diag Omega_p ~= D_p + diag(B_po X B_po^T) with X
+    the rank-k preconditioned Lanczos approximation of (W + Sigma~^{-1})^{-1}:
+      P_L1: M = P^{-1/2} A P^{-T/2}, P^{-1/2} = (W + D^{-1})^{-1/2} B^{-T}
+            (eq. P_VADU_prec), X = P^{-T/2} Q T^{-1} Q^T P^{-1/2};
+      P_L2: M = P^{-1/2} (Sigma~ + W^{-1}) P^{-1/2}, P = diag(sigma^2 + 1/W)
+            (diag Sigma = sigma^2 standing in for diag Sigma~),
+            X = W^{-1} P^{-1/2} Q T^{-1} Q^T P^{-1/2} Sigma~.
+    The Lanczos process starts from the average column x of B_po^T mapped
+    into M's coordinates: P^{-1/2} x (P_L1), P^{-1/2} Sigma~ x (P_L2)."""
+    coords_p = np.asarray(coords_p, dtype=np.float64)
+    npred = coords_p.shape[0]
+    nbr_p = _vec.pred_neighbours(model.coords, coords_p, model.m)
+    Ap, Dp = _vec.factor(model.coords, nbr_p, model.kind, model.theta, coords_self=coords_p)
+    Bpo = _vec.sparse_offdiag(-Ap, nbr_p, model.n)
+    Fp = np.zeros(npred) if Fp is None else np.asarray(Fp, dtype=np.float64)
+    mean = Fp - Bpo @ b
+    xbar = (Bpo.T @ np.ones(npred)) / npred
+    if precond == PRED_LANCZOS_L1:
+        s = 1.0 / np.sqrt(W + model.Dinv)
+
+        def apply_M(q):
+            y = model.solve_B(s * q)
+            return s * model.solve_Bt(W * y + model.prec_apply(y))
+
+        Q, T = lanczos_full_reorth(apply_M, s * model.solve_Bt(xbar), k)
+        G = Bpo @ model.solve_B(s[:, None] * Q)
+        var = Dp + np.sum(G * np.linalg.solve(T, G.T).T, axis=1)
+    elif precond == PRED_LANCZOS_L2:
+        s = 1.0 / np.sqrt(model.theta[0] + 1.0 / W)
+
+        def apply_M(q):
+            y = s * q
+            return s * (model.cov_apply(y) + y / W)
+
+        Q, T = lanczos_full_reorth(apply_M, s * model.cov_apply(xbar), k)
+        G1 = Bpo @ ((s / W)[:, None] * Q)
+        G2 = Bpo @ model.cov_apply(s[:, None] * Q)
+        var = Dp + np.sum(G1 * np.linalg.solve(T, G2.T).T, axis=1)
+    else:
+        raise ValueError("unknown Lanczos preconditioner")
+    return mean, var, {"nbr_p": nbr_p, "Ap": Ap, "Dp": Dp, "Q": Q, "T": T,
+                       "rank": Q.shape[1]}
 
 
 def _gaussian_cols(seed, tag, n, c0, c1):

@@ -719,3 +719,77 @@ def test_xi_gradient_gamma_matches_finite_differences():
         no_logdet = np.mean([i["grad_xi"] - 0.5 * i["dlogdet_xi"] for i in infos])
         no_implicit = np.mean([i["grad_xi"] - i["implicit_xi"] for i in infos])
         assert abs(no_logdet - fd) > 8 * se and abs(no_implicit - fd) > 8 * se
+
+
+# ------------------------------------------------------ Lanczos prediction
+def _lanczos_setup(n=70, m=6, npred=15, seed=41):
+    model, y, F = _problem(n=n, m=m, seed=seed, kind=V.COV_MATERN32, theta=(1.0, 0.2))
+    Xp = np.random.default_rng(seed + 1).uniform(size=(npred, 2))
+    o = L.Opts(cg_tol=1e-12, newton_tol=1e-15)
+    b, W, _ = L.find_mode(model, y, F, L.LIK_BERNOULLI_LOGIT, None, o)
+    _, _, info = L.predict(model, Xp, None, b, W, o, want_var=False)
+    Ap = np.zeros((npred, n))
+    for p in range(npred):
+        Ap[p, info["nbr_p"][p]] = info["Ap"][p]
+    A = np.diag(W) + DR.dense_precision(model.B, model.D)
+    exact = info["Dp"] + np.einsum("pi,pi->p", Ap, np.linalg.solve(A, Ap.T).T)
+    return model, Xp, b, W, Ap, exact
+
+
+@pytest.mark.parametrize("method", [L.PRED_LANCZOS_L1, L.PRED_LANCZOS_L2])
+def test_lanczos_full_rank_is_exact(method):
+    """k = n: the Lanczos vectors span the space and Q T^{-1} Q^T = M^{-1}, so
+    both preconditioned forms give the dense predictive variance D_p +
+    diag(A_p A^{-1} A_p^T) (eq. latentpostpredictive) and the mean A_p b*."""
+    model, Xp, b, W, Ap, exact = _lanczos_setup()
+    mean, var, info = L.predict_lanczos(model, Xp, None, b, W, model.n, method)
+    assert info["rank"] == model.n
+    np.testing.assert_allclose(mean, Ap @ b, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(var, exact, rtol=1e-8)
+
+
+@pytest.mark.parametrize("method", [L.PRED_LANCZOS_L1, L.PRED_LANCZOS_L2])
+def test_lanczos_relation_and_orthonormality(method):
+    """M Q_k = Q_k T_k + beta_k q_{k+1} e_k^T (the residual lives in the last
+    column only), Q_k^T Q_k = I, T_k symmetric positive definite, q_1 along
+    the mapped mean column; M built densely from the preconditioner's
+    definition (Sec. 3.3.2)."""
+    model, Xp, b, W, Ap, exact = _lanczos_setup()
+    k = 20
+    _, _, info = L.predict_lanczos(model, Xp, None, b, W, k, method)
+    Q, T = info["Q"], info["T"]
+    Bd = model.B.toarray()
+    Binv = np.linalg.inv(Bd)
+    St = Binv @ np.diag(model.D) @ Binv.T
+    if method == L.PRED_LANCZOS_L1:
+        Pih = np.diag((W + model.Dinv) ** -0.5) @ Binv.T
+        M = Pih @ (np.diag(W) + np.linalg.inv(St)) @ Pih.T
+    else:
+        s = (model.theta[0] + 1.0 / W) ** -0.5
+        M = np.diag(s) @ (St + np.diag(1.0 / W)) @ np.diag(s)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(k), atol=1e-12)
+    # the start: the mean column of B_po^T = -A_p^T mapped into M's coordinates
+    xbar = -Ap.sum(axis=0) / Ap.shape[0]
+    if method == L.PRED_LANCZOS_L1:
+        q1 = Pih @ xbar
+    else:
+        q1 = s * (St @ xbar)
+    np.testing.assert_allclose(Q[:, 0], q1 / np.linalg.norm(q1), atol=1e-12)
+    R = M @ Q - Q @ T
+    assert np.max(np.abs(R[:, :-1])) < 1e-10 * np.max(np.abs(M))
+    assert np.allclose(T, T.T) and np.linalg.eigvalsh(T).min() > 0
+
+
+def test_lanczos_l1_variance_increases_with_rank_to_the_exact_value():
+    """P_L1 form: g^T T_k^{-1} g is the quadratic form of the inverse projected
+    onto a growing (nested) Krylov space, so the variance never decreases in
+    k and never exceeds the exact value (the systematic underestimation the
+    paper reports)."""
+    model, Xp, b, W, Ap, exact = _lanczos_setup()
+    prev = None
+    for k in (2, 5, 10, 20, 40):
+        _, var, _ = L.predict_lanczos(model, Xp, None, b, W, k, L.PRED_LANCZOS_L1)
+        assert np.all(var <= exact * (1 + 1e-10))
+        if prev is not None:
+            assert np.all(var >= prev * (1 - 1e-10))
+        prev = var

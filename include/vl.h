@@ -79,6 +79,17 @@ typedef enum {
 } vl_precond;
 typedef enum { VL_FP64 = 0, VL_MIXED = 1 } vl_precision;
 
+/* Predictive-variance method of vl_predict (Sec. 3.3): simulation (Alg.
+ * simAlgo, s = num_pred_samples) or rank-k preconditioned Lanczos with
+ * complete reorthogonalization (Sec. 3.3.2, k = lanczos_rank) with P_L1 =
+ * B^T (W + D^{-1}) B or P_L2 = diag(sigma^2 + 1/W) on Sigma~ + W^{-1} (the
+ * original covariance's diagonal sigma^2 stands in for diag Sigma~). */
+typedef enum {
+  VL_PRED_SIMULATION = 0,
+  VL_PRED_LANCZOS_L1 = 1,
+  VL_PRED_LANCZOS_L2 = 2
+} vl_pred_method;
+
 /* Options.  vl_default_opts fills the paper's defaults (Sec. 4.1): t = 50
  * probes, LRAC rank k = 50, CG tolerance 1e-2 for likelihoods and 1e-3 for
  * predictive variances, s = 2000 simulation samples. */
@@ -110,6 +121,9 @@ typedef struct {
                               negative entries, keep the tolerance test; the
                               max_cg cap always applies                     */
   int replay_len;          /* number of entries of replay_cg_iters            */
+  int pred_method;         /* vl_pred_method (default simulation)             */
+  int lanczos_rank;        /* k of the Lanczos variances, 1..min(n, 4096)
+                              (default 100); FP64 in every precision form     */
 } vl_opts;
 
 /* Per-call statistics (host struct, filled by the call that receives it). */

@@ -159,6 +159,8 @@ static int64_t export_count(Model& M, int which) {
     case 17: return M.lrac_ready ? M.lrac_k : -1;
     case 18: return M.lrac_ready ? static_cast<int64_t>(M.lrac_K) * M.lrac_K : -1;
     case 19: return static_cast<int64_t>(M.newton_halvings.size());
+    case 20: return static_cast<int64_t>(M.last_lanczos_alpha.size());
+    case 21: return static_cast<int64_t>(M.last_lanczos_beta.size());
     default: return -1;
   }
 }
@@ -201,6 +203,8 @@ static Status do_export(Model& M, int which, void* dst, size_t bytes) {
     case 17: return copy_out(M, dst, M.lrac_piv.p, need, false);
     case 18: return copy_out(M, dst, M.lrac_M.p, need, false);
     case 19: return copy_out(M, dst, M.newton_halvings.data(), need, true);
+    case 20: return copy_out(M, dst, M.last_lanczos_alpha.data(), need, true);
+    case 21: return copy_out(M, dst, M.last_lanczos_beta.data(), need, true);
     default: return Status::invalid("unknown export");
   }
 }
@@ -234,6 +238,9 @@ static Status check_opts(const vl_opts* o) {
   if (o->precond != VL_PREC_VADU && o->precond != VL_PREC_LRAC && o->precond != VL_PREC_LVA &&
       o->precond != VL_PREC_DIAG)
     return Status::invalid("unknown preconditioner");
+  if (o->pred_method != VL_PRED_SIMULATION && o->pred_method != VL_PRED_LANCZOS_L1 &&
+      o->pred_method != VL_PRED_LANCZOS_L2)
+    return Status::invalid("unknown predictive-variance method");
   if (o->precision != VL_FP64 && o->precision != VL_MIXED)
     return Status::invalid("unknown precision");
   if (o->replay_len < 0 || (o->replay_len > 0 && !o->replay_cg_iters))
@@ -288,6 +295,8 @@ void vl_default_opts(vl_opts* o) {
   o->lrac_rank = 50;
   o->precision = VL_FP64;
   o->pred_tile = 0;
+  o->pred_method = VL_PRED_SIMULATION;
+  o->lanczos_rank = 100;
 }
 
 const char* vl_status_string(vl_status s) {

@@ -939,6 +939,7 @@ Status predict(Model& M, const double* coords_p, int64_t np, const double* Fp,
     VL_TRY(sync_stream(M.stream));
     return read_status(M);
   }
+  if (o.pred_method != VL_PRED_SIMULATION) return predict_lanczos_var(M, np, o, var_out, info);
   const int s = o.num_pred_samples;
   if (s < 1) return Status::invalid("num_pred_samples must be positive");
   const int64_t n = M.n;

@@ -128,6 +128,36 @@ Status build_transpose(Model& M) {
   return Status::ok();
 }
 
+Status transpose_pattern(Model& M, const int* nbr, int64_t rows, int m, int64_t cols,
+                         DevBuf<int>& ptr, DevBuf<int>& col, DevBuf<int>& src, int* nnz_out) {
+  hipStream_t s = M.stream;
+  VL_TRY(ptr.reserve(cols + 1));
+  DevBuf<int> cnt;
+  VL_TRY(cnt.alloc(cols + 1));
+  VL_TRY(fill_int(cnt.p, 0, cols + 1, s));
+  const int tb = 256;
+  const int64_t nm = rows * m;
+  if (nm > 0)
+    hipLaunchKernelGGL(bt_count, dim3((unsigned)((nm + tb - 1) / tb)), dim3(tb), 0, s, nbr,
+                       rows, m, cnt.p);
+  VL_TRY(exclusive_scan_int(cnt.p, ptr.p, cols + 1, s));
+  int nnz = 0;
+  VL_HIP(hipMemcpyAsync(&nnz, ptr.p + cols, sizeof(int), hipMemcpyDeviceToHost, s));
+  VL_TRY(sync_stream(s));
+  VL_TRY(col.reserve(nnz > 0 ? nnz : 1));
+  VL_TRY(src.reserve(nnz > 0 ? nnz : 1));
+  VL_TRY(fill_int(cnt.p, 0, cols + 1, s));
+  if (nm > 0)
+    hipLaunchKernelGGL(bt_fill, dim3((unsigned)((nm + tb - 1) / tb)), dim3(tb), 0, s, nbr, rows,
+                       m, ptr.p, cnt.p, col.p, src.p);
+  hipLaunchKernelGGL(bt_sort_rows, dim3((unsigned)((cols + tb - 1) / tb)), dim3(tb), 0, s, cols,
+                     ptr.p, col.p, src.p);
+  VL_TRY(check_launch("transpose pattern"));
+  VL_TRY(sync_stream(s));  // cnt is released on return
+  *nnz_out = nnz;
+  return Status::ok();
+}
+
 Status refresh_transpose_values(Model& M) {
   if (M.nnz == 0) return Status::ok();
   const int tb = 256;

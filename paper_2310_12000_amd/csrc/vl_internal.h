@@ -285,6 +285,9 @@ struct Model {
     return Status::ok();
   }
 
+  // Lanczos coefficients (alpha, beta) of the last Lanczos prediction
+  std::vector<double> last_lanczos_alpha, last_lanczos_beta;
+
   // gradient of the last likelihood call in the offset F (n), when asked
   DevBuf<double> grad_F;
   bool has_grad_F = false;

@@ -37,6 +37,11 @@ Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, Nl
 Status predict(Model& M, const double* coords_p, int64_t np, const double* Fp,
                const vl_opts& o, double* mean_out, double* var_out, PredInfo* info);
 
+// Lanczos predictive variances (lanczos.hip) at the test points whose
+// neighbours and factor rows predict() has placed in M.pred_*
+Status predict_lanczos_var(Model& M, int64_t np, const vl_opts& o, double* var_out,
+                           PredInfo* info);
+
 // out (host, p) = X^T dL/dF for F = X beta (X device, n x p row-major)
 Status grad_beta(Model& M, const double* X, int p, double* out);
 

@@ -196,6 +196,11 @@ Status spmm_ell_vals(Model& M, const double* vals, const double* X, double* Y, i
 Status spmm_bt_probe(Model& M, double* Y, int t, const double* s, uint64_t seed, uint32_t tag2,
                      int col0, int gauss2, const double* d, uint32_t tag1, int gauss1,
                      double* tmp1, double* tmp2);
+// CSR of the transpose of a rows x cols pattern given as rows x m column
+// indices (-1 = none): row j of the result lists the (row index, source slot
+// r * m + k) pairs with nbr[r * m + k] = j, sorted by row index.
+Status transpose_pattern(Model& M, const int* nbr, int64_t rows, int m, int64_t cols,
+                         DevBuf<int>& ptr, DevBuf<int>& col, DevBuf<int>& src, int* nnz_out);
 // Y[i, c] = s_i eps_ic (Rademacher probes of columns col0 .. col0 + t - 1)
 Status probe_fill(Model& M, double* Y, int t, const double* s, uint64_t seed, uint32_t tag,
                   int col0);

@@ -38,6 +38,9 @@ VL_PREC_LVA = 2
 VL_PREC_DIAG = 3
 VL_FP64 = 0
 VL_MIXED = 1
+VL_PRED_SIMULATION = 0
+VL_PRED_LANCZOS_L1 = 1
+VL_PRED_LANCZOS_L2 = 2
 
 EXPORT = {
     "nbr": (0, torch.int32), "bval": (1, torch.float64), "D": (2, torch.float64),
@@ -50,6 +53,7 @@ EXPORT = {
     "pred_D": (15, torch.float64),
     "lrac_L": (16, torch.float64), "lrac_piv": (17, torch.int32),
     "lrac_chol": (18, torch.float64), "newton_halvings": (19, torch.int32),
+    "lanczos_alpha": (20, torch.float64), "lanczos_beta": (21, torch.float64),
 }
 
 
@@ -62,6 +66,7 @@ class vl_opts(ctypes.Structure):
         ("precond", ctypes.c_int), ("lrac_rank", ctypes.c_int),
         ("precision", ctypes.c_int), ("pred_tile", ctypes.c_int),
         ("replay_cg_iters", ctypes.POINTER(ctypes.c_int)), ("replay_len", ctypes.c_int),
+        ("pred_method", ctypes.c_int), ("lanczos_rank", ctypes.c_int),
     ]
 
     def __copy__(self):

@@ -198,6 +198,10 @@ def main():
         for name, fn in (("mixed", lambda: form_mixed(P, torch, w, coords, y, F, coords_p, Fp,
                                                        theta, opts, args)),
                          ("mixed_c3_shape", lambda: form_mixed_c3(P, torch, synth, args)),
+                         ("preconditioners", lambda: form_preconditioners(
+                             P, torch, w, coords, y, F, theta, opts, args)),
+                         ("pred_variance_methods",
+                          lambda: form_pred_variance_methods(P, torch, synth, args)),
                          ("batch", lambda: form_batch(P, torch, synth, args)),
                          ("serving", lambda: form_serving(P, torch, synth, args))):
             print(f"form: {name}", file=sys.stderr, flush=True)
@@ -264,6 +268,99 @@ def form_mixed_c3(P, torch, synth, args):
                        "with offset 1, t=64, CG tol 1e-2, 10000 test points, s=256; one eval = "
                        "build + mode + NLL + predict")
     return out
+
+
+def form_preconditioners(P, torch, w, coords, y, F, theta, opts, args):
+    """The likelihood evaluation (set theta, mode from zero, SLQ NLL) with
+    each preconditioner on the same workload and probes: time, CG
+    iterations, and the probe standard error of the log-determinant estimate
+    (sample sd of r0^T z0 e_1^T log(T) e_1 over the t probes / sqrt t), the
+    variance the preconditioners of Sec. 3.1 are compared on."""
+    import copy
+    import numpy as np
+    res = {}
+    for name, pc in (("VADU", P.VL_PREC_VADU), ("LVA", P.VL_PREC_LVA), ("LRAC", P.VL_PREC_LRAC),
+                     ("P1", P.VL_PREC_DIAG)):
+        o = copy.copy(opts)
+        o.precond = pc
+        g = P.VecchiaLaplace(coords, w["m"], w["kind"], theta)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.set_theta(theta)
+        _, st = g.find_mode(y, F, w["lik"], None, o, allow_no_conv=True)
+        t1 = time.perf_counter()
+        nll, _, nst = g.neg_log_marglik(o, allow_no_conv=True)
+        t2 = time.perf_counter()
+        terms = g.export("slq_r0z0").cpu().numpy() * g.export("slq_quad").cpu().numpy()
+        g.close()
+        res[name] = {"mode_ms": 1e3 * (t1 - t0), "nll_ms": 1e3 * (t2 - t1), "nll": nll,
+                     "newton_cg_total": st.cg_iters_total, "slq_cg_max": nst.cg_iters_max,
+                     "hit_cap": bool(nst.cg_iters_max >= o.max_cg or st.hit_cap),
+                     "logdet_probe_se": float(np.std(terms, ddof=1) / np.sqrt(len(terms)))}
+        log(args, f"preconditioner {name}: {res[name]}")
+    return res
+
+
+def form_pred_variance_methods(P, torch, synth, args):
+    """Simulated (Alg. simAlgo) versus preconditioned-Lanczos (Sec. 3.3.2)
+    predictive variances at n = n_p = 5,000 (Matern-3/2 range 0.05, m = 20,
+    Bernoulli-logit): time on the GPU and the relative RMSE and largest
+    relative error against the exact variances D_p + diag(A_p A^{-1} A_p^T),
+    computed densely on the host from the device's own factor, mode and
+    prediction rows (so that only the variance method differs)."""
+    import copy
+    import numpy as np
+    w = synth.make("c2_n1e5", seed=args.seed, n=5000, n_pred=5000)
+    d = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    coords, y, F, cp, Fp = (d(w["coords"]), d(w["y"]), d(w["F"]), d(w["coords_pred"]),
+                            d(w["Fp"]))
+    base = P.vl_default_opts(cg_tol=1e-8, pred_cg_tol=1e-3, seed=args.seed)
+    g = P.VecchiaLaplace(coords, w["m"], w["kind"], (w["sigma2"], w["rho"]))
+    g.find_mode(y, F, w["lik"], None, base)
+    g.predict(cp, Fp, base, want_var=False)
+    h = lambda name: g.export(name).cpu().numpy()
+    n, m, npred = w["n"], w["m"], w["n_pred"]
+    nbr, bval, D, W = h("nbr").reshape(n, m), h("bval").reshape(n, m), h("D"), h("W")
+    pnbr, pval, Dp = h("pred_nbr").reshape(npred, m), h("pred_bval").reshape(npred, m), h("pred_D")
+    # dense exact reference: A = W + B^T D^{-1} B, B = I - (A_i entries) in ELL
+    B = np.eye(n)
+    Ap = np.zeros((npred, n))
+    for i in range(n):
+        ok = nbr[i] >= 0
+        B[i, nbr[i][ok]] = bval[i][ok]
+    for j in range(npred):
+        ok = pnbr[j] >= 0
+        Ap[j, pnbr[j][ok]] = pval[j][ok]
+    A = np.diag(W) + B.T @ (B / D[:, None])
+    exact = Dp + np.einsum("pi,pi->p", Ap, np.linalg.solve(A, Ap.T).T)
+    res = {"workload": "n=n_p=5000, Matern-3/2 rho=0.05, m=20, Bernoulli-logit; simulation "
+                       "CG tol 1e-3", "methods": {}}
+
+    def run(label, o):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, var, _ = g.predict(cp, Fp, o, allow_no_conv=True)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0)
+        v = var.cpu().numpy()
+        rel = (v - exact) / exact
+        res["methods"][label] = {"ms": ms, "rel_rmse": float(np.sqrt(np.mean(rel ** 2))),
+                                 "max_rel_err": float(np.max(np.abs(rel))),
+                                 "mean_rel_bias": float(np.mean(rel))}
+        log(args, f"variance method {label}: {res['methods'][label]}")
+
+    for s in (100, 500, 2000):
+        o = copy.copy(base)
+        o.num_pred_samples = s
+        run(f"simulation s={s}", o)
+    for method, tag in ((P.VL_PRED_LANCZOS_L1, "L1"), (P.VL_PRED_LANCZOS_L2, "L2")):
+        for k in (50, 200, 500):
+            o = copy.copy(base)
+            o.pred_method = method
+            o.lanczos_rank = k
+            run(f"lanczos P_{tag} k={k}", o)
+    g.close()
+    return res
 
 
 def form_batch(P, torch, synth, args):

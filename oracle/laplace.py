@@ -842,3 +842,51 @@ def estimate(coords, m, kind, y, F, lik, aux, theta0, opts, nbr=None, gtol=1e-6,
                    method="L-BFGS-B", options={"gtol": gtol, "ftol": 1e-15, "maxiter": maxiter})
     return np.exp(res.x), float(res.fun), res
 
+
+def glm_params_to_x(theta, aux, beta, lik):
+    """Search coordinates (log sigma2, log rho, [log xi], beta)."""
+    x = [np.log(theta[0]), np.log(theta[1])]
+    if lik_has_aux(lik):
+        x.append(np.log(aux))
+    return np.concatenate([np.asarray(x), np.asarray(beta, dtype=np.float64)])
+
+
+def estimate_glm(coords, m, kind, y, X, lik, theta0, aux0, beta0, opts, nbr=None, gtol=1e-6,
+                 maxiter=200):
+    """Joint estimate of theta, the likelihood's auxiliary parameter xi (when
+    it has one) and the coefficients beta of F = X beta (Sec. 2; Sec. 5's
+    estimation of the shape, the covariance parameters and beta), by scipy's
+    L-BFGS-B over (log sigma2, log rho, log xi, beta) with the probes of
+    opts.seed in every evaluation.  The gradient: theta- and xi-gradients
+    (STE, App. "Gradients of Vecchia-Laplace approximations") times the
+    parameter (log scale), and X^T dL/dF for beta.
+    Returns (theta, xi or None, beta, nll, scipy result)."""
+    from scipy.optimize import minimize
+
+    coords = np.asarray(coords, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    nbr = _vec.neighbours(coords, m) if nbr is None else nbr
+    has_aux = lik_has_aux(lik)
+    q = 3 if has_aux else 2
+
+    def unpack(x):
+        theta = np.exp(x[:2])
+        aux = float(np.exp(x[2])) if has_aux else None
+        return theta, aux, x[q:]
+
+    def fun(x):
+        theta, aux, beta = unpack(x)
+        F = X @ beta
+        model = Model(coords, m, kind, theta, nbr=nbr, deriv=True)
+        b, _, _ = find_mode(model, y, F, lik, aux, opts)
+        nll, info = neg_log_marglik(model, y, F, lik, aux, b, opts, want_grad=True)
+        g = [info["grad"][0] * theta[0], info["grad"][1] * theta[1]]
+        if has_aux:
+            g.append(info["grad_xi"] * aux)
+        return nll, np.concatenate([np.asarray(g), X.T @ info["grad_F"]])
+
+    res = minimize(fun, glm_params_to_x(theta0, aux0, beta0, lik), jac=True, method="L-BFGS-B",
+                   options={"gtol": gtol, "ftol": 1e-15, "maxiter": maxiter})
+    theta, aux, beta = unpack(res.x)
+    return theta, aux, beta, float(res.fun), res
+

@@ -268,6 +268,24 @@ vl_status vl_estimate(vl_model* h, const double* y, const double* F, int lik,
                       int max_iter, double grad_tol, double* nll_host, int* iters_host,
                       int* evals_host);
 
+/* Joint estimation (Sec. 5: shape, covariance parameters and beta; Sec.
+ * 4.1's L-BFGS with a sample average approximation, as vl_estimate) of
+ * theta, the likelihood's auxiliary parameter xi (VL_LIK_GAUSSIAN: tau^2,
+ * VL_LIK_GAMMA: shape; none for the others) and beta of F = X beta.  The
+ * search runs on (log sigma2, log rho, [log xi], beta) with the gradient
+ * from vl_neg_log_marglik, vl_grad_aux and vl_grad_beta.
+ *   X            device, n x p row-major (NULL when p = 0: F = 0)
+ *   params_inout host, 2 + r + p with r = 1 for a likelihood with xi, else
+ *                0: {sigma2, rho, [xi], beta_0 .. beta_{p-1}}, start, then
+ *                the estimate
+ *   other arguments as for vl_estimate.
+ * Leaves the model at the estimate.  VL_ERR_NO_CONVERGENCE when max_iter was
+ * reached (params_inout holds the last iterate).  Synchronises. */
+vl_status vl_estimate_glm(vl_model* h, const double* y, const double* X, int p, int lik,
+                          const vl_opts* o, double* params_inout, int max_iter,
+                          double grad_tol, double* nll_host, int* iters_host,
+                          int* evals_host);
+
 /* Gradient of the negative log-marginal likelihood in the offset F at the
  * stored mode (App. "Gradients of Vecchia-Laplace approximations"):
  *   dL/dF_i = -d log p(y_i|mu_i)/d mu_i + (1/2) d log det(Sigma~ W + I)/d mu_i

@@ -623,6 +623,22 @@ __global__ __launch_bounds__(256) void xt_vec_kernel(ChunkGrid g, const double* 
   block_colsum(g, acc, part);
 }
 
+// F = X beta (X n x p row-major, beta device p)
+__global__ void xbeta_kernel(int64_t n, int p, const double* __restrict__ X,
+                             const double* __restrict__ beta, double* __restrict__ F) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int k = 0; k < p; ++k) acc += X[i * p + k] * beta[k];
+  F[i] = acc;
+}
+
+Status xbeta(Model& M, const double* X, int p, const double* beta, double* F) {
+  hipLaunchKernelGGL(xbeta_kernel, dim3((unsigned)((M.n + 255) / 256)), dim3(256), 0, M.stream,
+                     M.n, p, X, beta, F);
+  return check_launch("X beta");
+}
+
 // out (host, p) = X^T grad_F: the gradient in beta when F = X beta.
 Status grad_beta(Model& M, const double* X, int p, double* out) {
   if (!M.has_grad_F)

@@ -42,6 +42,9 @@ Status predict(Model& M, const double* coords_p, int64_t np, const double* Fp,
 Status predict_lanczos_var(Model& M, int64_t np, const vl_opts& o, double* var_out,
                            PredInfo* info);
 
+// F = X beta (X device n x p row-major, beta device p, F device n)
+Status xbeta(Model& M, const double* X, int p, const double* beta, double* F);
+
 // out (host, p) = X^T dL/dF for F = X beta (X device, n x p row-major)
 Status grad_beta(Model& M, const double* X, int p, double* out);
 

@@ -163,6 +163,8 @@ def lib():
                               ctypes.POINTER(D), I, D, ctypes.POINTER(D), ctypes.POINTER(I),
                               ctypes.POINTER(I)]
     L.vl_grad_beta.argtypes = [P, P, I, ctypes.POINTER(D)]
+    L.vl_estimate_glm.argtypes = [P, P, P, I, I, ctypes.POINTER(vl_opts), ctypes.POINTER(D), I,
+                                  D, ctypes.POINTER(D), ctypes.POINTER(I), ctypes.POINTER(I)]
     L.vl_grad_aux.argtypes = [P, ctypes.POINTER(D)]
     L.vl_export_count.argtypes = [P, I]
     L.vl_export_count.restype = I64
@@ -194,7 +196,7 @@ def lib():
     L.vl_server_free.restype = None
     for f in ("vl_build_vecchia", "vl_set_theta", "vl_find_mode", "vl_neg_log_marglik",
               "vl_predict", "vl_export", "vl_spmm", "vl_trsm", "vl_trsm_noalloc",
-              "vl_set_allocator", "vl_grad_offset", "vl_grad_beta", "vl_grad_aux", "vl_estimate",
+              "vl_set_allocator", "vl_grad_offset", "vl_grad_beta", "vl_grad_aux", "vl_estimate", "vl_estimate_glm",
               "vl_timing_enable",
               "vl_timing_read", "vl_batch_create", "vl_batch_fit", "vl_batch_mode",
               "vl_batch_stats", "vl_server_create", "vl_server_submit", "vl_server_wait",
@@ -423,6 +425,22 @@ class VecchiaLaplace:
                                  ctypes.byref(it), ctypes.byref(ev))
         _check(code, allow=(VL_ERR_NO_CONVERGENCE,) if allow_no_conv else ())
         return (th[0], th[1]), nll.value, it.value, ev.value
+
+    def estimate_glm(self, y, X, lik, params0, opts=None, max_iter=100, grad_tol=1e-6,
+                     allow_no_conv=False):
+        """Joint L-BFGS estimate (vl_estimate_glm) of {sigma2, rho, [xi], beta}
+        with F = X beta (X: device n x p float64, or None for p = 0); returns
+        (params, nll, iters, evals)."""
+        opts = opts or vl_default_opts()
+        p = 0 if X is None else (1 if X.dim() == 1 else X.shape[1])
+        prm = (ctypes.c_double * len(params0))(*[float(v) for v in params0])
+        nll, it, ev = ctypes.c_double(), ctypes.c_int(), ctypes.c_int()
+        code = lib().vl_estimate_glm(self.h, _ptr(y), _ptr(X) if X is not None else None, p,
+                                     int(lik), ctypes.byref(opts), prm, int(max_iter),
+                                     float(grad_tol), ctypes.byref(nll), ctypes.byref(it),
+                                     ctypes.byref(ev))
+        _check(code, allow=(VL_ERR_NO_CONVERGENCE,) if allow_no_conv else ())
+        return list(prm), nll.value, it.value, ev.value
 
     def grad_offset(self):
         """dL/dF (device tensor, n) from the last neg_log_marglik with a gradient."""

@@ -17,8 +17,10 @@ Plain FP64 NumPy/SciPy, following the paper step by step:
                    eq. (logdetsplit) (VADU, Sec. 3.1.1) or eq. (logdetsplit2)
                    (LRAC, Sec. 3.1.2) and SLQ for the last term
   grad_theta       App. "Gradients of Vecchia-Laplace approximations" with the
-                   VADU STE / control-variate formulas of the appendix
-                   "Derivatives of log-determinants ... Preconditioner VADU";
+                   VADU or LRAC STE / control-variate formulas of the appendix
+                   "Derivatives of log-determinants ... Preconditioner VADU /
+                   LRAC" (LRAC with the forward-mode derivative of the
+                   pivoted Cholesky factor);
                    also the gradient in the offset F (for F = X beta the
                    beta-gradient is X^T of it) and in the likelihood's
                    auxiliary parameter xi (Gaussian tau^2, Gamma shape)
@@ -378,6 +380,41 @@ def pivoted_cholesky(coords, kind, theta, k, pivots=None):
     return L
 
 
+def pivoted_cholesky_deriv(coords, kind, theta, k, pivots=None):
+    """L_k of pivoted_cholesky and its derivatives dL[q] = d L_k / d theta_q
+    (q = 0: sigma2, 1: rho), the forward-mode derivative of the same steps
+    with the pivots held fixed (they are piecewise constant in theta).  The
+    paper leaves d L_k / d theta open (App. "Preconditioner LRAC"); with
+    d_p = Sigma_pp - sum_{l<j} L_pl^2 and column j = (Sigma[:, p] - L L_p^T) /
+    sqrt(d_p):
+      d col_j = (dSigma[:, p] - dL L_p^T - L dL_p^T - col_j d(sqrt d_p)) / sqrt(d_p),
+      d(sqrt d_p) = (dSigma_pp - 2 sum_{l<j} L_pl dL_pl) / (2 sqrt d_p).
+    Returns (L, dL, pivots)."""
+    sigma2, rho = theta
+    n = coords.shape[0]
+    k = min(k, n)
+    L = np.zeros((n, k))
+    dL = np.zeros((2, n, k))
+    d = np.full(n, float(sigma2))
+    dd = np.stack([np.ones(n), np.zeros(n)])  # d Sigma_ii / d theta: c(0) = sigma2
+    piv = []
+    for j in range(k):
+        p = int(np.argmax(d)) if pivots is None else int(pivots[j])
+        piv.append(p)
+        d2 = _vec.sqdist(coords, coords[p])
+        col = _vec.covariance(d2, kind, sigma2, rho)
+        dcol = _vec.covariance_grad(d2, kind, sigma2, rho)
+        s = np.sqrt(d[p])
+        L[:, j] = (col - L[:, :j] @ L[p, :j]) / s
+        for q in range(2):
+            ds = dd[q][p] / (2.0 * s)
+            dnum = dcol[q] - dL[q][:, :j] @ L[p, :j] - L[:, :j] @ dL[q][p, :j]
+            dL[q][:, j] = (dnum - L[:, j] * ds) / s
+            dd[q] = dd[q] - 2.0 * L[:, j] * dL[q][:, j]
+        d = d - L[:, j] ** 2
+    return L, dL, np.asarray(piv)
+
+
 class LracPrecond:
     """P_LRAC = L_k L_k^T + W^{-1} (eq. P_LRAC) with Woodbury solves and the
     determinant lemma."""
@@ -561,13 +598,105 @@ def neg_log_marglik(model, y, F, lik, aux, b, opts, replay_cg=None, L=None,
             "gamma": gamma, "cg_iters": res.iters.copy(), "quad": quad,
             "r0z0": res.r0z0.copy()}
     if want_grad:
-        if opts.precond != PRECOND_VADU:
-            raise NotImplementedError("theta-gradient is implemented for VADU")
-        grad, ginfo = _grad_theta_vadu(model, y, F, lik, aux, b, W, res, opts,
-                                       replay_grad_cg)
+        if opts.precond == PRECOND_VADU:
+            grad, ginfo = _grad_theta_vadu(model, y, F, lik, aux, b, W, res, opts,
+                                           replay_grad_cg)
+        elif opts.precond == PRECOND_LRAC:
+            grad, ginfo = _grad_lrac(model, y, F, lik, aux, b, W, res, opts, P,
+                                     replay_grad_cg)
+        else:
+            raise NotImplementedError("the gradient is implemented for VADU and LRAC")
         info["grad"] = grad
         info.update(ginfo)  # includes grad_F (offset) and, with a xi, grad_xi
     return nll, info
+
+
+def _dprec_form(model, k, X, Y):
+    """Column-wise X^T (d Sigma~^{-1} / d theta_k) Y by eq. (vecchiaSigmaderiv)."""
+    BX, BY = model.B @ X, model.B @ Y
+    dBX, dBY = model.dB[k] @ X, model.dB[k] @ Y
+    Dinv = model.Dinv
+    dD = model.dD[k]
+    return np.sum(dBX * Dinv[:, None] * BY, axis=0) + np.sum(BX * Dinv[:, None] * dBY, axis=0) \
+        - np.sum(BX * (Dinv * Dinv * dD)[:, None] * BY, axis=0)
+
+
+def _grad_lrac(model, y, F, lik, aux, b, W, res, opts, P, replay_grad_cg):
+    """Gradients of L^VLA (App. "Gradients of Vecchia-Laplace approximations")
+    with the LRAC STE formulas and control variates (App. "Preconditioner
+    LRAC").  With u = (Sigma~ + W^{-1})^{-1} z and v = P^{-1} z (z ~ N(0, P)),
+    M = I + L^T W L and l_i = L_i M^{-1} L_i^T:
+      mu_i: d log det / d mu_i = dW_i / W_i + c_i (dW_i l_i - dW_i / W_i)
+            - mean(h - c_i r), h = u_i dW_i v_i / W_i^2, r = dW_i v_i^2 / W_i^2;
+      theta_k: c tr(M^{-1} (dL^T W L + L^T W dL)) + mean(h - c r),
+            h = -(Sigma~ u)^T dSigma~^{-1} (Sigma~ v), r = v^T (dL L^T + L dL^T) v;
+      xi: as mu with dW/dxi summed over the rows.
+    The mode's response uses w = A^{-1} dL/db* = W^{-1} (Sigma~ + W^{-1})^{-1}
+    Sigma~ dL/db* (eq. pcls2), solved by PCG with P_LRAC."""
+    if not hasattr(model, "dB"):
+        raise ValueError("model built without derivatives")
+    n = model.n
+    U = res.U
+    V = res.Z0
+    L = P.L
+    Minv = np.linalg.inv(P.M)
+    lev = np.einsum("ij,jk,ik->i", L, Minv, L)
+    mu = F + b
+    parts = {}
+    dW = lik_dW(lik, y, mu, aux)
+    Wi2 = 1.0 / (W * W)
+    h_mu = (dW * Wi2)[:, None] * U * V
+    r_mu = (dW * Wi2)[:, None] * V * V
+    c_mu = _cv_weight(h_mu, r_mu)
+    dlogdet_dmu = dW / W + c_mu * (dW * lev - dW / W) - np.mean(h_mu - c_mu[:, None] * r_mu,
+                                                                axis=1)
+    dL_db = 0.5 * dlogdet_dmu
+    parts.update(h_mu=h_mu, r_mu=r_mu, c_mu=c_mu, dlogdet_dmu=dlogdet_dmu, lev=lev)
+    apply_S, apply_Pinv, _ = lrac_ops(model, W, L)
+    if np.any(dL_db != 0.0):
+        forced = None if replay_grad_cg is None else [replay_grad_cg]
+        wres = pcg(apply_S, apply_Pinv, model.cov_apply(dL_db), opts.cg_tol, opts.max_cg, forced)
+        wsol = wres.U / W
+        parts["grad_cg_iters"] = int(wres.iters[0])
+    else:
+        wsol = np.zeros(n)
+        parts["grad_cg_iters"] = 0
+    parts["grad_F"] = -lik_grad(lik, y, mu, aux) + dL_db - W * wsol
+    # theta: Sigma~ u and Sigma~ v, and the pivoted Cholesky's derivative
+    # the pivot of column j is the row where the column takes its largest
+    # value sqrt(d_p) (the residual covariance is bounded by its diagonal)
+    piv = [int(np.argmax(np.abs(L[:, j]))) for j in range(L.shape[1])]
+    _, dL, _ = pivoted_cholesky_deriv(model.coords, model.kind, model.theta, L.shape[1], piv)
+    SU = model.cov_apply(U)
+    SV = model.cov_apply(V)
+    LV = L.T @ V
+    Bb = model.B @ b
+    grad = np.zeros(2)
+    for k in range(2):
+        h = -_dprec_form(model, k, SU, SV)
+        r = 2.0 * np.sum(LV * (dL[k].T @ V), axis=0)
+        c = float(_cv_weight(h, r))
+        trP = 2.0 * np.trace(Minv @ (L.T @ (W[:, None] * dL[k])))
+        dlogdet = c * trP + float(np.mean(h - c * r))
+        quad_k = float(_dprec_form(model, k, b[:, None], b[:, None])[0])
+        implicit = -float(wsol @ _dprec_apply(model, k, b, Bb))
+        grad[k] = 0.5 * quad_k + 0.5 * dlogdet + implicit
+        parts.update({f"dlogdet_{k}": dlogdet, f"quad_{k}": quad_k, f"implicit_{k}": implicit,
+                      f"c_{k}": c, f"h_{k}": h, f"r_{k}": r, f"trP_{k}": trP})
+    if lik_has_aux(lik):
+        dWx = lik_dW_dxi(lik, y, mu, aux)
+        h_xi = np.sum((dWx * Wi2)[:, None] * U * V, axis=0)
+        r_xi = np.sum((dWx * Wi2)[:, None] * V * V, axis=0)
+        c_xi = float(_cv_weight(h_xi, r_xi))
+        trW = float(np.sum(dWx / W))
+        trM = float(np.sum(dWx * lev))
+        dlogdet_xi = trW + c_xi * (trM - trW) - float(np.mean(h_xi - c_xi * r_xi))
+        dlogp_xi = float(np.sum(lik_dlogp_dxi(lik, y, mu, aux)))
+        implicit_xi = float(wsol @ lik_dgrad_dxi(lik, y, mu, aux))
+        parts.update(grad_xi=-dlogp_xi + 0.5 * dlogdet_xi + implicit_xi, h_xi=h_xi, r_xi=r_xi,
+                     c_xi=c_xi, dlogdet_xi=dlogdet_xi, dlogp_xi=dlogp_xi,
+                     implicit_xi=implicit_xi)
+    return grad, parts
 
 
 def _dprec_apply(model, k, x, Bx=None):

@@ -9,6 +9,7 @@ import pytest
 from scipy.stats import multivariate_normal
 
 from oracle import laplace as L
+from oracle import laplace as L_
 from oracle import rng as R
 from oracle import vecchia as V
 from tests import dense_ref as DR
@@ -836,3 +837,97 @@ def test_lanczos_l1_variance_increases_with_rank_to_the_exact_value():
         if prev is not None:
             assert np.all(var >= prev * (1 - 1e-10))
         prev = var
+
+
+# ------------------------------------------------------------ LRAC gradient
+def test_pivoted_cholesky_derivative_matches_finite_differences():
+    """d L_k / d theta with the pivots held fixed against central differences
+    of the pivoted Cholesky factor at the same pivots."""
+    X = np.random.default_rng(61).uniform(size=(60, 2))
+    for kind in (V.COV_EXPONENTIAL, V.COV_MATERN32):
+        th = np.array([1.3, 0.25])
+        L, dL, piv = L_.pivoted_cholesky_deriv(X, kind, th, 12)
+        np.testing.assert_array_equal(L, L_.pivoted_cholesky(X, kind, th, 12))
+        for q, h in ((0, 1e-6), (1, 1e-7)):
+            e = np.zeros(2)
+            e[q] = h
+            fd = (L_.pivoted_cholesky(X, kind, th + e, 12, pivots=piv)
+                  - L_.pivoted_cholesky(X, kind, th - e, 12, pivots=piv)) / (2 * h)
+            np.testing.assert_allclose(dL[q], fd, rtol=1e-6, atol=1e-7 * np.abs(fd).max())
+
+
+def _lrac_fd_setup(lik, aux, n=45, m=5, seed=71):
+    model, y, F = _problem(n=n, m=m, seed=seed, lik=lik, deriv=True, theta=(0.9, 0.25))
+    o0 = L.Opts(cg_tol=1e-12, newton_tol=1e-15)
+    b, W, _ = L.find_mode(model, y, F, lik, aux, o0)
+    return model, y, F, b
+
+
+def test_lrac_gradient_exact_at_full_rank():
+    """k = n and m = n - 1: L L^T = Sigma = Sigma~ and P_LRAC equals the
+    operator, so u = P^{-1} z, h = r for every probe (c = 1) and the LRAC STE
+    gives the exact derivatives: theta, the offset F and the Gamma shape
+    against central differences of the dense exact NLL."""
+    n = 30
+    for lik, aux in ((L.LIK_BERNOULLI_LOGIT, None), (L.LIK_GAMMA, 2.0)):
+        model, y, F = _problem(n=n, m=n - 1, seed=73, lik=lik, deriv=True, theta=(0.9, 0.25))
+        o = L.Opts(cg_tol=1e-13, newton_tol=1e-15, num_probes=6, seed=1,
+                   precond=L.PRECOND_LRAC, lrac_rank=n)
+        b, W, _ = L.find_mode(model, y, F, lik, aux, o)
+        _, info = L.neg_log_marglik(model, y, F, lik, aux, b, o, want_grad=True)
+
+        def dense(th, FF, aa):
+            A, D = V.factor(model.coords, model.nbr, model.kind, th)
+            Q = DR.dense_precision(V.sparse_B(A, model.nbr), D)
+            lp, lg, lw = _liks(lik, aa)
+            return DR.dense_nll(Q, y, FF, lp, lg, lw)[0]
+
+        th = np.array(model.theta)
+        for q, h in ((0, 1e-5), (1, 1e-6)):
+            e = np.zeros(2)
+            e[q] = h
+            fd = (dense(th + e, F, aux) - dense(th - e, F, aux)) / (2 * h)
+            assert abs(info["grad"][q] - fd) <= 1e-6 * (1 + abs(fd)), (q, info["grad"][q], fd)
+        d = np.random.default_rng(5).standard_normal(n)
+        fd = (dense(th, F + 1e-5 * d, aux) - dense(th, F - 1e-5 * d, aux)) / 2e-5
+        assert abs(info["grad_F"] @ d - fd) <= 1e-6 * (1 + abs(fd))
+        if aux is not None:
+            fd = (dense(th, F, aux + 1e-5) - dense(th, F, aux - 1e-5)) / 2e-5
+            assert abs(info["grad_xi"] - fd) <= 1e-6 * (1 + abs(fd))
+
+
+@pytest.mark.parametrize("lik,aux", [(L.LIK_BERNOULLI_LOGIT, None), (L.LIK_GAMMA, 2.0)])
+def test_lrac_gradient_matches_finite_differences(lik, aux):
+    """k < n, m < n - 1: the LRAC STE gradients (theta, offset along an
+    averaging direction, Gamma shape) within 5 standard errors over
+    independent probe sets of central differences of the dense exact NLL."""
+    model, y, F, b = _lrac_fd_setup(lik, aux)
+    gs, gF, gx = [], [], []
+    d = np.random.default_rng(9).standard_normal(model.n)
+    for seed in range(8):
+        o = L.Opts(cg_tol=1e-12, newton_tol=1e-15, num_probes=400, seed=seed,
+                   precond=L.PRECOND_LRAC, lrac_rank=8)
+        _, info = L.neg_log_marglik(model, y, F, lik, aux, b, o, want_grad=True)
+        gs.append(info["grad"])
+        gF.append(info["grad_F"] @ d)
+        if aux is not None:
+            gx.append(info["grad_xi"])
+
+    def dense(th, FF, aa):
+        A, D = V.factor(model.coords, model.nbr, model.kind, th)
+        Q = DR.dense_precision(V.sparse_B(A, model.nbr), D)
+        lp, lg, lw = _liks(lik, aa)
+        return DR.dense_nll(Q, y, FF, lp, lg, lw)[0]
+
+    th = np.array(model.theta)
+    checks = []
+    for q, h in ((0, 1e-5), (1, 1e-6)):
+        e = np.zeros(2)
+        e[q] = h
+        checks.append((np.array(gs)[:, q], (dense(th + e, F, aux) - dense(th - e, F, aux)) / (2 * h)))
+    checks.append((np.array(gF), (dense(th, F + 1e-5 * d, aux) - dense(th, F - 1e-5 * d, aux)) / 2e-5))
+    if aux is not None:
+        checks.append((np.array(gx), (dense(th, F, aux + 1e-5) - dense(th, F, aux - 1e-5)) / 2e-5))
+    for est, fd in checks:
+        se = est.std(ddof=1) / np.sqrt(len(est))
+        assert abs(est.mean() - fd) <= 5 * se + 1e-6 * (1 + abs(fd)), (est.mean(), fd, se)

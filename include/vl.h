@@ -238,7 +238,10 @@ vl_status vl_find_mode(vl_model* h, const double* y, const double* F, int lik,
 /* SLQ negative log-marginal likelihood at the stored mode (eq. VLA_loss).
  *   nll_host        host, 1 double
  *   grad_theta_host host, 2 doubles d/d(sigma2, rho) (NULL = skip; needs
- *                   want_deriv at build and the VADU preconditioner)
+ *                   want_deriv at build and the VADU or the LRAC
+ *                   preconditioner: the STE formulas of App. A.4.1 / A.4.2,
+ *                   LRAC with the derivative of the pivoted Cholesky factor
+ *                   at fixed pivots, k <= 128)
  * VADU: eq. (logdetsplit) with probes z = B^T (W + D^{-1})^{1/2} eps and
  * log det P = sum log(W + D^{-1}); LVA: z = B^T D^{-1/2} eps, log det P =
  * -sum log D; P_1: z = P_1^{1/2} eps, log det P = sum log (P_1)_ii; LRAC:
@@ -253,7 +256,7 @@ vl_status vl_neg_log_marglik(vl_model* h, const vl_opts* o, double* nll_host,
  * history 10, backtracking Armijo line search) with a sample average
  * approximation: every evaluation uses the probes of o->seed, so the
  * objective is deterministic.  Each evaluation runs vl_set_theta,
- * vl_find_mode from b = 0 and vl_neg_log_marglik with the gradient (VADU;
+ * vl_find_mode from b = 0 and vl_neg_log_marglik with the gradient (VADU or LRAC;
  * the model must have been built with want_deriv).
  *   theta_inout host, 2: start, then the estimate
  *   max_iter    L-BFGS iterations at most; grad_tol: stop when every

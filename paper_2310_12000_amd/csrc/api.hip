@@ -341,6 +341,7 @@ vl_status vl_set_theta(vl_model* h, const double* theta_host) {
     h->has_grad_F = false;
     h->has_grad_xi = false;
     h->lrac_ready = false;
+    h->lrac_dL_ready = false;
     const double t0 = vl::now_ms();
     VL_TRY(vl::compute_factor(*h));
     h->t_build_us = 1e3 * (vl::now_ms() - t0);

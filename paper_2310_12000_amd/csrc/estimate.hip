@@ -206,7 +206,8 @@ static Status estimate_common(vl_model* h, const double* y, const double* X, int
                               int* evals_out) {
   Model& M = *model_of(h);
   if (!M.deriv) return Status::make(VL_ERR_STATE, "the model was built without derivatives");
-  if (o.precond != VL_PREC_VADU) return Status::invalid("the gradient needs the VADU preconditioner");
+  if (o.precond != VL_PREC_VADU && o.precond != VL_PREC_LRAC)
+    return Status::invalid("the gradient needs the VADU or the LRAC preconditioner");
   if (max_iter < 0) return Status::invalid("max_iter must be >= 0");
   DevBuf<double> beta_d, F_d;
   if (p > 0) {

@@ -490,6 +490,86 @@ __global__ __launch_bounds__(256) void grad_probe_kernel(
   }
 }
 
+// LRAC form of the mu- and xi-terms (App. "Preconditioner LRAC"), per probe
+// column c, with u = (Sigma~ + W^{-1})^{-1} z, v = P^{-1} z:
+//   h_ic = dW_i u_ic v_ic / W_i^2,  r_ic = dW_i v_ic^2 / W_i^2,
+//   dlogdet/dmu_i = dW_i / W_i + c_i (dW_i lev_i - dW_i / W_i) - mean_c(h - c_i r),
+// dLdb_i = dlogdet/dmu_i / 2; with dWx (nullable) the xi sums over rows
+// h_xi = sum_i dWx_i u_i v_i / W_i^2, r_xi = sum_i dWx_i v_i^2 / W_i^2.
+__global__ __launch_bounds__(256) void lrac_mu_kernel(
+    ChunkGrid g, const double* __restrict__ U, const double* __restrict__ V,
+    const double* __restrict__ W, const double* __restrict__ dW, const double* __restrict__ lev,
+    const double* __restrict__ dWx, double* __restrict__ dLdb, double* __restrict__ part) {
+  double hx = 0.0, rx = 0.0;
+  const int t = g.t;
+  const int lpr = 1 << g.L.lpr_log;
+  const int lane = threadIdx.x & 63;
+  const int c = lane & (lpr - 1);
+  const int _w = threadIdx.x >> 6;
+  const int _sub = lane >> g.L.lpr_log;
+  const int64_t r0w = (int64_t)blockIdx.x * g.rpc;
+  int64_t r1w = r0w + g.rpc;
+  if (r1w > g.n) r1w = g.n;
+  const int64_t step = 4LL << g.L.rpw_log;
+  for (int64_t base = r0w + ((int64_t)_w << g.L.rpw_log); base < r1w; base += step) {
+    const int64_t i = base + _sub;
+    const bool valid = (i < r1w) && (c < t);
+    double hm = 0.0, rm = 0.0, Wi = 1.0, dWi = 0.0;
+    if (valid) {
+      const double ui = U[i * t + c], vi = V[i * t + c];
+      Wi = W[i];
+      dWi = dW[i];
+      const double wi2 = 1.0 / (Wi * Wi);
+      hm = dWi * wi2 * ui * vi;
+      rm = dWi * wi2 * vi * vi;
+      if (dWx) {
+        const double dx = dWx[i] * wi2;
+        hx += dx * ui * vi;
+        rx += dx * vi * vi;
+      }
+    }
+    double sh = hm, sr = rm;
+    for (int o = 1; o < lpr; o <<= 1) {
+      sh += __shfl_xor(sh, o);
+      sr += __shfl_xor(sr, o);
+    }
+    const double mh = sh / t, mr = sr / t;
+    double vr = valid ? (rm - mr) * (rm - mr) : 0.0;
+    double cv = valid ? (hm - mh) * (rm - mr) : 0.0;
+    for (int o = 1; o < lpr; o <<= 1) {
+      vr += __shfl_xor(vr, o);
+      cv += __shfl_xor(cv, o);
+    }
+    if (valid && c == 0) {
+      vr /= (t - 1);
+      cv /= (t - 1);
+      const double cc = (vr > 1e-10 * mr * mr) ? cv / vr : 0.0;
+      const double tw = dWi / Wi;
+      dLdb[i] = 0.5 * (tw + cc * (dWi * lev[i] - tw) - (mh - cc * mr));
+    }
+  }
+  if (dWx) {
+    block_colsum(g, hx, part);
+    block_colsum(g, rx, part + (int64_t)g.nchunk * t);
+  }
+}
+
+// Row sums (t = 1 grid) of the LRAC xi traces: sum dWx / W, sum dWx lev.
+__global__ __launch_bounds__(256) void lrac_xi_rows_kernel(ChunkGrid g,
+                                                           const double* __restrict__ dWx,
+                                                           const double* __restrict__ W,
+                                                           const double* __restrict__ lev,
+                                                           double* __restrict__ part) {
+  double s0 = 0.0, s1 = 0.0;
+  CHUNK_LOOP_BEGIN(g)
+  (void)c;
+  s0 += dWx[i] / W[i];
+  s1 += dWx[i] * lev[i];
+  CHUNK_LOOP_END
+  block_colsum(g, s0, part);
+  block_colsum(g, s1, part + g.nchunk);
+}
+
 // d W / d xi per row at the mode (input of grad_probe_kernel).
 __global__ void xi_dw_kernel(int64_t n, int lik, double aux, const double* __restrict__ y,
                              const double* __restrict__ F, const double* __restrict__ b,
@@ -750,6 +830,124 @@ static Status grad_theta(Model& M, const vl_opts& o, const double* sdiag, double
   return Status::ok();
 }
 
+// Gradients with P_LRAC (App. "Gradients of Vecchia-Laplace approximations"
+// with the STE formulas of App. "Preconditioner LRAC"): theta, the offset F
+// and, for a likelihood with one, xi.  The probe solves u = (Sigma~ +
+// W^{-1})^{-1} z and v = P^{-1} z come from the SLQ block of the same call;
+// the mode's response w = A^{-1} dL/db = W^{-1} (Sigma~ + W^{-1})^{-1} Sigma~
+// dL/db (eq. pcls2).
+static Status grad_lrac(Model& M, const vl_opts& o, double* grad, GradInfo* info) {
+  const int t = M.cg.t;
+  const int64_t n = M.n;
+  if (t > 64) return Status::invalid("the gradient supports at most 64 probes");
+  if (t < 2) return Status::invalid("the gradient needs at least 2 probes");
+  VL_TRY(lrac_build_deriv(M));
+  VL_TRY(M.dWv.reserve(n));
+  VL_TRY(lik_rows(M, M.mode.p, nullptr, nullptr, nullptr, nullptr, nullptr, M.dWv.p));
+  const bool xi = lik_has_aux(M.lik);
+  DevBuf<double> lev, dWx, w, SU, SV, tmp;
+  VL_TRY(lev.alloc(n));
+  VL_TRY(lrac_leverage(M, lev.p));
+  if (xi) {
+    VL_TRY(dWx.alloc(n));
+    hipLaunchKernelGGL(xi_dw_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, M.stream,
+                       n, M.lik, M.aux, M.y.p, M.F.p, M.mode.p, dWx.p);
+    VL_TRY(check_launch("xi dW"));
+  }
+  VL_TRY(M.vec_c.reserve(n));  // dL/db
+  ChunkGrid g = ChunkGrid::of(n, t);
+  VL_TRY(M.red_part.reserve(static_cast<size_t>(g.nchunk) * t * 2 + 64));
+  hipLaunchKernelGGL(lrac_mu_kernel, dim3(g.nchunk, 1), dim3(256), 0, M.stream, g, M.cg.U.p,
+                     M.cg.Z0.p, M.W.p, M.dWv.p, lev.p, xi ? dWx.p : nullptr, M.vec_c.p,
+                     M.red_part.p);
+  VL_TRY(check_launch("lrac mu"));
+  std::vector<double> hx(t), rx(t);
+  if (xi) {
+    VL_TRY(M.red_out.reserve(2 * static_cast<size_t>(t) + 64));
+    for (int q = 0; q < 2; ++q)
+      VL_TRY(reduce_chunks(M.stream, M.red_part.p + (int64_t)q * g.nchunk * t, g.nchunk, t,
+                           M.red_out.p + q * t));
+    VL_HIP(hipMemcpyAsync(hx.data(), M.red_out.p, sizeof(double) * t, hipMemcpyDeviceToHost,
+                          M.stream));
+    VL_HIP(hipMemcpyAsync(rx.data(), M.red_out.p + t, sizeof(double) * t,
+                          hipMemcpyDeviceToHost, M.stream));
+  }
+  // theta terms from Sigma~ u, Sigma~ v (before the implicit solve reuses
+  // the CG scratch)
+  const size_t nt = static_cast<size_t>(n) * t;
+  VL_TRY(SU.alloc(nt));
+  VL_TRY(SV.alloc(nt));
+  VL_TRY(tmp.alloc(nt));
+  VL_TRY(lrac_sigma(M, M.cg.U.p, SU.p, tmp.p, t));
+  VL_TRY(lrac_sigma(M, M.cg.Z0.p, SV.p, tmp.p, t));
+  std::vector<double> h(2 * t), r(2 * t);
+  double trP[2];
+  VL_TRY(lrac_theta_terms(M, SU.p, SV.p, M.cg.Z0.p, M.W.p, t, h.data(), r.data(), trP));
+  SU.release();
+  SV.release();
+  tmp.release();
+  // w = A^{-1} dL/db by eq. (pcls2)
+  VL_TRY(w.alloc(n));
+  std::vector<int> rbuf;
+  VL_TRY(lrac_newton_solve(M, o, M.vec_c.p, w.p, replay_slice(o, t, 1, rbuf)));
+  info->grad_cg_iters = M.cg1.host_iters[0];
+  VL_TRY(M.grad_F.reserve(n));
+  hipLaunchKernelGGL(grad_offset_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     M.stream, n, M.g.p, M.vec_c.p, M.W.p, w.p, M.grad_F.p);
+  VL_TRY(check_launch("grad offset"));
+  M.has_grad_F = true;
+  // b*^T dSigma~^{-1} b* and -w^T dSigma~^{-1} b* (the VADU row sums serve)
+  ChunkGrid g1 = ChunkGrid::of(n, 1);
+  VL_TRY(M.red_part.reserve(static_cast<size_t>(g1.nchunk) * 8 + 64));
+  hipLaunchKernelGGL(grad_rows_kernel, dim3(g1.nchunk, 1), dim3(256), 0, M.stream, g1, M.m,
+                     M.nbr.p, M.bval.p, M.dbval_rho.p, M.mode.p, w.p, M.dval.p,
+                     M.dd_sigma2.p, M.dd_rho.p, M.W.p, M.red_part.p);
+  VL_TRY(check_launch("grad rows"));
+  double rows[8];
+  VL_TRY(host_sums(M, M.red_part.p, g1.nchunk, 8, rows));
+  for (int k = 0; k < 2; ++k) {
+    std::vector<double> hk(h.begin() + k * t, h.begin() + (k + 1) * t);
+    std::vector<double> rk(r.begin() + k * t, r.begin() + (k + 1) * t);
+    const double c = cv_weight(hk, rk);
+    double mean = 0.0;
+    for (int q = 0; q < t; ++q) mean += hk[q] - c * rk[q];
+    mean /= t;
+    const double quad = rows[4 * k + 0], impl = rows[4 * k + 1];
+    const double dlogdet = c * trP[k] + mean;
+    grad[k] = 0.5 * quad + 0.5 * dlogdet + impl;
+    info->c[k] = c;
+    info->dlogdet[k] = dlogdet;
+    info->quad[k] = quad;
+    info->implicit[k] = impl;
+  }
+  M.has_grad_xi = false;
+  if (xi) {
+    ChunkGrid gx = ChunkGrid::of(n, 1);
+    VL_TRY(M.red_part.reserve(static_cast<size_t>(gx.nchunk) * 3 + 64));
+    hipLaunchKernelGGL(grad_xi_rows_kernel, dim3(gx.nchunk, 1), dim3(256), 0, M.stream, gx,
+                       M.lik, M.aux, M.y.p, M.F.p, M.mode.p, M.W.p, M.dval.p, w.p, M.red_part.p);
+    VL_TRY(check_launch("grad xi rows"));
+    double xr[3];
+    VL_TRY(host_sums(M, M.red_part.p, gx.nchunk, 3, xr));
+    hipLaunchKernelGGL(lrac_xi_rows_kernel, dim3(gx.nchunk, 1), dim3(256), 0, M.stream, gx, dWx.p,
+                       M.W.p, lev.p, M.red_part.p);
+    VL_TRY(check_launch("lrac xi rows"));
+    double lr[2];
+    VL_TRY(host_sums(M, M.red_part.p, gx.nchunk, 2, lr));
+    const double c = cv_weight(hx, rx);
+    double mean = 0.0;
+    for (int q = 0; q < t; ++q) mean += hx[q] - c * rx[q];
+    mean /= t;
+    double dlogp = xr[0];
+    if (M.lik == VL_LIK_GAMMA)
+      dlogp += static_cast<double>(n) * (std::log(M.aux) + 1.0 - digamma_host(M.aux));
+    const double dlogdet = lr[0] + c * (lr[1] - lr[0]) - mean;
+    M.grad_xi = -dlogp + 0.5 * dlogdet + xr[2];
+    M.has_grad_xi = true;
+  }
+  return Status::ok();
+}
+
 // -------------------------------------------------------------- NLL (SLQ)
 Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, NllInfo* info) {
   if (!M.has_mode) return Status::make(VL_ERR_STATE, "no mode: call vl_find_mode first");
@@ -763,15 +961,15 @@ Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, Nl
   VL_TRY(M.vec_b.reserve(n));  // (W + D^{-1})^{-1}
   VL_TRY(lik_rows(M, M.mode.p, nullptr, M.W.p, nullptr, M.vec_b.p, M.vec_a.p, nullptr));
   const bool lrac = o.precond == VL_PREC_LRAC;
-  if (o.precond != VL_PREC_VADU && grad)
-    return Status::invalid("the gradient needs the VADU preconditioner");
+  if (o.precond != VL_PREC_VADU && o.precond != VL_PREC_LRAC && grad)
+    return Status::invalid("the gradient needs the VADU or the LRAC preconditioner");
   double logdet_lrac = 0.0;
   if (lrac) {
     // eq. (logdetsplit2): log det(Sigma~ W + I) = sum log W + log det P_LRAC
     // + log det(P^{-1} (Sigma~ + W^{-1})), probes z = L eps_k + W^{-1/2} eps_n
     VL_TRY(lrac_build(M, o.lrac_rank));
     std::vector<int> rbuf;
-    VL_TRY(lrac_slq(M, o, &logdet_lrac, replay_slice(o, 0, t, rbuf)));
+    VL_TRY(lrac_slq(M, o, &logdet_lrac, replay_slice(o, 0, t, rbuf), grad != nullptr));
   } else {
     VL_TRY(M.rhs_blk.reserve(static_cast<size_t>(n) * t));
     // probes z_i = P^{1/2} eps_i with Cov(z_i) = P:
@@ -855,7 +1053,11 @@ Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, Nl
   }
   if (grad) {
     GradInfo gi;
-    VL_TRY(grad_theta(M, o, M.vec_b.p, grad, &gi));
+    if (lrac) {
+      VL_TRY(grad_lrac(M, o, grad, &gi));
+    } else {
+      VL_TRY(grad_theta(M, o, M.vec_b.p, grad, &gi));
+    }
     if (info) info->grad = gi;
   }
   if (cg_max >= o.max_cg)

@@ -16,6 +16,9 @@
 // owns 16 x 16 output tiles and steps through the contraction 4 at a time.
 // Operand layout of one step, lane l = 16 q + i (q = l / 16, i = l mod 16):
 // A[i][q] and B[q][i] in, D[q + 4 r][i] (r = 0..3) out (measured on gfx950).
+#include <algorithm>
+#include <vector>
+
 #include "vl_internal.h"
 #include "vl_laplace.h"
 #include "vl_ops.h"
@@ -297,6 +300,127 @@ static unsigned blocks_for(int64_t count) {
   return static_cast<unsigned>((count + 255) / 256);
 }
 
+// ------------------------------------- derivative of the pivoted Cholesky
+// Forward-mode derivative of the pivoted Cholesky steps with the pivots held
+// fixed (q = 0: sigma2, q = 1: rho): with s = sqrt(d_p), column j =
+// (Sigma[:, p] - L L_p^T) / s and d_p's derivative dd_p,
+//   dL[:, j] = (dSigma[:, p] - dL L_p^T - L dL_p^T - L[:, j] dd_p / (2 s)) / s,
+//   dd -= 2 L[:, j] o dL[:, j].
+// snap[2 j + q] = dd_q[piv[j]] before column j (read by every row).
+__global__ void pc_deriv_snap_kernel(int j, const int* __restrict__ piv,
+                                     const double* __restrict__ dd0,
+                                     const double* __restrict__ dd1, double* __restrict__ snap) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int p = piv[j];
+    snap[2 * j] = dd0[p];
+    snap[2 * j + 1] = dd1[p];
+  }
+}
+
+__global__ __launch_bounds__(256) void pc_deriv_column_kernel(
+    int64_t n, int K, int j, const double* __restrict__ coords, int kind, double sigma2,
+    double rho, const int* __restrict__ piv, const double* __restrict__ pval,
+    const double* __restrict__ L, double* __restrict__ dL0, double* __restrict__ dL1,
+    double* __restrict__ dd0, double* __restrict__ dd1, const double* __restrict__ snap) {
+  const int p = piv[j];
+  const double sq = sqrt(pval[j]);
+  const double ds0 = snap[2 * j] / (2.0 * sq), ds1 = snap[2 * j + 1] / (2.0 * sq);
+  const double px = coords[2 * (int64_t)p], py = coords[2 * (int64_t)p + 1];
+  const double* Lp = L + (int64_t)p * K;
+  const double* dLp0 = dL0 + (int64_t)p * K;
+  const double* dLp1 = dL1 + (int64_t)p * K;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double d2 = sqdist(coords[2 * i], coords[2 * i + 1], px, py);
+    double n0 = cov_eval(kind, d2, 1.0, rho);  // d c / d sigma2 = c / sigma2
+    double n1 = cov_drho(kind, d2, sigma2, rho);
+    const double* Li = L + i * K;
+    double* dLi0 = dL0 + i * K;
+    double* dLi1 = dL1 + i * K;
+    double a0 = 0.0, b0 = 0.0, a1 = 0.0, b1 = 0.0;
+    for (int l = 0; l < j; ++l) {
+      a0 += dLi0[l] * Lp[l];
+      b0 += Li[l] * dLp0[l];
+      a1 += dLi1[l] * Lp[l];
+      b1 += Li[l] * dLp1[l];
+    }
+    const double lij = Li[j];
+    const double v0 = ((n0 - a0 - b0) - lij * ds0) / sq;
+    const double v1 = ((n1 - a1 - b1) - lij * ds1) / sq;
+    dLi0[j] = v0;
+    dLi1[j] = v1;
+    dd0[i] -= 2.0 * lij * v0;
+    dd1[i] -= 2.0 * lij * v1;
+  }
+}
+
+// dd_sigma2 = 1 (c(0) = sigma2), dd_rho = 0, dL = 0
+__global__ void pc_deriv_init_kernel(int64_t n, int K, double* __restrict__ dL0,
+                                     double* __restrict__ dL1, double* __restrict__ dd0,
+                                     double* __restrict__ dd1) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g < n) {
+    dd0[g] = 1.0;
+    dd1[g] = 0.0;
+  }
+  for (int64_t e = g; e < n * K; e += (int64_t)gridDim.x * blockDim.x) {
+    dL0[e] = 0.0;
+    dL1[e] = 0.0;
+  }
+}
+
+// lev[i] = L_i M^{-1} L_i^T = |C^{-1} L_i^T|^2 (C the Cholesky factor of M)
+__global__ void lrac_leverage_kernel(int64_t n, int K, const double* __restrict__ L,
+                                     const double* __restrict__ C, double* __restrict__ lev) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double y[128];
+  const double* Li = L + i * K;
+  double acc = 0.0;
+  for (int a = 0; a < K; ++a) {
+    double v = Li[a];
+    for (int l = 0; l < a; ++l) v -= C[a * K + l] * y[l];
+    v /= C[a * K + a];
+    y[a] = v;
+    acc += v * v;
+  }
+  lev[i] = acc;
+}
+
+// Per column c of the n x t blocks X, Y: part_k[chunk, c] = sum over the
+// chunk's rows of X^T (d Sigma~^{-1} / d theta_k) Y restricted to the row,
+// i.e. dBx' D^{-1} By + Bx' D^{-1} dBy - Bx' D^{-2} dD_k By (dB_sigma2 = 0).
+__global__ __launch_bounds__(256) void dprec_form_kernel(
+    ChunkGrid g, int m, const int* __restrict__ nbr, const double* __restrict__ bval,
+    const double* __restrict__ dbval, const double* __restrict__ X,
+    const double* __restrict__ Y, const double* __restrict__ D,
+    const double* __restrict__ dd_s2, const double* __restrict__ dd_rho,
+    double* __restrict__ part) {
+  double s0 = 0.0, s1 = 0.0;
+  const int t = g.t;
+  CHUNK_LOOP_BEGIN(g)
+  const int* nb = nbr + i * m;
+  const double* bv = bval + i * m;
+  const double* dbv = dbval + i * m;
+  double Bx = X[i * t + c], By = Y[i * t + c], dBx = 0.0, dBy = 0.0;
+  for (int k = 0; k < m; ++k) {
+    const int jn = nb[k];
+    if (jn < 0) break;
+    const double xj = X[(int64_t)jn * t + c], yj = Y[(int64_t)jn * t + c];
+    Bx += bv[k] * xj;
+    By += bv[k] * yj;
+    dBx += dbv[k] * xj;
+    dBy += dbv[k] * yj;
+  }
+  const double di = 1.0 / D[i];
+  const double di2 = di * di;
+  s0 += -Bx * di2 * dd_s2[i] * By;
+  s1 += dBx * di * By + Bx * di * dBy - Bx * di2 * dd_rho[i] * By;
+  CHUNK_LOOP_END
+  block_colsum(g, s0, part);
+  block_colsum(g, s1, part + (int64_t)g.nchunk * t);
+}
+
 // ---------------------------------------------------------------- drivers
 static int padded_rank(int k) { return (k + 15) / 16 * 16; }
 
@@ -329,12 +453,22 @@ Status lrac_build(Model& M, int k) {
   M.lrac_k = k;
   M.lrac_K = K;
   M.lrac_ready = true;
+  M.lrac_dL_ready = false;
   return Status::ok();
 }
+
+static Status gram_with(Model& M, const double* Lm, const double* w, const double* X, int ldx,
+                        int t, int ldp, double* out);
 
 // Parts of the K x ldp gram products: one block per 256 CUs' worth of rows.
 static Status gram(Model& M, const double* w, const double* X, int ldx, int t, int ldp,
                    double* out) {
+  return gram_with(M, M.lrac_L.p, w, X, ldx, t, ldp, out);
+}
+
+// The same with another n x K left factor (the derivative of L).
+static Status gram_with(Model& M, const double* Lm, const double* w, const double* X, int ldx,
+                        int t, int ldp, double* out) {
   const int K = M.lrac_K;
   const int64_t n = M.n;
   int nblk = 512;
@@ -343,7 +477,7 @@ static Status gram(Model& M, const double* w, const double* X, int ldx, int t, i
   nblk = static_cast<int>((n + rpb - 1) / rpb);
   const int64_t size = static_cast<int64_t>(K) * ldp;
   VL_TRY(M.lrac_gpart.reserve(static_cast<size_t>(nblk) * size));
-  hipLaunchKernelGGL(gram_kernel, dim3(nblk), dim3(256), 0, M.stream, n, K, rpb, M.lrac_L.p, w, X,
+  hipLaunchKernelGGL(gram_kernel, dim3(nblk), dim3(256), 0, M.stream, n, K, rpb, Lm, w, X,
                      ldx, t, ldp, M.lrac_gpart.p);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(blocks_for(size)), dim3(256), 0, M.stream, nblk,
                      size, M.lrac_gpart.p, out);
@@ -416,9 +550,121 @@ Status lrac_newton_solve(Model& M, const vl_opts& o, const double* rhs, double* 
   return check_launch("lrac newton");
 }
 
+Status lrac_build_deriv(Model& M) {
+  if (!M.lrac_ready) return Status::make(VL_ERR_STATE, "no LRAC factor");
+  if (M.lrac_dL_ready) return Status::ok();
+  const int64_t n = M.n;
+  const int K = M.lrac_K, k = M.lrac_k;
+  VL_TRY(M.lrac_dL.reserve(static_cast<size_t>(2) * n * K));
+  VL_TRY(M.lrac_dd.reserve(static_cast<size_t>(2) * n));
+  VL_TRY(M.lrac_snap.reserve(static_cast<size_t>(2) * k + 2));
+  double* dL0 = M.lrac_dL.p;
+  double* dL1 = M.lrac_dL.p + static_cast<size_t>(n) * K;
+  double* dd0 = M.lrac_dd.p;
+  double* dd1 = M.lrac_dd.p + n;
+  hipLaunchKernelGGL(pc_deriv_init_kernel, dim3(std::min<int64_t>(blocks_for(n * K), 8192)),
+                     dim3(256), 0, M.stream, n, K, dL0, dL1, dd0, dd1);
+  for (int j = 0; j < k; ++j) {
+    hipLaunchKernelGGL(pc_deriv_snap_kernel, dim3(1), dim3(64), 0, M.stream, j, M.lrac_piv.p,
+                       dd0, dd1, M.lrac_snap.p);
+    hipLaunchKernelGGL(pc_deriv_column_kernel, dim3(512), dim3(256), 0, M.stream, n, K, j,
+                       M.coords, M.cov, M.sigma2, M.rho, M.lrac_piv.p, M.lrac_pval.p,
+                       M.lrac_L.p, dL0, dL1, dd0, dd1, M.lrac_snap.p);
+  }
+  VL_TRY(check_launch("pivoted cholesky derivative"));
+  M.lrac_dL_ready = true;
+  return Status::ok();
+}
+
+Status lrac_leverage(Model& M, double* lev) {
+  if (M.lrac_K > 128) return Status::invalid("the LRAC gradient supports k <= 128");
+  hipLaunchKernelGGL(lrac_leverage_kernel, dim3(blocks_for(M.n)), dim3(256), 0, M.stream, M.n,
+                     M.lrac_K, M.lrac_L.p, M.lrac_M.p, lev);
+  return check_launch("lrac leverage");
+}
+
+Status lrac_sigma(Model& M, const double* X, double* Y, double* Tmp, int t) {
+  return sigma_apply(M, X, Y, Tmp, t, nullptr);
+}
+
+Status lrac_theta_terms(Model& M, const double* SU, const double* SV, const double* V,
+                        const double* W, int t, double* h, double* r, double* trP) {
+  const int64_t n = M.n;
+  const int K = M.lrac_K;
+  // h_k = -(Sigma~ u)^T (d Sigma~^{-1} / d theta_k) (Sigma~ v), per column
+  ChunkGrid g = ChunkGrid::of(n, t);
+  VL_TRY(M.red_part.reserve(static_cast<size_t>(g.nchunk) * t * 2 + 64));
+  hipLaunchKernelGGL(dprec_form_kernel, dim3(g.nchunk, g.L.slices), dim3(256), 0, M.stream, g,
+                     M.m, M.nbr.p, M.bval.p, M.dbval_rho.p, SU, SV, M.dval.p, M.dd_sigma2.p,
+                     M.dd_rho.p, M.red_part.p);
+  VL_TRY(check_launch("lrac h"));
+  VL_TRY(M.red_out.reserve(2 * static_cast<size_t>(t) + 64));
+  for (int q = 0; q < 2; ++q)
+    VL_TRY(reduce_chunks(M.stream, M.red_part.p + (int64_t)q * g.nchunk * t, g.nchunk, t,
+                         M.red_out.p + q * t));
+  std::vector<double> hv(2 * t);
+  VL_HIP(hipMemcpyAsync(hv.data(), M.red_out.p, sizeof(double) * 2 * t, hipMemcpyDeviceToHost,
+                        M.stream));
+  // r_k = 2 (L^T v) . (dL_k^T v) per column; tr(M^{-1} (dL^T W L + L^T W dL)) =
+  // 2 tr(M^{-1} L^T W dL)
+  const int ldp = (t + 15) / 16 * 16;
+  DevBuf<double> lv, dlv, gw;
+  VL_TRY(lv.alloc(static_cast<size_t>(K) * ldp));
+  VL_TRY(dlv.alloc(static_cast<size_t>(2) * K * ldp));
+  VL_TRY(gw.alloc(static_cast<size_t>(2) * K * K));
+  VL_TRY(gram(M, nullptr, V, t, t, ldp, lv.p));
+  for (int q = 0; q < 2; ++q) {
+    const double* dLq = M.lrac_dL.p + static_cast<size_t>(q) * n * K;
+    VL_TRY(gram_with(M, dLq, nullptr, V, t, t, ldp, dlv.p + static_cast<size_t>(q) * K * ldp));
+    VL_TRY(gram(M, W, dLq, K, K, K, gw.p + static_cast<size_t>(q) * K * K));  // L^T W dL_q
+  }
+  std::vector<double> lvh(static_cast<size_t>(K) * ldp), dlvh(static_cast<size_t>(2) * K * ldp),
+      gwh(static_cast<size_t>(2) * K * K), Ch(static_cast<size_t>(K) * K);
+  VL_HIP(hipMemcpyAsync(lvh.data(), lv.p, sizeof(double) * lvh.size(), hipMemcpyDeviceToHost,
+                        M.stream));
+  VL_HIP(hipMemcpyAsync(dlvh.data(), dlv.p, sizeof(double) * dlvh.size(), hipMemcpyDeviceToHost,
+                        M.stream));
+  VL_HIP(hipMemcpyAsync(gwh.data(), gw.p, sizeof(double) * gwh.size(), hipMemcpyDeviceToHost,
+                        M.stream));
+  VL_HIP(hipMemcpyAsync(Ch.data(), M.lrac_M.p, sizeof(double) * Ch.size(), hipMemcpyDeviceToHost,
+                        M.stream));
+  VL_TRY(sync_stream(M.stream));
+  for (int q = 0; q < 2; ++q) {
+    for (int c = 0; c < t; ++c) {
+      h[q * t + c] = -hv[q * t + c];
+      double acc = 0.0;
+      for (int a = 0; a < K; ++a)
+        acc += lvh[static_cast<size_t>(a) * ldp + c] *
+               dlvh[static_cast<size_t>(q) * K * ldp + static_cast<size_t>(a) * ldp + c];
+      r[q * t + c] = 2.0 * acc;
+    }
+    // tr(M^{-1} G), G = L^T W dL_q: column b of M^{-1} G by two triangular
+    // solves with the Cholesky factor C (M = C C^T), summing the diagonal
+    double tr = 0.0;
+    std::vector<double> y(K);
+    const double* G = gwh.data() + static_cast<size_t>(q) * K * K;
+    for (int b = 0; b < K; ++b) {
+      for (int a = 0; a < K; ++a) {
+        double v = G[static_cast<size_t>(a) * K + b];
+        for (int l = 0; l < a; ++l) v -= Ch[static_cast<size_t>(a) * K + l] * y[l];
+        y[a] = v / Ch[static_cast<size_t>(a) * K + a];
+      }
+      for (int a = K - 1; a >= 0; --a) {
+        double v = y[a];
+        for (int l = a + 1; l < K; ++l) v -= Ch[static_cast<size_t>(l) * K + a] * y[l];
+        y[a] = v / Ch[static_cast<size_t>(a) * K + a];
+      }
+      tr += y[b];
+    }
+    trP[q] = 2.0 * tr;
+  }
+  return Status::ok();
+}
+
 // SLQ with P_LRAC: probes z = L eps_k + W^{-1/2} eps_n, CG on Sigma~ + W^{-1};
 // returns log det M (= sum log W + log det P) on the host.
-Status lrac_slq(Model& M, const vl_opts& o, double* logdet_fixed, const int* forced) {
+Status lrac_slq(Model& M, const vl_opts& o, double* logdet_fixed, const int* forced,
+                bool keep_z0) {
   const int64_t n = M.n;
   const int t = o.num_probes;
   const int K = M.lrac_K;
@@ -437,7 +683,7 @@ Status lrac_slq(Model& M, const vl_opts& o, double* logdet_fixed, const int* for
   VL_HIP(hipMemcpyAsync(&ld, M.lrac_M.p + K * K, sizeof(double), hipMemcpyDeviceToHost,
                         M.stream));
   CgOps ops = lrac_ops(M.W.p);
-  VL_TRY(cg_solve(M, M.cg, ops, t, M.rhs_blk.p, o.cg_tol, o.max_cg, false, forced));
+  VL_TRY(cg_solve(M, M.cg, ops, t, M.rhs_blk.p, o.cg_tol, o.max_cg, keep_z0, forced));
   *logdet_fixed = ld;
   return Status::ok();
 }

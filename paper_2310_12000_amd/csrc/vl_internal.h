@@ -332,6 +332,10 @@ struct Model {
   bool lrac_ready = false;
   int lrac_k = 0, lrac_K = 0;
   DevBuf<double> lrac_L, lrac_pval, lrac_part, lrac_gpart, lrac_M, lrac_S;
+  // d L / d theta (2 x n x lrac_K, sigma2 then rho), the residual diagonals'
+  // derivatives (2 x n) and the pivots' values of them per column
+  bool lrac_dL_ready = false;
+  DevBuf<double> lrac_dL, lrac_dd, lrac_snap;
   DevBuf<int> lrac_piv;
   DevBuf<double> rhs_blk;  // n x t right-hand sides of block solves
   DevBuf<int> counter;     // dynamic work counters of sync-free kernels

@@ -28,7 +28,17 @@ Status lrac_build(Model& M, int k);
 Status lrac_factor(Model& M, const double* W);
 Status lrac_newton_solve(Model& M, const vl_opts& o, const double* rhs, double* b_out,
                          const int* forced);
-Status lrac_slq(Model& M, const vl_opts& o, double* logdet_fixed, const int* forced);
+Status lrac_slq(Model& M, const vl_opts& o, double* logdet_fixed, const int* forced,
+                bool keep_z0 = false);
+// For the gradients with P_LRAC: d L_k / d theta (pivots fixed), the
+// leverages L_i M^{-1} L_i^T, Y = Sigma~ X, and per probe column the theta
+// terms h_k = -(Sigma~ u)^T dSigma~^{-1} (Sigma~ v), r_k = 2 (L^T v).(dL_k^T v)
+// with the known means trP_k = 2 tr(M^{-1} L^T W dL_k) (host arrays 2t, 2t, 2).
+Status lrac_build_deriv(Model& M);
+Status lrac_leverage(Model& M, double* lev);
+Status lrac_sigma(Model& M, const double* X, double* Y, double* Tmp, int t);
+Status lrac_theta_terms(Model& M, const double* SU, const double* SV, const double* V,
+                        const double* W, int t, double* h, double* r, double* trP);
 
 Status lik_rows(Model& M, const double* b, double* g, double* W, double* rhs, double* s,
                 double* sq, double* dW);

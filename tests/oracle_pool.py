@@ -5,6 +5,7 @@ exactly as the single-process call would compute it; this module only splits
 the rows and joins the pieces."""
 import multiprocessing as mp
 import os
+import sys
 from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
@@ -35,9 +36,12 @@ def neighbours_and_factor(coords, m, kind, theta, workers=None, pieces=64):
     jobs = [(coords, m, kind, tuple(theta), int(a), int(b))
             for a, b in zip(cuts[:-1], cuts[1:]) if b > a]
     with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-        for r0, nb, a, d in ex.map(_rows_job, jobs):
+        for done, (r0, nb, a, d) in enumerate(ex.map(_rows_job, jobs), 1):
             r1 = r0 + nb.shape[0]
             nbr[r0:r1], A[r0:r1], D[r0:r1] = nb, a, d
+            if done % 8 == 0:
+                print(f"oracle factor rows: {done}/{len(jobs)} pieces", file=sys.stderr,
+                      flush=True)
     return nbr, A, D
 
 
@@ -96,7 +100,9 @@ def factor_cholesky(coords, nbr, kind, theta, workers=None, pieces=64):
     jobs = [(coords, nbr, kind, tuple(theta), int(a), int(b))
             for a, b in zip(cuts[:-1], cuts[1:]) if b > a]
     with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-        for r0, a, d in ex.map(_cholesky_rows_job, jobs):
+        for done, (r0, a, d) in enumerate(ex.map(_cholesky_rows_job, jobs), 1):
+            if done % 8 == 0:
+                print(f"oracle second factor: {done}/{len(jobs)} pieces", file=sys.stderr, flush=True)
             A[r0:r0 + a.shape[0]] = a
             D[r0:r0 + a.shape[0]] = d
     return A, D
@@ -116,12 +122,13 @@ def slq_columns(model, y, F, lik, b, opts, t, replay=None, workers=None):
     """Per-probe SLQ quadratures, weights and CG counts of probe columns
     0..t-1, each slice of columns run by the oracle in its own process."""
     workers = workers or max(1, min(16, os.cpu_count() or 1))
-    cuts = np.linspace(0, t, min(t, workers) + 1).astype(np.int64)
+    cuts = np.linspace(0, t, min(t, 4 * workers) + 1).astype(np.int64)
     quad, r0z0, iters = np.empty(t), np.empty(t), np.empty(t, dtype=np.int64)
     jobs = [(model, y, F, lik, b, opts, int(a), int(c), replay)
             for a, c in zip(cuts[:-1], cuts[1:]) if c > a]
     with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-        for c0, q, r, it in ex.map(_slq_job, jobs):
+        for done, (c0, q, r, it) in enumerate(ex.map(_slq_job, jobs), 1):
+            print(f"oracle probe columns: {done}/{len(jobs)} pieces", file=sys.stderr, flush=True)
             k = q.shape[0]
             quad[c0:c0 + k], r0z0[c0:c0 + k], iters[c0:c0 + k] = q, r, it
     return quad, r0z0, iters
@@ -142,12 +149,13 @@ def pred_columns(model, coords_p, Fp, b, W, opts, s, replay=None, workers=None):
     0..s-1 of (A_p u_i)^2 (Alg. simAlgo), the columns split over processes;
     returns (var, per-column CG counts)."""
     workers = workers or max(1, min(16, os.cpu_count() or 1))
-    cuts = np.linspace(0, s, min(s, workers) + 1).astype(np.int64)
+    cuts = np.linspace(0, s, min(s, 4 * workers) + 1).astype(np.int64)
     acc, Dp, iters = None, None, np.empty(s, dtype=np.int64)
     jobs = [(model, coords_p, Fp, b, W, opts, int(a), int(c), replay)
             for a, c in zip(cuts[:-1], cuts[1:]) if c > a]
     with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-        for c0, a, dp, it in ex.map(_pred_job, jobs):
+        for done, (c0, a, dp, it) in enumerate(ex.map(_pred_job, jobs), 1):
+            print(f"oracle sample columns: {done}/{len(jobs)} pieces", file=sys.stderr, flush=True)
             acc = a if acc is None else acc + a
             Dp = dp
             iters[c0:c0 + it.shape[0]] = it

@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--forms", default="all",
+                    help="comma-separated forms to run after the timed steps (default all)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision, batching and serving measurements")
     ap.add_argument("--batch-problems", type=int, default=32)
@@ -204,6 +206,8 @@ def main():
                           lambda: form_pred_variance_methods(P, torch, synth, args)),
                          ("batch", lambda: form_batch(P, torch, synth, args)),
                          ("serving", lambda: form_serving(P, torch, synth, args))):
+            if args.forms != "all" and name not in args.forms.split(","):
+                continue
             print(f"form: {name}", file=sys.stderr, flush=True)
             out["forms"][name] = fn()
     if not args.no_cpu_baseline:
@@ -283,7 +287,7 @@ def form_preconditioners(P, torch, w, coords, y, F, theta, opts, args):
                      ("P1", P.VL_PREC_DIAG)):
         o = copy.copy(opts)
         o.precond = pc
-        g = P.VecchiaLaplace(coords, w["m"], w["kind"], theta)
+        g = P.VecchiaLaplace(coords, w["m"], w["kind"], theta, want_deriv=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g.set_theta(theta)
@@ -292,11 +296,17 @@ def form_preconditioners(P, torch, w, coords, y, F, theta, opts, args):
         nll, _, nst = g.neg_log_marglik(o, allow_no_conv=True)
         t2 = time.perf_counter()
         terms = g.export("slq_r0z0").cpu().numpy() * g.export("slq_quad").cpu().numpy()
-        g.close()
         res[name] = {"mode_ms": 1e3 * (t1 - t0), "nll_ms": 1e3 * (t2 - t1), "nll": nll,
                      "newton_cg_total": st.cg_iters_total, "slq_cg_max": nst.cg_iters_max,
                      "hit_cap": bool(nst.cg_iters_max >= o.max_cg or st.hit_cap),
                      "logdet_probe_se": float(np.std(terms, ddof=1) / np.sqrt(len(terms)))}
+        if pc in (P.VL_PREC_VADU, P.VL_PREC_LRAC):  # the STE formulas the paper gives
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            _, grad, _ = g.neg_log_marglik(o, want_grad=True, allow_no_conv=True)
+            res[name]["nll_grad_ms"] = 1e3 * (time.perf_counter() - t3)
+            res[name]["grad"] = grad
+        g.close()
         log(args, f"preconditioner {name}: {res[name]}")
     return res
 

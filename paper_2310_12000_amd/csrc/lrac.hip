@@ -9,7 +9,8 @@
 //   M     I_K + L^T W L (K x K), its Cholesky factor C and log det M; the
 //         padded columns give identity rows, so log det M is that of the
 //         k x k matrix.  log det P = log det M - sum log W (determinant lemma).
-//   P^{-1} R = W o R - W o (L M^{-1} (L^T (W o R)))   (Woodbury)
+//   P^{-1} R = W o R - W o (L M^{-1} (L^T (W o R)))   (Woodbury), M^{-1}
+//         formed once per factor from C and applied as a K x K product
 //
 // The dense panels L^T diag(w) X (K x t, a reduction over the n rows) and
 // L Y (n x t) run on the FP64 matrix cores (v_mfma_f64_16x16x4f64): a wave
@@ -165,14 +166,22 @@ __global__ __launch_bounds__(256) void gram_kernel(int64_t n, int K, int64_t row
   }
 }
 
-// out (K x ldp) = sum of the parts in block order (deterministic).
-__global__ void gram_reduce_kernel(int nparts, int64_t size, const double* __restrict__ part,
-                                   double* __restrict__ out) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= size) return;
+// out (K x ldp) = sum of the parts (deterministic): a block takes 64
+// consecutive elements; wave w adds parts w, w + 4, ... in order (each read
+// a coalesced 512-byte row of the part array), then the four wave sums are
+// added in wave order.
+__global__ __launch_bounds__(256) void gram_reduce_kernel(int nparts, int64_t size,
+                                                          const double* __restrict__ part,
+                                                          double* __restrict__ out) {
+  __shared__ double sw[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t e = blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * size + e];
-  out[e] = s;
+  if (e < size)
+    for (int b = wave; b < nparts; b += 4) s += part[(int64_t)b * size + e];
+  sw[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && e < size) out[e] = ((sw[0][lane] + sw[1][lane]) + sw[2][lane]) + sw[3][lane];
 }
 
 // Z (n x t) = epilogue(L Y), Y K x ldy; one 16 x 16 output tile per wave.
@@ -254,22 +263,37 @@ __global__ void add_identity_kernel(int K, double* __restrict__ Mx) {
   if (e < K) Mx[e * K + e] += 1.0;
 }
 
-// S (K x ld) <- M^{-1} S with the Cholesky factor C (K x K), columns < t;
-// one thread per column.
-__global__ void chol_solve_kernel(int K, const double* __restrict__ C, int t, int ld,
-                                  double* __restrict__ S) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= t) return;
-  for (int i = 0; i < K; ++i) {  // C y = s
-    double v = S[(int64_t)i * ld + c];
-    for (int l = 0; l < i; ++l) v -= C[i * K + l] * S[(int64_t)l * ld + c];
-    S[(int64_t)i * ld + c] = v / C[i * K + i];
+// Minv (K x K) = M^{-1} from the Cholesky factor C (M = C C^T): column b by
+// C y = e_b, C^T x = y; one thread per column, once per factor.
+__global__ void chol_inverse_kernel(int K, const double* __restrict__ C,
+                                    double* __restrict__ Minv) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= K) return;
+  for (int i = 0; i < K; ++i) {
+    double v = (i == b) ? 1.0 : 0.0;
+    for (int l = 0; l < i; ++l) v -= C[i * K + l] * Minv[(int64_t)l * K + b];
+    Minv[(int64_t)i * K + b] = v / C[i * K + i];
   }
-  for (int i = K - 1; i >= 0; --i) {  // C^T x = y
-    double v = S[(int64_t)i * ld + c];
-    for (int l = i + 1; l < K; ++l) v -= C[l * K + i] * S[(int64_t)l * ld + c];
-    S[(int64_t)i * ld + c] = v / C[i * K + i];
+  for (int i = K - 1; i >= 0; --i) {
+    double v = Minv[(int64_t)i * K + b];
+    for (int l = i + 1; l < K; ++l) v -= C[l * K + i] * Minv[(int64_t)l * K + b];
+    Minv[(int64_t)i * K + b] = v / C[i * K + i];
   }
+}
+
+// Y (K x ld) = Minv S (columns < t): one thread per output element.
+__global__ void small_gemm_kernel(int K, int t, int ld, const double* __restrict__ Minv,
+                                  const double* __restrict__ S, double* __restrict__ Y) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)K * ld) return;
+  const int a = static_cast<int>(e / ld), c = static_cast<int>(e - (e / ld) * ld);
+  if (c >= t) {
+    Y[e] = 0.0;
+    return;
+  }
+  double acc = 0.0;
+  for (int b = 0; b < K; ++b) acc += Minv[(int64_t)a * K + b] * S[(int64_t)b * ld + c];
+  Y[e] = acc;
 }
 
 // E (K x ld): Rademacher eps_k for rows < k, 0 for the padded rows.
@@ -479,8 +503,8 @@ static Status gram_with(Model& M, const double* Lm, const double* w, const doubl
   VL_TRY(M.lrac_gpart.reserve(static_cast<size_t>(nblk) * size));
   hipLaunchKernelGGL(gram_kernel, dim3(nblk), dim3(256), 0, M.stream, n, K, rpb, Lm, w, X,
                      ldx, t, ldp, M.lrac_gpart.p);
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(blocks_for(size)), dim3(256), 0, M.stream, nblk,
-                     size, M.lrac_gpart.p, out);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((size + 63) / 64)), dim3(256), 0,
+                     M.stream, nblk, size, M.lrac_gpart.p, out);
   return check_launch("gram");
 }
 
@@ -492,6 +516,9 @@ Status lrac_factor(Model& M, const double* W) {
   hipLaunchKernelGGL(add_identity_kernel, dim3(1), dim3(K), 0, M.stream, K, M.lrac_M.p);
   hipLaunchKernelGGL(small_cholesky_kernel, dim3(1), dim3(256), sizeof(double) * K * K,
                      M.stream, K, M.lrac_M.p, M.lrac_M.p + K * K, M.status);
+  VL_TRY(M.lrac_Minv.reserve(static_cast<size_t>(K) * K));
+  hipLaunchKernelGGL(chol_inverse_kernel, dim3((K + 63) / 64), dim3(64), 0, M.stream, K,
+                     M.lrac_M.p, M.lrac_Minv.p);
   return check_launch("lrac factor");
 }
 
@@ -500,12 +527,14 @@ static Status lrac_precond(Model& M, const double* W, const double* R, double* Z
   const int K = M.lrac_K;
   const int ldp = (t + 15) / 16 * 16;
   VL_TRY(M.lrac_S.reserve(static_cast<size_t>(K) * ldp));
+  VL_TRY(M.lrac_S2.reserve(static_cast<size_t>(K) * ldp));
   VL_TRY(gram(M, W, R, t, t, ldp, M.lrac_S.p));
-  hipLaunchKernelGGL(chol_solve_kernel, dim3((t + 63) / 64), dim3(64), 0, M.stream, K,
-                     M.lrac_M.p, t, ldp, M.lrac_S.p);
+  // M^{-1} (L^T W R) with the explicit inverse (K x K, once per factor)
+  hipLaunchKernelGGL(small_gemm_kernel, dim3(blocks_for((int64_t)K * ldp)), dim3(256), 0,
+                     M.stream, K, t, ldp, M.lrac_Minv.p, M.lrac_S.p, M.lrac_S2.p);
   const int64_t tiles = ((M.n + 15) / 16) * ((t + 15) / 16);
   hipLaunchKernelGGL(panel_kernel, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, M.stream,
-                     M.n, K, M.lrac_L.p, M.lrac_S.p, ldp, t, 0, W, R, 0ull, Z);
+                     M.n, K, M.lrac_L.p, M.lrac_S2.p, ldp, t, 0, W, R, 0ull, Z);
   return check_launch("lrac precond");
 }
 

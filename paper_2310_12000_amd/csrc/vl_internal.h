@@ -331,7 +331,7 @@ struct Model {
   // past lrac_k), pivots, I + L^T W L (factored in place; log det after it)
   bool lrac_ready = false;
   int lrac_k = 0, lrac_K = 0;
-  DevBuf<double> lrac_L, lrac_pval, lrac_part, lrac_gpart, lrac_M, lrac_S;
+  DevBuf<double> lrac_L, lrac_pval, lrac_part, lrac_gpart, lrac_M, lrac_S, lrac_S2, lrac_Minv;
   // d L / d theta (2 x n x lrac_K, sigma2 then rho), the residual diagonals'
   // derivatives (2 x n) and the pivots' values of them per column
   bool lrac_dL_ready = false;

@@ -183,8 +183,8 @@ const char* vl_last_error(void);
  *              is the caller's order of i.i.d. locations, Sec. 4.1)
  *   n          number of locations, 1 <= n <= 262144 (VL_ERR_INVALID above:
  *              a build at n = 2,000,000 ended in a GPU memory fault whose
- *              cause is not found; the largest size run successfully is
- *              n = 117,434, and the limit sits below every size at which
+ *              cause is not found; the largest size run on the GPU is
+ *              n = 200,000, and the limit sits below every size at which
  *              the build's launch shapes or transfer sizes change from
  *              the verified ones)
  *   m          neighbours per point, 0 <= m <= 31; N(i) = the min(i, m)

@@ -48,9 +48,10 @@ VAR_TOL_MIXED = 1e-3
 FOC_CG_TOL = 1e-6
 
 C3_FAULT = ("the library refuses n above 262,144: a build at n = 2,000,000 ended in a GPU "
-            "memory fault whose cause is not found (a CPU emulation of every build kernel "
-            "at this size shows no out-of-bounds access); this case stays off the GPU until "
-            "the cause is shown")
+            "memory fault whose cause is not found (the library's own kernels run at this "
+            "size in a host emulation of the HIP runtime under AddressSanitizer, through "
+            "build, solves, mode, likelihood and prediction, show no invalid access); this "
+            "case stays off the GPU until the cause is shown")
 WORKLOADS = [
     pytest.param(("c2_n1e5", {}), id="c2_n1e5"),
     # the n = 2e6 workload's shape at the largest size the library runs

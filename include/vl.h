@@ -105,9 +105,10 @@ typedef struct {
   int precond;             /* vl_precond                                       */
   int lrac_rank;           /* k of the LRAC preconditioner                     */
   int precision;           /* vl_precision; VL_MIXED runs the preconditioner
-                              solves of the block solves (SLQ, prediction) in
-                              FP32 (FP32 B values and blocks, FP64 sums) inside
-                              the FP64 PCG; Newton stays FP64                  */
+                              solves of the block solves (SLQ, prediction) with
+                              FP32 n x t blocks and FP64 sums inside the FP64
+                              PCG (FP32 B values above 64 columns); Newton
+                              stays FP64                                       */
   int pred_tile;           /* columns per predictive-variance CG block
                               (0 = all s at once)                              */
   const int* replay_cg_iters; /* host, nullable: fixed CG iteration counts that

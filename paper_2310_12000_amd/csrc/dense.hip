@@ -136,9 +136,9 @@ __host__ __device__ __forceinline__ int seg_hi(int chunk, int K, bool lower) {
 // Batched form (tab_p given): block x takes entry x of the tables, a (problem,
 // row chunk, segment) triple of a packed block-diagonal system; the problem's
 // G sits at gofs[p], its rows at start[p], its partials at pofs[p] t.
-template <int TC, bool LOWER>
+template <int TC, bool LOWER, typename TV = double>
 __global__ __launch_bounds__(64 * kApplyWaves) void dense_part_kernel(
-    int K, int t, const double* __restrict__ A, const double* __restrict__ V,
+    int K, int t, const double* __restrict__ A, const TV* __restrict__ V,
     const double* __restrict__ rs, double* __restrict__ part, const int* __restrict__ tab_p,
     const int* __restrict__ tab_chunk, const int* __restrict__ tab_seg,
     const int* __restrict__ start, const int64_t* __restrict__ gofs,
@@ -166,7 +166,8 @@ __global__ __launch_bounds__(64 * kApplyWaves) void dense_part_kernel(
   for (int e = threadIdx.x; e < kSeg * TC; e += 64 * kApplyWaves) {
     const int s = g * kSeg + e / TC, c = c0 + e % TC;
     double v = 0.0;
-    if (s >= s_lo && s < s_hi && c < t) v = V[(int64_t)s * t + c] * (rs ? rs[s] : 1.0);
+    if (s >= s_lo && s < s_hi && c < t)
+      v = static_cast<double>(V[(int64_t)s * t + c]) * (rs ? rs[s] : 1.0);
     s_v[e / TC][e % TC] = v;
   }
   __syncthreads();
@@ -205,9 +206,9 @@ __global__ __launch_bounds__(64 * kApplyWaves) void dense_part_kernel(
   }
 }
 
-template <bool LOWER>
+template <bool LOWER, typename TO = double>
 __global__ void dense_reduce_kernel(int K, int t, const double* __restrict__ part,
-                                    double* __restrict__ out) {
+                                    TO* __restrict__ out) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= (int64_t)K * t) return;
   const int r = static_cast<int>(e / t);
@@ -215,7 +216,7 @@ __global__ void dense_reduce_kernel(int K, int t, const double* __restrict__ par
   double v = 0.0;
   for (int g = seg_lo(chunk, LOWER); g < seg_hi(chunk, K, LOWER); ++g)
     v += part[(int64_t)g * K * t + e];
-  out[e] = v;
+  out[e] = static_cast<TO>(v);
 }
 
 // Wide blocks (t > 64): out[r, c] = sum_s A[s lda + r] v(s, c) for the
@@ -319,12 +320,13 @@ __global__ __launch_bounds__(R * 4) void dense_gemm_kernel(int Kd, int lda, int 
 // from H on were subtracted from base before the head solve), with the
 // children's values from Y.  One wave per row, lanes over entries, a fixed
 // butterfly per column.
+template <typename TY = double>
 __global__ __launch_bounds__(256) void dense_fold_kernel(int K, int t, const int* __restrict__ lo,
                                                          const int* __restrict__ split,
                                                          const int* __restrict__ bt_col,
                                                          const double* __restrict__ bt_val,
-                                                         const double* __restrict__ base,
-                                                         const double* __restrict__ Y,
+                                                         const TY* __restrict__ base,
+                                                         const TY* __restrict__ Y,
                                                          double* __restrict__ xp) {
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -332,10 +334,11 @@ __global__ __launch_bounds__(256) void dense_fold_kernel(int K, int t, const int
   const int b = lo[j], e = split[j];
   for (int c = 0; c < t; ++c) {
     double part = 0.0;
-    for (int q = b + lane; q < e; q += 64) part += bt_val[q] * Y[(int64_t)bt_col[q] * t + c];
+    for (int q = b + lane; q < e; q += 64)
+      part += bt_val[q] * static_cast<double>(Y[(int64_t)bt_col[q] * t + c]);
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) part += __shfl_xor(part, o);
-    if (lane == 0) xp[(int64_t)j * t + c] = base[(int64_t)j * t + c] - part;
+    if (lane == 0) xp[(int64_t)j * t + c] = static_cast<double>(base[(int64_t)j * t + c]) - part;
   }
 }
 
@@ -408,9 +411,9 @@ Status dense_factor(Model& M) {
   return check_launch("dense inverse");
 }
 
-template <bool LOWER>
-static Status launch_apply(Model& M, const double* A, const double* V, const double* rs,
-                           double* out, int t) {
+template <bool LOWER, typename TV = double, typename TO = double>
+static Status launch_apply(Model& M, const double* A, const TV* V, const double* rs,
+                           TO* out, int t) {
   const int K = M.dense_rows;
   const int nseg = (K + kSeg - 1) / kSeg;
   const size_t need = static_cast<size_t>(nseg) * K * t;
@@ -424,17 +427,18 @@ static Status launch_apply(Model& M, const double* A, const double* V, const dou
   }
   const unsigned gx = static_cast<unsigned>((K + 63) / 64);
   if (t == 1) {
-    hipLaunchKernelGGL((dense_part_kernel<1, LOWER>), dim3(gx, nseg, 1), dim3(64 * kApplyWaves),
-                       0, M.stream, K, t, A, V, rs, part, nullptr, nullptr, nullptr,
-                       nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((dense_part_kernel<1, LOWER, TV>), dim3(gx, nseg, 1),
+                       dim3(64 * kApplyWaves), 0, M.stream, K, t, A, V, rs, part, nullptr,
+                       nullptr, nullptr, nullptr, nullptr, nullptr);
   } else {
-    hipLaunchKernelGGL((dense_part_kernel<8, LOWER>), dim3(gx, nseg, (t + 7) / 8),
+    hipLaunchKernelGGL((dense_part_kernel<8, LOWER, TV>), dim3(gx, nseg, (t + 7) / 8),
                        dim3(64 * kApplyWaves), 0, M.stream, K, t, A, V, rs, part,
                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
   }
   const int64_t kt = static_cast<int64_t>(K) * t;
-  hipLaunchKernelGGL(dense_reduce_kernel<LOWER>, dim3(static_cast<unsigned>((kt + 255) / 256)),
-                     dim3(256), 0, M.stream, K, t, part, out);
+  hipLaunchKernelGGL((dense_reduce_kernel<LOWER, TO>),
+                     dim3(static_cast<unsigned>((kt + 255) / 256)), dim3(256), 0, M.stream, K, t,
+                     part, out);
   return check_launch("dense apply");
 }
 
@@ -460,9 +464,25 @@ Status dense_upper(Model& M, double* Y, int t) {
     VL_TRY(M.dense_xp.reserve(need));
     xp = M.dense_xp.p;
   }
-  hipLaunchKernelGGL(dense_fold_kernel, dim3((K + 3) / 4), dim3(256), 0, M.stream, K, t,
+  hipLaunchKernelGGL(dense_fold_kernel<double>, dim3((K + 3) / 4), dim3(256), 0, M.stream, K, t,
                      M.dense_lo.p, M.head_split.p, M.bt_col.p, M.bt_val.p, Y, Y, xp);
   return launch_apply<false>(M, M.dense_gb.p, xp, nullptr, Y, t);
+}
+
+// FP32-storage forms for the mixed-precision narrow blocks (G, the sums and
+// the folded right-hand sides stay FP64).
+Status dense_lower_f32(Model& M, const float* X, float* Y, int t, const double* rs) {
+  TimedLaunch tl(M, kTimeHeadLower, apply_bytes(M, t) - 8.0 * M.dense_rows * t);
+  return launch_apply<true, float, float>(M, M.dense_gf.p, X, rs, Y, t);
+}
+
+Status dense_upper_f32(Model& M, float* Y, int t) {
+  const int K = M.dense_rows;
+  TimedLaunch tl(M, kTimeHeadUpper, apply_bytes(M, t) - 8.0 * K * t);
+  VL_TRY(M.dense_xp.reserve(static_cast<size_t>(K) * t));
+  hipLaunchKernelGGL(dense_fold_kernel<float>, dim3((K + 3) / 4), dim3(256), 0, M.stream, K, t,
+                     M.dense_lo.p, M.head_split.p, M.bt_col.p, M.bt_val.p, Y, Y, M.dense_xp.p);
+  return launch_apply<false, double, float>(M, M.dense_gb.p, M.dense_xp.p, nullptr, Y, t);
 }
 
 // Launches dense_gemm_kernel with 128-row blocks when those alone make a grid

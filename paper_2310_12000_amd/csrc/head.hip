@@ -136,11 +136,11 @@ __global__ __launch_bounds__(kHeadThreads) void head_sort_kernel(int H,
 // what depends on the row id (the right-hand side).  Results leave LDS only
 // at the end; a global store inside the polling loop would make every later
 // round wait for it.
-template <int W, int NT>
+template <int W, int NT, typename TX = double, typename TY = double>
 __global__ __launch_bounds__(NT) void head_lower_kernel(
     int H, int P, int K, int m, int t, const int* __restrict__ prow,
-    const int* __restrict__ pnbr, const double* __restrict__ pval, const double* __restrict__ X,
-    const double* __restrict__ rs, double* Y) {
+    const int* __restrict__ pnbr, const double* __restrict__ pval, const TX* __restrict__ X,
+    const double* __restrict__ rs, TY* Y) {
   extern __shared__ double s_y[];
   const int c = blockIdx.x;
   const int tid = threadIdx.x;
@@ -148,7 +148,8 @@ __global__ __launch_bounds__(NT) void head_lower_kernel(
   constexpr int kWaves = NT / 64;
   // rows below K are already solved in Y (the dense block); the P positions
   // hold rows K..H-1
-  for (int i = tid; i < H; i += NT) s_y[i] = i < K ? Y[(int64_t)i * t + c] : sentinel();
+  for (int i = tid; i < H; i += NT)
+    s_y[i] = i < K ? static_cast<double>(Y[(int64_t)i * t + c]) : sentinel();
   __syncthreads();
   int a_row = -1;            // stage A: row id, two batches ahead
   int ni = -1, nj[W];        // stage B: one batch ahead
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(NT) void head_lower_kernel(
     }
     nx = 0.0;
     if (row >= 0) {
-      nx = X[(int64_t)row * t + c];
+      nx = static_cast<double>(X[(int64_t)row * t + c]);
       if (rs) nx *= rs[row];
     }
   };
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(NT) void head_lower_kernel(
     batch += kWaves;
   }
   __syncthreads();
-  for (int i = tid; i < H; i += NT) Y[(int64_t)i * t + c] = s_y[i];
+  for (int i = tid; i < H; i += NT) Y[(int64_t)i * t + c] = static_cast<TY>(s_y[i]);
 }
 
 // Upper: the right-hand side of head row j arrives in Y already reduced by its
@@ -226,12 +227,12 @@ struct HeadRanges {
   int start[10];  // positions [start[k], start[k + 1]) hold range k
 };
 
-template <int NT>
+template <int NT, typename TY = double>
 __global__ __launch_bounds__(NT) void head_upper_kernel(
     int H, int K, int t, HeadRanges R, const int* __restrict__ prow, const int* __restrict__ pptr,
     const int* __restrict__ psplit, const int* __restrict__ pcol,
     const double* __restrict__ pval, const int* __restrict__ wcol,
-    const double* __restrict__ wval, double* Y) {
+    const double* __restrict__ wval, TY* Y) {
   extern __shared__ double s_y[];
   const int c = blockIdx.x;
   const int tid = threadIdx.x;
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(NT) void head_upper_kernel(
     if (r > 0) {
       for (int p = p0 + tid; p < p1; p += NT) {
         const int j = prow[p];
-        double acc = Y[(int64_t)j * t + c];
+        double acc = static_cast<double>(Y[(int64_t)j * t + c]);
         const int e = psplit[p];
         for (int q = pptr[p]; q < e; q += 8) {
           int cb[8];
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(NT) void head_upper_kernel(
 #pragma unroll
           for (int k = 0; k < 8; ++k) acc -= vb[k] * yv[k];
         }
-        Y[(int64_t)j * t + c] = acc;
+        Y[(int64_t)j * t + c] = static_cast<TY>(acc);
       }
       __syncthreads();  // the folded right-hand sides are visible to the block
     }
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(NT) void head_upper_kernel(
         ncb[k] = in ? wcol[(int64_t)p * kWin + k] : -1;
         nvb[k] = in ? wval[(int64_t)p * kWin + k] : 0.0;
       }
-      nacc = (nrow >= 0) ? Y[(int64_t)nrow * t + c] : 0.0;
+      nacc = (nrow >= 0) ? static_cast<double>(Y[(int64_t)nrow * t + c]) : 0.0;
     };
     int batch = tid >> 6;
     stage_a(p0 + batch * 64 + lane);
@@ -377,23 +378,25 @@ __global__ __launch_bounds__(NT) void head_upper_kernel(
     __syncthreads();  // the range is solved before the next one folds it in
   }
   // rows below K are solved afterwards (the dense block) from Y's folded values
-  for (int i = K + tid; i < H; i += NT) Y[(int64_t)i * t + c] = s_y[i];
+  for (int i = K + tid; i < H; i += NT) Y[(int64_t)i * t + c] = static_cast<TY>(s_y[i]);
 }
 
 // y_j <- x_j - sum over the tail entries of the B^T row of head row j (all
 // finished), for every head row and column; fully parallel.
+template <typename TY = double>
 __global__ void head_upper_pre_kernel(int H, int t, const int* __restrict__ split,
                                       const int* __restrict__ bt_ptr,
                                       const int* __restrict__ bt_col,
                                       const double* __restrict__ bt_val,
-                                      const double* __restrict__ X, double* Y) {
+                                      const double* __restrict__ X, TY* Y) {
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= (int64_t)H * t) return;
   const int j = static_cast<int>(g / t), c = static_cast<int>(g % t);
   double acc = X[(int64_t)j * t + c];
   const int e = bt_ptr[j + 1];
-  for (int q = split[j]; q < e; ++q) acc -= bt_val[q] * Y[(int64_t)bt_col[q] * t + c];
-  Y[(int64_t)j * t + c] = acc;
+  for (int q = split[j]; q < e; ++q)
+    acc -= bt_val[q] * static_cast<double>(Y[(int64_t)bt_col[q] * t + c]);
+  Y[(int64_t)j * t + c] = static_cast<TY>(acc);
 }
 
 Status head_lower(Model& M, const double* X, double* Y, int t, const double* rs) {
@@ -428,7 +431,7 @@ Status head_upper(Model& M, const double* X, double* Y, int t) {
   if (H == 0) return Status::ok();
   const int K = M.dense_rows, P = M.head_pos;
   const int64_t work = (int64_t)H * t;
-  hipLaunchKernelGGL(head_upper_pre_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0,
+  hipLaunchKernelGGL(head_upper_pre_kernel<double>, dim3((unsigned)((work + 255) / 256)), dim3(256), 0,
                      M.stream, H, t, M.head_split.p, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, Y);
   if (P > 0) {
     const size_t lds = sizeof(double) * H;
@@ -443,6 +446,55 @@ Status head_upper(Model& M, const double* X, double* Y, int t) {
   }
   if (K > 0) VL_TRY(dense_upper(M, Y, t));  // rows 0..K-1, after every later row
   return check_launch("head upper");
+}
+
+// FP32-storage forms of the head solves for the mixed-precision narrow
+// blocks: the same kernels with FP32 right-hand sides / results (LDS and
+// every sum stay FP64).
+Status head_lower_f32(Model& M, const float* X, float* Y, int t, const double* rs) {
+  const int H = M.head_rows;
+  if (H == 0) return Status::ok();
+  const int K = M.dense_rows, P = M.head_pos;
+  if (K > 0) VL_TRY(dense_lower_f32(M, X, Y, t, rs));  // rows 0..K-1
+  if (P == 0) return Status::ok();
+  TimedLaunch tl(M, kTimeHeadLower, 12.0 * M.nnz_head_f + 8.0 * H * t + (rs ? 8.0 * H : 0.0));
+  const size_t lds = sizeof(double) * H;
+  if (M.m <= 8) {
+    hipLaunchKernelGGL((head_lower_kernel<8, 1024, float, float>), dim3(t), dim3(1024), lds,
+                       M.stream, H, P, K, M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
+  } else if (M.m <= 16) {
+    hipLaunchKernelGGL((head_lower_kernel<16, 512, float, float>), dim3(t), dim3(512), lds,
+                       M.stream, H, P, K, M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
+  } else if (M.m <= 24) {
+    hipLaunchKernelGGL((head_lower_kernel<24, 512, float, float>), dim3(t), dim3(512), lds,
+                       M.stream, H, P, K, M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
+  } else {
+    hipLaunchKernelGGL((head_lower_kernel<32, 512, float, float>), dim3(t), dim3(512), lds,
+                       M.stream, H, P, K, M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
+  }
+  return check_launch("head lower f32");
+}
+
+Status head_upper_f32(Model& M, const double* X, float* Y, int t) {
+  const int H = M.head_rows;
+  if (H == 0) return Status::ok();
+  const int K = M.dense_rows, P = M.head_pos;
+  const int64_t work = (int64_t)H * t;
+  hipLaunchKernelGGL(head_upper_pre_kernel<float>, dim3((unsigned)((work + 255) / 256)), dim3(256),
+                     0, M.stream, H, t, M.head_split.p, M.bt_ptr.p, M.bt_col.p, M.bt_val.p, X, Y);
+  if (P > 0) {
+    const size_t lds = sizeof(double) * H;
+    TimedLaunch tl(M, kTimeHeadUpper, 12.0 * M.head_nnz_b + 4.0 * H + 8.0 * H * t);
+    HeadRanges R{};
+    R.n = static_cast<int>(M.hb_blocks.size()) - 1;
+    for (int k = 0; k <= R.n; ++k) R.start[k] = M.hb_blocks[k];
+    hipLaunchKernelGGL((head_upper_kernel<512, float>), dim3(t), dim3(512), lds, M.stream, H, K,
+                       t, R, M.hb_rows.p, M.hb_pptr.p, M.hb_split.p, M.hb_col.p, M.hb_val.p,
+                       M.hb_wcol.p, M.hb_wval.p, Y);
+    VL_TRY(check_launch("head upper f32"));
+  }
+  if (K > 0) VL_TRY(dense_upper_f32(M, Y, t));
+  return check_launch("head upper f32");
 }
 
 // ---- position-ordered copies of the head's rows of B and B^T

@@ -998,7 +998,7 @@ Status neg_log_marglik(Model& M, const vl_opts& o, double* nll, double* grad, Nl
     // mixed form (FP32 solves for t > 64): the FP32 preconditioner's
     // deviation from FP64 on the first probe, before the CG overwrites Z/H
     M.last_f32_dev = 0.0;
-    if (mixed && t > 64)
+    if (mixed)
       VL_TRY(precond_f32_deviation(M, o.precond == VL_PREC_LVA ? M.dval.p : M.vec_b.p,
                                    M.rhs_blk.p, t, &M.last_f32_dev));
     std::vector<int> rbuf;
@@ -1187,7 +1187,7 @@ Status predict(Model& M, const double* coords_p, int64_t np, const double* Fp,
                          kTagPredZ1, 1, M.cg.Z.p, M.cg.H.p));
     if (c0 == 0) {
       M.last_f32_dev = 0.0;
-      if (o.precision == VL_MIXED && tt > 64)
+      if (o.precision == VL_MIXED)
         VL_TRY(precond_f32_deviation(M, M.vec_b.p, M.rhs_blk.p, tt, &M.last_f32_dev));
     }
     std::vector<int> rbuf;

@@ -8,12 +8,14 @@
 // stopping test applies to the FP64 residual.  The Newton update, the
 // neighbour Cholesky, the tridiagonal eigensolve and all assembly stay FP64.
 //
-// The FP32 solves are used for blocks wider than 64 columns, where the
-// solves move bytes; they are level-scheduled (one launch per level of the
-// dependency DAG; no sentinel fill, no polling), and B^T solves fold the head
-// rows' tail entries in one launch between the tail and the head levels.  The
-// leading rows covered by the dense inverse G come from its FP64 GEMM, which
-// reads and writes the FP32 blocks.  Narrower blocks keep the FP64 solves.
+// Blocks wider than 64 columns use level-scheduled FP32 solves (one launch
+// per level of the dependency DAG; no sentinel fill, no polling; FP32 B
+// values), and B^T solves fold the head rows' tail entries in one launch
+// between the tail and the head levels; the leading rows covered by the
+// dense inverse G come from its FP64 GEMM, which reads and writes the FP32
+// blocks.  Narrower blocks run the FP64 path's kernels (dense leading block,
+// LDS head, sync-free tail) with FP32 right-hand sides and results: FP64 B
+// values, G and LDS, FP64 sums.
 #include <algorithm>
 #include <cmath>
 
@@ -288,6 +290,12 @@ __global__ void column_kernel(int64_t n, int t, const double* __restrict__ X,
 // Relative 2-norm deviation of the FP32 preconditioner application (the
 // level-scheduled FP32 solves of the mixed form) from the FP64 one on the
 // first column of X (n x t): z = B^{-1} (sdiag o B^{-T} x) both ways.
+// Z (FP64) = Zf (FP32) widened
+__global__ void to_f64_kernel(int64_t count, const float* __restrict__ x, double* __restrict__ y) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < count) y[e] = static_cast<double>(x[e]);
+}
+
 Status precond_f32_deviation(Model& M, const double* sdiag, const double* X, int t,
                              double* dev) {
   const int64_t n = M.n;
@@ -305,8 +313,16 @@ Status precond_f32_deviation(Model& M, const double* sdiag, const double* X, int
   VL_TRY(M.vec_d.reserve(n));
   VL_TRY(trsm_bt_slot(M, x, M.vec_d.p, 1, false, 0));
   VL_TRY(trsm_b_slot(M, M.vec_d.p, z64, 1, sdiag, false, 1));
-  VL_TRY(upper_f32(M, x, f1, 1));
-  VL_TRY(lower_f32(M, f1, f2, z32, 1, sdiag));
+  if (t <= 64 && !M.force_levels && !M.bd_use) {  // the narrow FP32 kernels the block uses
+    VL_TRY(trsm_bt_f32_narrow(M, x, f1, 1));
+    VL_TRY(trsm_b_f32_narrow(M, f1, f2, 1, sdiag));
+    hipLaunchKernelGGL(to_f64_kernel, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, M.stream,
+                       n, f2, z32);
+    VL_TRY(check_launch("to_f64"));
+  } else {
+    VL_TRY(upper_f32(M, x, f1, 1));
+    VL_TRY(lower_f32(M, f1, f2, z32, 1, sdiag));
+  }
   std::vector<double> a(n), b(n);
   VL_HIP(hipMemcpyAsync(a.data(), z64, sizeof(double) * n, hipMemcpyDeviceToHost, M.stream));
   VL_HIP(hipMemcpyAsync(b.data(), z32, sizeof(double) * n, hipMemcpyDeviceToHost, M.stream));
@@ -323,25 +339,27 @@ Status precond_f32_deviation(Model& M, const double* sdiag, const double* X, int
 
 CgOps vadu_ops_mixed(const double* W, const double* sdiag) {
   CgOps ops = vadu_ops(W, sdiag);  // the FP64 operator
-  const auto fp64_precond = ops.precond;
-  const auto fp64_fill = ops.needs_fill;
-  // FP32 solves for wide blocks only: for t <= 64 the solves are bound by
-  // the dependency chain (LDS head, sync-free tail), not by bytes, and the
-  // FP64 kernels are used unchanged.
-  ops.precond = [sdiag, fp64_precond](Model& M, const double* R, double* Z, double* Y,
-                                      int t) -> Status {
-    if (t <= 64) return fp64_precond(M, R, Z, Y, t);
-    VL_TRY(ensure_f32_values(M));
+  // FP32 solves at every width: wide blocks level-scheduled with FP32 B
+  // values; narrow blocks (t <= 64) through the LDS head and sync-free tail
+  // with FP32 right-hand sides and results, which fill their own FP32
+  // outputs with the sentinel (the FP64 blocks need no fill).
+  ops.precond = [sdiag](Model& M, const double* R, double* Z, double* Y, int t) -> Status {
+    (void)Y;
     const size_t nt = static_cast<size_t>(M.n) * t;
     VL_TRY(M.mx_rhs.reserve(nt));
     VL_TRY(M.mx_f2.reserve(nt));
+    if (t <= 64 && !M.force_levels && !M.bd_use) {
+      VL_TRY(trsm_bt_f32_narrow(M, R, M.mx_rhs.p, t));
+      VL_TRY(trsm_b_f32_narrow(M, M.mx_rhs.p, M.mx_f2.p, t, sdiag));
+      hipLaunchKernelGGL(to_f64_kernel, dim3(nblk(static_cast<int64_t>(nt))), dim3(256), 0,
+                         M.stream, static_cast<int64_t>(nt), M.mx_f2.p, Z);
+      return check_launch("to_f64");
+    }
+    VL_TRY(ensure_f32_values(M));
     VL_TRY(upper_f32(M, R, M.mx_rhs.p, t));
     return lower_f32(M, M.mx_rhs.p, M.mx_f2.p, Z, t, sdiag);
   };
-  ops.needs_fill = [fp64_fill](const Model& M, int t) {
-    if (t > 64) return false;
-    return fp64_fill ? fp64_fill(M, t) : true;
-  };
+  ops.needs_fill = [](const Model&, int) { return false; };
   return ops;
 }
 

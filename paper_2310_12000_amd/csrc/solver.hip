@@ -67,16 +67,7 @@ Status reduce_chunks(hipStream_t s, const double* part, int nchunk, int t, doubl
 // (double; float in the mixed-precision form); every sum is accumulated in
 // double.  Y and Z (the preconditioner's outputs) are pre-filled with the
 // sentinel of the sync-free solves when given.
-template <typename T>
-__device__ __forceinline__ T sentinel_of();
-template <>
-__device__ __forceinline__ double sentinel_of<double>() {
-  return sentinel();
-}
-template <>
-__device__ __forceinline__ float sentinel_of<float>() {
-  return sentinel_f();
-}
+
 
 template <typename T>
 __global__ __launch_bounds__(256) void cg_init_kernel(ChunkGrid g, const T* __restrict__ rhs,

@@ -35,6 +35,14 @@ struct InMem {
   int t;
   __device__ __forceinline__ double operator()(int64_t i, int c) const { return X[i * t + c]; }
 };
+// The same for an FP32 block (mixed-precision solves), widened on read.
+struct InMemF {
+  const float* X;
+  int t;
+  __device__ __forceinline__ double operator()(int64_t i, int c) const {
+    return static_cast<double>(X[i * t + c]);
+  }
+};
 // s_i * (Rademacher or Gaussian probe (seed, tag, col0 + c, i))
 struct InProbe {
   const double* s;
@@ -576,13 +584,13 @@ __device__ __forceinline__ int64_t grab_stream(int* counters, int lane, int nstr
 // strictly in order, so the sum order is fixed.  Rows r0..n-1 are solved,
 // taken in the topological order `order` (level by level) when given, else
 // ascending (lower) / descending (upper); rows below r0 must be final.
-template <int W, bool LOWER, class In>
+template <int W, bool LOWER, class In, typename TY = double>
 __global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m, int t, Lanes L,
                                                    const int* __restrict__ order,
                                                    const int* __restrict__ ptr,
                                                    const int* __restrict__ idx,
                                                    const double* __restrict__ vals, In x,
-                                                   const double* __restrict__ rs, double* Y,
+                                                   const double* __restrict__ rs, TY* Y,
                                                    int nstreams, int* counter, int* abort_flag,
                                                    int* status) {
   const int lane = threadIdx.x & 63;
@@ -613,12 +621,13 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m,
           e = ptr[i + 1];
         }
         if (q >= e) {
-          publish(&Y[i * t + c], acc);
+          publish(&Y[i * t + c], static_cast<TY>(acc));
           pending = false;
         }
       }
       int cb[W];
-      double vb[W], yv[W];
+      double vb[W];
+      TY yv[W];
       int kk = W;  // cursor in the current window; W = no window loaded
       int rounds = 0;
       while (__any(pending)) {
@@ -633,7 +642,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m,
             }
 #pragma unroll
             for (int k = 0; k < W; ++k)
-              yv[k] = (cb[k] >= 0) ? Y[(int64_t)cb[k] * t + c] : 0.0;
+              yv[k] = (cb[k] >= 0) ? Y[(int64_t)cb[k] * t + c] : TY(0);
             kk = 0;
           } else {
 #pragma unroll
@@ -646,7 +655,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m,
           kk = fm;
           if (kk == W) {
             if (q + W >= e) {  // slots past the row end are empty (-1)
-              publish(&Y[i * t + c], acc);
+              publish(&Y[i * t + c], static_cast<TY>(acc));
               pending = false;
             } else {
               q += W;  // window consumed: the next round loads the next one
@@ -673,12 +682,13 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m,
 }
 
 // Fill Y with the sentinel and reset the work counter and abort flag.
-__global__ void trsm_prefill(double* __restrict__ Y, int64_t count, int* counter) {
+template <typename TY>
+__global__ void trsm_prefill(TY* __restrict__ Y, int64_t count, int* counter) {
   if (blockIdx.x == 0)
     for (int k = threadIdx.x; k < kSlotInts; k += blockDim.x) counter[k] = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x)
-    Y[i] = sentinel();
+    Y[i] = sentinel_of<TY>();
 }
 
 // Level-scheduled solve of one level (wide blocks, t > 64).  All rows a
@@ -1053,12 +1063,13 @@ static int* counter_slot(Model& M, int slot) {
   return M.ext ? M.ext->counter : M.counter.p + slot * kSlotInts;
 }
 
-static Status trsm_prepare(Model& M, double* Y, int64_t count, int slot) {
+template <typename TY>
+static Status trsm_prepare(Model& M, TY* Y, int64_t count, int slot) {
   if (!M.ext) VL_TRY(M.counter.reserve(2 * kSlotInts + 64));
   int g = static_cast<int>((count + 255) / 256);
   if (g > 4096) g = 4096;
   if (g < 1) g = 1;
-  hipLaunchKernelGGL(trsm_prefill, dim3(g), dim3(256), 0, M.stream, Y, count,
+  hipLaunchKernelGGL(trsm_prefill<TY>, dim3(g), dim3(256), 0, M.stream, Y, count,
                      counter_slot(M, slot));
   return check_launch("trsm prefill");
 }
@@ -1134,6 +1145,63 @@ Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled,
     VL_TRY(check_launch("trsm_bt"));
   }
   if (H > 0) VL_TRY(head_upper(M, X, Y, t));
+  return Status::ok();
+}
+
+// FP32-storage narrow solves (t <= 64) of the mixed-precision form: the same
+// head and sync-free tail kernels with FP32 right-hand sides and results
+// (FP64 B values, FP64 row sums), for the preconditioner of the FP64 PCG.
+Status trsm_b_f32_narrow(Model& M, const float* X, float* Y, int t, const double* rowscale) {
+  if (t > 64) return Status::invalid("narrow FP32 solve with more than 64 columns");
+  VL_TRY(trsm_prepare(M, Y, M.n * (int64_t)t, 0));
+  const int64_t H = head_of(M, t);
+  if (H > 0) VL_TRY(head_lower_f32(M, X, Y, t, rowscale));
+  if (H >= M.n) return Status::ok();
+  Lanes L = Lanes::of(t);
+  int g = trsm_grid(units_of(M.n - H, t));
+  const int ns = trsm_streams(M, g);
+  int* cnt = counter_slot(M, 0);
+  PollingOrder order(M);
+  TimedLaunch tl(M, kTimeTrsmLower,
+                 12.0 * (M.nnz - (H ? M.nnz_head_f : 0)) + 8.0 * (M.n - H) * t +
+                     (rowscale ? 8.0 * (M.n - H) : 0.0));
+  const int* ord = H ? M.tail_order_f.p : M.full_order_f.p;
+  if (M.m <= 8) {
+    hipLaunchKernelGGL((trsm_kernel<8, true, InMemF, float>), dim3(g), dim3(256), 0, M.stream,
+                       M.n, H, M.m, t, L, ord, nullptr, M.nbr.p, M.bval.p, InMemF{X, t},
+                       rowscale, Y, ns, cnt, cnt + kAbortOffset, M.status);
+  } else if (M.m <= 16) {
+    hipLaunchKernelGGL((trsm_kernel<16, true, InMemF, float>), dim3(g), dim3(256), 0, M.stream,
+                       M.n, H, M.m, t, L, ord, nullptr, M.nbr.p, M.bval.p, InMemF{X, t},
+                       rowscale, Y, ns, cnt, cnt + kAbortOffset, M.status);
+  } else {
+    hipLaunchKernelGGL((trsm_kernel<32, true, InMemF, float>), dim3(g), dim3(256), 0, M.stream,
+                       M.n, H, M.m, t, L, ord, nullptr, M.nbr.p, M.bval.p, InMemF{X, t},
+                       rowscale, Y, ns, cnt, cnt + kAbortOffset, M.status);
+  }
+  return check_launch("trsm_b f32");
+}
+
+Status trsm_bt_f32_narrow(Model& M, const double* X, float* Y, int t) {
+  if (t > 64) return Status::invalid("narrow FP32 solve with more than 64 columns");
+  VL_TRY(trsm_prepare(M, Y, M.n * (int64_t)t, 0));
+  const int64_t H = head_of(M, t);
+  if (H < M.n) {
+    Lanes L = Lanes::of(t);
+    int g = trsm_grid(units_of(M.n - H, t));
+    const int ns = trsm_streams(M, g);
+    int* cnt = counter_slot(M, 0);
+    PollingOrder order(M);
+    TimedLaunch tl(M, kTimeTrsmUpper,
+                   12.0 * (M.nnz - (H ? M.nnz_head_bt : 0)) + 4.0 * (M.n - H) +
+                       12.0 * (M.n - H) * t);
+    hipLaunchKernelGGL((trsm_kernel<16, false, InMem, float>), dim3(g), dim3(256), 0, M.stream,
+                       M.n, H, 0, t, L, H ? M.tail_order_b.p : M.full_order_b.p, M.bt_ptr.p,
+                       M.bt_col.p, M.bt_val.p, InMem{X, t}, nullptr, Y, ns, cnt,
+                       cnt + kAbortOffset, M.status);
+    VL_TRY(check_launch("trsm_bt f32"));
+  }
+  if (H > 0) VL_TRY(head_upper_f32(M, X, Y, t));
   return Status::ok();
 }
 

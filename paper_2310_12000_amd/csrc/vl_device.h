@@ -24,20 +24,33 @@ __device__ __forceinline__ bool is_sentinel(float v) {
   return static_cast<unsigned>(__float_as_int(v)) == 0xFFA5BEEFu;
 }
 
+// The sentinel of a storage type (double; float in the mixed-precision form).
+template <typename T>
+__device__ __forceinline__ T sentinel_of();
+template <>
+__device__ __forceinline__ double sentinel_of<double>() {
+  return sentinel();
+}
+template <>
+__device__ __forceinline__ float sentinel_of<float>() {
+  return sentinel_f();
+}
+
 // In-order consumption of one window of a triangular-solve row.  Entries
 // k0 <= k < W are taken while their values are ready (slot < 0 = no entry;
 // its value and coefficient are 0), applying acc -= v[k] * y[k] in order.
 // Returns the first position still waiting (W once the window is done).
 // Branch-free: the ready prefix and the updates are computed with selects.
-template <int W>
-__device__ __forceinline__ int consume_ready(const int* cb, const double* vb, const double* yv,
+// The values y may be stored in FP64 or FP32; the update is FP64.
+template <int W, typename TY>
+__device__ __forceinline__ int consume_ready(const int* cb, const double* vb, const TY* yv,
                                              int k0, double& acc) {
   int fm = W;
 #pragma unroll
   for (int k = W - 1; k >= 0; --k) fm = (k >= k0 && cb[k] >= 0 && is_sentinel(yv[k])) ? k : fm;
 #pragma unroll
   for (int k = 0; k < W; ++k) {
-    const double nx = acc - vb[k] * yv[k];
+    const double nx = acc - vb[k] * static_cast<double>(yv[k]);
     acc = (k >= k0 && k < fm) ? nx : acc;
   }
   return fm;

@@ -444,6 +444,9 @@ constexpr int kHeadRows = 12288;  // with the dense first 4096 rows (measured be
 Status build_head_schedule(Model& M);
 Status head_lower(Model& M, const double* X, double* Y, int t, const double* rs);
 Status head_upper(Model& M, const double* X, double* Y, int t);
+// FP32-storage head solves (FP64 LDS and sums) for mixed-precision narrow blocks
+Status head_lower_f32(Model& M, const float* X, float* Y, int t, const double* rs);
+Status head_upper_f32(Model& M, const double* X, float* Y, int t);
 Status refresh_head_values(Model& M);
 
 // ---- dense leading block (dense.hip)
@@ -465,6 +468,8 @@ Status build_dense(Model& M);
 Status dense_factor(Model& M);
 Status dense_lower(Model& M, const double* X, double* Y, int t, const double* rs);
 Status dense_upper(Model& M, double* Y, int t);
+Status dense_lower_f32(Model& M, const float* X, float* Y, int t, const double* rs);
+Status dense_upper_f32(Model& M, float* Y, int t);
 
 // ---- solver kernels (solver.hip)
 Status tridiag_quadrature(Model& M, CgState& S, double* out_dev);

@@ -204,6 +204,10 @@ Status transpose_pattern(Model& M, const int* nbr, int64_t rows, int m, int64_t 
 // Y[i, c] = s_i eps_ic (Rademacher probes of columns col0 .. col0 + t - 1)
 Status probe_fill(Model& M, double* Y, int t, const double* s, uint64_t seed, uint32_t tag,
                   int col0);
+// FP32-storage narrow solves (t <= 64, mixed-precision form): B Y = rs o X
+// with X and Y FP32, and B^T Y = X with X FP64 and Y FP32.
+Status trsm_b_f32_narrow(Model& M, const float* X, float* Y, int t, const double* rowscale);
+Status trsm_bt_f32_narrow(Model& M, const double* X, float* Y, int t);
 Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* rowscale,
                    bool prefilled, int slot);
 Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled, int slot);

@@ -1,10 +1,11 @@
 """Mixed-precision form against the FP64 oracle: FP32 preconditioner solves
-(FP32 B values and blocks, FP64 row sums) inside the FP64 block PCG, whose
-FP64 operator and residual recurrence refine every FP32 solve, for blocks
-wider than 64 columns (narrower blocks keep the FP64 solves).  Probe and
-sample counts are chosen above 64 so that the FP32 solves run.  The bar: relative 1e-4 on the negative
-log-likelihood and 1e-3 on the predictive variances; the errors of the mode,
-the predictive means and the gradient are measured and printed."""
+(FP32 n x t blocks, FP64 row sums) inside the FP64 block PCG, whose FP64
+operator and residual recurrence refine every FP32 solve: level-scheduled
+with FP32 B values for blocks wider than 64 columns, the LDS head and
+sync-free tail with FP32 right-hand sides and results for narrower ones.
+Probe counts below and above 64 run both.  The bar: relative 1e-4 on the
+negative log-likelihood and 1e-3 on the predictive variances; the errors of
+the mode, the predictive means and the gradient are measured and printed."""
 import numpy as np
 import pytest
 
@@ -52,7 +53,8 @@ def test_mixed_against_fp64_oracle(P, case):
     g = P.VecchiaLaplace(dev(w["coords"]), w["m"], w["kind"], (w["sigma2"], w["rho"]),
                          want_deriv=True)
     mode, _ = g.find_mode(dev(w["y"]), dev(w["F"]), w["lik"], None, go)
-    # t <= 64 with the gradient (FP64 solves), then more than 64 probes (FP32)
+    # t <= 64 with the gradient (narrow FP32 solves), then more than 64 probes
+    # (level-scheduled FP32 solves)
     nll, grad, _ = g.neg_log_marglik(go, want_grad=True)
     nll_w, _, _ = g.neg_log_marglik(gw)
     mean, var, _ = g.predict(dev(w["coords_pred"]), dev(w["Fp"]), go)
@@ -67,7 +69,7 @@ def test_mixed_against_fp64_oracle(P, case):
     e_mode = rel_err(host(mode), b)
     e_mean = rel_err(host(mean), mean_o)
     e_grad = rel_err(np.array(grad), np.array(info["grad"]))
-    say(f"mixed {case}: rel err nll={e_nll:.2e} nll(t={tw}, FP32 solves)={e_nll_w:.2e} "
+    say(f"mixed {case}: rel err nll(t={w['t']})={e_nll:.2e} nll(t={tw})={e_nll_w:.2e} "
         f"var={e_var:.2e} mode={e_mode:.2e} mean={e_mean:.2e} grad={e_grad:.2e}")
     assert e_nll < NLL_TOL and e_nll_w < NLL_TOL
     assert e_var < VAR_TOL

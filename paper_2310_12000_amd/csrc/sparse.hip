@@ -575,15 +575,39 @@ __device__ __forceinline__ int64_t grab_stream(int* counters, int lane, int nstr
   return static_cast<int64_t>(s) + static_cast<int64_t>(nstreams) * v;
 }
 
+// In-order consumption of a window whose entries k < k0 are already taken:
+// applies acc -= v[k] y[k] while y[k] is ready and returns the first position
+// still waiting (W once the window is done).  Empty slots hold v = y = 0,
+// never the sentinel, and consumed entries are never reloaded, so the first
+// sentinel in the window is the first entry still missing.
+// A round in which no lane of the wave moves skips the updates.
+template <int W, typename TY>
+__device__ __forceinline__ int consume_window(const double* vb, const TY* yv, int k0,
+                                              double& acc) {
+  int fm = W;
+#pragma unroll
+  for (int k = W - 1; k >= 0; --k) fm = is_sentinel(yv[k]) ? k : fm;
+  if (__any(fm > k0)) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const double nx = acc - vb[k] * static_cast<double>(yv[k]);
+      acc = (k >= k0 && k < fm) ? nx : acc;
+    }
+  }
+  return fm;
+}
+
 // One row of a triangular solve, consumed in windows of W entries:
 //   Y_i = rs_i X_i - sum_q vals[q] Y_{idx[q]},  q in [q0, e) (idx < 0 ends the row).
-// A window's indices and values are loaded once; its Y entries are read first
-// through the caches (a cached copy can only be a stale sentinel, since every
-// entry changes once, from the sentinel to its final value) and then only the
-// still-missing ones are polled device-coherently.  Entries are consumed
-// strictly in order, so the sum order is fixed.  Rows r0..n-1 are solved,
-// taken in the topological order `order` (level by level) when given, else
-// ascending (lower) / descending (upper); rows below r0 must be final.
+// A window's coefficients and the byte offsets of its Y entries are loaded
+// once; its Y entries are read first through the caches (a cached copy can
+// only be a stale sentinel, since every entry changes once, from the sentinel
+// to its final value) and then only the still-missing ones are polled
+// device-coherently.  Entries are consumed strictly in order, so the sum
+// order is fixed.  Rows r0..n-1 are solved, taken in the topological order
+// `order` (level by level) when given, else ascending (lower) / descending
+// (upper); rows below r0 must be final.  The caller guarantees that every
+// byte offset n * t * sizeof(TY) fits in 32 bits.
 template <int W, bool LOWER, class In, typename TY = double>
 __global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m, int t, Lanes L,
                                                    const int* __restrict__ order,
@@ -596,6 +620,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m,
   const int lane = threadIdx.x & 63;
   const int64_t nt = n - r0;
   const int64_t total = units_of_hd(nt, t, L);
+  char* const ybase = reinterpret_cast<char*>(Y);
   for (;;) {
     const int64_t unit = grab_stream(counter, lane, nstreams);
     if (unit >= total) return;
@@ -625,7 +650,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m,
           pending = false;
         }
       }
-      int cb[W];
+      uint32_t bo[W];  // byte offset of each entry's Y value
       double vb[W];
       TY yv[W];
       int kk = W;  // cursor in the current window; W = no window loaded
@@ -634,27 +659,29 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m,
         bool progressed = false;
         if (pending) {
           if (kk == W) {
+            int jw[W];
 #pragma unroll
             for (int k = 0; k < W; ++k) {
-              const bool in = (q + k < e);
-              cb[k] = in ? idx[q + k] : -1;
-              vb[k] = in ? vals[q + k] : 0.0;
+              jw[k] = (q + k < e) ? idx[q + k] : -1;
+              vb[k] = (q + k < e) ? vals[q + k] : 0.0;  // 0 in padding slots
+              bo[k] = (static_cast<uint32_t>(jw[k]) * static_cast<uint32_t>(t) +
+                       static_cast<uint32_t>(c)) * static_cast<uint32_t>(sizeof(TY));
             }
 #pragma unroll
             for (int k = 0; k < W; ++k)
-              yv[k] = (cb[k] >= 0) ? Y[(int64_t)cb[k] * t + c] : TY(0);
+              yv[k] = (jw[k] >= 0) ? *reinterpret_cast<const TY*>(ybase + bo[k]) : TY(0);
             kk = 0;
           } else {
 #pragma unroll
             for (int k = 0; k < W; ++k)
-              if (k >= kk && cb[k] >= 0 && is_sentinel(yv[k]))
-                yv[k] = poll_load(&Y[(int64_t)cb[k] * t + c]);
+              if (is_sentinel(yv[k]))
+                yv[k] = poll_load(reinterpret_cast<const TY*>(ybase + bo[k]));
           }
-          const int fm = consume_ready<W>(cb, vb, yv, kk, acc);
+          const int fm = consume_window<W>(vb, yv, kk, acc);
           progressed = fm > kk;
           kk = fm;
           if (kk == W) {
-            if (q + W >= e) {  // slots past the row end are empty (-1)
+            if (q + W >= e) {  // slots past the row end are empty
               publish(&Y[i * t + c], static_cast<TY>(acc));
               pending = false;
             } else {
@@ -1086,6 +1113,45 @@ static bool use_levels(const Model& M, int t) {
   return (t > 64 || M.force_levels) && M.lvl_ptr_f.size() > 1;
 }
 
+// Window width of the sync-free tail solve: the row length rounded up to 8
+// (B's rows have m entries), capped at 32 (longer rows take several windows).
+static int tail_window(int len) {
+  return len <= 8 ? 8 : len <= 16 ? 16 : len <= 24 ? 24 : 32;
+}
+
+// Launch of the sync-free tail solve with window width W.
+template <bool LOWER, class In, typename TY>
+static Status launch_tail(Model& M, int W, int g, int64_t H, int t, Lanes L, const int* ord,
+                          const int* ptr, const int* idx, const double* val, In x,
+                          const double* rowscale, TY* Y, int ns, int* cnt) {
+  // Entries are addressed by 32-bit byte offsets into Y.
+  if (static_cast<uint64_t>(M.n) * static_cast<uint64_t>(t) * sizeof(TY) >= (1ull << 32))
+    return Status::invalid("triangular solve block larger than 4 GiB");
+  const int m = LOWER ? M.m : 0;
+#define VL_TAIL(WW)                                                                          \
+  hipLaunchKernelGGL((trsm_kernel<WW, LOWER, In, TY>), dim3(g), dim3(256), 0, M.stream, M.n, \
+                     H, m, t, L, ord, ptr, idx, val, x, rowscale, Y, ns, cnt,                \
+                     cnt + kAbortOffset, M.status)
+  switch (W) {
+    case 8: VL_TAIL(8); break;
+    case 16: VL_TAIL(16); break;
+    case 24: VL_TAIL(24); break;
+    default: VL_TAIL(32); break;
+  }
+#undef VL_TAIL
+  return check_launch(LOWER ? "trsm_b" : "trsm_bt");
+}
+
+// Window widths of the tail solve, measured at n = 1e5, m = 20: narrow blocks
+// (t <= 8, where every unit of the tail is resident at once) gain from fewer
+// windows per row, wider blocks from the occupancy of the 16-entry window
+// (179 VGPRs, two waves per SIMD, against one at 24 or 32 entries).
+static int lower_window(int m, int t) {
+  const int w = tail_window(m);
+  return (t <= 8 || w < 16) ? w : 16;
+}
+static int upper_window(int t) { return t <= 8 ? 32 : 16; }
+
 Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* rowscale,
                    bool prefilled, int slot) {
   if (M.bd_use) return bd_lower(M, X, Y, t, rowscale);
@@ -1102,26 +1168,9 @@ Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* ro
   TimedLaunch tl(M, kTimeTrsmLower,
                  12.0 * (M.nnz - (H ? M.nnz_head_f : 0)) + 16.0 * (M.n - H) * t +
                      (rowscale ? 8.0 * (M.n - H) : 0.0));
-  if (M.m <= 8) {
-    hipLaunchKernelGGL((trsm_kernel<8, true, InMem>), dim3(g), dim3(256), 0, M.stream, M.n, H,
-                       M.m, t, L, H ? M.tail_order_f.p : M.full_order_f.p, nullptr, M.nbr.p,
-                       M.bval.p, InMem{X, t},
-                       rowscale, Y, ns,
-                       cnt, cnt + kAbortOffset, M.status);
-  } else if (M.m <= 16) {
-    hipLaunchKernelGGL((trsm_kernel<16, true, InMem>), dim3(g), dim3(256), 0, M.stream, M.n, H,
-                       M.m, t, L, H ? M.tail_order_f.p : M.full_order_f.p, nullptr, M.nbr.p,
-                       M.bval.p, InMem{X, t},
-                       rowscale, Y, ns,
-                       cnt, cnt + kAbortOffset, M.status);
-  } else {
-    hipLaunchKernelGGL((trsm_kernel<32, true, InMem>), dim3(g), dim3(256), 0, M.stream, M.n, H,
-                       M.m, t, L, H ? M.tail_order_f.p : M.full_order_f.p, nullptr, M.nbr.p,
-                       M.bval.p, InMem{X, t},
-                       rowscale, Y, ns,
-                       cnt, cnt + kAbortOffset, M.status);
-  }
-  return check_launch("trsm_b");
+  return launch_tail<true>(M, lower_window(M.m, t), g, H, t, L,
+                           H ? M.tail_order_f.p : M.full_order_f.p, nullptr, M.nbr.p, M.bval.p,
+                           InMem{X, t}, rowscale, Y, ns, cnt);
 }
 
 Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled, int slot) {
@@ -1138,11 +1187,9 @@ Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled,
     TimedLaunch tl(M, kTimeTrsmUpper,
                    12.0 * (M.nnz - (H ? M.nnz_head_bt : 0)) + 4.0 * (M.n - H) +
                        16.0 * (M.n - H) * t);
-    hipLaunchKernelGGL((trsm_kernel<16, false, InMem>), dim3(g), dim3(256), 0, M.stream, M.n, H,
-                       0, t, L, H ? M.tail_order_b.p : M.full_order_b.p, M.bt_ptr.p,
-                       M.bt_col.p, M.bt_val.p,
-                       InMem{X, t}, nullptr, Y, ns, cnt, cnt + kAbortOffset, M.status);
-    VL_TRY(check_launch("trsm_bt"));
+    VL_TRY(launch_tail<false>(M, upper_window(t), g, H, t, L,
+                              H ? M.tail_order_b.p : M.full_order_b.p, M.bt_ptr.p, M.bt_col.p,
+                              M.bt_val.p, InMem{X, t}, nullptr, Y, ns, cnt));
   }
   if (H > 0) VL_TRY(head_upper(M, X, Y, t));
   return Status::ok();
@@ -1166,20 +1213,8 @@ Status trsm_b_f32_narrow(Model& M, const float* X, float* Y, int t, const double
                  12.0 * (M.nnz - (H ? M.nnz_head_f : 0)) + 8.0 * (M.n - H) * t +
                      (rowscale ? 8.0 * (M.n - H) : 0.0));
   const int* ord = H ? M.tail_order_f.p : M.full_order_f.p;
-  if (M.m <= 8) {
-    hipLaunchKernelGGL((trsm_kernel<8, true, InMemF, float>), dim3(g), dim3(256), 0, M.stream,
-                       M.n, H, M.m, t, L, ord, nullptr, M.nbr.p, M.bval.p, InMemF{X, t},
-                       rowscale, Y, ns, cnt, cnt + kAbortOffset, M.status);
-  } else if (M.m <= 16) {
-    hipLaunchKernelGGL((trsm_kernel<16, true, InMemF, float>), dim3(g), dim3(256), 0, M.stream,
-                       M.n, H, M.m, t, L, ord, nullptr, M.nbr.p, M.bval.p, InMemF{X, t},
-                       rowscale, Y, ns, cnt, cnt + kAbortOffset, M.status);
-  } else {
-    hipLaunchKernelGGL((trsm_kernel<32, true, InMemF, float>), dim3(g), dim3(256), 0, M.stream,
-                       M.n, H, M.m, t, L, ord, nullptr, M.nbr.p, M.bval.p, InMemF{X, t},
-                       rowscale, Y, ns, cnt, cnt + kAbortOffset, M.status);
-  }
-  return check_launch("trsm_b f32");
+  return launch_tail<true>(M, lower_window(M.m, t), g, H, t, L, ord, nullptr, M.nbr.p, M.bval.p,
+                           InMemF{X, t}, rowscale, Y, ns, cnt);
 }
 
 Status trsm_bt_f32_narrow(Model& M, const double* X, float* Y, int t) {
@@ -1195,11 +1230,9 @@ Status trsm_bt_f32_narrow(Model& M, const double* X, float* Y, int t) {
     TimedLaunch tl(M, kTimeTrsmUpper,
                    12.0 * (M.nnz - (H ? M.nnz_head_bt : 0)) + 4.0 * (M.n - H) +
                        12.0 * (M.n - H) * t);
-    hipLaunchKernelGGL((trsm_kernel<16, false, InMem, float>), dim3(g), dim3(256), 0, M.stream,
-                       M.n, H, 0, t, L, H ? M.tail_order_b.p : M.full_order_b.p, M.bt_ptr.p,
-                       M.bt_col.p, M.bt_val.p, InMem{X, t}, nullptr, Y, ns, cnt,
-                       cnt + kAbortOffset, M.status);
-    VL_TRY(check_launch("trsm_bt f32"));
+    VL_TRY(launch_tail<false>(M, upper_window(t), g, H, t, L,
+                              H ? M.tail_order_b.p : M.full_order_b.p, M.bt_ptr.p, M.bt_col.p,
+                              M.bt_val.p, InMem{X, t}, nullptr, Y, ns, cnt));
   }
   if (H > 0) VL_TRY(head_upper_f32(M, X, Y, t));
   return Status::ok();

@@ -448,7 +448,7 @@ static double apply_bytes(const Model& M, int t) {
 }
 
 Status dense_lower(Model& M, const double* X, double* Y, int t, const double* rs) {
-  TimedLaunch tl(M, kTimeHeadLower, apply_bytes(M, t));
+  TimedLaunch tl(M, kTimeDenseLower, apply_bytes(M, t));
   return launch_apply<true>(M, M.dense_gf.p, X, rs, Y, t);
 }
 
@@ -472,7 +472,7 @@ Status dense_upper(Model& M, double* Y, int t) {
 // FP32-storage forms for the mixed-precision narrow blocks (G, the sums and
 // the folded right-hand sides stay FP64).
 Status dense_lower_f32(Model& M, const float* X, float* Y, int t, const double* rs) {
-  TimedLaunch tl(M, kTimeHeadLower, apply_bytes(M, t) - 8.0 * M.dense_rows * t);
+  TimedLaunch tl(M, kTimeDenseLower, apply_bytes(M, t) - 8.0 * M.dense_rows * t);
   return launch_apply<true, float, float>(M, M.dense_gf.p, X, rs, Y, t);
 }
 
@@ -699,7 +699,7 @@ static Status bd_apply(Model& M, const double* X, double* Y, int t, const double
 }
 
 Status bd_lower(Model& M, const double* X, double* Y, int t, const double* rs) {
-  TimedLaunch tl(M, kTimeHeadLower, 16.0 * M.n * t);
+  TimedLaunch tl(M, kTimeDenseLower, 16.0 * M.n * t);
   return bd_apply<true>(M, X, Y, t, rs);
 }
 

@@ -1,22 +1,20 @@
-// Triangular solves with B over the "head" rows 0..H-1.
+// Backward triangular solves with B^T over the "head" rows 0..H-1.
 //
 // With a random ordering the dependency DAG of B is deep only among early
 // rows: for n = 1e5, m = 20 the first 16384 rows already span 214 of the 278
 // levels, while the remaining rows add only 68.  The first K rows are solved
-// with the dense inverse of B's leading block (dense.hip); rows K..H-1
-// (K = 4096, H = 12288 by default) are solved level by level inside one
-// workgroup per probe column, with the column's head values in LDS and no
-// barrier between levels (rows poll LDS); the data of later rows is
-// prefetched into registers while earlier ones are computed.  The tail rows
-// use the sync-free kernels (sparse.hip).
+// with the dense inverse of B's leading block (dense.hip).  Backward
+// (B^T Y = X), the tail rows are solved first (sparse.hip), then rows K..H-1
+// (K = 4096, H = 12288 by default) level by level inside one workgroup per
+// probe column, with the column's head values in LDS and no barrier between
+// levels (rows poll LDS), reading finished tail values from global memory;
+// then the dense block.  The early points' B^T rows are long (they are
+// neighbours of many later points), which is what the LDS head absorbs.
+// Forward (B Y = rs o X) needs no head: the dense block, then the sync-free
+// tail from row K.
 //
-// Forward (B Y = rs o X): the dense block first, then the head; every
-// dependency of a head row is a head row.  Backward (B^T Y = X): the tail
-// first, then the head rows K..H-1 read finished tail values from global
-// memory and head values from LDS, then the dense block.
-//
-// Level schedules (rows of the head grouped by level, separately for the two
-// directions) depend only on the neighbour sets and are built once.
+// Level schedules (rows of the head grouped by level, per direction) depend
+// only on the neighbour sets and are built once.
 #include <algorithm>
 #include <cstdlib>
 
@@ -122,91 +120,6 @@ __global__ __launch_bounds__(kHeadThreads) void head_sort_kernel(int H,
 }
 
 // ------------------------------------------------------------ head solves
-
-// One workgroup per column c = blockIdx.x.  The head values live in LDS,
-// pre-filled with the sentinel.  The level-ordered positions are cut into
-// batches of 64; wave w takes batches w, w + NT/64, ... and each lane one row
-// of the batch.  A position only depends on smaller positions, so the
-// smallest unfinished batch can always proceed and no barrier is needed: a
-// row polls LDS until each needed value differs from the sentinel.
-//
-// Global loads never sit on the critical path: the data of a batch is
-// fetched two batches ahead in two stages, first what depends only on the
-// position (row id, row length, position-ordered entries), one batch later
-// what depends on the row id (the right-hand side).  Results leave LDS only
-// at the end; a global store inside the polling loop would make every later
-// round wait for it.
-template <int W, int NT, typename TX = double, typename TY = double>
-__global__ __launch_bounds__(NT) void head_lower_kernel(
-    int H, int P, int K, int m, int t, const int* __restrict__ prow,
-    const int* __restrict__ pnbr, const double* __restrict__ pval, const TX* __restrict__ X,
-    const double* __restrict__ rs, TY* Y) {
-  extern __shared__ double s_y[];
-  const int c = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  constexpr int kWaves = NT / 64;
-  // rows below K are already solved in Y (the dense block); the P positions
-  // hold rows K..H-1
-  for (int i = tid; i < H; i += NT)
-    s_y[i] = i < K ? static_cast<double>(Y[(int64_t)i * t + c]) : sentinel();
-  __syncthreads();
-  int a_row = -1;            // stage A: row id, two batches ahead
-  int ni = -1, nj[W];        // stage B: one batch ahead
-  double nv[W], nx = 0.0;
-  auto stage_a = [&](int p) { a_row = (p < P) ? prow[p] : -1; };
-  auto stage_b = [&](int p, int row) {
-    ni = row;
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-      const bool in = (row >= 0) && (k < m);
-      nj[k] = in ? pnbr[(int64_t)p * m + k] : -1;
-      nv[k] = in ? pval[(int64_t)p * m + k] : 0.0;
-    }
-    nx = 0.0;
-    if (row >= 0) {
-      nx = static_cast<double>(X[(int64_t)row * t + c]);
-      if (rs) nx *= rs[row];
-    }
-  };
-  int batch = tid >> 6;
-  stage_a(batch * 64 + lane);
-  stage_b(batch * 64 + lane, a_row);
-  stage_a((batch + kWaves) * 64 + lane);
-  while (batch * 64 < P) {
-    const int ci = ni;
-    int cj[W];
-    double cv[W];
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-      cj[k] = nj[k];
-      cv[k] = nv[k];
-    }
-    double acc = nx;
-    const int row1 = a_row;
-    stage_b((batch + kWaves) * 64 + lane, row1);
-    stage_a((batch + 2 * kWaves) * 64 + lane);
-    bool pending = ci >= 0;
-    int kk = 0;
-    while (__any(pending)) {
-      if (pending) {
-        // all pending values first (independent LDS reads), then consume in order
-        double yv[W];
-#pragma unroll
-        for (int k = 0; k < W; ++k)
-          yv[k] = (k >= kk && cj[k] >= 0) ? lds_poll(&s_y[cj[k]]) : 0.0;
-        kk = consume_ready<W>(cj, cv, yv, kk, acc);
-        if (kk >= W) {
-          lds_publish(&s_y[ci], acc);
-          pending = false;
-        }
-      }
-    }
-    batch += kWaves;
-  }
-  __syncthreads();
-  for (int i = tid; i < H; i += NT) Y[(int64_t)i * t + c] = static_cast<TY>(s_y[i]);
-}
 
 // Upper: the right-hand side of head row j arrives in Y already reduced by its
 // tail dependents (head_upper_pre).  The head rows are cut into index ranges
@@ -399,33 +312,6 @@ __global__ void head_upper_pre_kernel(int H, int t, const int* __restrict__ spli
   Y[(int64_t)j * t + c] = static_cast<TY>(acc);
 }
 
-Status head_lower(Model& M, const double* X, double* Y, int t, const double* rs) {
-  const int H = M.head_rows;
-  if (H == 0) return Status::ok();
-  const int K = M.dense_rows, P = M.head_pos;
-  if (K > 0) VL_TRY(dense_lower(M, X, Y, t, rs));  // rows 0..K-1
-  if (P == 0) return Status::ok();
-  TimedLaunch tl(M, kTimeHeadLower,
-                 12.0 * M.nnz_head_f + 16.0 * H * t + (rs ? 8.0 * H : 0.0));
-  const size_t lds = sizeof(double) * H;
-  // two row windows (current and prefetched) stay in registers: 512 threads
-  // above 8 slots
-  if (M.m <= 8) {
-    hipLaunchKernelGGL((head_lower_kernel<8, 1024>), dim3(t), dim3(1024), lds, M.stream, H, P, K,
-                       M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
-  } else if (M.m <= 16) {
-    hipLaunchKernelGGL((head_lower_kernel<16, 512>), dim3(t), dim3(512), lds, M.stream, H, P, K,
-                       M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
-  } else if (M.m <= 24) {
-    hipLaunchKernelGGL((head_lower_kernel<24, 512>), dim3(t), dim3(512), lds, M.stream, H, P, K,
-                       M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
-  } else {
-    hipLaunchKernelGGL((head_lower_kernel<32, 512>), dim3(t), dim3(512), lds, M.stream, H, P, K,
-                       M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
-  }
-  return check_launch("head lower");
-}
-
 Status head_upper(Model& M, const double* X, double* Y, int t) {
   const int H = M.head_rows;
   if (H == 0) return Status::ok();
@@ -451,30 +337,6 @@ Status head_upper(Model& M, const double* X, double* Y, int t) {
 // FP32-storage forms of the head solves for the mixed-precision narrow
 // blocks: the same kernels with FP32 right-hand sides / results (LDS and
 // every sum stay FP64).
-Status head_lower_f32(Model& M, const float* X, float* Y, int t, const double* rs) {
-  const int H = M.head_rows;
-  if (H == 0) return Status::ok();
-  const int K = M.dense_rows, P = M.head_pos;
-  if (K > 0) VL_TRY(dense_lower_f32(M, X, Y, t, rs));  // rows 0..K-1
-  if (P == 0) return Status::ok();
-  TimedLaunch tl(M, kTimeHeadLower, 12.0 * M.nnz_head_f + 8.0 * H * t + (rs ? 8.0 * H : 0.0));
-  const size_t lds = sizeof(double) * H;
-  if (M.m <= 8) {
-    hipLaunchKernelGGL((head_lower_kernel<8, 1024, float, float>), dim3(t), dim3(1024), lds,
-                       M.stream, H, P, K, M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
-  } else if (M.m <= 16) {
-    hipLaunchKernelGGL((head_lower_kernel<16, 512, float, float>), dim3(t), dim3(512), lds,
-                       M.stream, H, P, K, M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
-  } else if (M.m <= 24) {
-    hipLaunchKernelGGL((head_lower_kernel<24, 512, float, float>), dim3(t), dim3(512), lds,
-                       M.stream, H, P, K, M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
-  } else {
-    hipLaunchKernelGGL((head_lower_kernel<32, 512, float, float>), dim3(t), dim3(512), lds,
-                       M.stream, H, P, K, M.m, t, M.hf_rows.p, M.hf_nbr.p, M.hf_val.p, X, rs, Y);
-  }
-  return check_launch("head lower f32");
-}
-
 Status head_upper_f32(Model& M, const double* X, float* Y, int t) {
   const int H = M.head_rows;
   if (H == 0) return Status::ok();
@@ -497,14 +359,7 @@ Status head_upper_f32(Model& M, const double* X, float* Y, int t) {
   return check_launch("head upper f32");
 }
 
-// ---- position-ordered copies of the head's rows of B and B^T
-__global__ void head_copy_fwd_kernel(int H, int m, const int* __restrict__ prow,
-                                     const int* __restrict__ nbr, int* __restrict__ pnbr) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= (int64_t)H * m) return;
-  const int p = static_cast<int>(e / m), k = static_cast<int>(e % m);
-  pnbr[e] = nbr[(int64_t)prow[p] * m + k];
-}
+// ---- position-ordered copies of the head's rows of B^T
 
 // Rows of B^T are sorted by column, so a head row's head-internal entries
 // (columns < H) form a prefix; split[j] is where its tail entries begin.
@@ -545,15 +400,9 @@ __global__ void head_copy_bwd_kernel(int H, const int* __restrict__ prow,
   }
 }
 
-__global__ void head_vals_kernel(int H, int m, const int* __restrict__ prow,
-                                 const double* __restrict__ bval, double* __restrict__ pval_f,
-                                 int nb, const int* __restrict__ psrc,
-                                 double* __restrict__ pval_b) {
+__global__ void head_vals_kernel(const double* __restrict__ bval, int nb,
+                                 const int* __restrict__ psrc, double* __restrict__ pval_b) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e < (int64_t)H * m) {
-    const int p = static_cast<int>(e / m), k = static_cast<int>(e % m);
-    pval_f[e] = bval[(int64_t)prow[p] * m + k];
-  }
   if (e < nb) pval_b[e] = bval[psrc[e]];
 }
 
@@ -577,11 +426,10 @@ __global__ void head_window_kernel(int H, const int* __restrict__ pptr,
 Status refresh_head_values(Model& M) {
   const int P = M.head_pos;
   if (M.head_rows == 0 || P == 0) return Status::ok();
-  const int64_t work = std::max<int64_t>((int64_t)P * M.m, M.head_nnz_b);
+  const int64_t work = M.head_nnz_b;
   if (work == 0) return Status::ok();
   hipLaunchKernelGGL(head_vals_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0,
-                     M.stream, P, M.m, M.hf_rows.p, M.bval.p, M.hf_val.p,
-                     static_cast<int>(M.head_nnz_b), M.hb_src.p, M.hb_val.p);
+                     M.stream, M.bval.p, static_cast<int>(M.head_nnz_b), M.hb_src.p, M.hb_val.p);
   hipLaunchKernelGGL(head_window_kernel, dim3((unsigned)(((int64_t)P * 16 + 255) / 256)),
                      dim3(256), 0, M.stream, P, M.hb_pptr.p, M.hb_split.p, M.hb_col.p,
                      M.hb_val.p, nullptr, M.hb_wval.p);
@@ -693,10 +541,6 @@ Status build_head_schedule(Model& M) {
   // in the process: always raise it to the largest head, so that a model
   // built later with a smaller head never lowers it under another's launches
   const size_t bytes = sizeof(double) * static_cast<size_t>(cap);
-  allow_lds(head_lower_kernel<8, 1024>, bytes);
-  allow_lds(head_lower_kernel<16, 512>, bytes);
-  allow_lds(head_lower_kernel<24, 512>, bytes);
-  allow_lds(head_lower_kernel<32, 512>, bytes);
   allow_lds(head_upper_kernel<512>, bytes);
   M.head_rows = static_cast<int>(H);
   if (M.dense_rows > H) M.dense_rows = static_cast<int>(H);
@@ -737,9 +581,6 @@ Status build_head_schedule(Model& M) {
     VL_TRY(sync_stream(M.stream));
     M.nnz_head_bt = bt_head;
     M.fold_nnz = static_cast<int64_t>(bt_head) - pp[H];
-    int64_t f = 0;  // row i < H has min(i, m) neighbours
-    for (int64_t i = 0; i < H; ++i) f += (i < m ? i : m);
-    M.nnz_head_f = f;
   }
   // ---- the wide B^T solves with the dense leading rows: head rows Kw..H-1
   // by their head-internal levels
@@ -770,19 +611,11 @@ Status build_head_schedule(Model& M) {
   } else {
     M.dense_wide = 0;
   }
-  // ---- the LDS head solves (t <= 64): rows K..H-1, P positions per direction
-  VL_TRY(M.hf_ptr.alloc(H + 1));
-  VL_TRY(M.hf_rows.alloc(H));
+  // ---- the LDS head solve of B^T (t <= 64): rows K..H-1 in P positions
   VL_TRY(M.hb_ptr.alloc(H + 1));
   VL_TRY(M.hb_rows.alloc(H));
-  VL_TRY(head_order(M, static_cast<int>(H), K, 0, M.hf_ptr.p, M.hf_rows.p, &M.head_nlev_f));
   VL_TRY(head_order(M, static_cast<int>(H), K, 1, M.hb_ptr.p, M.hb_rows.p, &M.head_nlev_b));
   // position-ordered copies (structure; values follow in refresh_head_values)
-  VL_TRY(M.hf_nbr.alloc((size_t)(P > 0 ? P : 1) * (m > 0 ? m : 1)));
-  VL_TRY(M.hf_val.alloc((size_t)(P > 0 ? P : 1) * (m > 0 ? m : 1)));
-  if ((int64_t)P * m > 0)
-    hipLaunchKernelGGL(head_copy_fwd_kernel, dim3((unsigned)(((int64_t)P * m + 255) / 256)),
-                       dim3(256), 0, M.stream, P, m, M.hf_rows.p, M.nbr.p, M.hf_nbr.p);
   DevBuf<int> len;
   VL_TRY(len.alloc(P + 1));
   VL_TRY(M.hb_pptr.alloc(P + 1));

@@ -1152,24 +1152,40 @@ static int lower_window(int m, int t) {
 }
 static int upper_window(int t) { return t <= 8 ? 32 : 16; }
 
+// First row of the forward sync-free tail for narrow blocks: the rows below
+// come from the dense block.  Forward, the tail starts there rather than at
+// the end of the LDS head the backward solve uses: at n = 1e5, m = 20 the
+// forward solve took 0.53 / 0.63 ms at t = 1 / 50 this way against 0.56 /
+// 0.69 ms through the LDS head, whose one workgroup per column walks the
+// head's levels no faster than the sync-free kernel does.
+static int64_t fwd_tail_start(const Model& M, int t) {
+  return head_of(M, t) > 0 ? M.dense_rows : 0;
+}
+
+// Entries of B's rows below r (row i has min(i, m) off-diagonal entries).
+static double nnz_below(const Model& M, int64_t r) {
+  const double m = M.m, rr = static_cast<double>(r);
+  return rr <= m ? rr * (rr - 1.0) / 2.0 : rr * m - m * (m + 1.0) / 2.0;
+}
+
 Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* rowscale,
                    bool prefilled, int slot) {
   if (M.bd_use) return bd_lower(M, X, Y, t, rowscale);
   if (use_levels(M, t)) return trsm_levels(M, true, X, Y, t, rowscale);
   if (!prefilled) VL_TRY(trsm_prepare(M, Y, M.n * (int64_t)t, slot));
-  const int64_t H = head_of(M, t);
-  if (H > 0) VL_TRY(head_lower(M, X, Y, t, rowscale));
-  if (H >= M.n) return Status::ok();
+  const int64_t R0 = fwd_tail_start(M, t);
+  if (R0 > 0) VL_TRY(dense_lower(M, X, Y, t, rowscale));
+  if (R0 >= M.n) return Status::ok();
   Lanes L = Lanes::of(t);
-  int g = trsm_grid(units_of(M.n - H, t));
+  int g = trsm_grid(units_of(M.n - R0, t));
   const int ns = trsm_streams(M, g);
   int* cnt = counter_slot(M, slot);
   PollingOrder order(M);
   TimedLaunch tl(M, kTimeTrsmLower,
-                 12.0 * (M.nnz - (H ? M.nnz_head_f : 0)) + 16.0 * (M.n - H) * t +
-                     (rowscale ? 8.0 * (M.n - H) : 0.0));
-  return launch_tail<true>(M, lower_window(M.m, t), g, H, t, L,
-                           H ? M.tail_order_f.p : M.full_order_f.p, nullptr, M.nbr.p, M.bval.p,
+                 12.0 * (M.nnz - nnz_below(M, R0)) + 16.0 * (M.n - R0) * t +
+                     (rowscale ? 8.0 * (M.n - R0) : 0.0));
+  return launch_tail<true>(M, lower_window(M.m, t), g, R0, t, L,
+                           R0 ? M.tail_order_f.p : M.full_order_f.p, nullptr, M.nbr.p, M.bval.p,
                            InMem{X, t}, rowscale, Y, ns, cnt);
 }
 
@@ -1201,19 +1217,19 @@ Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled,
 Status trsm_b_f32_narrow(Model& M, const float* X, float* Y, int t, const double* rowscale) {
   if (t > 64) return Status::invalid("narrow FP32 solve with more than 64 columns");
   VL_TRY(trsm_prepare(M, Y, M.n * (int64_t)t, 0));
-  const int64_t H = head_of(M, t);
-  if (H > 0) VL_TRY(head_lower_f32(M, X, Y, t, rowscale));
-  if (H >= M.n) return Status::ok();
+  const int64_t R0 = fwd_tail_start(M, t);
+  if (R0 > 0) VL_TRY(dense_lower_f32(M, X, Y, t, rowscale));
+  if (R0 >= M.n) return Status::ok();
   Lanes L = Lanes::of(t);
-  int g = trsm_grid(units_of(M.n - H, t));
+  int g = trsm_grid(units_of(M.n - R0, t));
   const int ns = trsm_streams(M, g);
   int* cnt = counter_slot(M, 0);
   PollingOrder order(M);
   TimedLaunch tl(M, kTimeTrsmLower,
-                 12.0 * (M.nnz - (H ? M.nnz_head_f : 0)) + 8.0 * (M.n - H) * t +
-                     (rowscale ? 8.0 * (M.n - H) : 0.0));
-  const int* ord = H ? M.tail_order_f.p : M.full_order_f.p;
-  return launch_tail<true>(M, lower_window(M.m, t), g, H, t, L, ord, nullptr, M.nbr.p, M.bval.p,
+                 12.0 * (M.nnz - nnz_below(M, R0)) + 8.0 * (M.n - R0) * t +
+                     (rowscale ? 8.0 * (M.n - R0) : 0.0));
+  return launch_tail<true>(M, lower_window(M.m, t), g, R0, t, L,
+                           R0 ? M.tail_order_f.p : M.full_order_f.p, nullptr, M.nbr.p, M.bval.p,
                            InMemF{X, t}, rowscale, Y, ns, cnt);
 }
 
@@ -1370,7 +1386,8 @@ __global__ void level_scatter_kernel(int64_t n, int64_t r0, const int* __restric
 
 Status build_tail_orders(Model& M) {
   const int64_t n = M.n, H = M.head_rows;
-  VL_TRY(M.tail_order_f.alloc(n - H > 0 ? n - H : 1));
+  const int64_t Hf = H > 0 ? M.dense_rows : 0;  // forward tail start (fwd_tail_start)
+  VL_TRY(M.tail_order_f.alloc(n - Hf > 0 ? n - Hf : 1));
   VL_TRY(M.tail_order_b.alloc(n - H > 0 ? n - H : 1));
   VL_TRY(M.full_order_f.alloc(n));
   VL_TRY(M.full_order_b.alloc(n));
@@ -1403,7 +1420,7 @@ Status build_tail_orders(Model& M) {
     VL_TRY(read_status(M));
     const int* spatial = static_cast<const int*>(M.grid_pts);
     for (int full = 0; full < 2; ++full) {
-      const int64_t r0 = full ? 0 : H;
+      const int64_t r0 = full ? 0 : (dir == 0 ? Hf : H);
       if (n - r0 <= 0) continue;
       int* out = full ? (dir == 0 ? M.full_order_f.p : M.full_order_b.p)
                       : (dir == 0 ? M.tail_order_f.p : M.tail_order_b.p);

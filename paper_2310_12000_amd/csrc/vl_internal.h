@@ -253,6 +253,7 @@ struct Model {
   std::vector<int> hb_blocks;                   // position ranges of the index ranges
   // tail rows in level order: forward rows >= dense_rows, backward rows >= head_rows
   DevBuf<int> tail_order_f, tail_order_b;
+  int tail_levels_f = 0, tail_levels_b = 0;  // dependency levels each tail order spans
   DevBuf<int> full_order_f, full_order_b;       // all rows in level order
   // level l of the full orders = positions [lvl_ptr[l], lvl_ptr[l + 1]); nnz
   // of the rows of each level (host copies, for the level-scheduled solves)

@@ -603,7 +603,8 @@ __device__ __forceinline__ int consume_window(const double* vb, const TY* yv, in
 // once; its Y entries are read first through the caches (a cached copy can
 // only be a stale sentinel, since every entry changes once, from the sentinel
 // to its final value) and then only the still-missing ones are polled
-// device-coherently.  Entries are consumed strictly in order, so the sum
+// device-coherently.  Entries are consumed in a fixed order (windows
+// ascending for B, descending for B^T; ascending inside a window), so the sum
 // order is fixed.  Rows r0..n-1 are solved, taken in the topological order
 // `order` (level by level) when given, else ascending (lower) / descending
 // (upper); rows below r0 must be final.  The caller guarantees that every
@@ -634,7 +635,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m,
       if (order && r < nt) i = order[r];
       bool pending = valid;
       double acc = 0.0;
-      int q = 0, e = 0;
+      int q = 0, e = 0, wb = 0;  // row entries [q, e); current window [wb, wb + W)
       if (valid) {
         acc = x(i, c);
         if (rs) acc *= rs[i];
@@ -645,6 +646,12 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m,
           q = ptr[i];
           e = ptr[i + 1];
         }
+        // Lower rows are consumed from their first window on.  B^T rows
+        // (children in ascending index) from their last window back: the
+        // latest children are solved first in the backward order, so the
+        // window that finishes a long row holds its slowest entries, and no
+        // window load follows the last arrival.
+        wb = LOWER ? q : e - W;
         if (q >= e) {
           publish(&Y[i * t + c], static_cast<TY>(acc));
           pending = false;
@@ -662,8 +669,9 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m,
             int jw[W];
 #pragma unroll
             for (int k = 0; k < W; ++k) {
-              jw[k] = (q + k < e) ? idx[q + k] : -1;
-              vb[k] = (q + k < e) ? vals[q + k] : 0.0;  // 0 in padding slots
+              const bool in = (wb + k >= q) && (wb + k < e);
+              jw[k] = in ? idx[wb + k] : -1;
+              vb[k] = in ? vals[wb + k] : 0.0;  // 0 in padding slots
               bo[k] = (static_cast<uint32_t>(jw[k]) * static_cast<uint32_t>(t) +
                        static_cast<uint32_t>(c)) * static_cast<uint32_t>(sizeof(TY));
             }
@@ -681,11 +689,11 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m,
           progressed = fm > kk;
           kk = fm;
           if (kk == W) {
-            if (q + W >= e) {  // slots past the row end are empty
+            if (LOWER ? (wb + W >= e) : (wb <= q)) {  // slots outside the row are empty
               publish(&Y[i * t + c], static_cast<TY>(acc));
               pending = false;
             } else {
-              q += W;  // window consumed: the next round loads the next one
+              wb += LOWER ? W : -W;  // window consumed: the next round loads the next one
             }
           }
         }

@@ -1144,7 +1144,7 @@ static bool use_levels(const Model& M, int t) {
 // Window width of the sync-free tail solve: the row length rounded up to 8
 // (B's rows have m entries), capped at 32 (longer rows take several windows).
 static int tail_window(int len) {
-  return len <= 8 ? 8 : len <= 16 ? 16 : len <= 24 ? 24 : 32;
+  return len <= 8 ? 8 : len <= 16 ? 16 : len <= 20 ? 20 : len <= 24 ? 24 : 32;
 }
 
 // Launch of the sync-free tail solve with window width W.
@@ -1163,6 +1163,7 @@ static Status launch_tail(Model& M, int W, int g, int64_t H, int t, Lanes L, con
   switch (W) {
     case 8: VL_TAIL(8); break;
     case 16: VL_TAIL(16); break;
+    case 20: VL_TAIL(20); break;
     case 24: VL_TAIL(24); break;
     default: VL_TAIL(32); break;
   }
@@ -1170,15 +1171,18 @@ static Status launch_tail(Model& M, int W, int g, int64_t H, int t, Lanes L, con
   return check_launch(LOWER ? "trsm_b" : "trsm_bt");
 }
 
-// Window widths of the tail solve, measured at n = 1e5, m = 20: narrow blocks
-// (t <= 8, where every unit of the tail is resident at once) gain from fewer
-// windows per row, wider blocks from the occupancy of the 16-entry window
-// (179 VGPRs, two waves per SIMD, against one at 24 or 32 entries).
+// Window widths of the tail solve, measured at n = 1e5, m = 20.  Forward,
+// narrow blocks (t <= 8) take the whole row in one window (t = 1: 0.39 ms at
+// 20 entries, 0.40 at 24, against 0.52 at 16 before the grid sizing), wider
+// blocks the occupancy of the 16-entry window (178 VGPRs, two waves per SIMD,
+// against one at 20 entries or more).  Backward rows are consumed from their
+// last window, so later windows cost no round after the last arrival: 16
+// entries at every width (t = 1: 0.56 ms, against 0.61 at 32).
 static int lower_window(int m, int t) {
   const int w = tail_window(m);
   return (t <= 8 || w < 16) ? w : 16;
 }
-static int upper_window(int t) { return t <= 8 ? 32 : 16; }
+static int upper_window(int) { return 16; }
 
 // First row of the forward sync-free tail for narrow blocks: the rows below
 // come from the dense block.  Forward, the tail starts there rather than at

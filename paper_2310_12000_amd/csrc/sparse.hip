@@ -646,12 +646,13 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t n, int64_t r0, int m,
           q = ptr[i];
           e = ptr[i + 1];
         }
-        // Lower rows are consumed from their first window on.  B^T rows
-        // (children in ascending index) from their last window back: the
-        // latest children are solved first in the backward order, so the
-        // window that finishes a long row holds its slowest entries, and no
-        // window load follows the last arrival.
-        wb = LOWER ? q : e - W;
+        // The last window consumed is a full one: a row's slowest entry is
+        // then likely in it, and no window load follows the last arrival.
+        // Lower rows run forward with the remainder in the first window (sum
+        // order unchanged).  B^T rows (children in ascending index) run from
+        // their last window back: the latest children are solved first in
+        // the backward order, so the last window holds the slowest entries.
+        wb = LOWER ? e - W * ((e - q + W - 1) / W) : e - W;
         if (q >= e) {
           publish(&Y[i * t + c], static_cast<TY>(acc));
           pending = false;

@@ -21,11 +21,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Laplace marginal-likelihood evals/s at n=1e5,m=20; B-SpMM HBM GB/s; p99 latency"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-KINDS = ("spmm_b", "spmm_bt", "trsm_lower", "trsm_upper", "dense_lower", "head_upper",
+KINDS = ("spmm_b", "spmm_bt", "trsm_lower", "trsm_upper", "dense_lower", "dense_upper",
          "level_lower", "level_upper", "level_upper_split", "level_upper_fold", "dense_wide")
 KERNEL_NAMES = {"spmm_b": "spmm_ell_kernel", "spmm_bt": "spmm_csr_t_kernel",
                 "trsm_lower": "trsm_kernel<lower>", "trsm_upper": "trsm_kernel<upper>",
-                "dense_lower": "dense_part_kernel", "head_upper": "head_upper_kernel",
+                "dense_lower": "dense_part_kernel", "dense_upper": "dense_fold_kernel",
                 "level_lower": "trsm_level_lower_kernel",
                 "level_upper": "trsm_level_upper_kernel",
                 "level_upper_split": "trsm_level_split_kernel",

@@ -394,10 +394,9 @@ vl_status vl_trsm_noalloc(vl_model* h, int transpose, const double* X, double* Y
  * written once, per-row vectors) are accumulated.  `kind`:
  *   0  Y = B X (B in ELL)                 1  Y = B^T X (B^T in CSR)
  *   2  sync-free rows of B Y = X          3  sync-free rows of B^T Y = X
- *   4  leading rows of B Y = X            5  head rows of B^T Y = X
- *      (4: the dense product with the inverse of B's leading block;
- *      5: that product and the LDS solve of the remaining head rows, one
- *      record each)
+ *   4  leading rows of B Y = X            5  leading rows of B^T Y = X
+ *      (4-5: the dense products with the inverse of B's leading block, or
+ *      with each problem's inverse in a batch)
  *   6  level-scheduled B Y = X            7  level-scheduled B^T Y = X
  *   8  level-scheduled B^T Y = X, levels of long rows (entries split over
  *      4 waves per row)
@@ -424,7 +423,7 @@ vl_status vl_timing_read(vl_model* h, int kind, double* total_ms, int64_t* launc
  * reductions add its rows in the order of a solo run (vl_build_vecchia +
  * vl_find_mode + vl_neg_log_marglik on that problem alone gives the same
  * result up to the rounding of the B^T solve).  The solve path of the packed
- * system (sync-free rows with the backward LDS head, or one launch per level) is chosen per
+ * system (sync-free rows, or one launch per level) is chosen per
  * block-width class by timing both on the packed system (autotuner). */
 typedef struct vl_batch vl_batch;
 
@@ -464,7 +463,7 @@ vl_status vl_batch_mode(vl_batch* b, int p, double* mode_out);
 vl_status vl_batch_stats(vl_batch* b, int p, vl_stats* st);
 
 /* Solve path the autotuner picked for a width class (0: one column, 1: 2..64,
- * 2: more), 0 = sync-free rows (LDS head backward), 1 = one launch per level, 2 = each
+ * 2: more), 0 = sync-free rows, 1 = one launch per level, 2 = each
  * problem's factor inverted whole and applied as a dense product (offered
  * when every problem has at most 4096 locations and the inverses take at
  * most 8 GB); -1 if that class was not used yet. */

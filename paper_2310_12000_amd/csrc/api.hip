@@ -30,7 +30,8 @@ __global__ void recip_kernel(int64_t n, const double* __restrict__ d, double* __
   if (i < n) out[i] = 1.0 / d[i];
 }
 
-// D^{-1} and the copies of the B values (B^T, head, FP32) after a factor.
+// D^{-1}, the copies of the B values (B^T, groups) and the dense inverse
+// after a factor.
 Status finish_factor(Model& M) {
   const int64_t n = M.n;
   const int tb = 256;
@@ -39,7 +40,6 @@ Status finish_factor(Model& M) {
   VL_TRY(check_launch("recip"));
   VL_TRY(refresh_transpose_values(M));
   VL_TRY(refresh_group_values(M));
-  VL_TRY(refresh_head_values(M));
   VL_TRY(dense_factor(M));
   ++M.factor_version;
   VL_TRY(sync_stream(M.stream));

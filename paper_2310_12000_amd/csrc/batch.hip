@@ -6,8 +6,8 @@
 // system; its neighbour sets stay inside its own rows (the Vecchia factor of
 // the batch is block diagonal), stored as ELL of width max_p m_p padded with
 // -1.  Neighbour search and the neighbour Cholesky run per problem on the
-// problem's own points; the packed model then builds B^T, the level
-// schedules and the LDS head once for all rows.
+// problem's own points; the packed model then builds B^T and the level
+// schedules once for all rows.
 //
 // Segmented CG.  Each problem's rows are cut into the row chunks a solo run
 // of that problem would use; a work item is (row chunk of a problem, probe
@@ -255,7 +255,7 @@ struct Batch {
 
 // ------------------------------------------------------------- autotuning
 // The tile choice of the packed system's triangular solves, per width class
-// (t = 1, 2..64, > 64): the LDS head with the sync-free tail, one launch per
+// (t = 1, 2..64, > 64): the sync-free rows, one launch per
 // level, or (when every problem is small enough) each problem's B inverted
 // whole and applied as a dense product.  Candidates are timed on the packed
 // system itself (one B^{-T} and one B^{-1} solve each, after one untimed

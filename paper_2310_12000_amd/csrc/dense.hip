@@ -8,10 +8,11 @@
 // most of the dependency depth of the head: at n = 1e5, m = 20 the first
 // 16384 rows span 214 levels, the rows 2048..16383 on their own 71 and the
 // rows 4096..16383 49.  Taking the first K = 4096 rows out of the
-// latency-bound LDS head solve and applying G instead (67 MB of FP64 per
-// application, read at bandwidth by the whole chip) took the t = 1 head
-// solves from 488 / 915 us to 298 / 321 us (forward / backward); K = 2048
-// gave 320 / 462 us.
+// latency-bound level-by-level solve and applying G instead (67 MB of FP64
+// per application, read at bandwidth by the whole chip) took the t = 1 head
+// solves of the time (an LDS solve of rows below 16384) from 488 / 915 us to
+// 298 / 321 us (forward / backward); K = 2048 gave 320 / 462 us.  Narrow
+// blocks now take every row from K on in the sync-free tail.
 //
 // G is computed once per factor (Sec. 2.1: B changes with the covariance
 // parameters) by forward substitution of B_KK G = I, column by column, and
@@ -315,17 +316,16 @@ __global__ __launch_bounds__(R * 4) void dense_gemm_kernel(int Kd, int lda, int 
       }
 }
 
-// xp[j, c] = base[j, c] - sum of the B^T entries of row j < K whose child
-// lies in K..H-1 (entries [lo[j], split[j]): children sorted ascending, those
-// from H on were subtracted from base before the head solve), with the
+// xp[j, c] = base[j, c] - sum of the B^T entries of row j < K whose child is
+// K or later (entries [lo[j], end[j]), end = the row ends), with the
 // children's values from Y.  One wave per row, lanes over entries, a fixed
 // butterfly per column.
-template <typename TY = double>
+template <typename TB, typename TY>
 __global__ __launch_bounds__(256) void dense_fold_kernel(int K, int t, const int* __restrict__ lo,
                                                          const int* __restrict__ split,
                                                          const int* __restrict__ bt_col,
                                                          const double* __restrict__ bt_val,
-                                                         const TY* __restrict__ base,
+                                                         const TB* __restrict__ base,
                                                          const TY* __restrict__ Y,
                                                          double* __restrict__ xp) {
   const int lane = threadIdx.x & 63;
@@ -452,9 +452,9 @@ Status dense_lower(Model& M, const double* X, double* Y, int t, const double* rs
   return launch_apply<true>(M, M.dense_gf.p, X, rs, Y, t);
 }
 
-Status dense_upper(Model& M, double* Y, int t) {
+Status dense_upper(Model& M, const double* X, double* Y, int t) {
   const int K = M.dense_rows;
-  TimedLaunch tl(M, kTimeHeadUpper, apply_bytes(M, t));
+  TimedLaunch tl(M, kTimeDenseUpper, apply_bytes(M, t));
   const size_t need = static_cast<size_t>(K) * t;
   double* xp = nullptr;
   if (M.ext) {
@@ -464,8 +464,9 @@ Status dense_upper(Model& M, double* Y, int t) {
     VL_TRY(M.dense_xp.reserve(need));
     xp = M.dense_xp.p;
   }
-  hipLaunchKernelGGL(dense_fold_kernel<double>, dim3((K + 3) / 4), dim3(256), 0, M.stream, K, t,
-                     M.dense_lo.p, M.head_split.p, M.bt_col.p, M.bt_val.p, Y, Y, xp);
+  hipLaunchKernelGGL((dense_fold_kernel<double, double>), dim3((K + 3) / 4), dim3(256), 0,
+                     M.stream, K, t, M.dense_lo.p, M.bt_ptr.p + 1, M.bt_col.p, M.bt_val.p, X, Y,
+                     xp);
   return launch_apply<false>(M, M.dense_gb.p, xp, nullptr, Y, t);
 }
 
@@ -476,12 +477,13 @@ Status dense_lower_f32(Model& M, const float* X, float* Y, int t, const double* 
   return launch_apply<true, float, float>(M, M.dense_gf.p, X, rs, Y, t);
 }
 
-Status dense_upper_f32(Model& M, float* Y, int t) {
+Status dense_upper_f32(Model& M, const double* X, float* Y, int t) {
   const int K = M.dense_rows;
-  TimedLaunch tl(M, kTimeHeadUpper, apply_bytes(M, t) - 8.0 * K * t);
+  TimedLaunch tl(M, kTimeDenseUpper, apply_bytes(M, t) - 4.0 * K * t);
   VL_TRY(M.dense_xp.reserve(static_cast<size_t>(K) * t));
-  hipLaunchKernelGGL(dense_fold_kernel<float>, dim3((K + 3) / 4), dim3(256), 0, M.stream, K, t,
-                     M.dense_lo.p, M.head_split.p, M.bt_col.p, M.bt_val.p, Y, Y, M.dense_xp.p);
+  hipLaunchKernelGGL((dense_fold_kernel<double, float>), dim3((K + 3) / 4), dim3(256), 0,
+                     M.stream, K, t, M.dense_lo.p, M.bt_ptr.p + 1, M.bt_col.p, M.bt_val.p, X, Y,
+                     M.dense_xp.p);
   return launch_apply<false, double, float>(M, M.dense_gb.p, M.dense_xp.p, nullptr, Y, t);
 }
 
@@ -704,7 +706,7 @@ Status bd_lower(Model& M, const double* X, double* Y, int t, const double* rs) {
 }
 
 Status bd_upper(Model& M, const double* X, double* Y, int t) {
-  TimedLaunch tl(M, kTimeHeadUpper, 16.0 * M.n * t);
+  TimedLaunch tl(M, kTimeDenseUpper, 16.0 * M.n * t);
   return bd_apply<false>(M, X, Y, t, nullptr);
 }
 

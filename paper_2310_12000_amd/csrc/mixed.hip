@@ -14,8 +14,8 @@
 // between the tail and the head levels; the leading rows covered by the
 // dense inverse G come from its FP64 GEMM, which reads and writes the FP32
 // blocks.  Narrower blocks run the FP64 path's kernels (dense leading block,
-// LDS head, sync-free tail) with FP32 right-hand sides and results: FP64 B
-// values, G and LDS, FP64 sums.
+// sync-free tail) with FP32 right-hand sides and results: FP64 B values and
+// G, FP64 sums.
 #include <algorithm>
 #include <cmath>
 
@@ -340,7 +340,7 @@ Status precond_f32_deviation(Model& M, const double* sdiag, const double* X, int
 CgOps vadu_ops_mixed(const double* W, const double* sdiag) {
   CgOps ops = vadu_ops(W, sdiag);  // the FP64 operator
   // FP32 solves at every width: wide blocks level-scheduled with FP32 B
-  // values; narrow blocks (t <= 64) through the LDS head and sync-free tail
+  // values; narrow blocks (t <= 64) through the dense block and sync-free tail
   // with FP32 right-hand sides and results, which fill their own FP32
   // outputs with the sentinel (the FP64 blocks need no fill).
   ops.precond = [sdiag](Model& M, const double* R, double* Z, double* Y, int t) -> Status {

@@ -1130,14 +1130,10 @@ static Status trsm_prepare(Model& M, TY* Y, int64_t count, int slot) {
   return check_launch("trsm prefill");
 }
 
-// Head rows are used for t <= 64 (one workgroup per column).
-// Head rows (solved in LDS) for t <= 64; wider blocks are bandwidth-bound
-// and use the sync-free kernels for all rows.
-static int64_t head_of(const Model& M, int t) { return t <= 64 ? M.head_rows : 0; }
-
 // Blocks wider than 64 columns have ample parallelism inside each level and
 // are bandwidth-bound: they take the level-scheduled path (no sentinel fill,
-// no polling).  Narrower blocks take the LDS head and the sync-free tail.
+// no polling).  Narrower blocks take the dense leading block and the
+// sync-free tail.
 static bool use_levels(const Model& M, int t) {
   return (t > 64 || M.force_levels) && M.lvl_ptr_f.size() > 1;
 }
@@ -1185,15 +1181,15 @@ static int lower_window(int m, int t) {
 }
 static int upper_window(int) { return 16; }
 
-// First row of the forward sync-free tail for narrow blocks: the rows below
-// come from the dense block.  Forward, the tail starts there rather than at
-// the end of the LDS head the backward solve uses: at n = 1e5, m = 20 the
-// forward solve took 0.53 / 0.63 ms at t = 1 / 50 this way against 0.56 /
-// 0.69 ms through the LDS head, whose one workgroup per column walks the
-// head's levels no faster than the sync-free kernel does.
-static int64_t fwd_tail_start(const Model& M, int t) {
-  return head_of(M, t) > 0 ? M.dense_rows : 0;
-}
+// First row of the sync-free tail for narrow blocks, in both directions: the
+// rows below come from the dense block.  An LDS head for the rows between
+// (one workgroup per column walking their levels in shared memory) was
+// measured and removed: it walks a level no faster than the sync-free kernel
+// does.  At n = 1e5, m = 20 the forward solve took 0.53 / 0.63 ms at t = 1 / 50
+// without it against 0.56 / 0.69 ms with it, and after the backward kernel's
+// window changes a backward head of 12288 rows cost 11 ms of mode and 16 ms of
+// likelihood per evaluation against none.
+static int64_t narrow_tail_start(const Model& M, int t) { return t <= 64 ? M.dense_rows : 0; }
 
 // Entries of B's rows below r (row i has min(i, m) off-diagonal entries).
 static double nnz_below(const Model& M, int64_t r) {
@@ -1206,7 +1202,7 @@ Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* ro
   if (M.bd_use) return bd_lower(M, X, Y, t, rowscale);
   if (use_levels(M, t)) return trsm_levels(M, true, X, Y, t, rowscale);
   if (!prefilled) VL_TRY(trsm_prepare(M, Y, M.n * (int64_t)t, slot));
-  const int64_t R0 = fwd_tail_start(M, t);
+  const int64_t R0 = narrow_tail_start(M, t);
   if (R0 > 0) VL_TRY(dense_lower(M, X, Y, t, rowscale));
   if (R0 >= M.n) return Status::ok();
   Lanes L = Lanes::of(t);
@@ -1226,21 +1222,21 @@ Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled,
   if (M.bd_use) return bd_upper(M, X, Y, t);
   if (use_levels(M, t)) return trsm_levels(M, false, X, Y, t, nullptr);
   if (!prefilled) VL_TRY(trsm_prepare(M, Y, M.n * (int64_t)t, slot));
-  const int64_t H = head_of(M, t);
-  if (H < M.n) {
+  const int64_t R0 = narrow_tail_start(M, t);  // the backward tail ends at the same row
+  if (R0 < M.n) {
     Lanes L = Lanes::of(t);
-    int g = tail_grid(units_of(M.n - H, t), H ? M.tail_levels_b : levels_of(M.lvl_ptr_b));
+    int g = tail_grid(units_of(M.n - R0, t), R0 ? M.tail_levels_b : levels_of(M.lvl_ptr_b));
     const int ns = trsm_streams(M, g);
     int* cnt = counter_slot(M, slot);
     PollingOrder order(M);
     TimedLaunch tl(M, kTimeTrsmUpper,
-                   12.0 * (M.nnz - (H ? M.nnz_head_bt : 0)) + 4.0 * (M.n - H) +
-                       16.0 * (M.n - H) * t);
-    VL_TRY(launch_tail<false>(M, upper_window(t), g, H, t, L,
-                              H ? M.tail_order_b.p : M.full_order_b.p, M.bt_ptr.p, M.bt_col.p,
+                   12.0 * (M.nnz - nnz_below(M, R0)) + 4.0 * (M.n - R0) +
+                       16.0 * (M.n - R0) * t);
+    VL_TRY(launch_tail<false>(M, upper_window(t), g, R0, t, L,
+                              R0 ? M.tail_order_bn.p : M.full_order_b.p, M.bt_ptr.p, M.bt_col.p,
                               M.bt_val.p, InMem{X, t}, nullptr, Y, ns, cnt));
   }
-  if (H > 0) VL_TRY(head_upper(M, X, Y, t));
+  if (R0 > 0) VL_TRY(dense_upper(M, X, Y, t));  // rows 0..K-1, after every later row
   return Status::ok();
 }
 
@@ -1250,7 +1246,7 @@ Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled,
 Status trsm_b_f32_narrow(Model& M, const float* X, float* Y, int t, const double* rowscale) {
   if (t > 64) return Status::invalid("narrow FP32 solve with more than 64 columns");
   VL_TRY(trsm_prepare(M, Y, M.n * (int64_t)t, 0));
-  const int64_t R0 = fwd_tail_start(M, t);
+  const int64_t R0 = narrow_tail_start(M, t);
   if (R0 > 0) VL_TRY(dense_lower_f32(M, X, Y, t, rowscale));
   if (R0 >= M.n) return Status::ok();
   Lanes L = Lanes::of(t);
@@ -1269,21 +1265,21 @@ Status trsm_b_f32_narrow(Model& M, const float* X, float* Y, int t, const double
 Status trsm_bt_f32_narrow(Model& M, const double* X, float* Y, int t) {
   if (t > 64) return Status::invalid("narrow FP32 solve with more than 64 columns");
   VL_TRY(trsm_prepare(M, Y, M.n * (int64_t)t, 0));
-  const int64_t H = head_of(M, t);
-  if (H < M.n) {
+  const int64_t R0 = narrow_tail_start(M, t);
+  if (R0 < M.n) {
     Lanes L = Lanes::of(t);
-    int g = tail_grid(units_of(M.n - H, t), H ? M.tail_levels_b : levels_of(M.lvl_ptr_b));
+    int g = tail_grid(units_of(M.n - R0, t), R0 ? M.tail_levels_b : levels_of(M.lvl_ptr_b));
     const int ns = trsm_streams(M, g);
     int* cnt = counter_slot(M, 0);
     PollingOrder order(M);
     TimedLaunch tl(M, kTimeTrsmUpper,
-                   12.0 * (M.nnz - (H ? M.nnz_head_bt : 0)) + 4.0 * (M.n - H) +
-                       12.0 * (M.n - H) * t);
-    VL_TRY(launch_tail<false>(M, upper_window(t), g, H, t, L,
-                              H ? M.tail_order_b.p : M.full_order_b.p, M.bt_ptr.p, M.bt_col.p,
+                   12.0 * (M.nnz - nnz_below(M, R0)) + 4.0 * (M.n - R0) +
+                       12.0 * (M.n - R0) * t);
+    VL_TRY(launch_tail<false>(M, upper_window(t), g, R0, t, L,
+                              R0 ? M.tail_order_bn.p : M.full_order_b.p, M.bt_ptr.p, M.bt_col.p,
                               M.bt_val.p, InMem{X, t}, nullptr, Y, ns, cnt));
   }
-  if (H > 0) VL_TRY(head_upper_f32(M, X, Y, t));
+  if (R0 > 0) VL_TRY(dense_upper_f32(M, X, Y, t));
   return Status::ok();
 }
 
@@ -1419,8 +1415,9 @@ __global__ void level_scatter_kernel(int64_t n, int64_t r0, const int* __restric
 
 Status build_tail_orders(Model& M) {
   const int64_t n = M.n, H = M.head_rows;
-  const int64_t Hf = H > 0 ? M.dense_rows : 0;  // forward tail start (fwd_tail_start)
-  VL_TRY(M.tail_order_f.alloc(n - Hf > 0 ? n - Hf : 1));
+  const int64_t K = H > 0 ? M.dense_rows : 0;  // start of the narrow tails (narrow_tail_start)
+  VL_TRY(M.tail_order_f.alloc(n - K > 0 ? n - K : 1));
+  VL_TRY(M.tail_order_bn.alloc(n - K > 0 ? n - K : 1));
   VL_TRY(M.tail_order_b.alloc(n - H > 0 ? n - H : 1));
   VL_TRY(M.full_order_f.alloc(n));
   VL_TRY(M.full_order_b.alloc(n));
@@ -1452,11 +1449,16 @@ Status build_tail_orders(Model& M) {
     VL_TRY(check_launch("levels"));
     VL_TRY(read_status(M));
     const int* spatial = static_cast<const int*>(M.grid_pts);
-    for (int full = 0; full < 2; ++full) {
-      const int64_t r0 = full ? 0 : (dir == 0 ? Hf : H);
+    // per direction: the narrow blocks' tail (rows >= K), the wide backward
+    // solve's tail (rows >= H), the full order
+    for (int kind = 0; kind < 3; ++kind) {
+      if (kind == 1 && dir == 0) continue;
+      const bool full = kind == 2;
+      const int64_t r0 = kind == 0 ? K : kind == 1 ? H : 0;
       if (n - r0 <= 0) continue;
       int* out = full ? (dir == 0 ? M.full_order_f.p : M.full_order_b.p)
-                      : (dir == 0 ? M.tail_order_f.p : M.tail_order_b.p);
+                 : kind == 0 ? (dir == 0 ? M.tail_order_f.p : M.tail_order_bn.p)
+                             : M.tail_order_b.p;
       VL_TRY(fill_int(cnt.p, 0, n + 1, M.stream));
       hipLaunchKernelGGL(level_count_kernel, dim3(gn), dim3(tb), 0, M.stream, n, r0, spatial,
                          lev.p, cnt.p);
@@ -1465,7 +1467,7 @@ Status build_tail_orders(Model& M) {
       hipLaunchKernelGGL(level_scatter_kernel, dim3(gn), dim3(tb), 0, M.stream, n, r0, spatial,
                          lev.p, start.p, cnt.p, out);
       VL_TRY(check_launch("level order"));
-      if (!full) {  // dependency levels the tail order spans (sizes its grid)
+      if (kind == 0) {  // dependency levels the narrow tail order spans (sizes its grid)
         std::vector<int> st(n + 1);
         VL_HIP(hipMemcpyAsync(st.data(), start.p, sizeof(int) * (n + 1), hipMemcpyDeviceToHost,
                               M.stream));
@@ -1475,8 +1477,8 @@ Status build_tail_orders(Model& M) {
         (dir == 0 ? M.tail_levels_f : M.tail_levels_b) = levels;
       }
       // level pointers and per-level nnz, to the host: of the full orders
-      // (both directions) and of the backward tail order
-      if (full || dir == 1) {
+      // (both directions) and of the wide backward tail order
+      if (kind != 0) {
         const int64_t cnt_rows = n - r0;
         std::vector<int> st(n + 1);
         VL_HIP(hipMemcpyAsync(st.data(), start.p, sizeof(int) * (n + 1), hipMemcpyDeviceToHost,

@@ -157,8 +157,8 @@ enum TimedKind : int {
   kTimeSpmmBt = 1,    // Y = B^T X (CSR)
   kTimeTrsmLower = 2, // sync-free rows of B Y = X
   kTimeTrsmUpper = 3, // sync-free rows of B^T Y = X
-  kTimeDenseLower = 4, // dense leading rows of B Y = X
-  kTimeHeadUpper = 5, // LDS head rows of B^T Y = X
+  kTimeDenseLower = 4, // dense products of B Y = X (leading block, per-problem inverses)
+  kTimeDenseUpper = 5, // dense products of B^T Y = X (leading block, per-problem inverses)
   kTimeLevelLower = 6, // level-scheduled rows of B Y = X (wide blocks)
   kTimeLevelUpper = 7, // level-scheduled rows of B^T Y = X (wide blocks)
   kTimeLevelUpperSplit = 8, // the same for levels of long B^T rows
@@ -211,11 +211,12 @@ struct Model {
   int64_t factor_version = 0, f32_version = -1;  // FP32 copies made at factor_version
   bool force_levels = false;  // level-scheduled solves for every block width (autotuner)
 
-  // head rows of the backward solve, in LDS: rows dense_rows..head_rows-1 in
-  // head_pos positions; the rows below dense_rows are solved with the dense
-  // inverse of B's leading block (dense.hip) in both directions
-  int head_rows = 0, head_nlev_b = 0;
-  int dense_rows = 0, head_pos = 0;
+  // head rows 0..head_rows-1: the wide blocks' B^T solve takes them after the
+  // tail (level schedules below); the rows below dense_rows are solved with
+  // the dense inverse of B's leading block (dense.hip), in both directions and
+  // at every width (dense_wide of them for wide blocks)
+  int head_rows = 0;
+  int dense_rows = 0;
   DevBuf<double> dense_gf, dense_gb;  // G = B_KK^{-1}: column-major, row-major
   DevBuf<double> dense_xp;            // K x t folded right-hand sides of B^T solves
   DevBuf<double> dense_part;          // partial products of the dense applications
@@ -243,17 +244,11 @@ struct Model {
   DevBuf<double> bd_gf, bd_gb, bd_part;
   const int* bd_row_prob = nullptr;           // packed row -> problem
   const int* bd_row_local = nullptr;          // packed row -> row in its problem
-  int64_t head_nnz_b = 0;
-  DevBuf<int> hb_ptr, hb_rows;
-  DevBuf<int> hb_pptr, hb_col, hb_src;  // position-ordered structure
-  DevBuf<double> hb_val;                // position-ordered values
-  DevBuf<int> hb_wcol;                          // first 16 in-range B^T head
-  DevBuf<double> hb_wval;                       // entries per position, padded
-  DevBuf<int> hb_split;                         // first in-range entry per position
-  std::vector<int> hb_blocks;                   // position ranges of the index ranges
-  // tail rows in level order: forward rows >= dense_rows, backward rows >= head_rows
-  DevBuf<int> tail_order_f, tail_order_b;
-  int tail_levels_f = 0, tail_levels_b = 0;  // dependency levels each tail order spans
+  // sync-free tails of narrow blocks: rows >= dense_rows in level order, per
+  // direction, and the number of dependency levels each spans
+  DevBuf<int> tail_order_f, tail_order_bn;
+  int tail_levels_f = 0, tail_levels_b = 0;
+  DevBuf<int> tail_order_b;  // rows >= head_rows, backward level order (wide blocks)
   DevBuf<int> full_order_f, full_order_b;       // all rows in level order
   // level l of the full orders = positions [lvl_ptr[l], lvl_ptr[l + 1]); nnz
   // of the rows of each level (host copies, for the level-scheduled solves)
@@ -356,7 +351,6 @@ struct Model {
   hipEvent_t poll_evt = nullptr;  // completion of this model's last polling kernel
   Timing timing;
   ~Model();  // releases poll_evt (util.hip)
-  int64_t nnz_head_bt = 0;  // nonzeros in head rows of B^T
 };
 
 // Records the message of a failed status for vl_last_error (api.hip).
@@ -441,13 +435,9 @@ Status spmm_group_b(Model& M, const double* X, double* Y, int t, const double* r
 Status spmm_group_bt(Model& M, const double* X, double* Y, int t, const double* d,
                      const double* V);
 
-// ---- head solves (head.hip)
+// ---- head schedules of the wide B^T solves (head.hip)
 constexpr int kHeadRows = 12288;  // with the dense first 4096 rows (measured best at n = 1e5)
 Status build_head_schedule(Model& M);
-Status head_upper(Model& M, const double* X, double* Y, int t);
-// FP32-storage head solves (FP64 LDS and sums) for mixed-precision narrow blocks
-Status head_upper_f32(Model& M, const double* X, float* Y, int t);
-Status refresh_head_values(Model& M);
 
 // ---- dense leading block (dense.hip)
 constexpr int kDenseRows = 4096;
@@ -467,9 +457,9 @@ Status bd_upper(Model& M, const double* X, double* Y, int t);
 Status build_dense(Model& M);
 Status dense_factor(Model& M);
 Status dense_lower(Model& M, const double* X, double* Y, int t, const double* rs);
-Status dense_upper(Model& M, double* Y, int t);
+Status dense_upper(Model& M, const double* X, double* Y, int t);
 Status dense_lower_f32(Model& M, const float* X, float* Y, int t, const double* rs);
-Status dense_upper_f32(Model& M, float* Y, int t);
+Status dense_upper_f32(Model& M, const double* X, float* Y, int t);
 
 // ---- solver kernels (solver.hip)
 Status tridiag_quadrature(Model& M, CgState& S, double* out_dev);

@@ -357,7 +357,7 @@ def vl_trsm(h, X, Y, transpose=False):
 
 
 TIMED_KINDS = {"spmm_b": 0, "spmm_bt": 1, "trsm_lower": 2, "trsm_upper": 3,
-               "dense_lower": 4, "head_upper": 5, "level_lower": 6, "level_upper": 7,
+               "dense_lower": 4, "dense_upper": 5, "level_lower": 6, "level_upper": 7,
                "level_upper_split": 8, "level_upper_fold": 9,
                "dense_wide": 10}
 

@@ -1,8 +1,8 @@
 """Mixed-precision form against the FP64 oracle: FP32 preconditioner solves
 (FP32 n x t blocks, FP64 row sums) inside the FP64 block PCG, whose FP64
 operator and residual recurrence refine every FP32 solve: level-scheduled
-with FP32 B values for blocks wider than 64 columns, the LDS head and
-sync-free tail with FP32 right-hand sides and results for narrower ones.
+with FP32 B values for blocks wider than 64 columns, the dense leading block
+and sync-free tail with FP32 right-hand sides and results for narrower ones.
 Probe counts below and above 64 run both.  The bar: relative 1e-4 on the
 negative log-likelihood and 1e-3 on the predictive variances; the errors of
 the mode, the predictive means and the gradient are measured and printed."""

@@ -226,11 +226,12 @@ def test_predict(c1, c1_fit):
 @pytest.mark.parametrize("t", [1, 8, 50, 65, 300, 1000])
 def test_trsm_head_and_tail(P, t, n):
     # For t <= 64 the first 4096 rows come from the dense inverse of B's
-    # leading block, the head rows after them are solved in LDS level by
-    # level, the rest (n = 40000) by the sync-free tail kernels; n = 5000 has
-    # no tail.  Wider blocks (65, 300: one and two column slices, ragged) take
-    # the first 2048 rows from the dense inverse and the others by
-    # level-scheduled launches; at t = 1000 the dense product runs in its
+    # leading block and the rest from the sync-free tail kernels, in both
+    # directions (35904 tail rows at n = 40000, a ragged 904 at n = 5000).
+    # Wider blocks (65, 300: one and two column slices, ragged) take the first
+    # 2048 rows from the dense inverse, the others by level-scheduled launches
+    # (backward: tail rows, the fold into the head rows up to 12288, the head
+    # rows by their own levels); at t = 1000 the dense product runs in its
     # 128-row blocks (ragged last column tile of 40).  The
     # reference solves with the oracle's factor.  The range (0.005, about the
     # spacing of the points) keeps every neighbour covariance well conditioned,

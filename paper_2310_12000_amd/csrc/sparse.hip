@@ -1138,13 +1138,15 @@ static bool use_levels(const Model& M, int t) {
   return (t > 64 || M.force_levels) && M.lvl_ptr_f.size() > 1;
 }
 
-// Window width of the sync-free tail solve: the row length rounded up to 8
-// (B's rows have m entries), capped at 32 (longer rows take several windows).
+// Window width of a forward tail row of B (m entries): m rounded up to one of
+// 8, 16, 20, 24, capped at 32 (longer rows take several windows).
 static int tail_window(int len) {
   return len <= 8 ? 8 : len <= 16 ? 16 : len <= 20 ? 20 : len <= 24 ? 24 : 32;
 }
+constexpr int kUpperWindow = 16;  // B^T rows, every width (see lower_window)
 
-// Launch of the sync-free tail solve with window width W.
+// Launch of the sync-free tail solve with window width W (forward), or
+// kUpperWindow (backward).
 template <bool LOWER, class In, typename TY>
 static Status launch_tail(Model& M, int W, int g, int64_t H, int t, Lanes L, const int* ord,
                           const int* ptr, const int* idx, const double* val, In x,
@@ -1157,12 +1159,17 @@ static Status launch_tail(Model& M, int W, int g, int64_t H, int t, Lanes L, con
   hipLaunchKernelGGL((trsm_kernel<WW, LOWER, In, TY>), dim3(g), dim3(256), 0, M.stream, M.n, \
                      H, m, t, L, ord, ptr, idx, val, x, rowscale, Y, ns, cnt,                \
                      cnt + kAbortOffset, M.status)
-  switch (W) {
-    case 8: VL_TAIL(8); break;
-    case 16: VL_TAIL(16); break;
-    case 20: VL_TAIL(20); break;
-    case 24: VL_TAIL(24); break;
-    default: VL_TAIL(32); break;
+  if constexpr (LOWER) {
+    switch (W) {
+      case 8: VL_TAIL(8); break;
+      case 16: VL_TAIL(16); break;
+      case 20: VL_TAIL(20); break;
+      case 24: VL_TAIL(24); break;
+      default: VL_TAIL(32); break;
+    }
+  } else {
+    if (W != kUpperWindow) return Status::invalid("backward tail window");
+    VL_TAIL(kUpperWindow);
   }
 #undef VL_TAIL
   return check_launch(LOWER ? "trsm_b" : "trsm_bt");
@@ -1179,7 +1186,7 @@ static int lower_window(int m, int t) {
   const int w = tail_window(m);
   return (t <= 8 || w < 16) ? w : 16;
 }
-static int upper_window(int) { return 16; }
+static int upper_window(int) { return kUpperWindow; }
 
 // First row of the sync-free tail for narrow blocks, in both directions: the
 // rows below come from the dense block.  An LDS head for the rows between
@@ -1230,7 +1237,7 @@ Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled,
     int* cnt = counter_slot(M, slot);
     PollingOrder order(M);
     TimedLaunch tl(M, kTimeTrsmUpper,
-                   12.0 * (M.nnz - nnz_below(M, R0)) + 4.0 * (M.n - R0) +
+                   12.0 * (M.nnz - (R0 ? M.nnz_bt_dense : 0)) + 4.0 * (M.n - R0) +
                        16.0 * (M.n - R0) * t);
     VL_TRY(launch_tail<false>(M, upper_window(t), g, R0, t, L,
                               R0 ? M.tail_order_bn.p : M.full_order_b.p, M.bt_ptr.p, M.bt_col.p,
@@ -1273,7 +1280,7 @@ Status trsm_bt_f32_narrow(Model& M, const double* X, float* Y, int t) {
     int* cnt = counter_slot(M, 0);
     PollingOrder order(M);
     TimedLaunch tl(M, kTimeTrsmUpper,
-                   12.0 * (M.nnz - nnz_below(M, R0)) + 4.0 * (M.n - R0) +
+                   12.0 * (M.nnz - (R0 ? M.nnz_bt_dense : 0)) + 4.0 * (M.n - R0) +
                        12.0 * (M.n - R0) * t);
     VL_TRY(launch_tail<false>(M, upper_window(t), g, R0, t, L,
                               R0 ? M.tail_order_bn.p : M.full_order_b.p, M.bt_ptr.p, M.bt_col.p,
@@ -1416,6 +1423,12 @@ __global__ void level_scatter_kernel(int64_t n, int64_t r0, const int* __restric
 Status build_tail_orders(Model& M) {
   const int64_t n = M.n, H = M.head_rows;
   const int64_t K = H > 0 ? M.dense_rows : 0;  // start of the narrow tails (narrow_tail_start)
+  M.nnz_bt_dense = 0;
+  if (K > 0) {
+    VL_HIP(hipMemcpyAsync(&M.nnz_bt_dense, M.bt_ptr.p + K, sizeof(int), hipMemcpyDeviceToHost,
+                          M.stream));
+    VL_TRY(sync_stream(M.stream));
+  }
   VL_TRY(M.tail_order_f.alloc(n - K > 0 ? n - K : 1));
   VL_TRY(M.tail_order_bn.alloc(n - K > 0 ? n - K : 1));
   VL_TRY(M.tail_order_b.alloc(n - H > 0 ? n - H : 1));

@@ -1143,10 +1143,10 @@ static bool use_levels(const Model& M, int t) {
 static int tail_window(int len) {
   return len <= 8 ? 8 : len <= 16 ? 16 : len <= 20 ? 20 : len <= 24 ? 24 : 32;
 }
-constexpr int kUpperWindow = 16;  // B^T rows, every width (see lower_window)
+// B^T rows (see lower_window): 2 entries for t <= 8, 4 for wider blocks
+constexpr int kUpperWindowNarrow = 2, kUpperWindowWide = 4;
 
-// Launch of the sync-free tail solve with window width W (forward), or
-// kUpperWindow (backward).
+// Launch of the sync-free tail solve with window width W.
 template <bool LOWER, class In, typename TY>
 static Status launch_tail(Model& M, int W, int g, int64_t H, int t, Lanes L, const int* ord,
                           const int* ptr, const int* idx, const double* val, In x,
@@ -1168,8 +1168,13 @@ static Status launch_tail(Model& M, int W, int g, int64_t H, int t, Lanes L, con
       default: VL_TAIL(32); break;
     }
   } else {
-    if (W != kUpperWindow) return Status::invalid("backward tail window");
-    VL_TAIL(kUpperWindow);
+    if (W == kUpperWindowNarrow) {
+      VL_TAIL(kUpperWindowNarrow);
+    } else if (W == kUpperWindowWide) {
+      VL_TAIL(kUpperWindowWide);
+    } else {
+      return Status::invalid("backward tail window");
+    }
   }
 #undef VL_TAIL
   return check_launch(LOWER ? "trsm_b" : "trsm_bt");
@@ -1179,14 +1184,17 @@ static Status launch_tail(Model& M, int W, int g, int64_t H, int t, Lanes L, con
 // narrow blocks (t <= 8) take the whole row in one window (t = 1: 0.39 ms at
 // 20 entries, 0.40 at 24, against 0.52 at 16 before the grid sizing), wider
 // blocks the occupancy of the 16-entry window (178 VGPRs, two waves per SIMD,
-// against one at 20 entries or more).  Backward rows are consumed from their
-// last window, so later windows cost no round after the last arrival: 16
-// entries at every width (t = 1: 0.56 ms, against 0.61 at 32).
+// against one at 20 entries or more; 8 entries took 0.60 ms at t = 50 against
+// 0.56).  Backward rows are consumed from their last window, so the earlier
+// windows are taken while the row still waits for its slowest children and
+// only the last one follows the last arrival; small windows then win on
+// registers and on the round's work: t = 1 took 0.34 / 0.35 / 0.39 / 0.48 ms
+// with 2 / 4 / 8 / 16 entries, t = 50 0.48 / 0.46 / 0.48 / 0.57 ms.
 static int lower_window(int m, int t) {
   const int w = tail_window(m);
   return (t <= 8 || w < 16) ? w : 16;
 }
-static int upper_window(int) { return kUpperWindow; }
+static int upper_window(int t) { return t <= 8 ? kUpperWindowNarrow : kUpperWindowWide; }
 
 // First row of the sync-free tail for narrow blocks, in both directions: the
 // rows below come from the dense block.  An LDS head for the rows between

@@ -166,11 +166,17 @@ Status transpose_pattern(Model& M, const int* nbr, int64_t rows, int m, int64_t 
   return Status::ok();
 }
 
+// Copies of the B values after a factor: B^T, and B's rows with their slots
+// in the forward tail's consumption order (tail_slots_kernel).
 Status refresh_transpose_values(Model& M) {
   if (M.nnz == 0) return Status::ok();
   const int tb = 256;
   hipLaunchKernelGGL(bt_gather_vals, dim3((unsigned)((M.nnz + tb - 1) / tb)), dim3(tb), 0,
                      M.stream, M.nnz, M.bt_src.p, M.bval.p, M.bt_val.p);
+  const int64_t nm = M.n * static_cast<int64_t>(M.m);
+  if (M.tsrc.p && nm > 0)
+    hipLaunchKernelGGL(bt_gather_vals, dim3((unsigned)((nm + tb - 1) / tb)), dim3(tb), 0,
+                       M.stream, nm, M.tsrc.p, M.bval.p, M.tval.p);
   return check_launch("transpose values");
 }
 
@@ -1138,13 +1144,9 @@ static bool use_levels(const Model& M, int t) {
   return (t > 64 || M.force_levels) && M.lvl_ptr_f.size() > 1;
 }
 
-// Window width of a forward tail row of B (m entries): m rounded up to one of
-// 8, 16, 20, 24, capped at 32 (longer rows take several windows).
-static int tail_window(int len) {
-  return len <= 8 ? 8 : len <= 16 ? 16 : len <= 20 ? 20 : len <= 24 ? 24 : 32;
-}
-// B^T rows (see lower_window): 2 entries for t <= 8, 4 for wider blocks
-constexpr int kUpperWindowNarrow = 2, kUpperWindowWide = 4;
+// Window widths of the tail solve (see lower_window / upper_window).
+constexpr int kLowerWindowNarrow = 8, kLowerWindowWide = 4;  // B's rows, level-sorted
+constexpr int kUpperWindowNarrow = 2, kUpperWindowWide = 4;  // B^T rows
 
 // Launch of the sync-free tail solve with window width W.
 template <bool LOWER, class In, typename TY>
@@ -1160,12 +1162,12 @@ static Status launch_tail(Model& M, int W, int g, int64_t H, int t, Lanes L, con
                      H, m, t, L, ord, ptr, idx, val, x, rowscale, Y, ns, cnt,                \
                      cnt + kAbortOffset, M.status)
   if constexpr (LOWER) {
-    switch (W) {
-      case 8: VL_TAIL(8); break;
-      case 16: VL_TAIL(16); break;
-      case 20: VL_TAIL(20); break;
-      case 24: VL_TAIL(24); break;
-      default: VL_TAIL(32); break;
+    if (W == kLowerWindowNarrow) {
+      VL_TAIL(kLowerWindowNarrow);
+    } else if (W == kLowerWindowWide) {
+      VL_TAIL(kLowerWindowWide);
+    } else {
+      return Status::invalid("forward tail window");
     }
   } else {
     if (W == kUpperWindowNarrow) {
@@ -1180,21 +1182,22 @@ static Status launch_tail(Model& M, int W, int g, int64_t H, int t, Lanes L, con
   return check_launch(LOWER ? "trsm_b" : "trsm_bt");
 }
 
-// Window widths of the tail solve, measured at n = 1e5, m = 20.  Forward,
-// narrow blocks (t <= 8) take the whole row in one window (t = 1: 0.39 ms at
-// 20 entries, 0.40 at 24, against 0.52 at 16 before the grid sizing), wider
-// blocks the occupancy of the 16-entry window (178 VGPRs, two waves per SIMD,
-// against one at 20 entries or more; 8 entries took 0.60 ms at t = 50 against
-// 0.56).  Backward rows are consumed from their last window, so the earlier
-// windows are taken while the row still waits for its slowest children and
-// only the last one follows the last arrival; small windows then win on
-// registers and on the round's work: t = 1 took 0.34 / 0.35 / 0.39 / 0.48 ms
-// with 2 / 4 / 8 / 16 entries, t = 50 0.48 / 0.46 / 0.48 / 0.57 ms.
-static int lower_window(int m, int t) {
-  const int w = tail_window(m);
-  return (t <= 8 || w < 16) ? w : 16;
-}
+// Window widths of the tail solve, measured at n = 1e5, m = 20.  A row is
+// consumed window by window with its slowest entries last: forward, B's rows
+// in tnbr order (neighbours sorted by forward level, tail_slots_kernel);
+// backward, B^T rows from their last window back (children in ascending index
+// finish in descending order).  The early windows are then taken while the
+// row still waits for its slowest entries, only the last one follows the last
+// arrival, and small windows win on registers and on the work of a round.
+// Forward, with the level-sorted slots: t = 1 took 0.28 / 0.30 / 0.36 ms with
+// 8 / 4 / 20 entries (0.39 ms with 20 in slot order), t = 50 0.38 / 0.35 /
+// 0.49 ms with 8 / 4 / 16 (0.56 ms with 16 in slot order).  Backward: t = 1
+// took 0.34 / 0.35 / 0.39 / 0.48 ms with 2 / 4 / 8 / 16 entries, t = 50
+// 0.48 / 0.46 / 0.48 / 0.57 ms.
+static int lower_window(int t) { return t <= 8 ? kLowerWindowNarrow : kLowerWindowWide; }
 static int upper_window(int t) { return t <= 8 ? kUpperWindowNarrow : kUpperWindowWide; }
+static const int* tail_nbr(const Model& M) { return M.tnbr.p ? M.tnbr.p : M.nbr.p; }
+static const double* tail_val(const Model& M) { return M.tval.p ? M.tval.p : M.bval.p; }
 
 // First row of the sync-free tail for narrow blocks, in both directions: the
 // rows below come from the dense block.  An LDS head for the rows between
@@ -1228,9 +1231,9 @@ Status trsm_b_slot(Model& M, const double* X, double* Y, int t, const double* ro
   TimedLaunch tl(M, kTimeTrsmLower,
                  12.0 * (M.nnz - nnz_below(M, R0)) + 16.0 * (M.n - R0) * t +
                      (rowscale ? 8.0 * (M.n - R0) : 0.0));
-  return launch_tail<true>(M, lower_window(M.m, t), g, R0, t, L,
-                           R0 ? M.tail_order_f.p : M.full_order_f.p, nullptr, M.nbr.p, M.bval.p,
-                           InMem{X, t}, rowscale, Y, ns, cnt);
+  return launch_tail<true>(M, lower_window(t), g, R0, t, L,
+                           R0 ? M.tail_order_f.p : M.full_order_f.p, nullptr, tail_nbr(M),
+                           tail_val(M), InMem{X, t}, rowscale, Y, ns, cnt);
 }
 
 Status trsm_bt_slot(Model& M, const double* X, double* Y, int t, bool prefilled, int slot) {
@@ -1272,9 +1275,9 @@ Status trsm_b_f32_narrow(Model& M, const float* X, float* Y, int t, const double
   TimedLaunch tl(M, kTimeTrsmLower,
                  12.0 * (M.nnz - nnz_below(M, R0)) + 8.0 * (M.n - R0) * t +
                      (rowscale ? 8.0 * (M.n - R0) : 0.0));
-  return launch_tail<true>(M, lower_window(M.m, t), g, R0, t, L,
-                           R0 ? M.tail_order_f.p : M.full_order_f.p, nullptr, M.nbr.p, M.bval.p,
-                           InMemF{X, t}, rowscale, Y, ns, cnt);
+  return launch_tail<true>(M, lower_window(t), g, R0, t, L,
+                           R0 ? M.tail_order_f.p : M.full_order_f.p, nullptr, tail_nbr(M),
+                           tail_val(M), InMemF{X, t}, rowscale, Y, ns, cnt);
 }
 
 Status trsm_bt_f32_narrow(Model& M, const double* X, float* Y, int t) {
@@ -1428,6 +1431,39 @@ __global__ void level_scatter_kernel(int64_t n, int64_t r0, const int* __restric
   order[start[l] + atomicAdd(&cursor[l], 1)] = r;
 }
 
+// Slots of every row of B ordered by the forward level of their neighbour
+// (ties by slot; padding slots first): the forward tail consumes a row in this
+// order, so its last window holds the neighbours solved last.  tnbr holds the
+// neighbours, tsrc the source slot of each (for the values, refreshed with
+// every factor).
+__global__ void tail_slots_kernel(int64_t n, int m, const int* __restrict__ nbr,
+                                  const int* __restrict__ lev, int* __restrict__ tnbr,
+                                  int* __restrict__ tsrc) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int key[32], slot[32];
+  for (int k = 0; k < m; ++k) {
+    const int j = nbr[i * m + k];
+    key[k] = j >= 0 ? lev[j] : -1;
+    slot[k] = k;
+  }
+  for (int a = 1; a < m; ++a) {  // insertion sort, stable
+    const int ka = key[a], sa = slot[a];
+    int b = a - 1;
+    while (b >= 0 && key[b] > ka) {
+      key[b + 1] = key[b];
+      slot[b + 1] = slot[b];
+      --b;
+    }
+    key[b + 1] = ka;
+    slot[b + 1] = sa;
+  }
+  for (int k = 0; k < m; ++k) {
+    tnbr[i * m + k] = nbr[i * m + slot[k]];
+    tsrc[i * m + k] = static_cast<int>(i * m + slot[k]);
+  }
+}
+
 Status build_tail_orders(Model& M) {
   const int64_t n = M.n, H = M.head_rows;
   const int64_t K = H > 0 ? M.dense_rows : 0;  // start of the narrow tails (narrow_tail_start)
@@ -1469,6 +1505,15 @@ Status build_tail_orders(Model& M) {
     // stop before anything indexes by level.
     VL_TRY(check_launch("levels"));
     VL_TRY(read_status(M));
+    if (dir == 0 && M.m > 0 && M.m <= 32) {
+      const size_t nm = static_cast<size_t>(n) * M.m;
+      VL_TRY(M.tnbr.alloc(nm));
+      VL_TRY(M.tsrc.alloc(nm));
+      VL_TRY(M.tval.alloc(nm));
+      hipLaunchKernelGGL(tail_slots_kernel, dim3(gn), dim3(tb), 0, M.stream, n, M.m, M.nbr.p,
+                         lev.p, M.tnbr.p, M.tsrc.p);
+      VL_TRY(check_launch("tail slots"));
+    }
     const int* spatial = static_cast<const int*>(M.grid_pts);
     // per direction: the narrow blocks' tail (rows >= K), the wide backward
     // solve's tail (rows >= H), the full order

@@ -249,6 +249,9 @@ struct Model {
   DevBuf<int> tail_order_f, tail_order_bn;
   int tail_levels_f = 0, tail_levels_b = 0;
   int nnz_bt_dense = 0;  // B^T entries of the rows below dense_rows
+  // B's rows with their slots in the forward tail's consumption order
+  DevBuf<int> tnbr, tsrc;
+  DevBuf<double> tval;
   DevBuf<int> tail_order_b;  // rows >= head_rows, backward level order (wide blocks)
   DevBuf<int> full_order_f, full_order_b;       // all rows in level order
   // level l of the full orders = positions [lvl_ptr[l], lvl_ptr[l + 1]); nnz

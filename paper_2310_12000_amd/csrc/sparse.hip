@@ -1096,9 +1096,11 @@ static int trsm_grid(int64_t total_units) {
 // waves only add waiting rows, and every waiting row re-polls its missing
 // entries each round: at t = 1 (1500 units over ~200 levels at n = 1e5) all
 // units in flight made each round 4.7 us of memory traffic, and 32-64 blocks
-// instead of 375 took the forward solve from 0.52 to 0.41 ms.  Wide blocks
-// (t = 50: 96k units) keep the resident maximum.
-constexpr int64_t kTailLookahead = 16;
+// instead of 375 took the forward solve from 0.52 to 0.41 ms.  With the
+// small windows a lookahead of 32 levels beat 8, 16 and 64 (mode 276 ms
+// against 320, 286 and 284).  Wide blocks (t = 50: 96k units) keep the
+// resident maximum.
+constexpr int64_t kTailLookahead = 32;
 static int levels_of(const std::vector<int>& level_ptr) {
   return level_ptr.size() > 1 ? static_cast<int>(level_ptr.size()) - 1 : 0;
 }

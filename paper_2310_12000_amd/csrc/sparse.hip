@@ -1148,7 +1148,7 @@ static bool use_levels(const Model& M, int t) {
 
 // Window widths of the tail solve (see lower_window / upper_window).
 constexpr int kLowerWindowNarrow = 8, kLowerWindowWide = 4;  // B's rows, level-sorted
-constexpr int kUpperWindowNarrow = 2, kUpperWindowWide = 4;  // B^T rows
+constexpr int kUpperWindowNarrow = 1, kUpperWindowWide = 4;  // B^T rows
 
 // Launch of the sync-free tail solve with window width W.
 template <bool LOWER, class In, typename TY>
@@ -1193,9 +1193,9 @@ static Status launch_tail(Model& M, int W, int g, int64_t H, int t, Lanes L, con
 // arrival, and small windows win on registers and on the work of a round.
 // Forward, with the level-sorted slots: t = 1 took 0.28 / 0.30 / 0.36 ms with
 // 8 / 4 / 20 entries (0.39 ms with 20 in slot order), t = 50 0.38 / 0.35 /
-// 0.49 ms with 8 / 4 / 16 (0.56 ms with 16 in slot order).  Backward: t = 1
-// took 0.34 / 0.35 / 0.39 / 0.48 ms with 2 / 4 / 8 / 16 entries, t = 50
-// 0.48 / 0.46 / 0.48 / 0.57 ms.
+// 0.49 ms with 8 / 4 / 16 (0.56 ms with 16 in slot order; 0.38 ms with 2).
+// Backward: t = 1 took 0.28 / 0.34 / 0.35 / 0.39 / 0.48 ms with 1 / 2 / 4 / 8 /
+// 16 entries, t = 50 0.48 / 0.46 / 0.48 / 0.57 ms with 2 / 4 / 8 / 16.
 static int lower_window(int t) { return t <= 8 ? kLowerWindowNarrow : kLowerWindowWide; }
 static int upper_window(int t) { return t <= 8 ? kUpperWindowNarrow : kUpperWindowWide; }
 static const int* tail_nbr(const Model& M) { return M.tnbr.p ? M.tnbr.p : M.nbr.p; }
